@@ -1,0 +1,213 @@
+"""FP64 CPU oracle for batched Picard-Chebyshev propagation (ctypes wrapper).
+
+TEST INFRASTRUCTURE, NOT PRODUCT CODE: only the test suite, the smoke check
+and the benchmark's CPU-baseline leg may import this package.  It shares no
+code with the HIP path.  The arithmetic lives in ``pc_oracle.c``; this module
+only builds it with gcc (on first use, or when the source is newer than the
+library) and marshals numpy arrays.
+
+Paper: Masat, Colombo, Boutonnet, arXiv 2301.03989.  Each function cites the
+passage it follows in ``pc_oracle.c``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pc_oracle.c")
+_LIB = os.path.join(_HERE, "libpc_oracle.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+def build(force: bool = False) -> str:
+    """Compile pc_oracle.c into libpc_oracle.so with gcc (FP64, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-fno-fast-math",
+               "-ffp-contract=off", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        lib.orc_propagate.restype = ctypes.c_int
+        lib.orc_propagate.argtypes = [
+            ctypes.c_int, _dp, _dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+            ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+            ctypes.c_int, _dp, ctypes.c_double, _dp, _ip, _dp, _dp, ctypes.c_int]
+        lib.orc_picard_step.restype = None
+        lib.orc_picard_step.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]
+        lib.orc_nodes.restype = None
+        lib.orc_nodes.argtypes = [ctypes.c_int, _dp]
+        lib.orc_accel.restype = None
+        lib.orc_accel.argtypes = [_dp, ctypes.c_int, _dp, _dp, ctypes.c_double, _dp]
+        lib.orc_accel_t.restype = None
+        lib.orc_accel_t.argtypes = [_dp, ctypes.c_double, ctypes.c_double, ctypes.c_int, _dp,
+                                    ctypes.c_double, _dp]
+        lib.orc_ephem.restype = None
+        lib.orc_ephem.argtypes = [_dp, ctypes.c_double, ctypes.c_double, _dp]
+        lib.orc_kepler.restype = ctypes.c_int
+        lib.orc_kepler.argtypes = [_dp, ctypes.c_double, _dp]
+        lib.orc_rk4.restype = None
+        lib.orc_rk4.argtypes = [_dp, ctypes.c_double, ctypes.c_double, ctypes.c_long,
+                                ctypes.c_double, ctypes.c_int, _dp, ctypes.c_double, _dp]
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(_dp if a.dtype == np.float64 else _ip)
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+class Model:
+    """Point-mass force model: Sun (mu_sun) plus perturbers on Keplerian orbits.
+
+    ``pert`` is an array [n_pert, 7] of (mu_p, a, e, inc, raan, argp, M0) with
+    angles in radians and M0 the mean anomaly at ``epoch``.
+    """
+
+    def __init__(self, mu_sun=1.0, pert=None, epoch=0.0):
+        self.mu_sun = float(mu_sun)
+        self.pert = _f64(np.zeros((0, 7)) if pert is None else pert).reshape(-1, 7)
+        self.epoch = float(epoch)
+
+    @property
+    def n_pert(self):
+        return int(self.pert.shape[0])
+
+    def _pert_ptr(self):
+        # ctypes needs a valid pointer even when there are no perturbers
+        if self.n_pert == 0:
+            self._dummy = np.zeros(7)
+            return _ptr(self._dummy)
+        return _ptr(self.pert)
+
+
+def propagate(ics, t0, tf, nodes, segments, tol, model=None, *, tol_mode=0, max_iter=64,
+              fixed_iters=0, init=0, want_bounds=False, want_nodes=False, threads=0):
+    """Propagate ICs [n,6] over [t0, tf] (scalars or per-IC arrays).
+
+    Returns (states[n,6], iters[n,segments]) and, when asked, the segment-boundary
+    states [n,S+1,6] and the node states [n,S,N,6].  ``init``: 0 Kepler, 1 cold.
+    """
+    lib = _load()
+    model = model or Model()
+    ics = _f64(ics).reshape(-1, 6)
+    n = ics.shape[0]
+    t0a = _f64(np.broadcast_to(np.asarray(t0, dtype=np.float64), (n,)))
+    tfa = _f64(np.broadcast_to(np.asarray(tf, dtype=np.float64), (n,)))
+    S, N = int(segments), int(nodes)
+    states = np.zeros((n, 6))
+    iters = np.zeros((n, S), dtype=np.int32)
+    bounds = np.zeros((n, S + 1, 6)) if want_bounds else None
+    nodes_out = np.zeros((n, S, N, 6)) if want_nodes else None
+    used = lib.orc_propagate(n, _ptr(ics), _ptr(t0a), _ptr(tfa), N, S, float(tol), int(tol_mode),
+                             int(max_iter), int(fixed_iters), int(init), model.mu_sun,
+                             model.n_pert, model._pert_ptr(), model.epoch, _ptr(states),
+                             iters.ctypes.data_as(_ip), _ptr(bounds), _ptr(nodes_out), int(threads))
+    out = [states, iters]
+    if want_bounds:
+        out.append(bounds)
+    if want_nodes:
+        out.append(nodes_out)
+    propagate.last_threads = used
+    return tuple(out)
+
+
+propagate.last_threads = 1
+
+
+def picard_step(g, y0):
+    """Steps (ii)-(v) of one iteration for one trajectory: g [N, ncomp] (w2-scaled
+    force matrix) and y0 [ncomp] -> y [N, ncomp]."""
+    lib = _load()
+    g = _f64(g)
+    if g.ndim == 1:
+        g = g[:, None]
+    N, nc = g.shape
+    y0 = _f64(y0).reshape(nc)
+    y = np.zeros((N, nc))
+    lib.orc_picard_step(N, nc, _ptr(g), _ptr(y0), _ptr(y))
+    return y
+
+
+def operator(N):
+    """The linear map g -> y - y0 of steps (ii)-(v), as an N x N matrix built by
+    applying the oracle's update to unit vectors."""
+    return picard_step(np.eye(N), np.zeros(N))
+
+
+def nodes(N):
+    lib = _load()
+    tau = np.zeros(N)
+    lib.orc_nodes(int(N), _ptr(tau))
+    return tau
+
+
+def accel(r, rp, mup, mu_sun=1.0):
+    """Acceleration at r [3] from perturbers at rp [P,3] with parameters mup [P]."""
+    lib = _load()
+    r = _f64(r).reshape(3)
+    rp = _f64(rp).reshape(-1, 3)
+    mup = _f64(mup).reshape(-1)
+    a = np.zeros(3)
+    dummy = np.zeros(3)
+    lib.orc_accel(_ptr(r), rp.shape[0], _ptr(rp) if rp.size else _ptr(dummy),
+                  _ptr(mup) if mup.size else _ptr(dummy), float(mu_sun), _ptr(a))
+    return a
+
+
+def accel_t(r, t, model):
+    lib = _load()
+    r = _f64(r).reshape(3)
+    a = np.zeros(3)
+    lib.orc_accel_t(_ptr(r), float(t), model.mu_sun, model.n_pert, model._pert_ptr(),
+                    model.epoch, _ptr(a))
+    return a
+
+
+def ephem(el, epoch, t):
+    lib = _load()
+    el = _f64(el).reshape(7)
+    r = np.zeros(3)
+    lib.orc_ephem(_ptr(el), float(epoch), float(t), _ptr(r))
+    return r
+
+
+def kepler(y0, dt):
+    """Two-body (mu = 1) propagation of y0 by dt; returns (ok, y)."""
+    lib = _load()
+    y0 = _f64(y0).reshape(6)
+    y = np.zeros(6)
+    rc = lib.orc_kepler(_ptr(y0), float(dt), _ptr(y))
+    return rc == 0, y
+
+
+def rk4(y0, t0, tf, nsteps, model):
+    lib = _load()
+    y0 = _f64(y0).reshape(6)
+    y = np.zeros(6)
+    lib.orc_rk4(_ptr(y0), float(t0), float(tf), int(nsteps), model.mu_sun, model.n_pert,
+                model._pert_ptr(), model.epoch, _ptr(y))
+    return y

@@ -1,0 +1,431 @@
+/*
+ * pc_oracle.c -- plain FP64 CPU oracle for batched Picard-Chebyshev propagation.
+ *
+ * TEST INFRASTRUCTURE, NOT PRODUCT CODE.  Only the test suite, the smoke check
+ * and the benchmark's CPU-baseline leg may load this library.  It shares no
+ * code, header, table or constant generator with the HIP path: it is a slow,
+ * step-by-step restatement of the method used to check the GPU results.
+ *
+ * Paper: Masat, Colombo, Boutonnet, "GPU-based high-precision orbital
+ * propagation of large sets of initial conditions through Picard-Chebyshev
+ * augmentation" (arXiv 2301.03989).
+ *
+ * What is computed, per initial condition (IC), independently of all others
+ * (the paper's "independent runs" workflow, Sec. 5.1, with a per-IC stopping
+ * rule, i.e. the per-block error of Sec. 3.2 with blocks of one member):
+ *
+ *   segments    T_s = t0 + s (tf - t0) / S, s = 0..S, integrated in sequence
+ *               (piecewise integration, Sec. 2.2; tf < t0 integrates backward)
+ *   nodes       tau_j = -cos(j pi / (N-1)), t_j = w2 tau_j + w1,
+ *               w1 = (T_{s+1} + T_s)/2, w2 = (T_{s+1} - T_s)/2   (Sec. 2.2, eqs. chnodes1/2)
+ *   guess       cold: y_j = y0; warm: two-body Kepler (mu = 1) from y0   (Sec. 2.1)
+ *   iteration   (i)   g_j = w2 f(y_j, t_j)                 (force matrix F, Sec. 2.2)
+ *               (ii)  c_k = 2/(N-1) sum''_j g_j T_k(tau_j), k = 0..N-2   (Chebyshev fit)
+ *               (iii) b_k = (c_{k-1} - c_{k+1}) / (2k), k = 1..N-1, c_{N-1} = c_N = 0
+ *               (iv)  b_0 = 2 y0 - 2 sum_k (-1)^k b_k     (the "B_1 = S A F + 2 y_0" row)
+ *               (v)   y_j = b_0/2 + sum_k b_k T_k(tau_j)   (Y = C B)
+ *               (vi)  e = max_j max(|dr_j|/|r_j|, |dv_j|/|v_j|); stop when e < tol
+ *   chaining    y0 of segment s+1 = last node of segment s
+ *
+ * The paper defines A, C and S only by citation (Sec. 2.2); steps (ii)-(v)
+ * are the Chebyshev fit/integrate/evaluate they stand for, with the constant
+ * term in the half-coefficient convention that the "2 y_0" term implies.
+ *
+ * Force model (point masses, heliocentric frame with the indirect term):
+ *   a(r,t) = -mu_S r/|r|^3 - sum_p mu_p [ (r - r_p)/|r - r_p|^3 + r_p/|r_p|^3 ]
+ * with perturber p on a fixed Keplerian orbit about the Sun (mu = 1).  The
+ * paper's own model is relativistic EIH with real ephemerides (Sec. 5.4.1);
+ * this point-mass model is the workload's substitute for it.  As the paper
+ * does (Sec. 5.4.1), perturber positions are evaluated once per node before
+ * the iterations of a segment.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_PI 3.14159265358979323846
+
+/* ------------------------------------------------------------------------ */
+/* Two-body Kepler orbits (mu = 1)                                           */
+/* ------------------------------------------------------------------------ */
+
+/* Solve Kepler's equation E - e sin E = M for the eccentric anomaly (Newton). */
+static double orc_solve_kepler_E(double M, double e)
+{
+    double Mr = fmod(M, 2.0 * ORC_PI);
+    if (Mr > ORC_PI) Mr -= 2.0 * ORC_PI;
+    if (Mr < -ORC_PI) Mr += 2.0 * ORC_PI;
+    double E = (e < 0.8) ? Mr : (Mr >= 0 ? ORC_PI : -ORC_PI);
+    for (int it = 0; it < 100; ++it) {
+        double f = E - e * sin(E) - Mr;
+        double fp = 1.0 - e * cos(E);
+        double dE = f / fp;
+        E -= dE;
+        if (fabs(dE) <= 1e-16 * (1.0 + fabs(E))) break;
+    }
+    return E + (M - Mr);
+}
+
+/* Heliocentric position of a body with elements
+ * el = {mu_p, a, e, inc, raan, argp, M0} (angles in radians) at time t,
+ * where M0 is the mean anomaly at time `epoch`. */
+void orc_ephem(const double* el, double epoch, double t, double r[3])
+{
+    double a = el[1], e = el[2], inc = el[3], raan = el[4], argp = el[5], M0 = el[6];
+    double n = sqrt(1.0 / (a * a * a));
+    double E = orc_solve_kepler_E(M0 + n * (t - epoch), e);
+    double xp = a * (cos(E) - e);
+    double yp = a * sqrt(1.0 - e * e) * sin(E);
+    double cO = cos(raan), sO = sin(raan), cw = cos(argp), sw = sin(argp);
+    double ci = cos(inc), si = sin(inc);
+    /* perifocal unit vectors P (towards pericentre) and Q */
+    double P[3] = { cO * cw - sO * sw * ci, sO * cw + cO * sw * ci, sw * si };
+    double Q[3] = { -cO * sw - sO * cw * ci, -sO * sw + cO * cw * ci, cw * si };
+    for (int k = 0; k < 3; ++k) r[k] = xp * P[k] + yp * Q[k];
+}
+
+/* Two-body propagation (mu = 1) of y0 by dt, through the Lagrange f and g
+ * coefficients written in the eccentric-anomaly difference dE.  Elliptic
+ * orbits only.  Returns 0 on success, -1 if the orbit is not elliptic or
+ * the state is degenerate (the caller then falls back to a cold start). */
+int orc_kepler(const double y0[6], double dt, double y[6])
+{
+    const double* r0 = y0;
+    const double* v0 = y0 + 3;
+    double r0n = sqrt(r0[0] * r0[0] + r0[1] * r0[1] + r0[2] * r0[2]);
+    double v02 = v0[0] * v0[0] + v0[1] * v0[1] + v0[2] * v0[2];
+    if (!(r0n > 0.0) || !isfinite(r0n) || !isfinite(v02)) return -1;
+    double alpha = 2.0 / r0n - v02;       /* = 1/a */
+    if (!(alpha > 0.0)) return -1;
+    double a = 1.0 / alpha;
+    double sqa = sqrt(a);
+    double n = sqrt(alpha * alpha * alpha);
+    double sig = r0[0] * v0[0] + r0[1] * v0[1] + r0[2] * v0[2]; /* r.v / sqrt(mu) */
+    double c1 = 1.0 - r0n / a;            /* e cos E0 */
+    double s1 = sig / sqa;                /* e sin E0 */
+    double Mdt = n * dt;
+    double x = Mdt;
+    for (int it = 0; it < 100; ++it) {
+        double sx = sin(x), cx = cos(x);
+        double F = x - c1 * sx + s1 * (1.0 - cx) - Mdt;
+        double Fp = 1.0 - c1 * cx + s1 * sx;
+        double dx = F / Fp;
+        x -= dx;
+        if (fabs(dx) <= 1e-16 * (1.0 + fabs(x))) break;
+    }
+    double sx = sin(x), cx = cos(x);
+    double rn = a + (r0n - a) * cx + sig * sqa * sx;
+    double f = 1.0 - (a / r0n) * (1.0 - cx);
+    double g = dt - (x - sx) / n;
+    double fd = -sqa * sx / (rn * r0n);
+    double gd = 1.0 - (a / rn) * (1.0 - cx);
+    for (int k = 0; k < 3; ++k) {
+        y[k] = f * r0[k] + g * v0[k];
+        y[3 + k] = fd * r0[k] + gd * v0[k];
+    }
+    for (int k = 0; k < 6; ++k)
+        if (!isfinite(y[k])) return -1;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Force model                                                               */
+/* ------------------------------------------------------------------------ */
+
+/* Acceleration at r given perturber positions rp[p][3] and parameters mup[p]. */
+void orc_accel(const double r[3], int n_pert, const double* rp, const double* mup,
+               double mu_sun, double acc[3])
+{
+    double rn2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    double rn = sqrt(rn2);
+    double s = mu_sun / (rn2 * rn);
+    for (int k = 0; k < 3; ++k) acc[k] = -s * r[k];
+    for (int p = 0; p < n_pert; ++p) {
+        const double* q = rp + 3 * p;
+        double d[3] = { r[0] - q[0], r[1] - q[1], r[2] - q[2] };
+        double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        double dn = sqrt(d2);
+        double q2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
+        double qn = sqrt(q2);
+        double sd = mup[p] / (d2 * dn);     /* direct term */
+        double sq = mup[p] / (q2 * qn);     /* indirect term: Sun's acceleration towards p */
+        for (int k = 0; k < 3; ++k) acc[k] -= sd * d[k] + sq * q[k];
+    }
+}
+
+/* Acceleration at (r, t) with perturber positions from their elements. */
+void orc_accel_t(const double r[3], double t, double mu_sun, int n_pert, const double* pert,
+                 double epoch, double acc[3])
+{
+    double rp[3 * 64], mup[64];
+    int np = n_pert > 64 ? 64 : n_pert;
+    for (int p = 0; p < np; ++p) {
+        orc_ephem(pert + 7 * p, epoch, t, rp + 3 * p);
+        mup[p] = pert[7 * p];
+    }
+    orc_accel(r, np, rp, mup, mu_sun, acc);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Chebyshev machinery at the N Chebyshev-Gauss-Lobatto nodes                */
+/* ------------------------------------------------------------------------ */
+
+/* tau_j = -cos(j pi / (N-1)), eq. chnodes2. */
+static double orc_tau(int j, int N)
+{
+    return -cos(ORC_PI * (double)j / (double)(N - 1));
+}
+
+/* T_k(tau_j).  Since tau_j = cos(pi (N-1-j)/(N-1)), T_k(tau_j) =
+ * cos(k pi (N-1-j)/(N-1)); the integer angle k (N-1-j) is reduced modulo
+ * 2(N-1) and folded into [0, N-1] so the cosine argument lies in [0, pi]. */
+static double orc_T(int k, int j, int N)
+{
+    long m = ((long)k * (long)(N - 1 - j)) % (2L * (N - 1));
+    if (m > N - 1) m = 2L * (N - 1) - m;
+    return cos(ORC_PI * (double)m / (double)(N - 1));
+}
+
+/* Steps (ii)-(v) of one Picard-Chebyshev iteration for one trajectory with
+ * `ncomp` state components: given the force matrix g[N][ncomp] (already
+ * scaled by w2) and the initial state y0[ncomp], produce y[N][ncomp].
+ * `Tkj` is the table T_k(tau_j), [N][N] row-major by k. */
+static void orc_picard_update(int N, int ncomp, const double* Tkj, const double* g,
+                              const double* y0, double* y, double* cbuf, double* bbuf)
+{
+    for (int comp = 0; comp < ncomp; ++comp) {
+        /* (ii) fit: c_k, k = 0..N-2; c_{N-1} = c_N = 0 (degree N-2 fit) */
+        for (int k = 0; k <= N; ++k) cbuf[k] = 0.0;
+        for (int k = 0; k <= N - 2; ++k) {
+            double s = 0.0;
+            for (int j = 0; j < N; ++j) {
+                double w = (j == 0 || j == N - 1) ? 0.5 : 1.0;
+                s += w * g[j * ncomp + comp] * Tkj[k * N + j];
+            }
+            cbuf[k] = 2.0 / (double)(N - 1) * s;
+        }
+        /* (iii) integrate: b_k = (c_{k-1} - c_{k+1}) / (2k), k = 1..N-1 */
+        for (int k = 1; k <= N - 1; ++k) bbuf[k] = (cbuf[k - 1] - cbuf[k + 1]) / (2.0 * k);
+        /* (iv) constant term from the initial condition: y(tau = -1) = y0 */
+        double alt = 0.0;
+        for (int k = 1; k <= N - 1; ++k) alt += ((k & 1) ? -1.0 : 1.0) * bbuf[k];
+        bbuf[0] = 2.0 * y0[comp] - 2.0 * alt;
+        /* (v) evaluate the series at the nodes */
+        for (int j = 0; j < N; ++j) {
+            double s = 0.5 * bbuf[0];
+            for (int k = 1; k <= N - 1; ++k) s += bbuf[k] * Tkj[k * N + j];
+            y[j * ncomp + comp] = s;
+        }
+    }
+}
+
+/* Test hook: one Picard update for a single trajectory (steps ii-v).
+ * g[N][ncomp] is the w2-scaled force matrix, y0[ncomp] the initial state. */
+void orc_picard_step(int N, int ncomp, const double* g, const double* y0, double* y)
+{
+    double* Tkj = (double*)malloc(sizeof(double) * (size_t)N * N);
+    double* cbuf = (double*)malloc(sizeof(double) * (size_t)(N + 2));
+    double* bbuf = (double*)malloc(sizeof(double) * (size_t)(N + 2));
+    for (int k = 0; k < N; ++k)
+        for (int j = 0; j < N; ++j) Tkj[k * N + j] = orc_T(k, j, N);
+    orc_picard_update(N, ncomp, Tkj, g, y0, y, cbuf, bbuf);
+    free(Tkj); free(cbuf); free(bbuf);
+}
+
+/* Test hook: the CGL nodes. */
+void orc_nodes(int N, double* tau)
+{
+    for (int j = 0; j < N; ++j) tau[j] = orc_tau(j, N);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Whole propagation                                                         */
+/* ------------------------------------------------------------------------ */
+
+/* Status codes per IC and segment, as stored in iters_out:
+ *   k >= 1 : converged after k iterations
+ *   -1     : not converged within max_iter (the last iterate is kept)
+ *   -2     : non-finite state (the IC stops; later segments also -2)      */
+
+/* Error of step (vi) between two iterates of one trajectory. */
+static double orc_iter_error(int N, const double* ynew, const double* yold, int tol_mode)
+{
+    double e = 0.0;
+    for (int j = 0; j < N; ++j) {
+        const double* a = ynew + 6 * j;
+        const double* b = yold + 6 * j;
+        double dr = 0, rr = 0, dv = 0, vv = 0;
+        for (int k = 0; k < 3; ++k) {
+            dr += (a[k] - b[k]) * (a[k] - b[k]);
+            rr += a[k] * a[k];
+            dv += (a[3 + k] - b[3 + k]) * (a[3 + k] - b[3 + k]);
+            vv += a[3 + k] * a[3 + k];
+        }
+        double ep, ev;
+        if (tol_mode == 0) { ep = sqrt(dr) / sqrt(rr); ev = sqrt(dv) / sqrt(vv); }
+        else { ep = sqrt(dr); ev = sqrt(dv); }
+        if (!(ep <= INFINITY) || !(ev <= INFINITY)) return NAN;
+        double m = ep > ev ? ep : ev;
+        if (m > e) e = m;
+    }
+    return e;
+}
+
+/*
+ * Propagate n_ic trajectories.
+ *   ics[n][6]          initial states at t0[n]
+ *   t0[n], tf[n]       per-IC interval (tf < t0: backward)
+ *   N, S               nodes per segment, number of segments
+ *   tol, tol_mode      stopping tolerance; 0 = relative, 1 = absolute
+ *   max_iter           iteration cap per segment
+ *   fixed_iters        if > 0, every segment runs exactly this many
+ *                      iterations and reports that count (no stopping rule)
+ *   init               0 = Kepler warm start, 1 = cold start
+ *   mu_sun, n_pert, pert[n_pert][7], epoch : force model
+ *   states_out[n][6]   final states
+ *   iters_out[n][S]    per-segment iteration counts / status
+ *   bounds_out         [n][S+1][6] segment-boundary states, or NULL
+ *   nodes_out          [n][S][N][6] converged node states, or NULL
+ *   nthreads           OpenMP threads (<= 0: library default)
+ * Returns the number of threads used.
+ */
+int orc_propagate(int n_ic, const double* ics, const double* t0, const double* tf,
+                  int N, int S, double tol, int tol_mode, int max_iter, int fixed_iters,
+                  int init, double mu_sun, int n_pert, const double* pert, double epoch,
+                  double* states_out, int* iters_out, double* bounds_out, double* nodes_out,
+                  int nthreads)
+{
+    int used = 1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    double* Tkj = (double*)malloc(sizeof(double) * (size_t)N * N);
+    double* tau = (double*)malloc(sizeof(double) * (size_t)N);
+    for (int k = 0; k < N; ++k)
+        for (int j = 0; j < N; ++j) Tkj[k * N + j] = orc_T(k, j, N);
+    for (int j = 0; j < N; ++j) tau[j] = orc_tau(j, N);
+    double mup[64];
+    int np = n_pert > 64 ? 64 : n_pert;
+    for (int p = 0; p < np; ++p) mup[p] = pert[7 * p];
+
+#pragma omp parallel
+    {
+#ifdef _OPENMP
+#pragma omp single
+        used = omp_get_num_threads();
+#endif
+        double* Y = (double*)malloc(sizeof(double) * (size_t)N * 6);
+        double* Yn = (double*)malloc(sizeof(double) * (size_t)N * 6);
+        double* G = (double*)malloc(sizeof(double) * (size_t)N * 6);
+        double* rp = (double*)malloc(sizeof(double) * (size_t)N * 3 * (np > 0 ? np : 1));
+        double* cbuf = (double*)malloc(sizeof(double) * (size_t)(N + 2));
+        double* bbuf = (double*)malloc(sizeof(double) * (size_t)(N + 2));
+#pragma omp for schedule(dynamic, 1)
+        for (int m = 0; m < n_ic; ++m) {
+            double y0[6];
+            memcpy(y0, ics + 6 * m, sizeof(y0));
+            int dead = 0;
+            for (int k = 0; k < 6; ++k) if (!isfinite(y0[k])) dead = 1;
+            if (bounds_out) memcpy(bounds_out + ((size_t)m * (S + 1)) * 6, y0, sizeof(y0));
+            for (int s = 0; s < S; ++s) {
+                int* it_out = iters_out + (size_t)m * S + s;
+                if (dead) {
+                    *it_out = -2;
+                    for (int k = 0; k < 6; ++k) y0[k] = NAN;
+                    if (bounds_out) memcpy(bounds_out + ((size_t)m * (S + 1) + s + 1) * 6, y0, sizeof(y0));
+                    if (nodes_out)
+                        for (int j = 0; j < N; ++j)
+                            memcpy(nodes_out + (((size_t)m * S + s) * N + j) * 6, y0, sizeof(y0));
+                    continue;
+                }
+                double h = (tf[m] - t0[m]) / (double)S;
+                double Ts = t0[m] + h * s;
+                double Te = t0[m] + h * (s + 1);
+                double w1 = 0.5 * (Te + Ts), w2 = 0.5 * (Te - Ts);
+                /* perturber positions at the nodes, before iterating (Sec. 5.4.1) */
+                for (int j = 0; j < N; ++j) {
+                    double tj = w2 * tau[j] + w1;
+                    for (int p = 0; p < np; ++p) orc_ephem(pert + 7 * p, epoch, tj, rp + 3 * (j * np + p));
+                }
+                /* initial guess */
+                int cold = (init == 1);
+                if (!cold) {
+                    for (int j = 0; j < N; ++j) {
+                        double dt = w2 * (tau[j] + 1.0);
+                        if (orc_kepler(y0, dt, Y + 6 * j) != 0) { cold = 1; break; }
+                    }
+                }
+                if (cold)
+                    for (int j = 0; j < N; ++j) memcpy(Y + 6 * j, y0, sizeof(y0));
+                /* Picard iterations */
+                int status = -1;
+                int n_it = fixed_iters > 0 ? fixed_iters : max_iter;
+                for (int it = 1; it <= n_it; ++it) {
+                    /* (i) force matrix */
+                    for (int j = 0; j < N; ++j) {
+                        double acc[3];
+                        orc_accel(Y + 6 * j, np, rp + 3 * j * np, mup, mu_sun, acc);
+                        for (int k = 0; k < 3; ++k) {
+                            G[6 * j + k] = w2 * Y[6 * j + 3 + k];
+                            G[6 * j + 3 + k] = w2 * acc[k];
+                        }
+                    }
+                    /* (ii)-(v) */
+                    orc_picard_update(N, 6, Tkj, G, y0, Yn, cbuf, bbuf);
+                    /* (vi) */
+                    double e = orc_iter_error(N, Yn, Y, tol_mode);
+                    double* tmp = Y; Y = Yn; Yn = tmp;   /* Y is now the newest iterate */
+                    if (isnan(e)) { status = -2; break; }
+                    if (fixed_iters > 0) { if (it == n_it) status = it; continue; }
+                    if (e < tol) { status = it; break; }
+                }
+                *it_out = status;
+                if (status == -2) dead = 1;
+                if (nodes_out)
+                    memcpy(nodes_out + (((size_t)m * S + s) * N) * 6, Y, sizeof(double) * 6 * N);
+                memcpy(y0, Y + 6 * (N - 1), sizeof(y0));
+                if (dead) for (int k = 0; k < 6; ++k) y0[k] = NAN;
+                if (bounds_out) memcpy(bounds_out + ((size_t)m * (S + 1) + s + 1) * 6, y0, sizeof(y0));
+            }
+            memcpy(states_out + 6 * m, y0, sizeof(y0));
+        }
+        free(Y); free(Yn); free(G); free(rp); free(cbuf); free(bbuf);
+    }
+    free(Tkj); free(tau);
+    return used;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Independent integrator for pinning: classical fixed-step RK4              */
+/* ------------------------------------------------------------------------ */
+
+static void orc_rhs(const double* y, double t, double mu_sun, int n_pert, const double* pert,
+                    double epoch, double* dy)
+{
+    double acc[3];
+    orc_accel_t(y, t, mu_sun, n_pert, pert, epoch, acc);
+    for (int k = 0; k < 3; ++k) { dy[k] = y[3 + k]; dy[3 + k] = acc[k]; }
+}
+
+/* Integrate y' = (v, a(r,t)) from t0 to tf with `nsteps` RK4 steps. */
+void orc_rk4(const double y0[6], double t0, double tf, long nsteps, double mu_sun, int n_pert,
+             const double* pert, double epoch, double y[6])
+{
+    double h = (tf - t0) / (double)nsteps;
+    double k1[6], k2[6], k3[6], k4[6], tmp[6];
+    memcpy(y, y0, sizeof(double) * 6);
+    for (long i = 0; i < nsteps; ++i) {
+        double t = t0 + h * (double)i;
+        orc_rhs(y, t, mu_sun, n_pert, pert, epoch, k1);
+        for (int k = 0; k < 6; ++k) tmp[k] = y[k] + 0.5 * h * k1[k];
+        orc_rhs(tmp, t + 0.5 * h, mu_sun, n_pert, pert, epoch, k2);
+        for (int k = 0; k < 6; ++k) tmp[k] = y[k] + 0.5 * h * k2[k];
+        orc_rhs(tmp, t + 0.5 * h, mu_sun, n_pert, pert, epoch, k3);
+        for (int k = 0; k < 6; ++k) tmp[k] = y[k] + h * k3[k];
+        orc_rhs(tmp, t + h, mu_sun, n_pert, pert, epoch, k4);
+        for (int k = 0; k < 6; ++k) y[k] += h / 6.0 * (k1[k] + 2.0 * k2[k] + 2.0 * k3[k] + k4[k]);
+    }
+}

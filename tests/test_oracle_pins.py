@@ -1,0 +1,359 @@
+"""Pins of the FP64 CPU oracle against what the mathematics fixes.
+
+Every check here compares the oracle with something other than itself: exact
+rational arithmetic, numpy's Chebyshev-series integration, Clenshaw-Curtis
+weights obtained from a moment system, a hand-derived force value, the
+gradient of the gravitational potential, scipy's DOP853 integrator, and
+conservation laws.  A dropped term, a wrong sign, a wrong index or a transposed
+operand anywhere in the oracle's steps fails at least one of them.
+"""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import numpy.polynomial.chebyshev as C
+import pytest
+from scipy.integrate import solve_ivp
+
+import oracle
+from paper_2301_03989_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------------------
+# Nodes (Sec. 2.2, eq. chnodes2)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("N", [3, 4, 5, 64, 128, 200, 256])
+def test_nodes_are_extrema_of_T_N_minus_1(N):
+    tau = oracle.nodes(N)
+    assert tau[0] == -1.0 and tau[-1] == 1.0
+    assert np.all(np.diff(tau) > 0)
+    np.testing.assert_allclose(tau, -tau[::-1], atol=1e-15)
+    # the CGL nodes are where T_{N-1} = +-1, alternating, starting at (-1)^(N-1)
+    vals = C.chebval(tau, [0] * (N - 1) + [1])
+    np.testing.assert_allclose(vals, [(-1) ** (N - 1 - j) for j in range(N)], atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Fit + integrate + evaluate (Sec. 2.2: B_1 = S A F + 2 y_0, B_j = A F, Y = C B)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("N", [3, 4, 7, 16, 64, 128, 200, 256])
+def test_update_integrates_polynomials_of_degree_N_minus_2_exactly(N):
+    rng = np.random.default_rng(N)
+    tau = np.cos(np.pi * (N - 1 - np.arange(N)) / (N - 1))
+    for deg in sorted({0, 1, max(0, N // 2), N - 2}):
+        coef = rng.standard_normal(deg + 1) / np.arange(1, deg + 2)   # Chebyshev series of p
+        g = C.chebval(tau, coef)
+        y0 = rng.standard_normal()
+        P = C.chebint(coef)                    # antiderivative, independent of the oracle
+        expect = y0 + C.chebval(tau, P) - C.chebval(-1.0, P)
+        got = oracle.picard_step(g, [y0])[:, 0]
+        scale = 1.0 + np.abs(expect).max()
+        np.testing.assert_allclose(got, expect, rtol=0, atol=2e-14 * scale * max(1, N / 64))
+
+
+@pytest.mark.parametrize("N", [3, 4, 9, 64, 128, 256])
+def test_update_annihilates_the_aliased_mode(N):
+    # g_j = (-1)^j = T_{N-1}(tau_j) up to sign: orthogonal to degree <= N-2 in the
+    # discrete inner product, so the degree N-2 fit is zero and y stays y0.
+    g = np.array([(-1.0) ** j for j in range(N)])
+    y = oracle.picard_step(g, [0.75])[:, 0]
+    np.testing.assert_allclose(y, 0.75, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("N", [3, 4, 64, 128, 256])
+def test_first_node_returns_the_initial_condition(N):
+    rng = np.random.default_rng(7)
+    g = rng.standard_normal((N, 6))
+    y0 = rng.standard_normal(6)
+    y = oracle.picard_step(g, y0)
+    np.testing.assert_allclose(y[0], y0, rtol=0, atol=1e-13 * N)
+
+
+def _exact_operator(taus):
+    """Exact rational operator for rational nodes: weighted least squares fit of
+    degree N-2 in the monomial basis (weights 1/2 at both ends, 1 inside, the
+    discrete inner product that makes T_0..T_{N-2} orthogonal), then exact
+    integration from -1.  Independent of the oracle's Chebyshev recurrences."""
+    N = len(taus)
+    d = N - 2
+    w = [Fraction(1, 2)] + [Fraction(1)] * (N - 2) + [Fraction(1, 2)]
+    V = [[t ** k for k in range(d + 1)] for t in taus]
+    M = [[sum(w[j] * V[j][a] * V[j][b] for j in range(N)) for b in range(d + 1)] for a in range(d + 1)]
+    K = [[Fraction(0)] * N for _ in range(N)]
+    for l in range(N):
+        rhs = [w[l] * V[l][a] for a in range(d + 1)]
+        # solve M x = rhs (Gauss-Jordan, exact)
+        A = [row[:] + [rhs[i]] for i, row in enumerate(M)]
+        n = d + 1
+        for c in range(n):
+            piv = next(r for r in range(c, n) if A[r][c] != 0)
+            A[c], A[piv] = A[piv], A[c]
+            A[c] = [x / A[c][c] for x in A[c]]
+            for r in range(n):
+                if r != c and A[r][c] != 0:
+                    f = A[r][c]
+                    A[r] = [x - f * y for x, y in zip(A[r], A[c])]
+        coef = [A[i][n] for i in range(n)]
+        for j, t in enumerate(taus):
+            K[j][l] = sum(coef[k] * (t ** (k + 1) - Fraction(-1) ** (k + 1)) / (k + 1) for k in range(n))
+    return K
+
+
+@pytest.mark.parametrize("taus", [
+    [Fraction(-1), Fraction(0), Fraction(1)],
+    [Fraction(-1), Fraction(-1, 2), Fraction(1, 2), Fraction(1)],
+])
+def test_small_operators_match_exact_rationals(taus):
+    N = len(taus)
+    K = _exact_operator(taus)
+    got = oracle.operator(N)
+    np.testing.assert_allclose(got, np.array([[float(x) for x in row] for row in K]), rtol=0, atol=1e-15)
+    if N == 3:   # the trapezoid rules on the linear least-squares fit
+        assert K == [[0, 0, 0], [Fraction(1, 2), Fraction(1, 2), 0], [Fraction(1, 2), 1, Fraction(1, 2)]]
+
+
+@pytest.mark.parametrize("N", [4, 16, 64, 128, 256])
+def test_last_row_is_clenshaw_curtis_for_even_N(N):
+    # CC weights from the moment system sum_j w_j T_k(tau_j) = int_{-1}^{1} T_k, k < N
+    tau = np.cos(np.pi * (N - 1 - np.arange(N)) / (N - 1))
+    A = np.array([C.chebval(tau, [0] * k + [1]) for k in range(N)])
+    mom = np.array([0.0 if k % 2 else 2.0 / (1.0 - k * k) for k in range(N)])
+    w = np.linalg.solve(A, mom)
+    np.testing.assert_allclose(oracle.operator(N)[-1], w, rtol=0, atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# Force model
+# ---------------------------------------------------------------------------
+def test_force_hand_value():
+    rows = np.loadtxt(os.path.join(GOLDEN, "force_hand.txt"), ndmin=2)
+    for row in rows:
+        mu_s, r, mup, rp, a = row[0], row[1:4], row[4], row[5:8], row[8:11]
+        got = oracle.accel(r, rp[None, :], [mup], mu_s)
+        np.testing.assert_allclose(got, a, rtol=0, atol=4e-16)
+
+
+def test_force_sun_only_and_massless_perturbers():
+    r = np.array([0.3, -0.6, 0.2])
+    a0 = oracle.accel(r, np.zeros((0, 3)), [], 1.0)
+    np.testing.assert_allclose(a0, -r / np.linalg.norm(r) ** 3, rtol=1e-15)
+    a1 = oracle.accel(r, np.array([[0.7, 0.1, 0.0], [5.0, 1.0, 0.1]]), [0.0, 0.0], 1.0)
+    assert np.array_equal(a0, a1)
+
+
+def test_force_is_gradient_of_potential():
+    rng = np.random.default_rng(3)
+    rp = rng.uniform(-2, 2, (4, 3))
+    mup = np.array([0.05, 0.02, 0.1, 0.01])
+
+    def U(r):
+        u = 1.0 / np.linalg.norm(r)
+        for q, m in zip(rp, mup):
+            u += m * (1.0 / np.linalg.norm(r - q) - r @ q / np.linalg.norm(q) ** 3)
+        return u
+
+    for _ in range(5):
+        r = rng.uniform(-1.5, 1.5, 3)
+        h = 1e-5
+        grad = np.array([(U(r + h * e) - U(r - h * e)) / (2 * h) for e in np.eye(3)])
+        a = oracle.accel(r, rp, mup, 1.0)
+        np.testing.assert_allclose(a, grad, rtol=0, atol=1e-8 * np.linalg.norm(a))
+
+
+# ---------------------------------------------------------------------------
+# Perturber ephemeris (two-body Kepler orbits)
+# ---------------------------------------------------------------------------
+def test_ephemeris_circular_equatorial_closed_form():
+    el = [0.0, 1.5, 0.0, 0.0, 0.0, 0.0, 0.3]
+    n = 1.5 ** -1.5
+    for t in (0.0, 1.0, 7.3, -2.0):
+        r = oracle.ephem(el, 0.0, t)
+        ang = 0.3 + n * t
+        np.testing.assert_allclose(r, [1.5 * math.cos(ang), 1.5 * math.sin(ang), 0.0], atol=1e-14)
+
+
+def test_ephemeris_plane_radius_and_period():
+    for el in W.planet_elements():
+        a, e, inc, raan = el[1], el[2], el[3], el[4]
+        h = np.array([math.sin(inc) * math.sin(raan), -math.sin(inc) * math.cos(raan), math.cos(inc)])
+        P = 2 * math.pi * a ** 1.5
+        ts = np.linspace(0, P, 97)
+        rs = np.array([oracle.ephem(el, 0.0, t) for t in ts])
+        rn = np.linalg.norm(rs, axis=1)
+        assert np.abs(rs @ h).max() < 1e-13 * a
+        assert rn.min() >= a * (1 - e) * (1 - 1e-12) and rn.max() <= a * (1 + e) * (1 + 1e-12)
+        np.testing.assert_allclose(rs[-1], rs[0], atol=1e-11 * a)
+
+
+# ---------------------------------------------------------------------------
+# Two-body warm start (Sec. 2.1: Keplerian initial guess)
+# ---------------------------------------------------------------------------
+def _twobody_dop853(y0, dt):
+    f = lambda t, y: np.concatenate([y[3:], -y[:3] / np.linalg.norm(y[:3]) ** 3])
+    sol = solve_ivp(f, (0.0, dt), y0, method="DOP853", rtol=1e-13, atol=1e-15)
+    return sol.y[:, -1]
+
+
+def test_kepler_matches_dop853_and_conserves():
+    w = W.uneven_batch(64, seed=11)      # eccentricities up to 0.6
+    for y0 in w.ics[:12]:
+        for dt in (0.37, -1.1, 4.0):
+            ok, y = oracle.kepler(y0, dt)
+            assert ok
+            ref = _twobody_dop853(y0, dt)
+            np.testing.assert_allclose(y, ref, rtol=0, atol=1e-10 * np.abs(ref).max())
+            E0 = 0.5 * y0[3:] @ y0[3:] - 1 / np.linalg.norm(y0[:3])
+            E1 = 0.5 * y[3:] @ y[3:] - 1 / np.linalg.norm(y[:3])
+            assert abs(E1 - E0) < 1e-13
+            np.testing.assert_allclose(np.cross(y[:3], y[3:]), np.cross(y0[:3], y0[3:]), atol=1e-13)
+
+
+def test_kepler_period_and_circular_and_hyperbolic():
+    w = W.sun_only_kepler(8, seed=5)
+    for y0, P in zip(w.ics, w.meta["period"]):
+        ok, y = oracle.kepler(y0, P)
+        assert ok
+        np.testing.assert_allclose(y, y0, atol=2e-13)
+    ok, y = oracle.kepler([1, 0, 0, 0, 1, 0], math.pi / 2)
+    np.testing.assert_allclose(y, [0, 1, 0, -1, 0, 0], atol=1e-15)
+    ok, _ = oracle.kepler([1, 0, 0, 0, 1.5, 0], 1.0)
+    assert not ok
+
+
+# ---------------------------------------------------------------------------
+# Whole map
+# ---------------------------------------------------------------------------
+def test_sun_only_nodes_match_kepler_closed_form():
+    w = W.sun_only_kepler(16)
+    t0 = np.array([g.t0 for g in w.groups])
+    tf = np.array([g.tf for g in w.groups])
+    st, it, nodes = oracle.propagate(w.ics, t0, tf, 64, 4, 1e-13, init=1, want_nodes=True)
+    assert (it > 0).all()
+    tau = oracle.nodes(64)
+    for m in range(w.n_ic):
+        h = (tf[m] - t0[m]) / 4
+        for s in range(4):
+            for j in range(0, 64, 9):
+                dt = h * s + 0.5 * h * (tau[j] + 1)
+                ok, ref = oracle.kepler(w.ics[m], dt)
+                y = nodes[m, s, j]
+                assert np.linalg.norm(y[:3] - ref[:3]) / np.linalg.norm(ref[:3]) < 1e-11
+                assert np.linalg.norm(y[3:] - ref[3:]) / np.linalg.norm(ref[3:]) < 1e-11
+        # invariants along the trajectory
+        ys = nodes[m].reshape(-1, 6)
+        En = 0.5 * (ys[:, 3:] ** 2).sum(1) - 1 / np.linalg.norm(ys[:, :3], axis=1)
+        assert np.ptp(En) < 1e-12
+        hv = np.cross(ys[:, :3], ys[:, 3:])
+        assert np.abs(hv - hv[0]).max() < 1e-12
+    # one period brings every IC back to its start
+    np.testing.assert_allclose(st, w.ics, rtol=0, atol=1e-11)
+
+
+def test_massless_perturbers_reduce_to_sun_only_exactly():
+    w = W.sun_only_kepler(6)
+    tf = np.array([g.tf for g in w.groups])
+    pert = W.planet_elements().copy()
+    pert[:, 0] = 0.0
+    a, ia = oracle.propagate(w.ics, 0.0, tf, 64, 4, 1e-13, init=0)
+    b, ib = oracle.propagate(w.ics, 0.0, tf, 64, 4, 1e-13, oracle.Model(1.0, pert), init=0)
+    assert np.array_equal(a, b) and np.array_equal(ia, ib)
+
+
+def _nbody_dop853(y0, t0, tf, model):
+    def f(t, y):
+        return np.concatenate([y[3:], oracle.accel_t(y[:3], t, model)])
+    sol = solve_ivp(f, (t0, tf), y0, method="DOP853", rtol=1e-13, atol=1e-16)
+    return sol.y[:, -1]
+
+
+def test_nbody_matches_dop853():
+    w = W.nbody_venus(4)
+    g = w.groups[0]
+    model = oracle.Model(1.0, w.pert)
+    st, it = oracle.propagate(w.ics, g.t0, g.tf, g.nodes, g.segments, g.tol, model)
+    assert (it > 0).all()
+    for m in range(w.n_ic):
+        ref = _nbody_dop853(w.ics[m], g.t0, g.tf, model)
+        assert np.linalg.norm(st[m, :3] - ref[:3]) / np.linalg.norm(ref[:3]) < 1e-10
+        assert np.linalg.norm(st[m, 3:] - ref[3:]) / np.linalg.norm(ref[3:]) < 1e-10
+
+
+def test_nbody_backward_returns_to_start():
+    w = W.nbody_venus(3)
+    g = w.groups[0]
+    model = oracle.Model(1.0, w.pert)
+    fwd, _ = oracle.propagate(w.ics, g.t0, g.tf, g.nodes, g.segments, 1e-13, model)
+    back, it = oracle.propagate(fwd, g.tf, g.t0, g.nodes, g.segments, 1e-13, model)
+    assert (it > 0).all()
+    np.testing.assert_allclose(back, w.ics, rtol=0, atol=5e-11)
+
+
+def test_resume_from_segment_boundary_equals_single_run():
+    w = W.nbody_venus(3)
+    g = w.groups[0]
+    model = oracle.Model(1.0, w.pert)
+    full, _, bounds = oracle.propagate(w.ics, g.t0, g.tf, g.nodes, 8, g.tol, model, want_bounds=True)
+    h = (g.tf - g.t0) / 8
+    mid = bounds[:, 3]
+    rest, _ = oracle.propagate(mid, g.t0 + 3 * h, g.tf, g.nodes, 5, g.tol, model)
+    np.testing.assert_allclose(rest, full, rtol=0, atol=1e-12)
+
+
+def test_reference_orbit_keeps_clear_of_venus():
+    w = W.nbody_venus(1)
+    g = w.groups[0]
+    w.ics[0] = W._perturbed_ensemble(1, 0, 0.0, 0.0)[0]
+    model = oracle.Model(1.0, w.pert)
+    _, _, nodes = oracle.propagate(w.ics, g.t0, g.tf, g.nodes, g.segments, g.tol, model, want_nodes=True)
+    tau = oracle.nodes(g.nodes)
+    h = (g.tf - g.t0) / g.segments
+    dmin = np.inf
+    for s in range(g.segments):
+        for j in range(g.nodes):
+            t = g.t0 + h * s + 0.5 * h * (tau[j] + 1)
+            dmin = min(dmin, np.linalg.norm(nodes[0, s, j, :3] - oracle.ephem(w.pert[1], 0.0, t)))
+    assert 0.05 <= dmin < 0.2
+
+
+def test_status_codes_and_fixed_iterations():
+    w = W.nbody_venus(3)
+    g = w.groups[0]
+    model = oracle.Model(1.0, w.pert)
+    _, it = oracle.propagate(w.ics, g.t0, g.tf, g.nodes, 2, 1e-16, model, max_iter=1)
+    assert (it == -1).all()
+    _, it = oracle.propagate(w.ics, g.t0, g.tf, g.nodes, 2, 1e-12, model, fixed_iters=5)
+    assert (it == 5).all()
+    bad = w.ics.copy()
+    bad[1, 2] = np.nan
+    st, it = oracle.propagate(bad, g.t0, g.tf, g.nodes, 2, 1e-12, model)
+    assert (it[1] == -2).all() and np.isnan(st[1]).all()
+    assert (it[[0, 2]] > 0).all()
+
+
+def test_ephemeris_obeys_two_body_dynamics():
+    # second differences of the ephemeris must equal the two-body acceleration
+    for el in [[0.0, 0.8, 0.5, 0.3, 1.0, 2.0, 0.4], [0.0, 1.3, 0.2, 0.05, 4.0, 0.7, 3.0]]:
+        h = 1e-3
+        for t in (0.0, 0.9, 2.5):
+            rm, r0, rp = (oracle.ephem(el, 0.0, t + d) for d in (-h, 0.0, h))
+            acc = (rp - 2 * r0 + rm) / h ** 2
+            np.testing.assert_allclose(acc, -r0 / np.linalg.norm(r0) ** 3, rtol=0, atol=1e-5)
+            hv = 1e-4
+            v = (oracle.ephem(el, 0.0, t + hv) - oracle.ephem(el, 0.0, t - hv)) / (2 * hv)
+            energy = 0.5 * v @ v - 1 / np.linalg.norm(r0)
+            assert abs(energy + 1 / (2 * el[1])) < 1e-7
+
+
+def test_iteration_count_convention():
+    # Sun-only with the Kepler warm start: the guess is already the solution, so
+    # the first iterate differs from it only by rounding and stops at i = 1.
+    w = W.sun_only_kepler(8)
+    tf = np.array([g.tf for g in w.groups])
+    _, it = oracle.propagate(w.ics, 0.0, tf, 64, 4, 1e-12, init=0)
+    assert (it == 1).all()
+    # any finite first error is below a huge tolerance: one iteration, cold start too
+    _, it = oracle.propagate(w.ics, 0.0, tf, 64, 4, 1e3, init=1)
+    assert (it == 1).all()
