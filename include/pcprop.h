@@ -1,0 +1,183 @@
+/*
+ * pcprop.h -- C ABI of the batched Picard-Chebyshev propagator for AMD MI355X (gfx950).
+ *
+ * Method: Masat, Colombo, Boutonnet, "GPU-based high-precision orbital propagation of
+ * large sets of initial conditions through Picard-Chebyshev augmentation"
+ * (arXiv 2301.03989).  The initial value problem is dx/dt = f(x, t), x(t0) = x0
+ * (Sec. 2.1, eq. ibvp); each Picard iteration evaluates the dynamics at the N
+ * Chebyshev-Gauss-Lobatto nodes of a segment, refits and integrates the Chebyshev
+ * coefficients and evaluates the new iterate at the nodes (Sec. 2.2, matrix form:
+ * F = w2 f(y, t), B_1 = S A F + 2 y_0, B_j = A F, y = C B), until the largest change
+ * between two iterates falls below a tolerance (Sec. 2.2).  Many initial conditions
+ * (ICs) are stacked into one augmented system (Sec. 3.1) and groups of them with
+ * different settings form the second augmentation level (Sec. 3.2).  Long spans are
+ * split into segments integrated in sequence, forward or backward (Sec. 2.2).
+ *
+ * Conventions for every entry point:
+ *   - Return PC_OK (0) or one of the PC_E* codes below; no exception crosses the ABI.
+ *   - Pointers marked "device" are HIP device allocations owned by the caller,
+ *     contiguous, float64 unless noted.  Pointers marked "host" are host memory owned
+ *     by the caller.  No pointer is retained after a call returns.
+ *   - Work is ordered on `stream` (a hipStream_t; NULL is the null stream).  Calls that
+ *     report a status return only after the stream has finished their work.
+ *   - Units are the caller's; the workloads use mu_Sun = 1, AU and TU = 1/k days.
+ *   - ICs are rows of six values (x, y, z, vx, vy, vz); output order = input order.
+ *   - tf < t0 integrates backward in time.
+ *   - A pc_ctx is used by one host thread at a time.
+ */
+#ifndef PCPROP_H
+#define PCPROP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define PC_OK          0  /* success */
+#define PC_EINVAL      1  /* invalid argument (null pointer, size out of range, bad model...) */
+#define PC_ENOTCONV    2  /* at least one IC hit max_iter in some segment; outputs are written */
+#define PC_ENONFINITE  3  /* at least one IC became non-finite (or was given non-finite); outputs written */
+#define PC_EHIP        4  /* a HIP runtime call failed */
+#define PC_ENOMEM      5  /* workspace too small (see pc_workspace_bytes) */
+
+/* Per-IC, per-segment iteration records written to iters_out:
+ *   k >= 1            the segment converged after k Picard iterations
+ *   PC_ITER_NOTCONV   max_iter reached; the last iterate is kept and chained on
+ *   PC_ITER_NONFINITE the state became non-finite; this and every later segment  */
+#define PC_ITER_NOTCONV    (-1)
+#define PC_ITER_NONFINITE  (-2)
+
+#define PC_MAX_NODES  256  /* N per segment: 3 .. 256 */
+#define PC_MAX_PERT   16   /* perturbing bodies */
+
+typedef struct pc_ctx pc_ctx;     /* owns the cached operators per node count */
+typedef void* pc_stream_t;        /* a hipStream_t */
+
+/* Force model: a(r, t) = -mu_sun r/|r|^3 - sum_p mu_p [(r - r_p)/|r - r_p|^3 + r_p/|r_p|^3],
+ * a point-mass, heliocentric form (with the indirect term) of the restricted N-body
+ * dynamics of Sec. 5.4.1, with perturber p on a two-body Keplerian orbit about the
+ * central body (gravitational parameter 1).  Perturber positions are evaluated once
+ * per node before the iterations, as Sec. 5.4.1 does for its ephemerides. */
+typedef struct {
+    double mu_sun;        /* central body's gravitational parameter */
+    int32_t n_pert;       /* 0 .. PC_MAX_PERT; 0 = two-body dynamics */
+    const double* pert;   /* host [n_pert][7]: mu_p, a, e, inc, raan, argp, M0 (radians);
+                             M0 is the mean anomaly at `epoch`; 0 <= e < 1, a > 0 */
+    double epoch;
+} pc_model;
+
+enum { PC_INIT_KEPLER = 0, PC_INIT_COLD = 1 };   /* initial guess, Sec. 2.1 (warm / cold start) */
+enum { PC_TOL_REL = 0, PC_TOL_ABS = 1 };         /* relative or absolute stopping rule, Sec. 2.2 */
+enum { PC_FP64 = 0 };                            /* arithmetic of the sweeps */
+enum { PC_PATH_FUSED = 0, PC_PATH_PLAIN = 1 };   /* one persistent launch / per-iteration kernels */
+
+typedef struct {
+    int32_t init;         /* PC_INIT_KEPLER (default) or PC_INIT_COLD */
+    int32_t max_iter;     /* Picard iterations per segment before PC_ITER_NOTCONV (default 64) */
+    int32_t tol_mode;     /* PC_TOL_REL (default) or PC_TOL_ABS */
+    int32_t precision;    /* PC_FP64 */
+    int32_t path;         /* PC_PATH_FUSED (default) or PC_PATH_PLAIN */
+    int32_t fixed_iters;  /* > 0: run exactly this many iterations per segment (no stopping rule) */
+    int32_t tile_pairs;   /* nodes x ICs held by one workgroup: 0 = tuned table, 1024 or 2048 */
+    int32_t reserved;
+} pc_opts;
+
+/* One outer-level group of the two-level augmentation (Sec. 3.2): ICs
+ * [ic_offset, ic_offset + n_ic) share the interval, node count, segment count and
+ * tolerance.  Segment s spans [t0 + s h, t0 + (s+1) h], h = (tf - t0)/segments. */
+typedef struct {
+    int64_t ic_offset;
+    int64_t n_ic;         /* >= 1 */
+    double t0, tf;        /* t0 != tf, both finite */
+    int32_t nodes;        /* 3 .. PC_MAX_NODES */
+    int32_t segments;     /* >= 1 */
+    double tol;           /* > 0, finite */
+} pc_group;
+
+/* Fill `opts` with the defaults listed above. */
+void pc_default_opts(pc_opts* opts);
+
+/* Create a context on HIP device `device`.  *out receives the context. */
+int pc_ctx_create(int device, pc_ctx** out);
+void pc_ctx_destroy(pc_ctx* ctx);
+
+/* Bytes of device workspace that pc_propagate_batched needs for these groups. */
+int pc_workspace_bytes(pc_ctx* ctx, const pc_group* groups /* host [n_groups] */, int32_t n_groups,
+                       const pc_model* model, const pc_opts* opts, size_t* bytes /* host out */);
+
+/* Propagate n_ic ICs over [t0, tf] in `segments` segments of `nodes` CGL nodes, each
+ * iterated until max_j max(|dr_j|/|r_j|, |dv_j|/|v_j|) < tol (Sec. 2.2, Sec. 5.4.2),
+ * per IC (the per-block error of Sec. 3.2 with blocks of one member).
+ *   ics        device [n_ic][6]          initial states at t0
+ *   states_out device [n_ic][6]          states at tf
+ *   iters_out  device int32 [n_ic][segments] iteration records, or NULL
+ *   workspace  device, ws_bytes >= pc_workspace_bytes(one group)
+ * Equivalent to pc_propagate_batched with a single group. */
+int pc_propagate(pc_ctx* ctx, const double* ics, int64_t n_ic, double t0, double tf,
+                 int32_t nodes, int32_t segments, double tol,
+                 const pc_model* model, const pc_opts* opts /* NULL = defaults */,
+                 double* states_out, int32_t* iters_out,
+                 void* workspace, size_t ws_bytes, pc_stream_t stream);
+
+/* Two-level augmented propagation (Sec. 3.2): all groups in one call.
+ *   ics          device [n_ic][6]; groups index into it and must not overlap
+ *   states_out   device [n_ic][6]
+ *   iters_out    device int32 [n_ic][iters_stride] or NULL; iters_stride >= every group's
+ *                segment count; unused columns are left untouched
+ *   bounds_out   device [n_ic][iters_stride + 1][6] segment-boundary states, or NULL
+ *   nodes_out    device [n_ic][iters_stride][nodes_stride][6] final node states of every
+ *                segment, or NULL; nodes_stride >= every group's node count
+ * The fused path runs every group in one launch; the plain path runs each group with
+ * per-iteration kernels and a host-side loop (the structure of Sec. 5.4). */
+int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic,
+                         const pc_group* groups /* host */, int32_t n_groups,
+                         const pc_model* model, const pc_opts* opts,
+                         double* states_out, int32_t* iters_out, int32_t iters_stride,
+                         double* bounds_out, double* nodes_out, int32_t nodes_stride,
+                         void* workspace, size_t ws_bytes, pc_stream_t stream);
+
+/* ---- operator and kernel-level entry points (used by the tests) ---- */
+
+/* The N x N matrix K_N with y_j = y_0 + sum_l K_N[j][l] g_l for the w2-scaled force
+ * samples g (steps F -> B -> y of Sec. 2.2 folded into one product).  K_host: host
+ * [nodes][nodes], row-major. */
+int pc_get_operator(pc_ctx* ctx, int32_t nodes, double* K_host);
+
+/* Y[j][c] = y0[c] + scale * sum_l K_N[j][l] F[l][c] on the GPU's FP64 matrix cores.
+ *   F device [nodes][n_cols], y0 device [n_cols], Y device [nodes][n_cols]. */
+int pc_apply_operator(pc_ctx* ctx, int32_t nodes, int64_t n_cols, const double* F,
+                      const double* y0, double scale, double* Y, pc_stream_t stream);
+
+/* Accelerations of the force model at n points: r device [3][n], t device [n],
+ * a_out device [3][n]. */
+int pc_eval_force(pc_ctx* ctx, const double* r, const double* t, int64_t n,
+                  const pc_model* model, double* a_out, pc_stream_t stream);
+
+/* Two-body (mu = 1) propagation used by the warm start (Sec. 2.1): y0 device [6][n],
+ * dt device [n] -> y device [6][n]; ok device int32 [n] (1 = elliptic orbit solved). */
+int pc_eval_kepler(pc_ctx* ctx, const double* y0, const double* dt, int64_t n,
+                   double* y, int32_t* ok, pc_stream_t stream);
+
+/* Kernel timing of the next calls: when enabled, pc_propagate_batched records HIP events
+ * on its stream around its propagation kernels (not the ephemeris table build or the
+ * copies), and pc_last_kernel_ms returns the elapsed time of the last such call in
+ * milliseconds.  Used by the benchmark for the roofline figure. */
+int pc_set_timing(pc_ctx* ctx, int enable);
+int pc_last_kernel_ms(pc_ctx* ctx, double* ms /* host out */);
+
+/* Message for a status code (static storage). */
+const char* pc_strerror(int code);
+
+/* Detail of the last error raised in this context (static per context). */
+const char* pc_last_error(pc_ctx* ctx);
+
+/* Library version, 100 * major + minor. */
+int pc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PCPROP_H */

@@ -1,0 +1,597 @@
+// pc_api.hip -- host side of the C ABI declared in include/pcprop.h.
+//
+// Plans a call (operators per node count, groups, jobs, ephemeris records), stages the
+// descriptor tables in pinned host memory, copies them into the caller's workspace on
+// the caller's stream and launches the kernels of pc_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "pcprop.h"
+#include "pc_internal.h"
+
+namespace {
+
+struct OperatorCache {
+    int N = 0, NP = 0;
+    double* kfrag = nullptr;   // device, [NP/16][NP/4][64]
+    double* tau = nullptr;     // device, [NP]
+    std::vector<double> K;     // host copy, [N][N]
+};
+
+}  // namespace
+
+struct pc_ctx {
+    int device = 0;
+    std::map<int, OperatorCache> ops;
+    void* staging = nullptr;        // pinned host memory for descriptor tables
+    size_t staging_bytes = 0;
+    PcBodyDev* d_bodies = nullptr;  // device copy of the perturber table (test hooks)
+    bool timing = false;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double last_ms = -1.0;
+    char last_error[512] = {0};
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int set_error(pc_ctx* ctx, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+int set_error(pc_ctx* ctx, int code, const char* fmt, ...)
+{
+    if (ctx) {
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(ctx->last_error, sizeof(ctx->last_error), fmt, ap);
+        va_end(ap);
+    }
+    return code;
+}
+
+#define PC_HIP(ctx, call)                                                                     \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return set_error(ctx, PC_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));  \
+    } while (0)
+
+int padded_nodes(int N)
+{
+    int np = 16;
+    while (np < N) np <<= 1;
+    return np;
+}
+
+// T_k at node j of the N-point CGL grid: tau_j = cos(pi (N-1-j)/(N-1)), so
+// T_k(tau_j) = cos(pi k (N-1-j)/(N-1)), with the integer angle reduced exactly.
+long double cheb_at_node(int k, int j, int N)
+{
+    const long double pi = 3.141592653589793238462643383279502884L;
+    long m = ((long)k * (long)(N - 1 - j)) % (2L * (N - 1));
+    if (m > N - 1) m = 2L * (N - 1) - m;
+    return cosl(pi * (long double)m / (long double)(N - 1));
+}
+
+// K_N such that y_j = y_0 + sum_l K_N[j][l] g_l (Sec. 2.2 with A, C, S folded):
+// fit g with the degree N-2 Chebyshev series c_k = 2/(N-1) sum''_l g_l T_k(tau_l),
+// integrate term by term, b_k = (c_{k-1} - c_{k+1})/(2k), and pin the constant so that
+// y(tau = -1) = y_0, which leaves y_j - y_0 = sum_{k>=1} b_k (T_k(tau_j) - (-1)^k).
+// Accumulated in long double, rounded once.
+void build_operator(int N, std::vector<double>& K)
+{
+    std::vector<long double> D((size_t)(N + 1) * N, 0.0L);   // fit coefficients c_m per unit g_l
+    for (int m = 0; m <= N - 2; ++m)
+        for (int l = 0; l < N; ++l) {
+            const long double w = (l == 0 || l == N - 1) ? 0.5L : 1.0L;
+            D[(size_t)m * N + l] = 2.0L / (long double)(N - 1) * w * cheb_at_node(m, l, N);
+        }
+    std::vector<long double> Bc((size_t)N * N, 0.0L);        // integrated coefficients b_k per g_l
+    for (int k = 1; k <= N - 1; ++k)
+        for (int l = 0; l < N; ++l) {
+            const long double lo = D[(size_t)(k - 1) * N + l];
+            const long double up = (k + 1 <= N - 2) ? D[(size_t)(k + 1) * N + l] : 0.0L;
+            Bc[(size_t)k * N + l] = (lo - up) / (2.0L * k);
+        }
+    K.assign((size_t)N * N, 0.0);
+    std::vector<long double> E(N);
+    for (int j = 1; j < N; ++j) {                              // row 0 is exactly zero
+        for (int k = 1; k <= N - 1; ++k) E[k] = cheb_at_node(k, j, N) - ((k & 1) ? -1.0L : 1.0L);
+        for (int l = 0; l < N; ++l) {
+            long double s = 0.0L;
+            for (int k = 1; k <= N - 1; ++k) s += E[k] * Bc[(size_t)k * N + l];
+            K[(size_t)j * N + l] = (double)s;
+        }
+    }
+}
+
+int get_operator(pc_ctx* ctx, int N, const OperatorCache** out)
+{
+    auto it = ctx->ops.find(N);
+    if (it != ctx->ops.end()) {
+        *out = &it->second;
+        return PC_OK;
+    }
+    OperatorCache oc;
+    oc.N = N;
+    oc.NP = padded_nodes(N);
+    build_operator(N, oc.K);
+    const int NP = oc.NP, NQ = NP / 4;
+    std::vector<double> frag((size_t)NP * NP, 0.0);
+    for (int strip = 0; strip < NP / 16; ++strip)
+        for (int q = 0; q < NQ; ++q)
+            for (int lane = 0; lane < 64; ++lane) {
+                const int row = 16 * strip + (lane & 15), col = 4 * q + (lane >> 4);
+                frag[((size_t)strip * NQ + q) * 64 + lane] =
+                    (row < N && col < N) ? oc.K[(size_t)row * N + col] : 0.0;
+            }
+    std::vector<double> tau(NP, 0.0);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int j = 0; j < N; ++j) tau[j] = (double)(-cosl(pi * (long double)j / (long double)(N - 1)));
+    PC_HIP(ctx, hipSetDevice(ctx->device));
+    PC_HIP(ctx, hipMalloc(&oc.kfrag, frag.size() * sizeof(double)));
+    PC_HIP(ctx, hipMalloc(&oc.tau, tau.size() * sizeof(double)));
+    PC_HIP(ctx, hipMemcpy(oc.kfrag, frag.data(), frag.size() * sizeof(double), hipMemcpyHostToDevice));
+    PC_HIP(ctx, hipMemcpy(oc.tau, tau.data(), tau.size() * sizeof(double), hipMemcpyHostToDevice));
+    auto res = ctx->ops.emplace(N, std::move(oc));
+    *out = &res.first->second;
+    return PC_OK;
+}
+
+int ensure_staging(pc_ctx* ctx, size_t bytes)
+{
+    if (bytes <= ctx->staging_bytes) return PC_OK;
+    if (ctx->staging) {
+        PC_HIP(ctx, hipHostFree(ctx->staging));
+        ctx->staging = nullptr;
+        ctx->staging_bytes = 0;
+    }
+    size_t cap = std::max<size_t>(bytes, 1 << 20);
+    PC_HIP(ctx, hipHostMalloc(&ctx->staging, cap, hipHostMallocDefault));
+    ctx->staging_bytes = cap;
+    return PC_OK;
+}
+
+int validate_model(pc_ctx* ctx, const pc_model* model)
+{
+    if (!model) return set_error(ctx, PC_EINVAL, "model is NULL");
+    if (!(model->mu_sun > 0.0) || !std::isfinite(model->mu_sun))
+        return set_error(ctx, PC_EINVAL, "mu_sun must be positive and finite");
+    if (model->n_pert < 0 || model->n_pert > PC_MAX_PERT)
+        return set_error(ctx, PC_EINVAL, "n_pert must be in [0, %d]", PC_MAX_PERT);
+    if (model->n_pert > 0 && !model->pert) return set_error(ctx, PC_EINVAL, "pert is NULL");
+    if (!std::isfinite(model->epoch)) return set_error(ctx, PC_EINVAL, "epoch not finite");
+    for (int p = 0; p < model->n_pert; ++p) {
+        const double* el = model->pert + 7 * p;
+        for (int k = 0; k < 7; ++k)
+            if (!std::isfinite(el[k])) return set_error(ctx, PC_EINVAL, "perturber %d: non-finite element", p);
+        if (!(el[0] >= 0.0)) return set_error(ctx, PC_EINVAL, "perturber %d: mu must be >= 0", p);
+        if (!(el[1] > 0.0)) return set_error(ctx, PC_EINVAL, "perturber %d: a must be > 0", p);
+        if (!(el[2] >= 0.0 && el[2] < 1.0)) return set_error(ctx, PC_EINVAL, "perturber %d: e must be in [0,1)", p);
+    }
+    return PC_OK;
+}
+
+// Orientation of each perturber's orbit, prepared once per call (plan step).
+void prepare_bodies(const pc_model* model, PcBodyDev* out)
+{
+    for (int p = 0; p < model->n_pert; ++p) {
+        const double* el = model->pert + 7 * p;
+        const double a = el[1], e = el[2], inc = el[3], raan = el[4], argp = el[5];
+        PcBodyDev& B = out[p];
+        B.mu = el[0];
+        B.a = a;
+        B.e = e;
+        B.n = std::sqrt(1.0 / (a * a * a));
+        B.M0 = el[6];
+        B.b = a * std::sqrt(1.0 - e * e);
+        const double cO = std::cos(raan), sO = std::sin(raan), cw = std::cos(argp), sw = std::sin(argp);
+        const double ci = std::cos(inc), si = std::sin(inc);
+        B.P[0] = cO * cw - sO * sw * ci;
+        B.P[1] = sO * cw + cO * sw * ci;
+        B.P[2] = sw * si;
+        B.Q[0] = -cO * sw - sO * cw * ci;
+        B.Q[1] = -sO * sw + cO * cw * ci;
+        B.Q[2] = cw * si;
+    }
+}
+
+struct JobClass {
+    int np, begin, end;
+};
+
+struct Plan {
+    int pairs = 2048;
+    std::vector<JobClass> classes;
+    std::vector<PcGroupDev> groups;
+    std::vector<PcJobDev> jobs;
+    int64_t n_recs = 0;
+    int max_S = 0, max_N = 0;
+    // workspace offsets
+    size_t off_counters = 0, off_groups = 0, off_jobs = 0, off_bodies = 0, off_recs = 0, total = 0;
+    size_t staged = 0;   // bytes of [counters .. bodies] copied from the staging buffer
+};
+
+int choose_pairs(const pc_group* groups, int n_groups, const pc_opts& o)
+{
+    if (o.tile_pairs == 1024 || o.tile_pairs == 2048) return o.tile_pairs;
+    (void)groups;
+    (void)n_groups;
+    return 2048;
+}
+
+int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, const pc_model* model,
+              const pc_opts& o, bool build_tables, Plan& plan)
+{
+    if (!groups || n_groups < 1) return set_error(ctx, PC_EINVAL, "need at least one group");
+    if (o.tile_pairs != 0 && o.tile_pairs != 1024 && o.tile_pairs != 2048)
+        return set_error(ctx, PC_EINVAL, "tile_pairs must be 0, 1024 or 2048");
+    plan.pairs = choose_pairs(groups, n_groups, o);
+    std::vector<std::pair<int64_t, int64_t>> spans;
+    plan.groups.clear();
+    plan.jobs.clear();
+    plan.n_recs = 0;
+    plan.max_S = plan.max_N = 0;
+    for (int gi = 0; gi < n_groups; ++gi) {
+        const pc_group& G = groups[gi];
+        if (G.n_ic < 1) return set_error(ctx, PC_EINVAL, "group %d: n_ic < 1", gi);
+        if (G.ic_offset < 0 || G.ic_offset + G.n_ic > n_ic)
+            return set_error(ctx, PC_EINVAL, "group %d: ICs out of range", gi);
+        if (G.nodes < 3 || G.nodes > PC_MAX_NODES)
+            return set_error(ctx, PC_EINVAL, "group %d: nodes must be in [3, %d]", gi, PC_MAX_NODES);
+        if (G.segments < 1) return set_error(ctx, PC_EINVAL, "group %d: segments < 1", gi);
+        if (!std::isfinite(G.t0) || !std::isfinite(G.tf) || G.t0 == G.tf)
+            return set_error(ctx, PC_EINVAL, "group %d: need finite t0 != tf", gi);
+        if (!(G.tol > 0.0) || !std::isfinite(G.tol))
+            return set_error(ctx, PC_EINVAL, "group %d: tol must be positive and finite", gi);
+        const int NP = padded_nodes(G.nodes);
+        if (NP * 8 > plan.pairs)
+            return set_error(ctx, PC_EINVAL, "group %d: %d nodes need tile_pairs >= %d", gi, G.nodes, NP * 8);
+        spans.push_back({G.ic_offset, G.ic_offset + G.n_ic});
+        plan.max_S = std::max(plan.max_S, G.segments);
+        plan.max_N = std::max(plan.max_N, G.nodes);
+    }
+    std::sort(spans.begin(), spans.end());
+    for (size_t i = 1; i < spans.size(); ++i)
+        if (spans[i].first < spans[i - 1].second) return set_error(ctx, PC_EINVAL, "groups overlap");
+
+    struct Cost { int np; double c; PcJobDev j; };
+    std::vector<Cost> costs;
+    for (int gi = 0; gi < n_groups; ++gi) {
+        const pc_group& G = groups[gi];
+        PcGroupDev d{};
+        d.t0 = G.t0;
+        d.h = (G.tf - G.t0) / (double)G.segments;
+        d.tol = G.tol;
+        d.ic_offset = G.ic_offset;
+        d.n_ic = G.n_ic;
+        d.rec_offset = plan.n_recs;
+        d.N = G.nodes;
+        d.NP = padded_nodes(G.nodes);
+        d.T = plan.pairs / d.NP;
+        d.S = G.segments;
+        if (build_tables) {
+            const OperatorCache* oc = nullptr;
+            int rc = get_operator(ctx, G.nodes, &oc);
+            if (rc != PC_OK) return rc;
+            d.kfrag = oc->kfrag;
+            d.tau = oc->tau;
+        }
+        plan.n_recs += (int64_t)G.segments * G.nodes;
+        plan.groups.push_back(d);
+        // cost model of one job: segments x NP (matrix work per iteration ~ NP^2 T = NP * PAIRS)
+        const double c = (double)G.segments * (double)d.NP;
+        for (int64_t i0 = 0; i0 < G.n_ic; i0 += d.T) {
+            PcJobDev j{};
+            j.ic0 = G.ic_offset + i0;
+            j.group = gi;
+            j.n = (int)std::min<int64_t>(d.T, G.n_ic - i0);
+            costs.push_back({d.NP, c, j});
+        }
+    }
+    // one launch per padded node count; within it the longest jobs first, so the hardware
+    // dispatcher fills the tail with short ones
+    std::stable_sort(costs.begin(), costs.end(), [](const Cost& a, const Cost& b) {
+        return a.np != b.np ? a.np > b.np : a.c > b.c;
+    });
+    plan.classes.clear();
+    for (size_t i = 0; i < costs.size(); ++i) {
+        if (plan.classes.empty() || plan.classes.back().np != costs[i].np)
+            plan.classes.push_back({costs[i].np, (int)i, (int)i});
+        plan.classes.back().end = (int)i + 1;
+        plan.jobs.push_back(costs[i].j);
+    }
+
+    const int P = model->n_pert;
+    size_t off = 0;
+    plan.off_counters = off; off = align_up(off + 2 * sizeof(int32_t));
+    plan.off_groups = off;   off = align_up(off + plan.groups.size() * sizeof(PcGroupDev));
+    plan.off_jobs = off;     off = align_up(off + plan.jobs.size() * sizeof(PcJobDev));
+    plan.off_bodies = off;   off = align_up(off + std::max(1, P) * sizeof(PcBodyDev));
+    plan.staged = off;
+    plan.off_recs = off;     off = align_up(off + (size_t)plan.n_recs * (P + 1) * 4 * sizeof(double));
+    plan.total = off;
+    return PC_OK;
+}
+
+pc_opts defaults()
+{
+    pc_opts o;
+    pc_default_opts(&o);
+    return o;
+}
+
+}  // namespace
+
+extern "C" {
+
+void pc_default_opts(pc_opts* o)
+{
+    if (!o) return;
+    o->init = PC_INIT_KEPLER;
+    o->max_iter = 64;
+    o->tol_mode = PC_TOL_REL;
+    o->precision = PC_FP64;
+    o->path = PC_PATH_FUSED;
+    o->fixed_iters = 0;
+    o->tile_pairs = 0;
+    o->reserved = 0;
+}
+
+int pc_version(void) { return PC_VERSION; }
+
+const char* pc_strerror(int code)
+{
+    switch (code) {
+    case PC_OK: return "ok";
+    case PC_EINVAL: return "invalid argument";
+    case PC_ENOTCONV: return "some initial conditions did not converge within max_iter";
+    case PC_ENONFINITE: return "some initial conditions became non-finite";
+    case PC_EHIP: return "HIP runtime error";
+    case PC_ENOMEM: return "workspace too small";
+    default: return "unknown status";
+    }
+}
+
+const char* pc_last_error(pc_ctx* ctx) { return ctx ? ctx->last_error : "no context"; }
+
+int pc_ctx_create(int device, pc_ctx** out)
+{
+    if (!out) return PC_EINVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return PC_EINVAL;
+    pc_ctx* ctx = new (std::nothrow) pc_ctx();
+    if (!ctx) return PC_ENOMEM;
+    ctx->device = device;
+    if (hipSetDevice(device) != hipSuccess ||
+        hipMalloc(&ctx->d_bodies, PC_MAX_PERT * sizeof(PcBodyDev)) != hipSuccess) {
+        delete ctx;
+        return PC_EHIP;
+    }
+    *out = ctx;
+    return PC_OK;
+}
+
+void pc_ctx_destroy(pc_ctx* ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (auto& kv : ctx->ops) {
+        (void)hipFree(kv.second.kfrag);
+        (void)hipFree(kv.second.tau);
+    }
+    if (ctx->staging) (void)hipHostFree(ctx->staging);
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    if (ctx->d_bodies) (void)hipFree(ctx->d_bodies);
+    delete ctx;
+}
+
+int pc_workspace_bytes(pc_ctx* ctx, const pc_group* groups, int32_t n_groups, const pc_model* model,
+                       const pc_opts* opts, size_t* bytes)
+{
+    if (!ctx || !bytes) return PC_EINVAL;
+    int rc = validate_model(ctx, model);
+    if (rc != PC_OK) return rc;
+    const pc_opts o = opts ? *opts : defaults();
+    int64_t n_ic = 0;
+    if (groups)
+        for (int i = 0; i < n_groups; ++i) n_ic = std::max<int64_t>(n_ic, groups[i].ic_offset + groups[i].n_ic);
+    Plan plan;
+    rc = make_plan(ctx, n_ic, groups, n_groups, model, o, false, plan);
+    if (rc != PC_OK) return rc;
+    *bytes = plan.total;
+    return PC_OK;
+}
+
+int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_group* groups,
+                         int32_t n_groups, const pc_model* model, const pc_opts* opts,
+                         double* states_out, int32_t* iters_out, int32_t iters_stride,
+                         double* bounds_out, double* nodes_out, int32_t nodes_stride,
+                         void* workspace, size_t ws_bytes, pc_stream_t stream)
+{
+    if (!ctx) return PC_EINVAL;
+    ctx->last_error[0] = 0;
+    if (!ics || !states_out || n_ic < 1) return set_error(ctx, PC_EINVAL, "null ics/states_out or n_ic < 1");
+    int rc = validate_model(ctx, model);
+    if (rc != PC_OK) return rc;
+    const pc_opts o = opts ? *opts : defaults();
+    if (o.init != PC_INIT_KEPLER && o.init != PC_INIT_COLD) return set_error(ctx, PC_EINVAL, "bad init");
+    if (o.tol_mode != PC_TOL_REL && o.tol_mode != PC_TOL_ABS) return set_error(ctx, PC_EINVAL, "bad tol_mode");
+    if (o.precision != PC_FP64) return set_error(ctx, PC_EINVAL, "unsupported precision");
+    if (o.path != PC_PATH_FUSED) return set_error(ctx, PC_EINVAL, "unsupported path");
+    if (o.max_iter < 1 || o.max_iter > 100000) return set_error(ctx, PC_EINVAL, "max_iter out of range");
+    if (o.fixed_iters < 0 || o.fixed_iters > 100000) return set_error(ctx, PC_EINVAL, "fixed_iters out of range");
+    PC_HIP(ctx, hipSetDevice(ctx->device));
+    Plan plan;
+    rc = make_plan(ctx, n_ic, groups, n_groups, model, o, true, plan);
+    if (rc != PC_OK) return rc;
+    if ((iters_out || bounds_out || nodes_out) && iters_stride < plan.max_S)
+        return set_error(ctx, PC_EINVAL, "iters_stride %d < %d segments", iters_stride, plan.max_S);
+    if (nodes_out && nodes_stride < plan.max_N)
+        return set_error(ctx, PC_EINVAL, "nodes_stride %d < %d nodes", nodes_stride, plan.max_N);
+    if (!workspace || ws_bytes < plan.total)
+        return set_error(ctx, PC_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, plan.total);
+
+    // stage [counters | groups | jobs | bodies] and copy them in one transfer
+    rc = ensure_staging(ctx, plan.staged + kAlign);
+    if (rc != PC_OK) return rc;
+    char* st = static_cast<char*>(ctx->staging);
+    std::memset(st, 0, plan.staged);
+    std::memcpy(st + plan.off_groups, plan.groups.data(), plan.groups.size() * sizeof(PcGroupDev));
+    std::memcpy(st + plan.off_jobs, plan.jobs.data(), plan.jobs.size() * sizeof(PcJobDev));
+    prepare_bodies(model, reinterpret_cast<PcBodyDev*>(st + plan.off_bodies));
+    char* ws = static_cast<char*>(workspace);
+    hipStream_t hs = (hipStream_t)stream;
+    PC_HIP(ctx, hipMemcpyAsync(ws, st, plan.staged, hipMemcpyHostToDevice, hs));
+
+    PcEphemParams ep{};
+    ep.groups = reinterpret_cast<const PcGroupDev*>(ws + plan.off_groups);
+    ep.n_groups = (int)plan.groups.size();
+    ep.n_recs = plan.n_recs;
+    ep.bodies = reinterpret_cast<const PcBodyDev*>(ws + plan.off_bodies);
+    ep.n_pert = model->n_pert;
+    ep.epoch = model->epoch;
+    ep.recs = reinterpret_cast<double*>(ws + plan.off_recs);
+    PC_HIP(ctx, (hipError_t)pc_launch_ephem(ep, stream));
+
+    PcParams pp{};
+    pp.groups = ep.groups;
+    pp.jobs = reinterpret_cast<const PcJobDev*>(ws + plan.off_jobs);
+    pp.n_jobs = (int)plan.jobs.size();
+    pp.n_pert = model->n_pert;
+    pp.ics = ics;
+    pp.states_out = states_out;
+    pp.iters_out = iters_out;
+    pp.iters_stride = iters_stride;
+    pp.nodes_stride = nodes_stride;
+    pp.bounds_out = bounds_out;
+    pp.nodes_out = nodes_out;
+    pp.recs = ep.recs;
+    pp.mu_sun = model->mu_sun;
+    pp.max_iter = o.max_iter;
+    pp.fixed_iters = o.fixed_iters;
+    pp.tol_mode = o.tol_mode;
+    pp.init = o.init;
+    pp.counters = reinterpret_cast<int32_t*>(ws + plan.off_counters);
+    if (ctx->timing) PC_HIP(ctx, hipEventRecord(ctx->ev0, hs));
+    for (const JobClass& jc : plan.classes)
+        PC_HIP(ctx, (hipError_t)pc_launch_fused(pp, plan.pairs, jc.np, jc.begin, jc.end, 0, stream));
+    if (ctx->timing) PC_HIP(ctx, hipEventRecord(ctx->ev1, hs));
+
+    int32_t* hc = reinterpret_cast<int32_t*>(st);   // staging is free again once the copy has run
+    PC_HIP(ctx, hipMemcpyAsync(hc, pp.counters, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, hs));
+    PC_HIP(ctx, hipStreamSynchronize(hs));
+    if (ctx->timing) {
+        float ms = 0.0f;
+        PC_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+        ctx->last_ms = ms;
+    }
+    if (hc[1] > 0) return set_error(ctx, PC_ENONFINITE, "%d initial conditions became non-finite", hc[1]);
+    if (hc[0] > 0) return set_error(ctx, PC_ENOTCONV, "%d initial conditions did not converge", hc[0]);
+    return PC_OK;
+}
+
+int pc_propagate(pc_ctx* ctx, const double* ics, int64_t n_ic, double t0, double tf, int32_t nodes,
+                 int32_t segments, double tol, const pc_model* model, const pc_opts* opts,
+                 double* states_out, int32_t* iters_out, void* workspace, size_t ws_bytes,
+                 pc_stream_t stream)
+{
+    pc_group g;
+    g.ic_offset = 0;
+    g.n_ic = n_ic;
+    g.t0 = t0;
+    g.tf = tf;
+    g.nodes = nodes;
+    g.segments = segments;
+    g.tol = tol;
+    return pc_propagate_batched(ctx, ics, n_ic, &g, 1, model, opts, states_out, iters_out, segments,
+                                nullptr, nullptr, 0, workspace, ws_bytes, stream);
+}
+
+int pc_set_timing(pc_ctx* ctx, int enable)
+{
+    if (!ctx) return PC_EINVAL;
+    PC_HIP(ctx, hipSetDevice(ctx->device));
+    if (enable && !ctx->ev0) {
+        PC_HIP(ctx, hipEventCreate(&ctx->ev0));
+        PC_HIP(ctx, hipEventCreate(&ctx->ev1));
+    }
+    ctx->timing = enable != 0;
+    ctx->last_ms = -1.0;
+    return PC_OK;
+}
+
+int pc_last_kernel_ms(pc_ctx* ctx, double* ms)
+{
+    if (!ctx || !ms) return PC_EINVAL;
+    *ms = ctx->last_ms;
+    return ctx->last_ms >= 0.0 ? PC_OK : set_error(ctx, PC_EINVAL, "no timed call yet");
+}
+
+int pc_get_operator(pc_ctx* ctx, int32_t nodes, double* K_host)
+{
+    if (!ctx || !K_host) return PC_EINVAL;
+    if (nodes < 3 || nodes > PC_MAX_NODES) return set_error(ctx, PC_EINVAL, "nodes out of range");
+    const OperatorCache* oc = nullptr;
+    int rc = get_operator(ctx, nodes, &oc);
+    if (rc != PC_OK) return rc;
+    std::memcpy(K_host, oc->K.data(), oc->K.size() * sizeof(double));
+    return PC_OK;
+}
+
+int pc_apply_operator(pc_ctx* ctx, int32_t nodes, int64_t n_cols, const double* F, const double* y0,
+                      double scale, double* Y, pc_stream_t stream)
+{
+    if (!ctx || !F || !y0 || !Y || n_cols < 1) return PC_EINVAL;
+    if (nodes < 3 || nodes > PC_MAX_NODES) return set_error(ctx, PC_EINVAL, "nodes out of range");
+    PC_HIP(ctx, hipSetDevice(ctx->device));
+    const OperatorCache* oc = nullptr;
+    int rc = get_operator(ctx, nodes, &oc);
+    if (rc != PC_OK) return rc;
+    PC_HIP(ctx, (hipError_t)pc_launch_apply_operator(oc->NP, oc->kfrag, nodes, n_cols, F, y0, scale, Y, stream));
+    PC_HIP(ctx, hipStreamSynchronize((hipStream_t)stream));
+    return PC_OK;
+}
+
+int pc_eval_force(pc_ctx* ctx, const double* r, const double* t, int64_t n, const pc_model* model,
+                  double* a_out, pc_stream_t stream)
+{
+    if (!ctx || !r || !t || !a_out || n < 1) return PC_EINVAL;
+    int rc = validate_model(ctx, model);
+    if (rc != PC_OK) return rc;
+    PC_HIP(ctx, hipSetDevice(ctx->device));
+    rc = ensure_staging(ctx, PC_MAX_PERT * sizeof(PcBodyDev));
+    if (rc != PC_OK) return rc;
+    prepare_bodies(model, static_cast<PcBodyDev*>(ctx->staging));
+    hipStream_t hs = (hipStream_t)stream;
+    if (model->n_pert > 0)
+        PC_HIP(ctx, hipMemcpyAsync(ctx->d_bodies, ctx->staging, model->n_pert * sizeof(PcBodyDev),
+                                   hipMemcpyHostToDevice, hs));
+    PC_HIP(ctx, (hipError_t)pc_launch_eval_force(r, t, n, ctx->d_bodies, model->n_pert, model->epoch,
+                                                 model->mu_sun, a_out, stream));
+    PC_HIP(ctx, hipStreamSynchronize(hs));
+    return PC_OK;
+}
+
+int pc_eval_kepler(pc_ctx* ctx, const double* y0, const double* dt, int64_t n, double* y, int32_t* ok,
+                   pc_stream_t stream)
+{
+    if (!ctx || !y0 || !dt || !y || !ok || n < 1) return PC_EINVAL;
+    PC_HIP(ctx, hipSetDevice(ctx->device));
+    PC_HIP(ctx, (hipError_t)pc_launch_eval_kepler(y0, dt, n, y, ok, stream));
+    PC_HIP(ctx, hipStreamSynchronize((hipStream_t)stream));
+    return PC_OK;
+}
+
+}  // extern "C"

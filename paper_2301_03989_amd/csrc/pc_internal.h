@@ -1,0 +1,83 @@
+// pc_internal.h -- structures shared by the host planner and the gfx950 kernels.
+//
+// Layout conventions (all FP64):
+//  * A "job" is one workgroup's share of one group: T consecutive ICs of the group,
+//    all NP (padded) nodes, all segments.  NP * T == PAIRS, PAIRS in {1024, 2048}.
+//  * Inside a workgroup the state of a job lives in LDS as [node j][comp 9][IC m]:
+//    comps 0..5 = x y z vx vy vz of the current iterate, comps 6..8 = the
+//    acceleration at the nodes.  Comps 3..8 are the force matrix F of Sec. 2.2
+//    (velocity and acceleration), so y_new = y0 + w2 * K_N F is one product with
+//    a contiguous right-hand side per node row.
+//  * K_N is stored as MFMA A-operand fragments: kfrag[strip][q][lane] =
+//    K_N[16*strip + lane%16][4*q + lane/16], zero-padded to NP x NP, so one wave
+//    reads a 16x4 slice with one coalesced 512-byte load.
+//  * Ephemeris records: for every (group, segment, node) the positions and
+//    parameters of the perturbers, rec[p] = (x, y, z, mu_p), followed by the
+//    indirect term rec[P] = (sum_p mu_p r_p/|r_p|^3, 0).
+#pragma once
+#include <stdint.h>
+
+#define PC_VERSION 100
+#define PC_MAX_NP_FOR_HOOK 256   // largest padded node count of the operator hook
+#define PC_MAX_PERT_DEV 16       // perturbers per force evaluation
+
+struct PcGroupDev {
+    double t0, h, tol;         // segment s spans [t0 + s h, t0 + (s+1) h]
+    int64_t ic_offset, n_ic;
+    int64_t rec_offset;        // first ephemeris record of the group (S * N records)
+    const double* kfrag;       // [NP/16][NP/4][64]
+    const double* tau;         // [NP] CGL nodes, zero past N
+    int32_t N, NP, T, S;
+};
+
+struct PcJobDev {
+    int64_t ic0;               // global index of the job's first IC
+    int32_t group;
+    int32_t n;                 // ICs in the job (<= T)
+};
+
+// Perturber on a Keplerian orbit, prepared on the host:
+// r(t) = a (cos E - e) P + b sin E Q,  E - e sin E = M0 + n (t - epoch).
+struct PcBodyDev {
+    double mu, a, e, n, M0, b;
+    double P[3], Q[3];
+};
+
+struct PcParams {
+    const PcGroupDev* groups;
+    const PcJobDev* jobs;
+    int32_t n_jobs;
+    int32_t n_pert;
+    const double* ics;          // [n_ic][6]
+    double* states_out;         // [n_ic][6]
+    int32_t* iters_out;         // [n_ic][iters_stride] or null
+    int32_t iters_stride;
+    int32_t nodes_stride;
+    double* bounds_out;         // [n_ic][iters_stride+1][6] or null
+    double* nodes_out;          // [n_ic][iters_stride][nodes_stride][6] or null
+    const double* recs;         // ephemeris records, (n_pert+1) double4 each
+    double mu_sun;
+    int32_t max_iter, fixed_iters, tol_mode, init;
+    int32_t* counters;          // [0] ICs with a not-converged segment, [1] non-finite ICs
+};
+
+struct PcEphemParams {
+    const PcGroupDev* groups;
+    int32_t n_groups;
+    int64_t n_recs;
+    const PcBodyDev* bodies;
+    int32_t n_pert;
+    double epoch;
+    double* recs;
+};
+
+// Launchers (pc_kernels.hip).  All return a hipError_t as int.
+int pc_launch_ephem(const PcEphemParams& p, void* stream);
+int pc_launch_fused(const PcParams& p, int pairs, int NP, int job_begin, int job_end, int grid,
+                    void* stream);
+int pc_launch_apply_operator(int NP, const double* kfrag, int N, int64_t n_cols, const double* F,
+                             const double* y0, double scale, double* Y, void* stream);
+int pc_launch_eval_force(const double* r, const double* t, int64_t n, const PcBodyDev* bodies,
+                         int n_pert, double epoch, double mu_sun, double* a, void* stream);
+int pc_launch_eval_kepler(const double* y0, const double* dt, int64_t n, double* y, int32_t* ok,
+                          void* stream);
