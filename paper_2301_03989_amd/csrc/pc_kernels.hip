@@ -66,7 +66,7 @@ static __device__ void pc_body_position(const PcBodyDev& B, double dt_epoch, dou
 // Lagrange coefficients f, g, fdot, gdot written in the eccentric-anomaly change x:
 //   x - (1 - r0/a) sin x + (r0.v0/sqrt(a)) (1 - cos x) = n dt.
 // Returns false for non-elliptic or degenerate states.
-static __device__ bool pc_kepler(const double y0[6], double dt, double y[6])
+static __device__ __attribute__((noinline)) bool pc_kepler(const double y0[6], double dt, double y[6])
 {
     const double r0n = sqrt(y0[0] * y0[0] + y0[1] * y0[1] + y0[2] * y0[2]);
     const double v02 = y0[3] * y0[3] + y0[4] * y0[4] + y0[5] * y0[5];
@@ -188,15 +188,100 @@ typedef const __attribute__((address_space(1))) double* gconst_dp;
 // Shared-memory arena of one workgroup (sized for the largest job shape).
 template <int PAIRS>
 struct PcSmem {
-    double Y[9 * PAIRS];         // [node][comp 9][IC]: iterate (0..5) and acceleration (6..8)
-    double Y0[6 * (PAIRS / 16)]; // [comp][IC] initial state of the current segment
-    double Err[(PAIRS / 256) * 16];
+    static constexpr int REC = PAIRS >= 2048 ? 7040 : 3072;   // doubles of ephemeris kept in LDS
+    double F[6 * PAIRS];          // [node][F comp 6][IC]: velocity (0..2), acceleration (3..5)
+    double Rec[REC];              // [node][body 0..P][3]: perturber positions, then the indirect term
+    double Y0[6 * (PAIRS / 16)];  // [comp][IC] initial state of the current segment
+    double Mu[PC_MAX_PERT_DEV];   // perturber parameters
+    int Flag[(PAIRS / 256) * 16]; // per wave, per IC: bit 0 not converged, bit 1 non-finite
     int Active[PAIRS / 16];
     int Dead[PAIRS / 16];
 };
 
-// One job: T = PAIRS/NP ICs of one group, all segments.  Compile-time NP makes every
-// LDS offset an immediate and lets a wave keep its 16-row strip of K_N in registers.
+// Accelerations at R points whose perturber records sit in LDS (compact [node][body][3]).
+template <int R>
+static __device__ __forceinline__ void pc_force_lds(const double (&x)[R], const double (&y)[R],
+                                                    const double (&z)[R], const int (&jr)[R], int P,
+                                                    double mu_sun, const double* srec, const double* smu,
+                                                    double (&ax)[R], double (&ay)[R], double (&az)[R])
+{
+    const int stride = 3 * (P + 1);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const double ir = rsqrt(x[r] * x[r] + y[r] * y[r] + z[r] * z[r]);
+        const double s = mu_sun * (ir * ir * ir);
+        ax[r] = -s * x[r];
+        ay[r] = -s * y[r];
+        az[r] = -s * z[r];
+    }
+    for (int b = 0; b < P; ++b) {
+        const double mu = smu[b];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double* q = srec + jr[r] * stride + 3 * b;
+            const double dx = x[r] - q[0], dy = y[r] - q[1], dz = z[r] - q[2];
+            const double id = rsqrt(dx * dx + dy * dy + dz * dz);
+            const double sd = mu * (id * id * id);
+            ax[r] -= sd * dx;
+            ay[r] -= sd * dy;
+            az[r] -= sd * dz;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const double* q = srec + jr[r] * stride + 3 * P;
+        ax[r] -= q[0];
+        ay[r] -= q[1];
+        az[r] -= q[2];
+    }
+}
+
+// Same with the records read from global memory ((x, y, z, mu) per body, then the indirect term).
+template <int R>
+static __device__ __forceinline__ void pc_force_glb(const double (&x)[R], const double (&y)[R],
+                                                    const double (&z)[R], const int (&jr)[R], int P,
+                                                    double mu_sun, const double4* grec,
+                                                    double (&ax)[R], double (&ay)[R], double (&az)[R])
+{
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const double ir = rsqrt(x[r] * x[r] + y[r] * y[r] + z[r] * z[r]);
+        const double s = mu_sun * (ir * ir * ir);
+        ax[r] = -s * x[r];
+        ay[r] = -s * y[r];
+        az[r] = -s * z[r];
+    }
+    for (int b = 0; b < P; ++b) {
+        double4 q[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) q[r] = grec[(size_t)jr[r] * (P + 1) + b];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double dx = x[r] - q[r].x, dy = y[r] - q[r].y, dz = z[r] - q[r].z;
+            const double id = rsqrt(dx * dx + dy * dy + dz * dz);
+            const double sd = q[r].w * (id * id * id);
+            ax[r] -= sd * dx;
+            ay[r] -= sd * dy;
+            az[r] -= sd * dz;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const double4 q = grec[(size_t)jr[r] * (P + 1) + P];
+        ax[r] -= q.x;
+        ay[r] -= q.y;
+        az[r] -= q.z;
+    }
+}
+
+// One job: T = PAIRS/NP ICs of one group, all segments.
+//
+// Ownership: every wave owns six 16x16 blocks of the iterate (node rows x component
+// columns) for the whole job.  It keeps its blocks of the current iterate in registers
+// (in the MFMA result layout), computes the dynamics for the (node, IC) pairs it owns
+// straight from them, and publishes only the force matrix F = (v, a) to LDS, where the
+// product y_new = y0 + w2 K_N F reads it as the B operand.  Compile-time NP makes every
+// LDS offset an immediate and lets a wave hold its 16-row strip of K_N in registers.
 template <int PAIRS, int NP>
 __device__ __forceinline__ void pc_job(const PcParams& p, const PcJobDev& job, const PcGroupDev& g,
                                        PcSmem<PAIRS>& sm)
@@ -204,15 +289,13 @@ __device__ __forceinline__ void pc_job(const PcParams& p, const PcJobDev& job, c
     constexpr int NT = PAIRS / 4;          // threads
     constexpr int W = NT / 64;             // waves
     constexpr int T = PAIRS / NP;          // ICs per job
-    constexpr int ROW = 9 * T;             // doubles per node row
+    constexpr int ROW = 6 * T;             // doubles per node row of F
     constexpr int NQ = NP / 4;             // k-steps of the 16x16x4 product
-    constexpr int JSTEP = NT / T;          // node stride between a thread's pairs
-    static_assert(T >= 8 && T <= NT, "unsupported job shape");
-    static_assert(NT % T == 0, "threads must tile the ICs");
-    constexpr bool WIDE = (T >= 16);       // one strip x six component blocks per wave
-    constexpr int G16 = WIDE ? T / 16 : 1;
+    static_assert(T >= 8 && T <= PAIRS / 16, "unsupported job shape");
+    constexpr bool WIDE = (T >= 16);       // WIDE: one strip x six component blocks per wave
+    constexpr int G16 = WIDE ? T / 16 : 1; // 16-IC groups per job
 
-    double* sY = sm.Y;
+    double* sF = sm.F;
     double* sY0 = sm.Y0;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -221,10 +304,16 @@ __device__ __forceinline__ void pc_job(const PcParams& p, const PcJobDev& job, c
     const int n = job.n;
     const int P = p.n_pert;
     const int64_t ic = job.ic0 + tid;      // this thread's IC when tid < n
-    const int pm = tid % T;                // IC of this thread's (node, IC) pairs
-    const int pj = tid / T;                // first node of this thread's pairs
+    const bool rec_lds = N * 3 * (P + 1) <= PcSmem<PAIRS>::REC;
+    const double t2 = g.tol * g.tol;
 
-    for (int i = tid; i < 9 * PAIRS; i += NT) sY[i] = 0.0;
+    // lane geometry
+    const int strip0 = WIDE ? wave / G16 : 2 * wave;
+    const int grp = WIDE ? wave - strip0 * G16 : 0;
+    const int my_m = WIDE ? grp * 16 + (lane & 15) : (lane & 7);
+    const int hi = WIDE ? 0 : (lane >> 3) & 1;          // T == 8: lane holds comps hi, 2+hi, 4+hi
+
+    for (int i = tid; i < 6 * PAIRS; i += NT) sF[i] = 0.0;
     if (tid < T) {
         const double* y = p.ics + (job.ic0 + (tid < n ? tid : 0)) * 6;
         bool fin = true;
@@ -235,20 +324,14 @@ __device__ __forceinline__ void pc_job(const PcParams& p, const PcJobDev& job, c
         }
         sm.Dead[tid] = !fin;
     }
+    if (tid < P) sm.Mu[tid] = 0.0;
 
-    // this wave's strip(s) of K_N
-    const int strip0 = WIDE ? wave / G16 : 2 * wave;
-    const int grp = WIDE ? wave - strip0 * G16 : 0;
     gconst_dp kp0 = (gconst_dp)g.kfrag + (size_t)strip0 * NQ * 64 + lane;
-    double kreg[WIDE ? NQ : 1];
-    if constexpr (WIDE) {
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) kreg[q] = kp0[q * 64];
-    }
-    // lane -> IC of its output columns
-    const int my_m = WIDE ? grp * 16 + (lane & 15) : (lane & 7);
     __syncthreads();
 
+    // the lane's share of the iterate: WIDE yc[comp][r] at node j0 + 4r;
+    // T == 8: yc[3h + cb][r] = comp 2cb + hi at node (strip0 + h) * 16 + lane/16 + 4r
+    double yc[6][4];
     int had_notconv = 0;
     for (int s = 0; s < S; ++s) {
         const double Ts = g.t0 + g.h * s, Te = g.t0 + g.h * (s + 1);
@@ -261,100 +344,175 @@ __device__ __forceinline__ void pc_job(const PcParams& p, const PcJobDev& job, c
             }
             if (sm.Dead[tid] && p.iters_out) p.iters_out[(size_t)ic * p.iters_stride + s] = -2;
         }
-
-        // initial guess: warm (Kepler) or cold start, Sec. 2.1
+        // this segment's ephemeris records into LDS (perturber positions precomputed per node, Sec. 5.4.1)
+        const double4* grec = reinterpret_cast<const double4*>(p.recs) +
+                              (size_t)(g.rec_offset + (int64_t)s * N) * (P + 1);
+        if (rec_lds) {
+            for (int i = tid; i < N * (P + 1); i += NT) {
+                const double4 q = grec[i];
+                sm.Rec[3 * i + 0] = q.x;
+                sm.Rec[3 * i + 1] = q.y;
+                sm.Rec[3 * i + 2] = q.z;
+                if (i < P) sm.Mu[i] = q.w;
+            }
+        }
+        // initial guess at every (node, IC) pair: warm (Kepler) or cold start, Sec. 2.1,
+        // staged through the F area as [node][comp 6][IC]
         {
+            const int pm = tid % T;
             double y0[6];
 #pragma unroll
             for (int c = 0; c < 6; ++c) y0[c] = sY0[c * T + pm];
             const bool warm = p.init == 0 && !sm.Dead[pm];
+#pragma unroll 1
+            for (int pr = tid; pr < PAIRS; pr += NT) {
+                const int j = pr / T;
+                double y[6];
+                if (!(j < N && warm && pc_kepler(y0, w2 * (g.tau[j < N ? j : 0] + 1.0), y))) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int j = pj + JSTEP * u;
-                if (j < N) {
-                    double y[6];
-                    if (!(warm && pc_kepler(y0, w2 * (g.tau[j] + 1.0), y))) {
+                    for (int c = 0; c < 6; ++c) y[c] = y0[c];
+                }
+                double* dst = sF + j * ROW + pm;
 #pragma unroll
-                        for (int c = 0; c < 6; ++c) y[c] = y0[c];
-                    }
-                    double* row = sY + j * ROW + pm;
+                for (int c = 0; c < 6; ++c) dst[c * T] = y[c];
+            }
+        }
+        __syncthreads();
 #pragma unroll
-                    for (int c = 0; c < 6; ++c) row[c * T] = y[c];
+        for (int h = 0; h < (WIDE ? 1 : 2); ++h) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = (strip0 + h) * 16 + (lane >> 4) + 4 * r;
+                const double* src = sF + j * ROW + my_m;
+                if constexpr (WIDE) {
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) yc[c][r] = src[c * T];
+                } else {
+#pragma unroll
+                    for (int cb = 0; cb < 3; ++cb) yc[3 * h + cb][r] = src[(2 * cb + hi) * T];
                 }
             }
         }
+        __syncthreads();   // staging read before F is rebuilt
+        for (int i = tid; i < 6 * PAIRS; i += NT) sF[i] = 0.0;
         if (tid < T) sm.Active[tid] = (tid < n) && !sm.Dead[tid];
-        __syncthreads();
+        __syncthreads();   // records and flags visible
 
-        const double4* recs = reinterpret_cast<const double4*>(p.recs) +
-                              (size_t)(g.rec_offset + (int64_t)s * N) * (P + 1);
-        const int n_it = p.fixed_iters > 0 ? p.fixed_iters : p.max_iter;
-        for (int it = 1; it <= n_it; ++it) {
-            // (1) dynamics at every node (the force matrix of Sec. 2.2, Sec. 5.4.1)
+        // publish F = (v, a(r)) of the lane's pairs (the force matrix of Sec. 2.2)
+        auto publish = [&]() {
+            if constexpr (WIDE) {
+                double ax[4], ay[4], az[4];
+                int jr[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int j = pj + JSTEP * u;
-                if (j < N) {
-                    double* row = sY + j * ROW + pm;
-                    double ax, ay, az;
-                    pc_accel(row[0], row[T], row[2 * T], recs + (size_t)j * (P + 1), P, p.mu_sun, ax, ay, az);
-                    row[6 * T] = ax;
-                    row[7 * T] = ay;
-                    row[8 * T] = az;
+                for (int r = 0; r < 4; ++r) {
+                    const int j = strip0 * 16 + (lane >> 4) + 4 * r;
+                    jr[r] = j < N ? j : N - 1;
+                }
+                if (rec_lds) pc_force_lds<4>(yc[0], yc[1], yc[2], jr, P, p.mu_sun, sm.Rec, sm.Mu, ax, ay, az);
+                else pc_force_glb<4>(yc[0], yc[1], yc[2], jr, P, p.mu_sun, grec, ax, ay, az);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int j = strip0 * 16 + (lane >> 4) + 4 * r;
+                    if (j < N) {
+                        double* f = sF + j * ROW + my_m;
+                        f[0 * T] = yc[3][r];
+                        f[1 * T] = yc[4][r];
+                        f[2 * T] = yc[5][r];
+                        f[3 * T] = ax[r];
+                        f[4 * T] = ay[r];
+                        f[5 * T] = az[r];
+                    }
+                }
+            } else {
+                // lanes with hi == 0 hold x (cb 0) and z (cb 1); y comes from the partner lane
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    double xs[4], ys[4], zs[4], ax[4], ay[4], az[4];
+                    int jr[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int j = (strip0 + h) * 16 + (lane >> 4) + 4 * r;
+                        jr[r] = j < N ? j : N - 1;
+                        xs[r] = yc[3 * h][r];
+                        ys[r] = __shfl_xor(yc[3 * h][r], 8);
+                        zs[r] = yc[3 * h + 1][r];
+                    }
+                    if (!hi) {
+                        if (rec_lds) pc_force_lds<4>(xs, ys, zs, jr, P, p.mu_sun, sm.Rec, sm.Mu, ax, ay, az);
+                        else pc_force_glb<4>(xs, ys, zs, jr, P, p.mu_sun, grec, ax, ay, az);
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int j = (strip0 + h) * 16 + (lane >> 4) + 4 * r;
+                        if (j < N) {
+                            double* f = sF + j * ROW + my_m;
+                            if (hi) {
+                                f[0 * T] = yc[3 * h + 1][r];   // vx (comp 3)
+                                f[2 * T] = yc[3 * h + 2][r];   // vz (comp 5)
+                            } else {
+                                f[1 * T] = yc[3 * h + 2][r];   // vy (comp 4)
+                                f[3 * T] = ax[r];
+                                f[4 * T] = ay[r];
+                                f[5 * T] = az[r];
+                            }
+                        }
+                    }
                 }
             }
-            __syncthreads();
+        };
+        if (sm.Active[my_m]) publish();
+        __syncthreads();
 
-            // (2) y_new = y0 + w2 K_N F on the FP64 matrix cores
+        const int n_it = p.fixed_iters > 0 ? p.fixed_iters : p.max_iter;
+        for (int it = 1; it <= n_it; ++it) {
+            // (1) y_new = y0 + w2 K_N F on the FP64 matrix cores (Sec. 2.2, folded A, C, S)
             f64x4 acc[6];
 #pragma unroll
             for (int b = 0; b < 6; ++b) acc[b] = f64x4{0.0, 0.0, 0.0, 0.0};
-            double e_lane = 0.0;
+            int flag = 0;   // bit 0: some node not converged, bit 1: non-finite
             if constexpr (WIDE) {
-                // B operand of block b (output comp b) is F comp 3+b: LDS column (3+b)T + 16 grp + lane%16
-                const double* bp = sY + (lane >> 4) * ROW + 3 * T + grp * 16 + (lane & 15);
+                // K_N strip streamed from L2 two k-steps ahead; B operands one k-step ahead
+                const double* bp = sF + (lane >> 4) * ROW + grp * 16 + (lane & 15);
                 double bc[6], bn[6];
+                double ka = kp0[0], kb = (NQ > 1) ? kp0[64] : 0.0;
 #pragma unroll
                 for (int b = 0; b < 6; ++b) bc[b] = bp[b * T];
-#pragma unroll
+#pragma unroll 2
                 for (int q = 0; q < NQ; ++q) {
+                    const double kn = (q + 2 < NQ) ? kp0[(q + 2) * 64] : 0.0;
                     if (q + 1 < NQ) {
 #pragma unroll
                         for (int b = 0; b < 6; ++b) bn[b] = bp[(q + 1) * 4 * ROW + b * T];
                     }
 #pragma unroll
-                    for (int b = 0; b < 6; ++b) acc[b] = mfma16(kreg[q], bc[b], acc[b]);
+                    for (int b = 0; b < 6; ++b) acc[b] = mfma16(ka, bc[b], acc[b]);
 #pragma unroll
                     for (int b = 0; b < 6; ++b) bc[b] = bn[b];
+                    ka = kb;
+                    kb = kn;
                 }
-                // (3) new iterate and its change (Sec. 2.2 stopping rule), in registers
-                const int j0 = strip0 * 16 + (lane >> 4);
-                double y0c[6];
-#pragma unroll
-                for (int b = 0; b < 6; ++b) y0c[b] = sY0[b * T + my_m];
+                // (2) new iterate and its change (stopping rule of Sec. 2.2, squared form)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int j = j0 + 4 * r;
-                    const double* yo = sY + j * ROW + my_m;
+                    const int j = strip0 * 16 + (lane >> 4) + 4 * r;
                     double pd = 0.0, py = 0.0, vd = 0.0, vy = 0.0;
 #pragma unroll
                     for (int b = 0; b < 6; ++b) {
-                        const double yn = y0c[b] + w2 * acc[b][r];
+                        const double yn = sY0[b * T + my_m] + w2 * acc[b][r];
                         acc[b][r] = yn;
-                        const double d = (j < N) ? yn - yo[b * T] : 0.0;
+                        const double d = yn - yc[b][r];
                         if (b < 3) { pd += d * d; py += yn * yn; }
                         else { vd += d * d; vy += yn * yn; }
                     }
                     if (j < N) {
-                        const double ep = p.tol_mode == 0 ? sqrt(pd) / sqrt(py) : sqrt(pd);
-                        const double ev = p.tol_mode == 0 ? sqrt(vd) / sqrt(vy) : sqrt(vd);
-                        e_lane = nmax(e_lane, nmax(ep, ev));
+                        const bool ok = p.tol_mode == 0 ? (pd < t2 * py && vd < t2 * vy) : (pd < t2 && vd < t2);
+                        const bool nf = !isfinite(pd + py + vd + vy);
+                        flag |= (ok ? 0 : 1) | (nf ? 2 : 0);
                     }
                 }
             } else {
-                // two strips per wave; block (h, cb) covers comps 2cb, 2cb+1 of the 8 ICs
                 gconst_dp kp1 = kp0 + (size_t)NQ * 64;
-                const double* bp = sY + (lane >> 4) * ROW + 3 * T + (lane & 15);
+                const double* bp = sF + (lane >> 4) * ROW + (lane & 15);
                 double a0 = kp0[0], a1 = kp1[0];
                 double a0n = 0.0, a1n = 0.0;
                 double b0 = bp[0], b1 = bp[16], b2 = bp[32];
@@ -378,20 +536,17 @@ __device__ __forceinline__ void pc_job(const PcParams& p, const PcJobDev& job, c
                     a0 = a0n; a1 = a1n;
                     b0 = b0n; b1 = b1n; b2 = b2n;
                 }
-                const int hi = (lane >> 3) & 1;    // lane holds comps hi, 2+hi, 4+hi of IC lane%8
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
-                    const int j0 = (strip0 + h) * 16 + (lane >> 4);
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int j = j0 + 4 * r;
+                        const int j = (strip0 + h) * 16 + (lane >> 4) + 4 * r;
                         double dd[3], yy[3];
 #pragma unroll
                         for (int cb = 0; cb < 3; ++cb) {
-                            const int comp = 2 * cb + hi;
-                            const double yn = sY0[comp * T + my_m] + w2 * acc[3 * h + cb][r];
+                            const double yn = sY0[(2 * cb + hi) * T + my_m] + w2 * acc[3 * h + cb][r];
                             acc[3 * h + cb][r] = yn;
-                            const double d = (j < N) ? yn - sY[j * ROW + 16 * cb + (lane & 15)] : 0.0;
+                            const double d = yn - yc[3 * h + cb][r];
                             dd[cb] = d * d;
                             yy[cb] = yn * yn;
                         }
@@ -404,61 +559,33 @@ __device__ __forceinline__ void pc_job(const PcParams& p, const PcJobDev& job, c
                         vd += __shfl_xor(vd, 8);
                         vy += __shfl_xor(vy, 8);
                         if (j < N) {
-                            const double ep = p.tol_mode == 0 ? sqrt(pd) / sqrt(py) : sqrt(pd);
-                            const double ev = p.tol_mode == 0 ? sqrt(vd) / sqrt(vy) : sqrt(vd);
-                            e_lane = nmax(e_lane, nmax(ep, ev));
+                            const bool ok = p.tol_mode == 0 ? (pd < t2 * py && vd < t2 * vy) : (pd < t2 && vd < t2);
+                            const bool nf = !isfinite(pd + py + vd + vy);
+                            flag |= (ok ? 0 : 1) | (nf ? 2 : 0);
                         }
                     }
                 }
-                e_lane = nmax(e_lane, __shfl_xor(e_lane, 8));
+                flag |= __shfl_xor(flag, 8);
             }
-            // (4) per-IC maximum over the wave's rows (Sec. 5.4.2), then across waves
-            e_lane = nmax(e_lane, __shfl_xor(e_lane, 16));
-            e_lane = nmax(e_lane, __shfl_xor(e_lane, 32));
-            if (lane < 16) sm.Err[wave * 16 + lane] = e_lane;
+            // (3) per-IC flags: over the wave's rows (lanes of one IC), then across waves
+            flag |= __shfl_xor(flag, 16);
+            flag |= __shfl_xor(flag, 32);
+            if (lane < 16) sm.Flag[wave * 16 + lane] = flag;
             const int act = sm.Active[my_m];
-            __syncthreads();
+            __syncthreads();   // every wave is done reading F; flags complete
 
-            if (act) {
-                if constexpr (WIDE) {
-                    const int j0 = strip0 * 16 + (lane >> 4);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int j = j0 + 4 * r;
-                        if (j < N) {
-                            double* yw = sY + j * ROW + my_m;
-#pragma unroll
-                            for (int b = 0; b < 6; ++b) yw[b * T] = acc[b][r];
-                        }
-                    }
-                } else {
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const int j0 = (strip0 + h) * 16 + (lane >> 4);
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const int j = j0 + 4 * r;
-                            if (j < N) {
-                                double* yw = sY + j * ROW + (lane & 15);
-#pragma unroll
-                                for (int cb = 0; cb < 3; ++cb) yw[16 * cb] = acc[3 * h + cb][r];
-                            }
-                        }
-                    }
-                }
-            }
-            // (5) stopping rule per IC (Sec. 2.2; per-block error of Sec. 3.2, blocks of one IC)
+            // (4) stopping rule per IC (Sec. 2.2; per-block error of Sec. 3.2 with blocks of one IC)
             if (tid < T && sm.Active[tid]) {
-                double e = 0.0;
+                int f = 0;
                 if constexpr (WIDE) {
-                    for (int w = tid >> 4; w < W; w += G16) e = nmax(e, sm.Err[w * 16 + (tid & 15)]);
+                    for (int w = tid >> 4; w < W; w += G16) f |= sm.Flag[w * 16 + (tid & 15)];
                 } else {
-                    for (int w = 0; w < W; ++w) e = nmax(e, sm.Err[w * 16 + tid]);
+                    for (int w = 0; w < W; ++w) f |= sm.Flag[w * 16 + tid];
                 }
                 int rec = 0;
-                if (e != e) rec = -2;
+                if (f & 2) rec = -2;
                 else if (p.fixed_iters > 0) rec = (it == p.fixed_iters) ? it : 0;
-                else if (e < g.tol) rec = it;
+                else if (!(f & 1)) rec = it;
                 else if (it == p.max_iter) rec = -1;
                 if (rec != 0) {
                     sm.Active[tid] = 0;
@@ -467,26 +594,60 @@ __device__ __forceinline__ void pc_job(const PcParams& p, const PcJobDev& job, c
                     if (tid < n && p.iters_out) p.iters_out[(size_t)ic * p.iters_stride + s] = rec;
                 }
             }
+            // (5) ICs that were iterating take the new iterate and publish its F
+            if (act) {
+#pragma unroll
+                for (int b = 0; b < 6; ++b) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) yc[b][r] = acc[b][r];
+                }
+                if (it < n_it) publish();
+            }
             const int any = __syncthreads_or(tid < T ? sm.Active[tid] : 0);
             if (!any) break;
         }
 
         // converged node states of the segment (optional output)
-        if (p.nodes_out && pm < n) {
+        if (p.nodes_out && my_m < n) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int j = pj + JSTEP * u;
-                if (j < N) {
-                    double* o = p.nodes_out +
-                                (((size_t)(job.ic0 + pm) * p.iters_stride + s) * p.nodes_stride + j) * 6;
-                    for (int c = 0; c < 6; ++c) o[c] = sY[j * ROW + c * T + pm];
+            for (int h = 0; h < (WIDE ? 1 : 2); ++h) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int j = (strip0 + h) * 16 + (lane >> 4) + 4 * r;
+                    if (j < N) {
+                        double* o = p.nodes_out +
+                                    (((size_t)(job.ic0 + my_m) * p.iters_stride + s) * p.nodes_stride + j) * 6;
+                        if constexpr (WIDE) {
+#pragma unroll
+                            for (int c = 0; c < 6; ++c) o[c] = yc[c][r];
+                        } else {
+#pragma unroll
+                            for (int cb = 0; cb < 3; ++cb) o[2 * cb + hi] = yc[3 * h + cb][r];
+                        }
+                    }
                 }
             }
         }
         // chaining: the last node starts the next segment (piecewise integration, Sec. 2.2)
-        if (tid < T) {
-            for (int c = 0; c < 6; ++c)
-                sY0[c * T + tid] = sm.Dead[tid] ? (double)NAN : sY[(N - 1) * ROW + c * T + tid];
+        {
+            const bool dead = sm.Dead[my_m];
+#pragma unroll
+            for (int h = 0; h < (WIDE ? 1 : 2); ++h) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int j = (strip0 + h) * 16 + (lane >> 4) + 4 * r;
+                    if (j == N - 1) {
+                        if constexpr (WIDE) {
+#pragma unroll
+                            for (int c = 0; c < 6; ++c) sY0[c * T + my_m] = dead ? (double)NAN : yc[c][r];
+                        } else {
+#pragma unroll
+                            for (int cb = 0; cb < 3; ++cb)
+                                sY0[(2 * cb + hi) * T + my_m] = dead ? (double)NAN : yc[3 * h + cb][r];
+                        }
+                    }
+                }
+            }
         }
         __syncthreads();
     }
