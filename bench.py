@@ -73,6 +73,8 @@ def main():
     ap.add_argument("--check-ics", type=int, default=64, help="ICs checked against the oracle")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="wall-time budget of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--plain-steps", type=int, default=3,
+                    help="steps of the per-iteration (plain) path timed for the speedup; 0 skips")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -134,6 +136,26 @@ def main():
     iters = r["iters"].cpu().numpy()
     gpu_states = r["states"].cpu().numpy()
 
+    plain = None
+    if args.plain_steps > 0:
+        # the same propagation with per-iteration kernels and a host loop (plain GPU path)
+        plain_states = torch.empty_like(states)
+        ctx.propagate_batched(ics, groups, model, init=init, path="plain", out=plain_states)
+        torch.cuda.synchronize()
+        p0 = torch.cuda.Event(enable_timing=True)
+        p1 = torch.cuda.Event(enable_timing=True)
+        p0.record()
+        for _ in range(args.plain_steps):
+            rp = ctx.propagate_batched(ics, groups, model, init=init, path="plain", out=plain_states)
+        p1.record()
+        torch.cuda.synchronize()
+        plain_ms = p0.elapsed_time(p1) / args.plain_steps
+        plain = {"path": "plain", "ms_per_step": round(plain_ms, 4), "steps": args.plain_steps,
+                 "speedup_batched_vs_plain": round(plain_ms / ms_per_step, 3),
+                 "max_rel_diff_vs_batched": float(rel_err(rp["states"].cpu().numpy(), gpu_states).max())}
+        print(f"bench: plain path {plain_ms:.3f} ms/step, batched speedup {plain_ms / ms_per_step:.2f}x",
+              flush=True)
+
     # accuracy gate against the FP64 oracle on an evenly spaced sample
     idx = np.unique(np.linspace(0, n_ic - 1, min(args.check_ics, n_ic)).astype(np.int64))
     ref, ref_iters, _ = oracle_states(w, idx)
@@ -194,6 +216,7 @@ def main():
                      "mean_iterations_per_segment": round(float(iters[iters > 0].mean()), 3)},
         "segment_iterations_per_s": round(float(np.where(iters > 0, iters, 0).sum()) /
                                           (ms_per_step * 1e-3), 1),
+        "vs_plain": plain,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -16,6 +16,7 @@
 
 #include "pcprop.h"
 #include "pc_internal.h"
+#include "pc_plain.h"
 
 namespace {
 
@@ -34,6 +35,7 @@ struct pc_ctx {
     void* staging = nullptr;        // pinned host memory for descriptor tables
     size_t staging_bytes = 0;
     PcBodyDev* d_bodies = nullptr;  // device copy of the perturber table (test hooks)
+    int32_t* pinned_count = nullptr;   // per-iteration read-back of the plain path
     bool timing = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double last_ms = -1.0;
@@ -210,7 +212,10 @@ struct JobClass {
 
 struct Plan {
     int pairs = 2048;
+    bool plain = false;
     std::vector<JobClass> classes;
+    std::vector<int> group_job_begin;   // plain path: jobs of group g are [begin[g], begin[g+1])
+    size_t off_plain = 0;
     std::vector<PcGroupDev> groups;
     std::vector<PcJobDev> jobs;
     int64_t n_recs = 0;
@@ -235,6 +240,8 @@ int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, c
     if (o.tile_pairs != 0 && o.tile_pairs != 1024 && o.tile_pairs != 2048)
         return set_error(ctx, PC_EINVAL, "tile_pairs must be 0, 1024 or 2048");
     plan.pairs = choose_pairs(groups, n_groups, o);
+    plan.plain = (o.path == PC_PATH_PLAIN);
+    if (plan.plain) plan.pairs = 2048;
     std::vector<std::pair<int64_t, int64_t>> spans;
     plan.groups.clear();
     plan.jobs.clear();
@@ -297,11 +304,15 @@ int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, c
             costs.push_back({d.NP, c, j});
         }
     }
-    // one launch per padded node count; within it the longest jobs first, so the hardware
-    // dispatcher fills the tail with short ones
-    std::stable_sort(costs.begin(), costs.end(), [](const Cost& a, const Cost& b) {
-        return a.np != b.np ? a.np > b.np : a.c > b.c;
-    });
+    // fused: one launch per padded node count; within it the longest jobs first, so the
+    // hardware dispatcher fills the tail with short ones.  plain: group-major, IC order.
+    if (!plan.plain)
+        std::stable_sort(costs.begin(), costs.end(), [](const Cost& a, const Cost& b) {
+            return a.np != b.np ? a.np > b.np : a.c > b.c;
+        });
+    plan.group_job_begin.assign(n_groups + 1, 0);
+    for (const Cost& c : costs) plan.group_job_begin[c.j.group + 1] += plan.plain ? 1 : 0;
+    for (int gi = 0; gi < n_groups; ++gi) plan.group_job_begin[gi + 1] += plan.group_job_begin[gi];
     plan.classes.clear();
     for (size_t i = 0; i < costs.size(); ++i) {
         if (plan.classes.empty() || plan.classes.back().np != costs[i].np)
@@ -318,6 +329,16 @@ int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, c
     plan.off_bodies = off;   off = align_up(off + std::max(1, P) * sizeof(PcBodyDev));
     plan.staged = off;
     plan.off_recs = off;     off = align_up(off + (size_t)plan.n_recs * (P + 1) * 4 * sizeof(double));
+    plan.off_plain = off;
+    if (plan.plain) {
+        size_t mx = 0;
+        for (int gi = 0; gi < n_groups; ++gi) {
+            const PcGroupDev& d = plan.groups[gi];
+            const int nj = plan.group_job_begin[gi + 1] - plan.group_job_begin[gi];
+            mx = std::max(mx, pc_plain_bytes(d.NP, nj, d.T));
+        }
+        off = align_up(off + mx);
+    }
     plan.total = off;
     return PC_OK;
 }
@@ -373,7 +394,8 @@ int pc_ctx_create(int device, pc_ctx** out)
     if (!ctx) return PC_ENOMEM;
     ctx->device = device;
     if (hipSetDevice(device) != hipSuccess ||
-        hipMalloc(&ctx->d_bodies, PC_MAX_PERT * sizeof(PcBodyDev)) != hipSuccess) {
+        hipMalloc(&ctx->d_bodies, PC_MAX_PERT * sizeof(PcBodyDev)) != hipSuccess ||
+        hipHostMalloc(&ctx->pinned_count, 64, hipHostMallocDefault) != hipSuccess) {
         delete ctx;
         return PC_EHIP;
     }
@@ -394,6 +416,7 @@ void pc_ctx_destroy(pc_ctx* ctx)
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     if (ctx->d_bodies) (void)hipFree(ctx->d_bodies);
+    if (ctx->pinned_count) (void)hipHostFree(ctx->pinned_count);
     delete ctx;
 }
 
@@ -429,7 +452,7 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_
     if (o.init != PC_INIT_KEPLER && o.init != PC_INIT_COLD) return set_error(ctx, PC_EINVAL, "bad init");
     if (o.tol_mode != PC_TOL_REL && o.tol_mode != PC_TOL_ABS) return set_error(ctx, PC_EINVAL, "bad tol_mode");
     if (o.precision != PC_FP64) return set_error(ctx, PC_EINVAL, "unsupported precision");
-    if (o.path != PC_PATH_FUSED) return set_error(ctx, PC_EINVAL, "unsupported path");
+    if (o.path != PC_PATH_FUSED && o.path != PC_PATH_PLAIN) return set_error(ctx, PC_EINVAL, "bad path");
     if (o.max_iter < 1 || o.max_iter > 100000) return set_error(ctx, PC_EINVAL, "max_iter out of range");
     if (o.fixed_iters < 0 || o.fixed_iters > 100000) return set_error(ctx, PC_EINVAL, "fixed_iters out of range");
     PC_HIP(ctx, hipSetDevice(ctx->device));
@@ -485,8 +508,26 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_
     pp.init = o.init;
     pp.counters = reinterpret_cast<int32_t*>(ws + plan.off_counters);
     if (ctx->timing) PC_HIP(ctx, hipEventRecord(ctx->ev0, hs));
-    for (const JobClass& jc : plan.classes)
-        PC_HIP(ctx, (hipError_t)pc_launch_fused(pp, plan.pairs, jc.np, jc.begin, jc.end, 0, stream));
+    if (!plan.plain) {
+        for (const JobClass& jc : plan.classes)
+            PC_HIP(ctx, (hipError_t)pc_launch_fused(pp, plan.pairs, jc.np, jc.begin, jc.end, 0, stream));
+    } else {
+        // one group at a time, kernels per iteration, host loop (the structure of Sec. 5.4)
+        for (int gi = 0; gi < n_groups; ++gi) {
+            PcPlainArgs a{};
+            a.p = pp;
+            a.g = pp.groups + gi;
+            a.g_host = plan.groups[gi];
+            a.jobs = pp.jobs + plan.group_job_begin[gi];
+            a.n_jobs = plan.group_job_begin[gi + 1] - plan.group_job_begin[gi];
+            a.N = plan.groups[gi].N;
+            a.NP = plan.groups[gi].NP;
+            a.T = plan.groups[gi].T;
+            a.S = plan.groups[gi].S;
+            a.t2 = plan.groups[gi].tol * plan.groups[gi].tol;
+            PC_HIP(ctx, (hipError_t)pc_run_plain(a, ws + plan.off_plain, ctx->pinned_count, stream));
+        }
+    }
     if (ctx->timing) PC_HIP(ctx, hipEventRecord(ctx->ev1, hs));
 
     int32_t* hc = reinterpret_cast<int32_t*>(st);   // staging is free again once the copy has run

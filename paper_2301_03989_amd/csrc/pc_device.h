@@ -1,0 +1,488 @@
+// pc_device.h -- device-side building blocks shared by the fused and the plain kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include "pc_internal.h"
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+#define PC_PI 3.14159265358979323846
+
+static __device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c)
+{
+    // D = A(16x4) B(4x16) + C.  Operand lanes: A[l%16][l/16], B[l/16][l%16];
+    // result lanes on gfx950: D[l/16 + 4r][l%16] in element r.
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// max that propagates NaN from either argument
+static __device__ __forceinline__ double nmax(double a, double b)
+{
+    return (a > b || a != a) ? a : b;
+}
+
+// ---------------------------------------------------------------------------
+// Two-body orbits (gravitational parameter 1)
+// ---------------------------------------------------------------------------
+
+// Eccentric anomaly from the mean anomaly (Kepler's equation, Newton's method).
+// Returns E modulo 2 pi.
+static __device__ double pc_ecc_anomaly(double M, double e)
+{
+    const double Mr = M - 2.0 * PC_PI * rint(M / (2.0 * PC_PI));
+    double E = (e < 0.8) ? Mr : (Mr >= 0.0 ? PC_PI : -PC_PI);
+    for (int it = 0; it < 60; ++it) {
+        double sE, cE;
+        sincos(E, &sE, &cE);
+        const double dE = (E - e * sE - Mr) / (1.0 - e * cE);
+        E -= dE;
+        if (fabs(dE) <= 1e-16 * (1.0 + fabs(E))) break;
+    }
+    return E;
+}
+
+static __device__ void pc_body_position(const PcBodyDev& B, double dt_epoch, double r[3])
+{
+    const double E = pc_ecc_anomaly(B.M0 + B.n * dt_epoch, B.e);
+    double sE, cE;
+    sincos(E, &sE, &cE);
+    const double xp = B.a * (cE - B.e);
+    const double yp = B.b * sE;
+    for (int k = 0; k < 3; ++k) r[k] = xp * B.P[k] + yp * B.Q[k];
+}
+
+// Warm start (Sec. 2.1): propagate y0 by dt on its osculating ellipse, through the
+// Lagrange coefficients f, g, fdot, gdot written in the eccentric-anomaly change x:
+//   x - (1 - r0/a) sin x + (r0.v0/sqrt(a)) (1 - cos x) = n dt.
+// Returns false for non-elliptic or degenerate states.
+static __device__ __attribute__((noinline)) bool pc_kepler(const double y0[6], double dt, double y[6])
+{
+    const double r0n = sqrt(y0[0] * y0[0] + y0[1] * y0[1] + y0[2] * y0[2]);
+    const double v02 = y0[3] * y0[3] + y0[4] * y0[4] + y0[5] * y0[5];
+    if (!(r0n > 0.0) || !isfinite(r0n) || !isfinite(v02)) return false;
+    const double alpha = 2.0 / r0n - v02;          // 1/a
+    if (!(alpha > 0.0)) return false;
+    const double a = 1.0 / alpha;
+    const double sqa = sqrt(a);
+    const double n = alpha * sqrt(alpha);          // mean motion
+    const double sig = y0[0] * y0[3] + y0[1] * y0[4] + y0[2] * y0[5];
+    const double ec = 1.0 - r0n * alpha;           // e cos E0
+    const double es = sig / sqa;                   // e sin E0
+    const double ndt = n * dt;
+    double x = ndt;
+    for (int it = 0; it < 60; ++it) {
+        double sx, cx;
+        sincos(x, &sx, &cx);
+        const double F = x - ec * sx + es * (1.0 - cx) - ndt;
+        const double dx = F / (1.0 - ec * cx + es * sx);
+        x -= dx;
+        if (fabs(dx) <= 1e-16 * (1.0 + fabs(x))) break;
+    }
+    double sx, cx;
+    sincos(x, &sx, &cx);
+    const double rn = a + (r0n - a) * cx + sig * sqa * sx;
+    const double f = 1.0 - (a / r0n) * (1.0 - cx);
+    const double g = dt - (x - sx) / n;
+    const double fd = -sqa * sx / (rn * r0n);
+    const double gd = 1.0 - (a / rn) * (1.0 - cx);
+    bool ok = true;
+    for (int k = 0; k < 3; ++k) {
+        y[k] = f * y0[k] + g * y0[3 + k];
+        y[3 + k] = fd * y0[k] + gd * y0[3 + k];
+        ok = ok && isfinite(y[k]) && isfinite(y[3 + k]);
+    }
+    return ok;
+}
+
+// ---------------------------------------------------------------------------
+// Force model: point masses in the heliocentric frame with the indirect term,
+//   a = -mu_S r/|r|^3 - sum_p mu_p (r - r_p)/|r - r_p|^3 - sum_p mu_p r_p/|r_p|^3.
+// rec[p] = (r_p, mu_p) for p < P; rec[P] = (precomputed indirect sum, 0).
+// ---------------------------------------------------------------------------
+static __device__ __forceinline__ void pc_accel(double x, double y, double z, const double4* rec,
+                                                int P, double mu_sun, double& ax, double& ay,
+                                                double& az)
+{
+    const double r2 = x * x + y * y + z * z;
+    const double ir = rsqrt(r2);
+    const double s = mu_sun * (ir * ir * ir);
+    ax = -s * x;
+    ay = -s * y;
+    az = -s * z;
+    for (int p = 0; p < P; ++p) {
+        const double4 q = rec[p];
+        const double dx = x - q.x, dy = y - q.y, dz = z - q.z;
+        const double id = rsqrt(dx * dx + dy * dy + dz * dz);
+        const double sd = q.w * (id * id * id);
+        ax -= sd * dx;
+        ay -= sd * dy;
+        az -= sd * dz;
+    }
+    const double4 ind = rec[P];
+    ax -= ind.x;
+    ay -= ind.y;
+    az -= ind.z;
+}
+
+
+// ---------------------------------------------------------------------------
+// Shared pieces of the propagation kernels
+// ---------------------------------------------------------------------------
+typedef const __attribute__((address_space(1))) double* gconst_dp;
+
+// Shared-memory arena of one workgroup (sized for the largest job shape).
+template <int PAIRS>
+struct PcSmem {
+    static constexpr int REC = PAIRS >= 2048 ? 7040 : 3072;   // doubles of ephemeris kept in LDS
+    double F[6 * PAIRS];          // [node][F comp 6][IC]: velocity (0..2), acceleration (3..5)
+    double Rec[REC];              // [node][body 0..P][3]: perturber positions, then the indirect term
+    double Y0[6 * (PAIRS / 16)];  // [comp][IC] initial state of the current segment
+    double Mu[PC_MAX_PERT_DEV];   // perturber parameters
+    int Flag[(PAIRS / 256) * 16]; // per wave, per IC: bit 0 not converged, bit 1 non-finite
+    int Active[PAIRS / 16];
+    int Dead[PAIRS / 16];
+};
+
+// Accelerations at R points whose perturber records sit in LDS (compact [node][body][3]).
+template <int R>
+static __device__ __forceinline__ void pc_force_lds(const double (&x)[R], const double (&y)[R],
+                                                    const double (&z)[R], const int (&jr)[R], int P,
+                                                    double mu_sun, const double* srec, const double* smu,
+                                                    double (&ax)[R], double (&ay)[R], double (&az)[R])
+{
+    const int stride = 3 * (P + 1);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const double ir = rsqrt(x[r] * x[r] + y[r] * y[r] + z[r] * z[r]);
+        const double s = mu_sun * (ir * ir * ir);
+        ax[r] = -s * x[r];
+        ay[r] = -s * y[r];
+        az[r] = -s * z[r];
+    }
+    for (int b = 0; b < P; ++b) {
+        const double mu = smu[b];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double* q = srec + jr[r] * stride + 3 * b;
+            const double dx = x[r] - q[0], dy = y[r] - q[1], dz = z[r] - q[2];
+            const double id = rsqrt(dx * dx + dy * dy + dz * dz);
+            const double sd = mu * (id * id * id);
+            ax[r] -= sd * dx;
+            ay[r] -= sd * dy;
+            az[r] -= sd * dz;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const double* q = srec + jr[r] * stride + 3 * P;
+        ax[r] -= q[0];
+        ay[r] -= q[1];
+        az[r] -= q[2];
+    }
+}
+
+// Same with the records read from global memory ((x, y, z, mu) per body, then the indirect term).
+template <int R>
+static __device__ __forceinline__ void pc_force_glb(const double (&x)[R], const double (&y)[R],
+                                                    const double (&z)[R], const int (&jr)[R], int P,
+                                                    double mu_sun, const double4* grec,
+                                                    double (&ax)[R], double (&ay)[R], double (&az)[R])
+{
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const double ir = rsqrt(x[r] * x[r] + y[r] * y[r] + z[r] * z[r]);
+        const double s = mu_sun * (ir * ir * ir);
+        ax[r] = -s * x[r];
+        ay[r] = -s * y[r];
+        az[r] = -s * z[r];
+    }
+    for (int b = 0; b < P; ++b) {
+        double4 q[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) q[r] = grec[(size_t)jr[r] * (P + 1) + b];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double dx = x[r] - q[r].x, dy = y[r] - q[r].y, dz = z[r] - q[r].z;
+            const double id = rsqrt(dx * dx + dy * dy + dz * dz);
+            const double sd = q[r].w * (id * id * id);
+            ax[r] -= sd * dx;
+            ay[r] -= sd * dy;
+            az[r] -= sd * dz;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const double4 q = grec[(size_t)jr[r] * (P + 1) + P];
+        ax[r] -= q.x;
+        ay[r] -= q.y;
+        az[r] -= q.z;
+    }
+}
+
+// Shape of a job: PAIRS = NP x T (node, IC) pairs, NT threads in W waves; every wave owns
+// six 16x16 blocks of the iterate.  WIDE (T >= 16): one 16-row strip x the six component
+// blocks of one 16-IC group.  Otherwise (T == 8): two strips x three blocks of two
+// components x 8 ICs; lane l holds components hi, 2+hi, 4+hi of IC l%8 (hi = bit 3 of l).
+template <int PAIRS, int NP>
+struct PcShape {
+    static constexpr int NT = PAIRS / 4;
+    static constexpr int W = NT / 64;
+    static constexpr int T = PAIRS / NP;
+    static constexpr int ROW = 6 * T;      // doubles per node row of F
+    static constexpr int NQ = NP / 4;      // k-steps of the 16x16x4 product
+    static constexpr bool WIDE = T >= 16;
+    static constexpr int G16 = WIDE ? T / 16 : 1;
+    static constexpr int H = WIDE ? 1 : 2; // strips per wave
+    static_assert(T >= 8 && T <= PAIRS / 16, "unsupported job shape");
+};
+
+struct PcLane {
+    int lane, wave, strip0, grp, my_m, hi;
+};
+
+template <int PAIRS, int NP>
+static __device__ __forceinline__ PcLane pc_lane_geometry(int tid)
+{
+    using Sh = PcShape<PAIRS, NP>;
+    PcLane L;
+    L.lane = tid & 63;
+    L.wave = tid >> 6;
+    L.strip0 = Sh::WIDE ? L.wave / Sh::G16 : 2 * L.wave;
+    L.grp = Sh::WIDE ? L.wave - L.strip0 * Sh::G16 : 0;
+    L.my_m = Sh::WIDE ? L.grp * 16 + (L.lane & 15) : (L.lane & 7);
+    L.hi = Sh::WIDE ? 0 : (L.lane >> 3) & 1;
+    return L;
+}
+
+// node of the lane's element r in strip h (MFMA f64 result layout: row l/16 + 4r)
+static __device__ __forceinline__ int pc_node(const PcLane& L, int h, int r)
+{
+    return (L.strip0 + h) * 16 + (L.lane >> 4) + 4 * r;
+}
+
+// y_new = y0 + w2 K_N F on the FP64 matrix cores (Sec. 2.2 with A, C and S folded into K_N)
+// for the lane's six blocks; acc receives y_new.  Also evaluates the stopping rule of
+// Sec. 2.2 against the previous iterate yc in squared form (|dr|^2 < tol^2 |r|^2 and the
+// same for v, or without the norms in absolute mode) and returns, OR-ed over the lanes
+// of each IC: bit 0 = some node not converged, bit 1 = non-finite.
+template <int PAIRS, int NP>
+static __device__ __forceinline__ int pc_product(const double* sF, const double* sY0, gconst_dp kp0,
+                                                  const double (&yc)[6][4], f64x4 (&acc)[6], double w2,
+                                                  double t2, int tol_mode, int N, const PcLane& L)
+{
+    using Sh = PcShape<PAIRS, NP>;
+    constexpr int T = Sh::T, ROW = Sh::ROW, NQ = Sh::NQ;
+    const int lane = L.lane, my_m = L.my_m, hi = L.hi;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) acc[b] = f64x4{0.0, 0.0, 0.0, 0.0};
+    int flag = 0;
+    if constexpr (Sh::WIDE) {
+        // K_N strip streamed from L2 two k-steps ahead; B operands one k-step ahead
+        const double* bp = sF + (lane >> 4) * ROW + L.grp * 16 + (lane & 15);
+        double bc[6], bn[6];
+        double ka = kp0[0], kb = (NQ > 1) ? kp0[64] : 0.0;
+#pragma unroll
+        for (int b = 0; b < 6; ++b) bc[b] = bp[b * T];
+#pragma unroll 2
+        for (int q = 0; q < NQ; ++q) {
+            const double kn = (q + 2 < NQ) ? kp0[(q + 2) * 64] : 0.0;
+            if (q + 1 < NQ) {
+#pragma unroll
+                for (int b = 0; b < 6; ++b) bn[b] = bp[(q + 1) * 4 * ROW + b * T];
+            }
+#pragma unroll
+            for (int b = 0; b < 6; ++b) acc[b] = mfma16(ka, bc[b], acc[b]);
+#pragma unroll
+            for (int b = 0; b < 6; ++b) bc[b] = bn[b];
+            ka = kb;
+            kb = kn;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = pc_node(L, 0, r);
+            double pd = 0.0, py = 0.0, vd = 0.0, vy = 0.0;
+#pragma unroll
+            for (int b = 0; b < 6; ++b) {
+                const double yn = sY0[b * T + my_m] + w2 * acc[b][r];
+                acc[b][r] = yn;
+                const double d = yn - yc[b][r];
+                if (b < 3) { pd += d * d; py += yn * yn; }
+                else { vd += d * d; vy += yn * yn; }
+            }
+            if (j < N) {
+                const bool ok = tol_mode == 0 ? (pd < t2 * py && vd < t2 * vy) : (pd < t2 && vd < t2);
+                const bool nf = !isfinite(pd + py + vd + vy);
+                flag |= (ok ? 0 : 1) | (nf ? 2 : 0);
+            }
+        }
+    } else {
+        gconst_dp kp1 = kp0 + (size_t)NQ * 64;
+        const double* bp = sF + (lane >> 4) * ROW + (lane & 15);
+        double a0 = kp0[0], a1 = kp1[0];
+        double a0n = 0.0, a1n = 0.0;
+        double b0 = bp[0], b1 = bp[16], b2 = bp[32];
+#pragma unroll 4
+        for (int q = 0; q < NQ; ++q) {
+            double b0n = 0.0, b1n = 0.0, b2n = 0.0;
+            if (q + 1 < NQ) {
+                a0n = kp0[(q + 1) * 64];
+                a1n = kp1[(q + 1) * 64];
+                const double* bq = bp + (q + 1) * 4 * ROW;
+                b0n = bq[0];
+                b1n = bq[16];
+                b2n = bq[32];
+            }
+            acc[0] = mfma16(a0, b0, acc[0]);
+            acc[1] = mfma16(a0, b1, acc[1]);
+            acc[2] = mfma16(a0, b2, acc[2]);
+            acc[3] = mfma16(a1, b0, acc[3]);
+            acc[4] = mfma16(a1, b1, acc[4]);
+            acc[5] = mfma16(a1, b2, acc[5]);
+            a0 = a0n; a1 = a1n;
+            b0 = b0n; b1 = b1n; b2 = b2n;
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = pc_node(L, h, r);
+                double dd[3], yy[3];
+#pragma unroll
+                for (int cb = 0; cb < 3; ++cb) {
+                    const double yn = sY0[(2 * cb + hi) * T + my_m] + w2 * acc[3 * h + cb][r];
+                    acc[3 * h + cb][r] = yn;
+                    const double d = yn - yc[3 * h + cb][r];
+                    dd[cb] = d * d;
+                    yy[cb] = yn * yn;
+                }
+                double pd = dd[0] + (hi ? 0.0 : dd[1]);
+                double py = yy[0] + (hi ? 0.0 : yy[1]);
+                double vd = (hi ? dd[1] : 0.0) + dd[2];
+                double vy = (hi ? yy[1] : 0.0) + yy[2];
+                pd += __shfl_xor(pd, 8);
+                py += __shfl_xor(py, 8);
+                vd += __shfl_xor(vd, 8);
+                vy += __shfl_xor(vy, 8);
+                if (j < N) {
+                    const bool ok = tol_mode == 0 ? (pd < t2 * py && vd < t2 * vy) : (pd < t2 && vd < t2);
+                    const bool nf = !isfinite(pd + py + vd + vy);
+                    flag |= (ok ? 0 : 1) | (nf ? 2 : 0);
+                }
+            }
+        }
+        flag |= __shfl_xor(flag, 8);
+    }
+    flag |= __shfl_xor(flag, 16);
+    flag |= __shfl_xor(flag, 32);
+    return flag;
+}
+
+// OR of the per-wave flags of IC m (written as Flag[wave][lane] by lanes < 16).
+template <int PAIRS, int NP>
+static __device__ __forceinline__ int pc_gather_flags(const int* sFlag, int m)
+{
+    using Sh = PcShape<PAIRS, NP>;
+    int f = 0;
+    if constexpr (Sh::WIDE) {
+        for (int w = m >> 4; w < Sh::W; w += Sh::G16) f |= sFlag[w * 16 + (m & 15)];
+    } else {
+        for (int w = 0; w < Sh::W; ++w) f |= sFlag[w * 16 + m];
+    }
+    return f;
+}
+
+// Dynamics of the lane's (node, IC) pairs from its registers, published with the
+// velocities as the force matrix F = (v, a) of Sec. 2.2 into sF[node][comp'][IC].
+// sRec/sMu: the segment's records in LDS (when rec_lds), grec: the same in global memory.
+template <int PAIRS, int NP>
+static __device__ __forceinline__ void pc_publish(double* sF, const double (&yc)[6][4], const PcLane& L,
+                                                  int N, int P, double mu_sun, bool rec_lds,
+                                                  const double* sRec, const double* sMu, const double4* grec)
+{
+    using Sh = PcShape<PAIRS, NP>;
+    constexpr int T = Sh::T, ROW = Sh::ROW;
+    const int my_m = L.my_m, hi = L.hi;
+    if constexpr (Sh::WIDE) {
+        double ax[4], ay[4], az[4];
+        int jr[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = pc_node(L, 0, r);
+            jr[r] = j < N ? j : N - 1;
+        }
+        if (rec_lds) pc_force_lds<4>(yc[0], yc[1], yc[2], jr, P, mu_sun, sRec, sMu, ax, ay, az);
+        else pc_force_glb<4>(yc[0], yc[1], yc[2], jr, P, mu_sun, grec, ax, ay, az);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = pc_node(L, 0, r);
+            if (j < N) {
+                double* f = sF + j * ROW + my_m;
+                f[0 * T] = yc[3][r];
+                f[1 * T] = yc[4][r];
+                f[2 * T] = yc[5][r];
+                f[3 * T] = ax[r];
+                f[4 * T] = ay[r];
+                f[5 * T] = az[r];
+            }
+        }
+    } else {
+        // lanes with hi == 0 hold x (cb 0) and z (cb 1); y comes from the partner lane
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            double xs[4], ys[4], zs[4], ax[4], ay[4], az[4];
+            int jr[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = pc_node(L, h, r);
+                jr[r] = j < N ? j : N - 1;
+                xs[r] = yc[3 * h][r];
+                ys[r] = __shfl_xor(yc[3 * h][r], 8);
+                zs[r] = yc[3 * h + 1][r];
+            }
+            if (!hi) {
+                if (rec_lds) pc_force_lds<4>(xs, ys, zs, jr, P, mu_sun, sRec, sMu, ax, ay, az);
+                else pc_force_glb<4>(xs, ys, zs, jr, P, mu_sun, grec, ax, ay, az);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = pc_node(L, h, r);
+                if (j < N) {
+                    double* f = sF + j * ROW + my_m;
+                    if (hi) {
+                        f[0 * T] = yc[3 * h + 1][r];   // vx (comp 3)
+                        f[2 * T] = yc[3 * h + 2][r];   // vz (comp 5)
+                    } else {
+                        f[1 * T] = yc[3 * h + 2][r];   // vy (comp 4)
+                        f[3 * T] = ax[r];
+                        f[4 * T] = ay[r];
+                        f[5 * T] = az[r];
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Load / store the lane's share of a [node][comp][IC] array with row stride `row` and
+// comp stride `cs` (WIDE: yc[c][r]; T == 8: yc[3h + cb][r] = comp 2cb + hi).
+template <int PAIRS, int NP, class Ptr>
+static __device__ __forceinline__ void pc_load_share(Ptr base, size_t row, size_t cs, double (&yc)[6][4],
+                                                     const PcLane& L, int N)
+{
+    using Sh = PcShape<PAIRS, NP>;
+#pragma unroll
+    for (int h = 0; h < Sh::H; ++h) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = pc_node(L, h, r);
+            const int jj = j < N ? j : N - 1;
+            if constexpr (Sh::WIDE) {
+#pragma unroll
+                for (int c = 0; c < 6; ++c) yc[c][r] = base[jj * row + c * cs + L.my_m];
+            } else {
+#pragma unroll
+                for (int cb = 0; cb < 3; ++cb) yc[3 * h + cb][r] = base[jj * row + (2 * cb + L.hi) * cs + L.my_m];
+            }
+        }
+    }
+}

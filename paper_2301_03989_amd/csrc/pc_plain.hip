@@ -1,0 +1,320 @@
+// pc_plain.hip -- the "plain" GPU path: one group at a time, a sequence of kernels per
+// Picard iteration and a host-side loop, the structure of the paper's CUDA program
+// (Sec. 5.4): dynamics kernel over all stacked states, the fit/integrate/evaluate
+// product (here one FP64 MFMA product with the +y0 term in its epilogue), the error
+// computation and its reduction, and a host check of the result every iteration.
+//
+// Differences from the paper's program: the error is per IC (converged ICs are frozen
+// and jobs whose ICs have all converged are compacted out of the next launches) and
+// the host reads back one active-job count per iteration instead of block maxima.
+//
+// State in HBM, per group: Y[node][comp 9][IC] (comps 0..5 iterate, 6..8 acceleration),
+// IC index fastest -- the component-major, row-by-node layout of Sec. 5.4.1.
+#include "pc_device.h"
+#include "pc_plain.h"
+
+namespace {
+
+constexpr int kPlainForceBlock = 256;
+
+// Initial states of the group's ICs (padding columns copy the job's first IC).
+__global__ void pc_plain_load(PcPlainArgs a)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= a.Mpad) return;
+    const PcJobDev job = a.jobs[m / a.T];
+    const int i = (int)(m % a.T);
+    const double* y = a.p.ics + (job.ic0 + (i < job.n ? i : 0)) * 6;
+    bool fin = true;
+    for (int c = 0; c < 6; ++c) {
+        const double v = y[c];
+        a.Y0[c * a.Mpad + m] = v;
+        fin = fin && isfinite(v);
+    }
+    a.dead[m] = !fin;
+    a.notconv[m] = 0;
+    a.valid[m] = i < job.n;
+}
+
+// Segment start: initial guess (Kepler or cold, Sec. 2.1) at every (node, IC) pair,
+// zero padding rows, flags and the full job list.
+__global__ void pc_plain_init(PcPlainArgs a, int s, double w2)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)a.NP * a.Mpad;
+    if (idx < a.n_jobs) a.job_list[idx] = (int32_t)idx;
+    if (idx == 0) a.count[0] = a.n_jobs;
+    if (idx >= total) return;
+    const int j = (int)(idx / a.Mpad);
+    const int64_t m = idx - (int64_t)j * a.Mpad;
+    double* Yj = a.Y + (size_t)j * 9 * a.Mpad + m;
+    if (j >= a.N) {
+        for (int c = 0; c < 9; ++c) Yj[c * a.Mpad] = 0.0;
+        return;
+    }
+    double y0[6], y[6];
+    for (int c = 0; c < 6; ++c) y0[c] = a.Y0[c * a.Mpad + m];
+    const bool dead = a.dead[m];
+    if (!(a.p.init == 0 && !dead && pc_kepler(y0, w2 * (a.g->tau[j] + 1.0), y)))
+        for (int c = 0; c < 6; ++c) y[c] = y0[c];
+    for (int c = 0; c < 6; ++c) Yj[c * a.Mpad] = y[c];
+    if (j == 0) {
+        a.active[m] = a.valid[m] && !dead;
+        if (dead && a.valid[m] && a.p.iters_out) {
+            const PcJobDev job = a.jobs[m / a.T];
+            a.p.iters_out[(size_t)(job.ic0 + m % a.T) * a.p.iters_stride + s] = -2;
+        }
+    }
+}
+
+// Dynamics at every (node, IC) pair of the active jobs (the paper's dynamics kernel):
+// one thread per pair, state read from and acceleration written to HBM.
+__global__ __launch_bounds__(kPlainForceBlock) void pc_plain_force(PcPlainArgs a, int s)
+{
+    const int bpj = (a.NP * a.T) / kPlainForceBlock;          // blocks per job
+    const int job = a.job_list[blockIdx.x / bpj];
+    const int pr = (blockIdx.x % bpj) * kPlainForceBlock + threadIdx.x;
+    const int j = pr / a.T;
+    const int64_t m = (int64_t)job * a.T + pr % a.T;
+    if (j >= a.N || !a.active[m]) return;
+    const int P = a.p.n_pert;
+    const double4* rec = reinterpret_cast<const double4*>(a.p.recs) +
+                         (size_t)(a.g->rec_offset + (int64_t)s * a.N + j) * (P + 1);
+    double* Yj = a.Y + (size_t)j * 9 * a.Mpad + m;
+    double ax, ay, az;
+    pc_accel(Yj[0], Yj[a.Mpad], Yj[2 * a.Mpad], rec, P, a.p.mu_sun, ax, ay, az);
+    Yj[6 * a.Mpad] = ax;
+    Yj[7 * a.Mpad] = ay;
+    Yj[8 * a.Mpad] = az;
+}
+
+// The product y_new = y0 + w2 K_N F for one active job per workgroup, with the error of
+// every IC against the previous iterate and the stopping decision in the epilogue.
+template <int PAIRS, int NP>
+__global__ __launch_bounds__(PAIRS / 4) void pc_plain_step(PcPlainArgs a, int s, int it, double w2)
+{
+    using Sh = PcShape<PAIRS, NP>;
+    constexpr int NT = Sh::NT, T = Sh::T, ROW = Sh::ROW, NQ = Sh::NQ;
+    __shared__ double sF[6 * PAIRS];
+    __shared__ double sY0[6 * T];
+    __shared__ int sFlag[Sh::W * 16];
+    __shared__ int sActive[T];
+
+    const int tid = threadIdx.x;
+    const int job = a.job_list[blockIdx.x];
+    const int64_t m0 = (int64_t)job * T;
+    const int N = a.N;
+    const PcLane L = pc_lane_geometry<PAIRS, NP>(tid);
+    const size_t row = (size_t)9 * a.Mpad;
+
+    // stage F = (v, a) of the job (Y comps 3..8) and its initial states
+    for (int i = tid; i < 6 * PAIRS; i += NT) {
+        const int j = i / ROW, c = (i % ROW) / T, k = i % T;
+        sF[i] = j < N ? a.Y[(size_t)j * row + (size_t)(3 + c) * a.Mpad + m0 + k] : 0.0;
+    }
+    for (int i = tid; i < 6 * T; i += NT) sY0[i] = a.Y0[(size_t)(i / T) * a.Mpad + m0 + i % T];
+    if (tid < T) sActive[tid] = a.active[m0 + tid];
+    double yc[6][4];
+    pc_load_share<PAIRS, NP>(a.Y + m0, row, (size_t)a.Mpad, yc, L, N);
+    __syncthreads();
+
+    f64x4 acc[6];
+    gconst_dp kp0 = (gconst_dp)a.g->kfrag + (size_t)L.strip0 * NQ * 64 + L.lane;
+    const int flag = pc_product<PAIRS, NP>(sF, sY0, kp0, yc, acc, w2, a.t2, a.p.tol_mode, N, L);
+    if (L.lane < 16) sFlag[L.wave * 16 + L.lane] = flag;
+    const int act = sActive[L.my_m];
+    __syncthreads();
+
+    if (tid < T && sActive[tid]) {
+        const int f = pc_gather_flags<PAIRS, NP>(sFlag, tid);
+        int rec = 0;
+        if (f & 2) rec = -2;
+        else if (a.p.fixed_iters > 0) rec = (it == a.p.fixed_iters) ? it : 0;
+        else if (!(f & 1)) rec = it;
+        else if (it == a.p.max_iter) rec = -1;
+        if (rec != 0) {
+            sActive[tid] = 0;
+            a.active[m0 + tid] = 0;
+            if (rec == -2) a.dead[m0 + tid] = 1;
+            if (rec == -1) a.notconv[m0 + tid] = 1;
+            const PcJobDev jd = a.jobs[job];
+            if (tid < jd.n && a.p.iters_out)
+                a.p.iters_out[(size_t)(jd.ic0 + tid) * a.p.iters_stride + s] = rec;
+        }
+    }
+    // new iterate of the ICs that were iterating
+    if (act) {
+#pragma unroll
+        for (int h = 0; h < Sh::H; ++h) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = pc_node(L, h, r);
+                if (j >= N) continue;
+                double* yw = a.Y + (size_t)j * row + m0 + L.my_m;
+                if constexpr (Sh::WIDE) {
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) yw[(size_t)c * a.Mpad] = acc[c][r];
+                } else {
+#pragma unroll
+                    for (int cb = 0; cb < 3; ++cb) yw[(size_t)(2 * cb + L.hi) * a.Mpad] = acc[3 * h + cb][r];
+                }
+            }
+        }
+    }
+    const int any = __syncthreads_or(tid < T ? sActive[tid] : 0);
+    if (tid == 0) a.job_flag[job] = any;
+}
+
+// Stream compaction of the active job list: prefix sum of the job flags (one workgroup).
+__global__ __launch_bounds__(1024) void pc_plain_compact(PcPlainArgs a)
+{
+    __shared__ int sScan[1024];
+    __shared__ int sBase;
+    const int n_in = a.count[0];
+    if (threadIdx.x == 0) sBase = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < n_in; c0 += 1024) {
+        const int i = c0 + threadIdx.x;
+        const int job = i < n_in ? a.job_list[i] : -1;
+        const int f = (job >= 0) ? (a.job_flag[job] != 0) : 0;
+        sScan[threadIdx.x] = f;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {          // inclusive Hillis-Steele scan
+            const int v = threadIdx.x >= off ? sScan[threadIdx.x - off] : 0;
+            __syncthreads();
+            sScan[threadIdx.x] += v;
+            __syncthreads();
+        }
+        if (f) a.job_list_out[sBase + sScan[threadIdx.x] - 1] = job;
+        __syncthreads();
+        if (threadIdx.x == 1023) sBase += sScan[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) a.count[1] = sBase;
+}
+
+// Segment end: the last node starts the next segment; optional node / boundary outputs.
+__global__ void pc_plain_chain(PcPlainArgs a, int s, int last)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= a.Mpad) return;
+    const PcJobDev job = a.jobs[m / a.T];
+    const int i = (int)(m % a.T);
+    const bool valid = i < job.n;
+    const int64_t ic = job.ic0 + i;
+    const size_t row = (size_t)9 * a.Mpad;
+    if (valid && a.p.nodes_out) {
+        for (int j = 0; j < a.N; ++j) {
+            double* o = a.p.nodes_out + (((size_t)ic * a.p.iters_stride + s) * a.p.nodes_stride + j) * 6;
+            for (int c = 0; c < 6; ++c) o[c] = a.Y[(size_t)j * row + (size_t)c * a.Mpad + m];
+        }
+    }
+    const bool dead = a.dead[m];
+    for (int c = 0; c < 6; ++c) {
+        const double v = dead ? (double)NAN : a.Y[(size_t)(a.N - 1) * row + (size_t)c * a.Mpad + m];
+        a.Y0[c * a.Mpad + m] = v;
+        if (valid && a.p.bounds_out)
+            a.p.bounds_out[((size_t)ic * (a.p.iters_stride + 1) + s + 1) * 6 + c] = v;
+    }
+    if (valid && last) {
+        for (int c = 0; c < 6; ++c) a.p.states_out[(size_t)ic * 6 + c] = a.Y0[c * a.Mpad + m];
+        if (a.notconv[m]) atomicAdd(&a.p.counters[0], 1);
+        if (dead) atomicAdd(&a.p.counters[1], 1);
+    }
+}
+
+__global__ void pc_plain_bounds0(PcPlainArgs a)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= a.Mpad || !a.p.bounds_out) return;
+    const PcJobDev job = a.jobs[m / a.T];
+    const int i = (int)(m % a.T);
+    if (i >= job.n) return;
+    for (int c = 0; c < 6; ++c)
+        a.p.bounds_out[((size_t)(job.ic0 + i) * (a.p.iters_stride + 1)) * 6 + c] = a.Y0[c * a.Mpad + m];
+}
+
+template <int PAIRS, int NP>
+void launch_step(const PcPlainArgs& a, int grid, int s, int it, double w2, hipStream_t st)
+{
+    hipLaunchKernelGGL((pc_plain_step<PAIRS, NP>), dim3(grid), dim3(PAIRS / 4), 0, st, a, s, it, w2);
+}
+
+int launch_step_np(const PcPlainArgs& a, int grid, int s, int it, double w2, hipStream_t st)
+{
+    switch (a.NP) {
+    case 16: launch_step<2048, 16>(a, grid, s, it, w2, st); break;
+    case 32: launch_step<2048, 32>(a, grid, s, it, w2, st); break;
+    case 64: launch_step<2048, 64>(a, grid, s, it, w2, st); break;
+    case 128: launch_step<2048, 128>(a, grid, s, it, w2, st); break;
+    case 256: launch_step<2048, 256>(a, grid, s, it, w2, st); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t pc_plain_bytes(int NP, int n_jobs, int T)
+{
+    const size_t Mpad = (size_t)n_jobs * T;
+    auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+    return al(9 * (size_t)NP * Mpad * 8) + al(6 * Mpad * 8) + 4 * al(Mpad * 4) + 3 * al((size_t)n_jobs * 4) + 256;
+}
+
+int pc_run_plain(PcPlainArgs a, void* workspace, int32_t* host_count, void* stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+    char* w = static_cast<char*>(workspace);
+    a.Mpad = (int64_t)a.n_jobs * a.T;
+    a.Y = reinterpret_cast<double*>(w);                w += al(9 * (size_t)a.NP * a.Mpad * 8);
+    a.Y0 = reinterpret_cast<double*>(w);               w += al(6 * (size_t)a.Mpad * 8);
+    a.active = reinterpret_cast<int32_t*>(w);          w += al(a.Mpad * 4);
+    a.dead = reinterpret_cast<int32_t*>(w);            w += al(a.Mpad * 4);
+    a.notconv = reinterpret_cast<int32_t*>(w);         w += al(a.Mpad * 4);
+    a.valid = reinterpret_cast<int32_t*>(w);           w += al(a.Mpad * 4);
+    int32_t* lists[2];
+    lists[0] = reinterpret_cast<int32_t*>(w);          w += al((size_t)a.n_jobs * 4);
+    lists[1] = reinterpret_cast<int32_t*>(w);          w += al((size_t)a.n_jobs * 4);
+    a.job_flag = reinterpret_cast<int32_t*>(w);        w += al((size_t)a.n_jobs * 4);
+    a.count = reinterpret_cast<int32_t*>(w);
+
+    const int bs = 256;
+    const unsigned gm = (unsigned)((a.Mpad + bs - 1) / bs);
+    hipLaunchKernelGGL(pc_plain_load, dim3(gm), dim3(bs), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(pc_plain_bounds0, dim3(gm), dim3(bs), 0, st, a);
+    const int bpj = a.NP * a.T / kPlainForceBlock;
+    const int n_it = a.p.fixed_iters > 0 ? a.p.fixed_iters : a.p.max_iter;
+    const double h = a.g_host.h;
+    for (int s = 0; s < a.S; ++s) {
+        const double Ts = a.g_host.t0 + h * s, Te = a.g_host.t0 + h * (s + 1);
+        const double w2 = 0.5 * (Te - Ts);
+        int cur = 0;
+        a.job_list = lists[cur];
+        const int64_t total = (int64_t)a.NP * a.Mpad;
+        hipLaunchKernelGGL(pc_plain_init, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, st, a, s, w2);
+        int count = a.n_jobs;
+        for (int it = 1; it <= n_it && count > 0; ++it) {
+            a.job_list = lists[cur];
+            a.job_list_out = lists[1 - cur];
+            hipLaunchKernelGGL(pc_plain_force, dim3((unsigned)(count * bpj)), dim3(kPlainForceBlock), 0, st, a, s);
+            e = (hipError_t)launch_step_np(a, count, s, it, w2, st);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(pc_plain_compact, dim3(1), dim3(1024), 0, st, a);
+            // host loop control: read back the number of jobs still iterating (Sec. 5.4.2)
+            e = hipMemcpyAsync(host_count, a.count + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+            if (e != hipSuccess) return e;
+            e = hipMemcpyAsync(a.count, a.count + 1, sizeof(int32_t), hipMemcpyDeviceToDevice, st);
+            if (e != hipSuccess) return e;
+            e = hipStreamSynchronize(st);
+            if (e != hipSuccess) return e;
+            count = *host_count;
+            cur = 1 - cur;
+        }
+        hipLaunchKernelGGL(pc_plain_chain, dim3(gm), dim3(bs), 0, st, a, s, s == a.S - 1 ? 1 : 0);
+    }
+    return hipGetLastError();
+}

@@ -221,3 +221,46 @@ def test_full_size_nbody_sampled(pc):
     o = oracle_run(w, idx)
     assert rel_err(r["states"][idx], o["states"]).max() < TOL
     assert np.abs(r["iters"][idx] - o["iters"]).max() <= 1
+
+
+# ---------------------------------------------------------------------------
+# plain path: per-iteration kernels and host loop
+# ---------------------------------------------------------------------------
+def test_plain_path_matches_oracle(pc):
+    w = W.nbody_venus(250)
+    r, _ = _run(pc, w, path="plain", want_bounds=True)
+    o = oracle_run(w, want_bounds=True)
+    assert r["status"] == 0
+    assert rel_err(r["states"], o["states"]).max() < TOL
+    assert rel_err(r["bounds"].reshape(-1, 6), o["bounds"].reshape(-1, 6)).max() < TOL
+    assert np.abs(r["iters"] - o["iters"]).max() <= 1
+
+
+def test_plain_and_fused_agree(pc):
+    w = W.nbody_venus(40)
+    a, _ = _run(pc, w, fixed_iters=7, want_nodes=True)
+    b, _ = _run(pc, w, fixed_iters=7, want_nodes=True, path="plain")
+    assert rel_err(a["nodes"].reshape(-1, 6), b["nodes"].reshape(-1, 6)).max() < 1e-14
+    c, _ = _run(pc, w)
+    d, _ = _run(pc, w, path="plain")
+    assert rel_err(c["states"], d["states"]).max() < 1e-13
+    assert np.abs(c["iters"] - d["iters"]).max() <= 1
+
+
+def test_plain_path_groups_and_status(pc):
+    from paper_2301_03989_amd import pcprop
+    w = W.uneven_batch(600, seed=21)
+    for g in w.groups:
+        g.segments = 1 + g.segments // 16
+        g.tf = g.segments * np.pi / 4.0
+    idx = np.concatenate([np.arange(g.ic_offset, g.ic_offset + min(g.n_ic, 5)) for g in w.groups])
+    r, sub = _run(pc, w, idx, path="plain")
+    o = oracle_run(sub)
+    assert rel_err(r["states"], o["states"]).max() < TOL
+    wn = W.nbody_venus(20)
+    bad = wn.ics.copy()
+    bad[3, 1] = np.nan
+    r, _ = _run(pc, W.Workload("bad", bad, wn.groups, wn.pert), path="plain")
+    assert r["status"] == pcprop.PC_ENONFINITE and (r["iters"][3] == -2).all()
+    r, _ = _run(pc, wn, path="plain", max_iter=1)
+    assert r["status"] == pcprop.PC_ENOTCONV and (r["iters"] == -1).all()
