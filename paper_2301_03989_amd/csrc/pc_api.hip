@@ -31,6 +31,7 @@ struct OperatorCache {
 
 struct pc_ctx {
     int device = 0;
+    int n_cu = 256;
     std::map<int, OperatorCache> ops;
     void* staging = nullptr;        // pinned host memory for descriptor tables
     size_t staging_bytes = 0;
@@ -304,12 +305,10 @@ int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, c
             costs.push_back({d.NP, c, j});
         }
     }
-    // fused: one launch per padded node count; within it the longest jobs first, so the
-    // hardware dispatcher fills the tail with short ones.  plain: group-major, IC order.
+    // fused: one queue over all jobs, longest first (the persistent workgroups then fill
+    // the tail with short jobs).  plain: group-major, IC order.
     if (!plan.plain)
-        std::stable_sort(costs.begin(), costs.end(), [](const Cost& a, const Cost& b) {
-            return a.np != b.np ? a.np > b.np : a.c > b.c;
-        });
+        std::stable_sort(costs.begin(), costs.end(), [](const Cost& a, const Cost& b) { return a.c > b.c; });
     plan.group_job_begin.assign(n_groups + 1, 0);
     for (const Cost& c : costs) plan.group_job_begin[c.j.group + 1] += plan.plain ? 1 : 0;
     for (int gi = 0; gi < n_groups; ++gi) plan.group_job_begin[gi + 1] += plan.group_job_begin[gi];
@@ -323,7 +322,7 @@ int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, c
 
     const int P = model->n_pert;
     size_t off = 0;
-    plan.off_counters = off; off = align_up(off + 2 * sizeof(int32_t));
+    plan.off_counters = off; off = align_up(off + 4 * sizeof(int32_t));   // 2 counters + queue head
     plan.off_groups = off;   off = align_up(off + plan.groups.size() * sizeof(PcGroupDev));
     plan.off_jobs = off;     off = align_up(off + plan.jobs.size() * sizeof(PcJobDev));
     plan.off_bodies = off;   off = align_up(off + std::max(1, P) * sizeof(PcBodyDev));
@@ -393,6 +392,8 @@ int pc_ctx_create(int device, pc_ctx** out)
     pc_ctx* ctx = new (std::nothrow) pc_ctx();
     if (!ctx) return PC_ENOMEM;
     ctx->device = device;
+    if (hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+        ctx->n_cu = 256;
     if (hipSetDevice(device) != hipSuccess ||
         hipMalloc(&ctx->d_bodies, PC_MAX_PERT * sizeof(PcBodyDev)) != hipSuccess ||
         hipHostMalloc(&ctx->pinned_count, 64, hipHostMallocDefault) != hipSuccess) {
@@ -507,10 +508,13 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_
     pp.tol_mode = o.tol_mode;
     pp.init = o.init;
     pp.counters = reinterpret_cast<int32_t*>(ws + plan.off_counters);
+    pp.queue = pp.counters + 2;
     if (ctx->timing) PC_HIP(ctx, hipEventRecord(ctx->ev0, hs));
     if (!plan.plain) {
-        for (const JobClass& jc : plan.classes)
-            PC_HIP(ctx, (hipError_t)pc_launch_fused(pp, plan.pairs, jc.np, jc.begin, jc.end, 0, stream));
+        int occ = 0;
+        PC_HIP(ctx, (hipError_t)pc_fused_occupancy(plan.pairs, &occ));
+        const int grid = std::max(1, ctx->n_cu * std::max(1, occ));
+        PC_HIP(ctx, (hipError_t)pc_launch_fused(pp, plan.pairs, grid, stream));
     } else {
         // one group at a time, kernels per iteration, host loop (the structure of Sec. 5.4)
         for (int gi = 0; gi < n_groups; ++gi) {

@@ -59,6 +59,7 @@ struct PcParams {
     double mu_sun;
     int32_t max_iter, fixed_iters, tol_mode, init;
     int32_t* counters;          // [0] ICs with a not-converged segment, [1] non-finite ICs
+    int32_t* queue;             // next job of the persistent kernel (starts at 0)
 };
 
 struct PcEphemParams {
@@ -73,8 +74,8 @@ struct PcEphemParams {
 
 // Launchers (pc_kernels.hip).  All return a hipError_t as int.
 int pc_launch_ephem(const PcEphemParams& p, void* stream);
-int pc_launch_fused(const PcParams& p, int pairs, int NP, int job_begin, int job_end, int grid,
-                    void* stream);
+int pc_launch_fused(const PcParams& p, int pairs, int grid, void* stream);
+int pc_fused_occupancy(int pairs, int* blocks_per_cu);
 int pc_launch_apply_operator(int NP, const double* kfrag, int N, int64_t n_cols, const double* F,
                              const double* y0, double scale, double* Y, void* stream);
 int pc_launch_eval_force(const double* r, const double* t, int64_t n, const PcBodyDev* bodies,

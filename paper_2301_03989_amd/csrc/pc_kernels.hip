@@ -65,10 +65,23 @@ int pc_launch_ephem(const PcEphemParams& p, void* stream)
 // (in the MFMA result layout), computes the dynamics for the (node, IC) pairs it owns
 // straight from them, and publishes only the force matrix F = (v, a) to LDS, where the
 // product y_new = y0 + w2 K_N F reads it as the B operand.
+// The workgroup's LDS arena, one per job shape (file scope, so that the non-inlined job
+// bodies below address it as LDS).
+__shared__ PcSmem<2048> g_smem2048;
+__shared__ PcSmem<1024> g_smem1024;
+template <int PAIRS>
+static __device__ __forceinline__ PcSmem<PAIRS>& pc_smem();
+template <>
+__device__ __forceinline__ PcSmem<2048>& pc_smem<2048>() { return g_smem2048; }
+template <>
+__device__ __forceinline__ PcSmem<1024>& pc_smem<1024>() { return g_smem1024; }
+
+// Not inlined: one register allocation per node count, so the work-queue kernel that
+// dispatches to all of them does not pay for the largest one everywhere.
 template <int PAIRS, int NP>
-__device__ __forceinline__ void pc_job(const PcParams& p, const PcJobDev& job, const PcGroupDev& g,
-                                       PcSmem<PAIRS>& sm)
+__device__ __attribute__((noinline)) void pc_job(const PcParams& p, const PcJobDev& job, const PcGroupDev& g)
 {
+    PcSmem<PAIRS>& sm = pc_smem<PAIRS>();
     using Sh = PcShape<PAIRS, NP>;
     constexpr int NT = Sh::NT, T = Sh::T, ROW = Sh::ROW, NQ = Sh::NQ;
 
@@ -235,51 +248,54 @@ __device__ __forceinline__ void pc_job(const PcParams& p, const PcJobDev& job, c
     __syncthreads();
 }
 
-// One kernel per (job shape, padded node count): jobs [job_begin, job_end) of the plan all
-// have NP padded nodes.  A workgroup loops over jobs with a grid stride, so a grid smaller
-// than the job count makes the launch persistent.
-template <int PAIRS, int NP>
-__global__ __launch_bounds__(PAIRS / 4) void pc_fused_kernel(const PcParams p, int job_begin, int job_end)
+// Persistent work-queue kernel: every workgroup takes the next job of the plan (jobs of
+// all groups and node counts, longest first) until the queue is empty, so one launch
+// runs an uneven two-level batch (Sec. 3.2) to completion.
+template <int PAIRS>
+__global__ __launch_bounds__(PAIRS / 4) void pc_fused_kernel(const PcParams p)
 {
-    __shared__ PcSmem<PAIRS> sm;
-    for (int jb = job_begin + blockIdx.x; jb < job_end; jb += gridDim.x) {
+    __shared__ int sJob;
+    for (;;) {
+        if (threadIdx.x == 0) sJob = atomicAdd(p.queue, 1);
+        __syncthreads();
+        const int jb = sJob;
+        __syncthreads();
+        if (jb >= p.n_jobs) break;
         const PcJobDev job = p.jobs[jb];
         const PcGroupDev g = p.groups[job.group];
-        pc_job<PAIRS, NP>(p, job, g, sm);
+        switch (g.NP) {
+        case 16: pc_job<PAIRS, 16>(p, job, g); break;
+        case 32: pc_job<PAIRS, 32>(p, job, g); break;
+        case 64: pc_job<PAIRS, 64>(p, job, g); break;
+        case 128: pc_job<PAIRS, 128>(p, job, g); break;
+        case 256:
+            if constexpr (PAIRS >= 2048) pc_job<PAIRS, 256>(p, job, g);
+            break;
+        default: break;
+        }
     }
 }
 
-template <int PAIRS, int NP>
-static void launch_np(const PcParams& p, int jb, int je, int grid, hipStream_t st)
+int pc_fused_occupancy(int pairs, int* blocks_per_cu)
 {
-    hipLaunchKernelGGL((pc_fused_kernel<PAIRS, NP>), dim3(grid), dim3(PAIRS / 4), 0, st, p, jb, je);
+    if (pairs == 2048)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, pc_fused_kernel<2048>, 512, 0);
+    if (pairs == 1024)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, pc_fused_kernel<1024>, 256, 0);
+    return hipErrorInvalidValue;
 }
 
-int pc_launch_fused(const PcParams& p, int pairs, int NP, int job_begin, int job_end, int grid, void* stream)
+int pc_launch_fused(const PcParams& p, int pairs, int grid, void* stream)
 {
-    if (job_end <= job_begin) return hipSuccess;
+    if (p.n_jobs <= 0) return hipSuccess;
     hipStream_t st = (hipStream_t)stream;
-    if (grid <= 0 || grid > job_end - job_begin) grid = job_end - job_begin;
-    if (pairs == 2048) {
-        switch (NP) {
-        case 16: launch_np<2048, 16>(p, job_begin, job_end, grid, st); break;
-        case 32: launch_np<2048, 32>(p, job_begin, job_end, grid, st); break;
-        case 64: launch_np<2048, 64>(p, job_begin, job_end, grid, st); break;
-        case 128: launch_np<2048, 128>(p, job_begin, job_end, grid, st); break;
-        case 256: launch_np<2048, 256>(p, job_begin, job_end, grid, st); break;
-        default: return hipErrorInvalidValue;
-        }
-    } else if (pairs == 1024) {
-        switch (NP) {
-        case 16: launch_np<1024, 16>(p, job_begin, job_end, grid, st); break;
-        case 32: launch_np<1024, 32>(p, job_begin, job_end, grid, st); break;
-        case 64: launch_np<1024, 64>(p, job_begin, job_end, grid, st); break;
-        case 128: launch_np<1024, 128>(p, job_begin, job_end, grid, st); break;
-        default: return hipErrorInvalidValue;
-        }
-    } else {
+    if (grid <= 0 || grid > p.n_jobs) grid = p.n_jobs;
+    if (pairs == 2048)
+        hipLaunchKernelGGL(pc_fused_kernel<2048>, dim3(grid), dim3(512), 0, st, p);
+    else if (pairs == 1024)
+        hipLaunchKernelGGL(pc_fused_kernel<1024>, dim3(grid), dim3(256), 0, st, p);
+    else
         return hipErrorInvalidValue;
-    }
     return hipGetLastError();
 }
 
