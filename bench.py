@@ -70,6 +70,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="nbody-venus-4096")
     ap.add_argument("--tile-pairs", type=int, default=0)
+    ap.add_argument("--graph", action="store_true", help="replay the call as a captured HIP graph")
+    ap.add_argument("--autotune", action="store_true", help="pick the job shape with the autotuner first")
     ap.add_argument("--check-ics", type=int, default=64, help="ICs checked against the oracle")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="wall-time budget of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -114,8 +116,13 @@ def main():
     init = "kepler" if w.init == 0 else "cold"
     states = torch.empty((n_ic, 6), dtype=torch.float64, device="cuda")
 
+    if args.autotune:
+        chosen = ctx.autotune(ics, groups, model)
+        print(f"bench: autotuner chose tile_pairs={chosen}", flush=True)
+
     def step():
-        return ctx.propagate_batched(ics, groups, model, init=init, tile_pairs=args.tile_pairs, out=states)
+        return ctx.propagate_batched(ics, groups, model, init=init, tile_pairs=args.tile_pairs, out=states,
+                                     graph=args.graph)
 
     print(f"bench: {w.name}: {n_ic} ICs, {ic_segments} IC-segments, warmup {args.warmup}", flush=True)
     for _ in range(args.warmup):
@@ -209,7 +216,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n_ic": n_ic, "segments": [g.segments for g in w.groups][:4],
                    "nodes": sorted({g.nodes for g in w.groups}), "tol": w.groups[0].tol,
-                   "perturbers": int(w.pert.shape[0]), "path": "fused",
+                   "perturbers": int(w.pert.shape[0]), "path": "fused", "graph": bool(args.graph),
                    "tile_pairs": args.tile_pairs or "tuned"},
         "accuracy": {"max_rel_err_vs_oracle": max_err, "checked_ics": int(idx.size),
                      "max_iteration_diff": iter_diff, "status": int(status),

@@ -82,7 +82,9 @@ typedef struct {
     int32_t path;         /* PC_PATH_FUSED (default) or PC_PATH_PLAIN */
     int32_t fixed_iters;  /* > 0: run exactly this many iterations per segment (no stopping rule) */
     int32_t tile_pairs;   /* nodes x ICs held by one workgroup: 0 = tuned table, 1024 or 2048 */
-    int32_t reserved;
+    int32_t graph;        /* fused path: 1 = capture the call's device work (table copy, ephemeris,
+                             propagation kernel, status copy) in a HIP graph and replay it while
+                             the call's shapes, options and pointers repeat (default 0) */
 } pc_opts;
 
 /* One outer-level group of the two-level augmentation (Sec. 3.2): ICs
@@ -167,6 +169,22 @@ int pc_eval_kepler(pc_ctx* ctx, const double* y0, const double* dt, int64_t n,
  * milliseconds.  Used by the benchmark for the roofline figure. */
 int pc_set_timing(pc_ctx* ctx, int enable);
 int pc_last_kernel_ms(pc_ctx* ctx, double* ms /* host out */);
+
+/* Autotuner: times the fused path on the caller's batch with each job shape
+ * (tile_pairs 1024 and 2048, where the node counts allow both) for two Picard sweeps of
+ * the first segment, and records the faster one in the context's table for the largest
+ * padded node count of the batch; later calls with tile_pairs = 0 use the table.
+ *   scratch_states  device [n_ic][6], overwritten
+ *   chosen_pairs    host out, the recorded shape
+ * Other arguments as pc_propagate_batched. */
+int pc_autotune(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_group* groups, int32_t n_groups,
+                const pc_model* model, double* scratch_states, void* workspace, size_t ws_bytes,
+                pc_stream_t stream, int32_t* chosen_pairs);
+
+/* Set / read the tuned job shape for a padded node count (16, 32, 64, 128 or 256):
+ * pairs 1024 or 2048, or 0 to clear. */
+int pc_set_tile_pairs(pc_ctx* ctx, int32_t padded_nodes, int32_t pairs);
+int pc_get_tile_pairs(pc_ctx* ctx, int32_t padded_nodes, int32_t* pairs);
 
 /* Message for a status code (static storage). */
 const char* pc_strerror(int code);

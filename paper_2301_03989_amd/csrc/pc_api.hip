@@ -37,6 +37,11 @@ struct pc_ctx {
     size_t staging_bytes = 0;
     PcBodyDev* d_bodies = nullptr;  // device copy of the perturber table (test hooks)
     int32_t* pinned_count = nullptr;   // per-iteration read-back of the plain path
+    int tile_table[5] = {0, 0, 0, 0, 0}; // tuned job shape per padded node count 16..256 (0: default)
+    hipStream_t cap_stream = nullptr;  // stream used to capture HIP graphs
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<char> graph_key;       // call signature of the captured graph
     bool timing = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double last_ms = -1.0;
@@ -226,11 +231,20 @@ struct Plan {
     size_t staged = 0;   // bytes of [counters .. bodies] copied from the staging buffer
 };
 
-int choose_pairs(const pc_group* groups, int n_groups, const pc_opts& o)
+int log2_index(int np)
+{
+    int k = 0;
+    while ((16 << k) < np) ++k;
+    return k;   // 16 -> 0 ... 256 -> 4
+}
+
+int choose_pairs(const pc_ctx* ctx, const pc_group* groups, int n_groups, const pc_opts& o)
 {
     if (o.tile_pairs == 1024 || o.tile_pairs == 2048) return o.tile_pairs;
-    (void)groups;
-    (void)n_groups;
+    int np_max = 16;
+    for (int i = 0; i < n_groups; ++i) np_max = std::max(np_max, padded_nodes(groups[i].nodes));
+    const int tuned = ctx->tile_table[log2_index(np_max)];
+    if (tuned == 1024 && np_max * 8 <= 1024) return 1024;
     return 2048;
 }
 
@@ -240,7 +254,7 @@ int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, c
     if (!groups || n_groups < 1) return set_error(ctx, PC_EINVAL, "need at least one group");
     if (o.tile_pairs != 0 && o.tile_pairs != 1024 && o.tile_pairs != 2048)
         return set_error(ctx, PC_EINVAL, "tile_pairs must be 0, 1024 or 2048");
-    plan.pairs = choose_pairs(groups, n_groups, o);
+    plan.pairs = choose_pairs(ctx, groups, n_groups, o);
     plan.plain = (o.path == PC_PATH_PLAIN);
     if (plan.plain) plan.pairs = 2048;
     std::vector<std::pair<int64_t, int64_t>> spans;
@@ -363,7 +377,7 @@ void pc_default_opts(pc_opts* o)
     o->path = PC_PATH_FUSED;
     o->fixed_iters = 0;
     o->tile_pairs = 0;
-    o->reserved = 0;
+    o->graph = 0;
 }
 
 int pc_version(void) { return PC_VERSION; }
@@ -396,7 +410,8 @@ int pc_ctx_create(int device, pc_ctx** out)
         ctx->n_cu = 256;
     if (hipSetDevice(device) != hipSuccess ||
         hipMalloc(&ctx->d_bodies, PC_MAX_PERT * sizeof(PcBodyDev)) != hipSuccess ||
-        hipHostMalloc(&ctx->pinned_count, 64, hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc(&ctx->pinned_count, 64, hipHostMallocDefault) != hipSuccess ||
+        hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         delete ctx;
         return PC_EHIP;
     }
@@ -418,6 +433,9 @@ void pc_ctx_destroy(pc_ctx* ctx)
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     if (ctx->d_bodies) (void)hipFree(ctx->d_bodies);
     if (ctx->pinned_count) (void)hipHostFree(ctx->pinned_count);
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     delete ctx;
 }
 
@@ -477,7 +495,6 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_
     prepare_bodies(model, reinterpret_cast<PcBodyDev*>(st + plan.off_bodies));
     char* ws = static_cast<char*>(workspace);
     hipStream_t hs = (hipStream_t)stream;
-    PC_HIP(ctx, hipMemcpyAsync(ws, st, plan.staged, hipMemcpyHostToDevice, hs));
 
     PcEphemParams ep{};
     ep.groups = reinterpret_cast<const PcGroupDev*>(ws + plan.off_groups);
@@ -487,7 +504,6 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_
     ep.n_pert = model->n_pert;
     ep.epoch = model->epoch;
     ep.recs = reinterpret_cast<double*>(ws + plan.off_recs);
-    PC_HIP(ctx, (hipError_t)pc_launch_ephem(ep, stream));
 
     PcParams pp{};
     pp.groups = ep.groups;
@@ -509,13 +525,29 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_
     pp.init = o.init;
     pp.counters = reinterpret_cast<int32_t*>(ws + plan.off_counters);
     pp.queue = pp.counters + 2;
-    if (ctx->timing) PC_HIP(ctx, hipEventRecord(ctx->ev0, hs));
+    int32_t* hc = reinterpret_cast<int32_t*>(st);   // staging is free again once the copy has run
+
+    int grid = 1;
     if (!plan.plain) {
         int occ = 0;
         PC_HIP(ctx, (hipError_t)pc_fused_occupancy(plan.pairs, &occ));
-        const int grid = std::max(1, ctx->n_cu * std::max(1, occ));
-        PC_HIP(ctx, (hipError_t)pc_launch_fused(pp, plan.pairs, grid, stream));
-    } else {
+        grid = std::max(1, ctx->n_cu * std::max(1, occ));
+    }
+    // the device work of a fused call: tables in, ephemeris, persistent kernel, status out
+    auto enqueue_fused = [&](hipStream_t sq, bool events) -> hipError_t {
+        hipError_t e = hipMemcpyAsync(ws, st, plan.staged, hipMemcpyHostToDevice, sq);
+        if (e == hipSuccess) e = (hipError_t)pc_launch_ephem(ep, sq);
+        if (e == hipSuccess && events) e = hipEventRecord(ctx->ev0, sq);
+        if (e == hipSuccess) e = (hipError_t)pc_launch_fused(pp, plan.pairs, grid, sq);
+        if (e == hipSuccess && events) e = hipEventRecord(ctx->ev1, sq);
+        if (e == hipSuccess) e = hipMemcpyAsync(hc, pp.counters, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, sq);
+        return e;
+    };
+
+    if (plan.plain) {
+        PC_HIP(ctx, hipMemcpyAsync(ws, st, plan.staged, hipMemcpyHostToDevice, hs));
+        PC_HIP(ctx, (hipError_t)pc_launch_ephem(ep, hs));
+        if (ctx->timing) PC_HIP(ctx, hipEventRecord(ctx->ev0, hs));
         // one group at a time, kernels per iteration, host loop (the structure of Sec. 5.4)
         for (int gi = 0; gi < n_groups; ++gi) {
             PcPlainArgs a{};
@@ -531,11 +563,54 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_
             a.t2 = plan.groups[gi].tol * plan.groups[gi].tol;
             PC_HIP(ctx, (hipError_t)pc_run_plain(a, ws + plan.off_plain, ctx->pinned_count, stream));
         }
+        if (ctx->timing) PC_HIP(ctx, hipEventRecord(ctx->ev1, hs));
+        PC_HIP(ctx, hipMemcpyAsync(hc, pp.counters, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, hs));
+    } else if (o.graph) {
+        // signature of the call: a captured graph is replayed only for the same one
+        std::vector<char> key;
+        auto put = [&key](const void* q, size_t nb) {
+            key.insert(key.end(), static_cast<const char*>(q), static_cast<const char*>(q) + nb);
+        };
+        const void* ptrs[7] = {ics, states_out, iters_out, bounds_out, nodes_out, workspace, stream};
+        put(ptrs, sizeof(ptrs));
+        put(&n_ic, sizeof(n_ic));
+        put(&n_groups, sizeof(n_groups));
+        put(groups, sizeof(pc_group) * n_groups);
+        put(&o, sizeof(o));
+        put(&model->mu_sun, sizeof(double));
+        put(&model->epoch, sizeof(double));
+        put(&model->n_pert, sizeof(int32_t));
+        if (model->n_pert > 0) put(model->pert, sizeof(double) * 7 * model->n_pert);
+        put(&iters_stride, sizeof(iters_stride));
+        put(&nodes_stride, sizeof(nodes_stride));
+        put(&ws_bytes, sizeof(ws_bytes));
+        put(&plan.pairs, sizeof(plan.pairs));
+        if (!ctx->graph_exec || key != ctx->graph_key) {
+            if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+            if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+            ctx->graph_exec = nullptr;
+            ctx->graph = nullptr;
+            ctx->graph_key.clear();
+            PC_HIP(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+            const hipError_t e = enqueue_fused(ctx->cap_stream, false);
+            hipGraph_t gr = nullptr;
+            const hipError_t e2 = hipStreamEndCapture(ctx->cap_stream, &gr);
+            if (e != hipSuccess || e2 != hipSuccess) {
+                if (gr) (void)hipGraphDestroy(gr);
+                return set_error(ctx, PC_EHIP, "graph capture failed: %s",
+                                 hipGetErrorString(e != hipSuccess ? e : e2));
+            }
+            ctx->graph = gr;
+            PC_HIP(ctx, hipGraphInstantiate(&ctx->graph_exec, ctx->graph, nullptr, nullptr, 0));
+            ctx->graph_key = key;
+        }
+        // the whole graph is timed in graph mode (copies and ephemeris included)
+        if (ctx->timing) PC_HIP(ctx, hipEventRecord(ctx->ev0, hs));
+        PC_HIP(ctx, hipGraphLaunch(ctx->graph_exec, hs));
+        if (ctx->timing) PC_HIP(ctx, hipEventRecord(ctx->ev1, hs));
+    } else {
+        PC_HIP(ctx, enqueue_fused(hs, ctx->timing));
     }
-    if (ctx->timing) PC_HIP(ctx, hipEventRecord(ctx->ev1, hs));
-
-    int32_t* hc = reinterpret_cast<int32_t*>(st);   // staging is free again once the copy has run
-    PC_HIP(ctx, hipMemcpyAsync(hc, pp.counters, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, hs));
     PC_HIP(ctx, hipStreamSynchronize(hs));
     if (ctx->timing) {
         float ms = 0.0f;
@@ -582,6 +657,72 @@ int pc_last_kernel_ms(pc_ctx* ctx, double* ms)
     if (!ctx || !ms) return PC_EINVAL;
     *ms = ctx->last_ms;
     return ctx->last_ms >= 0.0 ? PC_OK : set_error(ctx, PC_EINVAL, "no timed call yet");
+}
+
+int pc_set_tile_pairs(pc_ctx* ctx, int32_t padded_nodes, int32_t pairs)
+{
+    if (!ctx) return PC_EINVAL;
+    if (padded_nodes < 16 || padded_nodes > 256 || (padded_nodes & (padded_nodes - 1)))
+        return set_error(ctx, PC_EINVAL, "padded_nodes must be 16, 32, 64, 128 or 256");
+    if (pairs != 0 && pairs != 1024 && pairs != 2048) return set_error(ctx, PC_EINVAL, "pairs must be 0, 1024 or 2048");
+    if (pairs == 1024 && padded_nodes * 8 > 1024) return set_error(ctx, PC_EINVAL, "1024 pairs need <= 128 nodes");
+    ctx->tile_table[log2_index(padded_nodes)] = pairs;
+    return PC_OK;
+}
+
+int pc_get_tile_pairs(pc_ctx* ctx, int32_t padded_nodes, int32_t* pairs)
+{
+    if (!ctx || !pairs) return PC_EINVAL;
+    if (padded_nodes < 16 || padded_nodes > 256 || (padded_nodes & (padded_nodes - 1)))
+        return set_error(ctx, PC_EINVAL, "padded_nodes must be 16, 32, 64, 128 or 256");
+    *pairs = ctx->tile_table[log2_index(padded_nodes)];
+    return PC_OK;
+}
+
+int pc_autotune(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_group* groups, int32_t n_groups,
+                const pc_model* model, double* scratch_states, void* workspace, size_t ws_bytes,
+                pc_stream_t stream, int32_t* chosen_pairs)
+{
+    if (!ctx || !groups || n_groups < 1 || !scratch_states || !chosen_pairs) return PC_EINVAL;
+    int np_max = 16;
+    std::vector<pc_group> probe(groups, groups + n_groups);
+    for (auto& g : probe) {
+        np_max = std::max(np_max, padded_nodes(g.nodes));
+        if (g.segments < 1) return set_error(ctx, PC_EINVAL, "segments < 1");
+        g.tf = g.t0 + (g.tf - g.t0) / g.segments;   // first segment only
+        g.segments = 1;
+    }
+    std::vector<int> cands = {2048};
+    if (np_max * 8 <= 1024) cands.push_back(1024);
+    const bool was_timing = ctx->timing;
+    int rc = pc_set_timing(ctx, 1);
+    if (rc != PC_OK) return rc;
+    int best = 2048;
+    double best_ms = 1e300;
+    for (int c : cands) {
+        pc_opts o;
+        pc_default_opts(&o);
+        o.tile_pairs = c;
+        o.fixed_iters = 2;
+        double ms = 0.0;
+        for (int rep = 0; rep < 2; ++rep) {   // the second run is timed
+            rc = pc_propagate_batched(ctx, ics, n_ic, probe.data(), n_groups, model, &o, scratch_states,
+                                      nullptr, 0, nullptr, nullptr, 0, workspace, ws_bytes, stream);
+            if (rc != PC_OK && rc != PC_ENOTCONV && rc != PC_ENONFINITE) {
+                ctx->timing = was_timing;
+                return rc;
+            }
+            ms = ctx->last_ms;
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
+    ctx->timing = was_timing;
+    ctx->tile_table[log2_index(np_max)] = best;
+    *chosen_pairs = best;
+    return PC_OK;
 }
 
 int pc_get_operator(pc_ctx* ctx, int32_t nodes, double* K_host)

@@ -45,7 +45,7 @@ class _Opts(ctypes.Structure):
     _fields_ = [("init", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("tol_mode", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("path", ctypes.c_int32), ("fixed_iters", ctypes.c_int32),
-                ("tile_pairs", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("tile_pairs", ctypes.c_int32), ("graph", ctypes.c_int32)]
 
 
 class _Group(ctypes.Structure):
@@ -59,8 +59,8 @@ _lib = None
 
 EXPORTS = ("pc_default_opts", "pc_ctx_create", "pc_ctx_destroy", "pc_workspace_bytes",
            "pc_propagate", "pc_propagate_batched", "pc_get_operator", "pc_apply_operator",
-           "pc_eval_force", "pc_eval_kepler", "pc_set_timing", "pc_last_kernel_ms", "pc_strerror",
-           "pc_last_error", "pc_version")
+           "pc_eval_force", "pc_eval_kepler", "pc_set_timing", "pc_last_kernel_ms", "pc_autotune",
+           "pc_set_tile_pairs", "pc_get_tile_pairs", "pc_strerror", "pc_last_error", "pc_version")
 
 
 def load_library(path: str = LIB_PATH):
@@ -90,6 +90,10 @@ def load_library(path: str = LIB_PATH):
                                       _vp, _vp]
     lib.pc_eval_force.argtypes = [_vp, _vp, _vp, ctypes.c_int64, P(_Model), _vp, _vp]
     lib.pc_eval_kepler.argtypes = [_vp, _vp, _vp, ctypes.c_int64, _vp, _vp, _vp]
+    lib.pc_autotune.argtypes = [_vp, _vp, ctypes.c_int64, P(_Group), ctypes.c_int32, P(_Model), _vp, _vp,
+                                ctypes.c_size_t, _vp, P(ctypes.c_int32)]
+    lib.pc_set_tile_pairs.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32]
+    lib.pc_get_tile_pairs.argtypes = [_vp, ctypes.c_int32, P(ctypes.c_int32)]
     lib.pc_set_timing.argtypes = [_vp, ctypes.c_int]
     lib.pc_last_kernel_ms.argtypes = [_vp, ctypes.POINTER(ctypes.c_double)]
     lib.pc_strerror.argtypes = [ctypes.c_int]
@@ -177,11 +181,11 @@ class Context:
 
     @staticmethod
     def opts(init="kepler", max_iter=64, tol_mode="rel", path="fused", fixed_iters=0,
-             tile_pairs=0, precision="fp64"):
+             tile_pairs=0, precision="fp64", graph=False):
         o = _Opts()
         o.init, o.max_iter, o.tol_mode = INIT[init], int(max_iter), TOL_MODE[tol_mode]
         o.precision, o.path, o.fixed_iters = PRECISION[precision], PATH[path], int(fixed_iters)
-        o.tile_pairs, o.reserved = int(tile_pairs), 0
+        o.tile_pairs, o.graph = int(tile_pairs), int(bool(graph))
         return o
 
     def workspace_bytes(self, groups, model, **opts):
@@ -252,6 +256,41 @@ class Context:
         if rc != PC_OK:
             self._raise(rc)
         return ms.value
+
+    def autotune(self, ics, groups, model=None):
+        """Pick the job shape for this batch (pc_autotune); returns the chosen tile_pairs."""
+        model = model or Model()
+        _check_tensor(ics, "ics")
+        garr = (_Group * len(groups))(*[_Group(g.ic_offset, g.n_ic, g.t0, g.tf, g.nodes, g.segments, g.tol)
+                                       for g in groups])
+        mc, oc = model._c(), self.opts()
+        nb = ctypes.c_size_t()
+        rc = self.lib.pc_workspace_bytes(self.handle, garr, len(groups), ctypes.byref(mc), ctypes.byref(oc),
+                                         ctypes.byref(nb))
+        if rc != PC_OK:
+            self._raise(rc)
+        ws = self.workspace(nb.value)
+        scratch = torch.empty((ics.shape[0], 6), dtype=torch.float64, device=ics.device)
+        chosen = ctypes.c_int32()
+        rc = self.lib.pc_autotune(self.handle, ctypes.c_void_p(ics.data_ptr()), ics.shape[0], garr, len(groups),
+                                  ctypes.byref(mc), ctypes.c_void_p(scratch.data_ptr()),
+                                  ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(ics.device),
+                                  ctypes.byref(chosen))
+        if rc != PC_OK:
+            self._raise(rc)
+        return chosen.value
+
+    def tile_pairs(self, padded_nodes):
+        v = ctypes.c_int32()
+        rc = self.lib.pc_get_tile_pairs(self.handle, int(padded_nodes), ctypes.byref(v))
+        if rc != PC_OK:
+            self._raise(rc)
+        return v.value
+
+    def set_tile_pairs(self, padded_nodes, pairs):
+        rc = self.lib.pc_set_tile_pairs(self.handle, int(padded_nodes), int(pairs))
+        if rc != PC_OK:
+            self._raise(rc)
 
     def get_operator(self, nodes):
         K = np.zeros((nodes, nodes))

@@ -264,3 +264,53 @@ def test_plain_path_groups_and_status(pc):
     assert r["status"] == pcprop.PC_ENONFINITE and (r["iters"][3] == -2).all()
     r, _ = _run(pc, wn, path="plain", max_iter=1)
     assert r["status"] == pcprop.PC_ENOTCONV and (r["iters"] == -1).all()
+
+
+# ---------------------------------------------------------------------------
+# graph capture and autotuner
+# ---------------------------------------------------------------------------
+def test_graph_replays_match_eager(pc):
+    from paper_2301_03989_amd import pcprop
+    w = W.nbody_venus(300)
+    g = w.groups[0]
+    ics = torch.tensor(w.ics, device="cuda")
+    groups = [pcprop.Group(0, w.n_ic, g.t0, g.tf, g.nodes, g.segments, g.tol)]
+    model = pcprop.Model(1.0, w.pert, 0.0)
+    ref = pc.propagate_batched(ics, groups, model)
+    ref_s, ref_i = ref["states"].clone(), ref["iters"].clone()
+    out = torch.empty_like(ref_s)
+    for rep in range(4):
+        r = pc.propagate_batched(ics, groups, model, graph=True, out=out)
+        assert r["status"] == 0
+        assert torch.equal(r["states"], ref_s), rep
+        # eager work between replays
+        x = torch.randn(1 << 20, device="cuda", dtype=torch.float64)
+        assert torch.isfinite(x.sum())
+        torch.cuda.synchronize()
+    # same pointers, new contents: the replay reads the current inputs
+    ics2 = torch.tensor(W.nbody_venus(300, seed=77).ics, device="cuda")
+    ics.copy_(ics2)
+    r = pc.propagate_batched(ics, groups, model, graph=True, out=out)
+    ref2 = pc.propagate_batched(ics, groups, model)
+    assert torch.equal(r["states"], ref2["states"])
+    o = oracle_run(W.Workload("seed77", ics2.cpu().numpy(), w.groups, w.pert), np.arange(0, 300, 50))
+    assert rel_err(r["states"].cpu().numpy()[::50], o["states"]).max() < TOL
+
+
+def test_autotune_records_a_shape(pc):
+    from paper_2301_03989_amd import pcprop
+    w = W.nbody_venus(512)
+    g = w.groups[0]
+    ics = torch.tensor(w.ics, device="cuda")
+    groups = [pcprop.Group(0, w.n_ic, g.t0, g.tf, g.nodes, g.segments, g.tol)]
+    model = pcprop.Model(1.0, w.pert, 0.0)
+    chosen = pc.autotune(ics, groups, model)
+    assert chosen in (1024, 2048)
+    assert pc.tile_pairs(128) == chosen
+    a = pc.propagate_batched(ics, groups, model)
+    b = pc.propagate_batched(ics, groups, model, tile_pairs=2048)
+    assert rel_err(a["states"].cpu().numpy(), b["states"].cpu().numpy()).max() < 1e-13
+    pc.set_tile_pairs(128, 0)
+    assert pc.tile_pairs(128) == 0
+    with pytest.raises(pcprop.PcError):
+        pc.set_tile_pairs(256, 1024)
