@@ -71,6 +71,9 @@ def main():
     ap.add_argument("--workload", default="nbody-venus-4096")
     ap.add_argument("--tile-pairs", type=int, default=0)
     ap.add_argument("--graph", action="store_true", help="replay the call as a captured HIP graph")
+    ap.add_argument("--precision", default=None, choices=["fp64", "fp32-fp64"],
+                    help="sweep arithmetic (default: the workload's)")
+    ap.add_argument("--switch-tol", type=float, default=0.0, help="FP32 -> FP64 switch (0: library default)")
     ap.add_argument("--autotune", action="store_true", help="pick the job shape with the autotuner first")
     ap.add_argument("--check-ics", type=int, default=64, help="ICs checked against the oracle")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="wall-time budget of the oracle sample")
@@ -114,6 +117,7 @@ def main():
     groups = [pcprop.Group(g.ic_offset, g.n_ic, g.t0, g.tf, g.nodes, g.segments, g.tol) for g in w.groups]
     model = pcprop.Model(w.mu_sun, w.pert, w.epoch)
     init = "kepler" if w.init == 0 else "cold"
+    precision = args.precision or ("fp32-fp64" if w.precision == 1 else "fp64")
     states = torch.empty((n_ic, 6), dtype=torch.float64, device="cuda")
 
     if args.autotune:
@@ -122,7 +126,7 @@ def main():
 
     def step():
         return ctx.propagate_batched(ics, groups, model, init=init, tile_pairs=args.tile_pairs, out=states,
-                                     graph=args.graph)
+                                     graph=args.graph, precision=precision, switch_tol=args.switch_tol)
 
     print(f"bench: {w.name}: {n_ic} ICs, {ic_segments} IC-segments, warmup {args.warmup}", flush=True)
     for _ in range(args.warmup):
@@ -143,8 +147,31 @@ def main():
     iters = r["iters"].cpu().numpy()
     gpu_states = r["states"].cpu().numpy()
 
+    fp64_ref = None
+    if precision != "fp64":
+        # the same propagation with FP64 sweeps only, for the mixed-precision speedup
+        f64_states = torch.empty_like(states)
+        ctx.propagate_batched(ics, groups, model, init=init, out=f64_states)
+        torch.cuda.synchronize()
+        q0 = torch.cuda.Event(enable_timing=True)
+        q1 = torch.cuda.Event(enable_timing=True)
+        nq = max(1, min(args.steps, 5))
+        q0.record()
+        for _ in range(nq):
+            rq = ctx.propagate_batched(ics, groups, model, init=init, out=f64_states)
+        q1.record()
+        torch.cuda.synchronize()
+        f64_ms = q0.elapsed_time(q1) / nq
+        it64 = rq["iters"].cpu().numpy()
+        fp64_ref = {"precision": "fp64", "ms_per_step": round(f64_ms, 4), "steps": nq,
+                    "speedup_mixed_vs_fp64": round(f64_ms / ms_per_step, 3),
+                    "mean_iterations_per_segment_fp64": round(float(it64[it64 > 0].mean()), 3),
+                    "max_rel_diff_vs_fp64": float(rel_err(gpu_states, rq["states"].cpu().numpy()).max())}
+        print(f"bench: all-FP64 {f64_ms:.3f} ms/step, mixed-precision speedup {f64_ms / ms_per_step:.2f}x",
+              flush=True)
+
     plain = None
-    if args.plain_steps > 0:
+    if args.plain_steps > 0 and precision == "fp64":
         # the same propagation with per-iteration kernels and a host loop (plain GPU path)
         plain_states = torch.empty_like(states)
         ctx.propagate_batched(ics, groups, model, init=init, path="plain", out=plain_states)
@@ -166,7 +193,8 @@ def main():
     # accuracy gate against the FP64 oracle on an evenly spaced sample
     idx = np.unique(np.linspace(0, n_ic - 1, min(args.check_ics, n_ic)).astype(np.int64))
     ref, ref_iters, _ = oracle_states(w, idx)
-    max_err = float(rel_err(gpu_states[idx], ref).max())
+    errs = rel_err(gpu_states[idx], ref)
+    max_err = float(errs.max())
     iter_diff = int(np.abs(iters[idx] - ref_iters).max())
     valid = (max_err <= 1e-10) and status == 0
     print(f"bench: max rel err vs oracle on {idx.size} ICs: {max_err:.3e} (iteration diff {iter_diff})",
@@ -212,18 +240,20 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": w.name, "n_ic": n_ic, "segments": [g.segments for g in w.groups][:4],
                    "nodes": sorted({g.nodes for g in w.groups}), "tol": w.groups[0].tol,
-                   "perturbers": int(w.pert.shape[0]), "path": "fused", "graph": bool(args.graph),
+                   "perturbers": int(w.pert.shape[0]), "path": "fused", "graph": bool(args.graph), "precision": precision,
                    "tile_pairs": args.tile_pairs or "tuned"},
-        "accuracy": {"max_rel_err_vs_oracle": max_err, "checked_ics": int(idx.size),
+        "accuracy": {"max_rel_err_vs_oracle": max_err, "p99_rel_err_vs_oracle": float(np.percentile(errs, 99)),
+                     "median_rel_err_vs_oracle": float(np.median(errs)), "checked_ics": int(idx.size),
                      "max_iteration_diff": iter_diff, "status": int(status),
                      "mean_iterations_per_segment": round(float(iters[iters > 0].mean()), 3)},
         "segment_iterations_per_s": round(float(np.where(iters > 0, iters, 0).sum()) /
                                           (ms_per_step * 1e-3), 1),
         "vs_plain": plain,
+        "vs_fp64": fp64_ref,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

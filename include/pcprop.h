@@ -71,7 +71,12 @@ typedef struct {
 
 enum { PC_INIT_KEPLER = 0, PC_INIT_COLD = 1 };   /* initial guess, Sec. 2.1 (warm / cold start) */
 enum { PC_TOL_REL = 0, PC_TOL_ABS = 1 };         /* relative or absolute stopping rule, Sec. 2.2 */
-enum { PC_FP64 = 0 };                            /* arithmetic of the sweeps */
+/* Arithmetic of the sweeps.  PC_FP32_THEN_FP64 (fused path): a job starts every
+ * segment with sweeps whose force and fit/integrate/evaluate product are FP32, and
+ * moves to FP64 sweeps once the relative change of every iterating IC is below
+ * switch_tol (or after max_fp32 FP32 sweeps); y0 + w2 dY, the stopping test and all stored states stay
+ * FP64, so the converged result is the FP64 fixed point.  iters_out counts all sweeps. */
+enum { PC_FP64 = 0, PC_FP32_THEN_FP64 = 1 };
 enum { PC_PATH_FUSED = 0, PC_PATH_PLAIN = 1 };   /* one persistent launch / per-iteration kernels */
 
 typedef struct {
@@ -85,6 +90,10 @@ typedef struct {
     int32_t graph;        /* fused path: 1 = capture the call's device work (table copy, ephemeris,
                              propagation kernel, status copy) in a HIP graph and replay it while
                              the call's shapes, options and pointers repeat (default 0) */
+    double switch_tol;    /* PC_FP32_THEN_FP64: relative change below which a job leaves FP32
+                             (0 = default 1e-4) */
+    int32_t max_fp32;     /* PC_FP32_THEN_FP64: cap on FP32 sweeps per segment (0 = default 24) */
+    int32_t pad_;
 } pc_opts;
 
 /* One outer-level group of the two-level augmentation (Sec. 3.2): ICs

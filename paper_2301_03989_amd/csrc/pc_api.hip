@@ -23,6 +23,7 @@ namespace {
 struct OperatorCache {
     int N = 0, NP = 0;
     double* kfrag = nullptr;   // device, [NP/16][NP/4][64]
+    float* kfrag32 = nullptr;  // device, FP32 fragments with rows permuted per strip
     double* tau = nullptr;     // device, [NP]
     std::vector<double> K;     // host copy, [N][N]
 };
@@ -141,12 +142,26 @@ int get_operator(pc_ctx* ctx, int N, const OperatorCache** out)
                 frag[((size_t)strip * NQ + q) * 64 + lane] =
                     (row < N && col < N) ? oc.K[(size_t)row * N + col] : 0.0;
             }
+    // FP32 fragments: the f32 16x16x4 MFMA returns row 4(l/16) + r in element r, the f64
+    // one row l/16 + 4r.  Feeding A row i from strip row perm(i) = (i/4) + 4 (i%4) puts the
+    // same node in the same lane and element for both precisions.
+    std::vector<float> frag32((size_t)NP * NP, 0.0f);
+    for (int strip = 0; strip < NP / 16; ++strip)
+        for (int q = 0; q < NQ; ++q)
+            for (int lane = 0; lane < 64; ++lane) {
+                const int i = lane & 15;
+                const int row = 16 * strip + (i / 4) + 4 * (i % 4), col = 4 * q + (lane >> 4);
+                frag32[((size_t)strip * NQ + q) * 64 + lane] =
+                    (row < N && col < N) ? (float)oc.K[(size_t)row * N + col] : 0.0f;
+            }
     std::vector<double> tau(NP, 0.0);
     const long double pi = 3.141592653589793238462643383279502884L;
     for (int j = 0; j < N; ++j) tau[j] = (double)(-cosl(pi * (long double)j / (long double)(N - 1)));
     PC_HIP(ctx, hipSetDevice(ctx->device));
     PC_HIP(ctx, hipMalloc(&oc.kfrag, frag.size() * sizeof(double)));
     PC_HIP(ctx, hipMalloc(&oc.tau, tau.size() * sizeof(double)));
+    PC_HIP(ctx, hipMalloc(&oc.kfrag32, frag32.size() * sizeof(float)));
+    PC_HIP(ctx, hipMemcpy(oc.kfrag32, frag32.data(), frag32.size() * sizeof(float), hipMemcpyHostToDevice));
     PC_HIP(ctx, hipMemcpy(oc.kfrag, frag.data(), frag.size() * sizeof(double), hipMemcpyHostToDevice));
     PC_HIP(ctx, hipMemcpy(oc.tau, tau.data(), tau.size() * sizeof(double), hipMemcpyHostToDevice));
     auto res = ctx->ops.emplace(N, std::move(oc));
@@ -305,6 +320,7 @@ int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, c
             int rc = get_operator(ctx, G.nodes, &oc);
             if (rc != PC_OK) return rc;
             d.kfrag = oc->kfrag;
+            d.kfrag32 = oc->kfrag32;
             d.tau = oc->tau;
         }
         plan.n_recs += (int64_t)G.segments * G.nodes;
@@ -378,6 +394,9 @@ void pc_default_opts(pc_opts* o)
     o->fixed_iters = 0;
     o->tile_pairs = 0;
     o->graph = 0;
+    o->switch_tol = 0.0;
+    o->max_fp32 = 0;
+    o->pad_ = 0;
 }
 
 int pc_version(void) { return PC_VERSION; }
@@ -427,6 +446,7 @@ void pc_ctx_destroy(pc_ctx* ctx)
     for (auto& kv : ctx->ops) {
         (void)hipFree(kv.second.kfrag);
         (void)hipFree(kv.second.tau);
+        (void)hipFree(kv.second.kfrag32);
     }
     if (ctx->staging) (void)hipHostFree(ctx->staging);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
@@ -470,9 +490,14 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_
     const pc_opts o = opts ? *opts : defaults();
     if (o.init != PC_INIT_KEPLER && o.init != PC_INIT_COLD) return set_error(ctx, PC_EINVAL, "bad init");
     if (o.tol_mode != PC_TOL_REL && o.tol_mode != PC_TOL_ABS) return set_error(ctx, PC_EINVAL, "bad tol_mode");
-    if (o.precision != PC_FP64) return set_error(ctx, PC_EINVAL, "unsupported precision");
+    if (o.precision != PC_FP64 && o.precision != PC_FP32_THEN_FP64)
+        return set_error(ctx, PC_EINVAL, "unsupported precision");
+    if (o.precision == PC_FP32_THEN_FP64 && o.path != PC_PATH_FUSED)
+        return set_error(ctx, PC_EINVAL, "the FP32 -> FP64 schedule runs on the fused path");
     if (o.path != PC_PATH_FUSED && o.path != PC_PATH_PLAIN) return set_error(ctx, PC_EINVAL, "bad path");
     if (o.max_iter < 1 || o.max_iter > 100000) return set_error(ctx, PC_EINVAL, "max_iter out of range");
+    if (!(o.switch_tol >= 0.0) || !std::isfinite(o.switch_tol) || o.max_fp32 < 0)
+        return set_error(ctx, PC_EINVAL, "bad precision-schedule options");
     if (o.fixed_iters < 0 || o.fixed_iters > 100000) return set_error(ctx, PC_EINVAL, "fixed_iters out of range");
     PC_HIP(ctx, hipSetDevice(ctx->device));
     Plan plan;
@@ -523,6 +548,12 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_
     pp.fixed_iters = o.fixed_iters;
     pp.tol_mode = o.tol_mode;
     pp.init = o.init;
+    pp.precision = o.precision;
+    pp.max_fp32 = o.max_fp32 > 0 ? o.max_fp32 : 24;
+    {
+        const double sw = o.switch_tol > 0.0 ? o.switch_tol : 1e-4;
+        pp.switch2 = sw * sw;
+    }
     pp.counters = reinterpret_cast<int32_t*>(ws + plan.off_counters);
     pp.queue = pp.counters + 2;
     int32_t* hc = reinterpret_cast<int32_t*>(st);   // staging is free again once the copy has run

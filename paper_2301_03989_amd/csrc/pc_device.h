@@ -5,6 +5,7 @@
 #include "pc_internal.h"
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 #define PC_PI 3.14159265358979323846
 
@@ -13,6 +14,12 @@ static __device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c)
     // D = A(16x4) B(4x16) + C.  Operand lanes: A[l%16][l/16], B[l/16][l%16];
     // result lanes on gfx950: D[l/16 + 4r][l%16] in element r.
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+static __device__ __forceinline__ f32x4 mfma16f(float a, float b, f32x4 c)
+{
+    // f32 16x16x4: same operand lanes as the f64 form; result D[4(l/16) + r][l%16] in element r
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
 // max that propagates NaN from either argument
@@ -129,6 +136,7 @@ static __device__ __forceinline__ void pc_accel(double x, double y, double z, co
 // Shared pieces of the propagation kernels
 // ---------------------------------------------------------------------------
 typedef const __attribute__((address_space(1))) double* gconst_dp;
+typedef const __attribute__((address_space(1))) float* gconst_fp;
 
 // Shared-memory arena of one workgroup (sized for the largest job shape).
 template <int PAIRS>
@@ -138,7 +146,8 @@ struct PcSmem {
     double Rec[REC];              // [node][body 0..P][3]: perturber positions, then the indirect term
     double Y0[6 * (PAIRS / 16)];  // [comp][IC] initial state of the current segment
     double Mu[PC_MAX_PERT_DEV];   // perturber parameters
-    int Flag[(PAIRS / 256) * 16]; // per wave, per IC: bit 0 not converged, bit 1 non-finite
+    int Flag[(PAIRS / 256) * 16]; // per wave, per IC: bit 0 not converged, bit 1 non-finite, bit 2 large change
+    int Keep[PAIRS / 256];        // per wave: an iterating IC still changes by more than the FP32 switch
     int Active[PAIRS / 16];
     int Dead[PAIRS / 16];
 };
@@ -178,6 +187,47 @@ static __device__ __forceinline__ void pc_force_lds(const double (&x)[R], const 
         ax[r] -= q[0];
         ay[r] -= q[1];
         az[r] -= q[2];
+    }
+}
+
+// FP32 variant for the early sweeps of the precision schedule: the differences to the
+// perturbers are formed in FP64, everything after them in FP32.
+template <int R>
+static __device__ __forceinline__ void pc_force_lds32(const double (&x)[R], const double (&y)[R],
+                                                      const double (&z)[R], const int (&jr)[R], int P,
+                                                      double mu_sun, const double* srec, const double* smu,
+                                                      double (&ax)[R], double (&ay)[R], double (&az)[R])
+{
+    const int stride = 3 * (P + 1);
+    float fx[R], fy[R], fz[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const float xf = (float)x[r], yf = (float)y[r], zf = (float)z[r];
+        const float ir = rsqrtf(xf * xf + yf * yf + zf * zf);
+        const float s = (float)mu_sun * (ir * ir * ir);
+        fx[r] = -s * xf;
+        fy[r] = -s * yf;
+        fz[r] = -s * zf;
+    }
+    for (int b = 0; b < P; ++b) {
+        const float mu = (float)smu[b];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double* q = srec + jr[r] * stride + 3 * b;
+            const float dx = (float)(x[r] - q[0]), dy = (float)(y[r] - q[1]), dz = (float)(z[r] - q[2]);
+            const float id = rsqrtf(dx * dx + dy * dy + dz * dz);
+            const float sd = mu * (id * id * id);
+            fx[r] -= sd * dx;
+            fy[r] -= sd * dy;
+            fz[r] -= sd * dz;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const double* q = srec + jr[r] * stride + 3 * P;
+        ax[r] = (double)(fx[r] - (float)q[0]);
+        ay[r] = (double)(fy[r] - (float)q[1]);
+        az[r] = (double)(fz[r] - (float)q[2]);
     }
 }
 
@@ -260,15 +310,17 @@ static __device__ __forceinline__ int pc_node(const PcLane& L, int h, int r)
     return (L.strip0 + h) * 16 + (L.lane >> 4) + 4 * r;
 }
 
-// y_new = y0 + w2 K_N F on the FP64 matrix cores (Sec. 2.2 with A, C and S folded into K_N)
-// for the lane's six blocks; acc receives y_new.  Also evaluates the stopping rule of
-// Sec. 2.2 against the previous iterate yc in squared form (|dr|^2 < tol^2 |r|^2 and the
-// same for v, or without the norms in absolute mode) and returns, OR-ed over the lanes
-// of each IC: bit 0 = some node not converged, bit 1 = non-finite.
-template <int PAIRS, int NP>
+// y_new = y0 + w2 K_N F on the matrix cores (Sec. 2.2 with A, C and S folded into K_N) for
+// the lane's six blocks, FP64 or (FP32) FP32 products accumulated into FP64; acc receives
+// y_new.  Also evaluates the stopping rule of Sec. 2.2 against the previous iterate yc in
+// squared form (|dr|^2 < tol^2 |r|^2 and the same for v, or without the norms in absolute
+// mode) and returns, OR-ed over the lanes of each IC: bit 0 = some node not converged,
+// bit 1 = non-finite, bit 2 = some node changed by more than sqrt(sw2) (relative).
+template <int PAIRS, int NP, bool FP32 = false>
 static __device__ __forceinline__ int pc_product(const double* sF, const double* sY0, gconst_dp kp0,
-                                                  const double (&yc)[6][4], f64x4 (&acc)[6], double w2,
-                                                  double t2, int tol_mode, int N, const PcLane& L)
+                                                  gconst_fp kp0f, const double (&yc)[6][4], f64x4 (&acc)[6],
+                                                  double w2, double t2, double sw2, int tol_mode, int N,
+                                                  const PcLane& L)
 {
     using Sh = PcShape<PAIRS, NP>;
     constexpr int T = Sh::T, ROW = Sh::ROW, NQ = Sh::NQ;
@@ -276,15 +328,67 @@ static __device__ __forceinline__ int pc_product(const double* sF, const double*
 #pragma unroll
     for (int b = 0; b < 6; ++b) acc[b] = f64x4{0.0, 0.0, 0.0, 0.0};
     int flag = 0;
+    if constexpr (FP32) {
+        // FP32 sweep: FP32 fragments of K_N (rows permuted so the f32 result layout matches
+        // the f64 one), FP32 copies of the B operands, FP64 accumulation into y0 below
+        f32x4 accf[6];
+#pragma unroll
+        for (int b = 0; b < 6; ++b) accf[b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        if constexpr (Sh::WIDE) {
+            const double* bp = sF + (lane >> 4) * ROW + L.grp * 16 + (lane & 15);
+            float bc[6], bn[6];
+            float ka = kp0f[0], kb = (NQ > 1) ? kp0f[64] : 0.0f;
+#pragma unroll
+            for (int b = 0; b < 6; ++b) bc[b] = (float)bp[b * T];
+#pragma unroll 2
+            for (int q = 0; q < NQ; ++q) {
+                const float kn = (q + 2 < NQ) ? kp0f[(q + 2) * 64] : 0.0f;
+                if (q + 1 < NQ) {
+#pragma unroll
+                    for (int b = 0; b < 6; ++b) bn[b] = (float)bp[(q + 1) * 4 * ROW + b * T];
+                }
+#pragma unroll
+                for (int b = 0; b < 6; ++b) accf[b] = mfma16f(ka, bc[b], accf[b]);
+#pragma unroll
+                for (int b = 0; b < 6; ++b) bc[b] = bn[b];
+                ka = kb;
+                kb = kn;
+            }
+        } else {
+            gconst_fp kp1f = kp0f + (size_t)NQ * 64;
+            const double* bp = sF + (lane >> 4) * ROW + (lane & 15);
+#pragma unroll 4
+            for (int q = 0; q < NQ; ++q) {
+                const float a0 = kp0f[q * 64], a1 = kp1f[q * 64];
+                const double* bq = bp + q * 4 * ROW;
+                const float b0 = (float)bq[0], b1 = (float)bq[16], b2 = (float)bq[32];
+                accf[0] = mfma16f(a0, b0, accf[0]);
+                accf[1] = mfma16f(a0, b1, accf[1]);
+                accf[2] = mfma16f(a0, b2, accf[2]);
+                accf[3] = mfma16f(a1, b0, accf[3]);
+                accf[4] = mfma16f(a1, b1, accf[4]);
+                accf[5] = mfma16f(a1, b2, accf[5]);
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < 6; ++b) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[b][r] = (double)accf[b][r];
+        }
+    }
     if constexpr (Sh::WIDE) {
         // K_N strip streamed from L2 two k-steps ahead; B operands one k-step ahead
         const double* bp = sF + (lane >> 4) * ROW + L.grp * 16 + (lane & 15);
         double bc[6], bn[6];
-        double ka = kp0[0], kb = (NQ > 1) ? kp0[64] : 0.0;
+        double ka = 0.0, kb = 0.0;
+        if constexpr (!FP32) {
+            ka = kp0[0];
+            kb = (NQ > 1) ? kp0[64] : 0.0;
 #pragma unroll
-        for (int b = 0; b < 6; ++b) bc[b] = bp[b * T];
+            for (int b = 0; b < 6; ++b) bc[b] = bp[b * T];
+        }
 #pragma unroll 2
-        for (int q = 0; q < NQ; ++q) {
+        for (int q = 0; q < (FP32 ? 0 : NQ); ++q) {
             const double kn = (q + 2 < NQ) ? kp0[(q + 2) * 64] : 0.0;
             if (q + 1 < NQ) {
 #pragma unroll
@@ -311,18 +415,26 @@ static __device__ __forceinline__ int pc_product(const double* sF, const double*
             }
             if (j < N) {
                 const bool ok = tol_mode == 0 ? (pd < t2 * py && vd < t2 * vy) : (pd < t2 && vd < t2);
+                const bool lo = tol_mode == 0 ? (pd < sw2 * py && vd < sw2 * vy) : (pd < sw2 && vd < sw2);
                 const bool nf = !isfinite(pd + py + vd + vy);
-                flag |= (ok ? 0 : 1) | (nf ? 2 : 0);
+                flag |= (ok ? 0 : 1) | (nf ? 2 : 0) | (lo ? 0 : 4);
             }
         }
     } else {
         gconst_dp kp1 = kp0 + (size_t)NQ * 64;
         const double* bp = sF + (lane >> 4) * ROW + (lane & 15);
-        double a0 = kp0[0], a1 = kp1[0];
+        double a0 = 0.0, a1 = 0.0;
         double a0n = 0.0, a1n = 0.0;
-        double b0 = bp[0], b1 = bp[16], b2 = bp[32];
+        double b0 = 0.0, b1 = 0.0, b2 = 0.0;
+        if constexpr (!FP32) {
+            a0 = kp0[0];
+            a1 = kp1[0];
+            b0 = bp[0];
+            b1 = bp[16];
+            b2 = bp[32];
+        }
 #pragma unroll 4
-        for (int q = 0; q < NQ; ++q) {
+        for (int q = 0; q < (FP32 ? 0 : NQ); ++q) {
             double b0n = 0.0, b1n = 0.0, b2n = 0.0;
             if (q + 1 < NQ) {
                 a0n = kp0[(q + 1) * 64];
@@ -365,8 +477,9 @@ static __device__ __forceinline__ int pc_product(const double* sF, const double*
                 vy += __shfl_xor(vy, 8);
                 if (j < N) {
                     const bool ok = tol_mode == 0 ? (pd < t2 * py && vd < t2 * vy) : (pd < t2 && vd < t2);
+                    const bool lo = tol_mode == 0 ? (pd < sw2 * py && vd < sw2 * vy) : (pd < sw2 && vd < sw2);
                     const bool nf = !isfinite(pd + py + vd + vy);
-                    flag |= (ok ? 0 : 1) | (nf ? 2 : 0);
+                    flag |= (ok ? 0 : 1) | (nf ? 2 : 0) | (lo ? 0 : 4);
                 }
             }
         }
@@ -394,7 +507,7 @@ static __device__ __forceinline__ int pc_gather_flags(const int* sFlag, int m)
 // Dynamics of the lane's (node, IC) pairs from its registers, published with the
 // velocities as the force matrix F = (v, a) of Sec. 2.2 into sF[node][comp'][IC].
 // sRec/sMu: the segment's records in LDS (when rec_lds), grec: the same in global memory.
-template <int PAIRS, int NP>
+template <int PAIRS, int NP, bool FP32 = false>
 static __device__ __forceinline__ void pc_publish(double* sF, const double (&yc)[6][4], const PcLane& L,
                                                   int N, int P, double mu_sun, bool rec_lds,
                                                   const double* sRec, const double* sMu, const double4* grec)
@@ -410,7 +523,8 @@ static __device__ __forceinline__ void pc_publish(double* sF, const double (&yc)
             const int j = pc_node(L, 0, r);
             jr[r] = j < N ? j : N - 1;
         }
-        if (rec_lds) pc_force_lds<4>(yc[0], yc[1], yc[2], jr, P, mu_sun, sRec, sMu, ax, ay, az);
+        if (rec_lds && FP32) pc_force_lds32<4>(yc[0], yc[1], yc[2], jr, P, mu_sun, sRec, sMu, ax, ay, az);
+        else if (rec_lds) pc_force_lds<4>(yc[0], yc[1], yc[2], jr, P, mu_sun, sRec, sMu, ax, ay, az);
         else pc_force_glb<4>(yc[0], yc[1], yc[2], jr, P, mu_sun, grec, ax, ay, az);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -440,7 +554,8 @@ static __device__ __forceinline__ void pc_publish(double* sF, const double (&yc)
                 zs[r] = yc[3 * h + 1][r];
             }
             if (!hi) {
-                if (rec_lds) pc_force_lds<4>(xs, ys, zs, jr, P, mu_sun, sRec, sMu, ax, ay, az);
+                if (rec_lds && FP32) pc_force_lds32<4>(xs, ys, zs, jr, P, mu_sun, sRec, sMu, ax, ay, az);
+                else if (rec_lds) pc_force_lds<4>(xs, ys, zs, jr, P, mu_sun, sRec, sMu, ax, ay, az);
                 else pc_force_glb<4>(xs, ys, zs, jr, P, mu_sun, grec, ax, ay, az);
             }
 #pragma unroll

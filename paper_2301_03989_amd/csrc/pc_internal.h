@@ -26,6 +26,7 @@ struct PcGroupDev {
     int64_t ic_offset, n_ic;
     int64_t rec_offset;        // first ephemeris record of the group (S * N records)
     const double* kfrag;       // [NP/16][NP/4][64]
+    const float* kfrag32;      // FP32 copy, rows permuted for the f32 MFMA result layout
     const double* tau;         // [NP] CGL nodes, zero past N
     int32_t N, NP, T, S;
 };
@@ -58,6 +59,9 @@ struct PcParams {
     const double* recs;         // ephemeris records, (n_pert+1) double4 each
     double mu_sun;
     int32_t max_iter, fixed_iters, tol_mode, init;
+    int32_t precision;          // 0 FP64; 1 FP32 sweeps, then FP64
+    int32_t max_fp32;           // cap on FP32 sweeps per segment
+    double switch2;             // squared relative change below which a job leaves FP32
     int32_t* counters;          // [0] ICs with a not-converged segment, [1] non-finite ICs
     int32_t* queue;             // next job of the persistent kernel (starts at 0)
 };

@@ -161,25 +161,46 @@ __device__ __attribute__((noinline)) void pc_job(const PcParams& p, const PcJobD
         __syncthreads();   // staging read before F is rebuilt
         for (int i = tid; i < 6 * PAIRS; i += NT) sF[i] = 0.0;
         __syncthreads();
-        if (sm.Active[L.my_m]) pc_publish<PAIRS, NP>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
+        // precision schedule (uniform per job): FP32 sweeps first when asked, then FP64
+        bool fp32 = p.precision == 1;
+        int n32 = 0;
+        if (sm.Active[L.my_m]) {
+            if (fp32) pc_publish<PAIRS, NP, true>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
+            else pc_publish<PAIRS, NP>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
+        }
         __syncthreads();
 
+        gconst_fp kp0f = (gconst_fp)g.kfrag32 + (size_t)L.strip0 * NQ * 64 + L.lane;
         const int n_it = p.fixed_iters > 0 ? p.fixed_iters : p.max_iter;
         for (int it = 1; it <= n_it; ++it) {
             // (1)-(2) product and stopping-rule flags
             f64x4 acc[6];
-            const int flag = pc_product<PAIRS, NP>(sF, sY0, kp0, yc, acc, w2, t2, p.tol_mode, N, L);
+            const int flag = fp32 ? pc_product<PAIRS, NP, true>(sF, sY0, kp0, kp0f, yc, acc, w2, t2, p.switch2,
+                                                                  p.tol_mode, N, L)
+                                  : pc_product<PAIRS, NP, false>(sF, sY0, kp0, kp0f, yc, acc, w2, t2, p.switch2,
+                                                                   p.tol_mode, N, L);
             if (L.lane < 16) sm.Flag[L.wave * 16 + L.lane] = flag;
             const int act = sm.Active[L.my_m];
+            const unsigned long long keep = __ballot(act && (flag & 4));
+            if (L.lane == 0) sm.Keep[L.wave] = keep != 0ull;
             __syncthreads();   // every wave is done reading F; flags complete
 
-            // (3) stopping rule per IC (Sec. 2.2; per-block error of Sec. 3.2 with blocks of one IC)
+            // the job leaves FP32 once no iterating IC changes by more than the switch threshold
+            bool next32 = false;
+            if (fp32) {
+                int k = 0;
+                for (int w = 0; w < Sh::W; ++w) k |= sm.Keep[w];
+                ++n32;
+                next32 = k && n32 < p.max_fp32;
+            }
+            // (3) stopping rule per IC (Sec. 2.2; per-block error of Sec. 3.2 with blocks of one IC);
+            //     not applied to FP32 sweeps
             if (tid < T && sm.Active[tid]) {
                 const int f = pc_gather_flags<PAIRS, NP>(sm.Flag, tid);
                 int rec = 0;
                 if (f & 2) rec = -2;
                 else if (p.fixed_iters > 0) rec = (it == p.fixed_iters) ? it : 0;
-                else if (!(f & 1)) rec = it;
+                else if (!fp32 && !(f & 1)) rec = it;
                 else if (it == p.max_iter) rec = -1;
                 if (rec != 0) {
                     sm.Active[tid] = 0;
@@ -195,8 +216,12 @@ __device__ __attribute__((noinline)) void pc_job(const PcParams& p, const PcJobD
 #pragma unroll
                     for (int r = 0; r < 4; ++r) yc[b][r] = acc[b][r];
                 }
-                if (it < n_it) pc_publish<PAIRS, NP>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
+                if (it < n_it) {
+                    if (next32) pc_publish<PAIRS, NP, true>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
+                    else pc_publish<PAIRS, NP>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
+                }
             }
+            fp32 = next32;
             const int any = __syncthreads_or(tid < T ? sm.Active[tid] : 0);
             if (!any) break;
         }

@@ -314,3 +314,38 @@ def test_autotune_records_a_shape(pc):
     assert pc.tile_pairs(128) == 0
     with pytest.raises(pcprop.PcError):
         pc.set_tile_pairs(256, 1024)
+
+
+# ---------------------------------------------------------------------------
+# precision schedule: FP32 sweeps, then FP64 sweeps to the FP64 fixed point
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n_ic", [7, 250])
+def test_fp32_then_fp64_matches_fp64_oracle(pc, n_ic):
+    w = W.nbody_venus(n_ic, seed=104)
+    r, _ = _run(pc, w, precision="fp32-fp64", want_bounds=True)
+    o = oracle_run(w, want_bounds=True)
+    assert r["status"] == 0
+    err = rel_err(r["states"], o["states"])
+    assert err.max() < TOL, err.max()
+    assert rel_err(r["bounds"].reshape(-1, 6), o["bounds"].reshape(-1, 6)).max() < TOL
+    # the FP32 sweeps come on top of the FP64 ones needed from ~1e-6
+    assert (r["iters"] >= 2).all()
+
+
+def test_fp32_then_fp64_mixed_groups(pc):
+    w = W.uneven_batch(600, seed=22)
+    for g in w.groups:
+        g.segments = 1 + g.segments // 16
+        g.tf = g.segments * np.pi / 4.0
+    idx = np.concatenate([np.arange(g.ic_offset, g.ic_offset + min(g.n_ic, 6)) for g in w.groups])
+    r, sub = _run(pc, w, idx, precision="fp32-fp64")
+    o = oracle_run(sub)
+    assert r["status"] == 0
+    assert rel_err(r["states"], o["states"]).max() < TOL
+
+
+def test_fp32_then_fp64_rejected_on_plain_path(pc):
+    from paper_2301_03989_amd import pcprop
+    w = W.nbody_venus(4)
+    with pytest.raises(pcprop.PcError):
+        _run(pc, w, precision="fp32-fp64", path="plain")
