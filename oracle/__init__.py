@@ -60,6 +60,9 @@ def _load():
         lib.orc_ephem.argtypes = [_dp, ctypes.c_double, ctypes.c_double, _dp]
         lib.orc_kepler.restype = ctypes.c_int
         lib.orc_kepler.argtypes = [_dp, ctypes.c_double, _dp]
+        lib.orc_accel_jac_t.restype = None
+        lib.orc_accel_jac_t.argtypes = [_dp, ctypes.c_double, ctypes.c_double, ctypes.c_int, _dp,
+                                        ctypes.c_double, _dp]
         lib.orc_rk4.restype = None
         lib.orc_rk4.argtypes = [_dp, ctypes.c_double, ctypes.c_double, ctypes.c_long,
                                 ctypes.c_double, ctypes.c_int, _dp, ctypes.c_double, _dp]
@@ -211,3 +214,66 @@ def rk4(y0, t0, tf, nsteps, model):
     lib.orc_rk4(_ptr(y0), float(t0), float(tf), int(nsteps), model.mu_sun, model.n_pert,
                 model._pert_ptr(), model.epoch, _ptr(y))
     return y
+
+
+def accel_jac_t(r, t, model):
+    """da/dr (3x3) of the force model at (r, t)."""
+    lib = _load()
+    r = _f64(r).reshape(3)
+    J = np.zeros(9)
+    lib.orc_accel_jac_t(_ptr(r), float(t), model.mu_sun, model.n_pert, model._pert_ptr(),
+                        model.epoch, _ptr(J))
+    return J.reshape(3, 3)
+
+
+def adjoint(ics, t0, tf, nodes, segments, tol, model=None, gbar_final=None, gbar_nodes=None, *,
+            init=0, tol_mode=0, max_iter=64):
+    """Gradient dL/dy0 [n, 6] of a loss L(y_final, node states) through the converged
+    Picard-Chebyshev map, by implicit differentiation of its discrete fixed point.
+
+    Per segment the converged node states satisfy Y = 1 y0^T + K G(Y), G_j = w2 f(Y_j, t_j)
+    (Sec. 2.2 with the fit/integrate/evaluate steps as the linear map K, obtained here by
+    applying the oracle's update to unit vectors).  With J_j = w2 df/dy at node j, the
+    adjoint mu solves (I - K J)^T mu = gbar (a dense 6N x 6N solve, numpy), and
+    dL/dy0 = sum_j mu_j.  Segments are chained backwards: the end node of segment s-1 is
+    the initial state of segment s, so its seed is the gradient of segment s.
+
+    gbar_final [n, 6] = dL/dy_final; gbar_nodes [n, S, N, 6] = dL/dY (optional).
+    """
+    model = model or Model()
+    ics = _f64(ics).reshape(-1, 6)
+    n = ics.shape[0]
+    S, N = int(segments), int(nodes)
+    t0a = np.broadcast_to(np.asarray(t0, dtype=np.float64), (n,))
+    tfa = np.broadcast_to(np.asarray(tf, dtype=np.float64), (n,))
+    _, _, Ys = propagate(ics, t0a, tfa, N, S, tol, model, init=init, tol_mode=tol_mode, max_iter=max_iter,
+                         want_nodes=True)
+    K = operator(N)
+    tau = nodes_(N)
+    gbar_final = np.zeros((n, 6)) if gbar_final is None else _f64(gbar_final).reshape(n, 6)
+    grads = np.zeros((n, 6))
+    eye6 = np.eye(6)
+    for m in range(n):
+        lam = gbar_final[m].copy()
+        h = (tfa[m] - t0a[m]) / S
+        for s in range(S - 1, -1, -1):
+            Ts, Te = t0a[m] + h * s, t0a[m] + h * (s + 1)
+            w1, w2 = 0.5 * (Te + Ts), 0.5 * (Te - Ts)
+            Jb = np.zeros((N, 6, 6))
+            for j in range(N):
+                A = accel_jac_t(Ys[m, s, j, :3], w2 * tau[j] + w1, model)
+                Jb[j, :3, 3:] = w2 * np.eye(3)
+                Jb[j, 3:, :3] = w2 * A
+            # M[(j,a),(l,b)] = delta - K[j,l] J_l[a,b]
+            M = np.eye(6 * N) - np.einsum("jl,lab->jalb", K, Jb).reshape(6 * N, 6 * N)
+            gb = np.zeros((N, 6))
+            gb[N - 1] += lam
+            if gbar_nodes is not None:
+                gb += gbar_nodes[m, s]
+            mu = np.linalg.solve(M.T, gb.reshape(-1)).reshape(N, 6)
+            lam = mu.sum(axis=0)
+        grads[m] = lam
+    return grads
+
+
+nodes_ = nodes

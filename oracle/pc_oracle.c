@@ -156,6 +156,43 @@ void orc_accel(const double r[3], int n_pert, const double* rp, const double* mu
     }
 }
 
+/* Jacobian da/dr (3x3, row-major) of the force model at r with perturbers at rp:
+ * for every attracting body with parameter mu at offset d = r - r_b,
+ *   d/dr [-mu d/|d|^3] = -mu (I/|d|^3 - 3 d d^T/|d|^5);
+ * the indirect term does not depend on r. */
+void orc_accel_jac(const double r[3], int n_pert, const double* rp, const double* mup, double mu_sun,
+                   double J[9])
+{
+    for (int k = 0; k < 9; ++k) J[k] = 0.0;
+    for (int b = -1; b < n_pert; ++b) {
+        double d[3], mu;
+        if (b < 0) { d[0] = r[0]; d[1] = r[1]; d[2] = r[2]; mu = mu_sun; }
+        else {
+            for (int k = 0; k < 3; ++k) d[k] = r[k] - rp[3 * b + k];
+            mu = mup[b];
+        }
+        double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        double dn = sqrt(d2);
+        double i3 = 1.0 / (d2 * dn), i5 = i3 / d2;
+        for (int a = 0; a < 3; ++a)
+            for (int c = 0; c < 3; ++c)
+                J[3 * a + c] -= mu * ((a == c ? i3 : 0.0) - 3.0 * d[a] * d[c] * i5);
+    }
+}
+
+/* da/dr at (r, t) with perturber positions from their elements. */
+void orc_accel_jac_t(const double r[3], double t, double mu_sun, int n_pert, const double* pert,
+                     double epoch, double J[9])
+{
+    double rp[3 * 64], mup[64];
+    int np = n_pert > 64 ? 64 : n_pert;
+    for (int p = 0; p < np; ++p) {
+        orc_ephem(pert + 7 * p, epoch, t, rp + 3 * p);
+        mup[p] = pert[7 * p];
+    }
+    orc_accel_jac(r, np, rp, mup, mu_sun, J);
+}
+
 /* Acceleration at (r, t) with perturber positions from their elements. */
 void orc_accel_t(const double r[3], double t, double mu_sun, int n_pert, const double* pert,
                  double epoch, double acc[3])

@@ -357,3 +357,87 @@ def test_iteration_count_convention():
     # any finite first error is below a huge tolerance: one iteration, cold start too
     _, it = oracle.propagate(w.ics, 0.0, tf, 64, 4, 1e3, init=1)
     assert (it == 1).all()
+
+
+# ---------------------------------------------------------------------------
+# Adjoint of the converged map (implicit differentiation of the discrete fixed point)
+# ---------------------------------------------------------------------------
+def test_force_jacobian_matches_finite_differences():
+    w = W.nbody_venus(1)
+    m = oracle.Model(1.0, w.pert)
+    rng = np.random.default_rng(2)
+    for _ in range(4):
+        r = rng.uniform(-1.2, 1.2, 3)
+        t = rng.uniform(0, 5)
+        J = oracle.accel_jac_t(r, t, m)
+        h = 1e-6
+        fd = np.stack([(oracle.accel_t(r + h * e, t, m) - oracle.accel_t(r - h * e, t, m)) / (2 * h)
+                       for e in np.eye(3)], axis=1)
+        np.testing.assert_allclose(J, fd, rtol=0, atol=1e-7 * np.abs(J).max())
+        np.testing.assert_allclose(J, J.T, rtol=0, atol=1e-14 * np.abs(J).max())   # potential force
+
+
+def _fd_gradient(w, gbar, h=1e-6, fixed=40, **kw):
+    g = w.groups[0]
+    m = oracle.Model(1.0, w.pert)
+    fd = np.zeros((w.n_ic, 6))
+    for k in range(6):
+        e = np.zeros(6)
+        e[k] = h
+        sp, _ = oracle.propagate(w.ics + e, g.t0, g.tf, g.nodes, g.segments, g.tol, m, fixed_iters=fixed, **kw)
+        sm, _ = oracle.propagate(w.ics - e, g.t0, g.tf, g.nodes, g.segments, g.tol, m, fixed_iters=fixed, **kw)
+        fd[:, k] = ((sp - sm) * gbar).sum(axis=1) / (2 * h)
+    return fd
+
+
+@pytest.mark.parametrize("segments,nodes", [(1, 32), (3, 48)])
+def test_adjoint_matches_finite_differences(segments, nodes):
+    # finite differences of the map iterated to a fixed number of sweeps (smooth, no
+    # stopping-rule noise), against the implicit derivative at the converged point
+    w = W.nbody_venus(3, days=56.25 * segments, segments=segments, nodes=nodes, tol=1e-13)
+    g = w.groups[0]
+    gbar = np.random.default_rng(segments).standard_normal((3, 6))
+    gr = oracle.adjoint(w.ics, g.t0, g.tf, g.nodes, g.segments, g.tol, oracle.Model(1.0, w.pert), gbar)
+    fd = _fd_gradient(w, gbar)
+    np.testing.assert_allclose(gr, fd, rtol=0, atol=1e-8 * np.abs(fd).max())
+
+
+def test_adjoint_matches_variational_stm():
+    # continuous state-transition matrix along the trajectory, integrated by DOP853
+    w = W.nbody_venus(2, days=112.5, segments=2, nodes=64, tol=1e-13)
+    g = w.groups[0]
+    m = oracle.Model(1.0, w.pert)
+    gbar = np.array([[1.0, -0.5, 0.2, 0.3, 0.0, 0.1], [0.0, 0.0, 1.0, 0.0, 0.0, 0.0]])
+    gr = oracle.adjoint(w.ics, g.t0, g.tf, g.nodes, g.segments, g.tol, m, gbar)
+    for i in range(2):
+        def rhs(t, z):
+            y, Phi = z[:6], z[6:].reshape(6, 6)
+            A = oracle.accel_jac_t(y[:3], t, m)
+            Jc = np.zeros((6, 6))
+            Jc[:3, 3:] = np.eye(3)
+            Jc[3:, :3] = A
+            return np.concatenate([y[3:], oracle.accel_t(y[:3], t, m), (Jc @ Phi).reshape(-1)])
+        z0 = np.concatenate([w.ics[i], np.eye(6).reshape(-1)])
+        sol = solve_ivp(rhs, (g.t0, g.tf), z0, method="DOP853", rtol=1e-12, atol=1e-14)
+        Phi = sol.y[6:, -1].reshape(6, 6)
+        np.testing.assert_allclose(gr[i], Phi.T @ gbar[i], rtol=0, atol=1e-8 * np.abs(gr[i]).max())
+
+
+def test_adjoint_node_seeds_match_finite_differences():
+    # a loss on interior node states (seeded through gbar_nodes) against finite differences
+    w = W.nbody_venus(2, days=112.5, segments=2, nodes=32, tol=1e-13)
+    g = w.groups[0]
+    m = oracle.Model(1.0, w.pert)
+    c = np.random.default_rng(9).standard_normal((2, 6))
+    gn = np.zeros((2, 2, 32, 6))
+    gn[:, 0, 11] = c                        # L = c . Y(segment 0, node 11)
+    gr = oracle.adjoint(w.ics, g.t0, g.tf, g.nodes, g.segments, g.tol, m, None, gn)
+    h = 1e-6
+    fd = np.zeros((2, 6))
+    for k in range(6):
+        e = np.zeros(6)
+        e[k] = h
+        _, _, npl = oracle.propagate(w.ics + e, g.t0, g.tf, 32, 2, 1e-13, m, fixed_iters=40, want_nodes=True)
+        _, _, nmi = oracle.propagate(w.ics - e, g.t0, g.tf, 32, 2, 1e-13, m, fixed_iters=40, want_nodes=True)
+        fd[:, k] = ((npl[:, 0, 11] - nmi[:, 0, 11]) * c).sum(axis=1) / (2 * h)
+    np.testing.assert_allclose(gr, fd, rtol=0, atol=1e-8 * np.abs(fd).max())
