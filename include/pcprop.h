@@ -150,6 +150,27 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic,
                          double* bounds_out, double* nodes_out, int32_t nodes_stride,
                          void* workspace, size_t ws_bytes, pc_stream_t stream);
 
+/* Gradient of a loss through the converged propagation (reverse mode, segment
+ * checkpointing).  Per segment the converged node states satisfy Y = 1 y0^T + K_N G(Y)
+ * (the fixed point of Sec. 2.2); with J_j = w2 df/dy at node j the loss gradient seeds
+ * gbar give dL/dy0 = sum_j mu_j where mu = gbar + J^T (K_N^T mu), solved by sweeping until
+ * the propagated gradient changes by less than adj_tol (relative).  Segments are taken
+ * from the last: each is re-solved from its checkpoint with the forward code, then its
+ * gradient seeds the end node of the previous one.  Fused FP64 path, nodes <= 128.
+ *   groups, model, opts  as in the forward pc_propagate_batched call
+ *   ckpt        device [n_ic][ckpt_stride + 1][6] segment-boundary states of the forward call
+ *               (its bounds_out); ckpt_stride >= every group's segment count
+ *   gbar_final  device [n_ic][6] dL/d(final state)
+ *   gbar_nodes  device [n_ic][ckpt_stride][nodes_stride][6] dL/d(node states), or NULL
+ *   grad_ics    device [n_ic][6] dL/d(initial state), output
+ *   adj_iters   device int32 [n_ic][ckpt_stride] adjoint sweeps per segment, or NULL
+ * Returns PC_ENOTCONV if a forward re-solve or an adjoint sweep loop hit its cap. */
+int pc_adjoint(pc_ctx* ctx, int64_t n_ic, const pc_group* groups /* host */, int32_t n_groups,
+               const pc_model* model, const pc_opts* opts, const double* ckpt, int32_t ckpt_stride,
+               const double* gbar_final, const double* gbar_nodes, int32_t nodes_stride,
+               double adj_tol, int32_t adj_max_iter, double* grad_ics, int32_t* adj_iters,
+               void* workspace, size_t ws_bytes, pc_stream_t stream);
+
 /* ---- operator and kernel-level entry points (used by the tests) ---- */
 
 /* The N x N matrix K_N with y_j = y_0 + sum_l K_N[j][l] g_l for the w2-scaled force

@@ -24,6 +24,7 @@ struct OperatorCache {
     int N = 0, NP = 0;
     double* kfrag = nullptr;   // device, [NP/16][NP/4][64]
     float* kfrag32 = nullptr;  // device, FP32 fragments with rows permuted per strip
+    double* kfragT = nullptr;  // device, fragments of K_N^T
     double* tau = nullptr;     // device, [NP]
     std::vector<double> K;     // host copy, [N][N]
 };
@@ -154,12 +155,22 @@ int get_operator(pc_ctx* ctx, int N, const OperatorCache** out)
                 frag32[((size_t)strip * NQ + q) * 64 + lane] =
                     (row < N && col < N) ? (float)oc.K[(size_t)row * N + col] : 0.0f;
             }
+    std::vector<double> fragT((size_t)NP * NP, 0.0);
+    for (int strip = 0; strip < NP / 16; ++strip)
+        for (int q = 0; q < NQ; ++q)
+            for (int lane = 0; lane < 64; ++lane) {
+                const int row = 16 * strip + (lane & 15), col = 4 * q + (lane >> 4);   // of K_N^T
+                fragT[((size_t)strip * NQ + q) * 64 + lane] =
+                    (row < N && col < N) ? oc.K[(size_t)col * N + row] : 0.0;
+            }
     std::vector<double> tau(NP, 0.0);
     const long double pi = 3.141592653589793238462643383279502884L;
     for (int j = 0; j < N; ++j) tau[j] = (double)(-cosl(pi * (long double)j / (long double)(N - 1)));
     PC_HIP(ctx, hipSetDevice(ctx->device));
     PC_HIP(ctx, hipMalloc(&oc.kfrag, frag.size() * sizeof(double)));
     PC_HIP(ctx, hipMalloc(&oc.tau, tau.size() * sizeof(double)));
+    PC_HIP(ctx, hipMalloc(&oc.kfragT, fragT.size() * sizeof(double)));
+    PC_HIP(ctx, hipMemcpy(oc.kfragT, fragT.data(), fragT.size() * sizeof(double), hipMemcpyHostToDevice));
     PC_HIP(ctx, hipMalloc(&oc.kfrag32, frag32.size() * sizeof(float)));
     PC_HIP(ctx, hipMemcpy(oc.kfrag32, frag32.data(), frag32.size() * sizeof(float), hipMemcpyHostToDevice));
     PC_HIP(ctx, hipMemcpy(oc.kfrag, frag.data(), frag.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -321,6 +332,7 @@ int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, c
             if (rc != PC_OK) return rc;
             d.kfrag = oc->kfrag;
             d.kfrag32 = oc->kfrag32;
+            d.kfragT = oc->kfragT;
             d.tau = oc->tau;
         }
         plan.n_recs += (int64_t)G.segments * G.nodes;
@@ -447,6 +459,7 @@ void pc_ctx_destroy(pc_ctx* ctx)
         (void)hipFree(kv.second.kfrag);
         (void)hipFree(kv.second.tau);
         (void)hipFree(kv.second.kfrag32);
+        (void)hipFree(kv.second.kfragT);
     }
     if (ctx->staging) (void)hipHostFree(ctx->staging);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
@@ -688,6 +701,96 @@ int pc_last_kernel_ms(pc_ctx* ctx, double* ms)
     if (!ctx || !ms) return PC_EINVAL;
     *ms = ctx->last_ms;
     return ctx->last_ms >= 0.0 ? PC_OK : set_error(ctx, PC_EINVAL, "no timed call yet");
+}
+
+int pc_adjoint(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int32_t n_groups, const pc_model* model,
+               const pc_opts* opts, const double* ckpt, int32_t ckpt_stride, const double* gbar_final,
+               const double* gbar_nodes, int32_t nodes_stride, double adj_tol, int32_t adj_max_iter,
+               double* grad_ics, int32_t* adj_iters, void* workspace, size_t ws_bytes, pc_stream_t stream)
+{
+    if (!ctx) return PC_EINVAL;
+    ctx->last_error[0] = 0;
+    if (!ckpt || !gbar_final || !grad_ics || n_ic < 1)
+        return set_error(ctx, PC_EINVAL, "null ckpt/gbar_final/grad_ics or n_ic < 1");
+    int rc = validate_model(ctx, model);
+    if (rc != PC_OK) return rc;
+    pc_opts o = opts ? *opts : defaults();
+    if (o.path != PC_PATH_FUSED || o.precision != PC_FP64)
+        return set_error(ctx, PC_EINVAL, "the adjoint re-solves segments on the fused FP64 path");
+    if (o.init != PC_INIT_KEPLER && o.init != PC_INIT_COLD) return set_error(ctx, PC_EINVAL, "bad init");
+    if (o.max_iter < 1 || o.max_iter > 100000 || o.fixed_iters < 0) return set_error(ctx, PC_EINVAL, "bad iterations");
+    if (!(adj_tol > 0.0) || !std::isfinite(adj_tol) || adj_max_iter < 2 || adj_max_iter > 100000)
+        return set_error(ctx, PC_EINVAL, "adj_tol must be > 0 and adj_max_iter >= 2");
+    o.tile_pairs = 2048;
+    PC_HIP(ctx, hipSetDevice(ctx->device));
+    Plan plan;
+    rc = make_plan(ctx, n_ic, groups, n_groups, model, o, true, plan);
+    if (rc != PC_OK) return rc;
+    for (const PcGroupDev& d : plan.groups)
+        if (d.NP > 128) return set_error(ctx, PC_EINVAL, "the adjoint supports up to 128 nodes per segment");
+    if (ckpt_stride < plan.max_S) return set_error(ctx, PC_EINVAL, "ckpt_stride < segments");
+    if (gbar_nodes && nodes_stride < plan.max_N) return set_error(ctx, PC_EINVAL, "nodes_stride < nodes");
+    if (!workspace || ws_bytes < plan.total)
+        return set_error(ctx, PC_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, plan.total);
+    rc = ensure_staging(ctx, plan.staged + kAlign);
+    if (rc != PC_OK) return rc;
+    char* st = static_cast<char*>(ctx->staging);
+    std::memset(st, 0, plan.staged);
+    std::memcpy(st + plan.off_groups, plan.groups.data(), plan.groups.size() * sizeof(PcGroupDev));
+    std::memcpy(st + plan.off_jobs, plan.jobs.data(), plan.jobs.size() * sizeof(PcJobDev));
+    prepare_bodies(model, reinterpret_cast<PcBodyDev*>(st + plan.off_bodies));
+    char* ws = static_cast<char*>(workspace);
+    hipStream_t hs = (hipStream_t)stream;
+    PC_HIP(ctx, hipMemcpyAsync(ws, st, plan.staged, hipMemcpyHostToDevice, hs));
+    PcEphemParams ep{};
+    ep.groups = reinterpret_cast<const PcGroupDev*>(ws + plan.off_groups);
+    ep.n_groups = (int)plan.groups.size();
+    ep.n_recs = plan.n_recs;
+    ep.bodies = reinterpret_cast<const PcBodyDev*>(ws + plan.off_bodies);
+    ep.n_pert = model->n_pert;
+    ep.epoch = model->epoch;
+    ep.recs = reinterpret_cast<double*>(ws + plan.off_recs);
+    PC_HIP(ctx, (hipError_t)pc_launch_ephem(ep, hs));
+
+    PcAdjParams a{};
+    a.fwd.groups = ep.groups;
+    a.fwd.jobs = reinterpret_cast<const PcJobDev*>(ws + plan.off_jobs);
+    a.fwd.n_jobs = (int)plan.jobs.size();
+    a.fwd.n_pert = model->n_pert;
+    a.fwd.recs = ep.recs;
+    a.fwd.mu_sun = model->mu_sun;
+    a.fwd.max_iter = o.max_iter;
+    a.fwd.fixed_iters = o.fixed_iters;
+    a.fwd.tol_mode = o.tol_mode;
+    a.fwd.init = o.init;
+    a.fwd.precision = PC_FP64;
+    a.fwd.max_fp32 = 1;
+    a.fwd.switch2 = 0.0;
+    a.fwd.iters_stride = ckpt_stride;
+    a.ckpt = ckpt;
+    a.ckpt_stride = ckpt_stride;
+    a.nodes_stride = nodes_stride;
+    a.gbar_final = gbar_final;
+    a.gbar_nodes = gbar_nodes;
+    a.adj_tol = adj_tol;
+    a.adj_max_iter = adj_max_iter;
+    a.grad_out = grad_ics;
+    a.adj_iters = adj_iters;
+    a.counters = reinterpret_cast<int32_t*>(ws + plan.off_counters);
+    if (ctx->timing) PC_HIP(ctx, hipEventRecord(ctx->ev0, hs));
+    PC_HIP(ctx, (hipError_t)pc_launch_adjoint(a, ctx->n_cu, hs));
+    if (ctx->timing) PC_HIP(ctx, hipEventRecord(ctx->ev1, hs));
+    int32_t* hc = reinterpret_cast<int32_t*>(st);
+    PC_HIP(ctx, hipMemcpyAsync(hc, a.counters, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, hs));
+    PC_HIP(ctx, hipStreamSynchronize(hs));
+    if (ctx->timing) {
+        float ms = 0.0f;
+        PC_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+        ctx->last_ms = ms;
+    }
+    if (hc[1] > 0) return set_error(ctx, PC_ENONFINITE, "%d gradients are non-finite", hc[1]);
+    if (hc[0] > 0) return set_error(ctx, PC_ENOTCONV, "%d forward or adjoint sweeps did not converge", hc[0]);
+    return PC_OK;
 }
 
 int pc_set_tile_pairs(pc_ctx* ctx, int32_t padded_nodes, int32_t pairs)

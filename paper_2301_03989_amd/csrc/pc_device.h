@@ -269,6 +269,52 @@ static __device__ __forceinline__ void pc_force_glb(const double (&x)[R], const 
     }
 }
 
+// H w for the symmetric force Jacobian H = da/dr at R points: every attracting body with
+// parameter mu at offset d contributes -mu (w/|d|^3 - 3 d (d.w)/|d|^5); the indirect term
+// does not depend on r.  Records as in pc_force_lds (LDS) or pc_force_glb (global).
+template <int R, bool LDSREC>
+static __device__ __forceinline__ void pc_hess_apply(const double (&x)[R], const double (&y)[R],
+                                                     const double (&z)[R], const double (&wx)[R],
+                                                     const double (&wy)[R], const double (&wz)[R],
+                                                     const int (&jr)[R], int P, double mu_sun,
+                                                     const double* srec, const double* smu, const double4* grec,
+                                                     double (&hx)[R], double (&hy)[R], double (&hz)[R])
+{
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const double d2 = x[r] * x[r] + y[r] * y[r] + z[r] * z[r];
+        const double id = rsqrt(d2);
+        const double i3 = id * id * id, i5 = i3 * id * id;
+        const double dw = 3.0 * i5 * (x[r] * wx[r] + y[r] * wy[r] + z[r] * wz[r]);
+        hx[r] = -mu_sun * (i3 * wx[r] - dw * x[r]);
+        hy[r] = -mu_sun * (i3 * wy[r] - dw * y[r]);
+        hz[r] = -mu_sun * (i3 * wz[r] - dw * z[r]);
+    }
+    const int stride = 3 * (P + 1);
+    for (int b = 0; b < P; ++b) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            double qx, qy, qz, mu;
+            if constexpr (LDSREC) {
+                const double* q = srec + jr[r] * stride + 3 * b;
+                qx = q[0]; qy = q[1]; qz = q[2];
+                mu = smu[b];
+            } else {
+                const double4 q = grec[(size_t)jr[r] * (P + 1) + b];
+                qx = q.x; qy = q.y; qz = q.z;
+                mu = q.w;
+            }
+            const double dx = x[r] - qx, dy = y[r] - qy, dz = z[r] - qz;
+            const double id = rsqrt(dx * dx + dy * dy + dz * dz);
+            const double i3 = id * id * id, i5 = i3 * id * id;
+            const double dw = 3.0 * i5 * (dx * wx[r] + dy * wy[r] + dz * wz[r]);
+            hx[r] -= mu * (i3 * wx[r] - dw * dx);
+            hy[r] -= mu * (i3 * wy[r] - dw * dy);
+            hz[r] -= mu * (i3 * wz[r] - dw * dz);
+        }
+    }
+}
+
 // Shape of a job: PAIRS = NP x T (node, IC) pairs, NT threads in W waves; every wave owns
 // six 16x16 blocks of the iterate.  WIDE (T >= 16): one 16-row strip x the six component
 // blocks of one 16-IC group.  Otherwise (T == 8): two strips x three blocks of two
@@ -488,6 +534,39 @@ static __device__ __forceinline__ int pc_product(const double* sF, const double*
     flag |= __shfl_xor(flag, 16);
     flag |= __shfl_xor(flag, 32);
     return flag;
+}
+
+// acc = K_N^T mu for the lane's six blocks (WIDE shapes): the adjoint product, mu published
+// in sF as [node][comp 6][IC] and kpT the lane's strip of K_N^T fragments.
+template <int PAIRS, int NP>
+static __device__ __forceinline__ void pc_product_adj(const double* sF, gconst_dp kpT, f64x4 (&acc)[6],
+                                                      const PcLane& L)
+{
+    using Sh = PcShape<PAIRS, NP>;
+    static_assert(Sh::WIDE, "the adjoint runs on WIDE job shapes");
+    constexpr int T = Sh::T, ROW = Sh::ROW, NQ = Sh::NQ;
+    const int lane = L.lane;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) acc[b] = f64x4{0.0, 0.0, 0.0, 0.0};
+    const double* bp = sF + (lane >> 4) * ROW + L.grp * 16 + (lane & 15);
+    double bc[6], bn[6];
+    double ka = kpT[0], kb = (NQ > 1) ? kpT[64] : 0.0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) bc[b] = bp[b * T];
+#pragma unroll 2
+    for (int q = 0; q < NQ; ++q) {
+        const double kn = (q + 2 < NQ) ? kpT[(q + 2) * 64] : 0.0;
+        if (q + 1 < NQ) {
+#pragma unroll
+            for (int b = 0; b < 6; ++b) bn[b] = bp[(q + 1) * 4 * ROW + b * T];
+        }
+#pragma unroll
+        for (int b = 0; b < 6; ++b) acc[b] = mfma16(ka, bc[b], acc[b]);
+#pragma unroll
+        for (int b = 0; b < 6; ++b) bc[b] = bn[b];
+        ka = kb;
+        kb = kn;
+    }
 }
 
 // OR of the per-wave flags of IC m (written as Flag[wave][lane] by lanes < 16).

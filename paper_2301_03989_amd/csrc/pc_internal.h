@@ -27,6 +27,7 @@ struct PcGroupDev {
     int64_t rec_offset;        // first ephemeris record of the group (S * N records)
     const double* kfrag;       // [NP/16][NP/4][64]
     const float* kfrag32;      // FP32 copy, rows permuted for the f32 MFMA result layout
+    const double* kfragT;      // fragments of K_N^T (adjoint)
     const double* tau;         // [NP] CGL nodes, zero past N
     int32_t N, NP, T, S;
 };
@@ -66,6 +67,21 @@ struct PcParams {
     int32_t* queue;             // next job of the persistent kernel (starts at 0)
 };
 
+// Adjoint of a propagation (reverse sweep over segments from boundary checkpoints).
+struct PcAdjParams {
+    PcParams fwd;               // groups, jobs, model and forward options (outputs unused)
+    const double* ckpt;         // [n_ic][ckpt_stride + 1][6] segment-boundary states
+    int32_t ckpt_stride;
+    int32_t nodes_stride;
+    const double* gbar_final;   // [n_ic][6] dL/d(final state)
+    const double* gbar_nodes;   // [n_ic][ckpt_stride][nodes_stride][6] dL/d(node states), or null
+    double adj_tol;             // relative change of the propagated gradient that stops a sweep loop
+    int32_t adj_max_iter;
+    double* grad_out;           // [n_ic][6] dL/d(initial state)
+    int32_t* adj_iters;         // [n_ic][ckpt_stride] adjoint sweeps per segment, or null
+    int32_t* counters;          // [0] not converged, [1] non-finite, [2] queue
+};
+
 struct PcEphemParams {
     const PcGroupDev* groups;
     int32_t n_groups;
@@ -80,6 +96,7 @@ struct PcEphemParams {
 int pc_launch_ephem(const PcEphemParams& p, void* stream);
 int pc_launch_fused(const PcParams& p, int pairs, int grid, void* stream);
 int pc_fused_occupancy(int pairs, int* blocks_per_cu);
+int pc_launch_adjoint(const PcAdjParams& a, int grid, void* stream);
 int pc_launch_apply_operator(int NP, const double* kfrag, int N, int64_t n_cols, const double* F,
                              const double* y0, double scale, double* Y, void* stream);
 int pc_launch_eval_force(const double* r, const double* t, int64_t n, const PcBodyDev* bodies,

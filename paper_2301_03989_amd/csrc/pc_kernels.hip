@@ -76,6 +76,134 @@ __device__ __forceinline__ PcSmem<2048>& pc_smem<2048>() { return g_smem2048; }
 template <>
 __device__ __forceinline__ PcSmem<1024>& pc_smem<1024>() { return g_smem1024; }
 
+// Picard iterations of one segment for the job's ICs (initial states in sm.Y0): ephemeris
+// records into LDS, initial guess, then sweeps until every IC of the job has stopped.
+// On return yc holds the lane's share of the final iterate.  iters_out (may be null)
+// receives the iteration records.
+template <int PAIRS, int NP>
+static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const PcGroupDev& g, int n, int64_t ic0,
+                                                        int s, PcSmem<PAIRS>& sm, const PcLane& L, gconst_dp kp0,
+                                                        double (&yc)[6][4], int32_t* iters_out, int& had_notconv,
+                                                        int rec_cap = PcSmem<PAIRS>::REC)
+{
+    using Sh = PcShape<PAIRS, NP>;
+    constexpr int NT = Sh::NT, T = Sh::T, ROW = Sh::ROW, NQ = Sh::NQ;
+    double* sF = sm.F;
+    double* sY0 = sm.Y0;
+    const int tid = threadIdx.x;
+    const int N = g.N;
+    const int P = p.n_pert;
+    const int64_t ic = ic0 + tid;
+    const bool rec_lds = N * 3 * (P + 1) <= rec_cap;
+    const double t2 = g.tol * g.tol;
+    const double Ts = g.t0 + g.h * s, Te = g.t0 + g.h * (s + 1);
+    const double w2 = 0.5 * (Te - Ts);
+
+    // this segment's ephemeris records into LDS (perturber data per node, Sec. 5.4.1)
+    const double4* grec = reinterpret_cast<const double4*>(p.recs) +
+                          (size_t)(g.rec_offset + (int64_t)s * N) * (P + 1);
+    if (rec_lds) {
+        for (int i = tid; i < N * (P + 1); i += NT) {
+            const double4 q = grec[i];
+            sm.Rec[3 * i + 0] = q.x;
+            sm.Rec[3 * i + 1] = q.y;
+            sm.Rec[3 * i + 2] = q.z;
+            if (i < P) sm.Mu[i] = q.w;
+        }
+    }
+    // initial guess at every (node, IC) pair: warm (Kepler) or cold start, Sec. 2.1,
+    // staged through the F area as [node][comp 6][IC]
+    {
+        const int pm = tid % T;
+        double y0[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) y0[c] = sY0[c * T + pm];
+        const bool warm = p.init == 0 && !sm.Dead[pm];
+#pragma unroll 1
+        for (int pr = tid; pr < PAIRS; pr += NT) {
+            const int j = pr / T;
+            double y[6];
+            if (!(j < N && warm && pc_kepler(y0, w2 * (g.tau[j < N ? j : 0] + 1.0), y))) {
+#pragma unroll
+                for (int c = 0; c < 6; ++c) y[c] = y0[c];
+            }
+            double* dst = sF + j * ROW + pm;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) dst[c * T] = y[c];
+        }
+    }
+    __syncthreads();
+    pc_load_share<PAIRS, NP>(static_cast<const double*>(sF), ROW, T, yc, L, N);
+    if (tid < T) sm.Active[tid] = (tid < n) && !sm.Dead[tid];
+    __syncthreads();   // staging read before F is rebuilt
+    for (int i = tid; i < 6 * PAIRS; i += NT) sF[i] = 0.0;
+    __syncthreads();
+    // precision schedule (uniform per job): FP32 sweeps first when asked, then FP64
+    bool fp32 = p.precision == 1;
+    int n32 = 0;
+    if (sm.Active[L.my_m]) {
+        if (fp32) pc_publish<PAIRS, NP, true>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
+        else pc_publish<PAIRS, NP>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
+    }
+    __syncthreads();
+
+    gconst_fp kp0f = (gconst_fp)g.kfrag32 + (size_t)L.strip0 * NQ * 64 + L.lane;
+    const int n_it = p.fixed_iters > 0 ? p.fixed_iters : p.max_iter;
+    for (int it = 1; it <= n_it; ++it) {
+        // (1)-(2) product and stopping-rule flags
+        f64x4 acc[6];
+        const int flag = fp32 ? pc_product<PAIRS, NP, true>(sF, sY0, kp0, kp0f, yc, acc, w2, t2, p.switch2,
+                                                              p.tol_mode, N, L)
+                              : pc_product<PAIRS, NP, false>(sF, sY0, kp0, kp0f, yc, acc, w2, t2, p.switch2,
+                                                               p.tol_mode, N, L);
+        if (L.lane < 16) sm.Flag[L.wave * 16 + L.lane] = flag;
+        const int act = sm.Active[L.my_m];
+        const unsigned long long keep = __ballot(act && (flag & 4));
+        if (L.lane == 0) sm.Keep[L.wave] = keep != 0ull;
+        __syncthreads();   // every wave is done reading F; flags complete
+
+        // the job leaves FP32 once no iterating IC changes by more than the switch threshold
+        bool next32 = false;
+        if (fp32) {
+            int k = 0;
+            for (int w = 0; w < Sh::W; ++w) k |= sm.Keep[w];
+            ++n32;
+            next32 = k && n32 < p.max_fp32;
+        }
+        // (3) stopping rule per IC (Sec. 2.2; per-block error of Sec. 3.2 with blocks of one IC);
+        //     not applied to FP32 sweeps
+        if (tid < T && sm.Active[tid]) {
+            const int f = pc_gather_flags<PAIRS, NP>(sm.Flag, tid);
+            int rec = 0;
+            if (f & 2) rec = -2;
+            else if (p.fixed_iters > 0) rec = (it == p.fixed_iters) ? it : 0;
+            else if (!fp32 && !(f & 1)) rec = it;
+            else if (it == p.max_iter) rec = -1;
+            if (rec != 0) {
+                sm.Active[tid] = 0;
+                if (rec == -2) sm.Dead[tid] = 1;
+                if (rec == -1) had_notconv = 1;
+                if (tid < n && iters_out) iters_out[(size_t)ic * p.iters_stride + s] = rec;
+            }
+        }
+        // (4) ICs that were iterating take the new iterate and publish its F
+        if (act) {
+#pragma unroll
+            for (int b = 0; b < 6; ++b) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) yc[b][r] = acc[b][r];
+            }
+            if (it < n_it) {
+                if (next32) pc_publish<PAIRS, NP, true>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
+                else pc_publish<PAIRS, NP>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
+            }
+        }
+        fp32 = next32;
+        const int any = __syncthreads_or(tid < T ? sm.Active[tid] : 0);
+        if (!any) break;
+    }
+}
+
 // Not inlined: one register allocation per node count, so the work-queue kernel that
 // dispatches to all of them does not pay for the largest one everywhere.
 template <int PAIRS, int NP>
@@ -83,18 +211,14 @@ __device__ __attribute__((noinline)) void pc_job(const PcParams& p, const PcJobD
 {
     PcSmem<PAIRS>& sm = pc_smem<PAIRS>();
     using Sh = PcShape<PAIRS, NP>;
-    constexpr int NT = Sh::NT, T = Sh::T, ROW = Sh::ROW, NQ = Sh::NQ;
+    constexpr int T = Sh::T, NQ = Sh::NQ;
 
-    double* sF = sm.F;
     double* sY0 = sm.Y0;
     const int tid = threadIdx.x;
     const PcLane L = pc_lane_geometry<PAIRS, NP>(tid);
     const int N = g.N, S = g.S;
     const int n = job.n;
-    const int P = p.n_pert;
     const int64_t ic = job.ic0 + tid;      // this thread's IC when tid < n
-    const bool rec_lds = N * 3 * (P + 1) <= PcSmem<PAIRS>::REC;
-    const double t2 = g.tol * g.tol;
 
     if (tid < T) {
         const double* y = p.ics + (job.ic0 + (tid < n ? tid : 0)) * 6;
@@ -112,9 +236,6 @@ __device__ __attribute__((noinline)) void pc_job(const PcParams& p, const PcJobD
     double yc[6][4];       // the lane's share of the current iterate
     int had_notconv = 0;
     for (int s = 0; s < S; ++s) {
-        const double Ts = g.t0 + g.h * s, Te = g.t0 + g.h * (s + 1);
-        const double w2 = 0.5 * (Te - Ts);
-
         if (tid < n) {
             if (p.bounds_out) {
                 double* bo = p.bounds_out + ((size_t)ic * (p.iters_stride + 1) + s) * 6;
@@ -122,109 +243,7 @@ __device__ __attribute__((noinline)) void pc_job(const PcParams& p, const PcJobD
             }
             if (sm.Dead[tid] && p.iters_out) p.iters_out[(size_t)ic * p.iters_stride + s] = -2;
         }
-        // this segment's ephemeris records into LDS (perturber data per node, Sec. 5.4.1)
-        const double4* grec = reinterpret_cast<const double4*>(p.recs) +
-                              (size_t)(g.rec_offset + (int64_t)s * N) * (P + 1);
-        if (rec_lds) {
-            for (int i = tid; i < N * (P + 1); i += NT) {
-                const double4 q = grec[i];
-                sm.Rec[3 * i + 0] = q.x;
-                sm.Rec[3 * i + 1] = q.y;
-                sm.Rec[3 * i + 2] = q.z;
-                if (i < P) sm.Mu[i] = q.w;
-            }
-        }
-        // initial guess at every (node, IC) pair: warm (Kepler) or cold start, Sec. 2.1,
-        // staged through the F area as [node][comp 6][IC]
-        {
-            const int pm = tid % T;
-            double y0[6];
-#pragma unroll
-            for (int c = 0; c < 6; ++c) y0[c] = sY0[c * T + pm];
-            const bool warm = p.init == 0 && !sm.Dead[pm];
-#pragma unroll 1
-            for (int pr = tid; pr < PAIRS; pr += NT) {
-                const int j = pr / T;
-                double y[6];
-                if (!(j < N && warm && pc_kepler(y0, w2 * (g.tau[j < N ? j : 0] + 1.0), y))) {
-#pragma unroll
-                    for (int c = 0; c < 6; ++c) y[c] = y0[c];
-                }
-                double* dst = sF + j * ROW + pm;
-#pragma unroll
-                for (int c = 0; c < 6; ++c) dst[c * T] = y[c];
-            }
-        }
-        __syncthreads();
-        pc_load_share<PAIRS, NP>(static_cast<const double*>(sF), ROW, T, yc, L, N);
-        if (tid < T) sm.Active[tid] = (tid < n) && !sm.Dead[tid];
-        __syncthreads();   // staging read before F is rebuilt
-        for (int i = tid; i < 6 * PAIRS; i += NT) sF[i] = 0.0;
-        __syncthreads();
-        // precision schedule (uniform per job): FP32 sweeps first when asked, then FP64
-        bool fp32 = p.precision == 1;
-        int n32 = 0;
-        if (sm.Active[L.my_m]) {
-            if (fp32) pc_publish<PAIRS, NP, true>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
-            else pc_publish<PAIRS, NP>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
-        }
-        __syncthreads();
-
-        gconst_fp kp0f = (gconst_fp)g.kfrag32 + (size_t)L.strip0 * NQ * 64 + L.lane;
-        const int n_it = p.fixed_iters > 0 ? p.fixed_iters : p.max_iter;
-        for (int it = 1; it <= n_it; ++it) {
-            // (1)-(2) product and stopping-rule flags
-            f64x4 acc[6];
-            const int flag = fp32 ? pc_product<PAIRS, NP, true>(sF, sY0, kp0, kp0f, yc, acc, w2, t2, p.switch2,
-                                                                  p.tol_mode, N, L)
-                                  : pc_product<PAIRS, NP, false>(sF, sY0, kp0, kp0f, yc, acc, w2, t2, p.switch2,
-                                                                   p.tol_mode, N, L);
-            if (L.lane < 16) sm.Flag[L.wave * 16 + L.lane] = flag;
-            const int act = sm.Active[L.my_m];
-            const unsigned long long keep = __ballot(act && (flag & 4));
-            if (L.lane == 0) sm.Keep[L.wave] = keep != 0ull;
-            __syncthreads();   // every wave is done reading F; flags complete
-
-            // the job leaves FP32 once no iterating IC changes by more than the switch threshold
-            bool next32 = false;
-            if (fp32) {
-                int k = 0;
-                for (int w = 0; w < Sh::W; ++w) k |= sm.Keep[w];
-                ++n32;
-                next32 = k && n32 < p.max_fp32;
-            }
-            // (3) stopping rule per IC (Sec. 2.2; per-block error of Sec. 3.2 with blocks of one IC);
-            //     not applied to FP32 sweeps
-            if (tid < T && sm.Active[tid]) {
-                const int f = pc_gather_flags<PAIRS, NP>(sm.Flag, tid);
-                int rec = 0;
-                if (f & 2) rec = -2;
-                else if (p.fixed_iters > 0) rec = (it == p.fixed_iters) ? it : 0;
-                else if (!fp32 && !(f & 1)) rec = it;
-                else if (it == p.max_iter) rec = -1;
-                if (rec != 0) {
-                    sm.Active[tid] = 0;
-                    if (rec == -2) sm.Dead[tid] = 1;
-                    if (rec == -1) had_notconv = 1;
-                    if (tid < n && p.iters_out) p.iters_out[(size_t)ic * p.iters_stride + s] = rec;
-                }
-            }
-            // (4) ICs that were iterating take the new iterate and publish its F
-            if (act) {
-#pragma unroll
-                for (int b = 0; b < 6; ++b) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) yc[b][r] = acc[b][r];
-                }
-                if (it < n_it) {
-                    if (next32) pc_publish<PAIRS, NP, true>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
-                    else pc_publish<PAIRS, NP>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
-                }
-            }
-            fp32 = next32;
-            const int any = __syncthreads_or(tid < T ? sm.Active[tid] : 0);
-            if (!any) break;
-        }
+        pc_segment_solve<PAIRS, NP>(p, g, n, job.ic0, s, sm, L, kp0, yc, p.iters_out, had_notconv);
 
         // converged node states of the segment (optional output), chaining (Sec. 2.2)
         const bool dead = sm.Dead[L.my_m];
@@ -321,6 +340,233 @@ int pc_launch_fused(const PcParams& p, int pairs, int grid, void* stream)
         hipLaunchKernelGGL(pc_fused_kernel<1024>, dim3(grid), dim3(256), 0, st, p);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of the converged map (reverse sweep over segments)
+// ---------------------------------------------------------------------------
+// For a segment with converged node states Y = 1 y0^T + K G(Y), G_j = w2 f(Y_j, t_j), the
+// derivative of a loss L(Y) with seed gbar = dL/dY is dL/dy0 = sum_j mu_j, where mu solves
+// (I - K J)^T mu = gbar with J_j = w2 df/dy (implicit differentiation of the fixed point).
+// mu is found by the adjoint fixed-point sweep mu <- gbar + J^T (K^T mu), which contracts
+// like the forward Picard iteration; with f = (v, a(r)) and H = da/dr symmetric,
+//   (J^T w)_r = w2 H w_v,   (J^T w)_v = w2 w_r.
+// Segments are processed from the last: each is first re-solved from its checkpoint (the
+// same forward code, so the same converged states), and its gradient seeds the end node of
+// the previous one.  Only WIDE job shapes (NP <= 128) run the adjoint.
+template <int PAIRS, int NP>
+__device__ __attribute__((noinline)) void pc_adjoint_job(const PcAdjParams& a, const PcJobDev& job,
+                                                         const PcGroupDev& g)
+{
+    using Sh = PcShape<PAIRS, NP>;
+    constexpr int NT = Sh::NT, T = Sh::T, ROW = Sh::ROW, NQ = Sh::NQ, W = Sh::W;
+    PcSmem<PAIRS>& sm = pc_smem<PAIRS>();
+    const PcParams& p = a.fwd;
+    double* sF = sm.F;
+    double* sY0 = sm.Y0;
+    const int tid = threadIdx.x;
+    const PcLane L = pc_lane_geometry<PAIRS, NP>(tid);
+    const int N = g.N, S = g.S, P = p.n_pert;
+    const int n = job.n;
+    const int64_t ic = job.ic0 + tid;
+    // adjoint scratch at the top of the record area: seed Lam, estimate LamIt, partial sums
+    constexpr int ADJ = 12 * T + W * 6 * 16;
+    constexpr int REC_CAP = PcSmem<PAIRS>::REC - ADJ;
+    double* sLam = sm.Rec + REC_CAP;
+    double* sLamIt = sLam + 6 * T;
+    double* sLamPart = sLamIt + 6 * T;
+    const bool rec_lds = N * 3 * (P + 1) <= REC_CAP;
+    const double t2a = a.adj_tol * a.adj_tol;
+
+    if (tid < T) {
+        for (int c = 0; c < 6; ++c) sLam[c * T + tid] = tid < n ? a.gbar_final[(size_t)ic * 6 + c] : 0.0;
+    }
+    gconst_dp kp0 = (gconst_dp)g.kfrag + (size_t)L.strip0 * NQ * 64 + L.lane;
+    gconst_dp kpT = (gconst_dp)g.kfragT + (size_t)L.strip0 * NQ * 64 + L.lane;
+    double yc[6][4];
+    int had_notconv = 0, adj_notconv = 0, dead_any = 0;
+    for (int s = S - 1; s >= 0; --s) {
+        // re-solve segment s from its checkpoint
+        if (tid < T) {
+            const double* src = a.ckpt + ((size_t)(job.ic0 + (tid < n ? tid : 0)) * (a.ckpt_stride + 1) + s) * 6;
+            bool fin = true;
+            for (int c = 0; c < 6; ++c) {
+                const double v = src[c];
+                sY0[c * T + tid] = v;
+                fin = fin && isfinite(v);
+            }
+            sm.Dead[tid] = !fin;
+        }
+        __syncthreads();
+        pc_segment_solve<PAIRS, NP>(p, g, n, job.ic0, s, sm, L, kp0, yc, nullptr, had_notconv, REC_CAP);
+        __syncthreads();
+        const double Ts = g.t0 + g.h * s, Te = g.t0 + g.h * (s + 1);
+        const double w2 = 0.5 * (Te - Ts);
+        const double4* grec = reinterpret_cast<const double4*>(p.recs) +
+                              (size_t)(g.rec_offset + (int64_t)s * N) * (P + 1);
+
+        // seed of this segment at the lane's nodes: the next segment's gradient at the end
+        // node, plus the node seeds when given (recomputed where needed, not held)
+        int jr[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = pc_node(L, 0, r);
+            jr[r] = j < N ? j : N - 1;
+        }
+        const double* gnode = (a.gbar_nodes && L.my_m < n)
+                                  ? a.gbar_nodes + ((size_t)(job.ic0 + L.my_m) * a.ckpt_stride + s) * a.nodes_stride * 6
+                                  : nullptr;
+        auto seed = [&](int c, int r) -> double {
+            const int j = pc_node(L, 0, r);
+            double v = (j == N - 1) ? sLam[c * T + L.my_m] : 0.0;
+            if (gnode && j < N) v += gnode[j * 6 + c];
+            return v;
+        };
+        for (int i = tid; i < 6 * PAIRS; i += NT) sF[i] = 0.0;
+        if (tid < T) {
+            sm.Active[tid] = (tid < n) && !sm.Dead[tid];
+            for (int c = 0; c < 6; ++c) sLamIt[c * T + tid] = 0.0;
+        }
+        __syncthreads();
+        // mu^(0) = gbar
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = pc_node(L, 0, r);
+            if (j < N) {
+#pragma unroll
+                for (int c = 0; c < 6; ++c) sF[j * ROW + c * T + L.my_m] = seed(c, r);
+            }
+        }
+        __syncthreads();
+
+        int it = 1;
+        for (; it <= a.adj_max_iter; ++it) {
+            f64x4 acc[6];
+            pc_product_adj<PAIRS, NP>(sF, kpT, acc, L);          // w = K^T mu
+            double wx[4], wy[4], wz[4], hx[4], hy[4], hz[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                wx[r] = acc[3][r];
+                wy[r] = acc[4][r];
+                wz[r] = acc[5][r];
+            }
+            if (rec_lds)
+                pc_hess_apply<4, true>(yc[0], yc[1], yc[2], wx, wy, wz, jr, P, p.mu_sun, sm.Rec, sm.Mu, grec,
+                                       hx, hy, hz);
+            else
+                pc_hess_apply<4, false>(yc[0], yc[1], yc[2], wx, wy, wz, jr, P, p.mu_sun, sm.Rec, sm.Mu, grec,
+                                        hx, hy, hz);
+            // mu_new = gbar + J^T w, and its sum over the lane's nodes
+            double part[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = pc_node(L, 0, r);
+                const double nv0 = seed(3, r) + w2 * acc[0][r];
+                const double nv1 = seed(4, r) + w2 * acc[1][r];
+                const double nv2 = seed(5, r) + w2 * acc[2][r];
+                acc[0][r] = seed(0, r) + w2 * hx[r];
+                acc[1][r] = seed(1, r) + w2 * hy[r];
+                acc[2][r] = seed(2, r) + w2 * hz[r];
+                acc[3][r] = nv0;
+                acc[4][r] = nv1;
+                acc[5][r] = nv2;
+                if (j < N) {
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) part[c] += acc[c][r];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                part[c] += __shfl_xor(part[c], 16);
+                part[c] += __shfl_xor(part[c], 32);
+            }
+            if (L.lane < 16) {
+#pragma unroll
+                for (int c = 0; c < 6; ++c) sLamPart[(L.wave * 6 + c) * 16 + L.lane] = part[c];
+            }
+            const int act = sm.Active[L.my_m];
+            __syncthreads();   // K^T mu read by every wave; partial sums complete
+
+            // gradient estimate lambda = sum_j mu_j per IC; stop when it no longer changes
+            if (tid < T && sm.Active[tid]) {
+                double ln[6], d2 = 0.0, n2 = 0.0;
+                for (int c = 0; c < 6; ++c) {
+                    double v = 0.0;
+                    for (int w = tid >> 4; w < W; w += Sh::G16) v += sLamPart[(w * 6 + c) * 16 + (tid & 15)];
+                    ln[c] = v;
+                    const double d = v - sLamIt[c * T + tid];
+                    d2 += d * d;
+                    n2 += v * v;
+                    sLamIt[c * T + tid] = v;
+                }
+                int rec = 0;
+                if (!isfinite(n2)) rec = -2;
+                else if (it > 1 && d2 <= t2a * n2) rec = it;
+                else if (it == a.adj_max_iter) rec = -1;
+                if (rec != 0) {
+                    sm.Active[tid] = 0;
+                    if (rec == -2) sm.Dead[tid] = 1;
+                    if (rec == -1) adj_notconv = 1;
+                    if (tid < n && a.adj_iters) a.adj_iters[(size_t)ic * a.ckpt_stride + s] = rec;
+                }
+            }
+            if (act) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int j = pc_node(L, 0, r);
+                    if (j < N) {
+#pragma unroll
+                        for (int c = 0; c < 6; ++c) sF[j * ROW + c * T + L.my_m] = acc[c][r];
+                    }
+                }
+            }
+            const int any = __syncthreads_or(tid < T ? sm.Active[tid] : 0);
+            if (!any) break;
+        }
+        // this segment's gradient seeds the end node of the previous one
+        if (tid < T) {
+            const bool dead = sm.Dead[tid];
+            dead_any |= dead;
+            for (int c = 0; c < 6; ++c) sLam[c * T + tid] = dead ? (double)NAN : sLamIt[c * T + tid];
+        }
+        __syncthreads();
+    }
+    if (tid < n) {
+        for (int c = 0; c < 6; ++c) a.grad_out[(size_t)ic * 6 + c] = sLam[c * T + tid];
+        if (adj_notconv || had_notconv) atomicAdd(&a.counters[0], 1);
+        if (dead_any) atomicAdd(&a.counters[1], 1);
+    }
+    __syncthreads();
+}
+
+template <int PAIRS>
+__global__ __launch_bounds__(PAIRS / 4) void pc_adjoint_kernel(const PcAdjParams a)
+{
+    __shared__ int sJob;
+    for (;;) {
+        if (threadIdx.x == 0) sJob = atomicAdd(a.counters + 2, 1);
+        __syncthreads();
+        const int jb = sJob;
+        __syncthreads();
+        if (jb >= a.fwd.n_jobs) break;
+        const PcJobDev job = a.fwd.jobs[jb];
+        const PcGroupDev g = a.fwd.groups[job.group];
+        switch (g.NP) {
+        case 16: pc_adjoint_job<PAIRS, 16>(a, job, g); break;
+        case 32: pc_adjoint_job<PAIRS, 32>(a, job, g); break;
+        case 64: pc_adjoint_job<PAIRS, 64>(a, job, g); break;
+        case 128: pc_adjoint_job<PAIRS, 128>(a, job, g); break;
+        default: break;
+        }
+    }
+}
+
+int pc_launch_adjoint(const PcAdjParams& a, int grid, void* stream)
+{
+    if (a.fwd.n_jobs <= 0) return hipSuccess;
+    if (grid <= 0 || grid > a.fwd.n_jobs) grid = a.fwd.n_jobs;
+    hipLaunchKernelGGL(pc_adjoint_kernel<2048>, dim3(grid), dim3(512), 0, (hipStream_t)stream, a);
     return hipGetLastError();
 }
 

@@ -61,7 +61,8 @@ _lib = None
 EXPORTS = ("pc_default_opts", "pc_ctx_create", "pc_ctx_destroy", "pc_workspace_bytes",
            "pc_propagate", "pc_propagate_batched", "pc_get_operator", "pc_apply_operator",
            "pc_eval_force", "pc_eval_kepler", "pc_set_timing", "pc_last_kernel_ms", "pc_autotune",
-           "pc_set_tile_pairs", "pc_get_tile_pairs", "pc_strerror", "pc_last_error", "pc_version")
+           "pc_set_tile_pairs", "pc_get_tile_pairs", "pc_adjoint", "pc_strerror", "pc_last_error",
+           "pc_version")
 
 
 def load_library(path: str = LIB_PATH):
@@ -94,6 +95,9 @@ def load_library(path: str = LIB_PATH):
     lib.pc_autotune.argtypes = [_vp, _vp, ctypes.c_int64, P(_Group), ctypes.c_int32, P(_Model), _vp, _vp,
                                 ctypes.c_size_t, _vp, P(ctypes.c_int32)]
     lib.pc_set_tile_pairs.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32]
+    lib.pc_adjoint.argtypes = [_vp, ctypes.c_int64, P(_Group), ctypes.c_int32, P(_Model), P(_Opts), _vp,
+                               ctypes.c_int32, _vp, _vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                               _vp, _vp, _vp, ctypes.c_size_t, _vp]
     lib.pc_get_tile_pairs.argtypes = [_vp, ctypes.c_int32, P(ctypes.c_int32)]
     lib.pc_set_timing.argtypes = [_vp, ctypes.c_int]
     lib.pc_last_kernel_ms.argtypes = [_vp, ctypes.POINTER(ctypes.c_double)]
@@ -281,6 +285,43 @@ class Context:
         if rc != PC_OK:
             self._raise(rc)
         return chosen.value
+
+    def adjoint(self, ckpt, gbar_final, groups, model=None, gbar_nodes=None, adj_tol=1e-12,
+                adj_max_iter=200, raise_on_status=False, **opts):
+        """pc_adjoint: dL/dy0 [n, 6] from the forward call's segment-boundary states ``ckpt``
+        [n, S+1, 6] and the seeds dL/d(final state) [n, 6] (and dL/d(node states)
+        [n, S, N, 6]).  Returns (grad, adjoint sweeps per segment [n, S], status)."""
+        model = model or Model()
+        _check_tensor(ckpt, "ckpt")
+        _check_tensor(gbar_final, "gbar_final")
+        n = ckpt.shape[0]
+        S_max = max(g.segments for g in groups)
+        N_max = max(g.nodes for g in groups)
+        if ckpt.shape != (n, S_max + 1, 6) or gbar_final.shape != (n, 6):
+            raise ValueError("ckpt must be [n, S+1, 6] and gbar_final [n, 6]")
+        if gbar_nodes is not None:
+            _check_tensor(gbar_nodes, "gbar_nodes", (n, S_max, N_max, 6))
+        garr = (_Group * len(groups))(*[_Group(g.ic_offset, g.n_ic, g.t0, g.tf, g.nodes, g.segments, g.tol)
+                                       for g in groups])
+        mc, oc = model._c(), self.opts(**opts)
+        oc.tile_pairs = 2048
+        nb = ctypes.c_size_t()
+        rc = self.lib.pc_workspace_bytes(self.handle, garr, len(groups), ctypes.byref(mc), ctypes.byref(oc),
+                                         ctypes.byref(nb))
+        if rc != PC_OK:
+            self._raise(rc)
+        ws = self.workspace(nb.value)
+        grad = torch.empty((n, 6), dtype=torch.float64, device=ckpt.device)
+        adj_it = torch.zeros((n, S_max), dtype=torch.int32, device=ckpt.device)
+        rc = self.lib.pc_adjoint(self.handle, n, garr, len(groups), ctypes.byref(mc), ctypes.byref(oc),
+                                 ctypes.c_void_p(ckpt.data_ptr()), S_max, ctypes.c_void_p(gbar_final.data_ptr()),
+                                 ctypes.c_void_p(gbar_nodes.data_ptr() if gbar_nodes is not None else 0), N_max,
+                                 float(adj_tol), int(adj_max_iter), ctypes.c_void_p(grad.data_ptr()),
+                                 ctypes.c_void_p(adj_it.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                 _stream_ptr(ckpt.device))
+        if rc not in (PC_OK, PC_ENOTCONV, PC_ENONFINITE) or (raise_on_status and rc != PC_OK):
+            self._raise(rc)
+        return grad, adj_it, rc
 
     def tile_pairs(self, padded_nodes):
         v = ctypes.c_int32()

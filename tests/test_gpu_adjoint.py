@@ -1,0 +1,159 @@
+"""Adjoint (reverse-mode gradient through the converged propagation) on the GPU against
+the oracle's implicit derivative of the discrete fixed point (a dense linear solve per
+segment, itself pinned by finite differences and a variational STM in the CPU suite).
+
+Bar: per-IC relative gradient error (2-norm over the six components) <= 1e-8; the forward
+re-solve converges to 1e-13 and the adjoint sweeps to 1e-13, so the two derivatives are
+taken at iterates that differ by ~1e-13.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2301_03989_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GTOL = 1e-8
+
+
+@pytest.fixture(scope="module")
+def pc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2301_03989_amd import build, pcprop
+    build.ensure_built()
+    return pcprop.Context(0)
+
+
+def _setup(w):
+    from paper_2301_03989_amd import pcprop
+    g = w.groups[0]
+    ics = torch.tensor(w.ics, dtype=torch.float64, device="cuda")
+    groups = [pcprop.Group(0, w.n_ic, g.t0, g.tf, g.nodes, g.segments, g.tol)]
+    return ics, groups, pcprop.Model(1.0, w.pert, 0.0), oracle.Model(1.0, w.pert, 0.0), g
+
+
+def _gerr(a, b):
+    return np.linalg.norm(a - b, axis=1) / np.linalg.norm(b, axis=1)
+
+
+def test_adjoint_final_state_matches_oracle(pc):
+    w = W.nbody_venus(24, seed=105, days=76.8, segments=3, nodes=64, tol=1e-13)
+    ics, groups, model, om, g = _setup(w)
+    fwd = pc.propagate_batched(ics, groups, model, want_bounds=True)
+    assert fwd["status"] == 0
+    gbar = np.random.default_rng(1).standard_normal((w.n_ic, 6))
+    grad, adj_it, st = pc.adjoint(fwd["bounds"], torch.tensor(gbar, device="cuda"), groups, model)
+    assert st == 0 and (adj_it.cpu().numpy() > 1).all()
+    ref = oracle.adjoint(w.ics, g.t0, g.tf, g.nodes, g.segments, g.tol, om, gbar)
+    assert _gerr(grad.cpu().numpy(), ref).max() < GTOL
+
+
+def test_adjoint_node_seeds_match_oracle(pc):
+    w = W.nbody_venus(10, seed=106, days=51.2, segments=2, nodes=48, tol=1e-13)
+    ics, groups, model, om, g = _setup(w)
+    fwd = pc.propagate_batched(ics, groups, model, want_bounds=True)
+    rng = np.random.default_rng(4)
+    gn = np.zeros((w.n_ic, 2, 48, 6))
+    gn[:, 0, 7] = rng.standard_normal((w.n_ic, 6))
+    gn[:, 1, 30] = rng.standard_normal((w.n_ic, 6))
+    gbar = np.zeros((w.n_ic, 6))
+    grad, _, st = pc.adjoint(fwd["bounds"], torch.tensor(gbar, device="cuda"), groups, model,
+                             gbar_nodes=torch.tensor(gn, device="cuda"))
+    assert st == 0
+    ref = oracle.adjoint(w.ics, g.t0, g.tf, g.nodes, g.segments, g.tol, om, gbar, gn)
+    assert _gerr(grad.cpu().numpy(), ref).max() < GTOL
+
+
+def test_autograd_function(pc):
+    from paper_2301_03989_amd import autograd
+    w = W.nbody_venus(16, seed=107, days=51.2, segments=2, nodes=64, tol=1e-13)
+    ics, groups, model, om, g = _setup(w)
+    x = ics.clone().requires_grad_(True)
+    c = torch.tensor(np.random.default_rng(5).standard_normal((w.n_ic, 6)), device="cuda")
+    states = autograd.propagate(x, groups, model, pc=pc)
+    loss = (states * c).sum()
+    (gx,) = torch.autograd.grad(loss, x)
+    ref = oracle.adjoint(w.ics, g.t0, g.tf, g.nodes, g.segments, g.tol, om, c.cpu().numpy())
+    assert _gerr(gx.cpu().numpy(), ref).max() < GTOL
+
+
+def _venus_min_seeds(nodes, w, om, g, tau):
+    """Seeds of L = min over the CGL nodes of |r - r_Venus| (the discrete minimum, with the
+    minimising node held fixed): dL/dr at that node = (r - r_V)/|r - r_V|."""
+    n, S, N, _ = nodes.shape
+    h = (g.tf - g.t0) / S
+    gn = np.zeros_like(nodes)
+    dmin = np.zeros(n)
+    for m in range(n):
+        best = (np.inf, 0, 0)
+        for s in range(S):
+            for j in range(N):
+                t = g.t0 + h * s + 0.5 * h * (tau[j] + 1.0)
+                d = nodes[m, s, j, :3] - oracle.ephem(w.pert[1], 0.0, t)
+                dn = np.linalg.norm(d)
+                if dn < best[0]:
+                    best = (dn, s, j, d)
+        dmin[m] = best[0]
+        gn[m, best[1], best[2], :3] = best[3] / best[0]
+    return gn, dmin
+
+
+def test_min_venus_distance_gradient(pc):
+    w = W.nbody_venus(6, seed=108, days=153.6, segments=3, nodes=64, tol=1e-13)
+    ics, groups, model, om, g = _setup(w)
+    fwd = pc.propagate_batched(ics, groups, model, want_bounds=True, want_nodes=True)
+    tau = oracle.nodes(g.nodes)
+    gn, dmin = _venus_min_seeds(fwd["nodes"].cpu().numpy(), w, om, g, tau)
+    gbar = np.zeros((w.n_ic, 6))
+    grad, _, st = pc.adjoint(fwd["bounds"], torch.tensor(gbar, device="cuda"), groups, model,
+                             gbar_nodes=torch.tensor(gn, device="cuda"))
+    assert st == 0
+    ref = oracle.adjoint(w.ics, g.t0, g.tf, g.nodes, g.segments, g.tol, om, gbar, gn)
+    assert _gerr(grad.cpu().numpy(), ref).max() < GTOL
+    # and against central differences of the oracle's objective (minimising node held fixed)
+    hstep = 1e-6
+    sel = np.argwhere(gn[..., 0] != 0)
+    for m in range(2):
+        _, s_, j_ = sel[sel[:, 0] == m][0]
+        t = g.t0 + (g.tf - g.t0) / g.segments * s_ + 0.5 * (g.tf - g.t0) / g.segments * (tau[j_] + 1.0)
+        rv = oracle.ephem(w.pert[1], 0.0, t)
+        fd = np.zeros(6)
+        for k in range(6):
+            e = np.zeros(6)
+            e[k] = hstep
+            _, _, npl = oracle.propagate(w.ics[m:m + 1] + e, g.t0, g.tf, g.nodes, g.segments, g.tol, om,
+                                         fixed_iters=40, want_nodes=True)
+            _, _, nmi = oracle.propagate(w.ics[m:m + 1] - e, g.t0, g.tf, g.nodes, g.segments, g.tol, om,
+                                         fixed_iters=40, want_nodes=True)
+            fd[k] = (np.linalg.norm(npl[0, s_, j_, :3] - rv) - np.linalg.norm(nmi[0, s_, j_, :3] - rv)) / (2 * hstep)
+        assert np.linalg.norm(grad.cpu().numpy()[m] - fd) / np.linalg.norm(fd) < 1e-6
+
+
+def test_adjoint_full_size_sampled(pc):
+    """The 16384-IC, 256-day, 5-segment, 128-node ensemble: every IC's gradient is computed on
+    the GPU; 4 of them are checked against the oracle."""
+    w = W.adjoint_ensemble()
+    ics, groups, model, om, g = _setup(w)
+    fwd = pc.propagate_batched(ics, groups, model, want_bounds=True)
+    assert fwd["status"] == 0
+    gbar = np.zeros((w.n_ic, 6))
+    gbar[:, 0] = 1.0                         # d x_final / d y0
+    grad, adj_it, st = pc.adjoint(fwd["bounds"], torch.tensor(gbar, device="cuda"), groups, model)
+    assert st == 0
+    gr = grad.cpu().numpy()
+    assert np.isfinite(gr).all()
+    idx = np.array([0, 5000, 11111, w.n_ic - 1])
+    ref = oracle.adjoint(w.ics[idx], g.t0, g.tf, g.nodes, g.segments, g.tol, om, gbar[idx])
+    assert _gerr(gr[idx], ref).max() < GTOL
+
+
+def test_adjoint_argument_errors(pc):
+    from paper_2301_03989_amd import pcprop
+    w = W.nbody_venus(4, nodes=256, days=30.0, segments=1)
+    ics, groups, model, om, g = _setup(w)
+    fwd = pc.propagate_batched(ics, groups, model, want_bounds=True)
+    with pytest.raises(pcprop.PcError):
+        pc.adjoint(fwd["bounds"], torch.zeros((4, 6), dtype=torch.float64, device="cuda"), groups, model)
