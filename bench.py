@@ -24,6 +24,43 @@ sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
 METRIC = "IC-segment propagations/s at <=1e-10 rel err; batched/mixed vs plain GPU speedup"
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def kernel_source_hash():
+    """sha256 over the HIP sources and the ABI header, in a fixed order: the identity of
+    the kernels a counter summary was taken on."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2301_03989_amd", "csrc", "*")))
+    files.append(os.path.join(ROOT, "include", "pcprop.h"))
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of ``kernel`` on ``workload`` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size), or None when there is
+    none or the kernels have changed since it was taken."""
+    path = os.path.join(PROFILES, f"{kernel}.{workload}.traffic.md")
+    if not os.path.exists(path):
+        return None, "no counter summary"
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            m = line.strip().lstrip("-* ").split(":", 1)
+            if len(m) == 2:
+                vals[m[0].strip().strip("`")] = m[1].strip().strip("`")
+    if vals.get("source_sha256") != kernel_source_hash():
+        return None, "kernels changed since the counters were taken"
+    try:
+        return float(vals["traffic_bytes_per_launch"]), path
+    except (KeyError, ValueError):
+        return None, "malformed counter summary"
 
 
 def algorithmic_flops(w, iters):
@@ -63,12 +100,124 @@ def oracle_states(w, idx):
     return out, iters, oracle.propagate.last_threads
 
 
+def adjoint_flops(w, iters, adj_iters):
+    """Algorithmic FP64 work of one adjoint call: the forward re-solve of every segment
+    (as algorithmic_flops) plus, per adjoint sweep, the transposed product (6 columns x
+    2 N^2) and the Hessian-vector products H w_v at N nodes (30 flops per body: offset,
+    distance powers, the projection d (d.w) and the accumulation) and the 12 flops that
+    form mu_new."""
+    P = w.pert.shape[0]
+    total = algorithmic_flops(w, iters)
+    for g in w.groups:
+        it = adj_iters[g.ic_offset:g.ic_offset + g.n_ic, :g.segments]
+        it = np.where(it > 0, it, 0).astype(np.float64)
+        N = g.nodes
+        total += (12.0 * N * N + (30.0 * (P + 1) + 12.0) * N) * it.sum()
+    return total
+
+
+def run_adjoint(args):
+    """Forward propagation with segment checkpoints, then the adjoint of the final state
+    (seed: a fixed random dL/dy_final per IC); one step = both calls."""
+    import torch
+
+    import oracle
+    from paper_2301_03989_amd import pcprop, workloads
+    w = workloads.WORKLOADS[args.workload or "nbody-venus-16384-256d"]()
+    n_ic = w.n_ic
+    ic_segments = sum(g.n_ic * g.segments for g in w.groups)
+    ctx = pcprop.Context(0)
+    ctx.set_timing(True)
+    ics = torch.tensor(w.ics, dtype=torch.float64, device="cuda")
+    groups = [pcprop.Group(g.ic_offset, g.n_ic, g.t0, g.tf, g.nodes, g.segments, g.tol) for g in w.groups]
+    model = pcprop.Model(w.mu_sun, w.pert, w.epoch)
+    gbar_np = np.random.default_rng(7).standard_normal((n_ic, 6))
+    gbar = torch.tensor(gbar_np, dtype=torch.float64, device="cuda")
+
+    def step():
+        f = ctx.propagate_batched(ics, groups, model, want_bounds=True, tile_pairs=2048)
+        fwd_ms = ctx.last_kernel_ms()
+        grad, adj_it, st = ctx.adjoint(f["bounds"], gbar, groups, model)
+        return f, grad, adj_it, st, fwd_ms, ctx.last_kernel_ms()
+
+    print(f"bench: adjoint of {w.name}: {n_ic} ICs, {ic_segments} IC-segments", flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    fwd_ms, adj_ms = [], []
+    e0.record()
+    for _ in range(args.steps):
+        f, grad, adj_it, st, fm, am = step()
+        fwd_ms.append(fm)
+        adj_ms.append(am)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_per_step = e0.elapsed_time(e1) / args.steps
+    iters = f["iters"].cpu().numpy()
+    ait = adj_it.cpu().numpy()
+    g_np = grad.cpu().numpy()
+    print(f"bench: {ms_per_step:.3f} ms/step (forward kernel {np.mean(fwd_ms):.3f} ms, adjoint kernel "
+          f"{np.mean(adj_ms):.3f} ms)", flush=True)
+
+    g0 = w.groups[0]
+    idx = np.unique(np.linspace(0, n_ic - 1, max(1, min(args.check_ics, 4))).astype(np.int64))
+    om = oracle.Model(w.mu_sun, w.pert, w.epoch)
+    ref = oracle.adjoint(w.ics[idx], g0.t0, g0.tf, g0.nodes, g0.segments, g0.tol, om, gbar_np[idx])
+    gerr = np.linalg.norm(g_np[idx] - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    valid = bool(gerr.max() <= 1e-8 and st == 0 and f["status"] == 0)
+    print(f"bench: max rel gradient err vs oracle on {idx.size} ICs: {gerr.max():.3e}", flush=True)
+
+    flops = adjoint_flops(w, iters, ait)
+    kms = float(np.mean(adj_ms))
+    achieved = flops / (kms * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                "traffic_source": "not collected for the adjoint kernel",
+                "kernel": "pc_adjoint_kernel", "kernel_ms": round(kms, 4), "flops_per_launch": flops}
+    cpu = None
+    if not args.no_cpu_baseline:
+        rng = np.random.default_rng(0)
+        t0 = time.perf_counter()
+        probe = np.sort(rng.choice(n_ic, size=1, replace=False))
+        oracle.adjoint(w.ics[probe], g0.t0, g0.tf, g0.nodes, g0.segments, g0.tol, om, gbar_np[probe])
+        per_ic = time.perf_counter() - t0
+        k = int(min(n_ic, max(1, args.cpu_seconds / max(per_ic, 1e-9))))
+        sample = np.sort(rng.choice(n_ic, size=k, replace=False))
+        t0 = time.perf_counter()
+        oracle.adjoint(w.ics[sample], g0.t0, g0.tf, g0.nodes, g0.segments, g0.tol, om, gbar_np[sample])
+        dt = time.perf_counter() - t0
+        threads = oracle.propagate.last_threads
+        cpu = {"value": round(k * g0.segments / dt, 3), "unit": "IC-segment gradients/s", "cores": int(threads),
+               "kind": "oracle",
+               "sample": f"{k} of {n_ic} ICs, forward + dense implicit-derivative solve per segment, "
+                         f"{dt:.1f} s wall (propagation on {threads} threads, solves on numpy's BLAS)"}
+    line = {
+        "metric": METRIC + " (forward + adjoint)",
+        "value": round(ic_segments / (ms_per_step * 1e-3), 3) if valid else None,
+        "unit": "IC-segment gradients/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name, "n_ic": n_ic, "segments": g0.segments, "nodes": g0.nodes, "tol": g0.tol,
+                   "perturbers": int(w.pert.shape[0]), "seed": "random dL/dy_final", "checkpoints": "segment bounds"},
+        "accuracy": {"max_rel_grad_err_vs_oracle": float(gerr.max()), "checked_ics": int(idx.size),
+                     "status_forward": int(f["status"]), "status_adjoint": int(st),
+                     "mean_adjoint_sweeps_per_segment": round(float(ait[ait > 0].mean()), 3),
+                     "mean_iterations_per_segment": round(float(iters[iters > 0].mean()), 3)},
+        "forward_kernel_ms": round(float(np.mean(fwd_ms)), 4),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="nbody-venus-4096")
+    ap.add_argument("--workload", default=None, help="default nbody-venus-4096")
     ap.add_argument("--tile-pairs", type=int, default=0)
     ap.add_argument("--graph", action="store_true", help="replay the call as a captured HIP graph")
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32-fp64"],
@@ -80,6 +229,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain-steps", type=int, default=3,
                     help="steps of the per-iteration (plain) path timed for the speedup; 0 skips")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="time forward (with checkpoints) + adjoint of the final state; default "
+                         "workload then nbody-venus-16384-256d")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -108,7 +260,11 @@ def main():
         print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes}), flush=True)
         return
 
-    w = workloads.WORKLOADS[args.workload]()
+    if args.adjoint:
+        run_adjoint(args)
+        return
+
+    w = workloads.WORKLOADS[args.workload or "nbody-venus-4096"]()
     n_ic = w.n_ic
     ic_segments = sum(g.n_ic * g.segments for g in w.groups)
     ctx = pcprop.Context(0)
@@ -203,8 +359,11 @@ def main():
     flops = algorithmic_flops(w, iters)
     kms = float(np.mean(kernel_ms))
     achieved = flops / (kms * 1e-3) / 1e12
+    traffic, traffic_src = measured_traffic("pc_fused_kernel", w.name) if precision == "fp64" else \
+        (None, "counters taken on the FP64 path only")
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": traffic,
+                "traffic_source": os.path.relpath(traffic_src, ROOT) if traffic is not None else traffic_src,
                 "kernel": "pc_fused_kernel", "kernel_ms": round(kms, 4),
                 "flops_per_launch": flops}
 
