@@ -253,7 +253,7 @@ struct Plan {
     int64_t n_recs = 0;
     int max_S = 0, max_N = 0;
     // workspace offsets
-    size_t off_counters = 0, off_groups = 0, off_jobs = 0, off_bodies = 0, off_recs = 0, total = 0;
+    size_t off_counters = 0, off_params = 0, off_groups = 0, off_jobs = 0, off_bodies = 0, off_recs = 0, total = 0;
     size_t staged = 0;   // bytes of [counters .. bodies] copied from the staging buffer
 };
 
@@ -365,6 +365,7 @@ int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, c
     const int P = model->n_pert;
     size_t off = 0;
     plan.off_counters = off; off = align_up(off + 4 * sizeof(int32_t));   // 2 counters + queue head
+    plan.off_params = off;   off = align_up(off + std::max(sizeof(PcParams), sizeof(PcAdjParams)));
     plan.off_groups = off;   off = align_up(off + plan.groups.size() * sizeof(PcGroupDev));
     plan.off_jobs = off;     off = align_up(off + plan.jobs.size() * sizeof(PcJobDev));
     plan.off_bodies = off;   off = align_up(off + std::max(1, P) * sizeof(PcBodyDev));
@@ -569,6 +570,8 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_
     }
     pp.counters = reinterpret_cast<int32_t*>(ws + plan.off_counters);
     pp.queue = pp.counters + 2;
+    std::memcpy(st + plan.off_params, &pp, sizeof(pp));   // the device copy the kernel reads
+    const PcParams* pp_dev = reinterpret_cast<const PcParams*>(ws + plan.off_params);
     int32_t* hc = reinterpret_cast<int32_t*>(st);   // staging is free again once the copy has run
 
     int grid = 1;
@@ -582,7 +585,7 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_
         hipError_t e = hipMemcpyAsync(ws, st, plan.staged, hipMemcpyHostToDevice, sq);
         if (e == hipSuccess) e = (hipError_t)pc_launch_ephem(ep, sq);
         if (e == hipSuccess && events) e = hipEventRecord(ctx->ev0, sq);
-        if (e == hipSuccess) e = (hipError_t)pc_launch_fused(pp, plan.pairs, grid, sq);
+        if (e == hipSuccess) e = (hipError_t)pc_launch_fused(pp, pp_dev, plan.pairs, grid, sq);
         if (e == hipSuccess && events) e = hipEventRecord(ctx->ev1, sq);
         if (e == hipSuccess) e = hipMemcpyAsync(hc, pp.counters, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, sq);
         return e;
@@ -741,7 +744,6 @@ int pc_adjoint(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int32_t n_grou
     prepare_bodies(model, reinterpret_cast<PcBodyDev*>(st + plan.off_bodies));
     char* ws = static_cast<char*>(workspace);
     hipStream_t hs = (hipStream_t)stream;
-    PC_HIP(ctx, hipMemcpyAsync(ws, st, plan.staged, hipMemcpyHostToDevice, hs));
     PcEphemParams ep{};
     ep.groups = reinterpret_cast<const PcGroupDev*>(ws + plan.off_groups);
     ep.n_groups = (int)plan.groups.size();
@@ -750,7 +752,6 @@ int pc_adjoint(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int32_t n_grou
     ep.n_pert = model->n_pert;
     ep.epoch = model->epoch;
     ep.recs = reinterpret_cast<double*>(ws + plan.off_recs);
-    PC_HIP(ctx, (hipError_t)pc_launch_ephem(ep, hs));
 
     PcAdjParams a{};
     a.fwd.groups = ep.groups;
@@ -777,8 +778,12 @@ int pc_adjoint(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int32_t n_grou
     a.grad_out = grad_ics;
     a.adj_iters = adj_iters;
     a.counters = reinterpret_cast<int32_t*>(ws + plan.off_counters);
+    std::memcpy(st + plan.off_params, &a, sizeof(a));   // the device copy the kernel reads
+    const PcAdjParams* a_dev = reinterpret_cast<const PcAdjParams*>(ws + plan.off_params);
+    PC_HIP(ctx, hipMemcpyAsync(ws, st, plan.staged, hipMemcpyHostToDevice, hs));
+    PC_HIP(ctx, (hipError_t)pc_launch_ephem(ep, hs));
     if (ctx->timing) PC_HIP(ctx, hipEventRecord(ctx->ev0, hs));
-    PC_HIP(ctx, (hipError_t)pc_launch_adjoint(a, ctx->n_cu, hs));
+    PC_HIP(ctx, (hipError_t)pc_launch_adjoint(a, a_dev, ctx->n_cu, hs));
     if (ctx->timing) PC_HIP(ctx, hipEventRecord(ctx->ev1, hs));
     int32_t* hc = reinterpret_cast<int32_t*>(st);
     PC_HIP(ctx, hipMemcpyAsync(hc, a.counters, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, hs));

@@ -43,7 +43,7 @@ static __device__ double pc_ecc_anomaly(double M, double e)
         sincos(E, &sE, &cE);
         const double dE = (E - e * sE - Mr) / (1.0 - e * cE);
         E -= dE;
-        if (fabs(dE) <= 1e-16 * (1.0 + fabs(E))) break;
+        if (fabs(dE) <= 1e-10 * (1.0 + fabs(E))) break;   // quadratic: the next error is ~dE^2
     }
     return E;
 }
@@ -61,14 +61,26 @@ static __device__ void pc_body_position(const PcBodyDev& B, double dt_epoch, dou
 // Warm start (Sec. 2.1): propagate y0 by dt on its osculating ellipse, through the
 // Lagrange coefficients f, g, fdot, gdot written in the eccentric-anomaly change x:
 //   x - (1 - r0/a) sin x + (r0.v0/sqrt(a)) (1 - cos x) = n dt.
-// Returns false for non-elliptic or degenerate states.
-static __device__ __attribute__((noinline)) bool pc_kepler(const double y0[6], double dt, double y[6])
+// Newton converges quadratically: with F' >= 1 - e and |F''| <= e, a step below 1e-10
+// leaves an error below e/(2(1-e)) 1e-20, far under one ulp, so the loop stops there.
+// The state goes in and out by value (registers, no stack traffic); a non-elliptic or
+// degenerate state returns NaN components.
+struct PcState6 {
+    double c[6];
+};
+
+static __device__ __attribute__((noinline)) PcState6 pc_kepler_state(PcState6 s0, double dt)
 {
+    const double* y0 = s0.c;
+    PcState6 out;
     const double r0n = sqrt(y0[0] * y0[0] + y0[1] * y0[1] + y0[2] * y0[2]);
     const double v02 = y0[3] * y0[3] + y0[4] * y0[4] + y0[5] * y0[5];
-    if (!(r0n > 0.0) || !isfinite(r0n) || !isfinite(v02)) return false;
     const double alpha = 2.0 / r0n - v02;          // 1/a
-    if (!(alpha > 0.0)) return false;
+    if (!(r0n > 0.0) || !isfinite(r0n) || !isfinite(v02) || !(alpha > 0.0)) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) out.c[k] = (double)NAN;
+        return out;
+    }
     const double a = 1.0 / alpha;
     const double sqa = sqrt(a);
     const double n = alpha * sqrt(alpha);          // mean motion
@@ -83,7 +95,7 @@ static __device__ __attribute__((noinline)) bool pc_kepler(const double y0[6], d
         const double F = x - ec * sx + es * (1.0 - cx) - ndt;
         const double dx = F / (1.0 - ec * cx + es * sx);
         x -= dx;
-        if (fabs(dx) <= 1e-16 * (1.0 + fabs(x))) break;
+        if (fabs(dx) <= 1e-10 * (1.0 + fabs(x))) break;
     }
     double sx, cx;
     sincos(x, &sx, &cx);
@@ -92,11 +104,26 @@ static __device__ __attribute__((noinline)) bool pc_kepler(const double y0[6], d
     const double g = dt - (x - sx) / n;
     const double fd = -sqa * sx / (rn * r0n);
     const double gd = 1.0 - (a / rn) * (1.0 - cx);
-    bool ok = true;
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
-        y[k] = f * y0[k] + g * y0[3 + k];
-        y[3 + k] = fd * y0[k] + gd * y0[3 + k];
-        ok = ok && isfinite(y[k]) && isfinite(y[3 + k]);
+        out.c[k] = f * y0[k] + g * y0[3 + k];
+        out.c[3 + k] = fd * y0[k] + gd * y0[3 + k];
+    }
+    return out;
+}
+
+// Array form of the warm start; false when the result is not finite (y then unspecified).
+static __device__ __forceinline__ bool pc_kepler(const double (&y0)[6], double dt, double (&y)[6])
+{
+    PcState6 s0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) s0.c[k] = y0[k];
+    const PcState6 r = pc_kepler_state(s0, dt);
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        y[k] = r.c[k];
+        ok = ok && isfinite(r.c[k]);
     }
     return ok;
 }
@@ -356,6 +383,44 @@ static __device__ __forceinline__ int pc_node(const PcLane& L, int h, int r)
     return (L.strip0 + h) * 16 + (L.lane >> 4) + 4 * r;
 }
 
+// Software-pipelined k loop of a 16x16x4 product over NQ steps.  The A operand of step q
+// (a K_N fragment, read from L2) is loaded DK steps ahead into a ring of DK registers, the
+// B operands (LDS) one step ahead into two buffers, and the loop body is unrolled DK
+// times, so both rings rotate by register renaming.  A register move out of a ring would
+// make the wave wait for the load it copies right after issuing it.
+template <int NQ, int NB, class AT, class BT, class LA, class LB, class MM>
+static __device__ __forceinline__ void pc_kloop(LA loadA, LB loadB, MM mma)
+{
+    constexpr int DK = 4;
+    static_assert(NQ % DK == 0, "k steps must be a multiple of the A ring depth");
+    AT ka[DK];
+    BT bb[2][NB];
+#pragma unroll
+    for (int u = 0; u < DK; ++u) ka[u] = loadA(u);
+    loadB(0, bb[0]);
+#pragma unroll 1
+    for (int q0 = 0; q0 < NQ - DK; q0 += DK) {
+#pragma unroll
+        for (int u = 0; u < DK; ++u) {
+            loadB(q0 + u + 1, bb[(u + 1) & 1]);
+            mma(ka[u], bb[u & 1]);
+            ka[u] = loadA(q0 + u + DK);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < DK; ++u) {   // the last DK steps load nothing past the end
+        if (u + 1 < DK) loadB(NQ - DK + u + 1, bb[(u + 1) & 1]);
+        mma(ka[u], bb[u & 1]);
+    }
+}
+
+struct PcPairD {
+    double a0, a1;
+};
+struct PcPairF {
+    float a0, a1;
+};
+
 // y_new = y0 + w2 K_N F on the matrix cores (Sec. 2.2 with A, C and S folded into K_N) for
 // the lane's six blocks, FP64 or (FP32) FP32 products accumulated into FP64; acc receives
 // y_new.  Also evaluates the stopping rule of Sec. 2.2 against the previous iterate yc in
@@ -382,39 +447,31 @@ static __device__ __forceinline__ int pc_product(const double* sF, const double*
         for (int b = 0; b < 6; ++b) accf[b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
         if constexpr (Sh::WIDE) {
             const double* bp = sF + (lane >> 4) * ROW + L.grp * 16 + (lane & 15);
-            float bc[6], bn[6];
-            float ka = kp0f[0], kb = (NQ > 1) ? kp0f[64] : 0.0f;
+            pc_kloop<NQ, 6, float, float>(
+                [&](int q) { return kp0f[q * 64]; },
+                [&](int q, float (&bq)[6]) {
 #pragma unroll
-            for (int b = 0; b < 6; ++b) bc[b] = (float)bp[b * T];
-#pragma unroll 2
-            for (int q = 0; q < NQ; ++q) {
-                const float kn = (q + 2 < NQ) ? kp0f[(q + 2) * 64] : 0.0f;
-                if (q + 1 < NQ) {
+                    for (int b = 0; b < 6; ++b) bq[b] = (float)bp[q * 4 * ROW + b * T];
+                },
+                [&](float ka, const float (&bq)[6]) {
 #pragma unroll
-                    for (int b = 0; b < 6; ++b) bn[b] = (float)bp[(q + 1) * 4 * ROW + b * T];
-                }
-#pragma unroll
-                for (int b = 0; b < 6; ++b) accf[b] = mfma16f(ka, bc[b], accf[b]);
-#pragma unroll
-                for (int b = 0; b < 6; ++b) bc[b] = bn[b];
-                ka = kb;
-                kb = kn;
-            }
+                    for (int b = 0; b < 6; ++b) accf[b] = mfma16f(ka, bq[b], accf[b]);
+                });
         } else {
             gconst_fp kp1f = kp0f + (size_t)NQ * 64;
             const double* bp = sF + (lane >> 4) * ROW + (lane & 15);
-#pragma unroll 4
-            for (int q = 0; q < NQ; ++q) {
-                const float a0 = kp0f[q * 64], a1 = kp1f[q * 64];
-                const double* bq = bp + q * 4 * ROW;
-                const float b0 = (float)bq[0], b1 = (float)bq[16], b2 = (float)bq[32];
-                accf[0] = mfma16f(a0, b0, accf[0]);
-                accf[1] = mfma16f(a0, b1, accf[1]);
-                accf[2] = mfma16f(a0, b2, accf[2]);
-                accf[3] = mfma16f(a1, b0, accf[3]);
-                accf[4] = mfma16f(a1, b1, accf[4]);
-                accf[5] = mfma16f(a1, b2, accf[5]);
-            }
+            pc_kloop<NQ, 3, PcPairF, float>(
+                [&](int q) { return PcPairF{kp0f[q * 64], kp1f[q * 64]}; },
+                [&](int q, float (&bq)[3]) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) bq[c] = (float)bp[q * 4 * ROW + 16 * c];
+                },
+                [&](const PcPairF& ka, const float (&bq)[3]) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) accf[c] = mfma16f(ka.a0, bq[c], accf[c]);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) accf[3 + c] = mfma16f(ka.a1, bq[c], accf[3 + c]);
+                });
         }
 #pragma unroll
         for (int b = 0; b < 6; ++b) {
@@ -423,29 +480,19 @@ static __device__ __forceinline__ int pc_product(const double* sF, const double*
         }
     }
     if constexpr (Sh::WIDE) {
-        // K_N strip streamed from L2 two k-steps ahead; B operands one k-step ahead
-        const double* bp = sF + (lane >> 4) * ROW + L.grp * 16 + (lane & 15);
-        double bc[6], bn[6];
-        double ka = 0.0, kb = 0.0;
+        // K_N strip streamed from L2 four k-steps ahead; B operands one k-step ahead
         if constexpr (!FP32) {
-            ka = kp0[0];
-            kb = (NQ > 1) ? kp0[64] : 0.0;
+            const double* bp = sF + (lane >> 4) * ROW + L.grp * 16 + (lane & 15);
+            pc_kloop<NQ, 6, double, double>(
+                [&](int q) { return kp0[q * 64]; },
+                [&](int q, double (&bq)[6]) {
 #pragma unroll
-            for (int b = 0; b < 6; ++b) bc[b] = bp[b * T];
-        }
-#pragma unroll 2
-        for (int q = 0; q < (FP32 ? 0 : NQ); ++q) {
-            const double kn = (q + 2 < NQ) ? kp0[(q + 2) * 64] : 0.0;
-            if (q + 1 < NQ) {
+                    for (int b = 0; b < 6; ++b) bq[b] = bp[q * 4 * ROW + b * T];
+                },
+                [&](double ka, const double (&bq)[6]) {
 #pragma unroll
-                for (int b = 0; b < 6; ++b) bn[b] = bp[(q + 1) * 4 * ROW + b * T];
-            }
-#pragma unroll
-            for (int b = 0; b < 6; ++b) acc[b] = mfma16(ka, bc[b], acc[b]);
-#pragma unroll
-            for (int b = 0; b < 6; ++b) bc[b] = bn[b];
-            ka = kb;
-            kb = kn;
+                    for (int b = 0; b < 6; ++b) acc[b] = mfma16(ka, bq[b], acc[b]);
+                });
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -467,37 +514,21 @@ static __device__ __forceinline__ int pc_product(const double* sF, const double*
             }
         }
     } else {
-        gconst_dp kp1 = kp0 + (size_t)NQ * 64;
-        const double* bp = sF + (lane >> 4) * ROW + (lane & 15);
-        double a0 = 0.0, a1 = 0.0;
-        double a0n = 0.0, a1n = 0.0;
-        double b0 = 0.0, b1 = 0.0, b2 = 0.0;
         if constexpr (!FP32) {
-            a0 = kp0[0];
-            a1 = kp1[0];
-            b0 = bp[0];
-            b1 = bp[16];
-            b2 = bp[32];
-        }
-#pragma unroll 4
-        for (int q = 0; q < (FP32 ? 0 : NQ); ++q) {
-            double b0n = 0.0, b1n = 0.0, b2n = 0.0;
-            if (q + 1 < NQ) {
-                a0n = kp0[(q + 1) * 64];
-                a1n = kp1[(q + 1) * 64];
-                const double* bq = bp + (q + 1) * 4 * ROW;
-                b0n = bq[0];
-                b1n = bq[16];
-                b2n = bq[32];
-            }
-            acc[0] = mfma16(a0, b0, acc[0]);
-            acc[1] = mfma16(a0, b1, acc[1]);
-            acc[2] = mfma16(a0, b2, acc[2]);
-            acc[3] = mfma16(a1, b0, acc[3]);
-            acc[4] = mfma16(a1, b1, acc[4]);
-            acc[5] = mfma16(a1, b2, acc[5]);
-            a0 = a0n; a1 = a1n;
-            b0 = b0n; b1 = b1n; b2 = b2n;
+            gconst_dp kp1 = kp0 + (size_t)NQ * 64;
+            const double* bp = sF + (lane >> 4) * ROW + (lane & 15);
+            pc_kloop<NQ, 3, PcPairD, double>(
+                [&](int q) { return PcPairD{kp0[q * 64], kp1[q * 64]}; },
+                [&](int q, double (&bq)[3]) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) bq[c] = bp[q * 4 * ROW + 16 * c];
+                },
+                [&](const PcPairD& ka, const double (&bq)[3]) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) acc[c] = mfma16(ka.a0, bq[c], acc[c]);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) acc[3 + c] = mfma16(ka.a1, bq[c], acc[3 + c]);
+                });
         }
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -549,24 +580,16 @@ static __device__ __forceinline__ void pc_product_adj(const double* sF, gconst_d
 #pragma unroll
     for (int b = 0; b < 6; ++b) acc[b] = f64x4{0.0, 0.0, 0.0, 0.0};
     const double* bp = sF + (lane >> 4) * ROW + L.grp * 16 + (lane & 15);
-    double bc[6], bn[6];
-    double ka = kpT[0], kb = (NQ > 1) ? kpT[64] : 0.0;
+    pc_kloop<NQ, 6, double, double>(
+        [&](int q) { return kpT[q * 64]; },
+        [&](int q, double (&bq)[6]) {
 #pragma unroll
-    for (int b = 0; b < 6; ++b) bc[b] = bp[b * T];
-#pragma unroll 2
-    for (int q = 0; q < NQ; ++q) {
-        const double kn = (q + 2 < NQ) ? kpT[(q + 2) * 64] : 0.0;
-        if (q + 1 < NQ) {
+            for (int b = 0; b < 6; ++b) bq[b] = bp[q * 4 * ROW + b * T];
+        },
+        [&](double ka, const double (&bq)[6]) {
 #pragma unroll
-            for (int b = 0; b < 6; ++b) bn[b] = bp[(q + 1) * 4 * ROW + b * T];
-        }
-#pragma unroll
-        for (int b = 0; b < 6; ++b) acc[b] = mfma16(ka, bc[b], acc[b]);
-#pragma unroll
-        for (int b = 0; b < 6; ++b) bc[b] = bn[b];
-        ka = kb;
-        kb = kn;
-    }
+            for (int b = 0; b < 6; ++b) acc[b] = mfma16(ka, bq[b], acc[b]);
+        });
 }
 
 // OR of the per-wave flags of IC m (written as Flag[wave][lane] by lanes < 16).

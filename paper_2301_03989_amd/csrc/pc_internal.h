@@ -94,9 +94,12 @@ struct PcEphemParams {
 
 // Launchers (pc_kernels.hip).  All return a hipError_t as int.
 int pc_launch_ephem(const PcEphemParams& p, void* stream);
-int pc_launch_fused(const PcParams& p, int pairs, int grid, void* stream);
+// The launchers take the parameter block twice: by value for its host-side fields (job
+// count), and as a device copy (in the workspace, written by the call's table transfer)
+// that the kernels read, so that no lane keeps a private copy of it.
+int pc_launch_fused(const PcParams& p, const PcParams* p_dev, int pairs, int grid, void* stream);
 int pc_fused_occupancy(int pairs, int* blocks_per_cu);
-int pc_launch_adjoint(const PcAdjParams& a, int grid, void* stream);
+int pc_launch_adjoint(const PcAdjParams& a, const PcAdjParams* a_dev, int grid, void* stream);
 int pc_launch_apply_operator(int NP, const double* kfrag, int N, int64_t n_cols, const double* F,
                              const double* y0, double scale, double* Y, void* stream);
 int pc_launch_eval_force(const double* r, const double* t, int64_t n, const PcBodyDev* bodies,

@@ -296,15 +296,17 @@ __device__ __attribute__((noinline)) void pc_job(const PcParams& p, const PcJobD
 // all groups and node counts, longest first) until the queue is empty, so one launch
 // runs an uneven two-level batch (Sec. 3.2) to completion.
 template <int PAIRS>
-__global__ __launch_bounds__(PAIRS / 4) void pc_fused_kernel(const PcParams p)
+__global__ __launch_bounds__(PAIRS / 4) void pc_fused_kernel(const PcParams* __restrict__ pp)
 {
     __shared__ int sJob;
+    const PcParams& p = *pp;
     for (;;) {
         if (threadIdx.x == 0) sJob = atomicAdd(p.queue, 1);
         __syncthreads();
         const int jb = sJob;
         __syncthreads();
         if (jb >= p.n_jobs) break;
+        // private copies: with them the job bodies need not preserve the caller's registers
         const PcJobDev job = p.jobs[jb];
         const PcGroupDev g = p.groups[job.group];
         switch (g.NP) {
@@ -329,15 +331,15 @@ int pc_fused_occupancy(int pairs, int* blocks_per_cu)
     return hipErrorInvalidValue;
 }
 
-int pc_launch_fused(const PcParams& p, int pairs, int grid, void* stream)
+int pc_launch_fused(const PcParams& p, const PcParams* p_dev, int pairs, int grid, void* stream)
 {
     if (p.n_jobs <= 0) return hipSuccess;
     hipStream_t st = (hipStream_t)stream;
     if (grid <= 0 || grid > p.n_jobs) grid = p.n_jobs;
     if (pairs == 2048)
-        hipLaunchKernelGGL(pc_fused_kernel<2048>, dim3(grid), dim3(512), 0, st, p);
+        hipLaunchKernelGGL(pc_fused_kernel<2048>, dim3(grid), dim3(512), 0, st, p_dev);
     else if (pairs == 1024)
-        hipLaunchKernelGGL(pc_fused_kernel<1024>, dim3(grid), dim3(256), 0, st, p);
+        hipLaunchKernelGGL(pc_fused_kernel<1024>, dim3(grid), dim3(256), 0, st, p_dev);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -541,9 +543,10 @@ __device__ __attribute__((noinline)) void pc_adjoint_job(const PcAdjParams& a, c
 }
 
 template <int PAIRS>
-__global__ __launch_bounds__(PAIRS / 4) void pc_adjoint_kernel(const PcAdjParams a)
+__global__ __launch_bounds__(PAIRS / 4) void pc_adjoint_kernel(const PcAdjParams* __restrict__ ap)
 {
     __shared__ int sJob;
+    const PcAdjParams& a = *ap;
     for (;;) {
         if (threadIdx.x == 0) sJob = atomicAdd(a.counters + 2, 1);
         __syncthreads();
@@ -562,11 +565,11 @@ __global__ __launch_bounds__(PAIRS / 4) void pc_adjoint_kernel(const PcAdjParams
     }
 }
 
-int pc_launch_adjoint(const PcAdjParams& a, int grid, void* stream)
+int pc_launch_adjoint(const PcAdjParams& a, const PcAdjParams* a_dev, int grid, void* stream)
 {
     if (a.fwd.n_jobs <= 0) return hipSuccess;
     if (grid <= 0 || grid > a.fwd.n_jobs) grid = a.fwd.n_jobs;
-    hipLaunchKernelGGL(pc_adjoint_kernel<2048>, dim3(grid), dim3(512), 0, (hipStream_t)stream, a);
+    hipLaunchKernelGGL(pc_adjoint_kernel<2048>, dim3(grid), dim3(512), 0, (hipStream_t)stream, a_dev);
     return hipGetLastError();
 }
 
