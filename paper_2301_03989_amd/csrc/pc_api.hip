@@ -23,7 +23,8 @@ namespace {
 struct OperatorCache {
     int N = 0, NP = 0;
     double* kfrag = nullptr;   // device, [NP/16][NP/4][64]
-    float* kfrag32 = nullptr;  // device, FP32 fragments with rows permuted per strip
+    float* kfrag32 = nullptr;  // device, FP32 fragments in kfrag order
+    float* kfrag32p = nullptr; // device, FP32 fragments with rows permuted per strip
     double* kfragT = nullptr;  // device, fragments of K_N^T
     double* tau = nullptr;     // device, [NP]
     std::vector<double> K;     // host copy, [N][N]
@@ -143,9 +144,13 @@ int get_operator(pc_ctx* ctx, int N, const OperatorCache** out)
                 frag[((size_t)strip * NQ + q) * 64 + lane] =
                     (row < N && col < N) ? oc.K[(size_t)row * N + col] : 0.0;
             }
-    // FP32 fragments: the f32 16x16x4 MFMA returns row 4(l/16) + r in element r, the f64
-    // one row l/16 + 4r.  Feeding A row i from strip row perm(i) = (i/4) + 4 (i%4) puts the
-    // same node in the same lane and element for both precisions.
+    // FP32 fragments.  kfrag32 has the kfrag order: it is the B operand of the transposed
+    // product of jobs with 16 or more ICs.  kfrag32p serves the node-row layout of 8-IC
+    // jobs: the f32 16x16x4 MFMA returns row 4(l/16) + r in element r, the f64 one row
+    // l/16 + 4r, and feeding A row i from strip row perm(i) = (i/4) + 4 (i%4) puts the same
+    // node in the same lane and element for both precisions.
+    std::vector<float> frag32n((size_t)NP * NP, 0.0f);
+    for (size_t i = 0; i < frag.size(); ++i) frag32n[i] = (float)frag[i];
     std::vector<float> frag32((size_t)NP * NP, 0.0f);
     for (int strip = 0; strip < NP / 16; ++strip)
         for (int q = 0; q < NQ; ++q)
@@ -171,8 +176,10 @@ int get_operator(pc_ctx* ctx, int N, const OperatorCache** out)
     PC_HIP(ctx, hipMalloc(&oc.tau, tau.size() * sizeof(double)));
     PC_HIP(ctx, hipMalloc(&oc.kfragT, fragT.size() * sizeof(double)));
     PC_HIP(ctx, hipMemcpy(oc.kfragT, fragT.data(), fragT.size() * sizeof(double), hipMemcpyHostToDevice));
-    PC_HIP(ctx, hipMalloc(&oc.kfrag32, frag32.size() * sizeof(float)));
-    PC_HIP(ctx, hipMemcpy(oc.kfrag32, frag32.data(), frag32.size() * sizeof(float), hipMemcpyHostToDevice));
+    PC_HIP(ctx, hipMalloc(&oc.kfrag32, frag32n.size() * sizeof(float)));
+    PC_HIP(ctx, hipMemcpy(oc.kfrag32, frag32n.data(), frag32n.size() * sizeof(float), hipMemcpyHostToDevice));
+    PC_HIP(ctx, hipMalloc(&oc.kfrag32p, frag32.size() * sizeof(float)));
+    PC_HIP(ctx, hipMemcpy(oc.kfrag32p, frag32.data(), frag32.size() * sizeof(float), hipMemcpyHostToDevice));
     PC_HIP(ctx, hipMemcpy(oc.kfrag, frag.data(), frag.size() * sizeof(double), hipMemcpyHostToDevice));
     PC_HIP(ctx, hipMemcpy(oc.tau, tau.data(), tau.size() * sizeof(double), hipMemcpyHostToDevice));
     auto res = ctx->ops.emplace(N, std::move(oc));
@@ -332,6 +339,7 @@ int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, c
             if (rc != PC_OK) return rc;
             d.kfrag = oc->kfrag;
             d.kfrag32 = oc->kfrag32;
+            d.kfrag32p = oc->kfrag32p;
             d.kfragT = oc->kfragT;
             d.tau = oc->tau;
         }
@@ -460,6 +468,7 @@ void pc_ctx_destroy(pc_ctx* ctx)
         (void)hipFree(kv.second.kfrag);
         (void)hipFree(kv.second.tau);
         (void)hipFree(kv.second.kfrag32);
+        (void)hipFree(kv.second.kfrag32p);
         (void)hipFree(kv.second.kfragT);
     }
     if (ctx->staging) (void)hipHostFree(ctx->staging);

@@ -128,6 +128,17 @@ static __device__ __forceinline__ bool pc_kepler(const double (&y0)[6], double d
     return ok;
 }
 
+// 1/sqrt(x) in full FP64 for finite x > 0: the hardware estimate y refined by one
+// third-order step y (1 + e/2 + 3 e^2/8), e = 1 - x y^2 (the series of (1 - e)^(-1/2)).
+// No fix-up for x = 0 or x = inf: a zero distance or an infinite position gives a
+// non-finite result either way, and the stopping rule flags it.
+static __device__ __forceinline__ double pc_rsqrt(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-(x * y), y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
 // ---------------------------------------------------------------------------
 // Force model: point masses in the heliocentric frame with the indirect term,
 //   a = -mu_S r/|r|^3 - sum_p mu_p (r - r_p)/|r - r_p|^3 - sum_p mu_p r_p/|r_p|^3.
@@ -138,7 +149,7 @@ static __device__ __forceinline__ void pc_accel(double x, double y, double z, co
                                                 double& az)
 {
     const double r2 = x * x + y * y + z * z;
-    const double ir = rsqrt(r2);
+    const double ir = pc_rsqrt(r2);
     const double s = mu_sun * (ir * ir * ir);
     ax = -s * x;
     ay = -s * y;
@@ -146,7 +157,7 @@ static __device__ __forceinline__ void pc_accel(double x, double y, double z, co
     for (int p = 0; p < P; ++p) {
         const double4 q = rec[p];
         const double dx = x - q.x, dy = y - q.y, dz = z - q.z;
-        const double id = rsqrt(dx * dx + dy * dy + dz * dz);
+        const double id = pc_rsqrt(dx * dx + dy * dy + dz * dz);
         const double sd = q.w * (id * id * id);
         ax -= sd * dx;
         ay -= sd * dy;
@@ -189,7 +200,7 @@ static __device__ __forceinline__ void pc_force_lds(const double (&x)[R], const 
     const int stride = 3 * (P + 1);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const double ir = rsqrt(x[r] * x[r] + y[r] * y[r] + z[r] * z[r]);
+        const double ir = pc_rsqrt(x[r] * x[r] + y[r] * y[r] + z[r] * z[r]);
         const double s = mu_sun * (ir * ir * ir);
         ax[r] = -s * x[r];
         ay[r] = -s * y[r];
@@ -201,7 +212,7 @@ static __device__ __forceinline__ void pc_force_lds(const double (&x)[R], const 
         for (int r = 0; r < R; ++r) {
             const double* q = srec + jr[r] * stride + 3 * b;
             const double dx = x[r] - q[0], dy = y[r] - q[1], dz = z[r] - q[2];
-            const double id = rsqrt(dx * dx + dy * dy + dz * dz);
+            const double id = pc_rsqrt(dx * dx + dy * dy + dz * dz);
             const double sd = mu * (id * id * id);
             ax[r] -= sd * dx;
             ay[r] -= sd * dy;
@@ -267,7 +278,7 @@ static __device__ __forceinline__ void pc_force_glb(const double (&x)[R], const 
 {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const double ir = rsqrt(x[r] * x[r] + y[r] * y[r] + z[r] * z[r]);
+        const double ir = pc_rsqrt(x[r] * x[r] + y[r] * y[r] + z[r] * z[r]);
         const double s = mu_sun * (ir * ir * ir);
         ax[r] = -s * x[r];
         ay[r] = -s * y[r];
@@ -280,7 +291,7 @@ static __device__ __forceinline__ void pc_force_glb(const double (&x)[R], const 
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const double dx = x[r] - q[r].x, dy = y[r] - q[r].y, dz = z[r] - q[r].z;
-            const double id = rsqrt(dx * dx + dy * dy + dz * dz);
+            const double id = pc_rsqrt(dx * dx + dy * dy + dz * dz);
             const double sd = q[r].w * (id * id * id);
             ax[r] -= sd * dx;
             ay[r] -= sd * dy;
@@ -310,7 +321,7 @@ static __device__ __forceinline__ void pc_hess_apply(const double (&x)[R], const
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const double d2 = x[r] * x[r] + y[r] * y[r] + z[r] * z[r];
-        const double id = rsqrt(d2);
+        const double id = pc_rsqrt(d2);
         const double i3 = id * id * id, i5 = i3 * id * id;
         const double dw = 3.0 * i5 * (x[r] * wx[r] + y[r] * wy[r] + z[r] * wz[r]);
         hx[r] = -mu_sun * (i3 * wx[r] - dw * x[r]);
@@ -332,7 +343,7 @@ static __device__ __forceinline__ void pc_hess_apply(const double (&x)[R], const
                 mu = q.w;
             }
             const double dx = x[r] - qx, dy = y[r] - qy, dz = z[r] - qz;
-            const double id = rsqrt(dx * dx + dy * dy + dz * dz);
+            const double id = pc_rsqrt(dx * dx + dy * dy + dz * dz);
             const double i3 = id * id * id, i5 = i3 * id * id;
             const double dw = 3.0 * i5 * (dx * wx[r] + dy * wy[r] + dz * wz[r]);
             hx[r] -= mu * (i3 * wx[r] - dw * dx);
@@ -343,9 +354,12 @@ static __device__ __forceinline__ void pc_hess_apply(const double (&x)[R], const
 }
 
 // Shape of a job: PAIRS = NP x T (node, IC) pairs, NT threads in W waves; every wave owns
-// six 16x16 blocks of the iterate.  WIDE (T >= 16): one 16-row strip x the six component
-// blocks of one 16-IC group.  Otherwise (T == 8): two strips x three blocks of two
-// components x 8 ICs; lane l holds components hi, 2+hi, 4+hi of IC l%8 (hi = bit 3 of l).
+// six 16x16 blocks of the iterate.  WIDE (T >= 16): one 16-node strip x the six component
+// blocks of one 16-IC group, computed transposed (IC rows, node columns), so that lane l
+// holds node l%16 of the strip for ICs l/16 + 4r, r = 0..3 (one node per lane: the force
+// reads each perturber record once for its four points).  Otherwise (T == 8): two strips
+// x three blocks of two components x 8 ICs, node rows; lane l holds nodes l/16 + 4r and
+// components hi, 2+hi, 4+hi of IC l%8 (hi = bit 3 of l).
 template <int PAIRS, int NP>
 struct PcShape {
     static constexpr int NT = PAIRS / 4;
@@ -360,7 +374,9 @@ struct PcShape {
 };
 
 struct PcLane {
-    int lane, wave, strip0, grp, my_m, hi;
+    int lane, wave, strip0, grp, hi;
+    int wide;
+    int ic_base, ic_step;   // the lane's element r belongs to IC ic_base + ic_step r of the job
 };
 
 template <int PAIRS, int NP>
@@ -372,15 +388,42 @@ static __device__ __forceinline__ PcLane pc_lane_geometry(int tid)
     L.wave = tid >> 6;
     L.strip0 = Sh::WIDE ? L.wave / Sh::G16 : 2 * L.wave;
     L.grp = Sh::WIDE ? L.wave - L.strip0 * Sh::G16 : 0;
-    L.my_m = Sh::WIDE ? L.grp * 16 + (L.lane & 15) : (L.lane & 7);
     L.hi = Sh::WIDE ? 0 : (L.lane >> 3) & 1;
+    L.wide = Sh::WIDE;
+    L.ic_base = Sh::WIDE ? L.grp * 16 + (L.lane >> 4) : (L.lane & 7);
+    L.ic_step = Sh::WIDE ? 4 : 0;
     return L;
 }
 
-// node of the lane's element r in strip h (MFMA f64 result layout: row l/16 + 4r)
+// node of the lane's element r in strip h (MFMA f64 result layout: D[l/16 + 4r][l%16];
+// WIDE blocks are transposed, so their node is the column l%16)
 static __device__ __forceinline__ int pc_node(const PcLane& L, int h, int r)
 {
-    return (L.strip0 + h) * 16 + (L.lane >> 4) + 4 * r;
+    return L.wide ? L.strip0 * 16 + (L.lane & 15) : (L.strip0 + h) * 16 + (L.lane >> 4) + 4 * r;
+}
+
+// IC (index within the job) of the lane's element r
+static __device__ __forceinline__ int pc_ic(const PcLane& L, int r)
+{
+    return L.ic_base + L.ic_step * r;
+}
+
+// IC whose stopping-rule flag lane l < 16 returns from pc_product: grp * 16 + l (WIDE),
+// l % 8 (T == 8)
+template <int PAIRS, int NP>
+static __device__ __forceinline__ int pc_flag_ic(const PcLane& L)
+{
+    return PcShape<PAIRS, NP>::WIDE ? L.grp * 16 + (L.lane & 15) : (L.lane & 7);
+}
+
+// Column of IC m in node row j of the LDS force array F[node][comp][IC].  WIDE jobs XOR
+// the IC's place in its 16-IC group with j % 16: a row is 6T doubles, a multiple of the
+// bank count, so without it the 16 lanes of a row group (one node each, same IC) would
+// all hit one bank.  Readers of a 16-column group still see a permutation of it.
+template <int PAIRS, int NP>
+static __device__ __forceinline__ int pc_fcol(int j, int m)
+{
+    return PcShape<PAIRS, NP>::WIDE ? (m ^ (j & 15)) : m;
 }
 
 // Software-pipelined k loop of a 16x16x4 product over NQ steps.  The A operand of step q
@@ -388,6 +431,7 @@ static __device__ __forceinline__ int pc_node(const PcLane& L, int h, int r)
 // B operands (LDS) one step ahead into two buffers, and the loop body is unrolled DK
 // times, so both rings rotate by register renaming.  A register move out of a ring would
 // make the wave wait for the load it copies right after issuing it.
+// loadB(q, q % 4, buffer) gets the phase as a compile-time constant after unrolling.
 template <int NQ, int NB, class AT, class BT, class LA, class LB, class MM>
 static __device__ __forceinline__ void pc_kloop(LA loadA, LB loadB, MM mma)
 {
@@ -397,19 +441,19 @@ static __device__ __forceinline__ void pc_kloop(LA loadA, LB loadB, MM mma)
     BT bb[2][NB];
 #pragma unroll
     for (int u = 0; u < DK; ++u) ka[u] = loadA(u);
-    loadB(0, bb[0]);
+    loadB(0, 0, bb[0]);
 #pragma unroll 1
     for (int q0 = 0; q0 < NQ - DK; q0 += DK) {
 #pragma unroll
         for (int u = 0; u < DK; ++u) {
-            loadB(q0 + u + 1, bb[(u + 1) & 1]);
+            loadB(q0 + u + 1, (u + 1) & 3, bb[(u + 1) & 1]);
             mma(ka[u], bb[u & 1]);
             ka[u] = loadA(q0 + u + DK);
         }
     }
 #pragma unroll
     for (int u = 0; u < DK; ++u) {   // the last DK steps load nothing past the end
-        if (u + 1 < DK) loadB(NQ - DK + u + 1, bb[(u + 1) & 1]);
+        if (u + 1 < DK) loadB(NQ - DK + u + 1, (u + 1) & 3, bb[(u + 1) & 1]);
         mma(ka[u], bb[u & 1]);
     }
 }
@@ -425,8 +469,10 @@ struct PcPairF {
 // the lane's six blocks, FP64 or (FP32) FP32 products accumulated into FP64; acc receives
 // y_new.  Also evaluates the stopping rule of Sec. 2.2 against the previous iterate yc in
 // squared form (|dr|^2 < tol^2 |r|^2 and the same for v, or without the norms in absolute
-// mode) and returns, OR-ed over the lanes of each IC: bit 0 = some node not converged,
-// bit 1 = non-finite, bit 2 = some node changed by more than sqrt(sw2) (relative).
+// mode) and returns in lanes 0..15 the flags of IC pc_flag_ic, OR-ed over its nodes:
+// bit 0 = some node not converged, bit 1 = non-finite, bit 2 = some node changed by more
+// than sqrt(sw2) (relative).  WIDE blocks are computed as (K_N F)^T = F^T K_N^T: the F
+// slice is the A operand and the K_N fragment the B operand.
 template <int PAIRS, int NP, bool FP32 = false>
 static __device__ __forceinline__ int pc_product(const double* sF, const double* sY0, gconst_dp kp0,
                                                   gconst_fp kp0f, const double (&yc)[6][4], f64x4 (&acc)[6],
@@ -435,7 +481,7 @@ static __device__ __forceinline__ int pc_product(const double* sF, const double*
 {
     using Sh = PcShape<PAIRS, NP>;
     constexpr int T = Sh::T, ROW = Sh::ROW, NQ = Sh::NQ;
-    const int lane = L.lane, my_m = L.my_m, hi = L.hi;
+    const int lane = L.lane, hi = L.hi;
 #pragma unroll
     for (int b = 0; b < 6; ++b) acc[b] = f64x4{0.0, 0.0, 0.0, 0.0};
     int flag = 0;
@@ -446,23 +492,29 @@ static __device__ __forceinline__ int pc_product(const double* sF, const double*
 #pragma unroll
         for (int b = 0; b < 6; ++b) accf[b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
         if constexpr (Sh::WIDE) {
-            const double* bp = sF + (lane >> 4) * ROW + L.grp * 16 + (lane & 15);
+            // the f32 result holds A row 4(l/16) + r in element r: reading IC row i from
+            // column perm(i) = i/4 + 4 (i%4) puts IC l/16 + 4r there, as in the f64 layout
+            const int i = lane & 15, pi = (i >> 2) + 4 * (i & 3);
+            const double* bp[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                bp[u] = sF + (lane >> 4) * ROW + L.grp * 16 + (pi ^ ((4 * u + (lane >> 4)) & 15));
             pc_kloop<NQ, 6, float, float>(
                 [&](int q) { return kp0f[q * 64]; },
-                [&](int q, float (&bq)[6]) {
+                [&](int q, int u, float (&bq)[6]) {
 #pragma unroll
-                    for (int b = 0; b < 6; ++b) bq[b] = (float)bp[q * 4 * ROW + b * T];
+                    for (int b = 0; b < 6; ++b) bq[b] = (float)bp[u][q * 4 * ROW + b * T];
                 },
                 [&](float ka, const float (&bq)[6]) {
 #pragma unroll
-                    for (int b = 0; b < 6; ++b) accf[b] = mfma16f(ka, bq[b], accf[b]);
+                    for (int b = 0; b < 6; ++b) accf[b] = mfma16f(bq[b], ka, accf[b]);
                 });
         } else {
             gconst_fp kp1f = kp0f + (size_t)NQ * 64;
             const double* bp = sF + (lane >> 4) * ROW + (lane & 15);
             pc_kloop<NQ, 3, PcPairF, float>(
                 [&](int q) { return PcPairF{kp0f[q * 64], kp1f[q * 64]}; },
-                [&](int q, float (&bq)[3]) {
+                [&](int q, int, float (&bq)[3]) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c) bq[c] = (float)bp[q * 4 * ROW + 16 * c];
                 },
@@ -482,44 +534,61 @@ static __device__ __forceinline__ int pc_product(const double* sF, const double*
     if constexpr (Sh::WIDE) {
         // K_N strip streamed from L2 four k-steps ahead; B operands one k-step ahead
         if constexpr (!FP32) {
-            const double* bp = sF + (lane >> 4) * ROW + L.grp * 16 + (lane & 15);
+            // row 4q + l/16 of F: its column for IC l%16 depends on q % 4 through the swizzle
+            const double* bp[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                bp[u] = sF + (lane >> 4) * ROW + L.grp * 16 + ((lane & 15) ^ ((4 * u + (lane >> 4)) & 15));
             pc_kloop<NQ, 6, double, double>(
                 [&](int q) { return kp0[q * 64]; },
-                [&](int q, double (&bq)[6]) {
+                [&](int q, int u, double (&bq)[6]) {
 #pragma unroll
-                    for (int b = 0; b < 6; ++b) bq[b] = bp[q * 4 * ROW + b * T];
+                    for (int b = 0; b < 6; ++b) bq[b] = bp[u][q * 4 * ROW + b * T];
                 },
                 [&](double ka, const double (&bq)[6]) {
 #pragma unroll
-                    for (int b = 0; b < 6; ++b) acc[b] = mfma16(ka, bq[b], acc[b]);
+                    for (int b = 0; b < 6; ++b) acc[b] = mfma16(bq[b], ka, acc[b]);
                 });
         }
+        const bool node_ok = pc_node(L, 0, 0) < N;
+        int fr[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int j = pc_node(L, 0, r);
+            const int m = pc_ic(L, r);
             double pd = 0.0, py = 0.0, vd = 0.0, vy = 0.0;
 #pragma unroll
             for (int b = 0; b < 6; ++b) {
-                const double yn = sY0[b * T + my_m] + w2 * acc[b][r];
+                const double yn = sY0[b * T + m] + w2 * acc[b][r];
                 acc[b][r] = yn;
                 const double d = yn - yc[b][r];
                 if (b < 3) { pd += d * d; py += yn * yn; }
                 else { vd += d * d; vy += yn * yn; }
             }
-            if (j < N) {
-                const bool ok = tol_mode == 0 ? (pd < t2 * py && vd < t2 * vy) : (pd < t2 && vd < t2);
-                const bool lo = tol_mode == 0 ? (pd < sw2 * py && vd < sw2 * vy) : (pd < sw2 && vd < sw2);
-                const bool nf = !isfinite(pd + py + vd + vy);
-                flag |= (ok ? 0 : 1) | (nf ? 2 : 0) | (lo ? 0 : 4);
-            }
+            const bool ok = tol_mode == 0 ? (pd < t2 * py && vd < t2 * vy) : (pd < t2 && vd < t2);
+            const bool lo = tol_mode == 0 ? (pd < sw2 * py && vd < sw2 * vy) : (pd < sw2 && vd < sw2);
+            const bool nf = !isfinite(pd + py + vd + vy);
+            fr[r] = node_ok ? ((ok ? 0 : 1) | (nf ? 2 : 0) | (lo ? 0 : 4)) : 0;
+            // OR over the strip's 16 nodes (the lanes of one row group)
+            fr[r] |= __shfl_xor(fr[r], 1);
+            fr[r] |= __shfl_xor(fr[r], 2);
+            fr[r] |= __shfl_xor(fr[r], 4);
+            fr[r] |= __shfl_xor(fr[r], 8);
         }
+        // lane i < 16 returns the flag of local IC i = (i & 3) + 4 (i >> 2), held by the
+        // lanes of row group i & 3 in element i >> 2
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int v = __shfl(fr[r], 16 * (lane & 3));
+            if (((lane >> 2) & 3) == r) flag = v;
+        }
+        return flag;
     } else {
         if constexpr (!FP32) {
             gconst_dp kp1 = kp0 + (size_t)NQ * 64;
             const double* bp = sF + (lane >> 4) * ROW + (lane & 15);
             pc_kloop<NQ, 3, PcPairD, double>(
                 [&](int q) { return PcPairD{kp0[q * 64], kp1[q * 64]}; },
-                [&](int q, double (&bq)[3]) {
+                [&](int q, int, double (&bq)[3]) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c) bq[c] = bp[q * 4 * ROW + 16 * c];
                 },
@@ -530,6 +599,7 @@ static __device__ __forceinline__ int pc_product(const double* sF, const double*
                     for (int c = 0; c < 3; ++c) acc[3 + c] = mfma16(ka.a1, bq[c], acc[3 + c]);
                 });
         }
+        const int my_m = pc_ic(L, 0);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
 #pragma unroll
@@ -567,8 +637,9 @@ static __device__ __forceinline__ int pc_product(const double* sF, const double*
     return flag;
 }
 
-// acc = K_N^T mu for the lane's six blocks (WIDE shapes): the adjoint product, mu published
-// in sF as [node][comp 6][IC] and kpT the lane's strip of K_N^T fragments.
+// acc = K_N^T mu for the lane's six blocks (WIDE shapes, transposed like pc_product): the
+// adjoint product, mu published in sF as [node][comp 6][IC] and kpT the lane's strip of
+// K_N^T fragments.
 template <int PAIRS, int NP>
 static __device__ __forceinline__ void pc_product_adj(const double* sF, gconst_dp kpT, f64x4 (&acc)[6],
                                                       const PcLane& L)
@@ -579,16 +650,19 @@ static __device__ __forceinline__ void pc_product_adj(const double* sF, gconst_d
     const int lane = L.lane;
 #pragma unroll
     for (int b = 0; b < 6; ++b) acc[b] = f64x4{0.0, 0.0, 0.0, 0.0};
-    const double* bp = sF + (lane >> 4) * ROW + L.grp * 16 + (lane & 15);
+    const double* bp[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        bp[u] = sF + (lane >> 4) * ROW + L.grp * 16 + ((lane & 15) ^ ((4 * u + (lane >> 4)) & 15));
     pc_kloop<NQ, 6, double, double>(
         [&](int q) { return kpT[q * 64]; },
-        [&](int q, double (&bq)[6]) {
+        [&](int q, int u, double (&bq)[6]) {
 #pragma unroll
-            for (int b = 0; b < 6; ++b) bq[b] = bp[q * 4 * ROW + b * T];
+            for (int b = 0; b < 6; ++b) bq[b] = bp[u][q * 4 * ROW + b * T];
         },
         [&](double ka, const double (&bq)[6]) {
 #pragma unroll
-            for (int b = 0; b < 6; ++b) acc[b] = mfma16(ka, bq[b], acc[b]);
+            for (int b = 0; b < 6; ++b) acc[b] = mfma16(bq[b], ka, acc[b]);
         });
 }
 
@@ -616,23 +690,20 @@ static __device__ __forceinline__ void pc_publish(double* sF, const double (&yc)
 {
     using Sh = PcShape<PAIRS, NP>;
     constexpr int T = Sh::T, ROW = Sh::ROW;
-    const int my_m = L.my_m, hi = L.hi;
+    const int hi = L.hi;
     if constexpr (Sh::WIDE) {
+        // one node, four ICs: the same record index for every point
         double ax[4], ay[4], az[4];
-        int jr[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int j = pc_node(L, 0, r);
-            jr[r] = j < N ? j : N - 1;
-        }
+        const int j = pc_node(L, 0, 0);
+        const int jj = j < N ? j : N - 1;
+        const int jr[4] = {jj, jj, jj, jj};
         if (rec_lds && FP32) pc_force_lds32<4>(yc[0], yc[1], yc[2], jr, P, mu_sun, sRec, sMu, ax, ay, az);
         else if (rec_lds) pc_force_lds<4>(yc[0], yc[1], yc[2], jr, P, mu_sun, sRec, sMu, ax, ay, az);
         else pc_force_glb<4>(yc[0], yc[1], yc[2], jr, P, mu_sun, grec, ax, ay, az);
+        if (j < N) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int j = pc_node(L, 0, r);
-            if (j < N) {
-                double* f = sF + j * ROW + my_m;
+            for (int r = 0; r < 4; ++r) {
+                double* f = sF + j * ROW + pc_fcol<PAIRS, NP>(j, pc_ic(L, r));
                 f[0 * T] = yc[3][r];
                 f[1 * T] = yc[4][r];
                 f[2 * T] = yc[5][r];
@@ -642,6 +713,7 @@ static __device__ __forceinline__ void pc_publish(double* sF, const double (&yc)
             }
         }
     } else {
+        const int my_m = pc_ic(L, 0);
         // lanes with hi == 0 hold x (cb 0) and z (cb 1); y comes from the partner lane
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -680,9 +752,10 @@ static __device__ __forceinline__ void pc_publish(double* sF, const double (&yc)
     }
 }
 
-// Load / store the lane's share of a [node][comp][IC] array with row stride `row` and
-// comp stride `cs` (WIDE: yc[c][r]; T == 8: yc[3h + cb][r] = comp 2cb + hi).
-template <int PAIRS, int NP, class Ptr>
+// Load the lane's share of a [node][comp][IC] array with row stride `row` and comp stride
+// `cs` (WIDE: yc[c][r]; T == 8: yc[3h + cb][r] = comp 2cb + hi); SWZ: an LDS array with
+// the column swizzle of pc_fcol.
+template <int PAIRS, int NP, bool SWZ = false, class Ptr>
 static __device__ __forceinline__ void pc_load_share(Ptr base, size_t row, size_t cs, double (&yc)[6][4],
                                                      const PcLane& L, int N)
 {
@@ -693,12 +766,13 @@ static __device__ __forceinline__ void pc_load_share(Ptr base, size_t row, size_
         for (int r = 0; r < 4; ++r) {
             const int j = pc_node(L, h, r);
             const int jj = j < N ? j : N - 1;
+            const int m = SWZ ? pc_fcol<PAIRS, NP>(jj, pc_ic(L, r)) : pc_ic(L, r);
             if constexpr (Sh::WIDE) {
 #pragma unroll
-                for (int c = 0; c < 6; ++c) yc[c][r] = base[jj * row + c * cs + L.my_m];
+                for (int c = 0; c < 6; ++c) yc[c][r] = base[jj * row + c * cs + m];
             } else {
 #pragma unroll
-                for (int cb = 0; cb < 3; ++cb) yc[3 * h + cb][r] = base[jj * row + (2 * cb + L.hi) * cs + L.my_m];
+                for (int cb = 0; cb < 3; ++cb) yc[3 * h + cb][r] = base[jj * row + (2 * cb + L.hi) * cs + m];
             }
         }
     }

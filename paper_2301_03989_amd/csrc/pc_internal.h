@@ -26,7 +26,8 @@ struct PcGroupDev {
     int64_t ic_offset, n_ic;
     int64_t rec_offset;        // first ephemeris record of the group (S * N records)
     const double* kfrag;       // [NP/16][NP/4][64]
-    const float* kfrag32;      // FP32 copy, rows permuted for the f32 MFMA result layout
+    const float* kfrag32;      // FP32 copy in the same fragment order
+    const float* kfrag32p;     // FP32 copy, rows permuted for the f32 MFMA result layout
     const double* kfragT;      // fragments of K_N^T (adjoint)
     const double* tau;         // [NP] CGL nodes, zero past N
     int32_t N, NP, T, S;

@@ -127,13 +127,13 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
 #pragma unroll
                 for (int c = 0; c < 6; ++c) y[c] = y0[c];
             }
-            double* dst = sF + j * ROW + pm;
+            double* dst = sF + j * ROW + pc_fcol<PAIRS, NP>(j, pm);
 #pragma unroll
             for (int c = 0; c < 6; ++c) dst[c * T] = y[c];
         }
     }
     __syncthreads();
-    pc_load_share<PAIRS, NP>(static_cast<const double*>(sF), ROW, T, yc, L, N);
+    pc_load_share<PAIRS, NP, true>(static_cast<const double*>(sF), ROW, T, yc, L, N);
     if (tid < T) sm.Active[tid] = (tid < n) && !sm.Dead[tid];
     __syncthreads();   // staging read before F is rebuilt
     for (int i = tid; i < 6 * PAIRS; i += NT) sF[i] = 0.0;
@@ -141,13 +141,17 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
     // precision schedule (uniform per job): FP32 sweeps first when asked, then FP64
     bool fp32 = p.precision == 1;
     int n32 = 0;
-    if (sm.Active[L.my_m]) {
+    int act[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) act[r] = sm.Active[pc_ic(L, r)];
+    if (act[0] | act[1] | act[2] | act[3]) {
         if (fp32) pc_publish<PAIRS, NP, true>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
         else pc_publish<PAIRS, NP>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
     }
     __syncthreads();
 
-    gconst_fp kp0f = (gconst_fp)g.kfrag32 + (size_t)L.strip0 * NQ * 64 + L.lane;
+    // FP32 fragments: natural order for the transposed WIDE product, row-permuted otherwise
+    gconst_fp kp0f = (gconst_fp)(Sh::WIDE ? g.kfrag32 : g.kfrag32p) + (size_t)L.strip0 * NQ * 64 + L.lane;
     const int n_it = p.fixed_iters > 0 ? p.fixed_iters : p.max_iter;
     for (int it = 1; it <= n_it; ++it) {
         // (1)-(2) product and stopping-rule flags
@@ -157,8 +161,10 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
                               : pc_product<PAIRS, NP, false>(sF, sY0, kp0, kp0f, yc, acc, w2, t2, p.switch2,
                                                                p.tol_mode, N, L);
         if (L.lane < 16) sm.Flag[L.wave * 16 + L.lane] = flag;
-        const int act = sm.Active[L.my_m];
-        const unsigned long long keep = __ballot(act && (flag & 4));
+#pragma unroll
+        for (int r = 0; r < 4; ++r) act[r] = sm.Active[pc_ic(L, r)];
+        const unsigned long long keep =
+            __ballot(L.lane < 16 && sm.Active[pc_flag_ic<PAIRS, NP>(L)] && (flag & 4));
         if (L.lane == 0) sm.Keep[L.wave] = keep != 0ull;
         __syncthreads();   // every wave is done reading F; flags complete
 
@@ -187,11 +193,11 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
             }
         }
         // (4) ICs that were iterating take the new iterate and publish its F
-        if (act) {
+        if (act[0] | act[1] | act[2] | act[3]) {
 #pragma unroll
             for (int b = 0; b < 6; ++b) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) yc[b][r] = acc[b][r];
+                for (int r = 0; r < 4; ++r) yc[b][r] = act[r] ? acc[b][r] : yc[b][r];
             }
             if (it < n_it) {
                 if (next32) pc_publish<PAIRS, NP, true>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
@@ -246,16 +252,17 @@ __device__ __attribute__((noinline)) void pc_job(const PcParams& p, const PcJobD
         pc_segment_solve<PAIRS, NP>(p, g, n, job.ic0, s, sm, L, kp0, yc, p.iters_out, had_notconv);
 
         // converged node states of the segment (optional output), chaining (Sec. 2.2)
-        const bool dead = sm.Dead[L.my_m];
 #pragma unroll
         for (int h = 0; h < Sh::H; ++h) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int j = pc_node(L, h, r);
+                const int m = pc_ic(L, r);
+                const bool dead = sm.Dead[m];
                 if (j >= N) continue;
-                if (p.nodes_out && L.my_m < n) {
+                if (p.nodes_out && m < n) {
                     double* o = p.nodes_out +
-                                (((size_t)(job.ic0 + L.my_m) * p.iters_stride + s) * p.nodes_stride + j) * 6;
+                                (((size_t)(job.ic0 + m) * p.iters_stride + s) * p.nodes_stride + j) * 6;
                     if constexpr (Sh::WIDE) {
 #pragma unroll
                         for (int c = 0; c < 6; ++c) o[c] = yc[c][r];
@@ -267,11 +274,11 @@ __device__ __attribute__((noinline)) void pc_job(const PcParams& p, const PcJobD
                 if (j == N - 1) {
                     if constexpr (Sh::WIDE) {
 #pragma unroll
-                        for (int c = 0; c < 6; ++c) sY0[c * T + L.my_m] = dead ? (double)NAN : yc[c][r];
+                        for (int c = 0; c < 6; ++c) sY0[c * T + m] = dead ? (double)NAN : yc[c][r];
                     } else {
 #pragma unroll
                         for (int cb = 0; cb < 3; ++cb)
-                            sY0[(2 * cb + L.hi) * T + L.my_m] = dead ? (double)NAN : yc[3 * h + cb][r];
+                            sY0[(2 * cb + L.hi) * T + m] = dead ? (double)NAN : yc[3 * h + cb][r];
                     }
                 }
             }
@@ -416,13 +423,12 @@ __device__ __attribute__((noinline)) void pc_adjoint_job(const PcAdjParams& a, c
             const int j = pc_node(L, 0, r);
             jr[r] = j < N ? j : N - 1;
         }
-        const double* gnode = (a.gbar_nodes && L.my_m < n)
-                                  ? a.gbar_nodes + ((size_t)(job.ic0 + L.my_m) * a.ckpt_stride + s) * a.nodes_stride * 6
-                                  : nullptr;
         auto seed = [&](int c, int r) -> double {
             const int j = pc_node(L, 0, r);
-            double v = (j == N - 1) ? sLam[c * T + L.my_m] : 0.0;
-            if (gnode && j < N) v += gnode[j * 6 + c];
+            const int m = pc_ic(L, r);
+            double v = (j == N - 1) ? sLam[c * T + m] : 0.0;
+            if (a.gbar_nodes && m < n && j < N)
+                v += a.gbar_nodes[(((size_t)(job.ic0 + m) * a.ckpt_stride + s) * a.nodes_stride + j) * 6 + c];
             return v;
         };
         for (int i = tid; i < 6 * PAIRS; i += NT) sF[i] = 0.0;
@@ -437,7 +443,7 @@ __device__ __attribute__((noinline)) void pc_adjoint_job(const PcAdjParams& a, c
             const int j = pc_node(L, 0, r);
             if (j < N) {
 #pragma unroll
-                for (int c = 0; c < 6; ++c) sF[j * ROW + c * T + L.my_m] = seed(c, r);
+                for (int c = 0; c < 6; ++c) sF[j * ROW + c * T + pc_fcol<PAIRS, NP>(j, pc_ic(L, r))] = seed(c, r);
             }
         }
         __syncthreads();
@@ -459,11 +465,11 @@ __device__ __attribute__((noinline)) void pc_adjoint_job(const PcAdjParams& a, c
             else
                 pc_hess_apply<4, false>(yc[0], yc[1], yc[2], wx, wy, wz, jr, P, p.mu_sun, sm.Rec, sm.Mu, grec,
                                         hx, hy, hz);
-            // mu_new = gbar + J^T w, and its sum over the lane's nodes
-            double part[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            // mu_new = gbar + J^T w, and its sum over the strip's nodes (the 16 lanes of a
+            // row group hold one node each of the same four ICs)
+            const bool node_ok = pc_node(L, 0, 0) < N;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int j = pc_node(L, 0, r);
                 const double nv0 = seed(3, r) + w2 * acc[0][r];
                 const double nv1 = seed(4, r) + w2 * acc[1][r];
                 const double nv2 = seed(5, r) + w2 * acc[2][r];
@@ -473,21 +479,19 @@ __device__ __attribute__((noinline)) void pc_adjoint_job(const PcAdjParams& a, c
                 acc[3][r] = nv0;
                 acc[4][r] = nv1;
                 acc[5][r] = nv2;
-                if (j < N) {
 #pragma unroll
-                    for (int c = 0; c < 6; ++c) part[c] += acc[c][r];
+                for (int c = 0; c < 6; ++c) {
+                    double part = node_ok ? acc[c][r] : 0.0;
+                    part += __shfl_xor(part, 1);
+                    part += __shfl_xor(part, 2);
+                    part += __shfl_xor(part, 4);
+                    part += __shfl_xor(part, 8);
+                    if ((L.lane & 15) == 0) sLamPart[(L.wave * 6 + c) * 16 + (L.lane >> 4) + 4 * r] = part;
                 }
             }
+            int act[4];
 #pragma unroll
-            for (int c = 0; c < 6; ++c) {
-                part[c] += __shfl_xor(part[c], 16);
-                part[c] += __shfl_xor(part[c], 32);
-            }
-            if (L.lane < 16) {
-#pragma unroll
-                for (int c = 0; c < 6; ++c) sLamPart[(L.wave * 6 + c) * 16 + L.lane] = part[c];
-            }
-            const int act = sm.Active[L.my_m];
+            for (int r = 0; r < 4; ++r) act[r] = sm.Active[pc_ic(L, r)];
             __syncthreads();   // K^T mu read by every wave; partial sums complete
 
             // gradient estimate lambda = sum_j mu_j per IC; stop when it no longer changes
@@ -513,13 +517,13 @@ __device__ __attribute__((noinline)) void pc_adjoint_job(const PcAdjParams& a, c
                     if (tid < n && a.adj_iters) a.adj_iters[(size_t)ic * a.ckpt_stride + s] = rec;
                 }
             }
-            if (act) {
+            if (node_ok) {
+                const int j = pc_node(L, 0, 0);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int j = pc_node(L, 0, r);
-                    if (j < N) {
+                    if (act[r]) {
 #pragma unroll
-                        for (int c = 0; c < 6; ++c) sF[j * ROW + c * T + L.my_m] = acc[c][r];
+                        for (int c = 0; c < 6; ++c) sF[j * ROW + c * T + pc_fcol<PAIRS, NP>(j, pc_ic(L, r))] = acc[c][r];
                     }
                 }
             }

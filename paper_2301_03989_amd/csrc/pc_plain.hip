@@ -110,7 +110,8 @@ __global__ __launch_bounds__(PAIRS / 4) void pc_plain_step(PcPlainArgs a, int s,
     // stage F = (v, a) of the job (Y comps 3..8) and its initial states
     for (int i = tid; i < 6 * PAIRS; i += NT) {
         const int j = i / ROW, c = (i % ROW) / T, k = i % T;
-        sF[i] = j < N ? a.Y[(size_t)j * row + (size_t)(3 + c) * a.Mpad + m0 + k] : 0.0;
+        sF[j * ROW + c * T + pc_fcol<PAIRS, NP>(j, k)] =
+            j < N ? a.Y[(size_t)j * row + (size_t)(3 + c) * a.Mpad + m0 + k] : 0.0;
     }
     for (int i = tid; i < 6 * T; i += NT) sY0[i] = a.Y0[(size_t)(i / T) * a.Mpad + m0 + i % T];
     if (tid < T) sActive[tid] = a.active[m0 + tid];
@@ -122,7 +123,9 @@ __global__ __launch_bounds__(PAIRS / 4) void pc_plain_step(PcPlainArgs a, int s,
     gconst_dp kp0 = (gconst_dp)a.g->kfrag + (size_t)L.strip0 * NQ * 64 + L.lane;
     const int flag = pc_product<PAIRS, NP>(sF, sY0, kp0, nullptr, yc, acc, w2, a.t2, 0.0, a.p.tol_mode, N, L);
     if (L.lane < 16) sFlag[L.wave * 16 + L.lane] = flag;
-    const int act = sActive[L.my_m];
+    int act[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) act[r] = sActive[pc_ic(L, r)];
     __syncthreads();
 
     if (tid < T && sActive[tid]) {
@@ -143,14 +146,14 @@ __global__ __launch_bounds__(PAIRS / 4) void pc_plain_step(PcPlainArgs a, int s,
         }
     }
     // new iterate of the ICs that were iterating
-    if (act) {
 #pragma unroll
-        for (int h = 0; h < Sh::H; ++h) {
+    for (int h = 0; h < Sh::H; ++h) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < 4; ++r) {
+            {
                 const int j = pc_node(L, h, r);
-                if (j >= N) continue;
-                double* yw = a.Y + (size_t)j * row + m0 + L.my_m;
+                if (j >= N || !act[r]) continue;
+                double* yw = a.Y + (size_t)j * row + m0 + pc_ic(L, r);
                 if constexpr (Sh::WIDE) {
 #pragma unroll
                     for (int c = 0; c < 6; ++c) yw[(size_t)c * a.Mpad] = acc[c][r];
