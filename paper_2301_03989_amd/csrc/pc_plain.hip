@@ -89,16 +89,20 @@ __global__ __launch_bounds__(kPlainForceBlock) void pc_plain_force(PcPlainArgs a
 }
 
 // The product y_new = y0 + w2 K_N F for one active job per workgroup, with the error of
-// every IC against the previous iterate and the stopping decision in the epilogue.
+// every IC against the previous iterate and the stopping decision in the epilogue.  The
+// job's state moves between HBM and LDS with IC-contiguous (coalesced) accesses; the
+// lanes' shares of it come from LDS.
 template <int PAIRS, int NP>
 __global__ __launch_bounds__(PAIRS / 4) void pc_plain_step(PcPlainArgs a, int s, int it, double w2)
 {
     using Sh = PcShape<PAIRS, NP>;
     constexpr int NT = Sh::NT, T = Sh::T, ROW = Sh::ROW, NQ = Sh::NQ;
-    __shared__ double sF[6 * PAIRS];
+    __shared__ double sF[6 * PAIRS];   // F = (v, a); after the product: the new iterate (r, v)
+    __shared__ double sR[3 * PAIRS];   // positions of the current iterate, [node][3][IC]
     __shared__ double sY0[6 * T];
     __shared__ int sFlag[Sh::W * 16];
     __shared__ int sActive[T];
+    __shared__ int sWas[T];
 
     const int tid = threadIdx.x;
     const int job = a.job_list[blockIdx.x];
@@ -107,26 +111,51 @@ __global__ __launch_bounds__(PAIRS / 4) void pc_plain_step(PcPlainArgs a, int s,
     const PcLane L = pc_lane_geometry<PAIRS, NP>(tid);
     const size_t row = (size_t)9 * a.Mpad;
 
-    // stage F = (v, a) of the job (Y comps 3..8) and its initial states
+    // stage F = (v, a) (Y comps 3..8) and r (Y comps 0..2) of the job, and its initial states
     for (int i = tid; i < 6 * PAIRS; i += NT) {
         const int j = i / ROW, c = (i % ROW) / T, k = i % T;
         sF[j * ROW + c * T + pc_fcol<PAIRS, NP>(j, k)] =
             j < N ? a.Y[(size_t)j * row + (size_t)(3 + c) * a.Mpad + m0 + k] : 0.0;
     }
+    for (int i = tid; i < 3 * PAIRS; i += NT) {
+        const int j = i / (3 * T), c = (i % (3 * T)) / T, k = i % T;
+        sR[j * 3 * T + c * T + pc_fcol<PAIRS, NP>(j, k)] =
+            j < N ? a.Y[(size_t)j * row + (size_t)c * a.Mpad + m0 + k] : 0.0;
+    }
     for (int i = tid; i < 6 * T; i += NT) sY0[i] = a.Y0[(size_t)(i / T) * a.Mpad + m0 + i % T];
-    if (tid < T) sActive[tid] = a.active[m0 + tid];
-    double yc[6][4];
-    pc_load_share<PAIRS, NP>(a.Y + m0, row, (size_t)a.Mpad, yc, L, N);
+    if (tid < T) {
+        sActive[tid] = a.active[m0 + tid];
+        sWas[tid] = sActive[tid];
+    }
     __syncthreads();
+    double yc[6][4];
+#pragma unroll
+    for (int h = 0; h < Sh::H; ++h) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = pc_node(L, h, r);
+            const int jj = j < N ? j : N - 1;
+            const int col = pc_fcol<PAIRS, NP>(jj, pc_ic(L, r));
+            if constexpr (Sh::WIDE) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) yc[c][r] = sR[jj * 3 * T + c * T + col];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) yc[3 + c][r] = sF[jj * ROW + c * T + col];
+            } else {
+#pragma unroll
+                for (int cb = 0; cb < 3; ++cb) {
+                    const int c = 2 * cb + L.hi;
+                    yc[3 * h + cb][r] = c < 3 ? sR[jj * 3 * T + c * T + col] : sF[jj * ROW + (c - 3) * T + col];
+                }
+            }
+        }
+    }
 
     f64x4 acc[6];
     gconst_dp kp0 = (gconst_dp)a.g->kfrag + (size_t)L.strip0 * NQ * 64 + L.lane;
     const int flag = pc_product<PAIRS, NP>(sF, sY0, kp0, nullptr, yc, acc, w2, a.t2, 0.0, a.p.tol_mode, N, L);
     if (L.lane < 16) sFlag[L.wave * 16 + L.lane] = flag;
-    int act[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) act[r] = sActive[pc_ic(L, r)];
-    __syncthreads();
+    __syncthreads();   // F read by every wave, flags complete
 
     if (tid < T && sActive[tid]) {
         const int f = pc_gather_flags<PAIRS, NP>(sFlag, tid);
@@ -145,24 +174,28 @@ __global__ __launch_bounds__(PAIRS / 4) void pc_plain_step(PcPlainArgs a, int s,
                 a.p.iters_out[(size_t)(jd.ic0 + tid) * a.p.iters_stride + s] = rec;
         }
     }
-    // new iterate of the ICs that were iterating
+    // the new iterate into LDS (over F, now free), then out to HBM for the ICs that were
+    // iterating
 #pragma unroll
     for (int h = 0; h < Sh::H; ++h) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            {
-                const int j = pc_node(L, h, r);
-                if (j >= N || !act[r]) continue;
-                double* yw = a.Y + (size_t)j * row + m0 + pc_ic(L, r);
-                if constexpr (Sh::WIDE) {
+            const int j = pc_node(L, h, r);
+            if (j >= N) continue;
+            const int col = pc_fcol<PAIRS, NP>(j, pc_ic(L, r));
+            if constexpr (Sh::WIDE) {
 #pragma unroll
-                    for (int c = 0; c < 6; ++c) yw[(size_t)c * a.Mpad] = acc[c][r];
-                } else {
+                for (int c = 0; c < 6; ++c) sF[j * ROW + c * T + col] = acc[c][r];
+            } else {
 #pragma unroll
-                    for (int cb = 0; cb < 3; ++cb) yw[(size_t)(2 * cb + L.hi) * a.Mpad] = acc[3 * h + cb][r];
-                }
+                for (int cb = 0; cb < 3; ++cb) sF[j * ROW + (2 * cb + L.hi) * T + col] = acc[3 * h + cb][r];
             }
         }
+    }
+    __syncthreads();
+    for (int i = tid; i < 6 * PAIRS; i += NT) {
+        const int j = i / ROW, c = (i % ROW) / T, k = i % T;
+        if (j < N && sWas[k]) a.Y[(size_t)j * row + (size_t)c * a.Mpad + m0 + k] = sF[j * ROW + c * T + pc_fcol<PAIRS, NP>(j, k)];
     }
     const int any = __syncthreads_or(tid < T ? sActive[tid] : 0);
     if (tid == 0) a.job_flag[job] = any;
