@@ -714,24 +714,37 @@ static __device__ __forceinline__ void pc_publish(double* sF, const double (&yc)
         }
     } else {
         const int my_m = pc_ic(L, 0);
-        // lanes with hi == 0 hold x (cb 0) and z (cb 1); y comes from the partner lane
+        // Lane pairs (l, l ^ 8) share the points of one IC: the low lane holds x and z, the
+        // high lane y.  Each lane of the pair takes the force of one strip (hd = hi), so
+        // both do half the work: the low lane gets y of strip 0 from its partner, the high
+        // lane gets x and z of strip 1.
+        double xs[4], ys[4], zs[4], ax[4], ay[4], az[4];
+        int jr[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const double s1 = __shfl_xor(hi ? yc[0][r] : yc[3][r], 8);
+            const double s2 = __shfl_xor(yc[4][r], 8);
+            xs[r] = hi ? s1 : yc[0][r];
+            ys[r] = hi ? yc[3][r] : s1;
+            zs[r] = hi ? s2 : yc[1][r];
+            const int j = pc_node(L, hi, r);
+            jr[r] = j < N ? j : N - 1;
+        }
+        if (rec_lds && FP32) pc_force_lds32<4>(xs, ys, zs, jr, P, mu_sun, sRec, sMu, ax, ay, az);
+        else if (rec_lds) pc_force_lds<4>(xs, ys, zs, jr, P, mu_sun, sRec, sMu, ax, ay, az);
+        else pc_force_glb<4>(xs, ys, zs, jr, P, mu_sun, grec, ax, ay, az);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = pc_node(L, hi, r);
+            if (j < N) {
+                double* f = sF + j * ROW + my_m;
+                f[3 * T] = ax[r];
+                f[4 * T] = ay[r];
+                f[5 * T] = az[r];
+            }
+        }
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            double xs[4], ys[4], zs[4], ax[4], ay[4], az[4];
-            int jr[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int j = pc_node(L, h, r);
-                jr[r] = j < N ? j : N - 1;
-                xs[r] = yc[3 * h][r];
-                ys[r] = __shfl_xor(yc[3 * h][r], 8);
-                zs[r] = yc[3 * h + 1][r];
-            }
-            if (!hi) {
-                if (rec_lds && FP32) pc_force_lds32<4>(xs, ys, zs, jr, P, mu_sun, sRec, sMu, ax, ay, az);
-                else if (rec_lds) pc_force_lds<4>(xs, ys, zs, jr, P, mu_sun, sRec, sMu, ax, ay, az);
-                else pc_force_glb<4>(xs, ys, zs, jr, P, mu_sun, grec, ax, ay, az);
-            }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int j = pc_node(L, h, r);
@@ -742,9 +755,6 @@ static __device__ __forceinline__ void pc_publish(double* sF, const double (&yc)
                         f[2 * T] = yc[3 * h + 2][r];   // vz (comp 5)
                     } else {
                         f[1 * T] = yc[3 * h + 2][r];   // vy (comp 4)
-                        f[3 * T] = ax[r];
-                        f[4 * T] = ay[r];
-                        f[5 * T] = az[r];
                     }
                 }
             }
