@@ -431,16 +431,22 @@ static __device__ __forceinline__ int pc_fcol(int j, int m)
 // B operands (LDS) one step ahead into two buffers, and the loop body is unrolled DK
 // times, so both rings rotate by register renaming.  A register move out of a ring would
 // make the wave wait for the load it copies right after issuing it.
-// loadB(q, q % 4, buffer) gets the phase as a compile-time constant after unrolling.
-template <int NQ, int NB, class AT, class BT, class LA, class LB, class MM>
-static __device__ __forceinline__ void pc_kloop(LA loadA, LB loadB, MM mma)
+// loadB(q, q % 4, buffer) gets the phase as a compile-time constant after unrolling;
+// loadA0(u) supplies the first DK A operands (registers kept across calls, or loads).
+// SG_DS / SG_MFMA / SG_VMEM > 0 pin the order of one step in the steady-state loop for
+// the scheduler: the B reads of the next step, this step's MFMAs, then the A read DK
+// steps ahead (left to itself, the scheduler sinks the reads below the MFMAs that free
+// their registers, and the wave then waits on each read right after issuing it).
+template <int NQ, int NB, class AT, class BT, int SG_DS = 0, int SG_MFMA = 0, int SG_VMEM = 0, class LA0,
+          class LA, class LB, class MM>
+static __device__ __forceinline__ void pc_kloop(LA0 loadA0, LA loadA, LB loadB, MM mma)
 {
     constexpr int DK = 4;
     static_assert(NQ % DK == 0, "k steps must be a multiple of the A ring depth");
     AT ka[DK];
     BT bb[2][NB];
 #pragma unroll
-    for (int u = 0; u < DK; ++u) ka[u] = loadA(u);
+    for (int u = 0; u < DK; ++u) ka[u] = loadA0(u);
     loadB(0, 0, bb[0]);
 #pragma unroll 1
     for (int q0 = 0; q0 < NQ - DK; q0 += DK) {
@@ -449,6 +455,11 @@ static __device__ __forceinline__ void pc_kloop(LA loadA, LB loadB, MM mma)
             loadB(q0 + u + 1, (u + 1) & 3, bb[(u + 1) & 1]);
             mma(ka[u], bb[u & 1]);
             ka[u] = loadA(q0 + u + DK);
+            if constexpr (SG_MFMA > 0) {
+                __builtin_amdgcn_sched_group_barrier(0x100, SG_DS, 0);     // DS reads
+                __builtin_amdgcn_sched_group_barrier(0x008, SG_MFMA, 0);   // MFMA
+                __builtin_amdgcn_sched_group_barrier(0x020, SG_VMEM, 0);   // VMEM reads
+            }
         }
     }
 #pragma unroll
@@ -461,6 +472,19 @@ static __device__ __forceinline__ void pc_kloop(LA loadA, LB loadB, MM mma)
 struct PcPairD {
     double a0, a1;
 };
+
+// The first four FP64 A operands of the lane's strip (and, for 8-IC jobs, of its second
+// strip), loaded once per job: every product then starts without waiting on L2.
+template <int PAIRS, int NP>
+static __device__ __forceinline__ void pc_kpre_load(gconst_dp kp0, double (&kpre)[8])
+{
+    constexpr int NQ = NP / 4;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        kpre[u] = kp0[u * 64];
+        kpre[4 + u] = PcShape<PAIRS, NP>::WIDE ? 0.0 : kp0[(NQ + u) * 64];
+    }
+}
 struct PcPairF {
     float a0, a1;
 };
@@ -475,7 +499,8 @@ struct PcPairF {
 // slice is the A operand and the K_N fragment the B operand.
 template <int PAIRS, int NP, bool FP32 = false>
 static __device__ __forceinline__ int pc_product(const double* sF, const double* sY0, gconst_dp kp0,
-                                                  gconst_fp kp0f, const double (&yc)[6][4], f64x4 (&acc)[6],
+                                                  const double (&kpre)[8], gconst_fp kp0f,
+                                                  const double (&yc)[6][4], f64x4 (&acc)[6],
                                                   double w2, double t2, double sw2, int tol_mode, int N,
                                                   const PcLane& L)
 {
@@ -500,7 +525,7 @@ static __device__ __forceinline__ int pc_product(const double* sF, const double*
             for (int u = 0; u < 4; ++u)
                 bp[u] = sF + (lane >> 4) * ROW + L.grp * 16 + (pi ^ ((4 * u + (lane >> 4)) & 15));
             pc_kloop<NQ, 6, float, float>(
-                [&](int q) { return kp0f[q * 64]; },
+                [&](int q) { return kp0f[q * 64]; }, [&](int q) { return kp0f[q * 64]; },
                 [&](int q, int u, float (&bq)[6]) {
 #pragma unroll
                     for (int b = 0; b < 6; ++b) bq[b] = (float)bp[u][q * 4 * ROW + b * T];
@@ -513,6 +538,7 @@ static __device__ __forceinline__ int pc_product(const double* sF, const double*
             gconst_fp kp1f = kp0f + (size_t)NQ * 64;
             const double* bp = sF + (lane >> 4) * ROW + (lane & 15);
             pc_kloop<NQ, 3, PcPairF, float>(
+                [&](int q) { return PcPairF{kp0f[q * 64], kp1f[q * 64]}; },
                 [&](int q) { return PcPairF{kp0f[q * 64], kp1f[q * 64]}; },
                 [&](int q, int, float (&bq)[3]) {
 #pragma unroll
@@ -539,8 +565,8 @@ static __device__ __forceinline__ int pc_product(const double* sF, const double*
 #pragma unroll
             for (int u = 0; u < 4; ++u)
                 bp[u] = sF + (lane >> 4) * ROW + L.grp * 16 + ((lane & 15) ^ ((4 * u + (lane >> 4)) & 15));
-            pc_kloop<NQ, 6, double, double>(
-                [&](int q) { return kp0[q * 64]; },
+            pc_kloop<NQ, 6, double, double, 3, 6, 1>(
+                [&](int u) { return kpre[u]; }, [&](int q) { return kp0[q * 64]; },
                 [&](int q, int u, double (&bq)[6]) {
 #pragma unroll
                     for (int b = 0; b < 6; ++b) bq[b] = bp[u][q * 4 * ROW + b * T];
@@ -587,6 +613,7 @@ static __device__ __forceinline__ int pc_product(const double* sF, const double*
             gconst_dp kp1 = kp0 + (size_t)NQ * 64;
             const double* bp = sF + (lane >> 4) * ROW + (lane & 15);
             pc_kloop<NQ, 3, PcPairD, double>(
+                [&](int u) { return PcPairD{kpre[u], kpre[4 + u]}; },
                 [&](int q) { return PcPairD{kp0[q * 64], kp1[q * 64]}; },
                 [&](int q, int, double (&bq)[3]) {
 #pragma unroll
@@ -654,8 +681,8 @@ static __device__ __forceinline__ void pc_product_adj(const double* sF, gconst_d
 #pragma unroll
     for (int u = 0; u < 4; ++u)
         bp[u] = sF + (lane >> 4) * ROW + L.grp * 16 + ((lane & 15) ^ ((4 * u + (lane >> 4)) & 15));
-    pc_kloop<NQ, 6, double, double>(
-        [&](int q) { return kpT[q * 64]; },
+    pc_kloop<NQ, 6, double, double, 3, 6, 1>(
+        [&](int q) { return kpT[q * 64]; }, [&](int q) { return kpT[q * 64]; },
         [&](int q, int u, double (&bq)[6]) {
 #pragma unroll
             for (int b = 0; b < 6; ++b) bq[b] = bp[u][q * 4 * ROW + b * T];

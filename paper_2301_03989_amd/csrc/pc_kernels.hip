@@ -153,12 +153,14 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
     // FP32 fragments: natural order for the transposed WIDE product, row-permuted otherwise
     gconst_fp kp0f = (gconst_fp)(Sh::WIDE ? g.kfrag32 : g.kfrag32p) + (size_t)L.strip0 * NQ * 64 + L.lane;
     const int n_it = p.fixed_iters > 0 ? p.fixed_iters : p.max_iter;
+    double kpre[8];
+    pc_kpre_load<PAIRS, NP>(kp0, kpre);
     for (int it = 1; it <= n_it; ++it) {
         // (1)-(2) product and stopping-rule flags
         f64x4 acc[6];
-        const int flag = fp32 ? pc_product<PAIRS, NP, true>(sF, sY0, kp0, kp0f, yc, acc, w2, t2, p.switch2,
+        const int flag = fp32 ? pc_product<PAIRS, NP, true>(sF, sY0, kp0, kpre, kp0f, yc, acc, w2, t2, p.switch2,
                                                               p.tol_mode, N, L)
-                              : pc_product<PAIRS, NP, false>(sF, sY0, kp0, kp0f, yc, acc, w2, t2, p.switch2,
+                              : pc_product<PAIRS, NP, false>(sF, sY0, kp0, kpre, kp0f, yc, acc, w2, t2, p.switch2,
                                                                p.tol_mode, N, L);
         if (L.lane < 16) sm.Flag[L.wave * 16 + L.lane] = flag;
 #pragma unroll
