@@ -352,3 +352,19 @@ def test_fp32_then_fp64_rejected_on_plain_path(pc):
     w = W.nbody_venus(4)
     with pytest.raises(pcprop.PcError):
         _run(pc, w, precision="fp32-fp64", path="plain")
+
+
+# ---------------------------------------------------------------------------
+# every register layout of the job shapes, node by node
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("nodes,tile", [(12, 2048), (24, 2048), (48, 2048), (100, 2048), (200, 2048),
+                                        (48, 1024), (100, 1024)])
+def test_node_states_every_job_shape(pc, nodes, tile):
+    """Node outputs at fixed sweeps for NP = 16 .. 256 (16 to 128 ICs per job, transposed
+    blocks; 8 ICs per job, node-row blocks) with a ragged IC count, against the oracle."""
+    w = W.nbody_venus(37, seed=31, days=40.0, segments=2, nodes=nodes)
+    r, _ = _run(pc, w, fixed_iters=6, want_nodes=True, want_bounds=True, tile_pairs=tile)
+    o = oracle_run(w, fixed_iters=6, want_nodes=True, want_bounds=True)
+    assert rel_err(r["nodes"].reshape(-1, 6), o["nodes"].reshape(-1, 6)).max() < 1e-12
+    assert rel_err(r["bounds"].reshape(-1, 6), o["bounds"].reshape(-1, 6)).max() < 1e-12
+    assert (r["iters"] == 6).all()
