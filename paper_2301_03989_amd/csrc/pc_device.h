@@ -190,6 +190,55 @@ struct PcSmem {
     int Dead[PAIRS / 16];
 };
 
+// The same for R points at one node j (the transposed job layout): the bodies go in
+// chunks of four whose records are read together, so the wave waits on LDS once per chunk;
+// past the last body the indirect-term record (always present) stands in with zero mass.
+template <int R>
+static __device__ __forceinline__ void pc_force_lds_node(const double (&x)[R], const double (&y)[R],
+                                                         const double (&z)[R], int j, int P, double mu_sun,
+                                                         const double* srec, const double* smu,
+                                                         double (&ax)[R], double (&ay)[R], double (&az)[R])
+{
+    const double* rec = srec + j * 3 * (P + 1);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const double ir = pc_rsqrt(x[r] * x[r] + y[r] * y[r] + z[r] * z[r]);
+        const double s = mu_sun * (ir * ir * ir);
+        ax[r] = -s * x[r];
+        ay[r] = -s * y[r];
+        az[r] = -s * z[r];
+    }
+    for (int b0 = 0; b0 < P; b0 += 4) {
+        double qx[4], qy[4], qz[4], mu[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int b = b0 + k < P ? b0 + k : P;
+            mu[k] = b0 + k < P ? smu[b0 + k < P ? b0 + k : 0] : 0.0;
+            qx[k] = rec[3 * b];
+            qy[k] = rec[3 * b + 1];
+            qz[k] = rec[3 * b + 2];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double dx = x[r] - qx[k], dy = y[r] - qy[k], dz = z[r] - qz[k];
+                const double id = pc_rsqrt(dx * dx + dy * dy + dz * dz);
+                const double sd = mu[k] * (id * id * id);
+                ax[r] -= sd * dx;
+                ay[r] -= sd * dy;
+                az[r] -= sd * dz;
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        ax[r] -= rec[3 * P];
+        ay[r] -= rec[3 * P + 1];
+        az[r] -= rec[3 * P + 2];
+    }
+}
+
 // Accelerations at R points whose perturber records sit in LDS (compact [node][body][3]).
 template <int R>
 static __device__ __forceinline__ void pc_force_lds(const double (&x)[R], const double (&y)[R],
@@ -725,7 +774,7 @@ static __device__ __forceinline__ void pc_publish(double* sF, const double (&yc)
         const int jj = j < N ? j : N - 1;
         const int jr[4] = {jj, jj, jj, jj};
         if (rec_lds && FP32) pc_force_lds32<4>(yc[0], yc[1], yc[2], jr, P, mu_sun, sRec, sMu, ax, ay, az);
-        else if (rec_lds) pc_force_lds<4>(yc[0], yc[1], yc[2], jr, P, mu_sun, sRec, sMu, ax, ay, az);
+        else if (rec_lds) pc_force_lds_node<4>(yc[0], yc[1], yc[2], jj, P, mu_sun, sRec, sMu, ax, ay, az);
         else pc_force_glb<4>(yc[0], yc[1], yc[2], jr, P, mu_sun, grec, ax, ay, az);
         if (j < N) {
 #pragma unroll
