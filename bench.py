@@ -219,6 +219,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=None, help="default nbody-venus-4096")
     ap.add_argument("--tile-pairs", type=int, default=0)
+    ap.add_argument("--job-list", type=int, default=0,
+                    help="ICs per job in column blocks (0 automatic, 1 off, 2/4/8)")
     ap.add_argument("--graph", action="store_true", help="replay the call as a captured HIP graph")
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32-fp64"],
                     help="sweep arithmetic (default: the workload's)")
@@ -282,7 +284,8 @@ def main():
 
     def step():
         return ctx.propagate_batched(ics, groups, model, init=init, tile_pairs=args.tile_pairs, out=states,
-                                     graph=args.graph, precision=precision, switch_tol=args.switch_tol)
+                                     graph=args.graph, precision=precision, switch_tol=args.switch_tol,
+                                     job_list=args.job_list)
 
     print(f"bench: {w.name}: {n_ic} ICs, {ic_segments} IC-segments, warmup {args.warmup}", flush=True)
     for _ in range(args.warmup):
@@ -404,7 +407,7 @@ def main():
         "config": {"workload": w.name, "n_ic": n_ic, "segments": [g.segments for g in w.groups][:4],
                    "nodes": sorted({g.nodes for g in w.groups}), "tol": w.groups[0].tol,
                    "perturbers": int(w.pert.shape[0]), "path": "fused", "graph": bool(args.graph), "precision": precision,
-                   "tile_pairs": args.tile_pairs or "tuned"},
+                   "tile_pairs": args.tile_pairs or "tuned", "job_list": args.job_list or "auto"},
         "accuracy": {"max_rel_err_vs_oracle": max_err, "p99_rel_err_vs_oracle": float(np.percentile(errs, 99)),
                      "median_rel_err_vs_oracle": float(np.median(errs)), "checked_ics": int(idx.size),
                      "max_iteration_diff": iter_diff, "status": int(status),

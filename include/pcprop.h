@@ -93,7 +93,11 @@ typedef struct {
     double switch_tol;    /* PC_FP32_THEN_FP64: relative change below which a job leaves FP32
                              (0 = default 1e-4) */
     int32_t max_fp32;     /* PC_FP32_THEN_FP64: cap on FP32 sweeps per segment (0 = default 24) */
-    int32_t pad_;
+    int32_t job_list;     /* fused FP64 forward calls: ICs per job in units of its column block
+                             (16 ICs, or 8 at 256 nodes); when an IC converges its column takes
+                             the next IC of the job for the same segment.  0 = automatic (the
+                             largest of 1, 2, 4, 8 leaving >= 4 jobs per compute unit), 1 = off,
+                             2, 4 or 8 = that many blocks.  Results do not depend on it. */
 } pc_opts;
 
 /* One outer-level group of the two-level augmentation (Sec. 3.2): ICs

@@ -259,6 +259,7 @@ struct Plan {
     std::vector<PcJobDev> jobs;
     int64_t n_recs = 0;
     int max_S = 0, max_N = 0;
+    int list = 1;                  // job ICs in units of the job's columns
     // workspace offsets
     size_t off_counters = 0, off_params = 0, off_groups = 0, off_jobs = 0, off_bodies = 0, off_recs = 0, total = 0;
     size_t staged = 0;   // bytes of [counters .. bodies] copied from the staging buffer
@@ -281,8 +282,10 @@ int choose_pairs(const pc_ctx* ctx, const pc_group* groups, int n_groups, const 
     return 2048;
 }
 
+// lists_ok: jobs may hold more ICs than columns (refilled columns; fused FP64 forward calls).
+// A plan without lists has the most jobs, so its workspace size bounds every other plan's.
 int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, const pc_model* model,
-              const pc_opts& o, bool build_tables, Plan& plan)
+              const pc_opts& o, bool build_tables, Plan& plan, bool lists_ok = false)
 {
     if (!groups || n_groups < 1) return set_error(ctx, PC_EINVAL, "need at least one group");
     if (o.tile_pairs != 0 && o.tile_pairs != 1024 && o.tile_pairs != 2048)
@@ -318,6 +321,24 @@ int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, c
     for (size_t i = 1; i < spans.size(); ++i)
         if (spans[i].first < spans[i - 1].second) return set_error(ctx, PC_EINVAL, "groups overlap");
 
+    // ICs per job in units of the job's columns: the largest of 1, 2, 4, 8 that still
+    // leaves at least four jobs per compute unit for the work queue to balance
+    int list = 1;
+    if (lists_ok && o.job_list != 1) {
+        auto jobs_at = [&](int m) {
+            int64_t nj = 0;
+            for (int gi = 0; gi < n_groups; ++gi) {
+                const int64_t cols = (int64_t)m * (plan.pairs / padded_nodes(groups[gi].nodes));
+                nj += (groups[gi].n_ic + cols - 1) / cols;
+            }
+            return nj;
+        };
+        if (o.job_list > 1) list = o.job_list;
+        else
+            for (int m = 2; m <= 8; m *= 2)
+                if (jobs_at(m) >= 4 * (int64_t)ctx->n_cu) list = m;
+    }
+    plan.list = list;
     struct Cost { int np; double c; PcJobDev j; };
     std::vector<Cost> costs;
     for (int gi = 0; gi < n_groups; ++gi) {
@@ -345,13 +366,15 @@ int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, c
         }
         plan.n_recs += (int64_t)G.segments * G.nodes;
         plan.groups.push_back(d);
-        // cost model of one job: segments x NP (matrix work per iteration ~ NP^2 T = NP * PAIRS)
-        const double c = (double)G.segments * (double)d.NP;
-        for (int64_t i0 = 0; i0 < G.n_ic; i0 += d.T) {
+        // cost model of one job: segments x NP x column blocks (matrix work per iteration
+        // ~ NP^2 T = NP * PAIRS per block)
+        const int64_t per_job = (int64_t)list * d.T;
+        for (int64_t i0 = 0; i0 < G.n_ic; i0 += per_job) {
             PcJobDev j{};
             j.ic0 = G.ic_offset + i0;
             j.group = gi;
-            j.n = (int)std::min<int64_t>(d.T, G.n_ic - i0);
+            j.n = (int)std::min<int64_t>(per_job, G.n_ic - i0);
+            const double c = (double)G.segments * (double)d.NP * (double)((j.n + d.T - 1) / d.T);
             costs.push_back({d.NP, c, j});
         }
     }
@@ -417,7 +440,7 @@ void pc_default_opts(pc_opts* o)
     o->graph = 0;
     o->switch_tol = 0.0;
     o->max_fp32 = 0;
-    o->pad_ = 0;
+    o->job_list = 0;
 }
 
 int pc_version(void) { return PC_VERSION; }
@@ -521,10 +544,13 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_
     if (o.max_iter < 1 || o.max_iter > 100000) return set_error(ctx, PC_EINVAL, "max_iter out of range");
     if (!(o.switch_tol >= 0.0) || !std::isfinite(o.switch_tol) || o.max_fp32 < 0)
         return set_error(ctx, PC_EINVAL, "bad precision-schedule options");
+    if (o.job_list != 0 && o.job_list != 1 && o.job_list != 2 && o.job_list != 4 && o.job_list != 8)
+        return set_error(ctx, PC_EINVAL, "job_list must be 0, 1, 2, 4 or 8");
     if (o.fixed_iters < 0 || o.fixed_iters > 100000) return set_error(ctx, PC_EINVAL, "fixed_iters out of range");
     PC_HIP(ctx, hipSetDevice(ctx->device));
     Plan plan;
-    rc = make_plan(ctx, n_ic, groups, n_groups, model, o, true, plan);
+    rc = make_plan(ctx, n_ic, groups, n_groups, model, o, true, plan,
+                   o.path == PC_PATH_FUSED && o.precision == PC_FP64);
     if (rc != PC_OK) return rc;
     if ((iters_out || bounds_out || nodes_out) && iters_stride < plan.max_S)
         return set_error(ctx, PC_EINVAL, "iters_stride %d < %d segments", iters_stride, plan.max_S);

@@ -36,7 +36,7 @@ struct PcGroupDev {
 struct PcJobDev {
     int64_t ic0;               // global index of the job's first IC
     int32_t group;
-    int32_t n;                 // ICs in the job (<= T)
+    int32_t n;                 // ICs in the job: <= T, or more (refilled columns)
 };
 
 // Perturber on a Keplerian orbit, prepared on the host:

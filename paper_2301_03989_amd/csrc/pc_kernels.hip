@@ -301,6 +301,265 @@ __device__ __attribute__((noinline)) void pc_job(const PcParams& p, const PcJobD
     __syncthreads();
 }
 
+// A job with more ICs than columns (n > T), FP64 sweeps.  Every column of the product is
+// an independent fixed-point iteration (the product never mixes columns), so when an IC
+// stops, its end state is stored and its column takes the next IC of the job for the same
+// segment: the columns do not idle while a slower IC of the same block still iterates,
+// only the tail of each segment does.  The job's ICs are dealt to its column groups (entry
+// e to group e % GN); every wave of a group takes the same decisions from the same flags,
+// so the two barriers per sweep stay the only ones.  Each IC's sequence of iterates is the
+// one the one-block job body computes.  Between segments an IC's state lives in
+// states_out (the end state of its last completed segment).
+template <int PAIRS, int NP>
+__device__ __attribute__((noinline)) void pc_job_list(const PcParams& p, const PcJobDev& job, const PcGroupDev& g)
+{
+    using Sh = PcShape<PAIRS, NP>;
+    constexpr int NT = Sh::NT, T = Sh::T, ROW = Sh::ROW, NQ = Sh::NQ;
+    constexpr int COLS = Sh::WIDE ? 16 : 8;      // columns of one group
+    constexpr int GN = Sh::WIDE ? Sh::G16 : 1;   // groups of the job
+    constexpr int E = Sh::WIDE ? 4 : 1;          // columns a lane holds points of
+    constexpr unsigned CMASK = (1u << COLS) - 1u;
+    PcSmem<PAIRS>& sm = pc_smem<PAIRS>();
+    double* sF = sm.F;
+    double* sY0 = sm.Y0;
+    const int tid = threadIdx.x;
+    const PcLane L = pc_lane_geometry<PAIRS, NP>(tid);
+    const int N = g.N, S = g.S, P = p.n_pert;
+    const int n = job.n;
+    const int grp = Sh::WIDE ? L.grp : 0;
+    const int n_g = n > grp ? (n - grp + GN - 1) / GN : 0;   // entries of this wave's group
+    const bool rec_lds = N * 3 * (P + 1) <= PcSmem<PAIRS>::REC;
+    const double t2 = g.tol * g.tol;
+    gconst_dp kp0 = (gconst_dp)g.kfrag + (size_t)L.strip0 * NQ * 64 + L.lane;
+    double kpre[8];
+    pc_kpre_load<PAIRS, NP>(kp0, kpre);
+    const bool flane = L.lane < COLS;             // lanes < COLS carry the per-column decisions
+    const int fcol = L.lane & (COLS - 1);
+    const bool owner = flane && L.strip0 == 0;    // one wave per group writes per-IC records
+    auto ic_of = [&](int e) -> int64_t { return job.ic0 + grp + (int64_t)GN * e; };
+    auto col_of = [&](int e) -> int { return Sh::WIDE ? pc_ic(L, e) - grp * 16 : (L.lane & 7); };
+    int notconv = 0;
+
+    double yc[6][4];
+    for (int s = 0; s < S; ++s) {
+        const double Ts = g.t0 + g.h * s, Te = g.t0 + g.h * (s + 1);
+        const double w2 = 0.5 * (Te - Ts);
+        const double* src = s == 0 ? p.ics : p.states_out;
+        const double4* grec = reinterpret_cast<const double4*>(p.recs) +
+                              (size_t)(g.rec_offset + (int64_t)s * N) * (P + 1);
+        // Warm (or cold) start, Sec. 2.1, of the group's columns in `rm`, column c taking entry
+        // base + (its rank in rm).  The wave computes the points of its own node rows for
+        // all those columns together (one Kepler solve per lane and pass), stages them in
+        // the columns' F slots (free after the product), and the lanes that hold the points
+        // read them back.
+        auto warm_columns = [&](unsigned rm, int base) {
+            constexpr int WN = 16 * Sh::H;               // node rows of this wave
+            const int k = __popc(rm);
+            for (int q = L.lane; q < WN * k; q += 64) {
+                const int ci = q / WN, jn = q - ci * WN;
+                unsigned m = rm;
+                for (int t = 0; t < ci; ++t) m &= m - 1u;
+                const int c = __ffs(m) - 1;
+                const int j = L.strip0 * 16 + jn;
+                if (j >= N) continue;
+                const double* y0p = src + ic_of(base + ci) * 6;
+                double y0[6];
+                bool fin = true;
+#pragma unroll
+                for (int cc = 0; cc < 6; ++cc) {
+                    y0[cc] = y0p[cc];
+                    fin = fin && isfinite(y0[cc]);
+                }
+                double y[6];
+                if (!(p.init == 0 && fin && pc_kepler(y0, w2 * (g.tau[j] + 1.0), y))) {
+#pragma unroll
+                    for (int cc = 0; cc < 6; ++cc) y[cc] = y0[cc];
+                }
+                double* f = sF + j * ROW + pc_fcol<PAIRS, NP>(j, grp * 16 + c);
+#pragma unroll
+                for (int cc = 0; cc < 6; ++cc) f[cc * T] = y[cc];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");   // staged points visible to the wave
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                if (!((rm >> col_of(e)) & 1u)) continue;
+#pragma unroll
+                for (int h = 0; h < Sh::H; ++h) {
+#pragma unroll
+                    for (int r = 0; r < (Sh::WIDE ? 1 : 4); ++r) {
+                        const int j = pc_node(L, h, r);
+                        if (j >= N) continue;
+                        const double* f = sF + j * ROW + pc_fcol<PAIRS, NP>(j, Sh::WIDE ? pc_ic(L, e) : (L.lane & 7));
+                        if constexpr (Sh::WIDE) {
+#pragma unroll
+                            for (int cc = 0; cc < 6; ++cc) yc[cc][e] = f[cc * T];
+                        } else {
+#pragma unroll
+                            for (int cb = 0; cb < 3; ++cb) yc[3 * h + cb][r] = f[(2 * cb + L.hi) * T];
+                        }
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");   // read before the slots are rewritten
+        };
+        // the owner lane of a column writes its IC's y0 (product epilogue) and checkpoint
+        auto own_column = [&](int en) {
+            const int64_t icg = ic_of(en);
+            const double* y0p = src + icg * 6;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                const double v = y0p[c];
+                sY0[c * T + grp * 16 + fcol] = v;
+                if (p.bounds_out) p.bounds_out[((size_t)icg * (p.iters_stride + 1) + s) * 6 + c] = v;
+            }
+        };
+
+        if (rec_lds) {
+            for (int i = tid; i < N * (P + 1); i += NT) {
+                const double4 q = grec[i];
+                sm.Rec[3 * i + 0] = q.x;
+                sm.Rec[3 * i + 1] = q.y;
+                sm.Rec[3 * i + 2] = q.z;
+                if (i < P) sm.Mu[i] = q.w;
+            }
+        }
+        for (int i = tid; i < 6 * PAIRS; i += NT) sF[i] = 0.0;   // rows past N stay zero
+        __syncthreads();   // records staged, F cleared
+        // the group's first COLS entries into its columns
+        int next = n_g < COLS ? n_g : COLS;                                   // uniform per group
+        unsigned amask = next >= COLS ? CMASK : ((1u << next) - 1u);          // uniform per group
+        int ent[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) ent[e] = col_of(e) < next ? col_of(e) : -1;
+        warm_columns(amask, 0);
+        int fent = fcol < next ? fcol : -1;   // flag lane: entry of its column
+        int it0 = 0;                          // flag lane: sweep before its IC's first one
+        if (owner && fent >= 0) own_column(fent);
+        __syncthreads();   // y0 written
+        if (amask) pc_publish<PAIRS, NP>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
+        __syncthreads();
+
+        for (int it = 1;; ++it) {
+            f64x4 acc[6];
+            const int flag = pc_product<PAIRS, NP, false>(sF, sY0, kp0, kpre, nullptr, yc, acc, w2, t2, 0.0,
+                                                          p.tol_mode, N, L);
+            if (L.lane < 16) sm.Flag[L.wave * 16 + L.lane] = flag;
+            __syncthreads();   // every wave is done reading F; flags complete
+
+            // stopping rule per IC (Sec. 2.2), taken identically by every wave of the group
+            int rec = 0;
+            if (flane && fent >= 0) {
+                const int f = pc_gather_flags<PAIRS, NP>(sm.Flag, grp * 16 + fcol);
+                const int k = it - it0;
+                if (f & 2) rec = -2;
+                else if (p.fixed_iters > 0) rec = (k == p.fixed_iters) ? k : 0;
+                else if (!(f & 1)) rec = k;
+                else if (k >= p.max_iter) rec = -1;
+            }
+            const unsigned smask = (unsigned)__ballot(rec != 0) & CMASK;
+            const unsigned dmask = (unsigned)__ballot(rec == -2) & CMASK;
+            if (owner && rec != 0) {
+                if (p.iters_out) p.iters_out[(size_t)ic_of(fent) * p.iters_stride + s] = rec;
+                if (rec == -1) ++notconv;
+            }
+            // the columns that were iterating take the new iterate
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const bool act = (amask >> col_of(e)) & 1u;
+#pragma unroll
+                for (int b = 0; b < 6; ++b) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        if (Sh::WIDE ? r == e : true) yc[b][r] = act ? acc[b][r] : yc[b][r];
+                    }
+                }
+            }
+            if (smask) {
+                // outputs of the ICs that stopped: node states, end state (node N-1, NaN when
+                // non-finite) as the next segment's y0 and the checkpoint
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int c = col_of(e);
+                    if (!((smask >> c) & 1u)) continue;
+                    const int64_t icg = ic_of(ent[e]);
+                    const bool dead = (dmask >> c) & 1u;
+#pragma unroll
+                    for (int h = 0; h < Sh::H; ++h) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            if (Sh::WIDE && r != e) continue;
+                            const int j = Sh::WIDE ? pc_node(L, 0, 0) : pc_node(L, h, r);
+                            if (j >= N) continue;
+                            double* nd = p.nodes_out
+                                             ? p.nodes_out + (((size_t)icg * p.iters_stride + s) * p.nodes_stride + j) * 6
+                                             : nullptr;
+                            double* so = j == N - 1 ? p.states_out + icg * 6 : nullptr;
+                            double* bo = (j == N - 1 && p.bounds_out)
+                                             ? p.bounds_out + ((size_t)icg * (p.iters_stride + 1) + s + 1) * 6
+                                             : nullptr;
+                            if constexpr (Sh::WIDE) {
+#pragma unroll
+                                for (int cc = 0; cc < 6; ++cc) {
+                                    if (nd) nd[cc] = yc[cc][e];
+                                    if (so) so[cc] = dead ? (double)NAN : yc[cc][e];
+                                    if (bo) bo[cc] = dead ? (double)NAN : yc[cc][e];
+                                }
+                            } else {
+#pragma unroll
+                                for (int cb = 0; cb < 3; ++cb) {
+                                    const int cc = 2 * cb + L.hi;
+                                    if (nd) nd[cc] = yc[3 * h + cb][r];
+                                    if (so) so[cc] = dead ? (double)NAN : yc[3 * h + cb][r];
+                                    if (bo) bo[cc] = dead ? (double)NAN : yc[3 * h + cb][r];
+                                }
+                            }
+                        }
+                    }
+                }
+                // refill: the stopped columns, in column order, take the group's next entries
+                const int take = min(__popc(smask), n_g - next);
+                unsigned rmask = 0u;
+                {
+                    unsigned m = smask;
+                    for (int k = 0; k < take; ++k) {
+                        rmask |= m & (0u - m);   // lowest stopped column
+                        m &= m - 1u;
+                    }
+                }
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int c = col_of(e);
+                    if ((rmask >> c) & 1u) ent[e] = next + __popc(rmask & ((1u << c) - 1u));
+                    else if ((smask >> c) & 1u) ent[e] = -1;
+                }
+                if (rmask) warm_columns(rmask, next);
+                if (flane) {
+                    if ((rmask >> fcol) & 1u) {
+                        fent = next + __popc(rmask & ((1u << fcol) - 1u));
+                        it0 = it;
+                        if (owner) own_column(fent);
+                    } else if ((smask >> fcol) & 1u) {
+                        fent = -1;
+                    }
+                }
+                next += take;
+                amask = (amask & ~smask) | rmask;
+            }
+            if (amask) pc_publish<PAIRS, NP>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
+            if (!__syncthreads_or(amask != 0u)) break;
+        }
+    }
+    if (notconv) atomicAdd(&p.counters[0], notconv);
+    __syncthreads();   // every end state written
+    for (int e = tid; e < n; e += NT) {
+        const double* y = p.states_out + (job.ic0 + e) * 6;
+        bool fin = true;
+        for (int c = 0; c < 6; ++c) fin = fin && isfinite(y[c]);
+        if (!fin) atomicAdd(&p.counters[1], 1);
+    }
+    __syncthreads();
+}
+
 // Persistent work-queue kernel: every workgroup takes the next job of the plan (jobs of
 // all groups and node counts, longest first) until the queue is empty, so one launch
 // runs an uneven two-level batch (Sec. 3.2) to completion.
@@ -318,13 +577,17 @@ __global__ __launch_bounds__(PAIRS / 4) void pc_fused_kernel(const PcParams* __r
         // private copies: with them the job bodies need not preserve the caller's registers
         const PcJobDev job = p.jobs[jb];
         const PcGroupDev g = p.groups[job.group];
+        const bool list = job.n > g.T;   // more ICs than columns: refilled columns (FP64 only)
         switch (g.NP) {
-        case 16: pc_job<PAIRS, 16>(p, job, g); break;
-        case 32: pc_job<PAIRS, 32>(p, job, g); break;
-        case 64: pc_job<PAIRS, 64>(p, job, g); break;
-        case 128: pc_job<PAIRS, 128>(p, job, g); break;
+        case 16: list ? pc_job_list<PAIRS, 16>(p, job, g) : pc_job<PAIRS, 16>(p, job, g); break;
+        case 32: list ? pc_job_list<PAIRS, 32>(p, job, g) : pc_job<PAIRS, 32>(p, job, g); break;
+        case 64: list ? pc_job_list<PAIRS, 64>(p, job, g) : pc_job<PAIRS, 64>(p, job, g); break;
+        case 128: list ? pc_job_list<PAIRS, 128>(p, job, g) : pc_job<PAIRS, 128>(p, job, g); break;
         case 256:
-            if constexpr (PAIRS >= 2048) pc_job<PAIRS, 256>(p, job, g);
+            if constexpr (PAIRS >= 2048) {
+                if (list) pc_job_list<PAIRS, 256>(p, job, g);
+                else pc_job<PAIRS, 256>(p, job, g);
+            }
             break;
         default: break;
         }

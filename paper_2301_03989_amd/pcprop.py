@@ -46,7 +46,7 @@ class _Opts(ctypes.Structure):
                 ("tol_mode", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("path", ctypes.c_int32), ("fixed_iters", ctypes.c_int32),
                 ("tile_pairs", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("switch_tol", ctypes.c_double), ("max_fp32", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("switch_tol", ctypes.c_double), ("max_fp32", ctypes.c_int32), ("job_list", ctypes.c_int32)]
 
 
 class _Group(ctypes.Structure):
@@ -186,12 +186,12 @@ class Context:
 
     @staticmethod
     def opts(init="kepler", max_iter=64, tol_mode="rel", path="fused", fixed_iters=0,
-             tile_pairs=0, precision="fp64", graph=False, switch_tol=0.0, max_fp32=0):
+             tile_pairs=0, precision="fp64", graph=False, switch_tol=0.0, max_fp32=0, job_list=0):
         o = _Opts()
         o.init, o.max_iter, o.tol_mode = INIT[init], int(max_iter), TOL_MODE[tol_mode]
         o.precision, o.path, o.fixed_iters = PRECISION[precision], PATH[path], int(fixed_iters)
         o.tile_pairs, o.graph = int(tile_pairs), int(bool(graph))
-        o.switch_tol, o.max_fp32, o.pad_ = float(switch_tol), int(max_fp32), 0
+        o.switch_tol, o.max_fp32, o.job_list = float(switch_tol), int(max_fp32), int(job_list)
         return o
 
     def workspace_bytes(self, groups, model, **opts):

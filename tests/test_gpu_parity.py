@@ -368,3 +368,74 @@ def test_node_states_every_job_shape(pc, nodes, tile):
     assert rel_err(r["nodes"].reshape(-1, 6), o["nodes"].reshape(-1, 6)).max() < 1e-12
     assert rel_err(r["bounds"].reshape(-1, 6), o["bounds"].reshape(-1, 6)).max() < 1e-12
     assert (r["iters"] == 6).all()
+
+
+# ---------------------------------------------------------------------------
+# jobs with more ICs than columns (refilled columns) against one-block jobs
+# ---------------------------------------------------------------------------
+def _eccentric(n, seed, nodes, segments, tol=1e-12):
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(0.7, 1.0, n)
+    e = rng.uniform(0.0, 0.6, n)
+    inc = rng.uniform(0.0, 10.0, n) * W.DEG
+    raan, argp, M = (rng.uniform(0.0, 360.0, n) * W.DEG for _ in range(3))
+    ics = W.elements_to_states(a, e, inc, raan, argp, M)
+    return W.Workload("ecc", ics, [W.Group(0, n, 0.0, segments * np.pi / 4, nodes, segments, tol)],
+                      W.planet_elements())
+
+
+@pytest.mark.parametrize("nodes,list_", [(24, 8), (64, 2), (100, 4), (128, 8), (200, 4)])
+def test_refilled_columns_match_one_block_jobs(pc, nodes, list_):
+    """Every IC's iterates do not depend on which column or job runs it: refilled-column
+    jobs give the one-block results (states, node states, checkpoints, sweep records), with
+    a ragged IC count and non-finite ICs among them.  Bit for bit on the transposed shapes
+    (up to 128 nodes); at 256 nodes the two job bodies are compiled with different
+    multiply-add contractions, so there the bar is rounding (1e-13)."""
+    w = _eccentric(301, 41, nodes, 3)
+    w.ics[[5, 77, 200]] = np.nan
+    a, _ = _run(pc, w, want_nodes=True, want_bounds=True, job_list=1)
+    b, _ = _run(pc, w, want_nodes=True, want_bounds=True, job_list=list_)
+    assert a["status"] == b["status"]
+    np.testing.assert_array_equal(a["iters"], b["iters"])
+    for k in ("states", "nodes", "bounds"):
+        np.testing.assert_array_equal(np.isnan(a[k]), np.isnan(b[k]))
+        if nodes <= 128:
+            np.testing.assert_array_equal(np.nan_to_num(a[k]), np.nan_to_num(b[k]))
+        else:
+            fin = np.isfinite(a[k]).reshape(-1, 6).all(axis=1)
+            x, y = a[k].reshape(-1, 6)[fin], b[k].reshape(-1, 6)[fin]
+            keep = np.linalg.norm(x[:, :3], axis=1) > 0   # unused node slots are zero
+            assert rel_err(y[keep], x[keep]).max() < 1e-13
+    assert (a["iters"][[5, 77, 200]] == -2).all()
+
+
+def test_refilled_columns_against_oracle_and_fixed_sweeps(pc):
+    w = _eccentric(150, 42, 64, 4)
+    r, _ = _run(pc, w, want_bounds=True, job_list=4)
+    o = oracle_run(w, want_bounds=True)
+    assert r["status"] == 0
+    assert rel_err(r["states"], o["states"]).max() < TOL
+    assert rel_err(r["bounds"].reshape(-1, 6), o["bounds"].reshape(-1, 6)).max() < TOL
+    assert np.abs(r["iters"] - o["iters"]).max() <= 1
+    f, _ = _run(pc, w, fixed_iters=5, job_list=8)
+    assert (f["iters"] == 5).all()
+    of = oracle_run(w, fixed_iters=5)
+    assert rel_err(f["states"], of["states"]).max() < 1e-12
+
+
+def test_refilled_columns_mixed_groups_and_status(pc):
+    """An uneven batch (three node counts, uneven sizes) with automatic job lists, and a
+    max_iter too small to converge (status and records as on one-block jobs)."""
+    w = W.uneven_batch(2000, seed=23)
+    for g in w.groups:
+        g.segments = 1 + g.segments // 20
+        g.tf = g.segments * np.pi / 4.0
+    a, _ = _run(pc, w, job_list=1)
+    b, _ = _run(pc, w, job_list=0)
+    assert rel_err(b["states"], a["states"]).max() < 1e-13
+    np.testing.assert_array_equal(a["iters"], b["iters"])
+    c, _ = _run(pc, w, job_list=1, max_iter=3)
+    d, _ = _run(pc, w, job_list=4, max_iter=3)
+    assert c["status"] == d["status"] == 2
+    np.testing.assert_array_equal(c["iters"], d["iters"])
+    assert rel_err(d["states"], c["states"]).max() < 1e-13
