@@ -599,10 +599,7 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_
     pp.init = o.init;
     pp.precision = o.precision;
     pp.max_fp32 = o.max_fp32 > 0 ? o.max_fp32 : 24;
-    {
-        const double sw = o.switch_tol > 0.0 ? o.switch_tol : 1e-4;
-        pp.switch2 = sw * sw;
-    }
+    pp.switch2 = o.switch_tol * o.switch_tol;   // 0: the kernel's default for the job's sweep kind
     pp.counters = reinterpret_cast<int32_t*>(ws + plan.off_counters);
     pp.queue = pp.counters + 2;
     std::memcpy(st + plan.off_params, &pp, sizeof(pp));   // the device copy the kernel reads

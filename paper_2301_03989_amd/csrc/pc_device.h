@@ -538,6 +538,94 @@ struct PcPairF {
     float a0, a1;
 };
 
+// Epilogue of a transposed (WIDE) product: acc <- base + w2 acc, where base is y0 (a Picard
+// sweep, INCR false) or the previous iterate itself (an increment sweep, INCR true); the
+// stopping-rule flags of Sec. 2.2 against the previous iterate yc, OR-ed over the strip's
+// nodes, returned by lane i < 16 for local IC i.
+template <int PAIRS, int NP, bool INCR>
+static __device__ __forceinline__ int pc_wide_epilogue(const double* sY0, const double (&yc)[6][4],
+                                                       f64x4 (&acc)[6], double w2, double t2, double sw2,
+                                                       int tol_mode, int N, const PcLane& L)
+{
+    constexpr int T = PcShape<PAIRS, NP>::T;
+    const bool node_ok = pc_node(L, 0, 0) < N;
+    int fr[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int m = pc_ic(L, r);
+        double pd = 0.0, py = 0.0, vd = 0.0, vy = 0.0;
+#pragma unroll
+        for (int b = 0; b < 6; ++b) {
+            const double yn = (INCR ? yc[b][r] : sY0[b * T + m]) + w2 * acc[b][r];
+            acc[b][r] = yn;
+            const double d = yn - yc[b][r];
+            if (b < 3) { pd += d * d; py += yn * yn; }
+            else { vd += d * d; vy += yn * yn; }
+        }
+        const bool ok = tol_mode == 0 ? (pd < t2 * py && vd < t2 * vy) : (pd < t2 && vd < t2);
+        const bool lo = tol_mode == 0 ? (pd < sw2 * py && vd < sw2 * vy) : (pd < sw2 && vd < sw2);
+        const bool nf = !isfinite(pd + py + vd + vy);
+        fr[r] = node_ok ? ((ok ? 0 : 1) | (nf ? 2 : 0) | (lo ? 0 : 4)) : 0;
+        // OR over the strip's 16 nodes (the lanes of one row group)
+        fr[r] |= __shfl_xor(fr[r], 1);
+        fr[r] |= __shfl_xor(fr[r], 2);
+        fr[r] |= __shfl_xor(fr[r], 4);
+        fr[r] |= __shfl_xor(fr[r], 8);
+    }
+    // lane i < 16 returns the flag of local IC i = (i & 3) + 4 (i >> 2), held by the lanes
+    // of row group i & 3 in element i >> 2
+    int flag = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int v = __shfl(fr[r], 16 * (L.lane & 3));
+        if (((L.lane >> 2) & 3) == r) flag = v;
+    }
+    return flag;
+}
+
+// Increment sweep of the precision schedule (WIDE shapes): Y_new = Y + w2 K_N dF with
+// dF = F(Y) - F(Y_prev) held in LDS as FP32 (sD, [node][comp 6][IC] with the column
+// swizzle of pc_fcol) and multiplied on the FP32 matrix cores; the sum into Y stays FP64.
+// In exact arithmetic this is the Picard sweep (Y = y0 + w2 K F(Y_prev) by induction);
+// the FP32 rounding is relative to the increment, so it shrinks as the sweeps converge
+// instead of leaving a floor at the FP32 precision of Y.  Returns the flags as pc_product.
+template <int PAIRS, int NP>
+static __device__ __forceinline__ int pc_product_incr(const float* sD, gconst_fp kp0f, const double (&yc)[6][4],
+                                                      f64x4 (&acc)[6], double w2, double t2, double sw2,
+                                                      int tol_mode, int N, const PcLane& L)
+{
+    using Sh = PcShape<PAIRS, NP>;
+    static_assert(Sh::WIDE, "increment sweeps run on WIDE job shapes");
+    constexpr int T = Sh::T, ROW = Sh::ROW, NQ = Sh::NQ;
+    const int lane = L.lane;
+    f32x4 accf[6];
+#pragma unroll
+    for (int b = 0; b < 6; ++b) accf[b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    // IC rows read in the order perm(i) = i/4 + 4 (i%4), so the f32 result layout puts IC
+    // l/16 + 4r in element r as the f64 one does
+    const int i = lane & 15, pi = (i >> 2) + 4 * (i & 3);
+    const float* bp[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        bp[u] = sD + (lane >> 4) * ROW + L.grp * 16 + (pi ^ ((4 * u + (lane >> 4)) & 15));
+    pc_kloop<NQ, 6, float, float, 3, 6, 1>(
+        [&](int q) { return kp0f[q * 64]; }, [&](int q) { return kp0f[q * 64]; },
+        [&](int q, int u, float (&bq)[6]) {
+#pragma unroll
+            for (int b = 0; b < 6; ++b) bq[b] = bp[u][q * 4 * ROW + b * T];
+        },
+        [&](float ka, const float (&bq)[6]) {
+#pragma unroll
+            for (int b = 0; b < 6; ++b) accf[b] = mfma16f(bq[b], ka, accf[b]);
+        });
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[b][r] = (double)accf[b][r];
+    }
+    return pc_wide_epilogue<PAIRS, NP, true>(nullptr, yc, acc, w2, t2, sw2, tol_mode, N, L);
+}
+
 // y_new = y0 + w2 K_N F on the matrix cores (Sec. 2.2 with A, C and S folded into K_N) for
 // the lane's six blocks, FP64 or (FP32) FP32 products accumulated into FP64; acc receives
 // y_new.  Also evaluates the stopping rule of Sec. 2.2 against the previous iterate yc in
@@ -625,38 +713,7 @@ static __device__ __forceinline__ int pc_product(const double* sF, const double*
                     for (int b = 0; b < 6; ++b) acc[b] = mfma16(bq[b], ka, acc[b]);
                 });
         }
-        const bool node_ok = pc_node(L, 0, 0) < N;
-        int fr[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int m = pc_ic(L, r);
-            double pd = 0.0, py = 0.0, vd = 0.0, vy = 0.0;
-#pragma unroll
-            for (int b = 0; b < 6; ++b) {
-                const double yn = sY0[b * T + m] + w2 * acc[b][r];
-                acc[b][r] = yn;
-                const double d = yn - yc[b][r];
-                if (b < 3) { pd += d * d; py += yn * yn; }
-                else { vd += d * d; vy += yn * yn; }
-            }
-            const bool ok = tol_mode == 0 ? (pd < t2 * py && vd < t2 * vy) : (pd < t2 && vd < t2);
-            const bool lo = tol_mode == 0 ? (pd < sw2 * py && vd < sw2 * vy) : (pd < sw2 && vd < sw2);
-            const bool nf = !isfinite(pd + py + vd + vy);
-            fr[r] = node_ok ? ((ok ? 0 : 1) | (nf ? 2 : 0) | (lo ? 0 : 4)) : 0;
-            // OR over the strip's 16 nodes (the lanes of one row group)
-            fr[r] |= __shfl_xor(fr[r], 1);
-            fr[r] |= __shfl_xor(fr[r], 2);
-            fr[r] |= __shfl_xor(fr[r], 4);
-            fr[r] |= __shfl_xor(fr[r], 8);
-        }
-        // lane i < 16 returns the flag of local IC i = (i & 3) + 4 (i >> 2), held by the
-        // lanes of row group i & 3 in element i >> 2
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int v = __shfl(fr[r], 16 * (lane & 3));
-            if (((lane >> 2) & 3) == r) flag = v;
-        }
-        return flag;
+        return pc_wide_epilogue<PAIRS, NP, false>(sY0, yc, acc, w2, t2, sw2, tol_mode, N, L);
     } else {
         if constexpr (!FP32) {
             gconst_dp kp1 = kp0 + (size_t)NQ * 64;
@@ -835,6 +892,52 @@ static __device__ __forceinline__ void pc_publish(double* sF, const double (&yc)
                 }
             }
         }
+    }
+}
+
+// Publish for an increment sweep (WIDE shapes): the FP64 force at the new iterate yc, the
+// change of F since the last publish, dF = (dv, a - a_old), rounded to FP32 into sD, and a
+// into sA ([node][3][IC], FP64, read back only by the same lane).  dv is the change of the
+// velocities.  a_old comes from sA, or (FROM_F) from the registers of the caller, which
+// read it from the FP64 force array that sD and sA now overwrite.
+template <int PAIRS, int NP>
+static __device__ __forceinline__ void pc_publish_incr(float* sD, double* sA, const double (&yc)[6][4],
+                                                       const double (&dv)[3][4], const double (&aold)[3][4],
+                                                       bool aold_given, const PcLane& L, int N, int P,
+                                                       double mu_sun, const double* sRec, const double* sMu)
+{
+    using Sh = PcShape<PAIRS, NP>;
+    static_assert(Sh::WIDE, "increment sweeps run on WIDE job shapes");
+    constexpr int T = Sh::T, ROW = Sh::ROW;
+    const int j = pc_node(L, 0, 0);
+    if (j >= N) {   // rows past N meet zero operator columns: keep them zero (no stale NaN bits)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            float* d = sD + j * ROW + pc_fcol<PAIRS, NP>(j, pc_ic(L, r));
+#pragma unroll
+            for (int c = 0; c < 6; ++c) d[c * T] = 0.0f;
+        }
+        return;
+    }
+    double ax[4], ay[4], az[4];
+    pc_force_lds_node<4>(yc[0], yc[1], yc[2], j, P, mu_sun, sRec, sMu, ax, ay, az);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int col = pc_fcol<PAIRS, NP>(j, pc_ic(L, r));
+        double* a = sA + j * 3 * T + col;
+        const double a0 = aold_given ? aold[0][r] : a[0];
+        const double a1 = aold_given ? aold[1][r] : a[T];
+        const double a2 = aold_given ? aold[2][r] : a[2 * T];
+        float* d = sD + j * ROW + col;
+        d[0 * T] = (float)dv[0][r];
+        d[1 * T] = (float)dv[1][r];
+        d[2 * T] = (float)dv[2][r];
+        d[3 * T] = (float)(ax[r] - a0);
+        d[4 * T] = (float)(ay[r] - a1);
+        d[5 * T] = (float)(az[r] - a2);
+        a[0] = ax[r];
+        a[T] = ay[r];
+        a[2 * T] = az[r];
     }
 }
 

@@ -80,7 +80,9 @@ __device__ __forceinline__ PcSmem<1024>& pc_smem<1024>() { return g_smem1024; }
 // records into LDS, initial guess, then sweeps until every IC of the job has stopped.
 // On return yc holds the lane's share of the final iterate.  iters_out (may be null)
 // receives the iteration records.
-template <int PAIRS, int NP>
+// MIXED: the job runs the FP32 -> FP64 precision schedule (compiled apart, so that FP64-only
+// jobs carry none of its registers).
+template <int PAIRS, int NP, bool MIXED = false>
 static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const PcGroupDev& g, int n, int64_t ic0,
                                                         int s, PcSmem<PAIRS>& sm, const PcLane& L, gconst_dp kp0,
                                                         double (&yc)[6][4], int32_t* iters_out, int& had_notconv,
@@ -138,14 +140,23 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
     __syncthreads();   // staging read before F is rebuilt
     for (int i = tid; i < 6 * PAIRS; i += NT) sF[i] = 0.0;
     __syncthreads();
-    // precision schedule (uniform per job): FP32 sweeps first when asked, then FP64
-    bool fp32 = p.precision == 1;
+    // precision schedule (uniform per job): an FP32 phase first when asked, then FP64
+    // sweeps.  Sweep kinds: 0 FP64 Picard sweep, 1 FP32 Picard sweep (8-IC jobs),
+    // 2 FP32 increment sweep (WIDE jobs, after one FP64 sweep; records in LDS).
+    bool fp32 = MIXED;
+    const bool incr = Sh::WIDE && rec_lds;
+    int mode = (fp32 && !incr) ? 1 : 0;
+    // default switch: increment sweeps stay accurate to a relative change of ~1e-9 (their
+    // rounding is relative to the increment); FP32 Picard sweeps stall near 1e-7
+    const double sw2 = p.switch2 > 0.0 ? p.switch2 : (incr ? 1e-18 : 1e-8);
     int n32 = 0;
+    float* sD = reinterpret_cast<float*>(sF);   // increment sweeps: dF, FP32
+    double* sA = sF + 3 * PAIRS;                 // increment sweeps: a of the last publish
     int act[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) act[r] = sm.Active[pc_ic(L, r)];
     if (act[0] | act[1] | act[2] | act[3]) {
-        if (fp32) pc_publish<PAIRS, NP, true>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
+        if (MIXED && mode == 1) pc_publish<PAIRS, NP, MIXED>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
         else pc_publish<PAIRS, NP>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
     }
     __syncthreads();
@@ -158,10 +169,22 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
     for (int it = 1; it <= n_it; ++it) {
         // (1)-(2) product and stopping-rule flags
         f64x4 acc[6];
-        const int flag = fp32 ? pc_product<PAIRS, NP, true>(sF, sY0, kp0, kpre, kp0f, yc, acc, w2, t2, p.switch2,
-                                                              p.tol_mode, N, L)
-                              : pc_product<PAIRS, NP, false>(sF, sY0, kp0, kpre, kp0f, yc, acc, w2, t2, p.switch2,
-                                                               p.tol_mode, N, L);
+        int flag;
+        if constexpr (MIXED && Sh::WIDE) {
+            if (mode == 2)
+                flag = pc_product_incr<PAIRS, NP>(sD, kp0f, yc, acc, w2, t2, sw2, p.tol_mode, N, L);
+            else
+                flag = pc_product<PAIRS, NP, false>(sF, sY0, kp0, kpre, kp0f, yc, acc, w2, t2, sw2,
+                                                    p.tol_mode, N, L);
+        } else if constexpr (MIXED) {
+            flag = mode == 1 ? pc_product<PAIRS, NP, true>(sF, sY0, kp0, kpre, kp0f, yc, acc, w2, t2, sw2,
+                                                           p.tol_mode, N, L)
+                             : pc_product<PAIRS, NP, false>(sF, sY0, kp0, kpre, kp0f, yc, acc, w2, t2,
+                                                            sw2, p.tol_mode, N, L);
+        } else {
+            flag = pc_product<PAIRS, NP, false>(sF, sY0, kp0, kpre, kp0f, yc, acc, w2, t2, sw2, p.tol_mode,
+                                                N, L);
+        }
         if (L.lane < 16) sm.Flag[L.wave * 16 + L.lane] = flag;
 #pragma unroll
         for (int r = 0; r < 4; ++r) act[r] = sm.Active[pc_ic(L, r)];
@@ -194,7 +217,42 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
                 if (tid < n && iters_out) iters_out[(size_t)ic * p.iters_stride + s] = rec;
             }
         }
-        // (4) ICs that were iterating take the new iterate and publish its F
+        const int next_mode = next32 ? (incr ? 2 : 1) : 0;
+        // (4) ICs that were iterating take the new iterate and publish its F (or, before an
+        //     increment sweep, the change of F)
+        if constexpr (MIXED && Sh::WIDE) {
+            if (next_mode == 2 && it < n_it) {
+                double dv[3][4], aold[3][4];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) dv[c][r] = act[r] ? acc[3 + c][r] - yc[3 + c][r] : 0.0;
+                }
+                const bool from_f = mode != 2;   // first increment: a of the FP64 force array
+                if (from_f) {
+                    const int j = pc_node(L, 0, 0);
+                    const int jj = j < N ? j : N - 1;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const double* f = sF + jj * Sh::ROW + pc_fcol<PAIRS, NP>(jj, pc_ic(L, r));
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) aold[c][r] = f[(3 + c) * T];
+                    }
+                    __syncthreads();   // every lane has its a before the array is rewritten
+                }
+#pragma unroll
+                for (int b = 0; b < 6; ++b) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) yc[b][r] = act[r] ? acc[b][r] : yc[b][r];
+                }
+                pc_publish_incr<PAIRS, NP>(sD, sA, yc, dv, aold, from_f, L, N, P, p.mu_sun, sm.Rec, sm.Mu);
+                fp32 = next32;
+                mode = next_mode;
+                const int any = __syncthreads_or(tid < T ? sm.Active[tid] : 0);
+                if (!any) break;
+                continue;
+            }
+        }
         if (act[0] | act[1] | act[2] | act[3]) {
 #pragma unroll
             for (int b = 0; b < 6; ++b) {
@@ -202,11 +260,13 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
                 for (int r = 0; r < 4; ++r) yc[b][r] = act[r] ? acc[b][r] : yc[b][r];
             }
             if (it < n_it) {
-                if (next32) pc_publish<PAIRS, NP, true>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
+                if (MIXED && next_mode == 1)
+                    pc_publish<PAIRS, NP, MIXED>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
                 else pc_publish<PAIRS, NP>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
             }
         }
         fp32 = next32;
+        mode = next_mode;
         const int any = __syncthreads_or(tid < T ? sm.Active[tid] : 0);
         if (!any) break;
     }
@@ -214,7 +274,7 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
 
 // Not inlined: one register allocation per node count, so the work-queue kernel that
 // dispatches to all of them does not pay for the largest one everywhere.
-template <int PAIRS, int NP>
+template <int PAIRS, int NP, bool MIXED>
 __device__ __attribute__((noinline)) void pc_job(const PcParams& p, const PcJobDev& job, const PcGroupDev& g)
 {
     PcSmem<PAIRS>& sm = pc_smem<PAIRS>();
@@ -251,7 +311,7 @@ __device__ __attribute__((noinline)) void pc_job(const PcParams& p, const PcJobD
             }
             if (sm.Dead[tid] && p.iters_out) p.iters_out[(size_t)ic * p.iters_stride + s] = -2;
         }
-        pc_segment_solve<PAIRS, NP>(p, g, n, job.ic0, s, sm, L, kp0, yc, p.iters_out, had_notconv);
+        pc_segment_solve<PAIRS, NP, MIXED>(p, g, n, job.ic0, s, sm, L, kp0, yc, p.iters_out, had_notconv);
 
         // converged node states of the segment (optional output), chaining (Sec. 2.2)
 #pragma unroll
@@ -578,15 +638,33 @@ __global__ __launch_bounds__(PAIRS / 4) void pc_fused_kernel(const PcParams* __r
         const PcJobDev job = p.jobs[jb];
         const PcGroupDev g = p.groups[job.group];
         const bool list = job.n > g.T;   // more ICs than columns: refilled columns (FP64 only)
+        const bool mixed = p.precision == 1;
         switch (g.NP) {
-        case 16: list ? pc_job_list<PAIRS, 16>(p, job, g) : pc_job<PAIRS, 16>(p, job, g); break;
-        case 32: list ? pc_job_list<PAIRS, 32>(p, job, g) : pc_job<PAIRS, 32>(p, job, g); break;
-        case 64: list ? pc_job_list<PAIRS, 64>(p, job, g) : pc_job<PAIRS, 64>(p, job, g); break;
-        case 128: list ? pc_job_list<PAIRS, 128>(p, job, g) : pc_job<PAIRS, 128>(p, job, g); break;
+        case 16:
+            if (list) pc_job_list<PAIRS, 16>(p, job, g);
+            else if (mixed) pc_job<PAIRS, 16, true>(p, job, g);
+            else pc_job<PAIRS, 16, false>(p, job, g);
+            break;
+        case 32:
+            if (list) pc_job_list<PAIRS, 32>(p, job, g);
+            else if (mixed) pc_job<PAIRS, 32, true>(p, job, g);
+            else pc_job<PAIRS, 32, false>(p, job, g);
+            break;
+        case 64:
+            if (list) pc_job_list<PAIRS, 64>(p, job, g);
+            else if (mixed) pc_job<PAIRS, 64, true>(p, job, g);
+            else pc_job<PAIRS, 64, false>(p, job, g);
+            break;
+        case 128:
+            if (list) pc_job_list<PAIRS, 128>(p, job, g);
+            else if (mixed) pc_job<PAIRS, 128, true>(p, job, g);
+            else pc_job<PAIRS, 128, false>(p, job, g);
+            break;
         case 256:
             if constexpr (PAIRS >= 2048) {
                 if (list) pc_job_list<PAIRS, 256>(p, job, g);
-                else pc_job<PAIRS, 256>(p, job, g);
+                else if (mixed) pc_job<PAIRS, 256, true>(p, job, g);
+                else pc_job<PAIRS, 256, false>(p, job, g);
             }
             break;
         default: break;
