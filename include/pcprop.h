@@ -94,7 +94,7 @@ typedef struct {
                              propagation kernel, status copy) in a HIP graph and replay it while
                              the call's shapes, options and pointers repeat (default 0) */
     double switch_tol;    /* PC_FP32_THEN_FP64: relative change below which a job leaves FP32
-                             (0 = default: 1e-9 for FP32 increment sweeps, 1e-4 for FP32
+                             (0 = default: 1e-8 for FP32 increment sweeps, 1e-4 for FP32
                              Picard sweeps of 8-IC jobs) */
     int32_t max_fp32;     /* PC_FP32_THEN_FP64: cap on FP32 sweeps per segment (0 = default 24) */
     int32_t job_list;     /* fused FP64 forward calls: ICs per job in units of its column block

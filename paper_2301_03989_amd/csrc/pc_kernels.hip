@@ -146,9 +146,10 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
     bool fp32 = MIXED;
     const bool incr = Sh::WIDE && rec_lds;
     int mode = (fp32 && !incr) ? 1 : 0;
-    // default switch: increment sweeps stay accurate to a relative change of ~1e-9 (their
-    // rounding is relative to the increment); FP32 Picard sweeps stall near 1e-7
-    const double sw2 = p.switch2 > 0.0 ? p.switch2 : (incr ? 1e-18 : 1e-8);
+    // default switch: increment sweeps keep converging to a relative change of ~1e-9 (their
+    // rounding is relative to the increment), but their summed FP32 rounding grows when they
+    // run that far, so they hand over at 1e-8; FP32 Picard sweeps stall near 1e-7
+    const double sw2 = p.switch2 > 0.0 ? p.switch2 : (incr ? 1e-16 : 1e-8);
     int n32 = 0;
     float* sD = reinterpret_cast<float*>(sF);   // increment sweeps: dF, FP32
     double* sA = sF + 3 * PAIRS;                 // increment sweeps: a of the last publish
