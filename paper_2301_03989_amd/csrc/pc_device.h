@@ -139,6 +139,20 @@ static __device__ __forceinline__ double pc_rsqrt(double x)
     return fma(y * e, fma(e, 0.375, 0.5), y);
 }
 
+// mu / x^(3/2) in full FP64 for finite x > 0, the attraction factor of a point mass at
+// squared distance x: from the hardware estimate y of 1/sqrt(x) and e = 1 - x y^2 (x y^2
+// with y^2 rounded), x^(-3/2) = (y^2)^(3/2) (1 - e)^(-3/2) = y^3 (1 + 3e/2 + 15e^2/8 + O(e^3)).
+// The series coefficients come premultiplied into the mass (mu1 = 3 mu / 2,
+// mu2 = 15 mu / 8), so a point-body pair costs six operations after the estimate.  With
+// |e| near 2^-22 the dropped terms are below 2^-63 relative.
+static __device__ __forceinline__ double pc_mu_r3(double x, double mu, double mu1, double mu2)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    const double t = y * y;
+    const double e = fma(-x, t, 1.0);
+    return (y * t) * fma(e, fma(mu2, e, mu1), mu);
+}
+
 // ---------------------------------------------------------------------------
 // Force model: point masses in the heliocentric frame with the indirect term,
 //   a = -mu_S r/|r|^3 - sum_p mu_p (r - r_p)/|r - r_p|^3 - sum_p mu_p r_p/|r_p|^3.
@@ -148,17 +162,14 @@ static __device__ __forceinline__ void pc_accel(double x, double y, double z, co
                                                 int P, double mu_sun, double& ax, double& ay,
                                                 double& az)
 {
-    const double r2 = x * x + y * y + z * z;
-    const double ir = pc_rsqrt(r2);
-    const double s = mu_sun * (ir * ir * ir);
+    const double s = pc_mu_r3(x * x + y * y + z * z, mu_sun, 1.5 * mu_sun, 1.875 * mu_sun);
     ax = -s * x;
     ay = -s * y;
     az = -s * z;
     for (int p = 0; p < P; ++p) {
         const double4 q = rec[p];
         const double dx = x - q.x, dy = y - q.y, dz = z - q.z;
-        const double id = pc_rsqrt(dx * dx + dy * dy + dz * dz);
-        const double sd = q.w * (id * id * id);
+        const double sd = pc_mu_r3(dx * dx + dy * dy + dz * dz, q.w, 1.5 * q.w, 1.875 * q.w);
         ax -= sd * dx;
         ay -= sd * dy;
         az -= sd * dz;
@@ -183,12 +194,38 @@ struct PcSmem {
     double F[6 * PAIRS];          // [node][F comp 6][IC]: velocity (0..2), acceleration (3..5)
     double Rec[REC];              // [node][body 0..P][3]: perturber positions, then the indirect term
     double Y0[6 * (PAIRS / 16)];  // [comp][IC] initial state of the current segment
-    double Mu[PC_MAX_PERT_DEV];   // perturber parameters
+    double Mu[3 * PC_MAX_PERT_DEV];   // perturber mu, then 3 mu / 2, then 15 mu / 8 (pc_mu_r3)
     int Flag[(PAIRS / 256) * 16]; // per wave, per IC: bit 0 not converged, bit 1 non-finite, bit 2 large change
     int Keep[PAIRS / 256];        // per wave: an iterating IC still changes by more than the FP32 switch
+    int Go[PAIRS / 256];          // per wave (or IC group): some IC still iterates after this sweep
     int Active[PAIRS / 16];
     int Dead[PAIRS / 16];
 };
+
+// After the stopping rule (taken by threads tid < T on their IC's status word), the waves
+// that hold status words note whether some IC still iterates; the barrier that ends the
+// sweep makes the notes visible to every wave (one barrier instead of a barrier-reduction).
+// The notes are rewritten only after the next sweep's first barrier, when every wave has
+// read them.
+template <int PAIRS, int NP, class Lane>
+static __device__ __forceinline__ void pc_note_active(PcSmem<PAIRS>& sm, const Lane& L)
+{
+    constexpr int T = PAIRS / NP;
+    if (L.wave * 64 < T) {
+        const int tid = L.wave * 64 + L.lane;
+        const unsigned long long b = __ballot(tid < T && sm.Active[tid]);
+        if (L.lane == 0) sm.Go[L.wave] = b != 0ull;
+    }
+}
+template <int PAIRS, int NP>
+static __device__ __forceinline__ bool pc_any_active(const PcSmem<PAIRS>& sm)
+{
+    constexpr int T = PAIRS / NP;
+    int a = 0;
+#pragma unroll
+    for (int w = 0; w < (T + 63) / 64; ++w) a |= sm.Go[w];
+    return a != 0;
+}
 
 // The same for R points at one node j (the transposed job layout): the bodies go in
 // chunks of four whose records are read together, so the wave waits on LDS once per chunk;
@@ -202,18 +239,20 @@ static __device__ __forceinline__ void pc_force_lds_node(const double (&x)[R], c
     const double* rec = srec + j * 3 * (P + 1);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const double ir = pc_rsqrt(x[r] * x[r] + y[r] * y[r] + z[r] * z[r]);
-        const double s = mu_sun * (ir * ir * ir);
+        const double s = pc_mu_r3(x[r] * x[r] + y[r] * y[r] + z[r] * z[r], mu_sun, 1.5 * mu_sun, 1.875 * mu_sun);
         ax[r] = -s * x[r];
         ay[r] = -s * y[r];
         az[r] = -s * z[r];
     }
     for (int b0 = 0; b0 < P; b0 += 4) {
-        double qx[4], qy[4], qz[4], mu[4];
+        double qx[4], qy[4], qz[4], mu[4], mu1[4], mu2[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int b = b0 + k < P ? b0 + k : P;
-            mu[k] = b0 + k < P ? smu[b0 + k < P ? b0 + k : 0] : 0.0;
+            const int bm = b0 + k < P ? b0 + k : 0;
+            mu[k] = b0 + k < P ? smu[bm] : 0.0;
+            mu1[k] = b0 + k < P ? smu[PC_MAX_PERT_DEV + bm] : 0.0;
+            mu2[k] = b0 + k < P ? smu[2 * PC_MAX_PERT_DEV + bm] : 0.0;
             qx[k] = rec[3 * b];
             qy[k] = rec[3 * b + 1];
             qz[k] = rec[3 * b + 2];
@@ -223,8 +262,7 @@ static __device__ __forceinline__ void pc_force_lds_node(const double (&x)[R], c
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const double dx = x[r] - qx[k], dy = y[r] - qy[k], dz = z[r] - qz[k];
-                const double id = pc_rsqrt(dx * dx + dy * dy + dz * dz);
-                const double sd = mu[k] * (id * id * id);
+                const double sd = pc_mu_r3(dx * dx + dy * dy + dz * dz, mu[k], mu1[k], mu2[k]);
                 ax[r] -= sd * dx;
                 ay[r] -= sd * dy;
                 az[r] -= sd * dz;
@@ -249,20 +287,18 @@ static __device__ __forceinline__ void pc_force_lds(const double (&x)[R], const 
     const int stride = 3 * (P + 1);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const double ir = pc_rsqrt(x[r] * x[r] + y[r] * y[r] + z[r] * z[r]);
-        const double s = mu_sun * (ir * ir * ir);
+        const double s = pc_mu_r3(x[r] * x[r] + y[r] * y[r] + z[r] * z[r], mu_sun, 1.5 * mu_sun, 1.875 * mu_sun);
         ax[r] = -s * x[r];
         ay[r] = -s * y[r];
         az[r] = -s * z[r];
     }
     for (int b = 0; b < P; ++b) {
-        const double mu = smu[b];
+        const double mu = smu[b], mu1 = smu[PC_MAX_PERT_DEV + b], mu2 = smu[2 * PC_MAX_PERT_DEV + b];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const double* q = srec + jr[r] * stride + 3 * b;
             const double dx = x[r] - q[0], dy = y[r] - q[1], dz = z[r] - q[2];
-            const double id = pc_rsqrt(dx * dx + dy * dy + dz * dz);
-            const double sd = mu * (id * id * id);
+            const double sd = pc_mu_r3(dx * dx + dy * dy + dz * dz, mu, mu1, mu2);
             ax[r] -= sd * dx;
             ay[r] -= sd * dy;
             az[r] -= sd * dz;
@@ -327,8 +363,7 @@ static __device__ __forceinline__ void pc_force_glb(const double (&x)[R], const 
 {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const double ir = pc_rsqrt(x[r] * x[r] + y[r] * y[r] + z[r] * z[r]);
-        const double s = mu_sun * (ir * ir * ir);
+        const double s = pc_mu_r3(x[r] * x[r] + y[r] * y[r] + z[r] * z[r], mu_sun, 1.5 * mu_sun, 1.875 * mu_sun);
         ax[r] = -s * x[r];
         ay[r] = -s * y[r];
         az[r] = -s * z[r];
@@ -340,8 +375,7 @@ static __device__ __forceinline__ void pc_force_glb(const double (&x)[R], const 
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const double dx = x[r] - q[r].x, dy = y[r] - q[r].y, dz = z[r] - q[r].z;
-            const double id = pc_rsqrt(dx * dx + dy * dy + dz * dz);
-            const double sd = q[r].w * (id * id * id);
+            const double sd = pc_mu_r3(dx * dx + dy * dy + dz * dz, q[r].w, 1.5 * q[r].w, 1.875 * q[r].w);
             ax[r] -= sd * dx;
             ay[r] -= sd * dy;
             az[r] -= sd * dz;
@@ -497,8 +531,7 @@ static __device__ __forceinline__ void pc_kloop(LA0 loadA0, LA loadA, LB loadB, 
 #pragma unroll
     for (int u = 0; u < DK; ++u) ka[u] = loadA0(u);
     loadB(0, 0, bb[0]);
-#pragma unroll 1
-    for (int q0 = 0; q0 < NQ - DK; q0 += DK) {
+    auto steps = [&](int q0) {
 #pragma unroll
         for (int u = 0; u < DK; ++u) {
             loadB(q0 + u + 1, (u + 1) & 3, bb[(u + 1) & 1]);
@@ -510,7 +543,13 @@ static __device__ __forceinline__ void pc_kloop(LA0 loadA0, LA loadA, LB loadB, 
                 __builtin_amdgcn_sched_group_barrier(0x020, SG_VMEM, 0);   // VMEM reads
             }
         }
-    }
+    };
+    // the first DK steps outside the loop: their products start from the caller's
+    // accumulators directly (a zero start becomes the MFMA's inline constant instead of
+    // register moves on every sweep)
+    if constexpr (NQ > DK) steps(0);
+#pragma unroll 1
+    for (int q0 = DK; q0 < NQ - DK; q0 += DK) steps(q0);
 #pragma unroll
     for (int u = 0; u < DK; ++u) {   // the last DK steps load nothing past the end
         if (u + 1 < DK) loadB(NQ - DK + u + 1, (u + 1) & 3, bb[(u + 1) & 1]);
@@ -538,18 +577,31 @@ struct PcPairF {
     float a0, a1;
 };
 
+// Stopping-rule thresholds in fma form, fixed per segment: a squared change d2 passes
+// against the squared norm y2 when d2 < a y2 + b, with (a, b) = (tol^2, 0) for the relative
+// rule and (0, tol^2) for the absolute one (the same comparisons as d2 < tol^2 y2 and
+// d2 < tol^2 for finite norms, with no branch on the mode).  (sa, sb): the same for the
+// precision switch.
+struct PcTol {
+    double ta, tb, sa, sb;
+};
+static __device__ __forceinline__ PcTol pc_tol(int tol_mode, double t2, double sw2)
+{
+    return tol_mode == 0 ? PcTol{t2, 0.0, sw2, 0.0} : PcTol{0.0, t2, 0.0, sw2};
+}
+
 // Epilogue of a transposed (WIDE) product: acc <- base + w2 acc, where base is y0 (a Picard
 // sweep, INCR false) or the previous iterate itself (an increment sweep, INCR true); the
 // stopping-rule flags of Sec. 2.2 against the previous iterate yc, OR-ed over the strip's
-// nodes, returned by lane i < 16 for local IC i.
-template <int PAIRS, int NP, bool INCR>
+// nodes, returned by lane i < 16 for local IC i.  SW: evaluate the switch test (bit 2).
+template <int PAIRS, int NP, bool INCR, bool SW = true>
 static __device__ __forceinline__ int pc_wide_epilogue(const double* sY0, const double (&yc)[6][4],
-                                                       f64x4 (&acc)[6], double w2, double t2, double sw2,
-                                                       int tol_mode, int N, const PcLane& L)
+                                                       f64x4 (&acc)[6], double w2, const PcTol& tl, int N,
+                                                       const PcLane& L)
 {
     constexpr int T = PcShape<PAIRS, NP>::T;
     const bool node_ok = pc_node(L, 0, 0) < N;
-    int fr[4];
+    int fr = 0;   // element r's flags in bits 4r..4r+2
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int m = pc_ic(L, r);
@@ -562,25 +614,21 @@ static __device__ __forceinline__ int pc_wide_epilogue(const double* sY0, const 
             if (b < 3) { pd += d * d; py += yn * yn; }
             else { vd += d * d; vy += yn * yn; }
         }
-        const bool ok = tol_mode == 0 ? (pd < t2 * py && vd < t2 * vy) : (pd < t2 && vd < t2);
-        const bool lo = tol_mode == 0 ? (pd < sw2 * py && vd < sw2 * vy) : (pd < sw2 && vd < sw2);
-        const bool nf = !isfinite(pd + py + vd + vy);
-        fr[r] = node_ok ? ((ok ? 0 : 1) | (nf ? 2 : 0) | (lo ? 0 : 4)) : 0;
-        // OR over the strip's 16 nodes (the lanes of one row group)
-        fr[r] |= __shfl_xor(fr[r], 1);
-        fr[r] |= __shfl_xor(fr[r], 2);
-        fr[r] |= __shfl_xor(fr[r], 4);
-        fr[r] |= __shfl_xor(fr[r], 8);
+        const bool ok = pd < fma(tl.ta, py, tl.tb) && vd < fma(tl.ta, vy, tl.tb);
+        const bool lo = !SW || (pd < fma(tl.sa, py, tl.sb) && vd < fma(tl.sa, vy, tl.sb));
+        // the previous iterate is finite, so a non-finite change shows in the new norms
+        const bool nf = !isfinite(py + vy);
+        fr |= ((ok ? 0 : 1) | (nf ? 2 : 0) | (lo ? 0 : 4)) << (4 * r);
     }
+    if (!node_ok) fr = 0;
+    // OR over the strip's 16 nodes (the lanes of one row group)
+    fr |= __shfl_xor(fr, 1);
+    fr |= __shfl_xor(fr, 2);
+    fr |= __shfl_xor(fr, 4);
+    fr |= __shfl_xor(fr, 8);
     // lane i < 16 returns the flag of local IC i = (i & 3) + 4 (i >> 2), held by the lanes
     // of row group i & 3 in element i >> 2
-    int flag = 0;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int v = __shfl(fr[r], 16 * (L.lane & 3));
-        if (((L.lane >> 2) & 3) == r) flag = v;
-    }
-    return flag;
+    return (__shfl(fr, 16 * (L.lane & 3)) >> (4 * ((L.lane >> 2) & 3))) & 7;
 }
 
 // Increment sweep of the precision schedule (WIDE shapes): Y_new = Y + w2 K_N dF with
@@ -591,8 +639,8 @@ static __device__ __forceinline__ int pc_wide_epilogue(const double* sY0, const 
 // instead of leaving a floor at the FP32 precision of Y.  Returns the flags as pc_product.
 template <int PAIRS, int NP>
 static __device__ __forceinline__ int pc_product_incr(const float* sD, gconst_fp kp0f, const double (&yc)[6][4],
-                                                      f64x4 (&acc)[6], double w2, double t2, double sw2,
-                                                      int tol_mode, int N, const PcLane& L)
+                                                      f64x4 (&acc)[6], double w2, const PcTol& tl, int N,
+                                                      const PcLane& L)
 {
     using Sh = PcShape<PAIRS, NP>;
     static_assert(Sh::WIDE, "increment sweeps run on WIDE job shapes");
@@ -623,7 +671,7 @@ static __device__ __forceinline__ int pc_product_incr(const float* sD, gconst_fp
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[b][r] = (double)accf[b][r];
     }
-    return pc_wide_epilogue<PAIRS, NP, true>(nullptr, yc, acc, w2, t2, sw2, tol_mode, N, L);
+    return pc_wide_epilogue<PAIRS, NP, true>(nullptr, yc, acc, w2, tl, N, L);
 }
 
 // y_new = y0 + w2 K_N F on the matrix cores (Sec. 2.2 with A, C and S folded into K_N) for
@@ -633,12 +681,12 @@ static __device__ __forceinline__ int pc_product_incr(const float* sD, gconst_fp
 // mode) and returns in lanes 0..15 the flags of IC pc_flag_ic, OR-ed over its nodes:
 // bit 0 = some node not converged, bit 1 = non-finite, bit 2 = some node changed by more
 // than sqrt(sw2) (relative).  WIDE blocks are computed as (K_N F)^T = F^T K_N^T: the F
-// slice is the A operand and the K_N fragment the B operand.
-template <int PAIRS, int NP, bool FP32 = false>
+// slice is the A operand and the K_N fragment the B operand.  SW: evaluate bit 2.
+template <int PAIRS, int NP, bool FP32 = false, bool SW = true>
 static __device__ __forceinline__ int pc_product(const double* sF, const double* sY0, gconst_dp kp0,
                                                   const double (&kpre)[8], gconst_fp kp0f,
                                                   const double (&yc)[6][4], f64x4 (&acc)[6],
-                                                  double w2, double t2, double sw2, int tol_mode, int N,
+                                                  double w2, const PcTol& tl, int N,
                                                   const PcLane& L)
 {
     using Sh = PcShape<PAIRS, NP>;
@@ -713,7 +761,7 @@ static __device__ __forceinline__ int pc_product(const double* sF, const double*
                     for (int b = 0; b < 6; ++b) acc[b] = mfma16(bq[b], ka, acc[b]);
                 });
         }
-        return pc_wide_epilogue<PAIRS, NP, false>(sY0, yc, acc, w2, t2, sw2, tol_mode, N, L);
+        return pc_wide_epilogue<PAIRS, NP, false, SW>(sY0, yc, acc, w2, tl, N, L);
     } else {
         if constexpr (!FP32) {
             gconst_dp kp1 = kp0 + (size_t)NQ * 64;
@@ -756,9 +804,9 @@ static __device__ __forceinline__ int pc_product(const double* sF, const double*
                 vd += __shfl_xor(vd, 8);
                 vy += __shfl_xor(vy, 8);
                 if (j < N) {
-                    const bool ok = tol_mode == 0 ? (pd < t2 * py && vd < t2 * vy) : (pd < t2 && vd < t2);
-                    const bool lo = tol_mode == 0 ? (pd < sw2 * py && vd < sw2 * vy) : (pd < sw2 && vd < sw2);
-                    const bool nf = !isfinite(pd + py + vd + vy);
+                    const bool ok = pd < fma(tl.ta, py, tl.tb) && vd < fma(tl.ta, vy, tl.tb);
+                    const bool lo = !SW || (pd < fma(tl.sa, py, tl.sb) && vd < fma(tl.sa, vy, tl.sb));
+                    const bool nf = !isfinite(py + vy);
                     flag |= (ok ? 0 : 1) | (nf ? 2 : 0) | (lo ? 0 : 4);
                 }
             }

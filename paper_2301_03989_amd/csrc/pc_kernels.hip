@@ -110,7 +110,11 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
             sm.Rec[3 * i + 0] = q.x;
             sm.Rec[3 * i + 1] = q.y;
             sm.Rec[3 * i + 2] = q.z;
-            if (i < P) sm.Mu[i] = q.w;
+            if (i < P) {
+                sm.Mu[i] = q.w;
+                sm.Mu[PC_MAX_PERT_DEV + i] = 1.5 * q.w;
+                sm.Mu[2 * PC_MAX_PERT_DEV + i] = 1.875 * q.w;
+            }
         }
     }
     // initial guess at every (node, IC) pair: warm (Kepler) or cold start, Sec. 2.1,
@@ -150,6 +154,7 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
     // rounding is relative to the increment), but their summed FP32 rounding grows when they
     // run that far, so they hand over at 1e-8; FP32 Picard sweeps stall near 1e-7
     const double sw2 = p.switch2 > 0.0 ? p.switch2 : (incr ? 1e-16 : 1e-8);
+    const PcTol tl = pc_tol(p.tol_mode, t2, sw2);
     int n32 = 0;
     float* sD = reinterpret_cast<float*>(sF);   // increment sweeps: dF, FP32
     double* sA = sF + 3 * PAIRS;                 // increment sweeps: a of the last publish
@@ -173,25 +178,23 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
         int flag;
         if constexpr (MIXED && Sh::WIDE) {
             if (mode == 2)
-                flag = pc_product_incr<PAIRS, NP>(sD, kp0f, yc, acc, w2, t2, sw2, p.tol_mode, N, L);
+                flag = pc_product_incr<PAIRS, NP>(sD, kp0f, yc, acc, w2, tl, N, L);
             else
-                flag = pc_product<PAIRS, NP, false>(sF, sY0, kp0, kpre, kp0f, yc, acc, w2, t2, sw2,
-                                                    p.tol_mode, N, L);
+                flag = pc_product<PAIRS, NP, false>(sF, sY0, kp0, kpre, kp0f, yc, acc, w2, tl, N, L);
         } else if constexpr (MIXED) {
-            flag = mode == 1 ? pc_product<PAIRS, NP, true>(sF, sY0, kp0, kpre, kp0f, yc, acc, w2, t2, sw2,
-                                                           p.tol_mode, N, L)
-                             : pc_product<PAIRS, NP, false>(sF, sY0, kp0, kpre, kp0f, yc, acc, w2, t2,
-                                                            sw2, p.tol_mode, N, L);
+            flag = mode == 1 ? pc_product<PAIRS, NP, true>(sF, sY0, kp0, kpre, kp0f, yc, acc, w2, tl, N, L)
+                             : pc_product<PAIRS, NP, false>(sF, sY0, kp0, kpre, kp0f, yc, acc, w2, tl, N, L);
         } else {
-            flag = pc_product<PAIRS, NP, false>(sF, sY0, kp0, kpre, kp0f, yc, acc, w2, t2, sw2, p.tol_mode,
-                                                N, L);
+            flag = pc_product<PAIRS, NP, false, false>(sF, sY0, kp0, kpre, kp0f, yc, acc, w2, tl, N, L);
         }
         if (L.lane < 16) sm.Flag[L.wave * 16 + L.lane] = flag;
 #pragma unroll
         for (int r = 0; r < 4; ++r) act[r] = sm.Active[pc_ic(L, r)];
-        const unsigned long long keep =
-            __ballot(L.lane < 16 && sm.Active[pc_flag_ic<PAIRS, NP>(L)] && (flag & 4));
-        if (L.lane == 0) sm.Keep[L.wave] = keep != 0ull;
+        if constexpr (MIXED) {
+            const unsigned long long keep =
+                __ballot(L.lane < 16 && sm.Active[pc_flag_ic<PAIRS, NP>(L)] && (flag & 4));
+            if (L.lane == 0) sm.Keep[L.wave] = keep != 0ull;
+        }
         __syncthreads();   // every wave is done reading F; flags complete
 
         // the job leaves FP32 once no iterating IC changes by more than the switch threshold
@@ -218,6 +221,7 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
                 if (tid < n && iters_out) iters_out[(size_t)ic * p.iters_stride + s] = rec;
             }
         }
+        pc_note_active<PAIRS, NP>(sm, L);
         const int next_mode = next32 ? (incr ? 2 : 1) : 0;
         // (4) ICs that were iterating take the new iterate and publish its F (or, before an
         //     increment sweep, the change of F)
@@ -249,8 +253,8 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
                 pc_publish_incr<PAIRS, NP>(sD, sA, yc, dv, aold, from_f, L, N, P, p.mu_sun, sm.Rec, sm.Mu);
                 fp32 = next32;
                 mode = next_mode;
-                const int any = __syncthreads_or(tid < T ? sm.Active[tid] : 0);
-                if (!any) break;
+                __syncthreads();   // F complete; the active notes visible
+                if (!pc_any_active<PAIRS, NP>(sm)) break;
                 continue;
             }
         }
@@ -268,8 +272,8 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
         }
         fp32 = next32;
         mode = next_mode;
-        const int any = __syncthreads_or(tid < T ? sm.Active[tid] : 0);
-        if (!any) break;
+        __syncthreads();   // F complete; the active notes visible
+        if (!pc_any_active<PAIRS, NP>(sm)) break;
     }
 }
 
@@ -390,7 +394,7 @@ __device__ __attribute__((noinline)) void pc_job_list(const PcParams& p, const P
     const int grp = Sh::WIDE ? L.grp : 0;
     const int n_g = n > grp ? (n - grp + GN - 1) / GN : 0;   // entries of this wave's group
     const bool rec_lds = N * 3 * (P + 1) <= PcSmem<PAIRS>::REC;
-    const double t2 = g.tol * g.tol;
+    const PcTol tl = pc_tol(p.tol_mode, g.tol * g.tol, 0.0);
     gconst_dp kp0 = (gconst_dp)g.kfrag + (size_t)L.strip0 * NQ * 64 + L.lane;
     double kpre[8];
     pc_kpre_load<PAIRS, NP>(kp0, kpre);
@@ -481,7 +485,11 @@ __device__ __attribute__((noinline)) void pc_job_list(const PcParams& p, const P
                 sm.Rec[3 * i + 0] = q.x;
                 sm.Rec[3 * i + 1] = q.y;
                 sm.Rec[3 * i + 2] = q.z;
-                if (i < P) sm.Mu[i] = q.w;
+                if (i < P) {
+                    sm.Mu[i] = q.w;
+                    sm.Mu[PC_MAX_PERT_DEV + i] = 1.5 * q.w;
+                    sm.Mu[2 * PC_MAX_PERT_DEV + i] = 1.875 * q.w;
+                }
             }
         }
         for (int i = tid; i < 6 * PAIRS; i += NT) sF[i] = 0.0;   // rows past N stay zero
@@ -502,8 +510,7 @@ __device__ __attribute__((noinline)) void pc_job_list(const PcParams& p, const P
 
         for (int it = 1;; ++it) {
             f64x4 acc[6];
-            const int flag = pc_product<PAIRS, NP, false>(sF, sY0, kp0, kpre, nullptr, yc, acc, w2, t2, 0.0,
-                                                          p.tol_mode, N, L);
+            const int flag = pc_product<PAIRS, NP, false, false>(sF, sY0, kp0, kpre, nullptr, yc, acc, w2, tl, N, L);
             if (L.lane < 16) sm.Flag[L.wave * 16 + L.lane] = flag;
             __syncthreads();   // every wave is done reading F; flags complete
 
@@ -607,7 +614,14 @@ __device__ __attribute__((noinline)) void pc_job_list(const PcParams& p, const P
                 amask = (amask & ~smask) | rmask;
             }
             if (amask) pc_publish<PAIRS, NP>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
-            if (!__syncthreads_or(amask != 0u)) break;
+            // every wave of an IC group holds the group's column mask: the first strip's waves
+            // note it (rewritten only after the next sweep's first barrier)
+            if (L.strip0 == 0 && L.lane == 0) sm.Go[L.grp] = amask != 0u;
+            __syncthreads();   // F complete; the notes visible
+            int go = 0;
+#pragma unroll
+            for (int q = 0; q < Sh::G16; ++q) go |= sm.Go[q];
+            if (!go) break;
         }
     }
     if (notconv) atomicAdd(&p.counters[0], notconv);
@@ -871,8 +885,9 @@ __device__ __attribute__((noinline)) void pc_adjoint_job(const PcAdjParams& a, c
                     }
                 }
             }
-            const int any = __syncthreads_or(tid < T ? sm.Active[tid] : 0);
-            if (!any) break;
+            pc_note_active<PAIRS, NP>(sm, L);
+            __syncthreads();   // mu complete; the active notes visible
+            if (!pc_any_active<PAIRS, NP>(sm)) break;
         }
         // this segment's gradient seeds the end node of the previous one
         if (tid < T) {

@@ -155,7 +155,8 @@ __global__ __launch_bounds__(PAIRS / 4) void pc_plain_step(PcPlainArgs a, int s,
     gconst_dp kp0 = (gconst_dp)a.g->kfrag + (size_t)L.strip0 * NQ * 64 + L.lane;
     double kpre[8];
     pc_kpre_load<PAIRS, NP>(kp0, kpre);
-    const int flag = pc_product<PAIRS, NP>(sF, sY0, kp0, kpre, nullptr, yc, acc, w2, a.t2, 0.0, a.p.tol_mode, N, L);
+    const int flag = pc_product<PAIRS, NP, false, false>(sF, sY0, kp0, kpre, nullptr, yc, acc, w2,
+                                                         pc_tol(a.p.tol_mode, a.t2, 0.0), N, L);
     if (L.lane < 16) sFlag[L.wave * 16 + L.lane] = flag;
     __syncthreads();   // F read by every wave, flags complete
 
