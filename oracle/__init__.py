@@ -47,6 +47,11 @@ def _load():
             ctypes.c_int, _dp, _dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
             ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
             ctypes.c_int, _dp, ctypes.c_double, _dp, _ip, _dp, _dp, ctypes.c_int]
+        lib.orc_propagate_group.restype = ctypes.c_int
+        lib.orc_propagate_group.argtypes = [
+            ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+            ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+            ctypes.c_int, _dp, ctypes.c_double, _dp, _ip, _dp, _dp, ctypes.c_int]
         lib.orc_picard_step.restype = None
         lib.orc_picard_step.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]
         lib.orc_nodes.restype = None
@@ -108,11 +113,13 @@ class Model:
 
 
 def propagate(ics, t0, tf, nodes, segments, tol, model=None, *, tol_mode=0, max_iter=64,
-              fixed_iters=0, init=0, want_bounds=False, want_nodes=False, threads=0):
+              fixed_iters=0, init=0, want_bounds=False, want_nodes=False, threads=0, conv=0):
     """Propagate ICs [n,6] over [t0, tf] (scalars or per-IC arrays).
 
     Returns (states[n,6], iters[n,segments]) and, when asked, the segment-boundary
     states [n,S+1,6] and the node states [n,S,N,6].  ``init``: 0 Kepler, 1 cold.
+    ``conv``: 0 = stopping rule per IC; 1 = one stopping decision for all the ICs, on
+    the largest error over them (orc_propagate_group; scalar t0 and tf, no fixed sweeps).
     """
     lib = _load()
     model = model or Model()
@@ -125,10 +132,19 @@ def propagate(ics, t0, tf, nodes, segments, tol, model=None, *, tol_mode=0, max_
     iters = np.zeros((n, S), dtype=np.int32)
     bounds = np.zeros((n, S + 1, 6)) if want_bounds else None
     nodes_out = np.zeros((n, S, N, 6)) if want_nodes else None
-    used = lib.orc_propagate(n, _ptr(ics), _ptr(t0a), _ptr(tfa), N, S, float(tol), int(tol_mode),
-                             int(max_iter), int(fixed_iters), int(init), model.mu_sun,
-                             model.n_pert, model._pert_ptr(), model.epoch, _ptr(states),
-                             iters.ctypes.data_as(_ip), _ptr(bounds), _ptr(nodes_out), int(threads))
+    if conv == 1:
+        if np.ndim(t0) or np.ndim(tf) or fixed_iters:
+            raise ValueError("group-max convergence takes one t0 and tf and no fixed sweeps")
+        used = lib.orc_propagate_group(n, _ptr(ics), float(t0), float(tf), N, S, float(tol),
+                                       int(tol_mode), int(max_iter), int(init), model.mu_sun,
+                                       model.n_pert, model._pert_ptr(), model.epoch, _ptr(states),
+                                       iters.ctypes.data_as(_ip), _ptr(bounds), _ptr(nodes_out),
+                                       int(threads))
+    else:
+        used = lib.orc_propagate(n, _ptr(ics), _ptr(t0a), _ptr(tfa), N, S, float(tol), int(tol_mode),
+                                 int(max_iter), int(fixed_iters), int(init), model.mu_sun,
+                                 model.n_pert, model._pert_ptr(), model.epoch, _ptr(states),
+                                 iters.ctypes.data_as(_ip), _ptr(bounds), _ptr(nodes_out), int(threads))
     out = [states, iters]
     if want_bounds:
         out.append(bounds)

@@ -435,6 +435,137 @@ int orc_propagate(int n_ic, const double* ics, const double* t0, const double* t
     return used;
 }
 
+/*
+ * Group-max convergence.  Sec. 3.2 lets the stopping rule act on the whole augmented
+ * system or on blocks of it, and the paper's CUDA program (Sec. 5.4.2) stops once the
+ * largest error over the whole system is below tol.  Here the n_ic ICs of one group
+ * (common t0, tf) take their sweeps in lockstep: in each segment every IC still finite
+ * takes sweep after sweep until the largest error (vi) over those ICs is below tol, and
+ * every one of them returns that sweep's iterate, so all of them report the same count.
+ * An IC whose state turns non-finite leaves the group (status -2, as in orc_propagate)
+ * and no longer enters the maximum.  When max_iter sweeps do not bring the maximum below
+ * tol, every IC still in the group reports -1 and keeps its last iterate.
+ * Arguments as orc_propagate, with one t0 and tf for the group and no fixed-sweep mode.
+ * Returns the number of threads used.
+ */
+int orc_propagate_group(int n_ic, const double* ics, double t0, double tf, int N, int S, double tol,
+                        int tol_mode, int max_iter, int init, double mu_sun, int n_pert,
+                        const double* pert, double epoch, double* states_out, int* iters_out,
+                        double* bounds_out, double* nodes_out, int nthreads)
+{
+    int used = 1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+#pragma omp single
+    used = omp_get_num_threads();
+#endif
+    const size_t NS = (size_t)N * 6;
+    double* Tkj = (double*)malloc(sizeof(double) * (size_t)N * N);
+    double* tau = (double*)malloc(sizeof(double) * (size_t)N);
+    double* Y = (double*)malloc(sizeof(double) * NS * n_ic);      /* current iterate per IC */
+    double* Yn = (double*)malloc(sizeof(double) * NS * n_ic);     /* next iterate per IC */
+    double* G = (double*)malloc(sizeof(double) * NS * n_ic);      /* force matrix per IC */
+    double* cb = (double*)malloc(sizeof(double) * (size_t)(N + 2) * 2 * n_ic);
+    double* y0 = (double*)malloc(sizeof(double) * 6 * (size_t)n_ic);
+    double* err = (double*)malloc(sizeof(double) * (size_t)n_ic);
+    int* dead = (int*)malloc(sizeof(int) * (size_t)n_ic);
+    int np = n_pert > 64 ? 64 : n_pert;
+    double* rp = (double*)malloc(sizeof(double) * (size_t)N * 3 * (np > 0 ? np : 1));
+    double mup[64];
+    for (int p = 0; p < np; ++p) mup[p] = pert[7 * p];
+    for (int k = 0; k < N; ++k)
+        for (int j = 0; j < N; ++j) Tkj[k * N + j] = orc_T(k, j, N);
+    for (int j = 0; j < N; ++j) tau[j] = orc_tau(j, N);
+
+    for (int m = 0; m < n_ic; ++m) {
+        memcpy(y0 + 6 * m, ics + 6 * m, sizeof(double) * 6);
+        dead[m] = 0;
+        for (int k = 0; k < 6; ++k) if (!isfinite(y0[6 * m + k])) dead[m] = 1;
+        if (bounds_out) memcpy(bounds_out + ((size_t)m * (S + 1)) * 6, y0 + 6 * m, sizeof(double) * 6);
+    }
+    const double h = (tf - t0) / (double)S;
+    for (int s = 0; s < S; ++s) {
+        const double Ts = t0 + h * s, Te = t0 + h * (s + 1);
+        const double w1 = 0.5 * (Te + Ts), w2 = 0.5 * (Te - Ts);
+        /* perturber positions at the nodes, before iterating (Sec. 5.4.1) */
+        for (int j = 0; j < N; ++j) {
+            double tj = w2 * tau[j] + w1;
+            for (int p = 0; p < np; ++p) orc_ephem(pert + 7 * p, epoch, tj, rp + 3 * (j * np + p));
+        }
+        /* initial guess of every IC still in the group, as in orc_propagate */
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int m = 0; m < n_ic; ++m) {
+            if (dead[m]) continue;
+            double* Ym = Y + NS * m;
+            int cold = (init == 1);
+            if (!cold) {
+                for (int j = 0; j < N; ++j)
+                    if (orc_kepler(y0 + 6 * m, w2 * (tau[j] + 1.0), Ym + 6 * j) != 0) { cold = 1; break; }
+            }
+            if (cold)
+                for (int j = 0; j < N; ++j) memcpy(Ym + 6 * j, y0 + 6 * m, sizeof(double) * 6);
+        }
+        int status = -1;
+        for (int it = 1; it <= max_iter; ++it) {
+            /* one sweep (i)-(vi) of every IC still in the group */
+#pragma omp parallel for schedule(dynamic, 1)
+            for (int m = 0; m < n_ic; ++m) {
+                if (dead[m]) continue;
+                double* Ym = Y + NS * m;
+                double* Ynm = Yn + NS * m;
+                double* Gm = G + NS * m;
+                for (int j = 0; j < N; ++j) {
+                    double acc[3];
+                    orc_accel(Ym + 6 * j, np, rp + 3 * j * np, mup, mu_sun, acc);
+                    for (int k = 0; k < 3; ++k) {
+                        Gm[6 * j + k] = w2 * Ym[6 * j + 3 + k];
+                        Gm[6 * j + 3 + k] = w2 * acc[k];
+                    }
+                }
+                orc_picard_update(N, 6, Tkj, Gm, y0 + 6 * m, Ynm, cb + (size_t)(N + 2) * 2 * m,
+                                  cb + (size_t)(N + 2) * (2 * m + 1));
+                err[m] = orc_iter_error(N, Ynm, Ym, tol_mode);
+                memcpy(Ym, Ynm, sizeof(double) * NS);   /* Y is now the newest iterate */
+            }
+            /* the group's error: the largest over the ICs still in it */
+            double emax = 0.0;
+            for (int m = 0; m < n_ic; ++m) {
+                if (dead[m]) continue;
+                if (isnan(err[m])) {
+                    dead[m] = 2;   /* left the group in this segment */
+                    continue;
+                }
+                if (err[m] > emax) emax = err[m];
+            }
+            if (emax < tol) { status = it; break; }
+        }
+        for (int m = 0; m < n_ic; ++m) {
+            int* it_out = iters_out + (size_t)m * S + s;
+            double* Ym = Y + NS * m;
+            if (dead[m] == 1) {   /* non-finite before this segment */
+                *it_out = -2;
+                for (int k = 0; k < 6; ++k) y0[6 * m + k] = NAN;
+                if (nodes_out)
+                    for (int j = 0; j < N; ++j)
+                        memcpy(nodes_out + (((size_t)m * S + s) * N + j) * 6, y0 + 6 * m, sizeof(double) * 6);
+            } else {
+                *it_out = dead[m] == 2 ? -2 : status;
+                if (nodes_out) memcpy(nodes_out + (((size_t)m * S + s) * N) * 6, Ym, sizeof(double) * NS);
+                memcpy(y0 + 6 * m, Ym + 6 * (N - 1), sizeof(double) * 6);
+                if (dead[m] == 2) {
+                    dead[m] = 1;
+                    for (int k = 0; k < 6; ++k) y0[6 * m + k] = NAN;
+                }
+            }
+            if (bounds_out) memcpy(bounds_out + ((size_t)m * (S + 1) + s + 1) * 6, y0 + 6 * m, sizeof(double) * 6);
+        }
+    }
+    memcpy(states_out, y0, sizeof(double) * 6 * (size_t)n_ic);
+    free(Tkj); free(tau); free(Y); free(Yn); free(G); free(cb); free(y0); free(err); free(dead); free(rp);
+    return used;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Independent integrator for pinning: classical fixed-step RK4              */
 /* ------------------------------------------------------------------------ */
