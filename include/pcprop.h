@@ -81,6 +81,16 @@ enum { PC_TOL_REL = 0, PC_TOL_ABS = 1 };         /* relative or absolute stoppin
  * is the FP64 fixed point.  iters_out counts all sweeps. */
 enum { PC_FP64 = 0, PC_FP32_THEN_FP64 = 1 };
 enum { PC_PATH_FUSED = 0, PC_PATH_PLAIN = 1 };   /* one persistent launch / per-iteration kernels */
+/* Granularity of the stopping rule (Sec. 3.2).  PC_CONV_PER_IC: every IC stops at its own
+ * first sweep whose change is below tol and keeps that iterate.  PC_CONV_GROUP_MAX: one
+ * decision per group, on the largest change over the group's ICs that are still finite,
+ * as the paper's CUDA program does for the whole augmented system (Sec. 5.4.2): every IC
+ * of the group takes the same number of sweeps per segment (iters_out holds that number,
+ * or PC_ITER_NOTCONV for all of them when max_iter sweeps do not bring the maximum below
+ * tol).  A non-finite IC leaves its group (PC_ITER_NONFINITE) without holding the others
+ * back.  PC_CONV_GROUP_MAX runs on the plain path, whose host loop sees every sweep of
+ * the whole group; the fused path and the adjoint reject it with PC_EINVAL. */
+enum { PC_CONV_PER_IC = 0, PC_CONV_GROUP_MAX = 1 };
 
 typedef struct {
     int32_t init;         /* PC_INIT_KEPLER (default) or PC_INIT_COLD */
@@ -102,6 +112,7 @@ typedef struct {
                              the next IC of the job for the same segment.  0 = automatic (the
                              largest of 1, 2, 4, 8 leaving >= 4 jobs per compute unit), 1 = off,
                              2, 4 or 8 = that many blocks.  Results do not depend on it. */
+    int32_t conv;         /* PC_CONV_PER_IC (default) or PC_CONV_GROUP_MAX */
 } pc_opts;
 
 /* One outer-level group of the two-level augmentation (Sec. 3.2): ICs

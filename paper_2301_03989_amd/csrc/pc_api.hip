@@ -441,6 +441,7 @@ void pc_default_opts(pc_opts* o)
     o->switch_tol = 0.0;
     o->max_fp32 = 0;
     o->job_list = 0;
+    o->conv = PC_CONV_PER_IC;
 }
 
 int pc_version(void) { return PC_VERSION; }
@@ -547,6 +548,9 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_
     if (o.job_list != 0 && o.job_list != 1 && o.job_list != 2 && o.job_list != 4 && o.job_list != 8)
         return set_error(ctx, PC_EINVAL, "job_list must be 0, 1, 2, 4 or 8");
     if (o.fixed_iters < 0 || o.fixed_iters > 100000) return set_error(ctx, PC_EINVAL, "fixed_iters out of range");
+    if (o.conv != PC_CONV_PER_IC && o.conv != PC_CONV_GROUP_MAX) return set_error(ctx, PC_EINVAL, "bad conv");
+    if (o.conv == PC_CONV_GROUP_MAX && o.path != PC_PATH_PLAIN)
+        return set_error(ctx, PC_EINVAL, "group-max convergence runs on the plain path");
     PC_HIP(ctx, hipSetDevice(ctx->device));
     Plan plan;
     rc = make_plan(ctx, n_ic, groups, n_groups, model, o, true, plan,
@@ -596,6 +600,7 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_
     pp.max_iter = o.max_iter;
     pp.fixed_iters = o.fixed_iters;
     pp.tol_mode = o.tol_mode;
+    pp.conv = o.conv;
     pp.init = o.init;
     pp.precision = o.precision;
     pp.max_fp32 = o.max_fp32 > 0 ? o.max_fp32 : 24;
@@ -752,6 +757,8 @@ int pc_adjoint(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int32_t n_grou
     pc_opts o = opts ? *opts : defaults();
     if (o.path != PC_PATH_FUSED || o.precision != PC_FP64)
         return set_error(ctx, PC_EINVAL, "the adjoint re-solves segments on the fused FP64 path");
+    if (o.conv != PC_CONV_PER_IC)
+        return set_error(ctx, PC_EINVAL, "the adjoint linearises the map converged per IC");
     if (o.init != PC_INIT_KEPLER && o.init != PC_INIT_COLD) return set_error(ctx, PC_EINVAL, "bad init");
     if (o.max_iter < 1 || o.max_iter > 100000 || o.fixed_iters < 0) return set_error(ctx, PC_EINVAL, "bad iterations");
     if (!(adj_tol > 0.0) || !std::isfinite(adj_tol) || adj_max_iter < 2 || adj_max_iter > 100000)

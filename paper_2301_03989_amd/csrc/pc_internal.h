@@ -63,6 +63,7 @@ struct PcParams {
     int32_t max_iter, fixed_iters, tol_mode, init;
     int32_t precision;          // 0 FP64; 1 FP32 sweeps, then FP64
     int32_t max_fp32;           // cap on FP32 sweeps per segment
+    int32_t conv;               // PC_CONV_PER_IC or PC_CONV_GROUP_MAX (plain path only)
     double switch2;             // squared relative change below which a job leaves FP32
     int32_t* counters;          // [0] ICs with a not-converged segment, [1] non-finite ICs
     int32_t* queue;             // next job of the persistent kernel (starts at 0)

@@ -16,12 +16,13 @@ struct PcPlainArgs {
     double* Y0;                 // [6][Mpad]
     int32_t *active, *dead, *notconv, *valid;   // [Mpad]
     int32_t *job_list, *job_list_out, *job_flag; // [n_jobs]
-    int32_t* count;             // [2]: jobs in the current list, jobs in the compacted list
+    int32_t* count;             // [4]: jobs in the current list, jobs in the compacted list,
+                                //      jobs with a change above tol (accumulating, then as read)
 };
 
 // Workspace bytes of one group on the plain path.
 size_t pc_plain_bytes(int NP, int n_jobs, int T);
 
 // Propagate one group with per-iteration kernels and a host loop (returns a hipError_t).
-// host_count: pinned host int used for the per-iteration read-back.
+// host_count: pinned host ints (3) used for the per-iteration read-back.
 int pc_run_plain(PcPlainArgs a, void* workspace, int32_t* host_count, void* stream);

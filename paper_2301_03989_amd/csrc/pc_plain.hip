@@ -4,12 +4,16 @@
 // product (here one FP64 MFMA product with the +y0 term in its epilogue), the error
 // computation and its reduction, and a host check of the result every iteration.
 //
-// Differences from the paper's program: the error is per IC (converged ICs are frozen
-// and jobs whose ICs have all converged are compacted out of the next launches) and
-// the host reads back one active-job count per iteration instead of block maxima.
+// Differences from the paper's program: by default the error is per IC (converged ICs are
+// frozen and jobs whose ICs have all converged are compacted out of the next launches)
+// and the host reads back one active-job count per iteration instead of block maxima.
+// With PC_CONV_GROUP_MAX the paper's whole-system rule holds per group: no IC stops on
+// its own, the step kernels count the jobs that still hold a change above tol, and the
+// host ends the segment for the whole group when that count is zero.
 //
 // State in HBM, per group: Y[node][comp 9][IC] (comps 0..5 iterate, 6..8 acceleration),
 // IC index fastest -- the component-major, row-by-node layout of Sec. 5.4.1.
+#include "pcprop.h"
 #include "pc_device.h"
 #include "pc_plain.h"
 
@@ -43,7 +47,10 @@ __global__ void pc_plain_init(PcPlainArgs a, int s, double w2)
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t total = (int64_t)a.NP * a.Mpad;
     if (idx < a.n_jobs) a.job_list[idx] = (int32_t)idx;
-    if (idx == 0) a.count[0] = a.n_jobs;
+    if (idx == 0) {
+        a.count[0] = a.n_jobs;
+        a.count[2] = 0;
+    }
     if (idx >= total) return;
     const int j = (int)(idx / a.Mpad);
     const int64_t m = idx - (int64_t)j * a.Mpad;
@@ -103,6 +110,7 @@ __global__ __launch_bounds__(PAIRS / 4) void pc_plain_step(PcPlainArgs a, int s,
     __shared__ int sFlag[Sh::W * 16];
     __shared__ int sActive[T];
     __shared__ int sWas[T];
+    __shared__ int sOpen;   // group-max rule: some IC of the job changed by more than tol
 
     const int tid = threadIdx.x;
     const int job = a.job_list[blockIdx.x];
@@ -127,6 +135,7 @@ __global__ __launch_bounds__(PAIRS / 4) void pc_plain_step(PcPlainArgs a, int s,
         sActive[tid] = a.active[m0 + tid];
         sWas[tid] = sActive[tid];
     }
+    if (tid == 0) sOpen = 0;
     __syncthreads();
     double yc[6][4];
 #pragma unroll
@@ -165,6 +174,7 @@ __global__ __launch_bounds__(PAIRS / 4) void pc_plain_step(PcPlainArgs a, int s,
         int rec = 0;
         if (f & 2) rec = -2;
         else if (a.p.fixed_iters > 0) rec = (it == a.p.fixed_iters) ? it : 0;
+        else if (a.p.conv == PC_CONV_GROUP_MAX) { if (f & 1) sOpen = 1; }   // the host decides
         else if (!(f & 1)) rec = it;
         else if (it == a.p.max_iter) rec = -1;
         if (rec != 0) {
@@ -201,7 +211,10 @@ __global__ __launch_bounds__(PAIRS / 4) void pc_plain_step(PcPlainArgs a, int s,
         if (j < N && sWas[k]) a.Y[(size_t)j * row + (size_t)c * a.Mpad + m0 + k] = sF[j * ROW + c * T + pc_fcol<PAIRS, NP>(j, k)];
     }
     const int any = __syncthreads_or(tid < T ? sActive[tid] : 0);
-    if (tid == 0) a.job_flag[job] = any;
+    if (tid == 0) {
+        a.job_flag[job] = any;
+        if (sOpen) atomicAdd(&a.count[2], 1);
+    }
 }
 
 // Stream compaction of the active job list: prefix sum of the job flags (one workgroup).
@@ -229,7 +242,24 @@ __global__ __launch_bounds__(1024) void pc_plain_compact(PcPlainArgs a)
         if (threadIdx.x == 1023) sBase += sScan[1023];
         __syncthreads();
     }
-    if (threadIdx.x == 0) a.count[1] = sBase;
+    if (threadIdx.x == 0) {
+        a.count[1] = sBase;
+        a.count[3] = a.count[2];   // jobs with a change above tol (group-max rule)
+        a.count[2] = 0;
+    }
+}
+
+// Group-max rule, end of a segment's sweeps: every IC still in the group records the
+// group's status (the sweep count, or -1 when max_iter sweeps did not converge).
+__global__ void pc_plain_group_end(PcPlainArgs a, int s, int status)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= a.Mpad || !a.active[m]) return;
+    a.active[m] = 0;
+    if (status == -1) a.notconv[m] = 1;
+    const PcJobDev job = a.jobs[m / a.T];
+    const int i = (int)(m % a.T);
+    if (i < job.n && a.p.iters_out) a.p.iters_out[(size_t)(job.ic0 + i) * a.p.iters_stride + s] = status;
 }
 
 // Segment end: the last node starts the next segment; optional node / boundary outputs.
@@ -327,6 +357,7 @@ int pc_run_plain(PcPlainArgs a, void* workspace, int32_t* host_count, void* stre
     hipLaunchKernelGGL(pc_plain_bounds0, dim3(gm), dim3(bs), 0, st, a);
     const int bpj = a.NP * a.T / kPlainForceBlock;
     const int n_it = a.p.fixed_iters > 0 ? a.p.fixed_iters : a.p.max_iter;
+    const bool group = a.p.conv == PC_CONV_GROUP_MAX && a.p.fixed_iters == 0;
     const double h = a.g_host.h;
     for (int s = 0; s < a.S; ++s) {
         const double Ts = a.g_host.t0 + h * s, Te = a.g_host.t0 + h * (s + 1);
@@ -336,6 +367,7 @@ int pc_run_plain(PcPlainArgs a, void* workspace, int32_t* host_count, void* stre
         const int64_t total = (int64_t)a.NP * a.Mpad;
         hipLaunchKernelGGL(pc_plain_init, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, st, a, s, w2);
         int count = a.n_jobs;
+        int status = -1;   // group-max rule: the segment's sweep count once the group converged
         for (int it = 1; it <= n_it && count > 0; ++it) {
             a.job_list = lists[cur];
             a.job_list_out = lists[1 - cur];
@@ -343,15 +375,25 @@ int pc_run_plain(PcPlainArgs a, void* workspace, int32_t* host_count, void* stre
             e = (hipError_t)launch_step_np(a, count, s, it, w2, st);
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL(pc_plain_compact, dim3(1), dim3(1024), 0, st, a);
-            // host loop control: read back the number of jobs still iterating (Sec. 5.4.2)
-            e = hipMemcpyAsync(host_count, a.count + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+            // host loop control: read back the number of jobs still iterating and, for the
+            // group-max rule, of jobs with a change above tol (Sec. 5.4.2)
+            e = hipMemcpyAsync(host_count, a.count + 1, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, st);
             if (e != hipSuccess) return e;
             e = hipMemcpyAsync(a.count, a.count + 1, sizeof(int32_t), hipMemcpyDeviceToDevice, st);
             if (e != hipSuccess) return e;
             e = hipStreamSynchronize(st);
             if (e != hipSuccess) return e;
-            count = *host_count;
+            count = host_count[0];
             cur = 1 - cur;
+            if (group && host_count[2] == 0) {
+                status = it;
+                break;
+            }
+        }
+        if (group) {
+            hipLaunchKernelGGL(pc_plain_group_end, dim3(gm), dim3(bs), 0, st, a, s, status);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
         }
         hipLaunchKernelGGL(pc_plain_chain, dim3(gm), dim3(bs), 0, st, a, s, s == a.S - 1 ? 1 : 0);
     }

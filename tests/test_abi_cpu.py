@@ -64,3 +64,22 @@ def test_operator_cost_model_rejects_bad_groups_without_gpu():
         assert rc == 1 and not h.value
     elif rc == 0:
         lib.pc_ctx_destroy(h)
+
+
+def test_default_opts_fill_the_binding_struct_exactly():
+    """pc_default_opts writes every field of the binding's pc_opts and nothing past it:
+    the ctypes layout and the header's agree (a field missing on either side shifts or
+    overruns the sentinel bytes)."""
+    pytest.importorskip("torch")
+    from paper_2301_03989_amd import build, pcprop
+    build.ensure_built()
+    lib = ctypes.CDLL(build.LIB)
+    n = ctypes.sizeof(pcprop._Opts)
+    buf = (ctypes.c_ubyte * (n + 64))(*([0xAB] * (n + 64)))
+    lib.pc_default_opts(ctypes.byref(buf))
+    assert bytes(buf[n:]) == b"\xab" * 64
+    o = pcprop._Opts.from_buffer_copy(bytes(buf[:n]))
+    d = pcprop.Context.opts()
+    for name, _ in pcprop._Opts._fields_:
+        assert getattr(o, name) == getattr(d, name), name
+    assert o.conv == pcprop.CONV["ic"] and o.max_iter == 64

@@ -158,6 +158,14 @@ def test_adjoint_argument_errors(pc):
     fwd = pc.propagate_batched(ics, groups, model, want_bounds=True)
     with pytest.raises(pcprop.PcError):
         pc.adjoint(fwd["bounds"], torch.zeros((4, 6), dtype=torch.float64, device="cuda"), groups, model)
+    # the adjoint linearises the map converged per IC: the group-max rule is refused
+    w = W.nbody_venus(4, days=30.0, segments=1)
+    ics, groups, model, om, g = _setup(w)
+    fwd = pc.propagate_batched(ics, groups, model, want_bounds=True)
+    with pytest.raises(pcprop.PcError) as e:
+        pc.adjoint(fwd["bounds"], torch.zeros((4, 6), dtype=torch.float64, device="cuda"), groups, model,
+                   conv="group")
+    assert e.value.code == pcprop.PC_EINVAL
 
 
 @pytest.mark.parametrize("nodes", [12, 24, 100])

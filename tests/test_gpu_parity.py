@@ -384,6 +384,78 @@ def _eccentric(n, seed, nodes, segments, tol=1e-12):
                       W.planet_elements())
 
 
+@pytest.mark.parametrize("tile, list_, precision", [(1024, 1, "fp64"), (2048, 1, "fp64"), (2048, 4, "fp64"),
+                                                   (2048, 1, "fp32-fp64")])
+def test_absolute_tolerance_mode(pc, tile, list_, precision):
+    """The absolute stopping rule (tol on |dr| and |dv| at every node) on 8-IC, 16-IC and
+    refilled-column jobs and under the precision schedule, against the oracle's absolute
+    mode.  On these eccentric orbits (|r| from 0.3 to 1.6) the absolute rule stops other
+    ICs at other sweeps than the relative rule."""
+    w = _eccentric(70, 5, 64, 4, tol=1e-11)
+    r, _ = _run(pc, w, tol_mode="abs", tile_pairs=tile, job_list=list_, precision=precision, want_bounds=True)
+    o = oracle_run(w, tol_mode=1, want_bounds=True)
+    assert r["status"] == 0
+    assert rel_err(r["states"], o["states"]).max() < TOL
+    assert rel_err(r["bounds"].reshape(-1, 6), o["bounds"].reshape(-1, 6)).max() < TOL
+    if precision == "fp64":
+        # (under the precision schedule an IC also takes its job's FP32 sweeps: counts differ)
+        assert np.abs(r["iters"] - o["iters"]).max() <= 1
+    assert (oracle_run(w)["iters"] != o["iters"]).any()
+
+
+def _two_groups(tol=1e-11):
+    """70 eccentric ICs in two groups (48 nodes x 3 segments, 64 nodes x 2 segments)."""
+    w = _eccentric(70, 13, 48, 3, tol)
+    h = np.pi / 4
+    groups = [W.Group(0, 40, 0.0, 3 * h, 48, 3, tol), W.Group(40, 30, 0.0, 2 * h, 64, 2, tol)]
+    return W.Workload("ecc2", w.ics, groups, w.pert)
+
+
+@pytest.mark.parametrize("tol_mode", ["rel", "abs"])
+def test_group_max_convergence_matches_oracle(pc, tol_mode):
+    """Group-max stopping rule on the plain path: one sweep count per group and segment,
+    the oracle's group count within one sweep, states within the parity bar; the per-IC
+    rule stops some ICs earlier on the same inputs."""
+    w = _two_groups()
+    r, _ = _run(pc, w, path="plain", conv="group", tol_mode=tol_mode, want_bounds=True)
+    o = oracle_run(w, conv=1, tol_mode=0 if tol_mode == "rel" else 1, want_bounds=True)
+    assert r["status"] == 0
+    for g in w.groups:
+        sl = slice(g.ic_offset, g.ic_offset + g.n_ic)
+        it = r["iters"][sl, :g.segments]
+        assert (it == it[0]).all()
+        assert np.abs(it[0] - o["iters"][sl, :g.segments][0]).max() <= 1
+        b, ob = r["bounds"][sl, :g.segments + 1], o["bounds"][sl, :g.segments + 1]
+        assert rel_err(b.reshape(-1, 6), ob.reshape(-1, 6)).max() < TOL
+    assert rel_err(r["states"], o["states"]).max() < TOL
+    # first segment (same start for both rules): every IC's own first sweep below tol comes
+    # no later than the group's
+    per_ic, _ = _run(pc, w, path="plain", tol_mode=tol_mode)
+    assert (per_ic["iters"][:, 0] <= r["iters"][:, 0]).all() and (per_ic["iters"][:, 0] < r["iters"][:, 0]).any()
+
+
+def test_group_max_status_and_rejections(pc):
+    from paper_2301_03989_amd import pcprop
+    w = _two_groups()
+    bad = w.ics.copy()
+    bad[5, 2] = np.inf
+    r, _ = _run(pc, W.Workload("bad", bad, w.groups, w.pert), path="plain", conv="group")
+    o = oracle_run(W.Workload("bad", bad, w.groups, w.pert), conv=1)
+    assert r["status"] == pcprop.PC_ENONFINITE and (r["iters"][5, :3] == -2).all()
+    keep = np.arange(w.n_ic) != 5
+    assert np.abs(r["iters"][keep] - o["iters"][keep]).max() <= 1
+    assert rel_err(r["states"][keep], o["states"][keep]).max() < TOL
+    r, _ = _run(pc, w, path="plain", conv="group", max_iter=3)
+    assert r["status"] == pcprop.PC_ENOTCONV
+    for g in w.groups:
+        assert (r["iters"][g.ic_offset:g.ic_offset + g.n_ic, :g.segments] == -1).all()
+    o = oracle_run(w, fixed_iters=3)
+    assert rel_err(r["states"], o["states"]).max() < 1e-12
+    with pytest.raises(pcprop.PcError) as e:
+        _run(pc, w, conv="group")
+    assert e.value.code == pcprop.PC_EINVAL
+
+
 @pytest.mark.parametrize("nodes,list_", [(24, 8), (64, 2), (100, 4), (128, 8), (200, 4)])
 def test_refilled_columns_match_one_block_jobs(pc, nodes, list_):
     """Every IC's iterates do not depend on which column or job runs it: refilled-column
