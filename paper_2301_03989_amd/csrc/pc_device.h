@@ -60,9 +60,11 @@ static __device__ void pc_body_position(const PcBodyDev& B, double dt_epoch, dou
 
 // Warm start (Sec. 2.1): propagate y0 by dt on its osculating ellipse, through the
 // Lagrange coefficients f, g, fdot, gdot written in the eccentric-anomaly change x:
-//   x - (1 - r0/a) sin x + (r0.v0/sqrt(a)) (1 - cos x) = n dt.
+//   F(x) = x - (1 - r0/a) sin x + (r0.v0/sqrt(a)) (1 - cos x) - n dt = 0.
 // Newton converges quadratically: with F' >= 1 - e and |F''| <= e, a step below 1e-10
-// leaves an error below e/(2(1-e)) 1e-20, far under one ulp, so the loop stops there.
+// leaves an error below e/(2(1-e)) 1e-20, far under one ulp, so the loop stops there, and
+// the sine and cosine at the final x follow from those of the last step by its Taylor
+// expansion (the step is below 1e-9, so the dropped cubic term is under 1e-27).
 // The state goes in and out by value (registers, no stack traffic); a non-elliptic or
 // degenerate state returns NaN components.
 struct PcState6 {
@@ -89,16 +91,25 @@ static __device__ __attribute__((noinline)) PcState6 pc_kepler_state(PcState6 s0
     const double es = sig / sqa;                   // e sin E0
     const double ndt = n * dt;
     double x = ndt;
+    double sx, cx;
+    bool done = false;
     for (int it = 0; it < 60; ++it) {
-        double sx, cx;
         sincos(x, &sx, &cx);
         const double F = x - ec * sx + es * (1.0 - cx) - ndt;
         const double dx = F / (1.0 - ec * cx + es * sx);
         x -= dx;
-        if (fabs(dx) <= 1e-10 * (1.0 + fabs(x))) break;
+        if (fabs(dx) <= 1e-10 * (1.0 + fabs(x))) {
+            // sin and cos of x = x_prev - dx
+            const double h2 = 0.5 * dx * dx;
+            const double s1 = sx - dx * cx - h2 * sx;
+            const double c1 = cx + dx * sx - h2 * cx;
+            sx = s1;
+            cx = c1;
+            done = true;
+            break;
+        }
     }
-    double sx, cx;
-    sincos(x, &sx, &cx);
+    if (!done) sincos(x, &sx, &cx);
     const double rn = a + (r0n - a) * cx + sig * sqa * sx;
     const double f = 1.0 - (a / r0n) * (1.0 - cx);
     const double g = dt - (x - sx) / n;
