@@ -108,10 +108,12 @@ typedef struct {
                              Picard sweeps of 8-IC jobs) */
     int32_t max_fp32;     /* PC_FP32_THEN_FP64: cap on FP32 sweeps per segment (0 = default 24) */
     int32_t job_list;     /* fused FP64 forward calls: ICs per job in units of its column block
-                             (16 ICs, or 8 at 256 nodes); when an IC converges its column takes
-                             the next IC of the job for the same segment.  0 = automatic (the
-                             largest of 1, 2, 4, 8 leaving >= 4 jobs per compute unit), 1 = off,
-                             2, 4 or 8 = that many blocks.  Results do not depend on it. */
+                             (the ICs one workgroup iterates at once: 2048 / padded nodes, or
+                             1024 / padded nodes with tile_pairs 1024); when an IC converges,
+                             its column takes the next IC of the job for the same segment.
+                             0 = automatic (the largest of 1, 2, 4, 8 leaving a job for every
+                             compute unit), 1 = off, 2, 4 or 8 = that many blocks.  Results do
+                             not depend on it. */
     int32_t conv;         /* PC_CONV_PER_IC (default) or PC_CONV_GROUP_MAX */
 } pc_opts;
 

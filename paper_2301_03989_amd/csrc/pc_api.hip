@@ -322,7 +322,10 @@ int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, c
         if (spans[i].first < spans[i - 1].second) return set_error(ctx, PC_EINVAL, "groups overlap");
 
     // ICs per job in units of the job's columns: the largest of 1, 2, 4, 8 that still
-    // leaves at least four jobs per compute unit for the work queue to balance
+    // leaves a job for every compute unit (one workgroup fits per CU).  Longer jobs refill
+    // their columns for longer, so fewer columns idle in segment tails; measured on
+    // 16384 eccentric ICs, one job per CU beat four shorter ones per CU by about 10 % at
+    // 128 and 256 nodes, and by 1.3 % on the uneven 65536-IC batch
     int list = 1;
     if (lists_ok && o.job_list != 1) {
         auto jobs_at = [&](int m) {
@@ -336,7 +339,7 @@ int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, c
         if (o.job_list > 1) list = o.job_list;
         else
             for (int m = 2; m <= 8; m *= 2)
-                if (jobs_at(m) >= 4 * (int64_t)ctx->n_cu) list = m;
+                if (jobs_at(m) >= (int64_t)ctx->n_cu) list = m;
     }
     plan.list = list;
     struct Cost { int np; double c; PcJobDev j; };
