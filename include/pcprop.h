@@ -99,7 +99,9 @@ typedef struct {
     int32_t precision;    /* PC_FP64 */
     int32_t path;         /* PC_PATH_FUSED (default) or PC_PATH_PLAIN */
     int32_t fixed_iters;  /* > 0: run exactly this many iterations per segment (no stopping rule) */
-    int32_t tile_pairs;   /* nodes x ICs held by one workgroup: 0 = tuned table, 1024 or 2048 */
+    int32_t tile_pairs;   /* nodes x ICs held by one workgroup: 0 = the context's table (set by
+                             pc_autotune or pc_set_tile_pairs; untuned: 1024 up to 64 padded
+                             nodes, else 2048), 1024 or 2048 */
     int32_t graph;        /* fused path: 1 = capture the call's device work (table copy, ephemeris,
                              propagation kernel, status copy) in a HIP graph and replay it while
                              the call's shapes, options and pointers repeat (default 0) */

@@ -638,8 +638,10 @@ __device__ __attribute__((noinline)) void pc_job_list(const PcParams& p, const P
 // Persistent work-queue kernel: every workgroup takes the next job of the plan (jobs of
 // all groups and node counts, longest first) until the queue is empty, so one launch
 // runs an uneven two-level batch (Sec. 3.2) to completion.
+// Two waves per SIMD: 512-thread workgroups fill a CU alone (their LDS arena is the
+// CU's), 256-thread ones fit two workgroups, running two independent jobs, per CU.
 template <int PAIRS>
-__global__ __launch_bounds__(PAIRS / 4) void pc_fused_kernel(const PcParams* __restrict__ pp)
+__global__ __launch_bounds__(PAIRS / 4, 2) void pc_fused_kernel(const PcParams* __restrict__ pp)
 {
     __shared__ int sJob;
     const PcParams& p = *pp;
