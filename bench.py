@@ -100,14 +100,14 @@ def oracle_states(w, idx):
     return out, iters, oracle.propagate.last_threads
 
 
-def adjoint_flops(w, iters, adj_iters):
+def adjoint_flops(w, iters, adj_iters, resolve=True):
     """Algorithmic FP64 work of one adjoint call: the forward re-solve of every segment
-    (as algorithmic_flops) plus, per adjoint sweep, the transposed product (6 columns x
-    2 N^2) and the Hessian-vector products H w_v at N nodes (30 flops per body: offset,
-    distance powers, the projection d (d.w) and the accumulation) and the 12 flops that
-    form mu_new."""
+    (as algorithmic_flops; not when the forward's node states are read instead) plus, per
+    adjoint sweep, the transposed product (6 columns x 2 N^2) and the Hessian-vector
+    products H w_v at N nodes (30 flops per body: offset, distance powers, the projection
+    d (d.w) and the accumulation) and the 12 flops that form mu_new."""
     P = w.pert.shape[0]
-    total = algorithmic_flops(w, iters)
+    total = algorithmic_flops(w, iters) if resolve else 0.0
     for g in w.groups:
         it = adj_iters[g.ic_offset:g.ic_offset + g.n_ic, :g.segments]
         it = np.where(it > 0, it, 0).astype(np.float64)
@@ -135,9 +135,11 @@ def run_adjoint(args):
     gbar = torch.tensor(gbar_np, dtype=torch.float64, device="cuda")
 
     def step():
-        f = ctx.propagate_batched(ics, groups, model, want_bounds=True, tile_pairs=2048)
+        f = ctx.propagate_batched(ics, groups, model, want_bounds=True, want_nodes=args.adjoint_nodes,
+                                  tile_pairs=2048)
         fwd_ms = ctx.last_kernel_ms()
-        grad, adj_it, st = ctx.adjoint(f["bounds"], gbar, groups, model)
+        grad, adj_it, st = ctx.adjoint(f["bounds"], gbar, groups, model,
+                                       fwd_nodes=f["nodes"] if args.adjoint_nodes else None)
         return f, grad, adj_it, st, fwd_ms, ctx.last_kernel_ms()
 
     print(f"bench: adjoint of {w.name}: {n_ic} ICs, {ic_segments} IC-segments", flush=True)
@@ -169,7 +171,7 @@ def run_adjoint(args):
     valid = bool(gerr.max() <= 1e-8 and st == 0 and f["status"] == 0)
     print(f"bench: max rel gradient err vs oracle on {idx.size} ICs: {gerr.max():.3e}", flush=True)
 
-    flops = adjoint_flops(w, iters, ait)
+    flops = adjoint_flops(w, iters, ait, resolve=not args.adjoint_nodes)
     kms = float(np.mean(adj_ms))
     achieved = flops / (kms * 1e-3) / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -200,7 +202,8 @@ def run_adjoint(args):
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": w.name, "n_ic": n_ic, "segments": g0.segments, "nodes": g0.nodes, "tol": g0.tol,
-                   "perturbers": int(w.pert.shape[0]), "seed": "random dL/dy_final", "checkpoints": "segment bounds"},
+                   "perturbers": int(w.pert.shape[0]), "seed": "random dL/dy_final",
+                   "checkpoints": "node states" if args.adjoint_nodes else "segment bounds"},
         "accuracy": {"max_rel_grad_err_vs_oracle": float(gerr.max()), "checked_ics": int(idx.size),
                      "status_forward": int(f["status"]), "status_adjoint": int(st),
                      "mean_adjoint_sweeps_per_segment": round(float(ait[ait > 0].mean()), 3),
@@ -231,6 +234,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain-steps", type=int, default=3,
                     help="steps of the per-iteration (plain) path timed for the speedup; 0 skips")
+    ap.add_argument("--adjoint-nodes", action="store_true",
+                    help="with --adjoint: keep the forward's node states and read them in the adjoint "
+                         "instead of re-solving each segment from its checkpoint")
     ap.add_argument("--adjoint", action="store_true",
                     help="time forward (with checkpoints) + adjoint of the final state; default "
                          "workload then nbody-venus-16384-256d")

@@ -178,19 +178,24 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic,
  * (the fixed point of Sec. 2.2); with J_j = w2 df/dy at node j the loss gradient seeds
  * gbar give dL/dy0 = sum_j mu_j where mu = gbar + J^T (K_N^T mu), solved by sweeping until
  * the propagated gradient changes by less than adj_tol (relative).  Segments are taken
- * from the last: each is re-solved from its checkpoint with the forward code, then its
- * gradient seeds the end node of the previous one.  Fused FP64 path, nodes <= 128.
+ * from the last: each is re-solved from its checkpoint with the forward code (or, when
+ * fwd_nodes is given, its converged node states are read from there), then its gradient
+ * seeds the end node of the previous one.  Fused FP64 path, nodes <= 128.
  *   groups, model, opts  as in the forward pc_propagate_batched call
  *   ckpt        device [n_ic][ckpt_stride + 1][6] segment-boundary states of the forward call
  *               (its bounds_out); ckpt_stride >= every group's segment count
  *   gbar_final  device [n_ic][6] dL/d(final state)
  *   gbar_nodes  device [n_ic][ckpt_stride][nodes_stride][6] dL/d(node states), or NULL
+ *   fwd_nodes   device [n_ic][ckpt_stride][nodes_stride][6] the forward call's node states
+ *               (its nodes_out, same strides), or NULL: storing them costs 48 bytes per IC,
+ *               node and segment and saves the re-solves
  *   grad_ics    device [n_ic][6] dL/d(initial state), output
  *   adj_iters   device int32 [n_ic][ckpt_stride] adjoint sweeps per segment, or NULL
  * Returns PC_ENOTCONV if a forward re-solve or an adjoint sweep loop hit its cap. */
 int pc_adjoint(pc_ctx* ctx, int64_t n_ic, const pc_group* groups /* host */, int32_t n_groups,
                const pc_model* model, const pc_opts* opts, const double* ckpt, int32_t ckpt_stride,
-               const double* gbar_final, const double* gbar_nodes, int32_t nodes_stride,
+               const double* gbar_final, const double* gbar_nodes, const double* fwd_nodes,
+               int32_t nodes_stride,
                double adj_tol, int32_t adj_max_iter, double* grad_ics, int32_t* adj_iters,
                void* workspace, size_t ws_bytes, pc_stream_t stream);
 

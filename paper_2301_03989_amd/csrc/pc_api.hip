@@ -753,7 +753,8 @@ int pc_last_kernel_ms(pc_ctx* ctx, double* ms)
 
 int pc_adjoint(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int32_t n_groups, const pc_model* model,
                const pc_opts* opts, const double* ckpt, int32_t ckpt_stride, const double* gbar_final,
-               const double* gbar_nodes, int32_t nodes_stride, double adj_tol, int32_t adj_max_iter,
+               const double* gbar_nodes, const double* fwd_nodes, int32_t nodes_stride, double adj_tol,
+               int32_t adj_max_iter,
                double* grad_ics, int32_t* adj_iters, void* workspace, size_t ws_bytes, pc_stream_t stream)
 {
     if (!ctx) return PC_EINVAL;
@@ -779,7 +780,8 @@ int pc_adjoint(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int32_t n_grou
     for (const PcGroupDev& d : plan.groups)
         if (d.NP > 128) return set_error(ctx, PC_EINVAL, "the adjoint supports up to 128 nodes per segment");
     if (ckpt_stride < plan.max_S) return set_error(ctx, PC_EINVAL, "ckpt_stride < segments");
-    if (gbar_nodes && nodes_stride < plan.max_N) return set_error(ctx, PC_EINVAL, "nodes_stride < nodes");
+    if ((gbar_nodes || fwd_nodes) && nodes_stride < plan.max_N)
+        return set_error(ctx, PC_EINVAL, "nodes_stride < nodes");
     if (!workspace || ws_bytes < plan.total)
         return set_error(ctx, PC_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, plan.total);
     rc = ensure_staging(ctx, plan.staged + kAlign);
@@ -820,6 +822,7 @@ int pc_adjoint(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int32_t n_grou
     a.nodes_stride = nodes_stride;
     a.gbar_final = gbar_final;
     a.gbar_nodes = gbar_nodes;
+    a.fwd_nodes = fwd_nodes;
     a.adj_tol = adj_tol;
     a.adj_max_iter = adj_max_iter;
     a.grad_out = grad_ics;

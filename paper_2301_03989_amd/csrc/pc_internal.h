@@ -77,6 +77,8 @@ struct PcAdjParams {
     int32_t nodes_stride;
     const double* gbar_final;   // [n_ic][6] dL/d(final state)
     const double* gbar_nodes;   // [n_ic][ckpt_stride][nodes_stride][6] dL/d(node states), or null
+    const double* fwd_nodes;    // [n_ic][ckpt_stride][nodes_stride][6] the forward call's converged
+                                // node states, or null (each segment is re-solved from ckpt)
     double adj_tol;             // relative change of the propagated gradient that stops a sweep loop
     int32_t adj_max_iter;
     double* grad_out;           // [n_ic][6] dL/d(initial state)

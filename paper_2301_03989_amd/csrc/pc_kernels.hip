@@ -76,6 +76,25 @@ __device__ __forceinline__ PcSmem<2048>& pc_smem<2048>() { return g_smem2048; }
 template <>
 __device__ __forceinline__ PcSmem<1024>& pc_smem<1024>() { return g_smem1024; }
 
+// Segment s's ephemeris records (perturber data per node, Sec. 5.4.1) into LDS: positions
+// as [node][body][3] with the indirect term as body P, and per body mu, 3 mu / 2 and
+// 15 mu / 8 (the premultiplied series coefficients of pc_mu_r3).
+template <int PAIRS>
+static __device__ __forceinline__ void pc_stage_records(const double4* grec, int N, int P, PcSmem<PAIRS>& sm)
+{
+    for (int i = threadIdx.x; i < N * (P + 1); i += PAIRS / 4) {
+        const double4 q = grec[i];
+        sm.Rec[3 * i + 0] = q.x;
+        sm.Rec[3 * i + 1] = q.y;
+        sm.Rec[3 * i + 2] = q.z;
+        if (i < P) {
+            sm.Mu[i] = q.w;
+            sm.Mu[PC_MAX_PERT_DEV + i] = 1.5 * q.w;
+            sm.Mu[2 * PC_MAX_PERT_DEV + i] = 1.875 * q.w;
+        }
+    }
+}
+
 // Picard iterations of one segment for the job's ICs (initial states in sm.Y0): ephemeris
 // records into LDS, initial guess, then sweeps until every IC of the job has stopped.
 // On return yc holds the lane's share of the final iterate.  iters_out (may be null)
@@ -104,19 +123,7 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
     // this segment's ephemeris records into LDS (perturber data per node, Sec. 5.4.1)
     const double4* grec = reinterpret_cast<const double4*>(p.recs) +
                           (size_t)(g.rec_offset + (int64_t)s * N) * (P + 1);
-    if (rec_lds) {
-        for (int i = tid; i < N * (P + 1); i += NT) {
-            const double4 q = grec[i];
-            sm.Rec[3 * i + 0] = q.x;
-            sm.Rec[3 * i + 1] = q.y;
-            sm.Rec[3 * i + 2] = q.z;
-            if (i < P) {
-                sm.Mu[i] = q.w;
-                sm.Mu[PC_MAX_PERT_DEV + i] = 1.5 * q.w;
-                sm.Mu[2 * PC_MAX_PERT_DEV + i] = 1.875 * q.w;
-            }
-        }
-    }
+    if (rec_lds) pc_stage_records<PAIRS>(grec, N, P, sm);
     // initial guess at every (node, IC) pair: warm (Kepler) or cold start, Sec. 2.1,
     // staged through the F area as [node][comp 6][IC]
     {
@@ -479,19 +486,7 @@ __device__ __attribute__((noinline)) void pc_job_list(const PcParams& p, const P
             }
         };
 
-        if (rec_lds) {
-            for (int i = tid; i < N * (P + 1); i += NT) {
-                const double4 q = grec[i];
-                sm.Rec[3 * i + 0] = q.x;
-                sm.Rec[3 * i + 1] = q.y;
-                sm.Rec[3 * i + 2] = q.z;
-                if (i < P) {
-                    sm.Mu[i] = q.w;
-                    sm.Mu[PC_MAX_PERT_DEV + i] = 1.5 * q.w;
-                    sm.Mu[2 * PC_MAX_PERT_DEV + i] = 1.875 * q.w;
-                }
-            }
-        }
+        if (rec_lds) pc_stage_records<PAIRS>(grec, N, P, sm);
         for (int i = tid; i < 6 * PAIRS; i += NT) sF[i] = 0.0;   // rows past N stay zero
         __syncthreads();   // records staged, F cleared
         // the group's first COLS entries into its columns
@@ -756,7 +751,8 @@ __device__ __attribute__((noinline)) void pc_adjoint_job(const PcAdjParams& a, c
     double yc[6][4];
     int had_notconv = 0, adj_notconv = 0, dead_any = 0;
     for (int s = S - 1; s >= 0; --s) {
-        // re-solve segment s from its checkpoint
+        // segment s's converged iterate: the forward call's node states when given, else a
+        // re-solve from its checkpoint
         if (tid < T) {
             const double* src = a.ckpt + ((size_t)(job.ic0 + (tid < n ? tid : 0)) * (a.ckpt_stride + 1) + s) * 6;
             bool fin = true;
@@ -768,12 +764,29 @@ __device__ __attribute__((noinline)) void pc_adjoint_job(const PcAdjParams& a, c
             sm.Dead[tid] = !fin;
         }
         __syncthreads();
-        pc_segment_solve<PAIRS, NP>(p, g, n, job.ic0, s, sm, L, kp0, yc, nullptr, had_notconv, REC_CAP);
+        const double4* grec = reinterpret_cast<const double4*>(p.recs) +
+                              (size_t)(g.rec_offset + (int64_t)s * N) * (P + 1);
+        if (a.fwd_nodes) {
+            if (rec_lds) pc_stage_records<PAIRS>(grec, N, P, sm);
+            const int j = pc_node(L, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = pc_ic(L, r);
+                if (j < N && m < n) {
+                    const double* y = a.fwd_nodes + (((size_t)(job.ic0 + m) * a.ckpt_stride + s) * a.nodes_stride + j) * 6;
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) yc[c][r] = y[c];
+                } else {   // padding node or column: any finite state (its results are unused)
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) yc[c][r] = sY0[c * T + m];
+                }
+            }
+        } else {
+            pc_segment_solve<PAIRS, NP>(p, g, n, job.ic0, s, sm, L, kp0, yc, nullptr, had_notconv, REC_CAP);
+        }
         __syncthreads();
         const double Ts = g.t0 + g.h * s, Te = g.t0 + g.h * (s + 1);
         const double w2 = 0.5 * (Te - Ts);
-        const double4* grec = reinterpret_cast<const double4*>(p.recs) +
-                              (size_t)(g.rec_offset + (int64_t)s * N) * (P + 1);
 
         // seed of this segment at the lane's nodes: the next segment's gradient at the end
         // node, plus the node seeds when given (recomputed where needed, not held)

@@ -98,7 +98,7 @@ def load_library(path: str = LIB_PATH):
                                 ctypes.c_size_t, _vp, P(ctypes.c_int32)]
     lib.pc_set_tile_pairs.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32]
     lib.pc_adjoint.argtypes = [_vp, ctypes.c_int64, P(_Group), ctypes.c_int32, P(_Model), P(_Opts), _vp,
-                               ctypes.c_int32, _vp, _vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                               ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
                                _vp, _vp, _vp, ctypes.c_size_t, _vp]
     lib.pc_get_tile_pairs.argtypes = [_vp, ctypes.c_int32, P(ctypes.c_int32)]
     lib.pc_set_timing.argtypes = [_vp, ctypes.c_int]
@@ -290,10 +290,12 @@ class Context:
         return chosen.value
 
     def adjoint(self, ckpt, gbar_final, groups, model=None, gbar_nodes=None, adj_tol=1e-12,
-                adj_max_iter=200, raise_on_status=False, **opts):
+                adj_max_iter=200, raise_on_status=False, fwd_nodes=None, **opts):
         """pc_adjoint: dL/dy0 [n, 6] from the forward call's segment-boundary states ``ckpt``
         [n, S+1, 6] and the seeds dL/d(final state) [n, 6] (and dL/d(node states)
-        [n, S, N, 6]).  Returns (grad, adjoint sweeps per segment [n, S], status)."""
+        [n, S, N, 6]).  ``fwd_nodes``: the forward call's node states [n, S, N, 6]; given,
+        the segments are read instead of re-solved.  Returns (grad, adjoint sweeps per
+        segment [n, S], status)."""
         model = model or Model()
         _check_tensor(ckpt, "ckpt")
         _check_tensor(gbar_final, "gbar_final")
@@ -304,6 +306,8 @@ class Context:
             raise ValueError("ckpt must be [n, S+1, 6] and gbar_final [n, 6]")
         if gbar_nodes is not None:
             _check_tensor(gbar_nodes, "gbar_nodes", (n, S_max, N_max, 6))
+        if fwd_nodes is not None:
+            _check_tensor(fwd_nodes, "fwd_nodes", (n, S_max, N_max, 6))
         garr = (_Group * len(groups))(*[_Group(g.ic_offset, g.n_ic, g.t0, g.tf, g.nodes, g.segments, g.tol)
                                        for g in groups])
         mc, oc = model._c(), self.opts(**opts)
@@ -318,7 +322,8 @@ class Context:
         adj_it = torch.zeros((n, S_max), dtype=torch.int32, device=ckpt.device)
         rc = self.lib.pc_adjoint(self.handle, n, garr, len(groups), ctypes.byref(mc), ctypes.byref(oc),
                                  ctypes.c_void_p(ckpt.data_ptr()), S_max, ctypes.c_void_p(gbar_final.data_ptr()),
-                                 ctypes.c_void_p(gbar_nodes.data_ptr() if gbar_nodes is not None else 0), N_max,
+                                 ctypes.c_void_p(gbar_nodes.data_ptr() if gbar_nodes is not None else 0),
+                                 ctypes.c_void_p(fwd_nodes.data_ptr() if fwd_nodes is not None else 0), N_max,
                                  float(adj_tol), int(adj_max_iter), ctypes.c_void_p(grad.data_ptr()),
                                  ctypes.c_void_p(adj_it.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                  _stream_ptr(ckpt.device))

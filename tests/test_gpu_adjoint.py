@@ -78,6 +78,34 @@ def test_autograd_function(pc):
     (gx,) = torch.autograd.grad(loss, x)
     ref = oracle.adjoint(w.ics, g.t0, g.tf, g.nodes, g.segments, g.tol, om, c.cpu().numpy())
     assert _gerr(gx.cpu().numpy(), ref).max() < GTOL
+    # node states kept for the backward pass instead of re-solving from checkpoints
+    x2 = ics.clone().requires_grad_(True)
+    loss2 = (autograd.propagate(x2, groups, model, pc=pc, store_nodes=True) * c).sum()
+    (gx2,) = torch.autograd.grad(loss2, x2)
+    assert _gerr(gx2.cpu().numpy(), gx.cpu().numpy()).max() < 1e-12
+
+
+@pytest.mark.parametrize("nodes", [24, 64, 100])
+def test_adjoint_from_stored_node_states(pc, nodes):
+    """The forward call's node states in place of the re-solves: the same gradients (the
+    forward and a re-solve compute the same iterates, up to rounding where their job shapes
+    differ), also against the oracle, with end-state and node seeds."""
+    w = W.nbody_venus(37, seed=111, days=50.0, segments=3, nodes=nodes, tol=1e-13)
+    ics, groups, model, om, g = _setup(w)
+    fwd = pc.propagate_batched(ics, groups, model, want_bounds=True, want_nodes=True)
+    assert fwd["status"] == 0
+    rng = np.random.default_rng(nodes)
+    gbar = rng.standard_normal((w.n_ic, 6))
+    gn = np.zeros((w.n_ic, 3, nodes, 6))
+    gn[:, 1, nodes // 2] = rng.standard_normal((w.n_ic, 6))
+    gnt = torch.tensor(gn, device="cuda")
+    args = (fwd["bounds"], torch.tensor(gbar, device="cuda"), groups, model)
+    a, _, sa = pc.adjoint(*args, gbar_nodes=gnt)
+    b, _, sb = pc.adjoint(*args, gbar_nodes=gnt, fwd_nodes=fwd["nodes"])
+    assert sa == sb == 0
+    assert _gerr(b.cpu().numpy(), a.cpu().numpy()).max() < 1e-12
+    ref = oracle.adjoint(w.ics, g.t0, g.tf, g.nodes, g.segments, g.tol, om, gbar, gn)
+    assert _gerr(b.cpu().numpy(), ref).max() < GTOL
 
 
 def _venus_min_seeds(nodes, w, om, g, tau):
