@@ -85,6 +85,30 @@ def test_autograd_function(pc):
     assert _gerr(gx2.cpu().numpy(), gx.cpu().numpy()).max() < 1e-12
 
 
+def test_adjoint_sixteen_perturbers_global_records(pc):
+    """16 perturbers at 128 nodes: the records no longer fit beside the adjoint's scratch in
+    LDS, so the Hessian products read them from global memory."""
+    from paper_2301_03989_amd import pcprop
+    base = W.planet_elements()
+    extra = base.copy()
+    extra[:, 0] *= 0.37
+    extra[:, 6] += 2.1
+    pert = np.concatenate([base, extra])
+    w = W.nbody_venus(12, seed=112, days=40.0, segments=2, nodes=128, tol=1e-13)
+    g = w.groups[0]
+    ics = torch.tensor(w.ics, dtype=torch.float64, device="cuda")
+    groups = [pcprop.Group(0, w.n_ic, g.t0, g.tf, g.nodes, g.segments, g.tol)]
+    model, om = pcprop.Model(1.0, pert, 0.0), oracle.Model(1.0, pert, 0.0)
+    fwd = pc.propagate_batched(ics, groups, model, want_bounds=True, want_nodes=True)
+    assert fwd["status"] == 0
+    gbar = np.random.default_rng(12).standard_normal((w.n_ic, 6))
+    ref = oracle.adjoint(w.ics, g.t0, g.tf, g.nodes, g.segments, g.tol, om, gbar)
+    for nodes in (None, fwd["nodes"]):
+        grad, _, st = pc.adjoint(fwd["bounds"], torch.tensor(gbar, device="cuda"), groups, model, fwd_nodes=nodes)
+        assert st == 0
+        assert _gerr(grad.cpu().numpy(), ref).max() < GTOL
+
+
 @pytest.mark.parametrize("nodes", [24, 64, 100])
 def test_adjoint_from_stored_node_states(pc, nodes):
     """The forward call's node states in place of the re-solves: the same gradients (the

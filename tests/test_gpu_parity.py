@@ -120,6 +120,39 @@ def test_nbody_subset_parity(pc, n_ic):
     assert np.abs(r["iters"] - o["iters"]).max() <= 1
 
 
+def _many_bodies(n_pert):
+    """The eight planets and, past eight, copies of them shifted in phase with other masses."""
+    base = W.planet_elements()
+    extra = base.copy()
+    extra[:, 0] *= 0.37
+    extra[:, 6] += 2.1
+    return np.concatenate([base, extra])[:n_pert]
+
+
+@pytest.mark.parametrize("n_pert,nodes,precision", [(5, 64, "fp64"), (16, 64, "fp64"), (16, 256, "fp64"),
+                                                    (16, 256, "fp32-fp64"), (16, 128, "fp32-fp64")])
+def test_perturber_counts_and_record_paths(pc, n_pert, nodes, precision):
+    """Perturber counts that leave the four-body chunks ragged (5) and the maximum (16); at
+    256 nodes with 16 bodies a segment's records exceed the LDS share and the kernels read
+    them from global memory.  Both job shapes and the precision schedule."""
+    w0 = W.nbody_venus(29, days=80.0, segments=2, nodes=nodes, tol=1e-12)
+    w = W.Workload("many", w0.ics, w0.groups, _many_bodies(n_pert))
+    r, _ = _run(pc, w, want_bounds=True, precision=precision)
+    o = oracle_run(w, want_bounds=True)
+    assert r["status"] == 0
+    assert rel_err(r["states"], o["states"]).max() < TOL
+    assert rel_err(r["bounds"].reshape(-1, 6), o["bounds"].reshape(-1, 6)).max() < TOL
+    if precision == "fp64":
+        assert np.abs(r["iters"] - o["iters"]).max() <= 1
+        p, _ = _run(pc, w, path="plain")
+        assert rel_err(p["states"], o["states"]).max() < TOL
+    if n_pert == 16:   # one body past the limit is refused
+        from paper_2301_03989_amd import pcprop
+        with pytest.raises(pcprop.PcError) as e:
+            _run(pc, W.Workload("too-many", w0.ics, w0.groups, np.concatenate([w.pert, w.pert[:1]])))
+        assert e.value.code == pcprop.PC_EINVAL
+
+
 def test_fixed_iterations_agree_to_rounding(pc):
     w = W.nbody_venus(40)
     r, _ = _run(pc, w, fixed_iters=6, want_nodes=True)
