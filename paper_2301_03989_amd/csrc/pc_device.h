@@ -143,17 +143,6 @@ static __device__ __forceinline__ bool pc_kepler(const double (&y0)[6], double d
     return ok;
 }
 
-// 1/sqrt(x) in full FP64 for finite x > 0: the hardware estimate y refined by one
-// third-order step y (1 + e/2 + 3 e^2/8), e = 1 - x y^2 (the series of (1 - e)^(-1/2)).
-// No fix-up for x = 0 or x = inf: a zero distance or an infinite position gives a
-// non-finite result either way, and the stopping rule flags it.
-static __device__ __forceinline__ double pc_rsqrt(double x)
-{
-    const double y = __builtin_amdgcn_rsq(x);
-    const double e = fma(-(x * y), y, 1.0);
-    return fma(y * e, fma(e, 0.375, 0.5), y);
-}
-
 // mu / x^(3/2) in full FP64 for finite x > 0, the attraction factor of a point mass at
 // squared distance x: from the hardware estimate y of 1/sqrt(x) and e = 1 - x y^2 (x y^2
 // with y^2 rounded), x^(-3/2) = (y^2)^(3/2) (1 - e)^(-3/2) = y^3 (1 + 3e/2 + 15e^2/8 + O(e^3)).
@@ -405,6 +394,25 @@ static __device__ __forceinline__ void pc_force_glb(const double (&x)[R], const 
     }
 }
 
+// One attracting body's term of H w at offset d (squared length x): with A = mu/|d|^3 from
+// the premultiplied series of pc_mu_r3 and 1/|d|^2 = y^2 (1 + e + e^2) from the same
+// estimate y (error of order e^3), h -= A w - 3 A/|d|^2 (d.w) d.
+static __device__ __forceinline__ void pc_hess_term(double dx, double dy, double dz, double wx, double wy,
+                                                    double wz, double mu, double mu1, double mu2, double& hx,
+                                                    double& hy, double& hz)
+{
+    const double x = dx * dx + dy * dy + dz * dz;
+    const double y = __builtin_amdgcn_rsq(x);
+    const double t = y * y;
+    const double e = fma(-x, t, 1.0);
+    const double A = (y * t) * fma(e, fma(mu2, e, mu1), mu);
+    const double i2 = fma(t, fma(e, e, e), t);
+    const double c = (A * i2) * (3.0 * (dx * wx + dy * wy + dz * wz));
+    hx = fma(c, dx, fma(-A, wx, hx));
+    hy = fma(c, dy, fma(-A, wy, hy));
+    hz = fma(c, dz, fma(-A, wz, hz));
+}
+
 // H w for the symmetric force Jacobian H = da/dr at R points: every attracting body with
 // parameter mu at offset d contributes -mu (w/|d|^3 - 3 d (d.w)/|d|^5); the indirect term
 // does not depend on r.  Records as in pc_force_lds (LDS) or pc_force_glb (global).
@@ -416,37 +424,31 @@ static __device__ __forceinline__ void pc_hess_apply(const double (&x)[R], const
                                                      const double* srec, const double* smu, const double4* grec,
                                                      double (&hx)[R], double (&hy)[R], double (&hz)[R])
 {
+    const double ms1 = 1.5 * mu_sun, ms2 = 1.875 * mu_sun;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const double d2 = x[r] * x[r] + y[r] * y[r] + z[r] * z[r];
-        const double id = pc_rsqrt(d2);
-        const double i3 = id * id * id, i5 = i3 * id * id;
-        const double dw = 3.0 * i5 * (x[r] * wx[r] + y[r] * wy[r] + z[r] * wz[r]);
-        hx[r] = -mu_sun * (i3 * wx[r] - dw * x[r]);
-        hy[r] = -mu_sun * (i3 * wy[r] - dw * y[r]);
-        hz[r] = -mu_sun * (i3 * wz[r] - dw * z[r]);
+        hx[r] = hy[r] = hz[r] = 0.0;
+        pc_hess_term(x[r], y[r], z[r], wx[r], wy[r], wz[r], mu_sun, ms1, ms2, hx[r], hy[r], hz[r]);
     }
     const int stride = 3 * (P + 1);
     for (int b = 0; b < P; ++b) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            double qx, qy, qz, mu;
+            double qx, qy, qz, mu, mu1, mu2;
             if constexpr (LDSREC) {
                 const double* q = srec + jr[r] * stride + 3 * b;
                 qx = q[0]; qy = q[1]; qz = q[2];
                 mu = smu[b];
+                mu1 = smu[PC_MAX_PERT_DEV + b];
+                mu2 = smu[2 * PC_MAX_PERT_DEV + b];
             } else {
                 const double4 q = grec[(size_t)jr[r] * (P + 1) + b];
                 qx = q.x; qy = q.y; qz = q.z;
                 mu = q.w;
+                mu1 = 1.5 * q.w;
+                mu2 = 1.875 * q.w;
             }
-            const double dx = x[r] - qx, dy = y[r] - qy, dz = z[r] - qz;
-            const double id = pc_rsqrt(dx * dx + dy * dy + dz * dz);
-            const double i3 = id * id * id, i5 = i3 * id * id;
-            const double dw = 3.0 * i5 * (dx * wx[r] + dy * wy[r] + dz * wz[r]);
-            hx[r] -= mu * (i3 * wx[r] - dw * dx);
-            hy[r] -= mu * (i3 * wy[r] - dw * dy);
-            hz[r] -= mu * (i3 * wz[r] - dw * dz);
+            pc_hess_term(x[r] - qx, y[r] - qy, z[r] - qz, wx[r], wy[r], wz[r], mu, mu1, mu2, hx[r], hy[r], hz[r]);
         }
     }
 }
