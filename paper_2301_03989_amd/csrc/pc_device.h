@@ -9,6 +9,45 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 #define PC_PI 3.14159265358979323846
 
+// Moves inside a row of 16 lanes through DPP (no LDS round trip, unlike a lane shuffle).
+// CTRL: 0xB1 quad_perm [1,0,3,2] (lane ^ 1), 0x4E quad_perm [2,3,0,1] (lane ^ 2),
+// 0x128 row_ror:8 (lane ^ 8), 0x141 row_half_mirror (7 - lane in each 8),
+// 0x140 row_mirror (15 - lane).  Callers keep the source lanes active.
+template <int CTRL>
+static __device__ __forceinline__ int pc_dpp(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
+}
+template <int CTRL>
+static __device__ __forceinline__ double pc_dpp(double v)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)pc_dpp<CTRL>((int)(unsigned)b);
+    const unsigned hi = (unsigned)pc_dpp<CTRL>((int)(unsigned)(b >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Sum (OR) over the 16 lanes of a row, the butterfly over lane ^ 1, ^ 2, ^ 4, ^ 8: after
+// the two quad steps every quad holds one value, so the mirrored lanes (7 - lane within
+// each 8, then 15 - lane) hold what lane ^ 4 and lane ^ 8 hold, and every lane ends with
+// the butterfly's result bit for bit.
+static __device__ __forceinline__ double pc_row_sum16(double v)
+{
+    v += pc_dpp<0xB1>(v);
+    v += pc_dpp<0x4E>(v);
+    v += pc_dpp<0x141>(v);
+    v += pc_dpp<0x140>(v);
+    return v;
+}
+static __device__ __forceinline__ int pc_row_or16(int v)
+{
+    v |= pc_dpp<0xB1>(v);
+    v |= pc_dpp<0x4E>(v);
+    v |= pc_dpp<0x141>(v);
+    v |= pc_dpp<0x140>(v);
+    return v;
+}
+
 static __device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c)
 {
     // D = A(16x4) B(4x16) + C.  Operand lanes: A[l%16][l/16], B[l/16][l%16];
@@ -639,10 +678,7 @@ static __device__ __forceinline__ int pc_wide_epilogue(const double* sY0, const 
     }
     if (!node_ok) fr = 0;
     // OR over the strip's 16 nodes (the lanes of one row group)
-    fr |= __shfl_xor(fr, 1);
-    fr |= __shfl_xor(fr, 2);
-    fr |= __shfl_xor(fr, 4);
-    fr |= __shfl_xor(fr, 8);
+    fr = pc_row_or16(fr);
     // lane i < 16 returns the flag of local IC i = (i & 3) + 4 (i >> 2), held by the lanes
     // of row group i & 3 in element i >> 2
     return (__shfl(fr, 16 * (L.lane & 3)) >> (4 * ((L.lane >> 2) & 3))) & 7;
@@ -816,10 +852,10 @@ static __device__ __forceinline__ int pc_product(const double* sF, const double*
                 double py = yy[0] + (hi ? 0.0 : yy[1]);
                 double vd = (hi ? dd[1] : 0.0) + dd[2];
                 double vy = (hi ? yy[1] : 0.0) + yy[2];
-                pd += __shfl_xor(pd, 8);
-                py += __shfl_xor(py, 8);
-                vd += __shfl_xor(vd, 8);
-                vy += __shfl_xor(vy, 8);
+                pd += pc_dpp<0x128>(pd);   // lane ^ 8
+                py += pc_dpp<0x128>(py);
+                vd += pc_dpp<0x128>(vd);
+                vy += pc_dpp<0x128>(vy);
                 if (j < N) {
                     const bool ok = pd < fma(tl.ta, py, tl.tb) && vd < fma(tl.ta, vy, tl.tb);
                     const bool lo = !SW || (pd < fma(tl.sa, py, tl.sb) && vd < fma(tl.sa, vy, tl.sb));
@@ -828,7 +864,7 @@ static __device__ __forceinline__ int pc_product(const double* sF, const double*
                 }
             }
         }
-        flag |= __shfl_xor(flag, 8);
+        flag |= pc_dpp<0x128>(flag);
     }
     flag |= __shfl_xor(flag, 16);
     flag |= __shfl_xor(flag, 32);
@@ -920,8 +956,8 @@ static __device__ __forceinline__ void pc_publish(double* sF, const double (&yc)
         int jr[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const double s1 = __shfl_xor(hi ? yc[0][r] : yc[3][r], 8);
-            const double s2 = __shfl_xor(yc[4][r], 8);
+            const double s1 = pc_dpp<0x128>(hi ? yc[0][r] : yc[3][r]);   // lane ^ 8
+            const double s2 = pc_dpp<0x128>(yc[4][r]);
             xs[r] = hi ? s1 : yc[0][r];
             ys[r] = hi ? yc[3][r] : s1;
             zs[r] = hi ? s2 : yc[1][r];

@@ -855,10 +855,7 @@ __device__ __attribute__((noinline)) void pc_adjoint_job(const PcAdjParams& a, c
 #pragma unroll
                 for (int c = 0; c < 6; ++c) {
                     double part = node_ok ? acc[c][r] : 0.0;
-                    part += __shfl_xor(part, 1);
-                    part += __shfl_xor(part, 2);
-                    part += __shfl_xor(part, 4);
-                    part += __shfl_xor(part, 8);
+                    part = pc_row_sum16(part);
                     if ((L.lane & 15) == 0) sLamPart[(L.wave * 6 + c) * 16 + (L.lane >> 4) + 4 * r] = part;
                 }
             }
