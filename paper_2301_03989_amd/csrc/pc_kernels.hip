@@ -154,6 +154,11 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
     // precision schedule (uniform per job): an FP32 phase first when asked, then FP64
     // sweeps.  Sweep kinds: 0 FP64 Picard sweep, 1 FP32 Picard sweep (8-IC jobs),
     // 2 FP32 increment sweep (WIDE jobs, after one FP64 sweep; records in LDS).
+    // Increment jobs run in stages: increments to the switch threshold (0); one FP64 sweep
+    // (1) that re-anchors the iterate on y0 + w2 K_N F(Y) and so drops the FP32 rounding the
+    // large early increments left; increments again (2), now tiny and so accurate to far
+    // below tol (their summed rounding stays near 1e-16 relative), with the stopping rule
+    // applied to them; FP64 sweeps to the end (3) only if stage 2 hits its sweep cap.
     bool fp32 = MIXED;
     const bool incr = Sh::WIDE && rec_lds;
     int mode = (fp32 && !incr) ? 1 : 0;
@@ -161,8 +166,9 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
     // rounding is relative to the increment), but their summed FP32 rounding grows when they
     // run that far, so they hand over at 1e-8; FP32 Picard sweeps stall near 1e-7
     const double sw2 = p.switch2 > 0.0 ? p.switch2 : (incr ? 1e-16 : 1e-8);
-    const PcTol tl = pc_tol(p.tol_mode, t2, sw2);
+    PcTol tl = pc_tol(p.tol_mode, t2, sw2);
     int n32 = 0;
+    int stage = 0;
     float* sD = reinterpret_cast<float*>(sF);   // increment sweeps: dF, FP32
     double* sA = sF + 3 * PAIRS;                 // increment sweeps: a of the last publish
     int act[4];
@@ -205,21 +211,30 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
         __syncthreads();   // every wave is done reading F; flags complete
 
         // the job leaves FP32 once no iterating IC changes by more than the switch threshold
+        const bool stops = !fp32 || (MIXED && incr && stage == 2);   // stopping rule applies
         bool next32 = false;
         if (fp32) {
             int k = 0;
             for (int w = 0; w < Sh::W; ++w) k |= sm.Keep[w];
             ++n32;
             next32 = k && n32 < p.max_fp32;
+            if (MIXED && incr && !next32) stage = stage == 0 ? 1 : 3;
+        } else if (MIXED && incr && stage == 1) {
+            // the re-anchoring sweep ran: increments again until the change is below tol
+            stage = 2;
+            next32 = true;
+            n32 = 0;
+            tl.sa = tl.ta;
+            tl.sb = tl.tb;
         }
         // (3) stopping rule per IC (Sec. 2.2; per-block error of Sec. 3.2 with blocks of one IC);
-        //     not applied to FP32 sweeps
+        //     not applied to FP32 sweeps before the re-anchoring sweep
         if (tid < T && sm.Active[tid]) {
             const int f = pc_gather_flags<PAIRS, NP>(sm.Flag, tid);
             int rec = 0;
             if (f & 2) rec = -2;
             else if (p.fixed_iters > 0) rec = (it == p.fixed_iters) ? it : 0;
-            else if (!fp32 && !(f & 1)) rec = it;
+            else if (stops && !(f & 1)) rec = it;
             else if (it == p.max_iter) rec = -1;
             if (rec != 0) {
                 sm.Active[tid] = 0;
