@@ -72,13 +72,15 @@ typedef struct {
 enum { PC_INIT_KEPLER = 0, PC_INIT_COLD = 1 };   /* initial guess, Sec. 2.1 (warm / cold start) */
 enum { PC_TOL_REL = 0, PC_TOL_ABS = 1 };         /* relative or absolute stopping rule, Sec. 2.2 */
 /* Arithmetic of the sweeps.  PC_FP32_THEN_FP64 (fused path): every segment starts with
- * an FP32 phase and moves to FP64 sweeps once the relative change of every iterating IC
- * of the job is below switch_tol (or after max_fp32 FP32 sweeps).  Jobs of 16 or more ICs
- * run one FP64 sweep and then increment sweeps, Y <- Y + w2 K_N (F(Y) - F(Y_prev)), with
- * the FP64 force difference rounded to FP32 and multiplied on the FP32 matrix cores;
- * 8-IC jobs run Picard sweeps with an FP32 force and FP32 product.  The accumulation into
- * the iterate, the stopping test and all stored states stay FP64, so the converged result
- * is the FP64 fixed point.  iters_out counts all sweeps. */
+ * an FP32 phase, which ends once the relative change of every iterating IC of the job is
+ * below switch_tol (or after max_fp32 FP32 sweeps).  Jobs of 16 or more ICs run one FP64
+ * sweep and then increment sweeps, Y <- Y + w2 K_N (F(Y) - F(Y_prev)), with the FP64
+ * force difference rounded to FP32 and multiplied on the FP32 matrix cores; at the switch
+ * one FP64 sweep re-anchors the iterate on y0 + w2 K_N F(Y), and increment sweeps, now
+ * with the stopping rule, carry on to tol (FP64 sweeps follow only if max_fp32 is
+ * reached).  8-IC jobs run Picard sweeps with an FP32 force and FP32 product, then FP64
+ * sweeps.  The accumulation into the iterate, the stopping test and all stored states stay
+ * FP64, so the result converges to the FP64 fixed point.  iters_out counts all sweeps. */
 enum { PC_FP64 = 0, PC_FP32_THEN_FP64 = 1 };
 enum { PC_PATH_FUSED = 0, PC_PATH_PLAIN = 1 };   /* one persistent launch / per-iteration kernels */
 /* Granularity of the stopping rule (Sec. 3.2).  PC_CONV_PER_IC: every IC stops at its own
@@ -106,7 +108,7 @@ typedef struct {
                              propagation kernel, status copy) in a HIP graph and replay it while
                              the call's shapes, options and pointers repeat (default 0) */
     double switch_tol;    /* PC_FP32_THEN_FP64: relative change below which a job leaves FP32
-                             (0 = default: 1e-8 for FP32 increment sweeps, 1e-4 for FP32
+                             (0 = default: 1e-6 for FP32 increment sweeps, 1e-4 for FP32
                              Picard sweeps of 8-IC jobs) */
     int32_t max_fp32;     /* PC_FP32_THEN_FP64: cap on FP32 sweeps per segment (0 = default 24) */
     int32_t job_list;     /* fused FP64 forward calls: ICs per job in units of its column block
