@@ -364,8 +364,12 @@ def test_fp32_then_fp64_matches_fp64_oracle(pc, n_ic):
     err = rel_err(r["states"], o["states"])
     assert err.max() < TOL, err.max()
     assert rel_err(r["bounds"].reshape(-1, 6), o["bounds"].reshape(-1, 6)).max() < TOL
-    # the FP32 sweeps come on top of the FP64 ones needed from ~1e-6
     assert (r["iters"] >= 2).all()
+    # increment jobs (16-IC columns at 128 nodes): the re-anchoring sweep leaves the second
+    # stage's rounding far below tol, so the schedule stops where the FP64 iteration does,
+    # at nearly its accuracy
+    assert err.max() < 1e-11, err.max()
+    assert np.abs(r["iters"] - o["iters"]).max() <= 1
 
 
 def test_fp32_then_fp64_mixed_groups(pc):
