@@ -685,11 +685,11 @@ static __device__ __forceinline__ int pc_wide_epilogue(const double* sY0, const 
 }
 
 // Increment sweep of the precision schedule (WIDE shapes): Y_new = Y + w2 K_N dF with
-// dF = F(Y) - F(Y_prev) held in LDS as FP32 (sD, [node][comp 6][IC] with the column
-// swizzle of pc_fcol) and multiplied on the FP32 matrix cores; the sum into Y stays FP64.
-// In exact arithmetic this is the Picard sweep (Y = y0 + w2 K F(Y_prev) by induction);
-// the FP32 rounding is relative to the increment, so it shrinks as the sweeps converge
-// instead of leaving a floor at the FP32 precision of Y.  Returns the flags as pc_product.
+// dF, the change of F (pc_publish_chord), held in LDS as FP32 (sD, [node][comp 6][IC]
+// with the column swizzle of pc_fcol) and multiplied on the FP32 matrix cores; the sum
+// into Y stays FP64.  The FP32 rounding is relative to the increment, so it shrinks as the
+// sweeps converge instead of leaving a floor at the FP32 precision of Y.  Returns the
+// flags as pc_product.
 template <int PAIRS, int NP>
 static __device__ __forceinline__ int pc_product_incr(const float* sD, gconst_fp kp0f, const double (&yc)[6][4],
                                                       f64x4 (&acc)[6], double w2, const PcTol& tl, int N,
@@ -996,16 +996,61 @@ static __device__ __forceinline__ void pc_publish(double* sF, const double (&yc)
     }
 }
 
-// Publish for an increment sweep (WIDE shapes): the FP64 force at the new iterate yc, the
-// change of F since the last publish, dF = (dv, a - a_old), rounded to FP32 into sD, and a
-// into sA ([node][3][IC], FP64, read back only by the same lane).  dv is the change of the
-// velocities.  a_old comes from sA, or (FROM_F) from the registers of the caller, which
-// read it from the FP64 force array that sD and sA now overwrite.
+// Gravity gradient da/dr of the force model at R points of node j, in FP32, as the six
+// entries (xx, yy, zz, xy, xz, yz) of the symmetric 3x3 matrix: every point mass (the Sun
+// at the origin, the perturbers at their record positions) adds mu (3 d d^T / |d|^5 -
+// I / |d|^3), d the offset of the point from the mass; the indirect term does not depend
+// on the position.  Used as the linear map of the increment sweeps, whose limit moves by
+// the error of G times the distance of the anchor from the solution: d is formed in FP64
+// and then rounded (near a close approach, rounding the positions first would leave an
+// error of 1e-5 in G and of about 1e-12 in the result), the rest is FP32.
+template <int R>
+static __device__ __forceinline__ void pc_grad_lds_node32(const double (&x)[R], const double (&y)[R],
+                                                          const double (&z)[R], int j, int P, double mu_sun,
+                                                          const double* srec, const double* smu,
+                                                          float (&G)[6][R])
+{
+    const double* rec = srec + j * 3 * (P + 1);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+        for (int e = 0; e < 6; ++e) G[e][r] = 0.0f;
+    }
+    auto add = [&](int r, float dx, float dy, float dz, float mu) {
+        const float q = __builtin_amdgcn_rsqf(dx * dx + dy * dy + dz * dz);
+        const float q2 = q * q;
+        const float m3 = mu * q * q2;          // mu / |d|^3
+        const float m5 = 3.0f * m3 * q2;       // 3 mu / |d|^5
+        const float tx = m5 * dx, ty = m5 * dy, tz = m5 * dz;
+        G[0][r] += fmaf(tx, dx, -m3);
+        G[1][r] += fmaf(ty, dy, -m3);
+        G[2][r] += fmaf(tz, dz, -m3);
+        G[3][r] = fmaf(tx, dy, G[3][r]);
+        G[4][r] = fmaf(tx, dz, G[4][r]);
+        G[5][r] = fmaf(ty, dz, G[5][r]);
+    };
+    const float ms = (float)mu_sun;
+#pragma unroll
+    for (int r = 0; r < R; ++r) add(r, (float)x[r], (float)y[r], (float)z[r], ms);
+    for (int b = 0; b < P; ++b) {
+        const double qx = rec[3 * b], qy = rec[3 * b + 1], qz = rec[3 * b + 2];
+        const float mu = (float)smu[b];
+#pragma unroll
+        for (int r = 0; r < R; ++r) add(r, (float)(x[r] - qx), (float)(y[r] - qy), (float)(z[r] - qz), mu);
+    }
+}
+
+// Publish for an increment sweep (WIDE shapes).  The increment of F = (v, a) from the last
+// change dy of the iterate, to first order: dF = (dv, G dr), with G the gravity gradient
+// at the anchor, the iterate after the last FP64 sweep (ANCHOR: evaluated here at yc and
+// kept in sG, [node][6][IC] FP32, read back only by the same lane; else read from sG).
+// dF goes to sD rounded to FP32.  act[r]: the lane's IC r iterates (others publish zero,
+// so that no stale or non-finite value reaches the product).
 template <int PAIRS, int NP>
-static __device__ __forceinline__ void pc_publish_incr(float* sD, double* sA, const double (&yc)[6][4],
-                                                       const double (&dv)[3][4], const double (&aold)[3][4],
-                                                       bool aold_given, const PcLane& L, int N, int P,
-                                                       double mu_sun, const double* sRec, const double* sMu)
+static __device__ __forceinline__ void pc_publish_chord(float* sD, float* sG, const double (&yc)[6][4],
+                                                        const float (&dy)[6][4], const int (&act)[4],
+                                                        bool anchor, const PcLane& L, int N, int P,
+                                                        double mu_sun, const double* sRec, const double* sMu)
 {
     using Sh = PcShape<PAIRS, NP>;
     static_assert(Sh::WIDE, "increment sweeps run on WIDE job shapes");
@@ -1020,25 +1065,36 @@ static __device__ __forceinline__ void pc_publish_incr(float* sD, double* sA, co
         }
         return;
     }
-    double ax[4], ay[4], az[4];
-    pc_force_lds_node<4>(yc[0], yc[1], yc[2], j, P, mu_sun, sRec, sMu, ax, ay, az);
+    float G[6][4];
+    if (anchor) {
+        pc_grad_lds_node32<4>(yc[0], yc[1], yc[2], j, P, mu_sun, sRec, sMu, G);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            float* g = sG + j * 6 * T + pc_fcol<PAIRS, NP>(j, pc_ic(L, r));
+#pragma unroll
+            for (int e = 0; e < 6; ++e) {
+                G[e][r] = act[r] ? G[e][r] : 0.0f;
+                g[e * T] = G[e][r];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const float* g = sG + j * 6 * T + pc_fcol<PAIRS, NP>(j, pc_ic(L, r));
+#pragma unroll
+            for (int e = 0; e < 6; ++e) G[e][r] = g[e * T];
+        }
+    }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int col = pc_fcol<PAIRS, NP>(j, pc_ic(L, r));
-        double* a = sA + j * 3 * T + col;
-        const double a0 = aold_given ? aold[0][r] : a[0];
-        const double a1 = aold_given ? aold[1][r] : a[T];
-        const double a2 = aold_given ? aold[2][r] : a[2 * T];
-        float* d = sD + j * ROW + col;
-        d[0 * T] = (float)dv[0][r];
-        d[1 * T] = (float)dv[1][r];
-        d[2 * T] = (float)dv[2][r];
-        d[3 * T] = (float)(ax[r] - a0);
-        d[4 * T] = (float)(ay[r] - a1);
-        d[5 * T] = (float)(az[r] - a2);
-        a[0] = ax[r];
-        a[T] = ay[r];
-        a[2 * T] = az[r];
+        float* d = sD + j * ROW + pc_fcol<PAIRS, NP>(j, pc_ic(L, r));
+        const float rx = dy[0][r], ry = dy[1][r], rz = dy[2][r];
+        d[0 * T] = dy[3][r];
+        d[1 * T] = dy[4][r];
+        d[2 * T] = dy[5][r];
+        d[3 * T] = fmaf(G[0][r], rx, fmaf(G[3][r], ry, G[4][r] * rz));
+        d[4 * T] = fmaf(G[3][r], rx, fmaf(G[1][r], ry, G[5][r] * rz));
+        d[5 * T] = fmaf(G[4][r], rx, fmaf(G[5][r], ry, G[2][r] * rz));
     }
 }
 

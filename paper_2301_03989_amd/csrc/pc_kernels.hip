@@ -154,25 +154,31 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
     // precision schedule (uniform per job): an FP32 phase first when asked, then FP64
     // sweeps.  Sweep kinds: 0 FP64 Picard sweep, 1 FP32 Picard sweep (8-IC jobs),
     // 2 FP32 increment sweep (WIDE jobs, after one FP64 sweep; records in LDS).
-    // Increment jobs run in stages: increments to the switch threshold (0); one FP64 sweep
-    // (1) that re-anchors the iterate on y0 + w2 K_N F(Y) and so drops the FP32 rounding the
-    // large early increments left; increments again (2), now tiny and so accurate to far
-    // below tol (their summed rounding stays near 1e-16 relative), with the stopping rule
-    // applied to them; FP64 sweeps to the end (3) only if stage 2 hits its sweep cap.
+    // An increment sweep adds w2 K_N dF to the FP64 iterate, dF the change of F to first
+    // order in the last change of the iterate, (dv, G dr), with G the gravity gradient at
+    // the iterate of the last FP64 sweep (the anchor); dF and the product are FP32, and no
+    // force is evaluated.  From an anchor these sweeps converge, at the Picard rate, to the
+    // Newton step from it (error quadratic in the anchor's); the FP32 rounding they add is
+    // relative to the increments.  Increment jobs run in stages: increments to the switch
+    // threshold (0); one FP64 sweep (1) that re-anchors the iterate on y0 + w2 K_N F(Y),
+    // dropping the rounding and the linearisation error of stage 0; increments again (2),
+    // from the closer anchor, until no IC changes by more than tol; then FP64 sweeps (3),
+    // the only ones the stopping rule is applied to, so that every IC stops on an FP64
+    // sweep that changed it by less than tol (one sweep for most ICs; more where the
+    // linearisation left more, as near close approaches, or where stage 2 hit its cap).
     bool fp32 = MIXED;
     const bool incr = Sh::WIDE && rec_lds;
     int mode = (fp32 && !incr) ? 1 : 0;
-    // default switch: the first increment stage hands over at a relative change of 1e-6 (the
-    // re-anchoring sweep then drops its rounding, and the second stage's increments are
-    // small enough for its own rounding to stay far below tol; a switch at 1e-4 left 6e-10,
-    // 1e-8 left 3e-12, 1e-6 3e-13 on the 262144-IC workload at the same speed); FP32 Picard
-    // sweeps stall near 1e-7
+    // default switch: the first increment stage hands over at a relative change of 1e-6
+    // (on the 262144-IC N-body workload 1e-5, 1e-6 and 1e-7 took 96.5, 95.5 and 97.7 ms;
+    // a later switch lengthens stage 0, an earlier one leaves a farther anchor for stage 2);
+    // FP32 Picard sweeps stall near 1e-7
     const double sw2 = p.switch2 > 0.0 ? p.switch2 : (incr ? 1e-12 : 1e-8);
     PcTol tl = pc_tol(p.tol_mode, t2, sw2);
     int n32 = 0;
     int stage = 0;
-    float* sD = reinterpret_cast<float*>(sF);   // increment sweeps: dF, FP32
-    double* sA = sF + 3 * PAIRS;                 // increment sweeps: a of the last publish
+    float* sD = reinterpret_cast<float*>(sF);                // increment sweeps: dF, FP32
+    float* sG = reinterpret_cast<float*>(sF + 3 * PAIRS);    // increment sweeps: G at the anchor
     int act[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) act[r] = sm.Active[pc_ic(L, r)];
@@ -213,7 +219,7 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
         __syncthreads();   // every wave is done reading F; flags complete
 
         // the job leaves FP32 once no iterating IC changes by more than the switch threshold
-        const bool stops = !fp32 || (MIXED && incr && stage == 2);   // stopping rule applies
+        const bool stops = !fp32;   // stopping rule applies
         bool next32 = false;
         if (fp32) {
             int k = 0;
@@ -222,7 +228,7 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
             next32 = k && n32 < p.max_fp32;
             if (MIXED && incr && !next32) stage = stage == 0 ? 1 : 3;
         } else if (MIXED && incr && stage == 1) {
-            // the re-anchoring sweep ran: increments again until the change is below tol
+            // the re-anchoring sweep ran: increments again until no change exceeds tol
             stage = 2;
             next32 = true;
             n32 = 0;
@@ -230,7 +236,7 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
             tl.sb = tl.tb;
         }
         // (3) stopping rule per IC (Sec. 2.2; per-block error of Sec. 3.2 with blocks of one IC);
-        //     not applied to FP32 sweeps before the re-anchoring sweep
+        //     applied to FP64 sweeps only
         if (tid < T && sm.Active[tid]) {
             const int f = pc_gather_flags<PAIRS, NP>(sm.Flag, tid);
             int rec = 0;
@@ -251,35 +257,29 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
         //     increment sweep, the change of F)
         if constexpr (MIXED && Sh::WIDE) {
             if (next_mode == 2 && it < n_it) {
-                double dv[3][4], aold[3][4];
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) dv[c][r] = act[r] ? acc[3 + c][r] - yc[3 + c][r] : 0.0;
-                }
-                const bool from_f = mode != 2;   // first increment: a of the FP64 force array
-                if (from_f) {
-                    const int j = pc_node(L, 0, 0);
-                    const int jj = j < N ? j : N - 1;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const double* f = sF + jj * Sh::ROW + pc_fcol<PAIRS, NP>(jj, pc_ic(L, r));
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) aold[c][r] = f[(3 + c) * T];
-                    }
-                    __syncthreads();   // every lane has its a before the array is rewritten
-                }
+                float dy[6][4];
 #pragma unroll
                 for (int b = 0; b < 6; ++b) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) yc[b][r] = act[r] ? acc[b][r] : yc[b][r];
+                    for (int r = 0; r < 4; ++r) {
+                        dy[b][r] = act[r] ? (float)(acc[b][r] - yc[b][r]) : 0.0f;
+                        yc[b][r] = act[r] ? acc[b][r] : yc[b][r];
+                    }
                 }
-                pc_publish_incr<PAIRS, NP>(sD, sA, yc, dv, aold, from_f, L, N, P, p.mu_sun, sm.Rec, sm.Mu);
+                // after an FP64 sweep the new iterate is the anchor: G evaluated there
+                pc_publish_chord<PAIRS, NP>(sD, sG, yc, dy, act, mode != 2, L, N, P, p.mu_sun, sm.Rec, sm.Mu);
                 fp32 = next32;
                 mode = next_mode;
                 __syncthreads();   // F complete; the active notes visible
                 if (!pc_any_active<PAIRS, NP>(sm)) break;
                 continue;
+            }
+        }
+        if constexpr (MIXED && Sh::WIDE) {
+            // back to FP64 after increment sweeps: the FP32 arrays left arbitrary bits in the
+            // rows past N of the FP64 view, which meet zero operator columns; clear them
+            if (mode == 2 && N < NP) {
+                for (int i = N * ROW + tid; i < NP * ROW; i += NT) sF[i] = 0.0;
             }
         }
         if (act[0] | act[1] | act[2] | act[3]) {

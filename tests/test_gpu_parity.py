@@ -365,11 +365,14 @@ def test_fp32_then_fp64_matches_fp64_oracle(pc, n_ic):
     assert err.max() < TOL, err.max()
     assert rel_err(r["bounds"].reshape(-1, 6), o["bounds"].reshape(-1, 6)).max() < TOL
     assert (r["iters"] >= 2).all()
-    # increment jobs (16-IC columns at 128 nodes): the re-anchoring sweep leaves the second
-    # stage's rounding far below tol, so the schedule stops where the FP64 iteration does,
-    # at nearly its accuracy
+    # increment jobs (16-IC columns at 128 nodes): increment sweeps converge at the Picard
+    # rate until no IC of the job changes by more than tol, then every IC stops on an FP64
+    # sweep that changed it by less than tol: near the FP64 iteration's accuracy, mostly one
+    # sweep after the FP64 iteration stops (more where the job's slowest IC holds it)
     assert err.max() < 1e-11, err.max()
-    assert np.abs(r["iters"] - o["iters"]).max() <= 1
+    d = r["iters"] - o["iters"]
+    assert d.min() >= -1 and d.max() <= 3, (d.min(), d.max())
+    assert d.mean() <= 1.5, d.mean()
 
 
 def test_fp32_then_fp64_mixed_groups(pc):
