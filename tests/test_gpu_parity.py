@@ -375,6 +375,23 @@ def test_fp32_then_fp64_matches_fp64_oracle(pc, n_ic):
     assert d.mean() <= 1.5, d.mean()
 
 
+@pytest.mark.parametrize("nodes", [48, 100])
+def test_fp32_then_fp64_padded_nodes_and_nonfinite_ic(pc, nodes):
+    """Increment sweeps on job shapes padded past N (48 of 64 and 100 of 128 nodes: rows
+    past N of the force array, written by the FP32 sweeps, meet zero operator columns once
+    FP64 sweeps resume), with a non-finite IC in the job."""
+    w = W.nbody_venus(40, seed=105, nodes=nodes, segments=2, days=112.5)
+    w.ics = w.ics.copy()
+    w.ics[3, 1] = np.nan
+    r, _ = _run(pc, w, precision="fp32-fp64")
+    o = oracle_run(w)
+    assert (r["iters"][3] == -2).all() and np.isnan(r["states"][3]).all()
+    ok = np.arange(w.n_ic) != 3
+    assert (r["iters"][ok] > 0).all()
+    err = rel_err(r["states"][ok], o["states"][ok])
+    assert err.max() < 1e-11, err.max()
+
+
 def test_fp32_then_fp64_mixed_groups(pc):
     w = W.uneven_batch(600, seed=22)
     for g in w.groups:
