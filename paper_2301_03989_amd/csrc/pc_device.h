@@ -102,10 +102,12 @@ static __device__ void pc_body_position(const PcBodyDev& B, double dt_epoch, dou
 //   F(x) = x - (1 - r0/a) sin x + (r0.v0/sqrt(a)) (1 - cos x) - n dt = 0.
 // Solved by Halley's iteration x -= 2 F F' / (2 F'^2 - F F''), cubically convergent; F''
 // comes from the same sine and cosine as F and F', so a step costs what a Newton step
-// does and three steps replace five from the mean-anomaly start.  A step below 1e-10
-// leaves an error of order 1e-30, far under one ulp, so the loop stops there, and the
-// sine and cosine at the final x follow from those of the last step by its Taylor
-// expansion (the step is below 1e-9, so the dropped cubic term is under 1e-27).
+// does and three steps replace five from the mean-anomaly start.  The error after a step
+// is about K e^3, e the error before it (close to the step) and K = O(1) for e < 0.8, so
+// a step below 1e-5 leaves an error near 1e-15 and the loop stops there; the
+// sine and cosine at the final x follow from those of the last step by its second-order
+// Taylor expansion (the dropped cubic term is under 2e-16).  The warm start is only the
+// initial guess: the iteration converges to the same fixed point from any nearby one.
 // The state goes in and out by value (registers, no stack traffic); a non-elliptic or
 // degenerate state returns NaN components.
 struct PcState6 {
@@ -141,7 +143,7 @@ static __device__ __attribute__((noinline)) PcState6 pc_kepler_state(PcState6 s0
         const double F2 = ec * sx + es * cx;
         const double dx = 2.0 * F * F1 / (2.0 * F1 * F1 - F * F2);
         x -= dx;
-        if (fabs(dx) <= 1e-10 * (1.0 + fabs(x))) {
+        if (fabs(dx) <= 1e-5) {
             // sin and cos of x = x_prev - dx
             const double h2 = 0.5 * dx * dx;
             const double s1 = sx - dx * cx - h2 * sx;
