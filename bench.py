@@ -414,7 +414,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": w.name, "n_ic": n_ic, "segments": [g.segments for g in w.groups][:4],
+        "config": {"workload": w.name, "n_ic": n_ic, "segments": sorted({g.segments for g in w.groups}),
                    "nodes": sorted({g.nodes for g in w.groups}), "tol": w.groups[0].tol,
                    "perturbers": int(w.pert.shape[0]), "path": "fused", "graph": bool(args.graph), "precision": precision,
                    "tile_pairs": args.tile_pairs or "tuned", "job_list": args.job_list or "auto"},
