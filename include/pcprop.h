@@ -120,9 +120,9 @@ typedef struct {
                              (the ICs one workgroup iterates at once: 2048 / padded nodes, or
                              1024 / padded nodes with tile_pairs 1024); when an IC converges,
                              its column takes the next IC of the job for the same segment.
-                             0 = automatic (the largest of 1, 2, 4, 8 leaving a job for every
-                             compute unit), 1 = off, 2, 4 or 8 = that many blocks.  Results do
-                             not depend on it. */
+                             0 = automatic (the longest of 1, 2, 4, 8 whose jobs fill the
+                             workgroup slots within 25 % of the fewest block-times), 1 = off,
+                             2, 4 or 8 = that many blocks.  Results do not depend on it. */
     int32_t conv;         /* PC_CONV_PER_IC (default) or PC_CONV_GROUP_MAX */
 } pc_opts;
 

@@ -326,11 +326,17 @@ int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, c
     for (size_t i = 1; i < spans.size(); ++i)
         if (spans[i].first < spans[i - 1].second) return set_error(ctx, PC_EINVAL, "groups overlap");
 
-    // ICs per job in units of the job's columns: the largest of 1, 2, 4, 8 that still
-    // leaves a job for every compute unit (one workgroup fits per CU).  Longer jobs refill
-    // their columns for longer, so fewer columns idle in segment tails; measured on
-    // 16384 eccentric ICs, one job per CU beat four shorter ones per CU by about 10 % at
-    // 128 and 256 nodes, and by 1.3 % on the uneven 65536-IC batch
+    // ICs per job in units of the job's columns (1, 2, 4 or 8 blocks).  Longer jobs refill
+    // their columns for longer, so fewer columns idle in segment tails (on 16384 eccentric
+    // ICs, one 8-block job per CU beat eight one-block jobs per CU by about 10 % at 256
+    // nodes), but the queue hands out whole jobs: J jobs of m blocks on S workgroup slots
+    // take up to ceil(J / S) m block-times.  The choice is the longest jobs whose bound is
+    // within 25 % of the best one (the bound is loose when jobs of several groups, sorted
+    // longest first, fill each other's gaps: on the uneven 65536-IC batch 8-block jobs,
+    // 20 % above the bound of 1-, 2- and 4-block ones, ran fastest).  A rule that only
+    // asked for a job per CU gave 270 two-block jobs to 256 CUs for 539 blocks (34 %
+    // slower than one-block jobs) and counted one slot per CU where the 1024-pair shape
+    // has two (25 % slower at 64 nodes).
     int list = 1;
     if (lists_ok && o.job_list != 1) {
         auto jobs_at = [&](int m) {
@@ -342,9 +348,18 @@ int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, c
             return nj;
         };
         if (o.job_list > 1) list = o.job_list;
-        else
-            for (int m = 2; m <= 8; m *= 2)
-                if (jobs_at(m) >= (int64_t)ctx->n_cu) list = m;
+        else {
+            int occ = 1;
+            if (pc_fused_occupancy(plan.pairs, &occ) != 0 || occ < 1) occ = 1;
+            const int64_t slots = (int64_t)ctx->n_cu * occ;
+            int64_t span[4], best = 0;
+            for (int k = 0; k < 4; ++k) {
+                span[k] = (jobs_at(1 << k) + slots - 1) / slots * (1 << k);
+                best = k == 0 ? span[0] : std::min(best, span[k]);
+            }
+            for (int k = 0; k < 4; ++k)
+                if (4 * span[k] <= 5 * best) list = 1 << k;
+        }
     }
     plan.list = list;
     struct Cost { int np; double c; PcJobDev j; };
