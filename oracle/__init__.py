@@ -46,7 +46,7 @@ def _load():
         lib.orc_propagate.argtypes = [
             ctypes.c_int, _dp, _dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
             ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
-            ctypes.c_int, _dp, ctypes.c_double, _dp, _ip, _dp, _dp, ctypes.c_int]
+            ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double, _dp, _ip, _dp, _dp, ctypes.c_int]
         lib.orc_propagate_group.restype = ctypes.c_int
         lib.orc_propagate_group.argtypes = [
             ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
@@ -70,7 +70,12 @@ def _load():
                                         ctypes.c_double, _dp]
         lib.orc_rk4.restype = None
         lib.orc_rk4.argtypes = [_dp, ctypes.c_double, ctypes.c_double, ctypes.c_long,
-                                ctypes.c_double, ctypes.c_int, _dp, ctypes.c_double, _dp]
+                                ctypes.c_double, ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double, _dp]
+        lib.orc_accel_eih_t.restype = None
+        lib.orc_accel_eih_t.argtypes = [_dp, ctypes.c_double, ctypes.c_double, ctypes.c_int, _dp,
+                                        ctypes.c_double, ctypes.c_double, _dp]
+        lib.orc_ephem_state.restype = None
+        lib.orc_ephem_state.argtypes = [_dp, ctypes.c_double, ctypes.c_double, _dp, _dp]
         _lib = lib
     return _lib
 
@@ -92,13 +97,15 @@ class Model:
     """Point-mass force model: Sun (mu_sun) plus perturbers on Keplerian orbits.
 
     ``pert`` is an array [n_pert, 7] of (mu_p, a, e, inc, raan, argp, M0) with
-    angles in radians and M0 the mean anomaly at ``epoch``.
+    angles in radians and M0 the mean anomaly at ``epoch``.  ``inv_c2`` > 0 (1/c^2
+    in the model's units) selects the Einstein-Infeld-Hoffmann dynamics (orc_accel_eih).
     """
 
-    def __init__(self, mu_sun=1.0, pert=None, epoch=0.0):
+    def __init__(self, mu_sun=1.0, pert=None, epoch=0.0, inv_c2=0.0):
         self.mu_sun = float(mu_sun)
         self.pert = _f64(np.zeros((0, 7)) if pert is None else pert).reshape(-1, 7)
         self.epoch = float(epoch)
+        self.inv_c2 = float(inv_c2)
 
     @property
     def n_pert(self):
@@ -133,8 +140,9 @@ def propagate(ics, t0, tf, nodes, segments, tol, model=None, *, tol_mode=0, max_
     bounds = np.zeros((n, S + 1, 6)) if want_bounds else None
     nodes_out = np.zeros((n, S, N, 6)) if want_nodes else None
     if conv == 1:
-        if np.ndim(t0) or np.ndim(tf) or fixed_iters:
-            raise ValueError("group-max convergence takes one t0 and tf and no fixed sweeps")
+        if np.ndim(t0) or np.ndim(tf) or fixed_iters or model.inv_c2:
+            raise ValueError("group-max convergence takes one t0 and tf, no fixed sweeps and "
+                             "the point-mass model")
         used = lib.orc_propagate_group(n, _ptr(ics), float(t0), float(tf), N, S, float(tol),
                                        int(tol_mode), int(max_iter), int(init), model.mu_sun,
                                        model.n_pert, model._pert_ptr(), model.epoch, _ptr(states),
@@ -143,7 +151,7 @@ def propagate(ics, t0, tf, nodes, segments, tol, model=None, *, tol_mode=0, max_
     else:
         used = lib.orc_propagate(n, _ptr(ics), _ptr(t0a), _ptr(tfa), N, S, float(tol), int(tol_mode),
                                  int(max_iter), int(fixed_iters), int(init), model.mu_sun,
-                                 model.n_pert, model._pert_ptr(), model.epoch, _ptr(states),
+                                 model.n_pert, model._pert_ptr(), model.epoch, model.inv_c2, _ptr(states),
                                  iters.ctypes.data_as(_ip), _ptr(bounds), _ptr(nodes_out), int(threads))
     out = [states, iters]
     if want_bounds:
@@ -228,8 +236,27 @@ def rk4(y0, t0, tf, nsteps, model):
     y0 = _f64(y0).reshape(6)
     y = np.zeros(6)
     lib.orc_rk4(_ptr(y0), float(t0), float(tf), int(nsteps), model.mu_sun, model.n_pert,
-                model._pert_ptr(), model.epoch, _ptr(y))
+                model._pert_ptr(), model.epoch, model.inv_c2, _ptr(y))
     return y
+
+
+def accel_eih_t(y, t, model):
+    """Einstein-Infeld-Hoffmann acceleration at the state y (r, v) and time t."""
+    lib = _load()
+    y = _f64(y).reshape(6)
+    a = np.zeros(3)
+    lib.orc_accel_eih_t(_ptr(y), float(t), model.mu_sun, model.n_pert, model._pert_ptr(),
+                        model.epoch, model.inv_c2, _ptr(a))
+    return a
+
+
+def ephem_state(el, epoch, t):
+    """Position and velocity of a perturber with elements el at time t."""
+    lib = _load()
+    el = _f64(el).reshape(7)
+    r, v = np.zeros(3), np.zeros(3)
+    lib.orc_ephem_state(_ptr(el), float(epoch), float(t), _ptr(r), _ptr(v))
+    return r, v
 
 
 def accel_jac_t(r, t, model):
@@ -257,6 +284,8 @@ def adjoint(ics, t0, tf, nodes, segments, tol, model=None, gbar_final=None, gbar
     gbar_final [n, 6] = dL/dy_final; gbar_nodes [n, S, N, 6] = dL/dY (optional).
     """
     model = model or Model()
+    if model.inv_c2:
+        raise ValueError("the adjoint is written for the point-mass model")
     ics = _f64(ics).reshape(-1, 6)
     n = ics.shape[0]
     S, N = int(segments), int(nodes)

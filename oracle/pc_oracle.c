@@ -38,6 +38,16 @@
  * this point-mass model is the workload's substitute for it.  As the paper
  * does (Sec. 5.4.1), perturber positions are evaluated once per node before
  * the iterations of a segment.
+ *
+ * Relativistic option (inv_c2 = 1/c^2 > 0): the paper's restricted N-body
+ * problem in the Einstein-Infeld-Hoffmann form it cites (Sec. 5.4.1: the
+ * acceleration depends on the position and velocity of the propagated body
+ * and on the positions, velocities, accelerations and potentials of the
+ * major bodies), restated in orc_accel_eih for a massless body with the PPN
+ * parameters beta = gamma = 1.  The major bodies are the Sun, fixed at the
+ * origin, and the perturbers on their Keplerian orbits, whose velocities and
+ * accelerations are the time derivatives of those orbits; the Newtonian
+ * indirect term is kept, so that inv_c2 = 0 gives the point-mass model.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -85,6 +95,27 @@ void orc_ephem(const double* el, double epoch, double t, double r[3])
     double P[3] = { cO * cw - sO * sw * ci, sO * cw + cO * sw * ci, sw * si };
     double Q[3] = { -cO * sw - sO * cw * ci, -sO * sw + cO * cw * ci, cw * si };
     for (int k = 0; k < 3; ++k) r[k] = xp * P[k] + yp * Q[k];
+}
+
+/* Position and velocity of the body of orc_ephem: the velocity is the time derivative
+ * of the same Keplerian orbit, dE/dt = n / (1 - e cos E). */
+void orc_ephem_state(const double* el, double epoch, double t, double r[3], double v[3])
+{
+    double a = el[1], e = el[2], inc = el[3], raan = el[4], argp = el[5], M0 = el[6];
+    double n = sqrt(1.0 / (a * a * a));
+    double E = orc_solve_kepler_E(M0 + n * (t - epoch), e);
+    double b = a * sqrt(1.0 - e * e);
+    double Ed = n / (1.0 - e * cos(E));
+    double xp = a * (cos(E) - e), yp = b * sin(E);
+    double xd = -a * sin(E) * Ed, yd = b * cos(E) * Ed;
+    double cO = cos(raan), sO = sin(raan), cw = cos(argp), sw = sin(argp);
+    double ci = cos(inc), si = sin(inc);
+    double P[3] = { cO * cw - sO * sw * ci, sO * cw + cO * sw * ci, sw * si };
+    double Q[3] = { -cO * sw - sO * cw * ci, -sO * sw + cO * cw * ci, cw * si };
+    for (int k = 0; k < 3; ++k) {
+        r[k] = xp * P[k] + yp * Q[k];
+        v[k] = xd * P[k] + yd * Q[k];
+    }
 }
 
 /* Two-body propagation (mu = 1) of y0 by dt, through the Lagrange f and g
@@ -154,6 +185,93 @@ void orc_accel(const double r[3], int n_pert, const double* rp, const double* mu
         double sq = mup[p] / (q2 * qn);     /* indirect term: Sun's acceleration towards p */
         for (int k = 0; k < 3; ++k) acc[k] -= sd * d[k] + sq * q[k];
     }
+}
+
+/* Einstein-Infeld-Hoffmann acceleration of a massless body at (r, v) = y, PPN beta =
+ * gamma = 1, written for the major bodies b: the Sun (index -1: at the origin, at rest,
+ * unaccelerated, parameter mu_sun) and the perturbers at rp[p] with velocities vp[p] and
+ * parameters mup[p], each on a Keplerian orbit about the Sun (gravitational parameter 1),
+ * so accelerated by -rp/|rp|^3.  With d = r - r_b, rho = |d|, the potential at the body
+ * Phi = sum_b mu_b / rho_b and U_b = sum_{k != b} mu_k / |r_b - r_k| at body b:
+ *   a = sum_b -mu_b d / rho^3 [1 - (4 Phi + U_b - v^2 - 2 v_b^2 + 4 v.v_b
+ *                                   + 3/2 (d.v_b / rho)^2 + 1/2 d.a_b) / c^2]
+ *     + sum_b mu_b / (c^2 rho^3) [d.(4 v - 3 v_b)] (v - v_b)
+ *     + 7/2 sum_b mu_b a_b / (c^2 rho)
+ * plus the Newtonian indirect term -sum_p mu_p rp/|rp|^3 of the heliocentric frame. */
+void orc_accel_eih(const double y[6], int n_pert, const double* rp, const double* vp, const double* mup,
+                   double mu_sun, double inv_c2, double acc[3])
+{
+    const double* r = y;
+    const double* v = y + 3;
+    double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    /* major-body states */
+    double rb[3 * 65], vb[3 * 65], ab[3 * 65], mub[65], Ub[65];
+    int nb = n_pert + 1;
+    for (int k = 0; k < 3; ++k) rb[k] = vb[k] = ab[k] = 0.0;
+    mub[0] = mu_sun;
+    for (int p = 0; p < n_pert; ++p) {
+        const double* q = rp + 3 * p;
+        double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+        for (int k = 0; k < 3; ++k) {
+            rb[3 * (p + 1) + k] = q[k];
+            vb[3 * (p + 1) + k] = vp[3 * p + k];
+            ab[3 * (p + 1) + k] = -q[k] / (qn * qn * qn);
+        }
+        mub[p + 1] = mup[p];
+    }
+    for (int b = 0; b < nb; ++b) {
+        Ub[b] = 0.0;
+        for (int k = 0; k < nb; ++k) {
+            if (k == b) continue;
+            double dx = rb[3 * b] - rb[3 * k], dy = rb[3 * b + 1] - rb[3 * k + 1], dz = rb[3 * b + 2] - rb[3 * k + 2];
+            Ub[b] += mub[k] / sqrt(dx * dx + dy * dy + dz * dz);
+        }
+    }
+    double phi = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        double dx = r[0] - rb[3 * b], dy = r[1] - rb[3 * b + 1], dz = r[2] - rb[3 * b + 2];
+        phi += mub[b] / sqrt(dx * dx + dy * dy + dz * dz);
+    }
+    for (int k = 0; k < 3; ++k) acc[k] = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        const double* xb = rb + 3 * b;
+        const double* wb = vb + 3 * b;
+        const double* gb = ab + 3 * b;
+        double d[3] = { r[0] - xb[0], r[1] - xb[1], r[2] - xb[2] };
+        double rho = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        double i3 = 1.0 / (rho * rho * rho);
+        double vbv = v[0] * wb[0] + v[1] * wb[1] + v[2] * wb[2];
+        double vb2 = wb[0] * wb[0] + wb[1] * wb[1] + wb[2] * wb[2];
+        double dvb = (d[0] * wb[0] + d[1] * wb[1] + d[2] * wb[2]) / rho;
+        double dab = d[0] * gb[0] + d[1] * gb[1] + d[2] * gb[2];
+        double brk = 1.0 - inv_c2 * (4.0 * phi + Ub[b] - v2 - 2.0 * vb2 + 4.0 * vbv + 1.5 * dvb * dvb + 0.5 * dab);
+        double dw = d[0] * (4.0 * v[0] - 3.0 * wb[0]) + d[1] * (4.0 * v[1] - 3.0 * wb[1]) +
+                    d[2] * (4.0 * v[2] - 3.0 * wb[2]);
+        for (int k = 0; k < 3; ++k) {
+            acc[k] += -mub[b] * i3 * d[k] * brk;
+            acc[k] += inv_c2 * mub[b] * i3 * dw * (v[k] - wb[k]);
+            acc[k] += 3.5 * inv_c2 * mub[b] * gb[k] / rho;
+        }
+    }
+    for (int p = 0; p < n_pert; ++p) {   /* indirect term */
+        const double* q = rp + 3 * p;
+        double q2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
+        double sq = mup[p] / (q2 * sqrt(q2));
+        for (int k = 0; k < 3; ++k) acc[k] -= sq * q[k];
+    }
+}
+
+/* orc_accel_eih at time t with the perturber states from their elements. */
+void orc_accel_eih_t(const double y[6], double t, double mu_sun, int n_pert, const double* pert,
+                     double epoch, double inv_c2, double acc[3])
+{
+    double rp[3 * 64], vp[3 * 64], mup[64];
+    int np = n_pert > 64 ? 64 : n_pert;
+    for (int p = 0; p < np; ++p) {
+        orc_ephem_state(pert + 7 * p, epoch, t, rp + 3 * p, vp + 3 * p);
+        mup[p] = pert[7 * p];
+    }
+    orc_accel_eih(y, np, rp, vp, mup, mu_sun, inv_c2, acc);
 }
 
 /* Jacobian da/dr (3x3, row-major) of the force model at r with perturbers at rp:
@@ -332,8 +450,8 @@ static double orc_iter_error(int N, const double* ynew, const double* yold, int 
 int orc_propagate(int n_ic, const double* ics, const double* t0, const double* tf,
                   int N, int S, double tol, int tol_mode, int max_iter, int fixed_iters,
                   int init, double mu_sun, int n_pert, const double* pert, double epoch,
-                  double* states_out, int* iters_out, double* bounds_out, double* nodes_out,
-                  int nthreads)
+                  double inv_c2, double* states_out, int* iters_out, double* bounds_out,
+                  double* nodes_out, int nthreads)
 {
     int used = 1;
 #ifdef _OPENMP
@@ -358,6 +476,7 @@ int orc_propagate(int n_ic, const double* ics, const double* t0, const double* t
         double* Yn = (double*)malloc(sizeof(double) * (size_t)N * 6);
         double* G = (double*)malloc(sizeof(double) * (size_t)N * 6);
         double* rp = (double*)malloc(sizeof(double) * (size_t)N * 3 * (np > 0 ? np : 1));
+        double* vp = (double*)malloc(sizeof(double) * (size_t)N * 3 * (np > 0 ? np : 1));
         double* cbuf = (double*)malloc(sizeof(double) * (size_t)(N + 2));
         double* bbuf = (double*)malloc(sizeof(double) * (size_t)(N + 2));
 #pragma omp for schedule(dynamic, 1)
@@ -382,10 +501,16 @@ int orc_propagate(int n_ic, const double* ics, const double* t0, const double* t
                 double Ts = t0[m] + h * s;
                 double Te = t0[m] + h * (s + 1);
                 double w1 = 0.5 * (Te + Ts), w2 = 0.5 * (Te - Ts);
-                /* perturber positions at the nodes, before iterating (Sec. 5.4.1) */
+                /* perturber positions (and velocities, for EIH) at the nodes, before
+                   iterating (Sec. 5.4.1) */
                 for (int j = 0; j < N; ++j) {
                     double tj = w2 * tau[j] + w1;
-                    for (int p = 0; p < np; ++p) orc_ephem(pert + 7 * p, epoch, tj, rp + 3 * (j * np + p));
+                    for (int p = 0; p < np; ++p) {
+                        if (inv_c2 != 0.0)
+                            orc_ephem_state(pert + 7 * p, epoch, tj, rp + 3 * (j * np + p), vp + 3 * (j * np + p));
+                        else
+                            orc_ephem(pert + 7 * p, epoch, tj, rp + 3 * (j * np + p));
+                    }
                 }
                 /* initial guess */
                 int cold = (init == 1);
@@ -404,7 +529,10 @@ int orc_propagate(int n_ic, const double* ics, const double* t0, const double* t
                     /* (i) force matrix */
                     for (int j = 0; j < N; ++j) {
                         double acc[3];
-                        orc_accel(Y + 6 * j, np, rp + 3 * j * np, mup, mu_sun, acc);
+                        if (inv_c2 != 0.0)
+                            orc_accel_eih(Y + 6 * j, np, rp + 3 * j * np, vp + 3 * j * np, mup, mu_sun, inv_c2, acc);
+                        else
+                            orc_accel(Y + 6 * j, np, rp + 3 * j * np, mup, mu_sun, acc);
                         for (int k = 0; k < 3; ++k) {
                             G[6 * j + k] = w2 * Y[6 * j + 3 + k];
                             G[6 * j + 3 + k] = w2 * acc[k];
@@ -429,7 +557,7 @@ int orc_propagate(int n_ic, const double* ics, const double* t0, const double* t
             }
             memcpy(states_out + 6 * m, y0, sizeof(y0));
         }
-        free(Y); free(Yn); free(G); free(rp); free(cbuf); free(bbuf);
+        free(Y); free(Yn); free(G); free(rp); free(vp); free(cbuf); free(bbuf);
     }
     free(Tkj); free(tau);
     return used;
@@ -571,29 +699,30 @@ int orc_propagate_group(int n_ic, const double* ics, double t0, double tf, int N
 /* ------------------------------------------------------------------------ */
 
 static void orc_rhs(const double* y, double t, double mu_sun, int n_pert, const double* pert,
-                    double epoch, double* dy)
+                    double epoch, double inv_c2, double* dy)
 {
     double acc[3];
-    orc_accel_t(y, t, mu_sun, n_pert, pert, epoch, acc);
+    if (inv_c2 != 0.0) orc_accel_eih_t(y, t, mu_sun, n_pert, pert, epoch, inv_c2, acc);
+    else orc_accel_t(y, t, mu_sun, n_pert, pert, epoch, acc);
     for (int k = 0; k < 3; ++k) { dy[k] = y[3 + k]; dy[3 + k] = acc[k]; }
 }
 
-/* Integrate y' = (v, a(r,t)) from t0 to tf with `nsteps` RK4 steps. */
+/* Integrate y' = (v, a(r,v,t)) from t0 to tf with `nsteps` RK4 steps. */
 void orc_rk4(const double y0[6], double t0, double tf, long nsteps, double mu_sun, int n_pert,
-             const double* pert, double epoch, double y[6])
+             const double* pert, double epoch, double inv_c2, double y[6])
 {
     double h = (tf - t0) / (double)nsteps;
     double k1[6], k2[6], k3[6], k4[6], tmp[6];
     memcpy(y, y0, sizeof(double) * 6);
     for (long i = 0; i < nsteps; ++i) {
         double t = t0 + h * (double)i;
-        orc_rhs(y, t, mu_sun, n_pert, pert, epoch, k1);
+        orc_rhs(y, t, mu_sun, n_pert, pert, epoch, inv_c2, k1);
         for (int k = 0; k < 6; ++k) tmp[k] = y[k] + 0.5 * h * k1[k];
-        orc_rhs(tmp, t + 0.5 * h, mu_sun, n_pert, pert, epoch, k2);
+        orc_rhs(tmp, t + 0.5 * h, mu_sun, n_pert, pert, epoch, inv_c2, k2);
         for (int k = 0; k < 6; ++k) tmp[k] = y[k] + 0.5 * h * k2[k];
-        orc_rhs(tmp, t + 0.5 * h, mu_sun, n_pert, pert, epoch, k3);
+        orc_rhs(tmp, t + 0.5 * h, mu_sun, n_pert, pert, epoch, inv_c2, k3);
         for (int k = 0; k < 6; ++k) tmp[k] = y[k] + h * k3[k];
-        orc_rhs(tmp, t + h, mu_sun, n_pert, pert, epoch, k4);
+        orc_rhs(tmp, t + h, mu_sun, n_pert, pert, epoch, inv_c2, k4);
         for (int k = 0; k < 6; ++k) y[k] += h / 6.0 * (k1[k] + 2.0 * k2[k] + 2.0 * k3[k] + k4[k]);
     }
 }

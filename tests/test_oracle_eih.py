@@ -1,0 +1,113 @@
+"""Pins of the oracle's Einstein-Infeld-Hoffmann dynamics (the relativistic restricted
+N-body model of Sec. 5.4.1), each against something the formula of orc_accel_eih does not
+share: the point-mass model (the limit 1/c^2 -> 0), the textbook first post-Newtonian
+acceleration of a test body about one resting mass (the Sun-only special case), the
+general-relativistic perihelion advance 6 pi mu / (c^2 a (1 - e^2)) per orbit, the time
+derivative of the perturber positions (their velocities), and a small-step Runge-Kutta
+integration of the same equations (the Picard-Chebyshev iteration with a velocity-
+dependent force).  The terms in the perturbers' velocities, accelerations and potentials
+have no closed-form check here (parity unpinned for those terms)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2301_03989_amd import workloads as W
+
+
+def _states(n, seed):
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(0.6, 1.4, n)
+    e = rng.uniform(0.0, 0.5, n)
+    inc = rng.uniform(0.0, 20.0, n) * W.DEG
+    raan, argp, M = (rng.uniform(0.0, 360.0, n) * W.DEG for _ in range(3))
+    return W.elements_to_states(a, e, inc, raan, argp, M)
+
+
+def test_zero_inv_c2_is_the_point_mass_model():
+    pert = W.planet_elements()
+    m = oracle.Model(1.0, pert, 0.0)
+    for i, y in enumerate(_states(20, 1)):
+        t = 0.37 * i
+        a0 = oracle.accel_t(y[:3], t, m)
+        a1 = oracle.accel_eih_t(y, t, m)
+        assert np.abs(a1 - a0).max() <= 1e-15 * np.abs(a0).max()
+
+
+@pytest.mark.parametrize("inv_c2", [1e-3, 1e-6])
+def test_sun_only_is_the_first_post_newtonian_test_body(inv_c2):
+    """One resting mass: a = -mu r/r^3 + mu/(c^2 r^3) [(4 mu/r - v^2) r + 4 (r.v) v]
+    (harmonic coordinates, beta = gamma = 1)."""
+    mu = 1.3
+    m = oracle.Model(mu, None, 0.0, inv_c2=inv_c2)
+    for y in _states(20, 2):
+        r, v = y[:3], y[3:]
+        rn = np.linalg.norm(r)
+        ref = -mu * r / rn**3 + inv_c2 * mu / rn**3 * ((4.0 * mu / rn - v @ v) * r + 4.0 * (r @ v) * v)
+        got = oracle.accel_eih_t(y, 0.0, m)
+        assert np.abs(got - ref).max() <= 1e-14 * np.abs(ref).max()
+        # and the correction itself, to nine digits (the subtraction of the Newtonian
+        # term leaves a few ulps of the whole acceleration)
+        corr = ref + mu * r / rn**3
+        assert np.abs((got + mu * r / rn**3) - corr).max() <= 1e-9 * np.abs(corr).max()
+
+
+def test_perihelion_advance():
+    """Sun only, a = 1, e = 0.3, 1/c^2 = 1e-4: over ten orbits the Laplace-Runge-Lenz
+    vector turns by 10 x 6 pi mu / (c^2 a (1 - e^2)) (first order in 1/c^2)."""
+    inv_c2, a, e = 1e-4, 1.0, 0.3
+    y0 = W.elements_to_states(np.array([a]), np.array([e]), np.zeros(1), np.zeros(1),
+                              np.zeros(1), np.zeros(1))[0]   # at perihelion
+    m = oracle.Model(1.0, None, 0.0, inv_c2=inv_c2)
+    orbits, per = 10, 16
+    P = 2 * np.pi * a**1.5
+    st, it = oracle.propagate(y0[None], 0.0, orbits * P, 64, orbits * per, 1e-13, m)
+    assert (it > 0).all()
+
+    def lrl(y):
+        r, v = y[:3], y[3:]
+        return np.cross(v, np.cross(r, v)) - r / np.linalg.norm(r)
+
+    A0, A1 = lrl(y0), lrl(st[0])
+    dw = np.arctan2(np.cross(A0, A1)[2], A0 @ A1)
+    expect = orbits * 6 * np.pi * inv_c2 / (a * (1 - e * e))
+    assert abs(dw / expect - 1.0) < 0.02, (dw, expect)
+
+
+def test_perturber_velocity_is_the_derivative_of_its_position():
+    for el in W.planet_elements():
+        for t in (0.0, 3.3, 17.0):
+            h = 1e-5
+            rp, _ = oracle.ephem_state(el, 0.0, t + h)
+            rm, _ = oracle.ephem_state(el, 0.0, t - h)
+            r, v = oracle.ephem_state(el, 0.0, t)
+            assert np.allclose(r, oracle.ephem(el, 0.0, t), rtol=0, atol=1e-15)
+            fd = (rp - rm) / (2 * h)
+            assert np.abs(fd - v).max() <= 1e-8 * np.linalg.norm(v)
+
+
+def test_picard_chebyshev_with_eih_matches_small_step_rk4():
+    """N-body EIH with an exaggerated 1/c^2 = 1e-4 (the relativistic terms near 1e-4 of
+    the acceleration): the oracle's iteration against 40000 RK4 steps over 100 days."""
+    w = W.nbody_venus(3, days=100.0, segments=4, nodes=64)
+    m = oracle.Model(1.0, w.pert, 0.0, inv_c2=1e-4)
+    g = w.groups[0]
+    st, it = oracle.propagate(w.ics, g.t0, g.tf, g.nodes, g.segments, 1e-13, m)
+    assert (it > 0).all()
+    for i in range(3):
+        ref = oracle.rk4(w.ics[i], g.t0, g.tf, 40000, m)
+        err = max(np.linalg.norm(st[i, :3] - ref[:3]) / np.linalg.norm(ref[:3]),
+                  np.linalg.norm(st[i, 3:] - ref[3:]) / np.linalg.norm(ref[3:]))
+        assert err < 1e-11, err
+    # the relativistic terms matter at this 1/c^2: the point-mass result is far away
+    st0, _ = oracle.propagate(w.ics, g.t0, g.tf, g.nodes, g.segments, 1e-13, oracle.Model(1.0, w.pert, 0.0))
+    assert np.linalg.norm(st0[0, :3] - st[0, :3]) / np.linalg.norm(st[0, :3]) > 1e-6
+
+
+def test_eih_refused_by_group_mode_and_adjoint():
+    w = W.nbody_venus(2, days=20.0, segments=1, nodes=16)
+    m = oracle.Model(1.0, w.pert, 0.0, inv_c2=1e-8)
+    g = w.groups[0]
+    with pytest.raises(ValueError):
+        oracle.propagate(w.ics, g.t0, g.tf, g.nodes, g.segments, 1e-12, m, conv=1)
+    with pytest.raises(ValueError):
+        oracle.adjoint(w.ics, g.t0, g.tf, g.nodes, g.segments, 1e-12, m, gbar_final=np.ones((2, 6)))
