@@ -67,14 +67,18 @@ def algorithmic_flops(w, iters):
     """Algorithmic FP64 work of the Picard iterations actually run: per IC, segment and
     iteration, the folded fit/integrate/evaluate product (6 columns x 2 N^2) plus the
     dynamics at N nodes (20 flops per body interaction, Sun + P perturbers, and 3 for
-    the precomputed indirect term)."""
+    the precomputed indirect term; with the Einstein-Infeld-Hoffmann model 109 per body,
+    19 for its term of the potential and 90 for its terms of the acceleration, and 8
+    for v^2 and the indirect term)."""
     P = w.pert.shape[0]
+    eih = getattr(w, "inv_c2", 0.0) > 0.0
     total = 0.0
     for g in w.groups:
         it = iters[g.ic_offset:g.ic_offset + g.n_ic, :g.segments]
         it = np.where(it > 0, it, 0).astype(np.float64)
         N = g.nodes
-        per_iter = 12.0 * N * N + (20.0 * (P + 1) + 3.0) * N
+        force = (109.0 * (P + 1) + 8.0) if eih else (20.0 * (P + 1) + 3.0)
+        per_iter = 12.0 * N * N + force * N
         total += per_iter * it.sum()
     return total
 
@@ -87,7 +91,7 @@ def rel_err(a, b):
 
 def oracle_states(w, idx):
     import oracle
-    model = oracle.Model(w.mu_sun, w.pert, w.epoch)
+    model = oracle.Model(w.mu_sun, w.pert, w.epoch, inv_c2=w.inv_c2)
     out = np.zeros((idx.size, 6))
     iters = np.zeros((idx.size, max(g.segments for g in w.groups)), dtype=np.int32)
     for g in w.groups:
@@ -130,7 +134,7 @@ def run_adjoint(args):
     ctx.set_timing(True)
     ics = torch.tensor(w.ics, dtype=torch.float64, device="cuda")
     groups = [pcprop.Group(g.ic_offset, g.n_ic, g.t0, g.tf, g.nodes, g.segments, g.tol) for g in w.groups]
-    model = pcprop.Model(w.mu_sun, w.pert, w.epoch)
+    model = pcprop.Model(w.mu_sun, w.pert, w.epoch, w.inv_c2)
     gbar_np = np.random.default_rng(7).standard_normal((n_ic, 6))
     gbar = torch.tensor(gbar_np, dtype=torch.float64, device="cuda")
 
@@ -165,7 +169,7 @@ def run_adjoint(args):
 
     g0 = w.groups[0]
     idx = np.unique(np.linspace(0, n_ic - 1, max(1, min(args.check_ics, 4))).astype(np.int64))
-    om = oracle.Model(w.mu_sun, w.pert, w.epoch)
+    om = oracle.Model(w.mu_sun, w.pert, w.epoch, inv_c2=w.inv_c2)
     ref = oracle.adjoint(w.ics[idx], g0.t0, g0.tf, g0.nodes, g0.segments, g0.tol, om, gbar_np[idx])
     gerr = np.linalg.norm(g_np[idx] - ref, axis=1) / np.linalg.norm(ref, axis=1)
     valid = bool(gerr.max() <= 1e-8 and st == 0 and f["status"] == 0)
@@ -279,7 +283,7 @@ def main():
     ctx.set_timing(True)
     ics = torch.tensor(w.ics, dtype=torch.float64, device="cuda")
     groups = [pcprop.Group(g.ic_offset, g.n_ic, g.t0, g.tf, g.nodes, g.segments, g.tol) for g in w.groups]
-    model = pcprop.Model(w.mu_sun, w.pert, w.epoch)
+    model = pcprop.Model(w.mu_sun, w.pert, w.epoch, w.inv_c2)
     init = "kepler" if w.init == 0 else "cold"
     precision = args.precision or ("fp32-fp64" if w.precision == 1 else "fp64")
     states = torch.empty((n_ic, 6), dtype=torch.float64, device="cuda")
@@ -336,7 +340,7 @@ def main():
               flush=True)
 
     plain = None
-    if args.plain_steps > 0 and precision == "fp64":
+    if args.plain_steps > 0 and precision == "fp64" and not w.inv_c2:
         # the same propagation with per-iteration kernels and a host loop (plain GPU path)
         plain_states = torch.empty_like(states)
         ctx.propagate_batched(ics, groups, model, init=init, path="plain", out=plain_states)

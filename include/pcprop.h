@@ -60,13 +60,23 @@ typedef void* pc_stream_t;        /* a hipStream_t */
  * a point-mass, heliocentric form (with the indirect term) of the restricted N-body
  * dynamics of Sec. 5.4.1, with perturber p on a two-body Keplerian orbit about the
  * central body (gravitational parameter 1).  Perturber positions are evaluated once
- * per node before the iterations, as Sec. 5.4.1 does for its ephemerides. */
+ * per node before the iterations, as Sec. 5.4.1 does for its ephemerides.
+ * inv_c2 > 0 selects the relativistic form Sec. 5.4.1 uses, the Einstein-Infeld-Hoffmann
+ * acceleration of the massless propagated body (PPN beta = gamma = 1, 1/c^2 = inv_c2 in
+ * the model's units): it depends on the body's velocity and on the positions, velocities,
+ * accelerations and potentials of the major bodies (the central body at rest at the
+ * origin, the perturbers on their orbits, differentiated in time), all evaluated once per
+ * node before the iterations; the Newtonian indirect term is kept, so inv_c2 = 0 is the
+ * point-mass model.  It runs on the fused path, in FP64, with the per-IC stopping rule,
+ * forward only, on job shapes of 16 or more columns (at most 128 nodes with tile_pairs
+ * 2048, 64 with 1024); other calls with inv_c2 > 0 return PC_EINVAL. */
 typedef struct {
     double mu_sun;        /* central body's gravitational parameter */
     int32_t n_pert;       /* 0 .. PC_MAX_PERT; 0 = two-body dynamics */
     const double* pert;   /* host [n_pert][7]: mu_p, a, e, inc, raan, argp, M0 (radians);
                              M0 is the mean anomaly at `epoch`; 0 <= e < 1, a > 0 */
     double epoch;
+    double inv_c2;        /* 1/c^2: 0 = point masses (default), > 0 = Einstein-Infeld-Hoffmann */
 } pc_model;
 
 enum { PC_INIT_KEPLER = 0, PC_INIT_COLD = 1 };   /* initial guess, Sec. 2.1 (warm / cold start) */

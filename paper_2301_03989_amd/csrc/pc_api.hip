@@ -210,6 +210,8 @@ int validate_model(pc_ctx* ctx, const pc_model* model)
         return set_error(ctx, PC_EINVAL, "n_pert must be in [0, %d]", PC_MAX_PERT);
     if (model->n_pert > 0 && !model->pert) return set_error(ctx, PC_EINVAL, "pert is NULL");
     if (!std::isfinite(model->epoch)) return set_error(ctx, PC_EINVAL, "epoch not finite");
+    if (!(model->inv_c2 >= 0.0) || !std::isfinite(model->inv_c2))
+        return set_error(ctx, PC_EINVAL, "inv_c2 must be >= 0 and finite");
     for (int p = 0; p < model->n_pert; ++p) {
         const double* el = model->pert + 7 * p;
         for (int k = 0; k < 7; ++k)
@@ -262,6 +264,7 @@ struct Plan {
     int list = 1;                  // job ICs in units of the job's columns
     // workspace offsets
     size_t off_counters = 0, off_params = 0, off_groups = 0, off_jobs = 0, off_bodies = 0, off_recs = 0, total = 0;
+    size_t off_recs_eih = 0;   // relativistic model: per-node states of the major bodies
     size_t staged = 0;   // bytes of [counters .. bodies] copied from the staging buffer
 };
 
@@ -318,6 +321,9 @@ int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, c
         const int NP = padded_nodes(G.nodes);
         if (NP * 8 > plan.pairs)
             return set_error(ctx, PC_EINVAL, "group %d: %d nodes need tile_pairs >= %d", gi, G.nodes, NP * 8);
+        if (model->inv_c2 > 0.0 && NP * 16 > plan.pairs)
+            return set_error(ctx, PC_EINVAL, "group %d: the relativistic model runs on job shapes of 16 or "
+                             "more columns (%d nodes need tile_pairs >= %d)", gi, G.nodes, NP * 16);
         spans.push_back({G.ic_offset, G.ic_offset + G.n_ic});
         plan.max_S = std::max(plan.max_S, G.segments);
         plan.max_N = std::max(plan.max_N, G.nodes);
@@ -425,6 +431,8 @@ int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, c
     plan.off_bodies = off;   off = align_up(off + std::max(1, P) * sizeof(PcBodyDev));
     plan.staged = off;
     plan.off_recs = off;     off = align_up(off + (size_t)plan.n_recs * (P + 1) * 4 * sizeof(double));
+    plan.off_recs_eih = off;
+    if (model->inv_c2 > 0.0) off = align_up(off + (size_t)plan.n_recs * (3 * (P + 1) + 1) * 4 * sizeof(double));
     plan.off_plain = off;
     if (plan.plain) {
         size_t mx = 0;
@@ -574,10 +582,13 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_
     if (o.conv != PC_CONV_PER_IC && o.conv != PC_CONV_GROUP_MAX) return set_error(ctx, PC_EINVAL, "bad conv");
     if (o.conv == PC_CONV_GROUP_MAX && o.path != PC_PATH_PLAIN)
         return set_error(ctx, PC_EINVAL, "group-max convergence runs on the plain path");
+    const bool eih = model->inv_c2 > 0.0;
+    if (eih && (o.path != PC_PATH_FUSED || o.precision != PC_FP64 || o.conv != PC_CONV_PER_IC))
+        return set_error(ctx, PC_EINVAL, "the relativistic model runs on the fused FP64 path, per-IC stopping rule");
     PC_HIP(ctx, hipSetDevice(ctx->device));
     Plan plan;
     rc = make_plan(ctx, n_ic, groups, n_groups, model, o, true, plan,
-                   o.path == PC_PATH_FUSED && o.precision == PC_FP64);
+                   o.path == PC_PATH_FUSED && o.precision == PC_FP64 && !eih);
     if (rc != PC_OK) return rc;
     if ((iters_out || bounds_out || nodes_out) && iters_stride < plan.max_S)
         return set_error(ctx, PC_EINVAL, "iters_stride %d < %d segments", iters_stride, plan.max_S);
@@ -605,6 +616,8 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_
     ep.n_pert = model->n_pert;
     ep.epoch = model->epoch;
     ep.recs = reinterpret_cast<double*>(ws + plan.off_recs);
+    ep.recs_eih = eih ? reinterpret_cast<double*>(ws + plan.off_recs_eih) : nullptr;
+    ep.mu_sun = model->mu_sun;
 
     PcParams pp{};
     pp.groups = ep.groups;
@@ -620,6 +633,8 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_
     pp.nodes_out = nodes_out;
     pp.recs = ep.recs;
     pp.mu_sun = model->mu_sun;
+    pp.recs_eih = ep.recs_eih;
+    pp.inv_c2 = eih ? model->inv_c2 : 0.0;
     pp.max_iter = o.max_iter;
     pp.fixed_iters = o.fixed_iters;
     pp.tol_mode = o.tol_mode;
@@ -686,6 +701,7 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_
         put(&o, sizeof(o));
         put(&model->mu_sun, sizeof(double));
         put(&model->epoch, sizeof(double));
+        put(&model->inv_c2, sizeof(double));
         put(&model->n_pert, sizeof(int32_t));
         if (model->n_pert > 0) put(model->pert, sizeof(double) * 7 * model->n_pert);
         put(&iters_stride, sizeof(iters_stride));
@@ -779,6 +795,8 @@ int pc_adjoint(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int32_t n_grou
     int rc = validate_model(ctx, model);
     if (rc != PC_OK) return rc;
     pc_opts o = opts ? *opts : defaults();
+    if (model->inv_c2 > 0.0)
+        return set_error(ctx, PC_EINVAL, "the adjoint is written for the point-mass model");
     if (o.path != PC_PATH_FUSED || o.precision != PC_FP64)
         return set_error(ctx, PC_EINVAL, "the adjoint re-solves segments on the fused FP64 path");
     if (o.conv != PC_CONV_PER_IC)
@@ -897,7 +915,7 @@ int pc_autotune(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_group* gr
         g.segments = 1;
     }
     std::vector<int> cands = {2048};
-    if (np_max * 8 <= 1024) cands.push_back(1024);
+    if (np_max * (model && model->inv_c2 > 0.0 ? 16 : 8) <= 1024) cands.push_back(1024);
     const bool was_timing = ctx->timing;
     int rc = pc_set_timing(ctx, 1);
     if (rc != PC_OK) return rc;
@@ -960,6 +978,8 @@ int pc_eval_force(pc_ctx* ctx, const double* r, const double* t, int64_t n, cons
     if (!ctx || !r || !t || !a_out || n < 1) return PC_EINVAL;
     int rc = validate_model(ctx, model);
     if (rc != PC_OK) return rc;
+    if (model->inv_c2 > 0.0)
+        return set_error(ctx, PC_EINVAL, "the force hook takes positions only (point-mass model)");
     PC_HIP(ctx, hipSetDevice(ctx->device));
     rc = ensure_staging(ctx, PC_MAX_PERT * sizeof(PcBodyDev));
     if (rc != PC_OK) return rc;

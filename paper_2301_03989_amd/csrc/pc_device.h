@@ -97,6 +97,22 @@ static __device__ void pc_body_position(const PcBodyDev& B, double dt_epoch, dou
     for (int k = 0; k < 3; ++k) r[k] = xp * B.P[k] + yp * B.Q[k];
 }
 
+// Position and velocity of a body on its Keplerian orbit (gravitational parameter 1):
+// the velocity is the time derivative of the position, dE/dt = n / (1 - e cos E).
+static __device__ void pc_body_state(const PcBodyDev& B, double dt_epoch, double r[3], double v[3])
+{
+    const double E = pc_ecc_anomaly(B.M0 + B.n * dt_epoch, B.e);
+    double sE, cE;
+    sincos(E, &sE, &cE);
+    const double Ed = B.n / (1.0 - B.e * cE);
+    const double xp = B.a * (cE - B.e), yp = B.b * sE;
+    const double xd = -B.a * sE * Ed, yd = B.b * cE * Ed;
+    for (int k = 0; k < 3; ++k) {
+        r[k] = xp * B.P[k] + yp * B.Q[k];
+        v[k] = xd * B.P[k] + yd * B.Q[k];
+    }
+}
+
 // Warm start (Sec. 2.1): propagate y0 by dt on its osculating ellipse, through the
 // Lagrange coefficients f, g, fdot, gdot written in the eccentric-anomaly change x:
 //   F(x) = x - (1 - r0/a) sin x + (r0.v0/sqrt(a)) (1 - cos x) - n dt = 0.
@@ -1039,6 +1055,109 @@ static __device__ __forceinline__ void pc_grad_lds_node32(const double (&x)[R], 
         const float mu = (float)smu[b];
 #pragma unroll
         for (int r = 0; r < R; ++r) add(r, (float)(x[r] - qx), (float)(y[r] - qy), (float)(z[r] - qz), mu);
+    }
+}
+
+// 1/sqrt(x) in full FP64 for finite x > 0: the hardware estimate y, e = 1 - x y^2, and
+// (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + O(e^3) (|e| near 2^-22, dropped terms below 2^-63).
+static __device__ __forceinline__ double pc_rsqrt_full(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x, y * y, 1.0);
+    return y * fma(e, fma(0.375, e, 0.5), 1.0);
+}
+
+// Records of the relativistic model per node: for every major body b = 0..P (0 = the
+// central body) three double4, (r_b, U_b), (v_b, mu_b), (a_b, 0), with U_b the potential
+// of the other major bodies at b, then the indirect term (ax, ay, az, 0).
+constexpr int pc_eih_rec(int P) { return 3 * (P + 1) + 1; }
+
+// Einstein-Infeld-Hoffmann acceleration of R massless points (x, y, z, vx, vy, vz) at one
+// node (PPN beta = gamma = 1, Sec. 5.4.1): with d = r - r_b, rho = |d| and the potential
+// Phi = sum_b mu_b / rho_b at the point,
+//   a = sum_b -mu_b d / rho^3 [1 - (4 Phi + U_b - v^2 - 2 v_b^2 + 4 v.v_b
+//                                   + 3/2 (d.v_b / rho)^2 + 1/2 d.a_b) / c^2]
+//     + sum_b mu_b / (c^2 rho^3) [d.(4 v - 3 v_b)] (v - v_b) + 7/2 sum_b mu_b a_b / (c^2 rho)
+// minus the Newtonian indirect term.  e: the node's records (global memory); the first
+// pass over the bodies forms Phi, the second the terms.
+template <int R>
+static __device__ __forceinline__ void pc_force_eih_node(const double (&x)[R], const double (&y)[R],
+                                                         const double (&z)[R], const double (&vx)[R],
+                                                         const double (&vy)[R], const double (&vz)[R],
+                                                         const double4* __restrict__ e, int P, double inv_c2,
+                                                         double (&ax)[R], double (&ay)[R], double (&az)[R])
+{
+    double phi[R], v2[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        phi[r] = 0.0;
+        v2[r] = vx[r] * vx[r] + vy[r] * vy[r] + vz[r] * vz[r];
+        ax[r] = ay[r] = az[r] = 0.0;
+    }
+    for (int b = 0; b <= P; ++b) {
+        const double4 q = e[3 * b];
+        const double mu = e[3 * b + 1].w;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double dx = x[r] - q.x, dy = y[r] - q.y, dz = z[r] - q.z;
+            phi[r] = fma(mu, pc_rsqrt_full(dx * dx + dy * dy + dz * dz), phi[r]);
+        }
+    }
+    for (int b = 0; b <= P; ++b) {
+        const double4 q = e[3 * b], w = e[3 * b + 1], g = e[3 * b + 2];
+        const double mu = w.w, wb2 = w.x * w.x + w.y * w.y + w.z * w.z;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double dx = x[r] - q.x, dy = y[r] - q.y, dz = z[r] - q.z;
+            const double i1 = pc_rsqrt_full(dx * dx + dy * dy + dz * dz);
+            const double i3 = i1 * i1 * i1;
+            const double vbv = vx[r] * w.x + vy[r] * w.y + vz[r] * w.z;
+            const double dvb = (dx * w.x + dy * w.y + dz * w.z) * i1;
+            const double dab = dx * g.x + dy * g.y + dz * g.z;
+            const double s = 4.0 * phi[r] + q.w - v2[r] - 2.0 * wb2 + 4.0 * vbv + 1.5 * dvb * dvb + 0.5 * dab;
+            const double brk = fma(-inv_c2, s, 1.0);
+            const double dw = dx * (4.0 * vx[r] - 3.0 * w.x) + dy * (4.0 * vy[r] - 3.0 * w.y) +
+                              dz * (4.0 * vz[r] - 3.0 * w.z);
+            const double k1 = -mu * i3 * brk;
+            const double k2 = inv_c2 * mu * i3 * dw;
+            const double k3 = 3.5 * inv_c2 * mu * i1;
+            ax[r] += k1 * dx + k2 * (vx[r] - w.x) + k3 * g.x;
+            ay[r] += k1 * dy + k2 * (vy[r] - w.y) + k3 * g.y;
+            az[r] += k1 * dz + k2 * (vz[r] - w.z) + k3 * g.z;
+        }
+    }
+    const double4 ind = e[3 * (P + 1)];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        ax[r] -= ind.x;
+        ay[r] -= ind.y;
+        az[r] -= ind.z;
+    }
+}
+
+// Publish F = (v, a) with the relativistic acceleration (WIDE shapes: a lane's points
+// share node j).  erec: the segment's records, pc_eih_rec(P) double4 per node.
+template <int PAIRS, int NP>
+static __device__ __forceinline__ void pc_publish_eih(double* sF, const double (&yc)[6][4], const PcLane& L,
+                                                      int N, int P, const double4* erec, double inv_c2)
+{
+    using Sh = PcShape<PAIRS, NP>;
+    static_assert(Sh::WIDE, "the relativistic model runs on WIDE job shapes");
+    constexpr int T = Sh::T, ROW = Sh::ROW;
+    const int j = pc_node(L, 0, 0);
+    if (j >= N) return;
+    double ax[4], ay[4], az[4];
+    pc_force_eih_node<4>(yc[0], yc[1], yc[2], yc[3], yc[4], yc[5], erec + (size_t)j * pc_eih_rec(P), P, inv_c2,
+                         ax, ay, az);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        double* f = sF + j * ROW + pc_fcol<PAIRS, NP>(j, pc_ic(L, r));
+        f[0 * T] = yc[3][r];
+        f[1 * T] = yc[4][r];
+        f[2 * T] = yc[5][r];
+        f[3 * T] = ax[r];
+        f[4 * T] = ay[r];
+        f[5 * T] = az[r];
     }
 }
 

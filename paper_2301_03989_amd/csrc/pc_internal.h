@@ -59,6 +59,9 @@ struct PcParams {
     double* bounds_out;         // [n_ic][iters_stride+1][6] or null
     double* nodes_out;          // [n_ic][iters_stride][nodes_stride][6] or null
     const double* recs;         // ephemeris records, (n_pert+1) double4 each
+    const double* recs_eih;     // Einstein-Infeld-Hoffmann records (3 (n_pert+1) + 1 double4
+                                // each, pc_ephem_kernel), or null for the point-mass model
+    double inv_c2;              // 1/c^2 of the relativistic model (0: point masses)
     double mu_sun;
     int32_t max_iter, fixed_iters, tol_mode, init;
     int32_t precision;          // 0 FP64; 1 FP32 sweeps, then FP64
@@ -94,6 +97,8 @@ struct PcEphemParams {
     int32_t n_pert;
     double epoch;
     double* recs;
+    double* recs_eih;           // or null
+    double mu_sun;
 };
 
 // Launchers (pc_kernels.hip).  All return a hipError_t as int.

@@ -47,6 +47,32 @@ __global__ void pc_ephem_kernel(const PcEphemParams p)
         iz += sq * r[2];
     }
     rec[P] = make_double4(ix, iy, iz, 0.0);
+    if (p.recs_eih) {
+        // relativistic model: states, accelerations and potentials of the major bodies
+        // (pc_eih_rec layout); body 0, the central body, rests at the origin
+        double4* er = reinterpret_cast<double4*>(p.recs_eih) + i * pc_eih_rec(P);
+        double rb[PC_MAX_PERT_DEV][3], vb[PC_MAX_PERT_DEV][3];
+        for (int b = 0; b < P; ++b) pc_body_state(p.bodies[b], t - p.epoch, rb[b], vb[b]);
+        double u0 = 0.0;
+        for (int b = 0; b < P; ++b) {
+            const double q = sqrt(rb[b][0] * rb[b][0] + rb[b][1] * rb[b][1] + rb[b][2] * rb[b][2]);
+            u0 += p.bodies[b].mu / q;
+            double u = p.mu_sun / q;   // potential of the central body and the other perturbers
+            for (int k = 0; k < P; ++k) {
+                if (k == b) continue;
+                const double dx = rb[b][0] - rb[k][0], dy = rb[b][1] - rb[k][1], dz = rb[b][2] - rb[k][2];
+                u += p.bodies[k].mu / sqrt(dx * dx + dy * dy + dz * dz);
+            }
+            const double iq3 = 1.0 / (q * q * q);   // Keplerian orbit about the central body
+            er[3 * (b + 1)] = make_double4(rb[b][0], rb[b][1], rb[b][2], u);
+            er[3 * (b + 1) + 1] = make_double4(vb[b][0], vb[b][1], vb[b][2], p.bodies[b].mu);
+            er[3 * (b + 1) + 2] = make_double4(-rb[b][0] * iq3, -rb[b][1] * iq3, -rb[b][2] * iq3, 0.0);
+        }
+        er[0] = make_double4(0.0, 0.0, 0.0, u0);
+        er[1] = make_double4(0.0, 0.0, 0.0, p.mu_sun);
+        er[2] = make_double4(0.0, 0.0, 0.0, 0.0);
+        er[3 * (P + 1)] = make_double4(ix, iy, iz, 0.0);
+    }
 }
 
 int pc_launch_ephem(const PcEphemParams& p, void* stream)
@@ -101,7 +127,7 @@ static __device__ __forceinline__ void pc_stage_records(const double4* grec, int
 // receives the iteration records.
 // MIXED: the job runs the FP32 -> FP64 precision schedule (compiled apart, so that FP64-only
 // jobs carry none of its registers).
-template <int PAIRS, int NP, bool MIXED = false>
+template <int PAIRS, int NP, bool MIXED = false, bool EIH = false>
 static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const PcGroupDev& g, int n, int64_t ic0,
                                                         int s, PcSmem<PAIRS>& sm, const PcLane& L, gconst_dp kp0,
                                                         double (&yc)[6][4], int32_t* iters_out, int& had_notconv,
@@ -182,8 +208,13 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
     int act[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) act[r] = sm.Active[pc_ic(L, r)];
+    // relativistic model: the segment's records of the major bodies
+    const double4* erec = nullptr;
+    if constexpr (EIH)
+        erec = reinterpret_cast<const double4*>(p.recs_eih) + (size_t)(g.rec_offset + (int64_t)s * N) * pc_eih_rec(P);
     if (act[0] | act[1] | act[2] | act[3]) {
-        if (MIXED && mode == 1) pc_publish<PAIRS, NP, MIXED>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
+        if constexpr (EIH) pc_publish_eih<PAIRS, NP>(sF, yc, L, N, P, erec, p.inv_c2);
+        else if (MIXED && mode == 1) pc_publish<PAIRS, NP, MIXED>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
         else pc_publish<PAIRS, NP>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
     }
     __syncthreads();
@@ -289,7 +320,8 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
                 for (int r = 0; r < 4; ++r) yc[b][r] = act[r] ? acc[b][r] : yc[b][r];
             }
             if (it < n_it) {
-                if (MIXED && next_mode == 1)
+                if constexpr (EIH) pc_publish_eih<PAIRS, NP>(sF, yc, L, N, P, erec, p.inv_c2);
+                else if (MIXED && next_mode == 1)
                     pc_publish<PAIRS, NP, MIXED>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
                 else pc_publish<PAIRS, NP>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
             }
@@ -303,7 +335,7 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
 
 // Not inlined: one register allocation per node count, so the work-queue kernel that
 // dispatches to all of them does not pay for the largest one everywhere.
-template <int PAIRS, int NP, bool MIXED>
+template <int PAIRS, int NP, bool MIXED, bool EIH = false>
 __device__ __attribute__((noinline)) void pc_job(const PcParams& p, const PcJobDev& job, const PcGroupDev& g)
 {
     PcSmem<PAIRS>& sm = pc_smem<PAIRS>();
@@ -340,7 +372,7 @@ __device__ __attribute__((noinline)) void pc_job(const PcParams& p, const PcJobD
             }
             if (sm.Dead[tid] && p.iters_out) p.iters_out[(size_t)ic * p.iters_stride + s] = -2;
         }
-        pc_segment_solve<PAIRS, NP, MIXED>(p, g, n, job.ic0, s, sm, L, kp0, yc, p.iters_out, had_notconv);
+        pc_segment_solve<PAIRS, NP, MIXED, EIH>(p, g, n, job.ic0, s, sm, L, kp0, yc, p.iters_out, had_notconv);
 
         // converged node states of the segment (optional output), chaining (Sec. 2.2)
 #pragma unroll
@@ -668,23 +700,33 @@ __global__ __launch_bounds__(PAIRS / 4, 2) void pc_fused_kernel(const PcParams* 
         const PcGroupDev g = p.groups[job.group];
         const bool list = job.n > g.T;   // more ICs than columns: refilled columns (FP64 only)
         const bool mixed = p.precision == 1;
+        const bool eih = p.inv_c2 != 0.0;   // relativistic model: FP64, one-block jobs, WIDE shapes
         switch (g.NP) {
         case 16:
-            if (list) pc_job_list<PAIRS, 16>(p, job, g);
+            if (eih) pc_job<PAIRS, 16, false, true>(p, job, g);
+            else if (list) pc_job_list<PAIRS, 16>(p, job, g);
             else if (mixed) pc_job<PAIRS, 16, true>(p, job, g);
             else pc_job<PAIRS, 16, false>(p, job, g);
             break;
         case 32:
-            if (list) pc_job_list<PAIRS, 32>(p, job, g);
+            if (eih) pc_job<PAIRS, 32, false, true>(p, job, g);
+            else if (list) pc_job_list<PAIRS, 32>(p, job, g);
             else if (mixed) pc_job<PAIRS, 32, true>(p, job, g);
             else pc_job<PAIRS, 32, false>(p, job, g);
             break;
         case 64:
-            if (list) pc_job_list<PAIRS, 64>(p, job, g);
+            if (eih) pc_job<PAIRS, 64, false, true>(p, job, g);
+            else if (list) pc_job_list<PAIRS, 64>(p, job, g);
             else if (mixed) pc_job<PAIRS, 64, true>(p, job, g);
             else pc_job<PAIRS, 64, false>(p, job, g);
             break;
         case 128:
+            if constexpr (PcShape<PAIRS, 128>::WIDE) {
+                if (eih) {
+                    pc_job<PAIRS, 128, false, true>(p, job, g);
+                    break;
+                }
+            }
             if (list) pc_job_list<PAIRS, 128>(p, job, g);
             else if (mixed) pc_job<PAIRS, 128, true>(p, job, g);
             else pc_job<PAIRS, 128, false>(p, job, g);

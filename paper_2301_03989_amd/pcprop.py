@@ -39,7 +39,7 @@ class PcError(RuntimeError):
 
 class _Model(ctypes.Structure):
     _fields_ = [("mu_sun", ctypes.c_double), ("n_pert", ctypes.c_int32),
-                ("pert", _dp), ("epoch", ctypes.c_double)]
+                ("pert", _dp), ("epoch", ctypes.c_double), ("inv_c2", ctypes.c_double)]
 
 
 class _Opts(ctypes.Structure):
@@ -115,10 +115,12 @@ def load_library(path: str = LIB_PATH):
 @dataclass
 class Model:
     """Point-mass force model: central body mu_sun plus perturbers on Keplerian orbits.
-    ``pert``: [P, 7] rows (mu_p, a, e, inc, raan, argp, M0), radians, M0 at ``epoch``."""
+    ``pert``: [P, 7] rows (mu_p, a, e, inc, raan, argp, M0), radians, M0 at ``epoch``.
+    ``inv_c2`` > 0: the Einstein-Infeld-Hoffmann dynamics with 1/c^2 = inv_c2."""
     mu_sun: float = 1.0
     pert: np.ndarray | None = None
     epoch: float = 0.0
+    inv_c2: float = 0.0
 
     def _c(self):
         pert = np.zeros((0, 7)) if self.pert is None else np.ascontiguousarray(self.pert, dtype=np.float64).reshape(-1, 7)
@@ -128,6 +130,7 @@ class Model:
         m.n_pert = int(pert.shape[0])
         m.pert = pert.ctypes.data_as(_dp) if pert.size else ctypes.cast(None, _dp)
         m.epoch = float(self.epoch)
+        m.inv_c2 = float(self.inv_c2)
         return m
 
 

@@ -102,6 +102,7 @@ class Workload:
     precision: int = 0                   # 0 FP64, 1 FP32 sweeps then FP64
     mu_sun: float = 1.0
     epoch: float = 0.0
+    inv_c2: float = 0.0                  # > 0: Einstein-Infeld-Hoffmann dynamics, 1/c^2
     meta: dict = field(default_factory=dict)
 
     @property
@@ -121,7 +122,7 @@ class Workload:
             groups.append(Group(off, int(sel.size), g.t0, g.tf, g.nodes, g.segments, g.tol))
             off += int(sel.size)
         return Workload(self.name + "-subset", np.concatenate(parts), groups, self.pert,
-                        self.init, self.precision, self.mu_sun, self.epoch, dict(self.meta))
+                        self.init, self.precision, self.mu_sun, self.epoch, self.inv_c2, dict(self.meta))
 
 
 # ---------------------------------------------------------------------------
@@ -200,10 +201,23 @@ def adjoint_ensemble(n_ic: int = 16384, seed: int = 105) -> Workload:
                        name="nbody-venus-16384-256d")
 
 
+# speed of light in AU per time unit (299792.458 km/s, 1 AU = 149597870.7 km)
+C_AU_TU = 299792.458 * TU_DAYS * 86400.0 / 149597870.7
+
+
+def relativistic(n_ic: int = 4096, seed: int = 102) -> Workload:
+    """The N-body Venus ensemble with the Einstein-Infeld-Hoffmann dynamics (the
+    paper's relativistic restricted problem, Sec. 5.4.1): 1/c^2 in AU/TU units."""
+    w = nbody_venus(n_ic, seed, name="nbody-venus-4096-eih")
+    w.inv_c2 = 1.0 / (C_AU_TU * C_AU_TU)
+    return w
+
+
 WORKLOADS = {
     "sun-only-kepler-64": sun_only_kepler,
     "nbody-venus-4096": nbody_venus,
     "uneven-batch-65536": uneven_batch,
     "nbody-venus-262144-fp32-fp64": mixed_precision,
     "nbody-venus-16384-256d": adjoint_ensemble,
+    "nbody-venus-4096-eih": relativistic,
 }

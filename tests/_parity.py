@@ -24,7 +24,7 @@ def oracle_run(w, idx=None, want_nodes=False, want_bounds=False, **kw):
     iters = np.zeros((idx.size, S_max), dtype=np.int32)
     nodes = np.zeros((idx.size, S_max, N_max, 6)) if want_nodes else None
     bounds = np.zeros((idx.size, S_max + 1, 6)) if want_bounds else None
-    model = oracle.Model(w.mu_sun, w.pert, w.epoch)
+    model = oracle.Model(w.mu_sun, w.pert, w.epoch, inv_c2=w.inv_c2)
     for g in w.groups:
         sel = np.nonzero((idx >= g.ic_offset) & (idx < g.ic_offset + g.n_ic))[0]
         if sel.size == 0:

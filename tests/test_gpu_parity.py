@@ -33,7 +33,7 @@ def _run(pc, w, idx=None, **kw):
     sub = w if idx is None else w.subset(idx)
     ics = torch.tensor(sub.ics, dtype=torch.float64, device="cuda")
     groups = [pcprop.Group(g.ic_offset, g.n_ic, g.t0, g.tf, g.nodes, g.segments, g.tol) for g in sub.groups]
-    model = pcprop.Model(sub.mu_sun, sub.pert, sub.epoch)
+    model = pcprop.Model(sub.mu_sun, sub.pert, sub.epoch, sub.inv_c2)
     kw.setdefault("init", "kepler" if sub.init == 0 else "cold")
     r = pc.propagate_batched(ics, groups, model, **kw)
     torch.cuda.synchronize()
