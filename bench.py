@@ -67,9 +67,10 @@ def algorithmic_flops(w, iters):
     """Algorithmic FP64 work of the Picard iterations actually run: per IC, segment and
     iteration, the folded fit/integrate/evaluate product (6 columns x 2 N^2) plus the
     dynamics at N nodes (20 flops per body interaction, Sun + P perturbers, and 3 for
-    the precomputed indirect term; with the Einstein-Infeld-Hoffmann model 109 per body,
-    19 for its term of the potential and 90 for its terms of the acceleration, and 8
-    for v^2 and the indirect term)."""
+    the precomputed indirect term; with the Einstein-Infeld-Hoffmann model 96 per body:
+    offset, distance powers, potential, the projections and products of its terms and
+    their accumulation, and 15 per point for v^2, the term in the potential and the
+    indirect term)."""
     P = w.pert.shape[0]
     eih = getattr(w, "inv_c2", 0.0) > 0.0
     total = 0.0
@@ -77,7 +78,7 @@ def algorithmic_flops(w, iters):
         it = iters[g.ic_offset:g.ic_offset + g.n_ic, :g.segments]
         it = np.where(it > 0, it, 0).astype(np.float64)
         N = g.nodes
-        force = (109.0 * (P + 1) + 8.0) if eih else (20.0 * (P + 1) + 3.0)
+        force = (96.0 * (P + 1) + 15.0) if eih else (20.0 * (P + 1) + 3.0)
         per_iter = 12.0 * N * N + force * N
         total += per_iter * it.sum()
     return total

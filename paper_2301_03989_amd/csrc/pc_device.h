@@ -1078,8 +1078,9 @@ constexpr int pc_eih_rec(int P) { return 3 * (P + 1) + 1; }
 //   a = sum_b -mu_b d / rho^3 [1 - (4 Phi + U_b - v^2 - 2 v_b^2 + 4 v.v_b
 //                                   + 3/2 (d.v_b / rho)^2 + 1/2 d.a_b) / c^2]
 //     + sum_b mu_b / (c^2 rho^3) [d.(4 v - 3 v_b)] (v - v_b) + 7/2 sum_b mu_b a_b / (c^2 rho)
-// minus the Newtonian indirect term.  e: the node's records (global memory); the first
-// pass over the bodies forms Phi, the second the terms.
+// minus the Newtonian indirect term.  The term in Phi is 4 Phi / c^2 sum_b mu_b d / rho^3,
+// so one pass over the bodies accumulates Phi, that sum and the rest, and the term is
+// added at the end (the same sum in another order).  e: the node's records.
 template <int R>
 static __device__ __forceinline__ void pc_force_eih_node(const double (&x)[R], const double (&y)[R],
                                                          const double (&z)[R], const double (&vx)[R],
@@ -1087,21 +1088,13 @@ static __device__ __forceinline__ void pc_force_eih_node(const double (&x)[R], c
                                                          const double4* __restrict__ e, int P, double inv_c2,
                                                          double (&ax)[R], double (&ay)[R], double (&az)[R])
 {
-    double phi[R], v2[R];
+    double phi[R], v2[R], nx[R], ny[R], nz[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         phi[r] = 0.0;
         v2[r] = vx[r] * vx[r] + vy[r] * vy[r] + vz[r] * vz[r];
         ax[r] = ay[r] = az[r] = 0.0;
-    }
-    for (int b = 0; b <= P; ++b) {
-        const double4 q = e[3 * b];
-        const double mu = e[3 * b + 1].w;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const double dx = x[r] - q.x, dy = y[r] - q.y, dz = z[r] - q.z;
-            phi[r] = fma(mu, pc_rsqrt_full(dx * dx + dy * dy + dz * dz), phi[r]);
-        }
+        nx[r] = ny[r] = nz[r] = 0.0;
     }
     for (int b = 0; b <= P; ++b) {
         const double4 q = e[3 * b], w = e[3 * b + 1], g = e[3 * b + 2];
@@ -1110,17 +1103,21 @@ static __device__ __forceinline__ void pc_force_eih_node(const double (&x)[R], c
         for (int r = 0; r < R; ++r) {
             const double dx = x[r] - q.x, dy = y[r] - q.y, dz = z[r] - q.z;
             const double i1 = pc_rsqrt_full(dx * dx + dy * dy + dz * dz);
-            const double i3 = i1 * i1 * i1;
+            const double m1 = mu * i1;
+            const double m3 = m1 * i1 * i1;          // mu / rho^3
+            phi[r] += m1;
+            nx[r] = fma(m3, dx, nx[r]);
+            ny[r] = fma(m3, dy, ny[r]);
+            nz[r] = fma(m3, dz, nz[r]);
             const double vbv = vx[r] * w.x + vy[r] * w.y + vz[r] * w.z;
             const double dvb = (dx * w.x + dy * w.y + dz * w.z) * i1;
             const double dab = dx * g.x + dy * g.y + dz * g.z;
-            const double s = 4.0 * phi[r] + q.w - v2[r] - 2.0 * wb2 + 4.0 * vbv + 1.5 * dvb * dvb + 0.5 * dab;
-            const double brk = fma(-inv_c2, s, 1.0);
+            const double s = q.w - v2[r] - 2.0 * wb2 + 4.0 * vbv + 1.5 * dvb * dvb + 0.5 * dab;
+            const double k1 = -m3 * fma(-inv_c2, s, 1.0);
             const double dw = dx * (4.0 * vx[r] - 3.0 * w.x) + dy * (4.0 * vy[r] - 3.0 * w.y) +
                               dz * (4.0 * vz[r] - 3.0 * w.z);
-            const double k1 = -mu * i3 * brk;
-            const double k2 = inv_c2 * mu * i3 * dw;
-            const double k3 = 3.5 * inv_c2 * mu * i1;
+            const double k2 = inv_c2 * m3 * dw;
+            const double k3 = 3.5 * inv_c2 * m1;
             ax[r] += k1 * dx + k2 * (vx[r] - w.x) + k3 * g.x;
             ay[r] += k1 * dy + k2 * (vy[r] - w.y) + k3 * g.y;
             az[r] += k1 * dz + k2 * (vz[r] - w.z) + k3 * g.z;
@@ -1129,9 +1126,10 @@ static __device__ __forceinline__ void pc_force_eih_node(const double (&x)[R], c
     const double4 ind = e[3 * (P + 1)];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        ax[r] -= ind.x;
-        ay[r] -= ind.y;
-        az[r] -= ind.z;
+        const double f = 4.0 * inv_c2 * phi[r];
+        ax[r] = fma(f, nx[r], ax[r]) - ind.x;
+        ay[r] = fma(f, ny[r], ay[r]) - ind.y;
+        az[r] = fma(f, nz[r], az[r]) - ind.z;
     }
 }
 
