@@ -1069,7 +1069,9 @@ static __device__ __forceinline__ double pc_rsqrt_full(double x)
 
 // Records of the relativistic model per node: for every major body b = 0..P (0 = the
 // central body) three double4, (r_b, U_b), (v_b, mu_b), (a_b, 0), with U_b the potential
-// of the other major bodies at b, then the indirect term (ax, ay, az, 0).
+// of the other major bodies at b, then the indirect term (ax, ay, az, 0).  A segment's
+// records are stored slot-major, [slot][node], so that the lanes of a wave, which hold
+// consecutive nodes, read consecutive double4.
 constexpr int pc_eih_rec(int P) { return 3 * (P + 1) + 1; }
 
 // Einstein-Infeld-Hoffmann acceleration of R massless points (x, y, z, vx, vy, vz) at one
@@ -1080,13 +1082,15 @@ constexpr int pc_eih_rec(int P) { return 3 * (P + 1) + 1; }
 //     + sum_b mu_b / (c^2 rho^3) [d.(4 v - 3 v_b)] (v - v_b) + 7/2 sum_b mu_b a_b / (c^2 rho)
 // minus the Newtonian indirect term.  The term in Phi is 4 Phi / c^2 sum_b mu_b d / rho^3,
 // so one pass over the bodies accumulates Phi, that sum and the rest, and the term is
-// added at the end (the same sum in another order).  e: the node's records.
+// added at the end (the same sum in another order).  e: the node's first record, the
+// next slot `ns` double4 further.
 template <int R>
 static __device__ __forceinline__ void pc_force_eih_node(const double (&x)[R], const double (&y)[R],
                                                          const double (&z)[R], const double (&vx)[R],
                                                          const double (&vy)[R], const double (&vz)[R],
-                                                         const double4* __restrict__ e, int P, double inv_c2,
-                                                         double (&ax)[R], double (&ay)[R], double (&az)[R])
+                                                         const double4* __restrict__ e, int ns, int P,
+                                                         double inv_c2, double (&ax)[R], double (&ay)[R],
+                                                         double (&az)[R])
 {
     double phi[R], v2[R], nx[R], ny[R], nz[R];
 #pragma unroll
@@ -1097,7 +1101,7 @@ static __device__ __forceinline__ void pc_force_eih_node(const double (&x)[R], c
         nx[r] = ny[r] = nz[r] = 0.0;
     }
     for (int b = 0; b <= P; ++b) {
-        const double4 q = e[3 * b], w = e[3 * b + 1], g = e[3 * b + 2];
+        const double4 q = e[(3 * b) * ns], w = e[(3 * b + 1) * ns], g = e[(3 * b + 2) * ns];
         const double mu = w.w, wb2 = w.x * w.x + w.y * w.y + w.z * w.z;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -1123,7 +1127,7 @@ static __device__ __forceinline__ void pc_force_eih_node(const double (&x)[R], c
             az[r] += k1 * dz + k2 * (vz[r] - w.z) + k3 * g.z;
         }
     }
-    const double4 ind = e[3 * (P + 1)];
+    const double4 ind = e[(3 * (P + 1)) * ns];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const double f = 4.0 * inv_c2 * phi[r];
@@ -1134,7 +1138,7 @@ static __device__ __forceinline__ void pc_force_eih_node(const double (&x)[R], c
 }
 
 // Publish F = (v, a) with the relativistic acceleration (WIDE shapes: a lane's points
-// share node j).  erec: the segment's records, pc_eih_rec(P) double4 per node.
+// share node j).  erec: the segment's records, pc_eih_rec(P) slots of N double4.
 template <int PAIRS, int NP>
 static __device__ __forceinline__ void pc_publish_eih(double* sF, const double (&yc)[6][4], const PcLane& L,
                                                       int N, int P, const double4* erec, double inv_c2)
@@ -1145,8 +1149,7 @@ static __device__ __forceinline__ void pc_publish_eih(double* sF, const double (
     const int j = pc_node(L, 0, 0);
     if (j >= N) return;
     double ax[4], ay[4], az[4];
-    pc_force_eih_node<4>(yc[0], yc[1], yc[2], yc[3], yc[4], yc[5], erec + (size_t)j * pc_eih_rec(P), P, inv_c2,
-                         ax, ay, az);
+    pc_force_eih_node<4>(yc[0], yc[1], yc[2], yc[3], yc[4], yc[5], erec + j, N, P, inv_c2, ax, ay, az);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         double* f = sF + j * ROW + pc_fcol<PAIRS, NP>(j, pc_ic(L, r));

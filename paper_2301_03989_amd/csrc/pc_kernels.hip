@@ -49,8 +49,11 @@ __global__ void pc_ephem_kernel(const PcEphemParams p)
     rec[P] = make_double4(ix, iy, iz, 0.0);
     if (p.recs_eih) {
         // relativistic model: states, accelerations and potentials of the major bodies
-        // (pc_eih_rec layout); body 0, the central body, rests at the origin
-        double4* er = reinterpret_cast<double4*>(p.recs_eih) + i * pc_eih_rec(P);
+        // (pc_eih_rec slots, slot-major within the segment); body 0, the central body,
+        // rests at the origin
+        const int N = G.N;
+        double4* base = reinterpret_cast<double4*>(p.recs_eih) + (i - j) * pc_eih_rec(P) + j;
+        auto er = [&](int slot) -> double4& { return base[(size_t)slot * N]; };
         double rb[PC_MAX_PERT_DEV][3], vb[PC_MAX_PERT_DEV][3];
         for (int b = 0; b < P; ++b) pc_body_state(p.bodies[b], t - p.epoch, rb[b], vb[b]);
         double u0 = 0.0;
@@ -64,14 +67,14 @@ __global__ void pc_ephem_kernel(const PcEphemParams p)
                 u += p.bodies[k].mu / sqrt(dx * dx + dy * dy + dz * dz);
             }
             const double iq3 = 1.0 / (q * q * q);   // Keplerian orbit about the central body
-            er[3 * (b + 1)] = make_double4(rb[b][0], rb[b][1], rb[b][2], u);
-            er[3 * (b + 1) + 1] = make_double4(vb[b][0], vb[b][1], vb[b][2], p.bodies[b].mu);
-            er[3 * (b + 1) + 2] = make_double4(-rb[b][0] * iq3, -rb[b][1] * iq3, -rb[b][2] * iq3, 0.0);
+            er(3 * (b + 1)) = make_double4(rb[b][0], rb[b][1], rb[b][2], u);
+            er(3 * (b + 1) + 1) = make_double4(vb[b][0], vb[b][1], vb[b][2], p.bodies[b].mu);
+            er(3 * (b + 1) + 2) = make_double4(-rb[b][0] * iq3, -rb[b][1] * iq3, -rb[b][2] * iq3, 0.0);
         }
-        er[0] = make_double4(0.0, 0.0, 0.0, u0);
-        er[1] = make_double4(0.0, 0.0, 0.0, p.mu_sun);
-        er[2] = make_double4(0.0, 0.0, 0.0, 0.0);
-        er[3 * (P + 1)] = make_double4(ix, iy, iz, 0.0);
+        er(0) = make_double4(0.0, 0.0, 0.0, u0);
+        er(1) = make_double4(0.0, 0.0, 0.0, p.mu_sun);
+        er(2) = make_double4(0.0, 0.0, 0.0, 0.0);
+        er(3 * (P + 1)) = make_double4(ix, iy, iz, 0.0);
     }
 }
 
