@@ -104,3 +104,27 @@ def test_eih_refused_where_not_supported(pc):
         pc.adjoint(torch.zeros((8, g.segments + 1, 6), dtype=torch.float64, device="cuda") + ics[:, None, :],
                    torch.ones((8, 6), dtype=torch.float64, device="cuda"), groups,
                    pcprop.Model(1.0, w.pert, 0.0, 1e-8))
+
+
+def test_eih_graph_replay_and_model_switch(pc):
+    """Captured and replayed calls equal eager ones; changing only 1/c^2 between calls of
+    the same shapes and pointers re-captures (the model is part of the graph's key)."""
+    from paper_2301_03989_amd import pcprop
+    w = _venus(24, 64, 1e-4)
+    g = w.groups[0]
+    ics = torch.tensor(w.ics, device="cuda")
+    groups = [pcprop.Group(0, w.n_ic, g.t0, g.tf, g.nodes, g.segments, g.tol)]
+    m1 = pcprop.Model(1.0, w.pert, 0.0, 1e-4)
+    m0 = pcprop.Model(1.0, w.pert, 0.0, 0.0)
+    ref1 = pc.propagate_batched(ics, groups, m1)["states"].clone()
+    ref0 = pc.propagate_batched(ics, groups, m0)["states"].clone()
+    assert not torch.equal(ref1, ref0)
+    out = torch.empty_like(ref1)
+    for rep in range(3):
+        r = pc.propagate_batched(ics, groups, m1, graph=True, out=out)
+        assert r["status"] == 0 and torch.equal(r["states"], ref1), rep
+        r = pc.propagate_batched(ics, groups, m0, graph=True, out=out)
+        assert r["status"] == 0 and torch.equal(r["states"], ref0), rep
+        x = torch.randn(1 << 20, device="cuda", dtype=torch.float64)
+        assert torch.isfinite(x.sum())
+        torch.cuda.synchronize()
