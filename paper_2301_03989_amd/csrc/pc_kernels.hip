@@ -703,22 +703,25 @@ __global__ __launch_bounds__(PAIRS / 4, 2) void pc_fused_kernel(const PcParams* 
         const PcGroupDev g = p.groups[job.group];
         const bool list = job.n > g.T;   // more ICs than columns: refilled columns (FP64 only)
         const bool mixed = p.precision == 1;
-        const bool eih = p.inv_c2 != 0.0;   // relativistic model: FP64, one-block jobs, WIDE shapes
+        const bool eih = p.inv_c2 != 0.0;   // relativistic model: one-block jobs, WIDE shapes
         switch (g.NP) {
         case 16:
-            if (eih) pc_job<PAIRS, 16, false, true>(p, job, g);
+            if (eih && mixed) pc_job<PAIRS, 16, true, true>(p, job, g);
+            else if (eih) pc_job<PAIRS, 16, false, true>(p, job, g);
             else if (list) pc_job_list<PAIRS, 16>(p, job, g);
             else if (mixed) pc_job<PAIRS, 16, true>(p, job, g);
             else pc_job<PAIRS, 16, false>(p, job, g);
             break;
         case 32:
-            if (eih) pc_job<PAIRS, 32, false, true>(p, job, g);
+            if (eih && mixed) pc_job<PAIRS, 32, true, true>(p, job, g);
+            else if (eih) pc_job<PAIRS, 32, false, true>(p, job, g);
             else if (list) pc_job_list<PAIRS, 32>(p, job, g);
             else if (mixed) pc_job<PAIRS, 32, true>(p, job, g);
             else pc_job<PAIRS, 32, false>(p, job, g);
             break;
         case 64:
-            if (eih) pc_job<PAIRS, 64, false, true>(p, job, g);
+            if (eih && mixed) pc_job<PAIRS, 64, true, true>(p, job, g);
+            else if (eih) pc_job<PAIRS, 64, false, true>(p, job, g);
             else if (list) pc_job_list<PAIRS, 64>(p, job, g);
             else if (mixed) pc_job<PAIRS, 64, true>(p, job, g);
             else pc_job<PAIRS, 64, false>(p, job, g);
@@ -726,7 +729,8 @@ __global__ __launch_bounds__(PAIRS / 4, 2) void pc_fused_kernel(const PcParams* 
         case 128:
             if constexpr (PcShape<PAIRS, 128>::WIDE) {
                 if (eih) {
-                    pc_job<PAIRS, 128, false, true>(p, job, g);
+                    if (mixed) pc_job<PAIRS, 128, true, true>(p, job, g);
+                    else pc_job<PAIRS, 128, false, true>(p, job, g);
                     break;
                 }
             }

@@ -81,10 +81,27 @@ def test_eih_node_states_backward_and_sun_only(pc):
     assert rel_err(_run(pc, ws)["states"], oracle_run(ws)["states"]).max() < 1e-11
 
 
+@pytest.mark.parametrize("nodes,inv_c2,extra", [(64, 1.0 / W.C_AU_TU**2, 3), (128, 1.0 / W.C_AU_TU**2, 3),
+                                                (100, 1e-6, 3), (64, 1e-4, 15)])
+def test_eih_precision_schedule(pc, nodes, inv_c2, extra):
+    """FP32 -> FP64 schedule with the relativistic model: the FP64 sweeps evaluate it, the
+    increment sweeps linearise with the point-mass gradient; every IC still stops on an
+    FP64 sweep, near the FP64 iteration's accuracy.  The gradient misses the O(1/c^2)
+    terms, so an exaggerated 1/c^2 (1e-4) leaves the increments' limit farther off and
+    more FP64 sweeps follow (a CPU prototype of the schedule needed the same)."""
+    w = _venus(40, nodes, inv_c2)
+    r = _run(pc, w, precision="fp32-fp64")
+    o = oracle_run(w)
+    assert r["status"] == 0
+    assert rel_err(r["states"], o["states"]).max() < 1e-11
+    d = r["iters"] - o["iters"]
+    assert d.min() >= -1 and d.max() <= extra, (d.min(), d.max())
+
+
 def test_eih_refused_where_not_supported(pc):
     from paper_2301_03989_amd import pcprop
     w = _venus(8, 64, 1e-8)
-    for kw in (dict(path="plain"), dict(precision="fp32-fp64"), dict(path="plain", conv="group")):
+    for kw in (dict(path="plain"), dict(path="plain", conv="group")):
         with pytest.raises(pcprop.PcError):
             _run(pc, w, **kw)
     with pytest.raises(pcprop.PcError):      # 256 nodes: 8-column jobs
