@@ -68,8 +68,7 @@ typedef void* pc_stream_t;        /* a hipStream_t */
  * origin, the perturbers on their orbits, differentiated in time), all evaluated once per
  * node before the iterations; the Newtonian indirect term is kept, so inv_c2 = 0 is the
  * point-mass model.  It runs on the fused path with the per-IC stopping rule, forward
- * only, on job shapes of 16 or more columns (at most 128 nodes with tile_pairs 2048, 64
- * with 1024); other calls with inv_c2 > 0 return PC_EINVAL.  Under PC_FP32_THEN_FP64 the
+ * only; other calls with inv_c2 > 0 return PC_EINVAL.  Under PC_FP32_THEN_FP64 the
  * FP64 sweeps evaluate this acceleration and the increment sweeps linearise with the
  * point-mass gravity gradient (the relativistic terms change it by O(1/c^2), which only
  * perturbs the linearisation the FP64 sweeps correct). */

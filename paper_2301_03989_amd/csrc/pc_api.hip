@@ -321,9 +321,6 @@ int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, c
         const int NP = padded_nodes(G.nodes);
         if (NP * 8 > plan.pairs)
             return set_error(ctx, PC_EINVAL, "group %d: %d nodes need tile_pairs >= %d", gi, G.nodes, NP * 8);
-        if (model->inv_c2 > 0.0 && NP * 16 > plan.pairs)
-            return set_error(ctx, PC_EINVAL, "group %d: the relativistic model runs on job shapes of 16 or "
-                             "more columns (%d nodes need tile_pairs >= %d)", gi, G.nodes, NP * 16);
         spans.push_back({G.ic_offset, G.ic_offset + G.n_ic});
         plan.max_S = std::max(plan.max_S, G.segments);
         plan.max_N = std::max(plan.max_N, G.nodes);
@@ -915,7 +912,7 @@ int pc_autotune(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_group* gr
         g.segments = 1;
     }
     std::vector<int> cands = {2048};
-    if (np_max * (model && model->inv_c2 > 0.0 ? 16 : 8) <= 1024) cands.push_back(1024);
+    if (np_max * 8 <= 1024) cands.push_back(1024);
     const bool was_timing = ctx->timing;
     int rc = pc_set_timing(ctx, 1);
     if (rc != PC_OK) return rc;

@@ -1082,16 +1082,18 @@ constexpr int pc_eih_rec(int P) { return 3 * (P + 1) + 1; }
 //     + sum_b mu_b / (c^2 rho^3) [d.(4 v - 3 v_b)] (v - v_b) + 7/2 sum_b mu_b a_b / (c^2 rho)
 // minus the Newtonian indirect term.  The term in Phi is 4 Phi / c^2 sum_b mu_b d / rho^3,
 // so one pass over the bodies accumulates Phi, that sum and the rest, and the term is
-// added at the end (the same sum in another order).  e: the node's first record, the
-// next slot `ns` double4 further.
-template <int R>
-static __device__ __forceinline__ void pc_force_eih_node(const double (&x)[R], const double (&y)[R],
-                                                         const double (&z)[R], const double (&vx)[R],
-                                                         const double (&vy)[R], const double (&vz)[R],
-                                                         const double4* __restrict__ e, int ns, int P,
-                                                         double inv_c2, double (&ax)[R], double (&ay)[R],
-                                                         double (&az)[R])
+// added at the end (the same sum in another order).  e: the segment's records, slot k of
+// node j at e[k ns + j]; point r sits at node jr[r] (ONE_NODE: all at jr[0], one load
+// per record for the R points).
+template <int R, bool ONE_NODE>
+static __device__ __forceinline__ void pc_force_eih(const double (&x)[R], const double (&y)[R],
+                                                    const double (&z)[R], const double (&vx)[R],
+                                                    const double (&vy)[R], const double (&vz)[R],
+                                                    const double4* __restrict__ e, const int (&jr)[R], int ns,
+                                                    int P, double inv_c2, double (&ax)[R], double (&ay)[R],
+                                                    double (&az)[R])
 {
+    auto rec = [&](int k, int r) -> double4 { return e[(size_t)k * ns + jr[ONE_NODE ? 0 : r]]; };
     double phi[R], v2[R], nx[R], ny[R], nz[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -1101,10 +1103,15 @@ static __device__ __forceinline__ void pc_force_eih_node(const double (&x)[R], c
         nx[r] = ny[r] = nz[r] = 0.0;
     }
     for (int b = 0; b <= P; ++b) {
-        const double4 q = e[(3 * b) * ns], w = e[(3 * b + 1) * ns], g = e[(3 * b + 2) * ns];
-        const double mu = w.w, wb2 = w.x * w.x + w.y * w.y + w.z * w.z;
+        double4 q = rec(3 * b, 0), w = rec(3 * b + 1, 0), g = rec(3 * b + 2, 0);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
+            if (!ONE_NODE && r > 0) {
+                q = rec(3 * b, r);
+                w = rec(3 * b + 1, r);
+                g = rec(3 * b + 2, r);
+            }
+            const double mu = w.w, wb2 = w.x * w.x + w.y * w.y + w.z * w.z;
             const double dx = x[r] - q.x, dy = y[r] - q.y, dz = z[r] - q.z;
             const double i1 = pc_rsqrt_full(dx * dx + dy * dy + dz * dz);
             const double m1 = mu * i1;
@@ -1127,9 +1134,9 @@ static __device__ __forceinline__ void pc_force_eih_node(const double (&x)[R], c
             az[r] += k1 * dz + k2 * (vz[r] - w.z) + k3 * g.z;
         }
     }
-    const double4 ind = e[(3 * (P + 1)) * ns];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
+        const double4 ind = rec(3 * (P + 1), r);
         const double f = 4.0 * inv_c2 * phi[r];
         ax[r] = fma(f, nx[r], ax[r]) - ind.x;
         ay[r] = fma(f, ny[r], ay[r]) - ind.y;
@@ -1137,28 +1144,79 @@ static __device__ __forceinline__ void pc_force_eih_node(const double (&x)[R], c
     }
 }
 
-// Publish F = (v, a) with the relativistic acceleration (WIDE shapes: a lane's points
-// share node j).  erec: the segment's records, pc_eih_rec(P) slots of N double4.
+// Publish F = (v, a) with the relativistic acceleration.  erec: the segment's records,
+// pc_eih_rec(P) slots of N double4.  WIDE shapes: a lane's four points share node j.
+// 8-column shapes: as in pc_publish, lane pairs (l, l ^ 8) hold the points of one IC (the
+// low lane x, z, vy, the high lane y, vx, vz) and each lane evaluates one strip (hd = hi),
+// taking the three components it lacks from its partner.
 template <int PAIRS, int NP>
 static __device__ __forceinline__ void pc_publish_eih(double* sF, const double (&yc)[6][4], const PcLane& L,
                                                       int N, int P, const double4* erec, double inv_c2)
 {
     using Sh = PcShape<PAIRS, NP>;
-    static_assert(Sh::WIDE, "the relativistic model runs on WIDE job shapes");
     constexpr int T = Sh::T, ROW = Sh::ROW;
-    const int j = pc_node(L, 0, 0);
-    if (j >= N) return;
-    double ax[4], ay[4], az[4];
-    pc_force_eih_node<4>(yc[0], yc[1], yc[2], yc[3], yc[4], yc[5], erec + j, N, P, inv_c2, ax, ay, az);
+    if constexpr (Sh::WIDE) {
+        const int j = pc_node(L, 0, 0);
+        if (j >= N) return;
+        const int jr[4] = {j, j, j, j};
+        double ax[4], ay[4], az[4];
+        pc_force_eih<4, true>(yc[0], yc[1], yc[2], yc[3], yc[4], yc[5], erec, jr, N, P, inv_c2, ax, ay, az);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        double* f = sF + j * ROW + pc_fcol<PAIRS, NP>(j, pc_ic(L, r));
-        f[0 * T] = yc[3][r];
-        f[1 * T] = yc[4][r];
-        f[2 * T] = yc[5][r];
-        f[3 * T] = ax[r];
-        f[4 * T] = ay[r];
-        f[5 * T] = az[r];
+        for (int r = 0; r < 4; ++r) {
+            double* f = sF + j * ROW + pc_fcol<PAIRS, NP>(j, pc_ic(L, r));
+            f[0 * T] = yc[3][r];
+            f[1 * T] = yc[4][r];
+            f[2 * T] = yc[5][r];
+            f[3 * T] = ax[r];
+            f[4 * T] = ay[r];
+            f[5 * T] = az[r];
+        }
+    } else {
+        const int hi = L.hi;
+        const int my_m = pc_ic(L, 0);
+        double xs[4], ys[4], zs[4], us[4], vs[4], ws[4], ax[4], ay[4], az[4];
+        int jr[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const double e1 = pc_dpp<0x128>(hi ? yc[0][r] : yc[3][r]);   // lane ^ 8
+            const double e2 = pc_dpp<0x128>(hi ? yc[1][r] : yc[4][r]);
+            const double e3 = pc_dpp<0x128>(hi ? yc[2][r] : yc[5][r]);
+            xs[r] = hi ? e1 : yc[0][r];
+            ys[r] = hi ? yc[3][r] : e1;
+            zs[r] = hi ? e2 : yc[1][r];
+            us[r] = hi ? yc[4][r] : e2;
+            vs[r] = hi ? e3 : yc[2][r];
+            ws[r] = hi ? yc[5][r] : e3;
+            const int j = pc_node(L, hi, r);
+            jr[r] = j < N ? j : N - 1;
+        }
+        pc_force_eih<4, false>(xs, ys, zs, us, vs, ws, erec, jr, N, P, inv_c2, ax, ay, az);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = pc_node(L, hi, r);
+            if (j < N) {
+                double* f = sF + j * ROW + my_m;
+                f[3 * T] = ax[r];
+                f[4 * T] = ay[r];
+                f[5 * T] = az[r];
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = pc_node(L, h, r);
+                if (j < N) {
+                    double* f = sF + j * ROW + my_m;
+                    if (hi) {
+                        f[0 * T] = yc[3 * h + 1][r];   // vx (comp 3)
+                        f[2 * T] = yc[3 * h + 2][r];   // vz (comp 5)
+                    } else {
+                        f[1 * T] = yc[3 * h + 2][r];   // vy (comp 4)
+                    }
+                }
+            }
+        }
     }
 }
 

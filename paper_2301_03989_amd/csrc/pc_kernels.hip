@@ -703,7 +703,7 @@ __global__ __launch_bounds__(PAIRS / 4, 2) void pc_fused_kernel(const PcParams* 
         const PcGroupDev g = p.groups[job.group];
         const bool list = job.n > g.T;   // more ICs than columns: refilled columns (FP64 only)
         const bool mixed = p.precision == 1;
-        const bool eih = p.inv_c2 != 0.0;   // relativistic model: one-block jobs, WIDE shapes
+        const bool eih = p.inv_c2 != 0.0;   // relativistic model: one-block jobs
         switch (g.NP) {
         case 16:
             if (eih && mixed) pc_job<PAIRS, 16, true, true>(p, job, g);
@@ -727,20 +727,17 @@ __global__ __launch_bounds__(PAIRS / 4, 2) void pc_fused_kernel(const PcParams* 
             else pc_job<PAIRS, 64, false>(p, job, g);
             break;
         case 128:
-            if constexpr (PcShape<PAIRS, 128>::WIDE) {
-                if (eih) {
-                    if (mixed) pc_job<PAIRS, 128, true, true>(p, job, g);
-                    else pc_job<PAIRS, 128, false, true>(p, job, g);
-                    break;
-                }
-            }
-            if (list) pc_job_list<PAIRS, 128>(p, job, g);
+            if (eih && mixed) pc_job<PAIRS, 128, true, true>(p, job, g);
+            else if (eih) pc_job<PAIRS, 128, false, true>(p, job, g);
+            else if (list) pc_job_list<PAIRS, 128>(p, job, g);
             else if (mixed) pc_job<PAIRS, 128, true>(p, job, g);
             else pc_job<PAIRS, 128, false>(p, job, g);
             break;
         case 256:
             if constexpr (PAIRS >= 2048) {
-                if (list) pc_job_list<PAIRS, 256>(p, job, g);
+                if (eih && mixed) pc_job<PAIRS, 256, true, true>(p, job, g);
+                else if (eih) pc_job<PAIRS, 256, false, true>(p, job, g);
+                else if (list) pc_job_list<PAIRS, 256>(p, job, g);
                 else if (mixed) pc_job<PAIRS, 256, true>(p, job, g);
                 else pc_job<PAIRS, 256, false>(p, job, g);
             }

@@ -1,6 +1,7 @@
 """The Einstein-Infeld-Hoffmann dynamics on the HIP path against the oracle's (the
-relativistic restricted problem of Sec. 5.4.1): every job shape it runs on, physical and
-exaggerated 1/c^2, backward propagation, node states, and the calls it refuses."""
+relativistic restricted problem of Sec. 5.4.1): every job shape (transposed and 8-column),
+physical and exaggerated 1/c^2, backward propagation, node states, the precision schedule,
+graph replays, and the calls it refuses."""
 import numpy as np
 import pytest
 import torch
@@ -38,7 +39,7 @@ def _venus(n, nodes, inv_c2, days=112.5, segments=2, seed=106):
 
 
 @pytest.mark.parametrize("nodes,tile", [(16, 2048), (48, 2048), (64, 2048), (100, 2048), (128, 2048),
-                                        (64, 1024), (40, 1024)])
+                                        (200, 2048), (256, 2048), (64, 1024), (40, 1024), (128, 1024)])
 @pytest.mark.parametrize("inv_c2", [1e-4, 1.0 / W.C_AU_TU**2])
 def test_eih_matches_oracle(pc, nodes, tile, inv_c2):
     w = _venus(40, nodes, inv_c2)
@@ -82,7 +83,7 @@ def test_eih_node_states_backward_and_sun_only(pc):
 
 
 @pytest.mark.parametrize("nodes,inv_c2,extra", [(64, 1.0 / W.C_AU_TU**2, 3), (128, 1.0 / W.C_AU_TU**2, 3),
-                                                (100, 1e-6, 3), (64, 1e-4, 15)])
+                                                (100, 1e-6, 3), (64, 1e-4, 15), (256, 1.0 / W.C_AU_TU**2, 12)])
 def test_eih_precision_schedule(pc, nodes, inv_c2, extra):
     """FP32 -> FP64 schedule with the relativistic model: the FP64 sweeps evaluate it, the
     increment sweeps linearise with the point-mass gradient; every IC still stops on an
@@ -104,10 +105,6 @@ def test_eih_refused_where_not_supported(pc):
     for kw in (dict(path="plain"), dict(path="plain", conv="group")):
         with pytest.raises(pcprop.PcError):
             _run(pc, w, **kw)
-    with pytest.raises(pcprop.PcError):      # 256 nodes: 8-column jobs
-        _run(pc, _venus(8, 256, 1e-8))
-    with pytest.raises(pcprop.PcError):      # 128 nodes in the 1024-pair shape: 8 columns
-        _run(pc, _venus(8, 128, 1e-8), tile_pairs=1024)
     with pytest.raises(pcprop.PcError):
         _run(pc, _venus(8, 64, -1e-8))
     with pytest.raises(pcprop.PcError):
