@@ -341,7 +341,7 @@ def main():
               flush=True)
 
     plain = None
-    if args.plain_steps > 0 and precision == "fp64" and not w.inv_c2:
+    if args.plain_steps > 0 and precision == "fp64":
         # the same propagation with per-iteration kernels and a host loop (plain GPU path)
         plain_states = torch.empty_like(states)
         ctx.propagate_batched(ics, groups, model, init=init, path="plain", out=plain_states)

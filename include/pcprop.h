@@ -67,8 +67,8 @@ typedef void* pc_stream_t;        /* a hipStream_t */
  * accelerations and potentials of the major bodies (the central body at rest at the
  * origin, the perturbers on their orbits, differentiated in time), all evaluated once per
  * node before the iterations; the Newtonian indirect term is kept, so inv_c2 = 0 is the
- * point-mass model.  It runs on the fused path with the per-IC stopping rule, forward
- * only; other calls with inv_c2 > 0 return PC_EINVAL.  Under PC_FP32_THEN_FP64 the
+ * point-mass model.  It runs with the per-IC stopping rule, forward only (fused and plain
+ * paths); other calls with inv_c2 > 0 return PC_EINVAL.  Under PC_FP32_THEN_FP64 the
  * FP64 sweeps evaluate this acceleration and the increment sweeps linearise with the
  * point-mass gravity gradient (the relativistic terms change it by O(1/c^2), which only
  * perturbs the linearisation the FP64 sweeps correct). */

@@ -580,8 +580,8 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_
     if (o.conv == PC_CONV_GROUP_MAX && o.path != PC_PATH_PLAIN)
         return set_error(ctx, PC_EINVAL, "group-max convergence runs on the plain path");
     const bool eih = model->inv_c2 > 0.0;
-    if (eih && (o.path != PC_PATH_FUSED || o.conv != PC_CONV_PER_IC))
-        return set_error(ctx, PC_EINVAL, "the relativistic model runs on the fused path, per-IC stopping rule");
+    if (eih && o.conv != PC_CONV_PER_IC)
+        return set_error(ctx, PC_EINVAL, "the relativistic model runs with the per-IC stopping rule");
     PC_HIP(ctx, hipSetDevice(ctx->device));
     Plan plan;
     rc = make_plan(ctx, n_ic, groups, n_groups, model, o, true, plan,

@@ -85,9 +85,23 @@ __global__ __launch_bounds__(kPlainForceBlock) void pc_plain_force(PcPlainArgs a
     const int64_t m = (int64_t)job * a.T + pr % a.T;
     if (j >= a.N || !a.active[m]) return;
     const int P = a.p.n_pert;
+    double* Yj = a.Y + (size_t)j * 9 * a.Mpad + m;
+    if (a.p.inv_c2 != 0.0) {
+        // relativistic model: the segment's records of the major bodies (slot-major)
+        const double4* erec = reinterpret_cast<const double4*>(a.p.recs_eih) +
+                              (size_t)(a.g->rec_offset + (int64_t)s * a.N) * pc_eih_rec(P);
+        const double x[1] = {Yj[0]}, y[1] = {Yj[a.Mpad]}, z[1] = {Yj[2 * a.Mpad]};
+        const double vx[1] = {Yj[3 * a.Mpad]}, vy[1] = {Yj[4 * a.Mpad]}, vz[1] = {Yj[5 * a.Mpad]};
+        const int jr[1] = {j};
+        double ax[1], ay[1], az[1];
+        pc_force_eih<1, true>(x, y, z, vx, vy, vz, erec, jr, a.N, P, a.p.inv_c2, ax, ay, az);
+        Yj[6 * a.Mpad] = ax[0];
+        Yj[7 * a.Mpad] = ay[0];
+        Yj[8 * a.Mpad] = az[0];
+        return;
+    }
     const double4* rec = reinterpret_cast<const double4*>(a.p.recs) +
                          (size_t)(a.g->rec_offset + (int64_t)s * a.N + j) * (P + 1);
-    double* Yj = a.Y + (size_t)j * 9 * a.Mpad + m;
     double ax, ay, az;
     pc_accel(Yj[0], Yj[a.Mpad], Yj[2 * a.Mpad], rec, P, a.p.mu_sun, ax, ay, az);
     Yj[6 * a.Mpad] = ax;

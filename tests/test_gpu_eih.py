@@ -99,10 +99,24 @@ def test_eih_precision_schedule(pc, nodes, inv_c2, extra):
     assert d.min() >= -1 and d.max() <= extra, (d.min(), d.max())
 
 
+@pytest.mark.parametrize("nodes", [64, 128, 256])
+def test_eih_plain_path(pc, nodes):
+    """The per-iteration (plain) path with the relativistic force kernel: against the
+    oracle, and against the fused path."""
+    w = _venus(40, nodes, 1.0 / W.C_AU_TU**2)
+    r = _run(pc, w, path="plain")
+    f = _run(pc, w)
+    o = oracle_run(w)
+    assert r["status"] == 0
+    assert rel_err(r["states"], o["states"]).max() < 1e-11
+    assert rel_err(r["states"], f["states"]).max() < 1e-13
+    assert np.abs(r["iters"] - o["iters"]).max() <= 1
+
+
 def test_eih_refused_where_not_supported(pc):
     from paper_2301_03989_amd import pcprop
     w = _venus(8, 64, 1e-8)
-    for kw in (dict(path="plain"), dict(path="plain", conv="group")):
+    for kw in (dict(path="plain", conv="group"),):
         with pytest.raises(pcprop.PcError):
             _run(pc, w, **kw)
     with pytest.raises(pcprop.PcError):
