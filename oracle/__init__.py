@@ -74,6 +74,8 @@ def _load():
         lib.orc_accel_eih_t.restype = None
         lib.orc_accel_eih_t.argtypes = [_dp, ctypes.c_double, ctypes.c_double, ctypes.c_int, _dp,
                                         ctypes.c_double, ctypes.c_double, _dp]
+        lib.orc_accel_eih_bodies.restype = None
+        lib.orc_accel_eih_bodies.argtypes = [_dp, ctypes.c_int, _dp, _dp, _dp, _dp, _dp, ctypes.c_double, _dp]
         lib.orc_ephem_state.restype = None
         lib.orc_ephem_state.argtypes = [_dp, ctypes.c_double, ctypes.c_double, _dp, _dp]
         _lib = lib
@@ -247,6 +249,20 @@ def accel_eih_t(y, t, model):
     a = np.zeros(3)
     lib.orc_accel_eih_t(_ptr(y), float(t), model.mu_sun, model.n_pert, model._pert_ptr(),
                         model.epoch, model.inv_c2, _ptr(a))
+    return a
+
+
+def accel_eih_bodies(y, rb, vb, ab, mub, Ub, inv_c2):
+    """The Einstein-Infeld-Hoffmann sums for a massless body at y (r, v) and major bodies
+    with positions rb, velocities vb, accelerations ab [nb, 3], parameters mub and
+    potentials Ub [nb] (no indirect term)."""
+    lib = _load()
+    y = _f64(y).reshape(6)
+    rb, vb, ab = (_f64(x).reshape(-1, 3) for x in (rb, vb, ab))
+    mub, Ub = _f64(mub).reshape(-1), _f64(Ub).reshape(-1)
+    a = np.zeros(3)
+    lib.orc_accel_eih_bodies(_ptr(y), rb.shape[0], _ptr(rb), _ptr(vb), _ptr(ab), _ptr(mub), _ptr(Ub),
+                             float(inv_c2), _ptr(a))
     return a
 
 

@@ -197,36 +197,15 @@ void orc_accel(const double r[3], int n_pert, const double* rp, const double* mu
  *                                   + 3/2 (d.v_b / rho)^2 + 1/2 d.a_b) / c^2]
  *     + sum_b mu_b / (c^2 rho^3) [d.(4 v - 3 v_b)] (v - v_b)
  *     + 7/2 sum_b mu_b a_b / (c^2 rho)
- * plus the Newtonian indirect term -sum_p mu_p rp/|rp|^3 of the heliocentric frame. */
-void orc_accel_eih(const double y[6], int n_pert, const double* rp, const double* vp, const double* mup,
-                   double mu_sun, double inv_c2, double acc[3])
+ * plus the Newtonian indirect term -sum_p mu_p rp/|rp|^3 of the heliocentric frame
+ * (orc_accel_eih).  orc_accel_eih_bodies evaluates the sums for any nb major bodies with
+ * positions rb, velocities vb, accelerations ab, parameters mub and potentials Ub. */
+void orc_accel_eih_bodies(const double y[6], int nb, const double* rb, const double* vb, const double* ab,
+                          const double* mub, const double* Ub, double inv_c2, double acc[3])
 {
     const double* r = y;
     const double* v = y + 3;
     double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-    /* major-body states */
-    double rb[3 * 65], vb[3 * 65], ab[3 * 65], mub[65], Ub[65];
-    int nb = n_pert + 1;
-    for (int k = 0; k < 3; ++k) rb[k] = vb[k] = ab[k] = 0.0;
-    mub[0] = mu_sun;
-    for (int p = 0; p < n_pert; ++p) {
-        const double* q = rp + 3 * p;
-        double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
-        for (int k = 0; k < 3; ++k) {
-            rb[3 * (p + 1) + k] = q[k];
-            vb[3 * (p + 1) + k] = vp[3 * p + k];
-            ab[3 * (p + 1) + k] = -q[k] / (qn * qn * qn);
-        }
-        mub[p + 1] = mup[p];
-    }
-    for (int b = 0; b < nb; ++b) {
-        Ub[b] = 0.0;
-        for (int k = 0; k < nb; ++k) {
-            if (k == b) continue;
-            double dx = rb[3 * b] - rb[3 * k], dy = rb[3 * b + 1] - rb[3 * k + 1], dz = rb[3 * b + 2] - rb[3 * k + 2];
-            Ub[b] += mub[k] / sqrt(dx * dx + dy * dy + dz * dz);
-        }
-    }
     double phi = 0.0;
     for (int b = 0; b < nb; ++b) {
         double dx = r[0] - rb[3 * b], dy = r[1] - rb[3 * b + 1], dz = r[2] - rb[3 * b + 2];
@@ -253,6 +232,35 @@ void orc_accel_eih(const double y[6], int n_pert, const double* rp, const double
             acc[k] += 3.5 * inv_c2 * mub[b] * gb[k] / rho;
         }
     }
+}
+
+void orc_accel_eih(const double y[6], int n_pert, const double* rp, const double* vp, const double* mup,
+                   double mu_sun, double inv_c2, double acc[3])
+{
+    /* major-body states: the Sun at rest at the origin, the perturbers on their orbits */
+    double rb[3 * 65], vb[3 * 65], ab[3 * 65], mub[65], Ub[65];
+    int nb = n_pert + 1;
+    for (int k = 0; k < 3; ++k) rb[k] = vb[k] = ab[k] = 0.0;
+    mub[0] = mu_sun;
+    for (int p = 0; p < n_pert; ++p) {
+        const double* q = rp + 3 * p;
+        double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+        for (int k = 0; k < 3; ++k) {
+            rb[3 * (p + 1) + k] = q[k];
+            vb[3 * (p + 1) + k] = vp[3 * p + k];
+            ab[3 * (p + 1) + k] = -q[k] / (qn * qn * qn);
+        }
+        mub[p + 1] = mup[p];
+    }
+    for (int b = 0; b < nb; ++b) {
+        Ub[b] = 0.0;
+        for (int k = 0; k < nb; ++k) {
+            if (k == b) continue;
+            double dx = rb[3 * b] - rb[3 * k], dy = rb[3 * b + 1] - rb[3 * k + 1], dz = rb[3 * b + 2] - rb[3 * k + 2];
+            Ub[b] += mub[k] / sqrt(dx * dx + dy * dy + dz * dz);
+        }
+    }
+    orc_accel_eih_bodies(y, nb, rb, vb, ab, mub, Ub, inv_c2, acc);
     for (int p = 0; p < n_pert; ++p) {   /* indirect term */
         const double* q = rp + 3 * p;
         double q2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];

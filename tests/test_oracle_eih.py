@@ -5,8 +5,10 @@ acceleration of a test body about one resting mass (the Sun-only special case), 
 general-relativistic perihelion advance 6 pi mu / (c^2 a (1 - e^2)) per orbit, the time
 derivative of the perturber positions (their velocities), and a small-step Runge-Kutta
 integration of the same equations (the Picard-Chebyshev iteration with a velocity-
-dependent force).  The terms in the perturbers' velocities, accelerations and potentials
-have no closed-form check here (parity unpinned for those terms)."""
+dependent force), and the Lorentz boost of a resting mass (a mass in uniform motion, which
+checks the terms in the perturbers' velocities).  The terms in the perturbers'
+accelerations and potentials have no closed-form check here (parity unpinned for those
+terms)."""
 import numpy as np
 import pytest
 
@@ -71,6 +73,34 @@ def test_perihelion_advance():
     dw = np.arctan2(np.cross(A0, A1)[2], A0 @ A1)
     expect = orbits * 6 * np.pi * inv_c2 / (a * (1 - e * e))
     assert abs(dw / expect - 1.0) < 0.02, (dw, expect)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_uniformly_moving_mass_is_the_boosted_resting_one(seed):
+    """A mass in uniform motion (velocity V, no acceleration) and a body moving with it at
+    offset d: in their common rest frame the body feels the resting-mass acceleration
+    -mu d'/|d'|^3 (1 - 4 mu/(c^2 |d'|)) (pinned above), with d' the offset lengthened by
+    gamma along V; the Lorentz transformation of an acceleration for a body at rest in the
+    moving frame divides its component along V by gamma^3 and the rest by gamma^2.  The
+    relativistic sums must agree to first order in 1/c^2 (this checks their terms in the
+    mass's velocity)."""
+    rng = np.random.default_rng(seed)
+    inv_c2, mu = 1e-6, 0.8
+    V = rng.uniform(-1.5, 1.5, 3)
+    rb = rng.uniform(-1.0, 1.0, 3)
+    d = rng.uniform(-1.0, 1.0, 3)
+    d *= rng.uniform(0.3, 1.2) / np.linalg.norm(d)
+    y = np.concatenate([rb + d, V])
+    got = oracle.accel_eih_bodies(y, rb[None], V[None], np.zeros((1, 3)), [mu], [0.0], inv_c2)
+    gamma = 1.0 / np.sqrt(1.0 - inv_c2 * (V @ V))
+    u = V / np.linalg.norm(V)
+    dp = d + (gamma - 1.0) * (d @ u) * u                    # offset in the rest frame
+    rp = np.linalg.norm(dp)
+    ap = -mu * dp / rp**3 * (1.0 - 4.0 * mu * inv_c2 / rp)
+    ref = (ap @ u) * u / gamma**3 + (ap - (ap @ u) * u) / gamma**2
+    newton = -mu * d / np.linalg.norm(d)**3
+    # the first-order correction itself (about 1e-6 of the acceleration) to 1e-5 of it
+    assert np.abs((got - newton) - (ref - newton)).max() <= 1e-5 * np.abs(ref - newton).max()
 
 
 def test_perturber_velocity_is_the_derivative_of_its_position():
