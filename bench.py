@@ -237,6 +237,8 @@ def main():
     ap.add_argument("--check-ics", type=int, default=64, help="ICs checked against the oracle")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="wall-time budget of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--plain-streams", type=int, default=1,
+                    help="streams of the plain path's outer level (one host thread each)")
     ap.add_argument("--plain-steps", type=int, default=3,
                     help="steps of the per-iteration (plain) path timed for the speedup; 0 skips")
     ap.add_argument("--adjoint-nodes", action="store_true",
@@ -344,21 +346,23 @@ def main():
     if args.plain_steps > 0 and precision == "fp64":
         # the same propagation with per-iteration kernels and a host loop (plain GPU path)
         plain_states = torch.empty_like(states)
-        ctx.propagate_batched(ics, groups, model, init=init, path="plain", out=plain_states)
+        pkw = dict(init=init, path="plain", out=plain_states, streams=args.plain_streams)
+        ctx.propagate_batched(ics, groups, model, **pkw)
         torch.cuda.synchronize()
         p0 = torch.cuda.Event(enable_timing=True)
         p1 = torch.cuda.Event(enable_timing=True)
         p0.record()
         for _ in range(args.plain_steps):
-            rp = ctx.propagate_batched(ics, groups, model, init=init, path="plain", out=plain_states)
+            rp = ctx.propagate_batched(ics, groups, model, **pkw)
         p1.record()
         torch.cuda.synchronize()
         plain_ms = p0.elapsed_time(p1) / args.plain_steps
-        plain = {"path": "plain", "ms_per_step": round(plain_ms, 4), "steps": args.plain_steps,
+        plain = {"path": "plain", "streams": args.plain_streams, "ms_per_step": round(plain_ms, 4),
+                 "steps": args.plain_steps,
                  "speedup_batched_vs_plain": round(plain_ms / ms_per_step, 3),
                  "max_rel_diff_vs_batched": float(rel_err(rp["states"].cpu().numpy(), gpu_states).max())}
-        print(f"bench: plain path {plain_ms:.3f} ms/step, batched speedup {plain_ms / ms_per_step:.2f}x",
-              flush=True)
+        print(f"bench: plain path ({args.plain_streams} stream(s)) {plain_ms:.3f} ms/step, "
+              f"batched speedup {plain_ms / ms_per_step:.2f}x", flush=True)
 
     # accuracy gate against the FP64 oracle on an evenly spaced sample
     idx = np.unique(np.linspace(0, n_ic - 1, min(args.check_ics, n_ic)).astype(np.int64))

@@ -52,6 +52,7 @@ extern "C" {
 
 #define PC_MAX_NODES  256  /* N per segment: 3 .. 256 */
 #define PC_MAX_PERT   16   /* perturbing bodies */
+#define PC_MAX_STREAMS 16  /* streams of the plain path's outer level (pc_opts.streams) */
 
 typedef struct pc_ctx pc_ctx;     /* owns the cached operators per node count */
 typedef void* pc_stream_t;        /* a hipStream_t */
@@ -136,6 +137,10 @@ typedef struct {
                              workgroup slots within 25 % of the fewest block-times), 1 = off,
                              2, 4 or 8 = that many blocks.  Results do not depend on it. */
     int32_t conv;         /* PC_CONV_PER_IC (default) or PC_CONV_GROUP_MAX */
+    int32_t streams;      /* plain path: groups run on this many streams at once, each driven
+                             by its own host thread and read-back (the outer-level streams of
+                             Sec. 5.4; 1..PC_MAX_STREAMS, default 1); the workspace holds one
+                             plain-path state per stream.  Results do not depend on it. */
 } pc_opts;
 
 /* One outer-level group of the two-level augmentation (Sec. 3.2): ICs

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <map>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "pcprop.h"
@@ -40,6 +41,13 @@ struct pc_ctx {
     size_t staging_bytes = 0;
     PcBodyDev* d_bodies = nullptr;  // device copy of the perturber table (test hooks)
     int32_t* pinned_count = nullptr;   // per-iteration read-back of the plain path
+    // plain path on several streams (pc_opts.streams): one stream, read-back slot and
+    // completion event per stream, created on first use
+    hipStream_t pl_stream[PC_MAX_STREAMS] = {};
+    hipEvent_t pl_done[PC_MAX_STREAMS] = {};
+    hipEvent_t pl_start = nullptr;
+    int32_t* pl_count = nullptr;       // pinned, 16 ints per stream
+    int pl_streams = 0;
     int tile_table[5] = {0, 0, 0, 0, 0}; // tuned job shape per padded node count 16..256 (0: default)
     hipStream_t cap_stream = nullptr;  // stream used to capture HIP graphs
     hipGraph_t graph = nullptr;
@@ -201,6 +209,21 @@ int ensure_staging(pc_ctx* ctx, size_t bytes)
     return PC_OK;
 }
 
+// Streams, completion events and pinned read-back slots of the multi-stream plain path
+// (default priority; created once, kept by the context).
+int ensure_plain_streams(pc_ctx* ctx, int ns)
+{
+    if (!ctx->pl_start) PC_HIP(ctx, hipEventCreateWithFlags(&ctx->pl_start, hipEventDisableTiming));
+    if (!ctx->pl_count) PC_HIP(ctx, hipHostMalloc(&ctx->pl_count, PC_MAX_STREAMS * 16 * sizeof(int32_t),
+                                                  hipHostMallocDefault));
+    for (; ctx->pl_streams < ns; ++ctx->pl_streams) {
+        const int t = ctx->pl_streams;
+        PC_HIP(ctx, hipStreamCreateWithFlags(&ctx->pl_stream[t], hipStreamNonBlocking));
+        PC_HIP(ctx, hipEventCreateWithFlags(&ctx->pl_done[t], hipEventDisableTiming));
+    }
+    return PC_OK;
+}
+
 int validate_model(pc_ctx* ctx, const pc_model* model)
 {
     if (!model) return set_error(ctx, PC_EINVAL, "model is NULL");
@@ -265,6 +288,8 @@ struct Plan {
     // workspace offsets
     size_t off_counters = 0, off_params = 0, off_groups = 0, off_jobs = 0, off_bodies = 0, off_recs = 0, total = 0;
     size_t off_recs_eih = 0;   // relativistic model: per-node states of the major bodies
+    size_t plain_stride = 0;   // bytes of one plain-path state (one per stream)
+    int plain_streams = 1;
     size_t staged = 0;   // bytes of [counters .. bodies] copied from the staging buffer
 };
 
@@ -438,7 +463,9 @@ int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, c
             const int nj = plan.group_job_begin[gi + 1] - plan.group_job_begin[gi];
             mx = std::max(mx, pc_plain_bytes(d.NP, nj, d.T));
         }
-        off = align_up(off + mx);
+        plan.plain_streams = std::min(std::max(1, (int)o.streams), n_groups);
+        plan.plain_stride = align_up(mx);
+        off = align_up(off + plan.plain_stride * plan.plain_streams);
     }
     plan.total = off;
     return PC_OK;
@@ -470,6 +497,7 @@ void pc_default_opts(pc_opts* o)
     o->max_fp32 = 0;
     o->job_list = 0;
     o->conv = PC_CONV_PER_IC;
+    o->streams = 1;
 }
 
 int pc_version(void) { return PC_VERSION; }
@@ -528,6 +556,12 @@ void pc_ctx_destroy(pc_ctx* ctx)
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     if (ctx->d_bodies) (void)hipFree(ctx->d_bodies);
     if (ctx->pinned_count) (void)hipHostFree(ctx->pinned_count);
+    for (int t = 0; t < ctx->pl_streams; ++t) {
+        if (ctx->pl_stream[t]) (void)hipStreamDestroy(ctx->pl_stream[t]);
+        if (ctx->pl_done[t]) (void)hipEventDestroy(ctx->pl_done[t]);
+    }
+    if (ctx->pl_start) (void)hipEventDestroy(ctx->pl_start);
+    if (ctx->pl_count) (void)hipHostFree(ctx->pl_count);
     if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
     if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
@@ -579,6 +613,9 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_
     if (o.conv != PC_CONV_PER_IC && o.conv != PC_CONV_GROUP_MAX) return set_error(ctx, PC_EINVAL, "bad conv");
     if (o.conv == PC_CONV_GROUP_MAX && o.path != PC_PATH_PLAIN)
         return set_error(ctx, PC_EINVAL, "group-max convergence runs on the plain path");
+    if (o.streams < 0 || o.streams > PC_MAX_STREAMS || (o.streams > 1 && o.path != PC_PATH_PLAIN))
+        return set_error(ctx, PC_EINVAL, "streams must be 1..%d, and above 1 only on the plain path",
+                         PC_MAX_STREAMS);
     const bool eih = model->inv_c2 > 0.0;
     if (eih && o.conv != PC_CONV_PER_IC)
         return set_error(ctx, PC_EINVAL, "the relativistic model runs with the per-IC stopping rule");
@@ -668,7 +705,7 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_
         PC_HIP(ctx, (hipError_t)pc_launch_ephem(ep, hs));
         if (ctx->timing) PC_HIP(ctx, hipEventRecord(ctx->ev0, hs));
         // one group at a time, kernels per iteration, host loop (the structure of Sec. 5.4)
-        for (int gi = 0; gi < n_groups; ++gi) {
+        auto plain_args = [&](int gi) {
             PcPlainArgs a{};
             a.p = pp;
             a.g = pp.groups + gi;
@@ -680,7 +717,36 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_
             a.T = plan.groups[gi].T;
             a.S = plan.groups[gi].S;
             a.t2 = plan.groups[gi].tol * plan.groups[gi].tol;
-            PC_HIP(ctx, (hipError_t)pc_run_plain(a, ws + plan.off_plain, ctx->pinned_count, stream));
+            return a;
+        };
+        const int ns = plan.plain_streams;
+        if (ns <= 1) {
+            for (int gi = 0; gi < n_groups; ++gi)
+                PC_HIP(ctx, (hipError_t)pc_run_plain(plain_args(gi), ws + plan.off_plain, ctx->pinned_count, stream));
+        } else {
+            // the outer level on ns streams: group gi on stream gi % ns, each stream driven by
+            // its own host thread (its per-iteration read-back waits on that stream only);
+            // the streams start after the work queued so far and the caller's stream waits
+            // for all of them
+            rc = ensure_plain_streams(ctx, ns);
+            if (rc != PC_OK) return rc;
+            PC_HIP(ctx, hipEventRecord(ctx->pl_start, hs));
+            std::vector<hipError_t> errs(ns, hipSuccess);
+            std::vector<std::thread> workers;
+            for (int t = 0; t < ns; ++t) {
+                workers.emplace_back([&, t] {
+                    hipError_t e = hipSetDevice(ctx->device);
+                    if (e == hipSuccess) e = hipStreamWaitEvent(ctx->pl_stream[t], ctx->pl_start, 0);
+                    for (int gi = t; gi < n_groups && e == hipSuccess; gi += ns)
+                        e = (hipError_t)pc_run_plain(plain_args(gi), ws + plan.off_plain + t * plan.plain_stride,
+                                                     ctx->pl_count + 16 * t, ctx->pl_stream[t]);
+                    if (e == hipSuccess) e = hipEventRecord(ctx->pl_done[t], ctx->pl_stream[t]);
+                    errs[t] = e;
+                });
+            }
+            for (auto& w : workers) w.join();
+            for (int t = 0; t < ns; ++t) PC_HIP(ctx, errs[t]);
+            for (int t = 0; t < ns; ++t) PC_HIP(ctx, hipStreamWaitEvent(hs, ctx->pl_done[t], 0));
         }
         if (ctx->timing) PC_HIP(ctx, hipEventRecord(ctx->ev1, hs));
         PC_HIP(ctx, hipMemcpyAsync(hc, pp.counters, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, hs));

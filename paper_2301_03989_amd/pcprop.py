@@ -48,7 +48,7 @@ class _Opts(ctypes.Structure):
                 ("path", ctypes.c_int32), ("fixed_iters", ctypes.c_int32),
                 ("tile_pairs", ctypes.c_int32), ("graph", ctypes.c_int32),
                 ("switch_tol", ctypes.c_double), ("max_fp32", ctypes.c_int32), ("job_list", ctypes.c_int32),
-                ("conv", ctypes.c_int32)]
+                ("conv", ctypes.c_int32), ("streams", ctypes.c_int32)]
 
 
 class _Group(ctypes.Structure):
@@ -191,13 +191,15 @@ class Context:
 
     @staticmethod
     def opts(init="kepler", max_iter=64, tol_mode="rel", path="fused", fixed_iters=0,
-             tile_pairs=0, precision="fp64", graph=False, switch_tol=0.0, max_fp32=0, job_list=0, conv="ic"):
+             tile_pairs=0, precision="fp64", graph=False, switch_tol=0.0, max_fp32=0, job_list=0, conv="ic",
+             streams=1):
         o = _Opts()
         o.init, o.max_iter, o.tol_mode = INIT[init], int(max_iter), TOL_MODE[tol_mode]
         o.precision, o.path, o.fixed_iters = PRECISION[precision], PATH[path], int(fixed_iters)
         o.tile_pairs, o.graph = int(tile_pairs), int(bool(graph))
         o.switch_tol, o.max_fp32, o.job_list = float(switch_tol), int(max_fp32), int(job_list)
         o.conv = CONV[conv]
+        o.streams = int(streams)
         return o
 
     def workspace_bytes(self, groups, model, **opts):

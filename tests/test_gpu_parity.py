@@ -404,6 +404,28 @@ def test_fp32_then_fp64_mixed_groups(pc):
     assert rel_err(r["states"], o["states"]).max() < TOL
 
 
+@pytest.mark.parametrize("conv", ["ic", "group"])
+def test_plain_path_on_several_streams(pc, conv):
+    """The outer level on several streams (Sec. 5.4): 15 groups spread over 2, 4 and 16
+    streams, each driven by its own host thread, give the one-stream results bit for bit,
+    with the per-IC and the group-max rule."""
+    from paper_2301_03989_amd import pcprop
+    w = W.uneven_batch(450, seed=23)
+    for g in w.groups:
+        g.segments = 1 + g.segments // 16
+        g.tf = g.segments * np.pi / 4.0
+    a, _ = _run(pc, w, path="plain", conv=conv)
+    assert a["status"] == 0
+    for ns in (2, 4, 16):
+        b, _ = _run(pc, w, path="plain", conv=conv, streams=ns)
+        assert np.array_equal(a["states"], b["states"]), ns
+        assert np.array_equal(a["iters"], b["iters"]), ns
+    with pytest.raises(pcprop.PcError):
+        _run(pc, w, streams=2)                  # fused path: one launch, no streams
+    with pytest.raises(pcprop.PcError):
+        _run(pc, w, path="plain", streams=17)
+
+
 def test_fp32_then_fp64_rejected_on_plain_path(pc):
     from paper_2301_03989_amd import pcprop
     w = W.nbody_venus(4)
