@@ -745,6 +745,10 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_
                 });
             }
             for (auto& w : workers) w.join();
+            bool failed = false;
+            for (int t = 0; t < ns; ++t) failed = failed || errs[t] != hipSuccess;
+            if (failed)   // let the other streams drain before the caller can free its buffers
+                for (int t = 0; t < ns; ++t) (void)hipStreamSynchronize(ctx->pl_stream[t]);
             for (int t = 0; t < ns; ++t) PC_HIP(ctx, errs[t]);
             for (int t = 0; t < ns; ++t) PC_HIP(ctx, hipStreamWaitEvent(hs, ctx->pl_done[t], 0));
         }
