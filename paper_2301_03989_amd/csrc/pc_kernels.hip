@@ -188,24 +188,28 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
     // the iterate of the last FP64 sweep (the anchor); dF and the product are FP32, and no
     // force is evaluated.  From an anchor these sweeps converge, at the Picard rate, to the
     // Newton step from it (error quadratic in the anchor's); the FP32 rounding they add is
-    // relative to the increments.  Increment jobs run in stages: increments to the switch
-    // threshold (0); one FP64 sweep (1) that re-anchors the iterate on y0 + w2 K_N F(Y),
+    // relative to the increments.  Increment jobs run in stages: FP64 sweeps until no IC
+    // changes by more than 1e-3 (-1; one sweep after a warm start); increments to the
+    // switch threshold (0); one FP64 sweep (1) that re-anchors the iterate on y0 + w2 K_N F(Y),
     // dropping the rounding and the linearisation error of stage 0; increments again (2),
     // from the closer anchor, until no IC changes by more than tol; then FP64 sweeps (3),
     // the only ones the stopping rule is applied to, so that every IC stops on an FP64
     // sweep that changed it by less than tol (one sweep for most ICs; more where the
     // linearisation left more, as near close approaches, or where stage 2 hit its cap).
-    bool fp32 = MIXED;
     const bool incr = Sh::WIDE && rec_lds;
-    int mode = (fp32 && !incr) ? 1 : 0;
+    // increment jobs open with FP64 sweeps until no IC changes by more than 1e-3 (stage
+    // -1): the linearisation needs an anchor near the solution, which a warm start gives
+    // after one sweep and a cold start after several
+    bool fp32 = MIXED && !incr;
+    int mode = fp32 ? 1 : 0;
     // default switch: the first increment stage hands over at a relative change of 1e-6
     // (on the 262144-IC N-body workload 1e-5, 1e-6 and 1e-7 took 96.5, 95.5 and 97.7 ms;
     // a later switch lengthens stage 0, an earlier one leaves a farther anchor for stage 2);
     // FP32 Picard sweeps stall near 1e-7
     const double sw2 = p.switch2 > 0.0 ? p.switch2 : (incr ? 1e-12 : 1e-8);
-    PcTol tl = pc_tol(p.tol_mode, t2, sw2);
+    PcTol tl = pc_tol(p.tol_mode, t2, (MIXED && incr) ? 1e-6 : sw2);
     int n32 = 0;
-    int stage = 0;
+    int stage = (MIXED && incr) ? -1 : 0;
     float* sD = reinterpret_cast<float*>(sF);                // increment sweeps: dF, FP32
     float* sG = reinterpret_cast<float*>(sF + 3 * PAIRS);    // increment sweeps: G at the anchor
     int act[4];
@@ -261,6 +265,16 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
             ++n32;
             next32 = k && n32 < p.max_fp32;
             if (MIXED && incr && !next32) stage = stage == 0 ? 1 : 3;
+        } else if (MIXED && incr && stage == -1) {
+            // FP64 sweeps until the anchor is close enough, then increments (stage 0)
+            int k = 0;
+            for (int w = 0; w < Sh::W; ++w) k |= sm.Keep[w];
+            if (!k) {
+                stage = 0;
+                next32 = true;
+                n32 = 0;
+                tl = pc_tol(p.tol_mode, t2, sw2);
+            }
         } else if (MIXED && incr && stage == 1) {
             // the re-anchoring sweep ran: increments again until no change exceeds tol
             stage = 2;
