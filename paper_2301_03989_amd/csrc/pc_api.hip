@@ -731,10 +731,11 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_
             rc = ensure_plain_streams(ctx, ns);
             if (rc != PC_OK) return rc;
             PC_HIP(ctx, hipEventRecord(ctx->pl_start, hs));
-            std::vector<hipError_t> errs(ns, hipSuccess);
+            std::vector<hipError_t> errs(ns, hipErrorNotReady);   // a worker that never ran stays failed
             std::vector<std::thread> workers;
+            workers.reserve(ns);
             for (int t = 0; t < ns; ++t) {
-                workers.emplace_back([&, t] {
+                auto body = [&, t] {
                     hipError_t e = hipSetDevice(ctx->device);
                     if (e == hipSuccess) e = hipStreamWaitEvent(ctx->pl_stream[t], ctx->pl_start, 0);
                     for (int gi = t; gi < n_groups && e == hipSuccess; gi += ns)
@@ -742,7 +743,12 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_
                                                      ctx->pl_count + 16 * t, ctx->pl_stream[t]);
                     if (e == hipSuccess) e = hipEventRecord(ctx->pl_done[t], ctx->pl_stream[t]);
                     errs[t] = e;
-                });
+                };
+                try {
+                    workers.emplace_back(body);
+                } catch (...) {   // no thread: no exception may cross the C ABI
+                    break;
+                }
             }
             for (auto& w : workers) w.join();
             bool failed = false;
