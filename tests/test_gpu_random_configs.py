@@ -1,7 +1,9 @@
 """Randomised configurations against the oracle: node counts 3..256 (every padding and job
 shape), 1-3 segments, forward and backward spans, relative and absolute tolerances, warm
 and cold starts, both paths, both precisions, point-mass and relativistic dynamics, and
-the 1024-pair shape where it applies.  Seeded, so every case is reproducible by its id."""
+the 1024-pair shape where it applies; and multi-group batches of eccentric orbits with
+job lengths, graph replays, plain-path streams and the group-max rule.  Seeded, so every
+case is reproducible by its id."""
 import numpy as np
 import pytest
 import torch
@@ -65,3 +67,61 @@ def test_random_configuration(pc, seed):
     assert err.max() < 1e-10, err.max()
     d = r["iters"].cpu().numpy() - o["iters"]
     assert d.min() >= -1 and d.max() <= (12 if kw.get("precision") else 1), (d.min(), d.max())
+
+
+def _batch(seed):
+    """A seeded multi-group batch of eccentric orbits (2-6 groups of the uneven recipe:
+    node counts 64/128/256 or random, 1-3 segments) and random call options."""
+    rng = np.random.default_rng(5000 + seed)
+    w = W.uneven_batch(int(rng.integers(60, 400)), seed=300 + seed)
+    keep = sorted(rng.choice(len(w.groups), size=int(rng.integers(2, 7)), replace=False))
+    groups, parts, off = [], [], 0
+    for gi in keep:
+        g = w.groups[gi]
+        n = int(min(g.n_ic, rng.integers(4, 40)))
+        parts.append(w.ics[g.ic_offset:g.ic_offset + n])
+        S = int(rng.integers(1, 4))
+        N = g.nodes if rng.random() < 0.6 else int(rng.integers(3, 257))
+        groups.append(W.Group(off, n, 0.0, S * np.pi / 4.0, N, S, float(rng.choice([1e-11, 1e-12]))))
+        off += n
+    b = W.Workload("random-batch", np.concatenate(parts), groups, w.pert)
+    kw = {}
+    r = rng.random()
+    if r < 0.2:
+        kw = dict(path="plain", streams=int(rng.integers(1, 5)))
+        if rng.random() < 0.4:
+            kw["conv"] = "group"
+    elif r < 0.4:
+        kw = dict(precision="fp32-fp64")
+    else:
+        kw = dict(job_list=int(rng.choice([0, 1, 2, 4, 8])), graph=bool(rng.random() < 0.3))
+    return b, kw
+
+
+@pytest.mark.parametrize("seed", range(32))
+def test_random_batch(pc, seed):
+    from paper_2301_03989_amd import pcprop
+    import oracle
+    b, kw = _batch(seed)
+    print(f"batch {seed}: " + ", ".join(f"N {g.nodes} S {g.segments} n {g.n_ic}" for g in b.groups) + f" {kw}",
+          flush=True)
+    ics = torch.tensor(b.ics, dtype=torch.float64, device="cuda")
+    groups = [pcprop.Group(g.ic_offset, g.n_ic, g.t0, g.tf, g.nodes, g.segments, g.tol) for g in b.groups]
+    r = pc.propagate_batched(ics, groups, pcprop.Model(b.mu_sun, b.pert, b.epoch), **kw)
+    torch.cuda.synchronize()
+    assert r["status"] in (pcprop.PC_OK, pcprop.PC_ENOTCONV), r["status"]
+    states, iters = r["states"].cpu().numpy(), r["iters"].cpu().numpy()
+    if kw.get("conv") == "group":
+        m = oracle.Model(b.mu_sun, b.pert, b.epoch)
+        for g in b.groups:
+            sl = slice(g.ic_offset, g.ic_offset + g.n_ic)
+            so, io = oracle.propagate(b.ics[sl], g.t0, g.tf, g.nodes, g.segments, g.tol, m, conv=1)
+            assert rel_err(states[sl], so).max() < 1e-10
+            assert np.abs(iters[sl, :g.segments] - io).max() <= 1
+        return
+    o = oracle_run(b)
+    assert rel_err(states, o["states"]).max() < 1e-10
+    d = iters - o["iters"]
+    # the precision schedule's counts follow the slowest IC of each job (eccentric orbits
+    # spread them widely); the FP64 counts are the oracle's
+    assert d.min() >= -1 and d.max() <= (20 if kw.get("precision") else 1), (d.min(), d.max())
