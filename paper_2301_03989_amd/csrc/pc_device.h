@@ -1102,8 +1102,15 @@ static __device__ __forceinline__ void pc_force_eih(const double (&x)[R], const 
         ax[r] = ay[r] = az[r] = 0.0;
         nx[r] = ny[r] = nz[r] = 0.0;
     }
+    // the next body's records are loaded while this one's terms are formed
+    double4 qn = rec(0, 0), wn = rec(1, 0), gn = rec(2, 0);
     for (int b = 0; b <= P; ++b) {
-        double4 q = rec(3 * b, 0), w = rec(3 * b + 1, 0), g = rec(3 * b + 2, 0);
+        double4 q = qn, w = wn, g = gn;
+        if (b < P) {
+            qn = rec(3 * b + 3, 0);
+            wn = rec(3 * b + 4, 0);
+            gn = rec(3 * b + 5, 0);
+        }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if (!ONE_NODE && r > 0) {
