@@ -253,3 +253,35 @@ def test_adjoint_mixed_groups_and_backward(pc):
         sl = slice(G.ic_offset, G.ic_offset + G.n_ic)
         ref = oracle.adjoint(w.ics[sl], G.t0, G.tf, G.nodes, G.segments, G.tol, om, gbar[sl])
         assert _gerr(gr[sl], ref).max() < GTOL
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_adjoint_random_configuration(pc, seed):
+    """Seeded random adjoint cases against the oracle: node counts 3..128, 1-3 segments,
+    forward or backward spans, final-state and node seeds, checkpoints or stored nodes."""
+    rng = np.random.default_rng(700 + seed)
+    N = int(rng.integers(3, 129))
+    S = int(rng.integers(1, 4))
+    n = int(rng.integers(2, 7))
+    w = W.nbody_venus(n, seed=800 + seed, days=float(rng.uniform(15.0, 40.0)) * S, segments=S, nodes=N,
+                      tol=1e-13)
+    if rng.random() < 0.3:
+        g0 = w.groups[0]
+        g0.t0, g0.tf = g0.tf, g0.t0
+    ics, groups, model, om, g = _setup(w)
+    stored = bool(rng.random() < 0.4)
+    fwd = pc.propagate_batched(ics, groups, model, want_bounds=True, want_nodes=stored)
+    assert fwd["status"] == 0
+    gbar = rng.standard_normal((n, 6))
+    gn = None
+    if rng.random() < 0.5:
+        gn = np.zeros((n, S, N, 6))
+        gn[:, rng.integers(0, S), rng.integers(0, N)] = rng.standard_normal((n, 6))
+    print(f"adjoint case {seed}: N {N} S {S} n {n} span {g.t0:.3f}->{g.tf:.3f} stored {stored} "
+          f"node seeds {gn is not None}", flush=True)
+    grad, _, st = pc.adjoint(fwd["bounds"], torch.tensor(gbar, device="cuda"), groups, model,
+                             gbar_nodes=None if gn is None else torch.tensor(gn, device="cuda"),
+                             fwd_nodes=fwd["nodes"] if stored else None)
+    assert st == 0
+    ref = oracle.adjoint(w.ics, g.t0, g.tf, g.nodes, g.segments, g.tol, om, gbar, gn)
+    assert _gerr(grad.cpu().numpy(), ref).max() < GTOL
