@@ -6,9 +6,9 @@ general-relativistic perihelion advance 6 pi mu / (c^2 a (1 - e^2)) per orbit, t
 derivative of the perturber positions (their velocities), and a small-step Runge-Kutta
 integration of the same equations (the Picard-Chebyshev iteration with a velocity-
 dependent force), and the Lorentz boost of a resting mass (a mass in uniform motion, which
-checks the terms in the perturbers' velocities).  The terms in the perturbers'
-accelerations and potentials have no closed-form check here (parity unpinned for those
-terms)."""
+checks the terms in the perturbers' velocities), and the Euler-Lagrange equations of the
+first post-Newtonian Lagrangian solved numerically (which pins every term, the perturbers'
+accelerations and potentials included, up to O(1/c^4))."""
 import numpy as np
 import pytest
 
@@ -141,3 +141,93 @@ def test_eih_refused_by_group_mode_and_adjoint():
         oracle.propagate(w.ics, g.t0, g.tf, g.nodes, g.segments, 1e-12, m, conv=1)
     with pytest.raises(ValueError):
         oracle.adjoint(w.ics, g.t0, g.tf, g.nodes, g.segments, 1e-12, m, gbar_final=np.ones((2, 6)))
+
+
+# -- the first post-Newtonian Lagrangian ---------------------------------------------------
+# The relativistic N-body equations are the Euler-Lagrange equations of the 1PN Lagrangian
+# in harmonic coordinates (the Einstein-Infeld-Hoffmann Lagrangian), with the test body's own
+# acceleration replaced by its Newtonian value inside the O(1/c^2) terms.  For a massless
+# body, the terms linear in its mass are, per unit mass (eps = 1/c^2, rho_b = |r - r_b|,
+# n_b = (r - r_b)/rho_b, U_b the potential at body b of the other major bodies):
+#   L = v^2/2 + eps v^4/8
+#       + sum_b mu_b/rho_b [1 + eps (3 v^2 + 3 v_b^2 - 7 v.v_b - (n_b.v)(n_b.v_b))/2]
+#       - eps/2 (sum_b mu_b/rho_b)^2 - eps sum_b mu_b U_b/rho_b.
+# Solving d/dt dL/dv = dL/dr exactly, for major bodies on prescribed paths, therefore gives
+# the relativistic acceleration up to O(eps^2).  The check below differentiates L
+# numerically and never uses the acceleration formula, so it pins every term of it: the
+# major bodies' velocities, their accelerations (through d/dt of dL/dv) and their
+# potentials.  A wrong term leaves an O(eps) difference, which halves when eps halves
+# instead of falling by four.
+
+def _paths(seed):
+    """Three major bodies in uniform acceleration (positions, velocities, accelerations at
+    t = 0), their parameters, and a massless body's state."""
+    rng = np.random.default_rng(seed)
+    r0 = rng.normal(size=(3, 3)) * 1.2
+    v0 = rng.normal(size=(3, 3)) * 0.4
+    a0 = rng.normal(size=(3, 3)) * 0.5
+    mu = rng.uniform(0.05, 0.3, 3)
+    y = np.concatenate([rng.normal(size=3) * 0.3, rng.normal(size=3) * 0.5])
+    U = np.array([sum(mu[c] / np.linalg.norm(r0[b] - r0[c]) for c in range(3) if c != b) for b in range(3)])
+    return r0, v0, a0, mu, U + 0.7, y                # + a distant mass's constant potential
+
+
+def _lagrangian(r, v, t, body, eps):
+    r0, v0, a0, mu, U = body
+    L = 0.5 * v @ v + eps * (v @ v) ** 2 / 8
+    phi = 0.0
+    for b in range(len(mu)):
+        rb, vb = r0[b] + v0[b] * t + 0.5 * a0[b] * t * t, v0[b] + a0[b] * t
+        d = r - rb
+        rho = np.linalg.norm(d)
+        n = d / rho
+        L += mu[b] / rho * (1 + eps * (3 * v @ v + 3 * vb @ vb - 7 * v @ vb - (n @ v) * (n @ vb)) / 2)
+        L -= eps * mu[b] * U[b] / rho
+        phi += mu[b] / rho
+    return L - eps * phi * phi / 2
+
+
+def _grad(f, x, h=1e-6):
+    e = np.eye(len(x))
+    return np.stack([(f(x + h * e[k]) - f(x - h * e[k])) / (2 * h) for k in range(len(x))], axis=-1)
+
+
+def _momentum(r, v, t, body, eps):
+    """dL/dv, differentiated by hand (checked against central differences of L below)."""
+    r0, v0, a0, mu, U = body
+    p = v + eps * (v @ v) * v / 2
+    for b in range(len(mu)):
+        rb, vb = r0[b] + v0[b] * t + 0.5 * a0[b] * t * t, v0[b] + a0[b] * t
+        d = r - rb
+        rho = np.linalg.norm(d)
+        n = d / rho
+        p = p + eps * mu[b] / rho * (6 * v - 7 * vb - n * (n @ vb)) / 2
+    return p
+
+
+def _euler_lagrange_accel(y, body, eps, h=1e-6):
+    """Acceleration from d/dt dL/dv = dL/dr, the derivatives of L and of dL/dv by central
+    differences: (d2L/dv dv) a = dL/dr - (d2L/dv dr) v - d2L/dv dt."""
+    r, v = y[:3], y[3:]
+    p = lambda rr, vv, t: _momentum(rr, vv, t, body, eps)
+    assert np.allclose(p(r, v, 0.0), _grad(lambda w: _lagrangian(r, w, 0.0, body, eps), v), rtol=0, atol=1e-9)
+    dLdr = _grad(lambda w: _lagrangian(w, v, 0.0, body, eps), r, h)
+    Jr = _grad(lambda w: p(w, v, 0.0), r, h)
+    Jv = _grad(lambda w: p(r, w, 0.0), v, h)
+    dpt = (p(r, v, h) - p(r, v, -h)) / (2 * h)
+    return np.linalg.solve(Jv, dLdr - Jr @ v - dpt)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_euler_lagrange_equations_of_the_1pn_lagrangian(seed):
+    r0, v0, a0, mu, U, y = _paths(seed)
+    body = (r0, v0, a0, mu, U)
+    newton = oracle.accel_eih_bodies(y, r0, v0, a0, mu, U, 0.0)
+    assert np.linalg.norm(_euler_lagrange_accel(y, body, 0.0) - newton) < 1e-7
+    d = {}
+    for eps in (4e-4, 2e-4):
+        a = oracle.accel_eih_bodies(y, r0, v0, a0, mu, U, eps)
+        assert np.linalg.norm(a - newton) > 50 * eps * eps       # the 1PN part is O(eps)
+        d[eps] = np.linalg.norm(_euler_lagrange_accel(y, body, eps) - a)
+    assert d[4e-4] < 20 * 4e-4 ** 2, d
+    assert 3.7 < d[4e-4] / d[2e-4] < 4.3, d                      # O(eps^2), not O(eps)
