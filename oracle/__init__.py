@@ -46,7 +46,10 @@ def _load():
         lib.orc_propagate.argtypes = [
             ctypes.c_int, _dp, _dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
             ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
-            ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double, _dp, _ip, _dp, _dp, ctypes.c_int]
+            ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double, _dp, _ip, _dp, _dp, ctypes.c_int,
+            ctypes.c_int, ctypes.c_int]
+        lib.orc_second_order_step.restype = None
+        lib.orc_second_order_step.argtypes = [ctypes.c_int, _dp, _dp, _dp, ctypes.c_double, _dp, _dp]
         lib.orc_propagate_group.restype = ctypes.c_int
         lib.orc_propagate_group.argtypes = [
             ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
@@ -122,13 +125,17 @@ class Model:
 
 
 def propagate(ics, t0, tf, nodes, segments, tol, model=None, *, tol_mode=0, max_iter=64,
-              fixed_iters=0, init=0, want_bounds=False, want_nodes=False, threads=0, conv=0):
+              fixed_iters=0, init=0, want_bounds=False, want_nodes=False, threads=0, conv=0,
+              order=1, feedback=0):
     """Propagate ICs [n,6] over [t0, tf] (scalars or per-IC arrays).
 
     Returns (states[n,6], iters[n,segments]) and, when asked, the segment-boundary
     states [n,S+1,6] and the node states [n,S,N,6].  ``init``: 0 Kepler, 1 cold.
     ``conv``: 0 = stopping rule per IC; 1 = one stopping decision for all the ICs, on
     the largest error over them (orc_propagate_group; scalar t0 and tf, no fixed sweeps).
+    ``order``: 1 = the first-order iteration, 2 = the second-order form (velocity and
+    position both from the accelerations); ``feedback``: 1 = the second-order form with
+    integral error feedback (orc_propagate).
     """
     lib = _load()
     model = model or Model()
@@ -141,7 +148,11 @@ def propagate(ics, t0, tf, nodes, segments, tol, model=None, *, tol_mode=0, max_
     iters = np.zeros((n, S), dtype=np.int32)
     bounds = np.zeros((n, S + 1, 6)) if want_bounds else None
     nodes_out = np.zeros((n, S, N, 6)) if want_nodes else None
+    if order not in (1, 2) or (feedback and order != 2):
+        raise ValueError("order must be 1 or 2, and feedback needs order 2")
     if conv == 1:
+        if order != 1:
+            raise ValueError("group-max convergence is written for the first-order iteration")
         if np.ndim(t0) or np.ndim(tf) or fixed_iters or model.inv_c2:
             raise ValueError("group-max convergence takes one t0 and tf, no fixed sweeps and "
                              "the point-mass model")
@@ -154,7 +165,8 @@ def propagate(ics, t0, tf, nodes, segments, tol, model=None, *, tol_mode=0, max_
         used = lib.orc_propagate(n, _ptr(ics), _ptr(t0a), _ptr(tfa), N, S, float(tol), int(tol_mode),
                                  int(max_iter), int(fixed_iters), int(init), model.mu_sun,
                                  model.n_pert, model._pert_ptr(), model.epoch, model.inv_c2, _ptr(states),
-                                 iters.ctypes.data_as(_ip), _ptr(bounds), _ptr(nodes_out), int(threads))
+                                 iters.ctypes.data_as(_ip), _ptr(bounds), _ptr(nodes_out), int(threads),
+                                 int(order), int(feedback))
     out = [states, iters]
     if want_bounds:
         out.append(bounds)
@@ -179,6 +191,30 @@ def picard_step(g, y0):
     y = np.zeros((N, nc))
     lib.orc_picard_step(N, nc, _ptr(g), _ptr(y0), _ptr(y))
     return y
+
+
+def second_order_step(a, x0, v0, w2):
+    """One second-order update for a single trajectory: accelerations a [N, 3] at the nodes,
+    initial position x0 [3] and velocity v0 [3], half-length w2 -> (x [N, 3], v [N, 3])."""
+    lib = _load()
+    a = _f64(a).reshape(-1, 3)
+    N = a.shape[0]
+    x0, v0 = _f64(x0).reshape(3), _f64(v0).reshape(3)
+    x, v = np.zeros((N, 3)), np.zeros((N, 3))
+    lib.orc_second_order_step(N, _ptr(a), _ptr(x0), _ptr(v0), float(w2), _ptr(x), _ptr(v))
+    return x, v
+
+
+def operator2(N):
+    """The linear maps a -> (x - x0 - w2 v0 (tau + 1)) / w2^2 and a -> (v - v0) / w2 of the
+    second-order update, as N x N matrices (K2, K1) built from unit vectors."""
+    K2, K1 = np.zeros((N, N)), np.zeros((N, N))
+    for l in range(N):
+        a = np.zeros((N, 3))
+        a[l, 0] = 1.0
+        x, v = second_order_step(a, np.zeros(3), np.zeros(3), 1.0)
+        K2[:, l], K1[:, l] = x[:, 0], v[:, 0]
+    return K2, K1
 
 
 def operator(N):

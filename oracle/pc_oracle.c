@@ -404,6 +404,72 @@ void orc_nodes(int N, double* tau)
     for (int j = 0; j < N; ++j) tau[j] = orc_tau(j, N);
 }
 
+/*
+ * Second-order form (the version of the method for x'' = a(x, v, t) that Sec. 1 cites
+ * as a further development applicable to the augmented system): velocity and position
+ * are both obtained from the acceleration samples, the position by integrating the new
+ * velocity series rather than the previous velocity iterate.  For one trajectory, with
+ * a[N][3] the unscaled accelerations at the nodes, x0, v0 the initial state and w2 the
+ * half-length of the segment (dt = w2 dtau):
+ *   (ii)  c_k = 2/(N-1) sum''_j a_j T_k(tau_j), k = 0..N-2      (the fit of step ii)
+ *   (iii) velocity series b_k = (c_{k-1} - c_{k+1}) / (2k), k = 1..N-1, and
+ *         b_0 = -2 sum_k (-1)^k b_k, so that the series vanishes at tau = -1;
+ *         v_j = v0 + w2 (b_0/2 + sum_{k=1}^{N-1} b_k T_k(tau_j))
+ *   (iv)  position series d_k = (b_{k-1} - b_{k+1}) / (2k), k = 1..N (b_N = b_{N+1} = 0,
+ *         b_0 taken with its half weight, as in the integral of b_0/2 T_0), and
+ *         d_0 = -2 sum_k (-1)^k d_k;
+ *         x_j = x0 + w2 v0 (tau_j + 1) + w2^2 (d_0/2 + sum_{k=1}^{N} d_k T_k(tau_j))
+ * so x is the exact double integral of the degree N-2 fit (degree N), v its single one.
+ * Tkj: T_k(tau_j) for k = 0..N, [N+1][N] row-major by k.
+ */
+static void orc_second_order_update(int N, const double* Tkj, const double* a, const double* x0,
+                                    const double* v0, double w2, const double* tau, double* x, double* v,
+                                    double* cbuf, double* bbuf, double* dbuf)
+{
+    for (int comp = 0; comp < 3; ++comp) {
+        for (int k = 0; k <= N + 1; ++k) cbuf[k] = bbuf[k] = dbuf[k] = 0.0;
+        for (int k = 0; k <= N - 2; ++k) {
+            double s = 0.0;
+            for (int j = 0; j < N; ++j) {
+                double w = (j == 0 || j == N - 1) ? 0.5 : 1.0;
+                s += w * a[3 * j + comp] * Tkj[k * N + j];
+            }
+            cbuf[k] = 2.0 / (double)(N - 1) * s;
+        }
+        for (int k = 1; k <= N - 1; ++k) bbuf[k] = (cbuf[k - 1] - cbuf[k + 1]) / (2.0 * k);
+        double alt = 0.0;
+        for (int k = 1; k <= N - 1; ++k) alt += ((k & 1) ? -1.0 : 1.0) * bbuf[k];
+        bbuf[0] = -2.0 * alt;
+        for (int k = 1; k <= N; ++k) dbuf[k] = (bbuf[k - 1] - bbuf[k + 1]) / (2.0 * k);
+        alt = 0.0;
+        for (int k = 1; k <= N; ++k) alt += ((k & 1) ? -1.0 : 1.0) * dbuf[k];
+        dbuf[0] = -2.0 * alt;
+        for (int j = 0; j < N; ++j) {
+            double sv = 0.5 * bbuf[0], sx = 0.5 * dbuf[0];
+            for (int k = 1; k <= N - 1; ++k) sv += bbuf[k] * Tkj[k * N + j];
+            for (int k = 1; k <= N; ++k) sx += dbuf[k] * Tkj[k * N + j];
+            v[3 * j + comp] = v0[comp] + w2 * sv;
+            x[3 * j + comp] = x0[comp] + w2 * v0[comp] * (tau[j] + 1.0) + w2 * w2 * sx;
+        }
+    }
+}
+
+/* Test hook: one second-order update (steps ii-iv above) for a single trajectory. */
+void orc_second_order_step(int N, const double* a, const double* x0, const double* v0, double w2,
+                           double* x, double* v)
+{
+    double* Tkj = (double*)malloc(sizeof(double) * (size_t)(N + 1) * N);
+    double* tau = (double*)malloc(sizeof(double) * (size_t)N);
+    double* cbuf = (double*)malloc(sizeof(double) * (size_t)(N + 2));
+    double* bbuf = (double*)malloc(sizeof(double) * (size_t)(N + 2));
+    double* dbuf = (double*)malloc(sizeof(double) * (size_t)(N + 2));
+    for (int k = 0; k <= N; ++k)
+        for (int j = 0; j < N; ++j) Tkj[k * N + j] = orc_T(k, j, N);
+    for (int j = 0; j < N; ++j) tau[j] = orc_tau(j, N);
+    orc_second_order_update(N, Tkj, a, x0, v0, w2, tau, x, v, cbuf, bbuf, dbuf);
+    free(Tkj); free(tau); free(cbuf); free(bbuf); free(dbuf);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Whole propagation                                                         */
 /* ------------------------------------------------------------------------ */
@@ -453,21 +519,32 @@ static double orc_iter_error(int N, const double* ynew, const double* yold, int 
  *   bounds_out         [n][S+1][6] segment-boundary states, or NULL
  *   nodes_out          [n][S][N][6] converged node states, or NULL
  *   nthreads           OpenMP threads (<= 0: library default)
+ *   order              1: the iteration of Sec. 2.2 on the first-order system (steps
+ *                      i-vi above); 2: the second-order form (orc_second_order_update),
+ *                      the same stopping rule (vi) on the position and velocity iterates
+ *   feedback           order 2 only, 1 = integral error feedback, read here as: the
+ *                      sweep's accelerations were taken at the previous position iterate,
+ *                      so the change dx_j that the sweep makes to the position is fed back
+ *                      through the linear part of the dynamics, da_j = (da/dr)_j dx_j (the
+ *                      point-mass gravity gradient at the previous iterate), and the
+ *                      integrals of da (orc_second_order_update with zero initial state)
+ *                      are added to the new velocity and position.  At the fixed point dx
+ *                      vanishes, so the converged result is that of order 2 without it.
  * Returns the number of threads used.
  */
 int orc_propagate(int n_ic, const double* ics, const double* t0, const double* tf,
                   int N, int S, double tol, int tol_mode, int max_iter, int fixed_iters,
                   int init, double mu_sun, int n_pert, const double* pert, double epoch,
                   double inv_c2, double* states_out, int* iters_out, double* bounds_out,
-                  double* nodes_out, int nthreads)
+                  double* nodes_out, int nthreads, int order, int feedback)
 {
     int used = 1;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #endif
-    double* Tkj = (double*)malloc(sizeof(double) * (size_t)N * N);
+    double* Tkj = (double*)malloc(sizeof(double) * (size_t)(N + 1) * N);   /* k = 0..N */
     double* tau = (double*)malloc(sizeof(double) * (size_t)N);
-    for (int k = 0; k < N; ++k)
+    for (int k = 0; k <= N; ++k)
         for (int j = 0; j < N; ++j) Tkj[k * N + j] = orc_T(k, j, N);
     for (int j = 0; j < N; ++j) tau[j] = orc_tau(j, N);
     double mup[64];
@@ -487,6 +564,12 @@ int orc_propagate(int n_ic, const double* ics, const double* t0, const double* t
         double* vp = (double*)malloc(sizeof(double) * (size_t)N * 3 * (np > 0 ? np : 1));
         double* cbuf = (double*)malloc(sizeof(double) * (size_t)(N + 2));
         double* bbuf = (double*)malloc(sizeof(double) * (size_t)(N + 2));
+        double* dbuf = (double*)malloc(sizeof(double) * (size_t)(N + 2));
+        double* A2 = (double*)malloc(sizeof(double) * (size_t)N * 3);    /* order 2: a at the nodes */
+        double* X2 = (double*)malloc(sizeof(double) * (size_t)N * 3);
+        double* V2 = (double*)malloc(sizeof(double) * (size_t)N * 3);
+        double* dX2 = (double*)malloc(sizeof(double) * (size_t)N * 3);
+        double* dV2 = (double*)malloc(sizeof(double) * (size_t)N * 3);
 #pragma omp for schedule(dynamic, 1)
         for (int m = 0; m < n_ic; ++m) {
             double y0[6];
@@ -544,10 +627,36 @@ int orc_propagate(int n_ic, const double* ics, const double* t0, const double* t
                         for (int k = 0; k < 3; ++k) {
                             G[6 * j + k] = w2 * Y[6 * j + 3 + k];
                             G[6 * j + 3 + k] = w2 * acc[k];
+                            A2[3 * j + k] = acc[k];
                         }
                     }
-                    /* (ii)-(v) */
-                    orc_picard_update(N, 6, Tkj, G, y0, Yn, cbuf, bbuf);
+                    if (order == 2) {
+                        /* second-order form: velocity and position from the accelerations */
+                        orc_second_order_update(N, Tkj, A2, y0, y0 + 3, w2, tau, X2, V2, cbuf, bbuf, dbuf);
+                        if (feedback) {
+                            const double zero[3] = {0.0, 0.0, 0.0};
+                            for (int j = 0; j < N; ++j) {
+                                double J[9], dx[3];
+                                orc_accel_jac(Y + 6 * j, np, rp + 3 * j * np, mup, mu_sun, J);
+                                for (int k = 0; k < 3; ++k) dx[k] = X2[3 * j + k] - Y[6 * j + k];
+                                for (int k = 0; k < 3; ++k)
+                                    A2[3 * j + k] = J[3 * k] * dx[0] + J[3 * k + 1] * dx[1] + J[3 * k + 2] * dx[2];
+                            }
+                            orc_second_order_update(N, Tkj, A2, zero, zero, w2, tau, dX2, dV2, cbuf, bbuf, dbuf);
+                            for (int i = 0; i < 3 * N; ++i) {
+                                X2[i] += dX2[i];
+                                V2[i] += dV2[i];
+                            }
+                        }
+                        for (int j = 0; j < N; ++j)
+                            for (int k = 0; k < 3; ++k) {
+                                Yn[6 * j + k] = X2[3 * j + k];
+                                Yn[6 * j + 3 + k] = V2[3 * j + k];
+                            }
+                    } else {
+                        /* (ii)-(v) */
+                        orc_picard_update(N, 6, Tkj, G, y0, Yn, cbuf, bbuf);
+                    }
                     /* (vi) */
                     double e = orc_iter_error(N, Yn, Y, tol_mode);
                     double* tmp = Y; Y = Yn; Yn = tmp;   /* Y is now the newest iterate */
@@ -566,6 +675,7 @@ int orc_propagate(int n_ic, const double* ics, const double* t0, const double* t
             memcpy(states_out + 6 * m, y0, sizeof(y0));
         }
         free(Y); free(Yn); free(G); free(rp); free(vp); free(cbuf); free(bbuf);
+        free(dbuf); free(A2); free(X2); free(V2); free(dX2); free(dV2);
     }
     free(Tkj); free(tau);
     return used;
