@@ -82,7 +82,11 @@ typedef struct {
     double inv_c2;        /* 1/c^2: 0 = point masses (default), > 0 = Einstein-Infeld-Hoffmann */
 } pc_model;
 
-enum { PC_INIT_KEPLER = 0, PC_INIT_COLD = 1 };   /* initial guess, Sec. 2.1 (warm / cold start) */
+/* Initial guess of every segment (Sec. 2.1): warm (two-body Kepler from the segment's
+ * initial state), cold (the initial state at every node), or the caller's node states
+ * (opts.guess): a hot start from a previous propagation, e.g. of a simpler model or of
+ * nearby initial conditions, which Sec. 2.1 lists as guesses closer to the solution. */
+enum { PC_INIT_KEPLER = 0, PC_INIT_COLD = 1, PC_INIT_GUESS = 2 };
 enum { PC_TOL_REL = 0, PC_TOL_ABS = 1 };         /* relative or absolute stopping rule, Sec. 2.2 */
 /* Arithmetic of the sweeps.  PC_FP32_THEN_FP64 (fused path): every segment starts with
  * an FP32 phase, which ends once the relative change of every iterating IC of the job is
@@ -112,7 +116,7 @@ enum { PC_PATH_FUSED = 0, PC_PATH_PLAIN = 1 };   /* one persistent launch / per-
 enum { PC_CONV_PER_IC = 0, PC_CONV_GROUP_MAX = 1 };
 
 typedef struct {
-    int32_t init;         /* PC_INIT_KEPLER (default) or PC_INIT_COLD */
+    int32_t init;         /* PC_INIT_KEPLER (default), PC_INIT_COLD or PC_INIT_GUESS */
     int32_t max_iter;     /* Picard iterations per segment before PC_ITER_NOTCONV (default 64) */
     int32_t tol_mode;     /* PC_TOL_REL (default) or PC_TOL_ABS */
     int32_t precision;    /* PC_FP64 */
@@ -137,10 +141,33 @@ typedef struct {
                              workgroup slots within 25 % of the fewest block-times), 1 = off,
                              2, 4 or 8 = that many blocks.  Results do not depend on it. */
     int32_t conv;         /* PC_CONV_PER_IC (default) or PC_CONV_GROUP_MAX */
-    int32_t streams;      /* plain path: groups run on this many streams at once, each driven
-                             by its own host thread and read-back (the outer-level streams of
-                             Sec. 5.4; 1..PC_MAX_STREAMS, default 1); the workspace holds one
-                             plain-path state per stream.  Results do not depend on it. */
+    int32_t streams;      /* plain path: groups run on this many streams at once (the
+                             outer-level streams of Sec. 5.4; 1..PC_MAX_STREAMS, default 1),
+                             all driven from the calling thread, which polls each stream's
+                             per-iteration read-back and takes that stream's next loop decision
+                             when it has landed; the workspace holds one plain-path state per
+                             stream.  Results do not depend on it. */
+    int32_t order;        /* 1 (default): the iteration of Sec. 2.2 on the first-order system,
+                             y = y0 + w2 K_N F(y).  2: the second-order form that Sec. 1 cites
+                             as applicable to the augmented system: the velocity and the
+                             position are both obtained from the acceleration samples,
+                             v = v0 + w2 K_N a and x = x0 + w2 v0 (tau + 1) + w2^2 K2_N a, with
+                             K2_N the degree N-2 fit integrated twice, so the position takes
+                             the new velocity instead of the previous one (about half the
+                             sweeps at the same product cost per sweep).  Its fixed point is a
+                             different discretisation of the same ODE (the position series
+                             has degree N).  Order 2 runs on the fused FP64 path with the
+                             per-IC rule and the point-mass model, for node counts up to 128;
+                             other calls with order 2 return PC_EINVAL. */
+    int32_t feedback;     /* order 2 with integral error feedback (the linear change of the
+                             acceleration over the position change of the sweep, integrated
+                             and added to the iterate): reserved, must be 0 (the HIP path
+                             returns PC_EINVAL for 1) */
+    const double* guess;  /* init = PC_INIT_GUESS: device [n_ic][iters_stride][nodes_stride][6],
+                             the node states of the initial guess of every segment, in the
+                             layout of the same call's nodes_out (e.g. the nodes_out of an
+                             earlier call); a non-finite row falls back to the segment's
+                             initial state at that node.  NULL otherwise (default) */
 } pc_opts;
 
 /* One outer-level group of the two-level augmentation (Sec. 3.2): ICs
@@ -245,6 +272,20 @@ int pc_eval_force(pc_ctx* ctx, const double* r, const double* t, int64_t n,
 int pc_eval_kepler(pc_ctx* ctx, const double* y0, const double* dt, int64_t n,
                    double* y, int32_t* ok, pc_stream_t stream);
 
+/* On-chip ceilings for the roofline figures, measured on this device: out[0] = FP64
+ * matrix-core rate (a loop of independent v_mfma_f64_16x16x4 chains on every SIMD),
+ * out[1] = FP64 vector rate (a loop of independent FMA chains on every lane), both in
+ * TFLOP/s, and out[2] = device copy bandwidth in GB/s (bytes read plus written, one half of
+ * buf copied to the other).  Best of three timed launches each.
+ *   buf  device scratch, overwritten; buf_bytes >= 16 MiB (the copy moves buf_bytes / 2)
+ *   out  host [3] */
+int pc_measure_ceilings(pc_ctx* ctx, void* buf, size_t buf_bytes, pc_stream_t stream, double* out);
+
+/* Number of HIP graphs the context has captured for graph = 1 calls (test hook: a call
+ * whose signature, or whose pinned staging buffer, differs from the captured one's is
+ * captured again). */
+int pc_graph_captures(pc_ctx* ctx, int64_t* count /* host out */);
+
 /* Kernel timing of the next calls: when enabled, pc_propagate_batched records HIP events
  * on its stream around its propagation kernels (not the ephemeris table build or the
  * copies), and pc_last_kernel_ms returns the elapsed time of the last such call in
@@ -252,10 +293,15 @@ int pc_eval_kepler(pc_ctx* ctx, const double* y0, const double* dt, int64_t n,
 int pc_set_timing(pc_ctx* ctx, int enable);
 int pc_last_kernel_ms(pc_ctx* ctx, double* ms /* host out */);
 
-/* Autotuner: times the fused path on the caller's batch with each job shape
- * (tile_pairs 1024 and 2048, where the node counts allow both) for two Picard sweeps of
- * the first segment, and records the faster one in the context's table for the largest
- * padded node count of the batch; later calls with tile_pairs = 0 use the table.
+/* Autotuner of the fused FP64 path: on the caller's batch (the whole call, default options,
+ * median kernel time of three runs per candidate) it starts from the untuned rules and
+ * keeps each change that makes the call faster, in coordinate order: first the job shape
+ * of the call (tile_pairs 2048, or 1024 where every node count fits it; one shape per
+ * launch, recorded for the batch's largest padded node count), then, for each padded node
+ * count of the batch from the largest, the job length (job_list 1, 2, 4 or 8 column blocks,
+ * recorded per padded node count).  Later calls with tile_pairs = 0 and job_list = 0 read
+ * these tables; nothing is recorded that measured slower than the untuned rules.
+ * 4 + 12 x (node counts) calls of the batch are run.
  *   scratch_states  device [n_ic][6], overwritten
  *   chosen_pairs    host out, the recorded shape
  * Other arguments as pc_propagate_batched. */
@@ -267,6 +313,11 @@ int pc_autotune(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_group* gr
  * pairs 1024 or 2048, or 0 to clear. */
 int pc_set_tile_pairs(pc_ctx* ctx, int32_t padded_nodes, int32_t pairs);
 int pc_get_tile_pairs(pc_ctx* ctx, int32_t padded_nodes, int32_t* pairs);
+
+/* Set / read the tuned job length (column blocks per job: 1, 2, 4 or 8; 0 = the untuned
+ * rule) for a padded node count, used by fused FP64 calls with job_list = 0. */
+int pc_set_job_list(pc_ctx* ctx, int32_t padded_nodes, int32_t blocks);
+int pc_get_job_list(pc_ctx* ctx, int32_t padded_nodes, int32_t* blocks);
 
 /* Message for a status code (static storage). */
 const char* pc_strerror(int code);

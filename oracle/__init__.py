@@ -47,7 +47,7 @@ def _load():
             ctypes.c_int, _dp, _dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
             ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
             ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double, _dp, _ip, _dp, _dp, ctypes.c_int,
-            ctypes.c_int, ctypes.c_int]
+            ctypes.c_int, ctypes.c_int, _dp]
         lib.orc_second_order_step.restype = None
         lib.orc_second_order_step.argtypes = [ctypes.c_int, _dp, _dp, _dp, ctypes.c_double, _dp, _dp]
         lib.orc_propagate_group.restype = ctypes.c_int
@@ -126,7 +126,7 @@ class Model:
 
 def propagate(ics, t0, tf, nodes, segments, tol, model=None, *, tol_mode=0, max_iter=64,
               fixed_iters=0, init=0, want_bounds=False, want_nodes=False, threads=0, conv=0,
-              order=1, feedback=0):
+              order=1, feedback=0, guess=None):
     """Propagate ICs [n,6] over [t0, tf] (scalars or per-IC arrays).
 
     Returns (states[n,6], iters[n,segments]) and, when asked, the segment-boundary
@@ -135,7 +135,8 @@ def propagate(ics, t0, tf, nodes, segments, tol, model=None, *, tol_mode=0, max_
     the largest error over them (orc_propagate_group; scalar t0 and tf, no fixed sweeps).
     ``order``: 1 = the first-order iteration, 2 = the second-order form (velocity and
     position both from the accelerations); ``feedback``: 1 = the second-order form with
-    integral error feedback (orc_propagate).
+    integral error feedback (orc_propagate).  ``init`` 2 starts every segment from
+    ``guess`` [n, S, N, 6] (node states of an earlier propagation).
     """
     lib = _load()
     model = model or Model()
@@ -150,8 +151,11 @@ def propagate(ics, t0, tf, nodes, segments, tol, model=None, *, tol_mode=0, max_
     nodes_out = np.zeros((n, S, N, 6)) if want_nodes else None
     if order not in (1, 2) or (feedback and order != 2):
         raise ValueError("order must be 1 or 2, and feedback needs order 2")
+    if (init == 2) != (guess is not None):
+        raise ValueError("init 2 takes a guess [n, S, N, 6], and only it does")
+    garr = _f64(guess, (n, S, N, 6)) if guess is not None else None
     if conv == 1:
-        if order != 1:
+        if order != 1 or init == 2:
             raise ValueError("group-max convergence is written for the first-order iteration")
         if np.ndim(t0) or np.ndim(tf) or fixed_iters or model.inv_c2:
             raise ValueError("group-max convergence takes one t0 and tf, no fixed sweeps and "
@@ -166,7 +170,7 @@ def propagate(ics, t0, tf, nodes, segments, tol, model=None, *, tol_mode=0, max_
                                  int(max_iter), int(fixed_iters), int(init), model.mu_sun,
                                  model.n_pert, model._pert_ptr(), model.epoch, model.inv_c2, _ptr(states),
                                  iters.ctypes.data_as(_ip), _ptr(bounds), _ptr(nodes_out), int(threads),
-                                 int(order), int(feedback))
+                                 int(order), int(feedback), _ptr(garr))
     out = [states, iters]
     if want_bounds:
         out.append(bounds)

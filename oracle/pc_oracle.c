@@ -512,7 +512,9 @@ static double orc_iter_error(int N, const double* ynew, const double* yold, int 
  *   max_iter           iteration cap per segment
  *   fixed_iters        if > 0, every segment runs exactly this many
  *                      iterations and reports that count (no stopping rule)
- *   init               0 = Kepler warm start, 1 = cold start
+ *   init               0 = Kepler warm start, 1 = cold start, 2 = the node states in
+ *                      guess[n][S][N][6] (a hot start from an earlier propagation, Sec. 2.1;
+ *                      a non-finite row starts from the segment's initial state)
  *   mu_sun, n_pert, pert[n_pert][7], epoch : force model
  *   states_out[n][6]   final states
  *   iters_out[n][S]    per-segment iteration counts / status
@@ -536,7 +538,7 @@ int orc_propagate(int n_ic, const double* ics, const double* t0, const double* t
                   int N, int S, double tol, int tol_mode, int max_iter, int fixed_iters,
                   int init, double mu_sun, int n_pert, const double* pert, double epoch,
                   double inv_c2, double* states_out, int* iters_out, double* bounds_out,
-                  double* nodes_out, int nthreads, int order, int feedback)
+                  double* nodes_out, int nthreads, int order, int feedback, const double* guess)
 {
     int used = 1;
 #ifdef _OPENMP
@@ -605,7 +607,14 @@ int orc_propagate(int n_ic, const double* ics, const double* t0, const double* t
                 }
                 /* initial guess */
                 int cold = (init == 1);
-                if (!cold) {
+                if (init == 2) {
+                    for (int j = 0; j < N; ++j) {
+                        const double* gq = guess + (((size_t)m * S + s) * N + j) * 6;
+                        int fin = 1;
+                        for (int k = 0; k < 6; ++k) fin = fin && isfinite(gq[k]);
+                        memcpy(Y + 6 * j, fin ? gq : y0, sizeof(y0));
+                    }
+                } else if (!cold) {
                     for (int j = 0; j < N; ++j) {
                         double dt = w2 * (tau[j] + 1.0);
                         if (orc_kepler(y0, dt, Y + 6 * j) != 0) { cold = 1; break; }

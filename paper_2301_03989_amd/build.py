@@ -29,6 +29,22 @@ def sources():
     return sorted(glob.glob(os.path.join(PKG, "csrc", "*.hip")))
 
 
+def _deps():
+    return sources() + sorted(glob.glob(os.path.join(PKG, "csrc", "*.h"))) + \
+        [os.path.join(ROOT, "include", "pcprop.h")]
+
+
+def source_hash() -> str:
+    """sha256 over the sources the library is built from (names and contents)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in _deps():
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp%d" % os.getpid()
@@ -45,21 +61,28 @@ def build(verbose: bool = False) -> str:
     if verbose and msgs:
         print("\n".join(msgs))
     os.replace(tmp, LIB)
+    with open(LIB + ".srchash", "w") as fh:   # what the library was built from
+        fh.write(source_hash() + "\n")
     return LIB
 
 
 def is_stale() -> bool:
+    """True when no library is built or its sources have changed since (by content, so
+    that copies of the tree whose file times differ agree)."""
     if not os.path.exists(LIB):
         return True
-    t = os.path.getmtime(LIB)
-    deps = sources() + glob.glob(os.path.join(PKG, "csrc", "*.h")) + \
-        [os.path.join(ROOT, "include", "pcprop.h")]
-    return any(os.path.getmtime(d) > t for d in deps)
+    try:
+        with open(LIB + ".srchash") as fh:
+            return fh.read().strip() != source_hash()
+    except OSError:
+        t = os.path.getmtime(LIB)
+        return any(os.path.getmtime(d) > t for d in _deps())
 
 
 def ensure_built() -> str:
-    """Build only if no library exists (tests, smoke and bench load what is built)."""
-    if not os.path.exists(LIB):
+    """Build if no library exists or a source is newer than it (tests, smoke and bench
+    otherwise load what is built)."""
+    if is_stale():
         build()
     return LIB
 

@@ -27,8 +27,20 @@ struct OperatorCache {
     float* kfrag32 = nullptr;  // device, FP32 fragments in kfrag order
     float* kfrag32p = nullptr; // device, FP32 fragments with rows permuted per strip
     double* kfragT = nullptr;  // device, fragments of K_N^T
+    double* kfrag2 = nullptr;  // device, fragments of K2_N
     double* tau = nullptr;     // device, [NP]
     std::vector<double> K;     // host copy, [N][N]
+};
+
+struct HostOperator {
+    int N = 0, NP = 0;
+    std::vector<double> K;        // [N][N]
+    std::vector<double> frag;     // [NP/16][NP/4][64]
+    std::vector<float> frag32;    // FP32, frag order
+    std::vector<float> frag32p;   // FP32, rows permuted per strip
+    std::vector<double> fragT;    // fragments of K_N^T
+    std::vector<double> frag2;    // fragments of K2_N (second-order sweeps)
+    std::vector<double> tau;      // [NP]
 };
 
 }  // namespace
@@ -37,6 +49,7 @@ struct pc_ctx {
     int device = 0;
     int n_cu = 256;
     std::map<int, OperatorCache> ops;
+    std::map<int, HostOperator> host_ops;
     void* staging = nullptr;        // pinned host memory for descriptor tables
     size_t staging_bytes = 0;
     PcBodyDev* d_bodies = nullptr;  // device copy of the perturber table (test hooks)
@@ -45,14 +58,17 @@ struct pc_ctx {
     // completion event per stream, created on first use
     hipStream_t pl_stream[PC_MAX_STREAMS] = {};
     hipEvent_t pl_done[PC_MAX_STREAMS] = {};
+    hipEvent_t pl_poll[PC_MAX_STREAMS] = {};   // each stream's last read-back
     hipEvent_t pl_start = nullptr;
     int32_t* pl_count = nullptr;       // pinned, 16 ints per stream
     int pl_streams = 0;
     int tile_table[5] = {0, 0, 0, 0, 0}; // tuned job shape per padded node count 16..256 (0: default)
+    int list_table[5] = {0, 0, 0, 0, 0}; // tuned job length (column blocks) per padded node count (0: default)
     hipStream_t cap_stream = nullptr;  // stream used to capture HIP graphs
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     std::vector<char> graph_key;       // call signature of the captured graph
+    int64_t graph_captures = 0;        // graphs captured so far (test hook)
     bool timing = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double last_ms = -1.0;
@@ -62,6 +78,8 @@ struct pc_ctx {
 namespace {
 
 constexpr size_t kAlign = 256;
+// pinned staging allocated with every context (grown by calls that need more)
+constexpr size_t kStagingBytes = (size_t)4 << 20;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 int set_error(pc_ctx* ctx, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
@@ -81,6 +99,18 @@ int set_error(pc_ctx* ctx, int code, const char* fmt, ...)
         hipError_t e_ = (call);                                                               \
         if (e_ != hipSuccess)                                                                 \
             return set_error(ctx, PC_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));  \
+    } while (0)
+
+// The same, for calls made after work has been queued on `sq`: the stream is drained
+// first, so that no queued kernel can still write into the caller's buffers after the
+// call has returned.
+#define PC_HIP_DRAIN(ctx, sq, call)                                                           \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess) {                                                               \
+            (void)hipStreamSynchronize(sq);                                                   \
+            return set_error(ctx, PC_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));  \
+        }                                                                                     \
     } while (0)
 
 int padded_nodes(int N)
@@ -132,6 +162,98 @@ void build_operator(int N, std::vector<double>& K)
     }
 }
 
+// K2_N such that x_j = x_0 + w2 v_0 (tau_j + 1) + w2^2 sum_l K2_N[j][l] a_l for the
+// accelerations a at the nodes (the second-order form of the method): the degree N-2 fit
+// of build_operator, integrated once to the velocity series b (zero at tau = -1, constant
+// b_0 = -2 sum_k (-1)^k b_k in the half-coefficient convention) and once more to the
+// position series d_k = (b_{k-1} - b_{k+1}) / (2k), k = 1..N, pinned to zero at tau = -1.
+// Accumulated in long double, rounded once.
+void build_operator2(int N, std::vector<double>& K2)
+{
+    std::vector<long double> Tt((size_t)(N + 1) * N);   // T_k(tau_j), k = 0..N
+    for (int k = 0; k <= N; ++k)
+        for (int j = 0; j < N; ++j) Tt[(size_t)k * N + j] = cheb_at_node(k, j, N);
+    std::vector<long double> c(N + 2), b(N + 2), d(N + 2);
+    K2.assign((size_t)N * N, 0.0);
+    for (int l = 0; l < N; ++l) {
+        std::fill(c.begin(), c.end(), 0.0L);
+        std::fill(b.begin(), b.end(), 0.0L);
+        std::fill(d.begin(), d.end(), 0.0L);
+        const long double w = (l == 0 || l == N - 1) ? 0.5L : 1.0L;
+        for (int m = 0; m <= N - 2; ++m) c[m] = 2.0L / (long double)(N - 1) * w * Tt[(size_t)m * N + l];
+        long double alt = 0.0L;
+        for (int k = 1; k <= N - 1; ++k) {
+            b[k] = (c[k - 1] - c[k + 1]) / (2.0L * k);
+            alt += (k & 1) ? -b[k] : b[k];
+        }
+        b[0] = -2.0L * alt;
+        for (int k = 1; k <= N; ++k) d[k] = (b[k - 1] - b[k + 1]) / (2.0L * k);
+        for (int j = 1; j < N; ++j) {   // row 0 is exactly zero
+            long double sx = 0.0L;
+            for (int k = 1; k <= N; ++k) sx += d[k] * (Tt[(size_t)k * N + j] - ((k & 1) ? -1.0L : 1.0L));
+            K2[(size_t)j * N + l] = (double)sx;
+        }
+    }
+}
+
+// Host copies of K_N and of its fragments in the kernels' layouts, built once per N.
+const HostOperator& host_operator(pc_ctx* ctx, int N)
+{
+    auto it = ctx->host_ops.find(N);
+    if (it != ctx->host_ops.end()) return it->second;
+    HostOperator h;
+    h.N = N;
+    h.NP = padded_nodes(N);
+    build_operator(N, h.K);
+    const int NP = h.NP, NQ = NP / 4;
+    h.frag.assign((size_t)NP * NP, 0.0);
+    for (int strip = 0; strip < NP / 16; ++strip)
+        for (int q = 0; q < NQ; ++q)
+            for (int lane = 0; lane < 64; ++lane) {
+                const int row = 16 * strip + (lane & 15), col = 4 * q + (lane >> 4);
+                h.frag[((size_t)strip * NQ + q) * 64 + lane] =
+                    (row < N && col < N) ? h.K[(size_t)row * N + col] : 0.0;
+            }
+    // FP32 fragments.  frag32 has the frag order: it is the B operand of the transposed
+    // product of jobs with 16 or more ICs.  frag32p serves the node-row layout of 8-IC
+    // jobs: the f32 16x16x4 MFMA returns row 4(l/16) + r in element r, the f64 one row
+    // l/16 + 4r, and feeding A row i from strip row perm(i) = (i/4) + 4 (i%4) puts the same
+    // node in the same lane and element for both precisions.
+    h.frag32.assign((size_t)NP * NP, 0.0f);
+    for (size_t i = 0; i < h.frag.size(); ++i) h.frag32[i] = (float)h.frag[i];
+    h.frag32p.assign((size_t)NP * NP, 0.0f);
+    for (int strip = 0; strip < NP / 16; ++strip)
+        for (int q = 0; q < NQ; ++q)
+            for (int lane = 0; lane < 64; ++lane) {
+                const int i = lane & 15;
+                const int row = 16 * strip + (i / 4) + 4 * (i % 4), col = 4 * q + (lane >> 4);
+                h.frag32p[((size_t)strip * NQ + q) * 64 + lane] =
+                    (row < N && col < N) ? (float)h.K[(size_t)row * N + col] : 0.0f;
+            }
+    h.fragT.assign((size_t)NP * NP, 0.0);
+    for (int strip = 0; strip < NP / 16; ++strip)
+        for (int q = 0; q < NQ; ++q)
+            for (int lane = 0; lane < 64; ++lane) {
+                const int row = 16 * strip + (lane & 15), col = 4 * q + (lane >> 4);   // of K_N^T
+                h.fragT[((size_t)strip * NQ + q) * 64 + lane] =
+                    (row < N && col < N) ? h.K[(size_t)col * N + row] : 0.0;
+            }
+    std::vector<double> K2;
+    build_operator2(N, K2);
+    h.frag2.assign((size_t)NP * NP, 0.0);
+    for (int strip = 0; strip < NP / 16; ++strip)
+        for (int q = 0; q < NQ; ++q)
+            for (int lane = 0; lane < 64; ++lane) {
+                const int row = 16 * strip + (lane & 15), col = 4 * q + (lane >> 4);
+                h.frag2[((size_t)strip * NQ + q) * 64 + lane] =
+                    (row < N && col < N) ? K2[(size_t)row * N + col] : 0.0;
+            }
+    h.tau.assign(NP, 0.0);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int j = 0; j < N; ++j) h.tau[j] = (double)(-cosl(pi * (long double)j / (long double)(N - 1)));
+    return ctx->host_ops.emplace(N, std::move(h)).first->second;
+}
+
 int get_operator(pc_ctx* ctx, int N, const OperatorCache** out)
 {
     auto it = ctx->ops.find(N);
@@ -139,65 +261,44 @@ int get_operator(pc_ctx* ctx, int N, const OperatorCache** out)
         *out = &it->second;
         return PC_OK;
     }
+    const HostOperator& h = host_operator(ctx, N);
     OperatorCache oc;
     oc.N = N;
-    oc.NP = padded_nodes(N);
-    build_operator(N, oc.K);
-    const int NP = oc.NP, NQ = NP / 4;
-    std::vector<double> frag((size_t)NP * NP, 0.0);
-    for (int strip = 0; strip < NP / 16; ++strip)
-        for (int q = 0; q < NQ; ++q)
-            for (int lane = 0; lane < 64; ++lane) {
-                const int row = 16 * strip + (lane & 15), col = 4 * q + (lane >> 4);
-                frag[((size_t)strip * NQ + q) * 64 + lane] =
-                    (row < N && col < N) ? oc.K[(size_t)row * N + col] : 0.0;
-            }
-    // FP32 fragments.  kfrag32 has the kfrag order: it is the B operand of the transposed
-    // product of jobs with 16 or more ICs.  kfrag32p serves the node-row layout of 8-IC
-    // jobs: the f32 16x16x4 MFMA returns row 4(l/16) + r in element r, the f64 one row
-    // l/16 + 4r, and feeding A row i from strip row perm(i) = (i/4) + 4 (i%4) puts the same
-    // node in the same lane and element for both precisions.
-    std::vector<float> frag32n((size_t)NP * NP, 0.0f);
-    for (size_t i = 0; i < frag.size(); ++i) frag32n[i] = (float)frag[i];
-    std::vector<float> frag32((size_t)NP * NP, 0.0f);
-    for (int strip = 0; strip < NP / 16; ++strip)
-        for (int q = 0; q < NQ; ++q)
-            for (int lane = 0; lane < 64; ++lane) {
-                const int i = lane & 15;
-                const int row = 16 * strip + (i / 4) + 4 * (i % 4), col = 4 * q + (lane >> 4);
-                frag32[((size_t)strip * NQ + q) * 64 + lane] =
-                    (row < N && col < N) ? (float)oc.K[(size_t)row * N + col] : 0.0f;
-            }
-    std::vector<double> fragT((size_t)NP * NP, 0.0);
-    for (int strip = 0; strip < NP / 16; ++strip)
-        for (int q = 0; q < NQ; ++q)
-            for (int lane = 0; lane < 64; ++lane) {
-                const int row = 16 * strip + (lane & 15), col = 4 * q + (lane >> 4);   // of K_N^T
-                fragT[((size_t)strip * NQ + q) * 64 + lane] =
-                    (row < N && col < N) ? oc.K[(size_t)col * N + row] : 0.0;
-            }
-    std::vector<double> tau(NP, 0.0);
-    const long double pi = 3.141592653589793238462643383279502884L;
-    for (int j = 0; j < N; ++j) tau[j] = (double)(-cosl(pi * (long double)j / (long double)(N - 1)));
+    oc.NP = h.NP;
+    oc.K = h.K;
     PC_HIP(ctx, hipSetDevice(ctx->device));
-    PC_HIP(ctx, hipMalloc(&oc.kfrag, frag.size() * sizeof(double)));
-    PC_HIP(ctx, hipMalloc(&oc.tau, tau.size() * sizeof(double)));
-    PC_HIP(ctx, hipMalloc(&oc.kfragT, fragT.size() * sizeof(double)));
-    PC_HIP(ctx, hipMemcpy(oc.kfragT, fragT.data(), fragT.size() * sizeof(double), hipMemcpyHostToDevice));
-    PC_HIP(ctx, hipMalloc(&oc.kfrag32, frag32n.size() * sizeof(float)));
-    PC_HIP(ctx, hipMemcpy(oc.kfrag32, frag32n.data(), frag32n.size() * sizeof(float), hipMemcpyHostToDevice));
-    PC_HIP(ctx, hipMalloc(&oc.kfrag32p, frag32.size() * sizeof(float)));
-    PC_HIP(ctx, hipMemcpy(oc.kfrag32p, frag32.data(), frag32.size() * sizeof(float), hipMemcpyHostToDevice));
-    PC_HIP(ctx, hipMemcpy(oc.kfrag, frag.data(), frag.size() * sizeof(double), hipMemcpyHostToDevice));
-    PC_HIP(ctx, hipMemcpy(oc.tau, tau.data(), tau.size() * sizeof(double), hipMemcpyHostToDevice));
+    PC_HIP(ctx, hipMalloc(&oc.kfrag, h.frag.size() * sizeof(double)));
+    PC_HIP(ctx, hipMalloc(&oc.tau, h.tau.size() * sizeof(double)));
+    PC_HIP(ctx, hipMalloc(&oc.kfragT, h.fragT.size() * sizeof(double)));
+    PC_HIP(ctx, hipMemcpy(oc.kfragT, h.fragT.data(), h.fragT.size() * sizeof(double), hipMemcpyHostToDevice));
+    PC_HIP(ctx, hipMalloc(&oc.kfrag32, h.frag32.size() * sizeof(float)));
+    PC_HIP(ctx, hipMemcpy(oc.kfrag32, h.frag32.data(), h.frag32.size() * sizeof(float), hipMemcpyHostToDevice));
+    PC_HIP(ctx, hipMalloc(&oc.kfrag32p, h.frag32p.size() * sizeof(float)));
+    PC_HIP(ctx, hipMemcpy(oc.kfrag32p, h.frag32p.data(), h.frag32p.size() * sizeof(float), hipMemcpyHostToDevice));
+    PC_HIP(ctx, hipMemcpy(oc.kfrag, h.frag.data(), h.frag.size() * sizeof(double), hipMemcpyHostToDevice));
+    PC_HIP(ctx, hipMemcpy(oc.tau, h.tau.data(), h.tau.size() * sizeof(double), hipMemcpyHostToDevice));
+    PC_HIP(ctx, hipMalloc(&oc.kfrag2, h.frag2.size() * sizeof(double)));
+    PC_HIP(ctx, hipMemcpy(oc.kfrag2, h.frag2.data(), h.frag2.size() * sizeof(double), hipMemcpyHostToDevice));
     auto res = ctx->ops.emplace(N, std::move(oc));
     *out = &res.first->second;
     return PC_OK;
 }
 
+// A captured graph copies its tables from the staging buffer it was captured with, so a
+// reallocation of that buffer retires the graph (it is captured again on its next call).
+void drop_graph(pc_ctx* ctx)
+{
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    ctx->graph_exec = nullptr;
+    ctx->graph = nullptr;
+    ctx->graph_key.clear();
+}
+
 int ensure_staging(pc_ctx* ctx, size_t bytes)
 {
     if (bytes <= ctx->staging_bytes) return PC_OK;
+    drop_graph(ctx);
     if (ctx->staging) {
         PC_HIP(ctx, hipHostFree(ctx->staging));
         ctx->staging = nullptr;
@@ -220,6 +321,7 @@ int ensure_plain_streams(pc_ctx* ctx, int ns)
         const int t = ctx->pl_streams;
         PC_HIP(ctx, hipStreamCreateWithFlags(&ctx->pl_stream[t], hipStreamNonBlocking));
         PC_HIP(ctx, hipEventCreateWithFlags(&ctx->pl_done[t], hipEventDisableTiming));
+        PC_HIP(ctx, hipEventCreateWithFlags(&ctx->pl_poll[t], hipEventDisableTiming));
     }
     return PC_OK;
 }
@@ -284,7 +386,7 @@ struct Plan {
     std::vector<PcJobDev> jobs;
     int64_t n_recs = 0;
     int max_S = 0, max_N = 0;
-    int list = 1;                  // job ICs in units of the job's columns
+    int list = 1;                  // job ICs in units of the job's columns (untuned node counts)
     // workspace offsets
     size_t off_counters = 0, off_params = 0, off_groups = 0, off_jobs = 0, off_bodies = 0, off_recs = 0, total = 0;
     size_t off_recs_eih = 0;   // relativistic model: per-node states of the major bodies
@@ -326,6 +428,17 @@ int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, c
     plan.pairs = choose_pairs(ctx, groups, n_groups, o);
     plan.plain = (o.path == PC_PATH_PLAIN);
     if (plan.plain) plan.pairs = 2048;
+    if (o.order == 2) {
+        // second-order sweeps need blocks of 16 or more ICs (the transposed product)
+        for (int gi = 0; gi < n_groups; ++gi) {
+            const int np = padded_nodes(std::max(3, std::min((int)groups[gi].nodes, PC_MAX_NODES)));
+            if (np > 128) return set_error(ctx, PC_EINVAL, "order 2 runs with up to 128 nodes per segment");
+            if (plan.pairs / np < 16) {
+                if (o.tile_pairs == 1024) return set_error(ctx, PC_EINVAL, "order 2 with %d nodes needs tile_pairs 2048", groups[gi].nodes);
+                plan.pairs = 2048;
+            }
+        }
+    }
     std::vector<std::pair<int64_t, int64_t>> spans;
     plan.groups.clear();
     plan.jobs.clear();
@@ -389,6 +502,13 @@ int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, c
                 if (4 * span[k] <= 5 * best) list = 1 << k;
         }
     }
+    // per padded node count: the autotuner's job length where it has tuned one (automatic
+    // calls only), else the call's
+    int list_np[5];
+    for (int k = 0; k < 5; ++k) {
+        list_np[k] = list;
+        if (lists_ok && o.job_list == 0 && ctx->list_table[k] != 0) list_np[k] = ctx->list_table[k];
+    }
     plan.list = list;
     struct Cost { int np; double c; PcJobDev j; };
     std::vector<Cost> costs;
@@ -413,13 +533,14 @@ int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, c
             d.kfrag32 = oc->kfrag32;
             d.kfrag32p = oc->kfrag32p;
             d.kfragT = oc->kfragT;
+            d.kfrag2 = oc->kfrag2;
             d.tau = oc->tau;
         }
         plan.n_recs += (int64_t)G.segments * G.nodes;
         plan.groups.push_back(d);
         // cost model of one job: segments x NP x column blocks (matrix work per iteration
         // ~ NP^2 T = NP * PAIRS per block)
-        const int64_t per_job = (int64_t)list * d.T;
+        const int64_t per_job = (int64_t)list_np[log2_index(d.NP)] * d.T;
         for (int64_t i0 = 0; i0 < G.n_ic; i0 += per_job) {
             PcJobDev j{};
             j.ic0 = G.ic_offset + i0;
@@ -471,6 +592,100 @@ int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, c
     return PC_OK;
 }
 
+// Options of a forward call.
+int validate_forward(pc_ctx* ctx, const pc_opts& o, const pc_model* model)
+{
+    if (o.init != PC_INIT_KEPLER && o.init != PC_INIT_COLD && o.init != PC_INIT_GUESS)
+        return set_error(ctx, PC_EINVAL, "bad init");
+    if ((o.init == PC_INIT_GUESS) != (o.guess != nullptr))
+        return set_error(ctx, PC_EINVAL, "init PC_INIT_GUESS needs a guess buffer, and only it takes one");
+    if (o.tol_mode != PC_TOL_REL && o.tol_mode != PC_TOL_ABS) return set_error(ctx, PC_EINVAL, "bad tol_mode");
+    if (o.precision != PC_FP64 && o.precision != PC_FP32_THEN_FP64)
+        return set_error(ctx, PC_EINVAL, "unsupported precision");
+    if (o.precision == PC_FP32_THEN_FP64 && o.path != PC_PATH_FUSED)
+        return set_error(ctx, PC_EINVAL, "the FP32 -> FP64 schedule runs on the fused path");
+    if (o.path != PC_PATH_FUSED && o.path != PC_PATH_PLAIN) return set_error(ctx, PC_EINVAL, "bad path");
+    if (o.max_iter < 1 || o.max_iter > 100000) return set_error(ctx, PC_EINVAL, "max_iter out of range");
+    if (!(o.switch_tol >= 0.0) || !std::isfinite(o.switch_tol) || o.max_fp32 < 0)
+        return set_error(ctx, PC_EINVAL, "bad precision-schedule options");
+    if (o.job_list != 0 && o.job_list != 1 && o.job_list != 2 && o.job_list != 4 && o.job_list != 8)
+        return set_error(ctx, PC_EINVAL, "job_list must be 0, 1, 2, 4 or 8");
+    if (o.fixed_iters < 0 || o.fixed_iters > 100000) return set_error(ctx, PC_EINVAL, "fixed_iters out of range");
+    if (o.conv != PC_CONV_PER_IC && o.conv != PC_CONV_GROUP_MAX) return set_error(ctx, PC_EINVAL, "bad conv");
+    if (o.conv == PC_CONV_GROUP_MAX && o.path != PC_PATH_PLAIN)
+        return set_error(ctx, PC_EINVAL, "group-max convergence runs on the plain path");
+    if (o.streams < 0 || o.streams > PC_MAX_STREAMS || (o.streams > 1 && o.path != PC_PATH_PLAIN))
+        return set_error(ctx, PC_EINVAL, "streams must be 1..%d, and above 1 only on the plain path",
+                         PC_MAX_STREAMS);
+    if (model->inv_c2 > 0.0 && o.conv != PC_CONV_PER_IC)
+        return set_error(ctx, PC_EINVAL, "the relativistic model runs with the per-IC stopping rule");
+    if (o.order != 1 && o.order != 2) return set_error(ctx, PC_EINVAL, "order must be 1 or 2");
+    if (o.feedback != 0 && o.feedback != 1) return set_error(ctx, PC_EINVAL, "feedback must be 0 or 1");
+    if (o.feedback && o.order != 2) return set_error(ctx, PC_EINVAL, "feedback needs order 2");
+    if (o.feedback) return set_error(ctx, PC_EINVAL, "the integral error feedback is not on the HIP path");
+    if (o.order == 2 && (o.path != PC_PATH_FUSED || o.precision != PC_FP64 || model->inv_c2 > 0.0 ||
+                         o.conv != PC_CONV_PER_IC))
+        return set_error(ctx, PC_EINVAL, "order 2 runs on the fused FP64 path, point masses, per-IC rule");
+    return PC_OK;
+}
+
+// Stage the call's tables [counters | params | groups | jobs | bodies] in the pinned
+// staging buffer (zeroed counters and queue head, so that the one host-to-device copy of
+// this region also clears them) and describe the call for the kernels, whose tables live
+// at device address `base` (the caller's workspace).
+void stage_call(pc_ctx* ctx, const Plan& plan, const pc_model* model, const pc_opts& o, char* base,
+                const double* ics, double* states_out, int32_t* iters_out, int32_t iters_stride,
+                double* bounds_out, double* nodes_out, int32_t nodes_stride, PcEphemParams& ep, PcParams& pp)
+{
+    const bool eih = model->inv_c2 > 0.0;
+    char* st = static_cast<char*>(ctx->staging);
+    std::memset(st, 0, plan.staged);
+    std::memcpy(st + plan.off_groups, plan.groups.data(), plan.groups.size() * sizeof(PcGroupDev));
+    std::memcpy(st + plan.off_jobs, plan.jobs.data(), plan.jobs.size() * sizeof(PcJobDev));
+    prepare_bodies(model, reinterpret_cast<PcBodyDev*>(st + plan.off_bodies));
+
+    ep = PcEphemParams{};
+    ep.groups = reinterpret_cast<const PcGroupDev*>(base + plan.off_groups);
+    ep.n_groups = (int)plan.groups.size();
+    ep.n_recs = plan.n_recs;
+    ep.bodies = reinterpret_cast<const PcBodyDev*>(base + plan.off_bodies);
+    ep.n_pert = model->n_pert;
+    ep.epoch = model->epoch;
+    ep.recs = reinterpret_cast<double*>(base + plan.off_recs);
+    ep.recs_eih = eih ? reinterpret_cast<double*>(base + plan.off_recs_eih) : nullptr;
+    ep.mu_sun = model->mu_sun;
+
+    pp = PcParams{};
+    pp.groups = ep.groups;
+    pp.jobs = reinterpret_cast<const PcJobDev*>(base + plan.off_jobs);
+    pp.n_jobs = (int)plan.jobs.size();
+    pp.n_pert = model->n_pert;
+    pp.ics = ics;
+    pp.states_out = states_out;
+    pp.iters_out = iters_out;
+    pp.iters_stride = iters_stride;
+    pp.nodes_stride = nodes_stride;
+    pp.bounds_out = bounds_out;
+    pp.nodes_out = nodes_out;
+    pp.recs = ep.recs;
+    pp.mu_sun = model->mu_sun;
+    pp.recs_eih = ep.recs_eih;
+    pp.inv_c2 = eih ? model->inv_c2 : 0.0;
+    pp.max_iter = o.max_iter;
+    pp.fixed_iters = o.fixed_iters;
+    pp.tol_mode = o.tol_mode;
+    pp.conv = o.conv;
+    pp.init = o.init;
+    pp.guess = o.guess;
+    pp.precision = o.precision;
+    pp.order = o.order;
+    pp.max_fp32 = o.max_fp32 > 0 ? o.max_fp32 : 24;
+    pp.switch2 = o.switch_tol * o.switch_tol;   // 0: the kernel's default for the job's sweep kind
+    pp.counters = reinterpret_cast<int32_t*>(base + plan.off_counters);
+    pp.queue = pp.counters + 2;
+    std::memcpy(st + plan.off_params, &pp, sizeof(pp));   // the device copy the kernel reads
+}
+
 pc_opts defaults()
 {
     pc_opts o;
@@ -498,6 +713,9 @@ void pc_default_opts(pc_opts* o)
     o->job_list = 0;
     o->conv = PC_CONV_PER_IC;
     o->streams = 1;
+    o->order = 1;
+    o->feedback = 0;
+    o->guess = nullptr;
 }
 
 int pc_version(void) { return PC_VERSION; }
@@ -531,8 +749,9 @@ int pc_ctx_create(int device, pc_ctx** out)
     if (hipSetDevice(device) != hipSuccess ||
         hipMalloc(&ctx->d_bodies, PC_MAX_PERT * sizeof(PcBodyDev)) != hipSuccess ||
         hipHostMalloc(&ctx->pinned_count, 64, hipHostMallocDefault) != hipSuccess ||
-        hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) {
-        delete ctx;
+        hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+        ensure_staging(ctx, kStagingBytes) != PC_OK) {
+        pc_ctx_destroy(ctx);
         return PC_EHIP;
     }
     *out = ctx;
@@ -550,6 +769,7 @@ void pc_ctx_destroy(pc_ctx* ctx)
         (void)hipFree(kv.second.kfrag32);
         (void)hipFree(kv.second.kfrag32p);
         (void)hipFree(kv.second.kfragT);
+        (void)hipFree(kv.second.kfrag2);
     }
     if (ctx->staging) (void)hipHostFree(ctx->staging);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
@@ -559,6 +779,7 @@ void pc_ctx_destroy(pc_ctx* ctx)
     for (int t = 0; t < ctx->pl_streams; ++t) {
         if (ctx->pl_stream[t]) (void)hipStreamDestroy(ctx->pl_stream[t]);
         if (ctx->pl_done[t]) (void)hipEventDestroy(ctx->pl_done[t]);
+        if (ctx->pl_poll[t]) (void)hipEventDestroy(ctx->pl_poll[t]);
     }
     if (ctx->pl_start) (void)hipEventDestroy(ctx->pl_start);
     if (ctx->pl_count) (void)hipHostFree(ctx->pl_count);
@@ -597,89 +818,34 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_
     int rc = validate_model(ctx, model);
     if (rc != PC_OK) return rc;
     const pc_opts o = opts ? *opts : defaults();
-    if (o.init != PC_INIT_KEPLER && o.init != PC_INIT_COLD) return set_error(ctx, PC_EINVAL, "bad init");
-    if (o.tol_mode != PC_TOL_REL && o.tol_mode != PC_TOL_ABS) return set_error(ctx, PC_EINVAL, "bad tol_mode");
-    if (o.precision != PC_FP64 && o.precision != PC_FP32_THEN_FP64)
-        return set_error(ctx, PC_EINVAL, "unsupported precision");
-    if (o.precision == PC_FP32_THEN_FP64 && o.path != PC_PATH_FUSED)
-        return set_error(ctx, PC_EINVAL, "the FP32 -> FP64 schedule runs on the fused path");
-    if (o.path != PC_PATH_FUSED && o.path != PC_PATH_PLAIN) return set_error(ctx, PC_EINVAL, "bad path");
-    if (o.max_iter < 1 || o.max_iter > 100000) return set_error(ctx, PC_EINVAL, "max_iter out of range");
-    if (!(o.switch_tol >= 0.0) || !std::isfinite(o.switch_tol) || o.max_fp32 < 0)
-        return set_error(ctx, PC_EINVAL, "bad precision-schedule options");
-    if (o.job_list != 0 && o.job_list != 1 && o.job_list != 2 && o.job_list != 4 && o.job_list != 8)
-        return set_error(ctx, PC_EINVAL, "job_list must be 0, 1, 2, 4 or 8");
-    if (o.fixed_iters < 0 || o.fixed_iters > 100000) return set_error(ctx, PC_EINVAL, "fixed_iters out of range");
-    if (o.conv != PC_CONV_PER_IC && o.conv != PC_CONV_GROUP_MAX) return set_error(ctx, PC_EINVAL, "bad conv");
-    if (o.conv == PC_CONV_GROUP_MAX && o.path != PC_PATH_PLAIN)
-        return set_error(ctx, PC_EINVAL, "group-max convergence runs on the plain path");
-    if (o.streams < 0 || o.streams > PC_MAX_STREAMS || (o.streams > 1 && o.path != PC_PATH_PLAIN))
-        return set_error(ctx, PC_EINVAL, "streams must be 1..%d, and above 1 only on the plain path",
-                         PC_MAX_STREAMS);
+    rc = validate_forward(ctx, o, model);
+    if (rc != PC_OK) return rc;
     const bool eih = model->inv_c2 > 0.0;
-    if (eih && o.conv != PC_CONV_PER_IC)
-        return set_error(ctx, PC_EINVAL, "the relativistic model runs with the per-IC stopping rule");
     PC_HIP(ctx, hipSetDevice(ctx->device));
     Plan plan;
     rc = make_plan(ctx, n_ic, groups, n_groups, model, o, true, plan,
-                   o.path == PC_PATH_FUSED && o.precision == PC_FP64 && !eih);
+                   o.path == PC_PATH_FUSED && o.precision == PC_FP64 && !eih && o.order == 1 &&
+                   o.init != PC_INIT_GUESS);
     if (rc != PC_OK) return rc;
     if ((iters_out || bounds_out || nodes_out) && iters_stride < plan.max_S)
         return set_error(ctx, PC_EINVAL, "iters_stride %d < %d segments", iters_stride, plan.max_S);
-    if (nodes_out && nodes_stride < plan.max_N)
+    if ((nodes_out || o.guess) && nodes_stride < plan.max_N)
         return set_error(ctx, PC_EINVAL, "nodes_stride %d < %d nodes", nodes_stride, plan.max_N);
+    if (o.guess && iters_stride < plan.max_S)
+        return set_error(ctx, PC_EINVAL, "iters_stride %d < %d segments", iters_stride, plan.max_S);
     if (!workspace || ws_bytes < plan.total)
         return set_error(ctx, PC_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, plan.total);
 
-    // stage [counters | groups | jobs | bodies] and copy them in one transfer
+    // stage [counters | params | groups | jobs | bodies] and copy them in one transfer
     rc = ensure_staging(ctx, plan.staged + kAlign);
     if (rc != PC_OK) return rc;
     char* st = static_cast<char*>(ctx->staging);
-    std::memset(st, 0, plan.staged);
-    std::memcpy(st + plan.off_groups, plan.groups.data(), plan.groups.size() * sizeof(PcGroupDev));
-    std::memcpy(st + plan.off_jobs, plan.jobs.data(), plan.jobs.size() * sizeof(PcJobDev));
-    prepare_bodies(model, reinterpret_cast<PcBodyDev*>(st + plan.off_bodies));
     char* ws = static_cast<char*>(workspace);
     hipStream_t hs = (hipStream_t)stream;
-
-    PcEphemParams ep{};
-    ep.groups = reinterpret_cast<const PcGroupDev*>(ws + plan.off_groups);
-    ep.n_groups = (int)plan.groups.size();
-    ep.n_recs = plan.n_recs;
-    ep.bodies = reinterpret_cast<const PcBodyDev*>(ws + plan.off_bodies);
-    ep.n_pert = model->n_pert;
-    ep.epoch = model->epoch;
-    ep.recs = reinterpret_cast<double*>(ws + plan.off_recs);
-    ep.recs_eih = eih ? reinterpret_cast<double*>(ws + plan.off_recs_eih) : nullptr;
-    ep.mu_sun = model->mu_sun;
-
-    PcParams pp{};
-    pp.groups = ep.groups;
-    pp.jobs = reinterpret_cast<const PcJobDev*>(ws + plan.off_jobs);
-    pp.n_jobs = (int)plan.jobs.size();
-    pp.n_pert = model->n_pert;
-    pp.ics = ics;
-    pp.states_out = states_out;
-    pp.iters_out = iters_out;
-    pp.iters_stride = iters_stride;
-    pp.nodes_stride = nodes_stride;
-    pp.bounds_out = bounds_out;
-    pp.nodes_out = nodes_out;
-    pp.recs = ep.recs;
-    pp.mu_sun = model->mu_sun;
-    pp.recs_eih = ep.recs_eih;
-    pp.inv_c2 = eih ? model->inv_c2 : 0.0;
-    pp.max_iter = o.max_iter;
-    pp.fixed_iters = o.fixed_iters;
-    pp.tol_mode = o.tol_mode;
-    pp.conv = o.conv;
-    pp.init = o.init;
-    pp.precision = o.precision;
-    pp.max_fp32 = o.max_fp32 > 0 ? o.max_fp32 : 24;
-    pp.switch2 = o.switch_tol * o.switch_tol;   // 0: the kernel's default for the job's sweep kind
-    pp.counters = reinterpret_cast<int32_t*>(ws + plan.off_counters);
-    pp.queue = pp.counters + 2;
-    std::memcpy(st + plan.off_params, &pp, sizeof(pp));   // the device copy the kernel reads
+    PcEphemParams ep;
+    PcParams pp;
+    stage_call(ctx, plan, model, o, ws, ics, states_out, iters_out, iters_stride, bounds_out, nodes_out,
+               nodes_stride, ep, pp);
     const PcParams* pp_dev = reinterpret_cast<const PcParams*>(ws + plan.off_params);
     int32_t* hc = reinterpret_cast<int32_t*>(st);   // staging is free again once the copy has run
 
@@ -701,9 +867,9 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_
     };
 
     if (plan.plain) {
-        PC_HIP(ctx, hipMemcpyAsync(ws, st, plan.staged, hipMemcpyHostToDevice, hs));
-        PC_HIP(ctx, (hipError_t)pc_launch_ephem(ep, hs));
-        if (ctx->timing) PC_HIP(ctx, hipEventRecord(ctx->ev0, hs));
+        PC_HIP_DRAIN(ctx, hs, hipMemcpyAsync(ws, st, plan.staged, hipMemcpyHostToDevice, hs));
+        PC_HIP_DRAIN(ctx, hs, (hipError_t)pc_launch_ephem(ep, hs));
+        if (ctx->timing) PC_HIP_DRAIN(ctx, hs, hipEventRecord(ctx->ev0, hs));
         // one group at a time, kernels per iteration, host loop (the structure of Sec. 5.4)
         auto plain_args = [&](int gi) {
             PcPlainArgs a{};
@@ -722,51 +888,84 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_
         const int ns = plan.plain_streams;
         if (ns <= 1) {
             for (int gi = 0; gi < n_groups; ++gi)
-                PC_HIP(ctx, (hipError_t)pc_run_plain(plain_args(gi), ws + plan.off_plain, ctx->pinned_count, stream));
+                PC_HIP_DRAIN(ctx, hs, (hipError_t)pc_run_plain(plain_args(gi), ws + plan.off_plain, ctx->pinned_count, stream));
         } else {
-            // the outer level on ns streams: group gi on stream gi % ns, each stream driven by
-            // its own host thread (its per-iteration read-back waits on that stream only);
-            // the streams start after the work queued so far and the caller's stream waits
-            // for all of them
+            // the outer level on ns streams: group gi on stream gi % ns.  The calling thread
+            // drives every stream: it polls each stream's last read-back with an event and
+            // takes that stream's next loop decision when it has landed, so the streams' host
+            // round trips overlap without any thread of ours but this one launching work.
+            // The streams start after the work queued so far; the caller's stream waits for
+            // all of them.
             rc = ensure_plain_streams(ctx, ns);
-            if (rc != PC_OK) return rc;
-            PC_HIP(ctx, hipEventRecord(ctx->pl_start, hs));
-            std::vector<hipError_t> errs(ns, hipErrorNotReady);   // a worker that never ran stays failed
-            std::vector<std::thread> workers;
-            workers.reserve(ns);
-            for (int t = 0; t < ns; ++t) {
-                auto body = [&, t] {
-                    hipError_t e = hipSetDevice(ctx->device);
-                    if (e == hipSuccess) e = hipStreamWaitEvent(ctx->pl_stream[t], ctx->pl_start, 0);
-                    for (int gi = t; gi < n_groups && e == hipSuccess; gi += ns)
-                        e = (hipError_t)pc_run_plain(plain_args(gi), ws + plan.off_plain + t * plan.plain_stride,
-                                                     ctx->pl_count + 16 * t, ctx->pl_stream[t]);
-                    if (e == hipSuccess) e = hipEventRecord(ctx->pl_done[t], ctx->pl_stream[t]);
-                    errs[t] = e;
-                };
-                try {
-                    workers.emplace_back(body);
-                } catch (...) {   // no thread: no exception may cross the C ABI
-                    break;
+            if (rc != PC_OK) {
+                (void)hipStreamSynchronize(hs);
+                return rc;
+            }
+            PC_HIP_DRAIN(ctx, hs, hipEventRecord(ctx->pl_start, hs));
+            std::vector<PcPlainRun> runs(ns);
+            std::vector<int> next(ns);      // next group of each stream
+            std::vector<char> busy(ns, 0);
+            hipError_t e = hipSuccess;
+            auto drain = [&] {   // let every stream finish before the caller can free its buffers
+                for (int t = 0; t < ns; ++t) (void)hipStreamSynchronize(ctx->pl_stream[t]);
+            };
+            for (int t = 0; t < ns && e == hipSuccess; ++t) {
+                next[t] = t + ns;
+                e = hipStreamWaitEvent(ctx->pl_stream[t], ctx->pl_start, 0);
+                if (e == hipSuccess && t < n_groups) {
+                    e = (hipError_t)pc_plain_begin(runs[t], plain_args(t), ws + plan.off_plain + t * plan.plain_stride,
+                                                   ctx->pl_count + 16 * t, ctx->pl_stream[t]);
+                    if (e == hipSuccess) e = hipEventRecord(ctx->pl_poll[t], ctx->pl_stream[t]);
+                    busy[t] = 1;
                 }
             }
-            for (auto& w : workers) w.join();
-            bool failed = false;
-            for (int t = 0; t < ns; ++t) failed = failed || errs[t] != hipSuccess;
-            if (failed)   // let the other streams drain before the caller can free its buffers
-                for (int t = 0; t < ns; ++t) (void)hipStreamSynchronize(ctx->pl_stream[t]);
-            for (int t = 0; t < ns; ++t) PC_HIP(ctx, errs[t]);
-            for (int t = 0; t < ns; ++t) PC_HIP(ctx, hipStreamWaitEvent(hs, ctx->pl_done[t], 0));
+            int running = 0;
+            for (int t = 0; t < ns; ++t) running += busy[t];
+            while (e == hipSuccess && running > 0) {
+                bool moved = false;
+                for (int t = 0; t < ns && e == hipSuccess; ++t) {
+                    if (!busy[t]) continue;
+                    const hipError_t q = hipEventQuery(ctx->pl_poll[t]);
+                    if (q == hipErrorNotReady) continue;
+                    if (q != hipSuccess) {
+                        e = q;
+                        break;
+                    }
+                    moved = true;
+                    e = (hipError_t)pc_plain_advance(runs[t]);
+                    if (e == hipSuccess && runs[t].done) {
+                        if (next[t] < n_groups) {
+                            const int gi = next[t];
+                            next[t] += ns;
+                            e = (hipError_t)pc_plain_begin(runs[t], plain_args(gi),
+                                                           ws + plan.off_plain + t * plan.plain_stride,
+                                                           ctx->pl_count + 16 * t, ctx->pl_stream[t]);
+                        } else {
+                            busy[t] = 0;
+                            --running;
+                        }
+                    }
+                    if (e == hipSuccess && busy[t]) e = hipEventRecord(ctx->pl_poll[t], ctx->pl_stream[t]);
+                }
+                if (!moved) std::this_thread::yield();
+            }
+            for (int t = 0; t < ns && e == hipSuccess; ++t) e = hipEventRecord(ctx->pl_done[t], ctx->pl_stream[t]);
+            if (e != hipSuccess) {
+                drain();
+                (void)hipStreamSynchronize(hs);
+                return set_error(ctx, PC_EHIP, "plain path on %d streams: %s", ns, hipGetErrorString(e));
+            }
+            for (int t = 0; t < ns; ++t) PC_HIP_DRAIN(ctx, hs, hipStreamWaitEvent(hs, ctx->pl_done[t], 0));
         }
-        if (ctx->timing) PC_HIP(ctx, hipEventRecord(ctx->ev1, hs));
-        PC_HIP(ctx, hipMemcpyAsync(hc, pp.counters, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, hs));
+        if (ctx->timing) PC_HIP_DRAIN(ctx, hs, hipEventRecord(ctx->ev1, hs));
+        PC_HIP_DRAIN(ctx, hs, hipMemcpyAsync(hc, pp.counters, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, hs));
     } else if (o.graph) {
         // signature of the call: a captured graph is replayed only for the same one
         std::vector<char> key;
         auto put = [&key](const void* q, size_t nb) {
             key.insert(key.end(), static_cast<const char*>(q), static_cast<const char*>(q) + nb);
         };
-        const void* ptrs[7] = {ics, states_out, iters_out, bounds_out, nodes_out, workspace, stream};
+        const void* ptrs[8] = {ics, states_out, iters_out, bounds_out, nodes_out, workspace, stream, ctx->staging};
         put(ptrs, sizeof(ptrs));
         put(&n_ic, sizeof(n_ic));
         put(&n_groups, sizeof(n_groups));
@@ -782,11 +981,7 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_
         put(&ws_bytes, sizeof(ws_bytes));
         put(&plan.pairs, sizeof(plan.pairs));
         if (!ctx->graph_exec || key != ctx->graph_key) {
-            if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
-            if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
-            ctx->graph_exec = nullptr;
-            ctx->graph = nullptr;
-            ctx->graph_key.clear();
+            drop_graph(ctx);
             PC_HIP(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
             const hipError_t e = enqueue_fused(ctx->cap_stream, false);
             hipGraph_t gr = nullptr;
@@ -799,13 +994,14 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_
             ctx->graph = gr;
             PC_HIP(ctx, hipGraphInstantiate(&ctx->graph_exec, ctx->graph, nullptr, nullptr, 0));
             ctx->graph_key = key;
+            ++ctx->graph_captures;
         }
         // the whole graph is timed in graph mode (copies and ephemeris included)
-        if (ctx->timing) PC_HIP(ctx, hipEventRecord(ctx->ev0, hs));
-        PC_HIP(ctx, hipGraphLaunch(ctx->graph_exec, hs));
-        if (ctx->timing) PC_HIP(ctx, hipEventRecord(ctx->ev1, hs));
+        if (ctx->timing) PC_HIP_DRAIN(ctx, hs, hipEventRecord(ctx->ev0, hs));
+        PC_HIP_DRAIN(ctx, hs, hipGraphLaunch(ctx->graph_exec, hs));
+        if (ctx->timing) PC_HIP_DRAIN(ctx, hs, hipEventRecord(ctx->ev1, hs));
     } else {
-        PC_HIP(ctx, enqueue_fused(hs, ctx->timing));
+        PC_HIP_DRAIN(ctx, hs, enqueue_fused(hs, ctx->timing));
     }
     PC_HIP(ctx, hipStreamSynchronize(hs));
     if (ctx->timing) {
@@ -833,6 +1029,22 @@ int pc_propagate(pc_ctx* ctx, const double* ics, int64_t n_ic, double t0, double
     g.tol = tol;
     return pc_propagate_batched(ctx, ics, n_ic, &g, 1, model, opts, states_out, iters_out, segments,
                                 nullptr, nullptr, 0, workspace, ws_bytes, stream);
+}
+
+int pc_measure_ceilings(pc_ctx* ctx, void* buf, size_t buf_bytes, pc_stream_t stream, double* out)
+{
+    if (!ctx || !buf || !out) return PC_EINVAL;
+    if (buf_bytes < ((size_t)16 << 20)) return set_error(ctx, PC_EINVAL, "buf_bytes must be at least 16 MiB");
+    PC_HIP(ctx, hipSetDevice(ctx->device));
+    PC_HIP_DRAIN(ctx, (hipStream_t)stream, (hipError_t)pc_ceilings_run(ctx->n_cu, buf, buf_bytes, stream, out));
+    return PC_OK;
+}
+
+int pc_graph_captures(pc_ctx* ctx, int64_t* count)
+{
+    if (!ctx || !count) return PC_EINVAL;
+    *count = ctx->graph_captures;
+    return PC_OK;
 }
 
 int pc_set_timing(pc_ctx* ctx, int enable)
@@ -874,6 +1086,8 @@ int pc_adjoint(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int32_t n_grou
         return set_error(ctx, PC_EINVAL, "the adjoint re-solves segments on the fused FP64 path");
     if (o.conv != PC_CONV_PER_IC)
         return set_error(ctx, PC_EINVAL, "the adjoint linearises the map converged per IC");
+    if (o.order != 1) return set_error(ctx, PC_EINVAL, "the adjoint linearises the first-order map");
+    if (o.init == PC_INIT_GUESS) return set_error(ctx, PC_EINVAL, "the adjoint re-solves with a warm or cold start");
     if (o.init != PC_INIT_KEPLER && o.init != PC_INIT_COLD) return set_error(ctx, PC_EINVAL, "bad init");
     if (o.max_iter < 1 || o.max_iter > 100000 || o.fixed_iters < 0) return set_error(ctx, PC_EINVAL, "bad iterations");
     if (!(adj_tol > 0.0) || !std::isfinite(adj_tol) || adj_max_iter < 2 || adj_max_iter > 100000)
@@ -936,13 +1150,13 @@ int pc_adjoint(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int32_t n_grou
     a.counters = reinterpret_cast<int32_t*>(ws + plan.off_counters);
     std::memcpy(st + plan.off_params, &a, sizeof(a));   // the device copy the kernel reads
     const PcAdjParams* a_dev = reinterpret_cast<const PcAdjParams*>(ws + plan.off_params);
-    PC_HIP(ctx, hipMemcpyAsync(ws, st, plan.staged, hipMemcpyHostToDevice, hs));
-    PC_HIP(ctx, (hipError_t)pc_launch_ephem(ep, hs));
-    if (ctx->timing) PC_HIP(ctx, hipEventRecord(ctx->ev0, hs));
-    PC_HIP(ctx, (hipError_t)pc_launch_adjoint(a, a_dev, ctx->n_cu, hs));
-    if (ctx->timing) PC_HIP(ctx, hipEventRecord(ctx->ev1, hs));
+    PC_HIP_DRAIN(ctx, hs, hipMemcpyAsync(ws, st, plan.staged, hipMemcpyHostToDevice, hs));
+    PC_HIP_DRAIN(ctx, hs, (hipError_t)pc_launch_ephem(ep, hs));
+    if (ctx->timing) PC_HIP_DRAIN(ctx, hs, hipEventRecord(ctx->ev0, hs));
+    PC_HIP_DRAIN(ctx, hs, (hipError_t)pc_launch_adjoint(a, a_dev, ctx->n_cu, hs));
+    if (ctx->timing) PC_HIP_DRAIN(ctx, hs, hipEventRecord(ctx->ev1, hs));
     int32_t* hc = reinterpret_cast<int32_t*>(st);
-    PC_HIP(ctx, hipMemcpyAsync(hc, a.counters, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, hs));
+    PC_HIP_DRAIN(ctx, hs, hipMemcpyAsync(hc, a.counters, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, hs));
     PC_HIP(ctx, hipStreamSynchronize(hs));
     if (ctx->timing) {
         float ms = 0.0f;
@@ -974,49 +1188,118 @@ int pc_get_tile_pairs(pc_ctx* ctx, int32_t padded_nodes, int32_t* pairs)
     return PC_OK;
 }
 
+int pc_set_job_list(pc_ctx* ctx, int32_t padded_nodes, int32_t blocks)
+{
+    if (!ctx) return PC_EINVAL;
+    if (padded_nodes < 16 || padded_nodes > 256 || (padded_nodes & (padded_nodes - 1)))
+        return set_error(ctx, PC_EINVAL, "padded_nodes must be 16, 32, 64, 128 or 256");
+    if (blocks != 0 && blocks != 1 && blocks != 2 && blocks != 4 && blocks != 8)
+        return set_error(ctx, PC_EINVAL, "blocks must be 0, 1, 2, 4 or 8");
+    ctx->list_table[log2_index(padded_nodes)] = blocks;
+    return PC_OK;
+}
+
+int pc_get_job_list(pc_ctx* ctx, int32_t padded_nodes, int32_t* blocks)
+{
+    if (!ctx || !blocks) return PC_EINVAL;
+    if (padded_nodes < 16 || padded_nodes > 256 || (padded_nodes & (padded_nodes - 1)))
+        return set_error(ctx, PC_EINVAL, "padded_nodes must be 16, 32, 64, 128 or 256");
+    *blocks = ctx->list_table[log2_index(padded_nodes)];
+    return PC_OK;
+}
+
 int pc_autotune(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_group* groups, int32_t n_groups,
                 const pc_model* model, double* scratch_states, void* workspace, size_t ws_bytes,
                 pc_stream_t stream, int32_t* chosen_pairs)
 {
     if (!ctx || !groups || n_groups < 1 || !scratch_states || !chosen_pairs) return PC_EINVAL;
     int np_max = 16;
-    std::vector<pc_group> probe(groups, groups + n_groups);
-    for (auto& g : probe) {
-        np_max = std::max(np_max, padded_nodes(g.nodes));
-        if (g.segments < 1) return set_error(ctx, PC_EINVAL, "segments < 1");
-        g.tf = g.t0 + (g.tf - g.t0) / g.segments;   // first segment only
-        g.segments = 1;
+    bool present[5] = {false, false, false, false, false};
+    for (int i = 0; i < n_groups; ++i) {
+        const int np = padded_nodes(std::max(3, std::min((int)groups[i].nodes, PC_MAX_NODES)));
+        np_max = std::max(np_max, np);
+        present[log2_index(np)] = true;
     }
-    std::vector<int> cands = {2048};
-    if (np_max * 8 <= 1024) cands.push_back(1024);
+    const int kmax = log2_index(np_max);
+    // start from the untuned rules: tables cleared for the batch's node counts
+    int tile_saved = ctx->tile_table[kmax], list_saved[5];
+    for (int k = 0; k < 5; ++k) list_saved[k] = ctx->list_table[k];
+    auto restore = [&] {
+        ctx->tile_table[kmax] = tile_saved;
+        for (int k = 0; k < 5; ++k) ctx->list_table[k] = list_saved[k];
+    };
+    ctx->tile_table[kmax] = 0;
+    for (int k = 0; k < 5; ++k)
+        if (present[k]) ctx->list_table[k] = 0;
     const bool was_timing = ctx->timing;
     int rc = pc_set_timing(ctx, 1);
-    if (rc != PC_OK) return rc;
-    int best = 2048;
-    double best_ms = 1e300;
-    for (int c : cands) {
-        pc_opts o;
-        pc_default_opts(&o);
-        o.tile_pairs = c;
-        o.fixed_iters = 2;
-        double ms = 0.0;
-        for (int rep = 0; rep < 2; ++rep) {   // the second run is timed
-            rc = pc_propagate_batched(ctx, ics, n_ic, probe.data(), n_groups, model, &o, scratch_states,
-                                      nullptr, 0, nullptr, nullptr, 0, workspace, ws_bytes, stream);
-            if (rc != PC_OK && rc != PC_ENOTCONV && rc != PC_ENONFINITE) {
-                ctx->timing = was_timing;
-                return rc;
-            }
-            ms = ctx->last_ms;
+    if (rc != PC_OK) {
+        restore();
+        return rc;
+    }
+    pc_opts o;
+    pc_default_opts(&o);
+    // median kernel time of three runs of the caller's batch under the current tables
+    auto measure = [&](double* ms) -> int {
+        double t[3];
+        for (int rep = 0; rep < 3; ++rep) {
+            const int r = pc_propagate_batched(ctx, ics, n_ic, groups, n_groups, model, &o, scratch_states, nullptr,
+                                               0, nullptr, nullptr, 0, workspace, ws_bytes, stream);
+            if (r != PC_OK && r != PC_ENOTCONV && r != PC_ENONFINITE) return r;
+            t[rep] = ctx->last_ms;
         }
+        std::sort(t, t + 3);
+        *ms = t[1];
+        return PC_OK;
+    };
+    auto fail = [&](int r) {
+        ctx->timing = was_timing;
+        restore();
+        return r;
+    };
+    // one untimed run (operators, staging), then the untuned rules as the first incumbent
+    rc = pc_propagate_batched(ctx, ics, n_ic, groups, n_groups, model, &o, scratch_states, nullptr, 0, nullptr,
+                              nullptr, 0, workspace, ws_bytes, stream);
+    if (rc != PC_OK && rc != PC_ENOTCONV && rc != PC_ENONFINITE) return fail(rc);
+    double best_ms = 0.0, ms = 0.0;
+    if ((rc = measure(&best_ms)) != PC_OK) return fail(rc);
+    int best_pairs = 0;   // 0: the untuned shape rule
+    // the job shape of the call (one per launch): the 1024-pair shape only fits up to 128
+    // padded nodes
+    const int cands[2] = {2048, 1024};
+    for (int c : cands) {
+        if (c == 1024 && np_max * 8 > 1024) continue;
+        ctx->tile_table[kmax] = c;
+        if ((rc = measure(&ms)) != PC_OK) return fail(rc);
         if (ms < best_ms) {
             best_ms = ms;
-            best = c;
+            best_pairs = c;
         }
     }
+    ctx->tile_table[kmax] = best_pairs;
+    // then the job length of each node count, largest first, the others held at their best
+    for (int k = 4; k >= 0; --k) {
+        if (!present[k]) continue;
+        int best_list = 0;   // 0: the untuned rule
+        for (int m : {1, 2, 4, 8}) {
+            ctx->list_table[k] = m;
+            if ((rc = measure(&ms)) != PC_OK) return fail(rc);
+            if (ms < best_ms) {
+                best_ms = ms;
+                best_list = m;
+            }
+        }
+        ctx->list_table[k] = best_list;
+    }
     ctx->timing = was_timing;
-    ctx->tile_table[log2_index(np_max)] = best;
-    *chosen_pairs = best;
+    int pairs = best_pairs;
+    if (pairs == 0) {   // record the shape the untuned rule picked
+        pc_opts d;
+        pc_default_opts(&d);
+        pairs = choose_pairs(ctx, groups, n_groups, d);
+    }
+    ctx->tile_table[kmax] = pairs;
+    *chosen_pairs = pairs;
     return PC_OK;
 }
 
@@ -1040,7 +1323,7 @@ int pc_apply_operator(pc_ctx* ctx, int32_t nodes, int64_t n_cols, const double* 
     const OperatorCache* oc = nullptr;
     int rc = get_operator(ctx, nodes, &oc);
     if (rc != PC_OK) return rc;
-    PC_HIP(ctx, (hipError_t)pc_launch_apply_operator(oc->NP, oc->kfrag, nodes, n_cols, F, y0, scale, Y, stream));
+    PC_HIP_DRAIN(ctx, (hipStream_t)stream, (hipError_t)pc_launch_apply_operator(oc->NP, oc->kfrag, nodes, n_cols, F, y0, scale, Y, stream));
     PC_HIP(ctx, hipStreamSynchronize((hipStream_t)stream));
     return PC_OK;
 }
@@ -1059,9 +1342,9 @@ int pc_eval_force(pc_ctx* ctx, const double* r, const double* t, int64_t n, cons
     prepare_bodies(model, static_cast<PcBodyDev*>(ctx->staging));
     hipStream_t hs = (hipStream_t)stream;
     if (model->n_pert > 0)
-        PC_HIP(ctx, hipMemcpyAsync(ctx->d_bodies, ctx->staging, model->n_pert * sizeof(PcBodyDev),
+        PC_HIP_DRAIN(ctx, hs, hipMemcpyAsync(ctx->d_bodies, ctx->staging, model->n_pert * sizeof(PcBodyDev),
                                    hipMemcpyHostToDevice, hs));
-    PC_HIP(ctx, (hipError_t)pc_launch_eval_force(r, t, n, ctx->d_bodies, model->n_pert, model->epoch,
+    PC_HIP_DRAIN(ctx, hs, (hipError_t)pc_launch_eval_force(r, t, n, ctx->d_bodies, model->n_pert, model->epoch,
                                                  model->mu_sun, a_out, stream));
     PC_HIP(ctx, hipStreamSynchronize(hs));
     return PC_OK;
@@ -1072,7 +1355,7 @@ int pc_eval_kepler(pc_ctx* ctx, const double* y0, const double* dt, int64_t n, d
 {
     if (!ctx || !y0 || !dt || !y || !ok || n < 1) return PC_EINVAL;
     PC_HIP(ctx, hipSetDevice(ctx->device));
-    PC_HIP(ctx, (hipError_t)pc_launch_eval_kepler(y0, dt, n, y, ok, stream));
+    PC_HIP_DRAIN(ctx, (hipStream_t)stream, (hipError_t)pc_launch_eval_kepler(y0, dt, n, y, ok, stream));
     PC_HIP(ctx, hipStreamSynchronize((hipStream_t)stream));
     return PC_OK;
 }

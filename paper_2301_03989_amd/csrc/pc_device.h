@@ -889,6 +889,53 @@ static __device__ __forceinline__ int pc_product(const double* sF, const double*
     return flag;
 }
 
+// Second-order sweep (WIDE shapes): the velocity and the position both come from the
+// acceleration columns of F (comps 3..5), v_new = v0 + w2 K_N a and
+// x_new = x0 + w2 v0 (tau_j + 1) + w2^2 K2_N a, with K2_N the double-integration operator
+// (the degree N-2 fit integrated twice, zero value and slope at tau = -1).  Per k step a
+// lane loads the two operators' fragments (kp1: K_N, kp2: K2_N) and three F values, and
+// issues six MFMAs, as the first-order product does.  tp1 = tau_j + 1 of the lane's node.
+// Flags as pc_product.
+template <int PAIRS, int NP>
+static __device__ __forceinline__ int pc_product2(const double* sF, const double* sY0, gconst_dp kp1,
+                                                   gconst_dp kp2, const double (&kpre)[8],
+                                                   const double (&yc)[6][4], f64x4 (&acc)[6], double w2,
+                                                   double tp1, const PcTol& tl, int N, const PcLane& L)
+{
+    using Sh = PcShape<PAIRS, NP>;
+    static_assert(Sh::WIDE, "second-order sweeps run on WIDE job shapes");
+    constexpr int T = Sh::T, ROW = Sh::ROW, NQ = Sh::NQ;
+    const int lane = L.lane;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) acc[b] = f64x4{0.0, 0.0, 0.0, 0.0};
+    const double* bp[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        bp[u] = sF + (lane >> 4) * ROW + L.grp * 16 + ((lane & 15) ^ ((4 * u + (lane >> 4)) & 15));
+    pc_kloop<NQ, 3, PcPairD, double, 3, 6, 2>(
+        [&](int u) { return PcPairD{kpre[u], kpre[4 + u]}; },
+        [&](int q) { return PcPairD{kp1[q * 64], kp2[q * 64]}; },
+        [&](int q, int u, double (&bq)[3]) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) bq[c] = bp[u][q * 4 * ROW + (3 + c) * T];
+        },
+        [&](const PcPairD& ka, const double (&bq)[3]) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[c] = mfma16(bq[c], ka.a1, acc[c]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[3 + c] = mfma16(bq[c], ka.a0, acc[3 + c]);
+        });
+    // position: x0 + w2 v0 (tau + 1) + w2^2 acc; the common epilogue adds w2 * acc to
+    // its base, so the position blocks become w2 acc + v0 (tau + 1) first
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int m = pc_ic(L, r);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[c][r] = fma(w2, acc[c][r], tp1 * sY0[(3 + c) * T + m]);
+    }
+    return pc_wide_epilogue<PAIRS, NP, false, false>(sY0, yc, acc, w2, tl, N, L);
+}
+
 // acc = K_N^T mu for the lane's six blocks (WIDE shapes, transposed like pc_product): the
 // adjoint product, mu published in sF as [node][comp 6][IC] and kpT the lane's strip of
 // K_N^T fragments.

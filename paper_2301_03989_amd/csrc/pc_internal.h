@@ -29,6 +29,7 @@ struct PcGroupDev {
     const float* kfrag32;      // FP32 copy in the same fragment order
     const float* kfrag32p;     // FP32 copy, rows permuted for the f32 MFMA result layout
     const double* kfragT;      // fragments of K_N^T (adjoint)
+    const double* kfrag2;      // fragments of the double-integration operator K2_N (second order)
     const double* tau;         // [NP] CGL nodes, zero past N
     int32_t N, NP, T, S;
 };
@@ -64,9 +65,11 @@ struct PcParams {
     double inv_c2;              // 1/c^2 of the relativistic model (0: point masses)
     double mu_sun;
     int32_t max_iter, fixed_iters, tol_mode, init;
+    const double* guess;        // init 2: [n_ic][iters_stride][nodes_stride][6] initial node states
     int32_t precision;          // 0 FP64; 1 FP32 sweeps, then FP64
     int32_t max_fp32;           // cap on FP32 sweeps per segment
     int32_t conv;               // PC_CONV_PER_IC or PC_CONV_GROUP_MAX (plain path only)
+    int32_t order;              // 1: first-order sweeps; 2: second-order sweeps (WIDE shapes)
     double switch2;             // squared relative change below which a job leaves FP32
     int32_t* counters;          // [0] ICs with a not-converged segment, [1] non-finite ICs
     int32_t* queue;             // next job of the persistent kernel (starts at 0)
@@ -115,3 +118,6 @@ int pc_launch_eval_force(const double* r, const double* t, int64_t n, const PcBo
                          int n_pert, double epoch, double mu_sun, double* a, void* stream);
 int pc_launch_eval_kepler(const double* y0, const double* dt, int64_t n, double* y, int32_t* ok,
                           void* stream);
+// On-chip ceilings (pc_ceilings.hip): out[0] FP64 matrix-core TFLOP/s, out[1] FP64 vector FMA
+// TFLOP/s, out[2] device copy GB/s (bytes read + written).  buf: device scratch of buf_bytes.
+int pc_ceilings_run(int n_cu, void* buf, size_t buf_bytes, void* stream, double* out);

@@ -130,7 +130,7 @@ static __device__ __forceinline__ void pc_stage_records(const double4* grec, int
 // receives the iteration records.
 // MIXED: the job runs the FP32 -> FP64 precision schedule (compiled apart, so that FP64-only
 // jobs carry none of its registers).
-template <int PAIRS, int NP, bool MIXED = false, bool EIH = false>
+template <int PAIRS, int NP, bool MIXED = false, bool EIH = false, bool SO = false>
 static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const PcGroupDev& g, int n, int64_t ic0,
                                                         int s, PcSmem<PAIRS>& sm, const PcLane& L, gconst_dp kp0,
                                                         double (&yc)[6][4], int32_t* iters_out, int& had_notconv,
@@ -161,11 +161,25 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
 #pragma unroll
         for (int c = 0; c < 6; ++c) y0[c] = sY0[c * T + pm];
         const bool warm = p.init == 0 && !sm.Dead[pm];
+        const bool hot = p.init == 2 && !sm.Dead[pm] && pm < n;   // the caller's node states
 #pragma unroll 1
         for (int pr = tid; pr < PAIRS; pr += NT) {
             const int j = pr / T;
             double y[6];
-            if (!(j < N && warm && pc_kepler(y0, w2 * (g.tau[j < N ? j : 0] + 1.0), y))) {
+            bool have = false;
+            if (hot && j < N) {
+                const double* gp = p.guess + (((size_t)(ic0 + pm) * p.iters_stride + s) * p.nodes_stride + j) * 6;
+                bool fin = true;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    y[c] = gp[c];
+                    fin = fin && isfinite(y[c]);
+                }
+                have = fin;
+            } else if (j < N && warm) {
+                have = pc_kepler(y0, w2 * (g.tau[j] + 1.0), y);
+            }
+            if (!have) {
 #pragma unroll
                 for (int c = 0; c < 6; ++c) y[c] = y0[c];
             }
@@ -231,6 +245,16 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
     const int n_it = p.fixed_iters > 0 ? p.fixed_iters : p.max_iter;
     double kpre[8];
     pc_kpre_load<PAIRS, NP>(kp0, kpre);
+    // second-order sweeps: the K2_N strip and its first fragments next to K_N's, and the
+    // lane's node offset tau_j + 1 for the x0 + w2 v0 (tau_j + 1) term
+    gconst_dp kp2 = nullptr;
+    double tp1 = 0.0;
+    if constexpr (SO) {
+        kp2 = (gconst_dp)g.kfrag2 + (size_t)L.strip0 * NQ * 64 + L.lane;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) kpre[4 + u] = kp2[u * 64];
+        tp1 = g.tau[pc_node(L, 0, 0)] + 1.0;
+    }
     for (int it = 1; it <= n_it; ++it) {
         // (1)-(2) product and stopping-rule flags
         f64x4 acc[6];
@@ -243,6 +267,8 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
         } else if constexpr (MIXED) {
             flag = mode == 1 ? pc_product<PAIRS, NP, true>(sF, sY0, kp0, kpre, kp0f, yc, acc, w2, tl, N, L)
                              : pc_product<PAIRS, NP, false>(sF, sY0, kp0, kpre, kp0f, yc, acc, w2, tl, N, L);
+        } else if constexpr (SO) {
+            flag = pc_product2<PAIRS, NP>(sF, sY0, kp0, kp2, kpre, yc, acc, w2, tp1, tl, N, L);
         } else {
             flag = pc_product<PAIRS, NP, false, false>(sF, sY0, kp0, kpre, kp0f, yc, acc, w2, tl, N, L);
         }
@@ -352,7 +378,7 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
 
 // Not inlined: one register allocation per node count, so the work-queue kernel that
 // dispatches to all of them does not pay for the largest one everywhere.
-template <int PAIRS, int NP, bool MIXED, bool EIH = false>
+template <int PAIRS, int NP, bool MIXED, bool EIH = false, bool SO = false>
 __device__ __attribute__((noinline)) void pc_job(const PcParams& p, const PcJobDev& job, const PcGroupDev& g)
 {
     PcSmem<PAIRS>& sm = pc_smem<PAIRS>();
@@ -389,7 +415,7 @@ __device__ __attribute__((noinline)) void pc_job(const PcParams& p, const PcJobD
             }
             if (sm.Dead[tid] && p.iters_out) p.iters_out[(size_t)ic * p.iters_stride + s] = -2;
         }
-        pc_segment_solve<PAIRS, NP, MIXED, EIH>(p, g, n, job.ic0, s, sm, L, kp0, yc, p.iters_out, had_notconv);
+        pc_segment_solve<PAIRS, NP, MIXED, EIH, SO>(p, g, n, job.ic0, s, sm, L, kp0, yc, p.iters_out, had_notconv);
 
         // converged node states of the segment (optional output), chaining (Sec. 2.2)
 #pragma unroll
@@ -718,8 +744,15 @@ __global__ __launch_bounds__(PAIRS / 4, 2) void pc_fused_kernel(const PcParams* 
         const bool list = job.n > g.T;   // more ICs than columns: refilled columns (FP64 only)
         const bool mixed = p.precision == 1;
         const bool eih = p.inv_c2 != 0.0;   // relativistic model: one-block jobs
+        const bool order2 = p.order == 2;   // second-order sweeps: FP64, point masses, WIDE shapes
         switch (g.NP) {
         case 16:
+            if constexpr (PcShape<PAIRS, 16>::WIDE) {
+                if (order2) {
+                    pc_job<PAIRS, 16, false, false, true>(p, job, g);
+                    break;
+                }
+            }
             if (eih && mixed) pc_job<PAIRS, 16, true, true>(p, job, g);
             else if (eih) pc_job<PAIRS, 16, false, true>(p, job, g);
             else if (list) pc_job_list<PAIRS, 16>(p, job, g);
@@ -727,6 +760,12 @@ __global__ __launch_bounds__(PAIRS / 4, 2) void pc_fused_kernel(const PcParams* 
             else pc_job<PAIRS, 16, false>(p, job, g);
             break;
         case 32:
+            if constexpr (PcShape<PAIRS, 32>::WIDE) {
+                if (order2) {
+                    pc_job<PAIRS, 32, false, false, true>(p, job, g);
+                    break;
+                }
+            }
             if (eih && mixed) pc_job<PAIRS, 32, true, true>(p, job, g);
             else if (eih) pc_job<PAIRS, 32, false, true>(p, job, g);
             else if (list) pc_job_list<PAIRS, 32>(p, job, g);
@@ -734,6 +773,12 @@ __global__ __launch_bounds__(PAIRS / 4, 2) void pc_fused_kernel(const PcParams* 
             else pc_job<PAIRS, 32, false>(p, job, g);
             break;
         case 64:
+            if constexpr (PcShape<PAIRS, 64>::WIDE) {
+                if (order2) {
+                    pc_job<PAIRS, 64, false, false, true>(p, job, g);
+                    break;
+                }
+            }
             if (eih && mixed) pc_job<PAIRS, 64, true, true>(p, job, g);
             else if (eih) pc_job<PAIRS, 64, false, true>(p, job, g);
             else if (list) pc_job_list<PAIRS, 64>(p, job, g);
@@ -741,6 +786,12 @@ __global__ __launch_bounds__(PAIRS / 4, 2) void pc_fused_kernel(const PcParams* 
             else pc_job<PAIRS, 64, false>(p, job, g);
             break;
         case 128:
+            if constexpr (PcShape<PAIRS, 128>::WIDE) {
+                if (order2) {
+                    pc_job<PAIRS, 128, false, false, true>(p, job, g);
+                    break;
+                }
+            }
             if (eih && mixed) pc_job<PAIRS, 128, true, true>(p, job, g);
             else if (eih) pc_job<PAIRS, 128, false, true>(p, job, g);
             else if (list) pc_job_list<PAIRS, 128>(p, job, g);

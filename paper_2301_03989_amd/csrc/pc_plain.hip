@@ -62,7 +62,20 @@ __global__ void pc_plain_init(PcPlainArgs a, int s, double w2)
     double y0[6], y[6];
     for (int c = 0; c < 6; ++c) y0[c] = a.Y0[c * a.Mpad + m];
     const bool dead = a.dead[m];
-    if (!(a.p.init == 0 && !dead && pc_kepler(y0, w2 * (a.g->tau[j] + 1.0), y)))
+    bool have = false;
+    if (a.p.init == 2 && !dead && a.valid[m]) {   // the caller's node states
+        const PcJobDev job = a.jobs[m / a.T];
+        const double* gp =
+            a.p.guess + (((size_t)(job.ic0 + m % a.T) * a.p.iters_stride + s) * a.p.nodes_stride + j) * 6;
+        have = true;
+        for (int c = 0; c < 6; ++c) {
+            y[c] = gp[c];
+            have = have && isfinite(y[c]);
+        }
+    } else if (a.p.init == 0 && !dead) {
+        have = pc_kepler(y0, w2 * (a.g->tau[j] + 1.0), y);
+    }
+    if (!have)
         for (int c = 0; c < 6; ++c) y[c] = y0[c];
     for (int c = 0; c < 6; ++c) Yj[c * a.Mpad] = y[c];
     if (j == 0) {
@@ -345,8 +358,59 @@ size_t pc_plain_bytes(int NP, int n_jobs, int T)
     return al(9 * (size_t)NP * Mpad * 8) + al(6 * Mpad * 8) + 4 * al(Mpad * 4) + 3 * al((size_t)n_jobs * 4) + 256;
 }
 
-int pc_run_plain(PcPlainArgs a, void* workspace, int32_t* host_count, void* stream)
+namespace {
+
+constexpr int kPlainBs = 256;
+
+// One Picard iteration of the active jobs, then the read-back of the active-job count
+// (and, for the group-max rule, of the jobs with a change above tol) that drives the
+// host loop (Sec. 5.4.2).
+hipError_t plain_enqueue_iteration(PcPlainRun& r)
 {
+    PcPlainArgs& a = r.a;
+    hipStream_t st = (hipStream_t)r.stream;
+    a.job_list = r.lists[r.cur];
+    a.job_list_out = r.lists[1 - r.cur];
+    const int bpj = a.NP * a.T / kPlainForceBlock;
+    hipLaunchKernelGGL(pc_plain_force, dim3((unsigned)(r.count * bpj)), dim3(kPlainForceBlock), 0, st, a, r.s);
+    hipError_t e = (hipError_t)launch_step_np(a, r.count, r.s, r.it, r.w2, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(pc_plain_compact, dim3(1), dim3(1024), 0, st, a);
+    e = hipMemcpyAsync(r.host, a.count + 1, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return e;
+    return hipMemcpyAsync(a.count, a.count + 1, sizeof(int32_t), hipMemcpyDeviceToDevice, st);
+}
+
+// Segment r.s: initial guess at every node, full job list, first iteration.
+hipError_t plain_begin_segment(PcPlainRun& r)
+{
+    PcPlainArgs& a = r.a;
+    hipStream_t st = (hipStream_t)r.stream;
+    const double h = a.g_host.h;
+    const double Ts = a.g_host.t0 + h * r.s, Te = a.g_host.t0 + h * (r.s + 1);
+    r.w2 = 0.5 * (Te - Ts);
+    r.cur = 0;
+    a.job_list = r.lists[0];
+    const int64_t total = (int64_t)a.NP * a.Mpad;
+    hipLaunchKernelGGL(pc_plain_init, dim3((unsigned)((total + kPlainBs - 1) / kPlainBs)), dim3(kPlainBs), 0, st,
+                       a, r.s, r.w2);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    r.count = a.n_jobs;
+    r.status = -1;
+    r.it = 1;
+    return plain_enqueue_iteration(r);
+}
+
+}  // namespace
+
+int pc_plain_begin(PcPlainRun& r, const PcPlainArgs& args, void* workspace, int32_t* host_count, void* stream)
+{
+    r = PcPlainRun{};
+    r.a = args;
+    r.host = host_count;
+    r.stream = stream;
+    PcPlainArgs& a = r.a;
     hipStream_t st = (hipStream_t)stream;
     auto al = [](size_t x) { return (x + 255) / 256 * 256; };
     char* w = static_cast<char*>(workspace);
@@ -357,59 +421,63 @@ int pc_run_plain(PcPlainArgs a, void* workspace, int32_t* host_count, void* stre
     a.dead = reinterpret_cast<int32_t*>(w);            w += al(a.Mpad * 4);
     a.notconv = reinterpret_cast<int32_t*>(w);         w += al(a.Mpad * 4);
     a.valid = reinterpret_cast<int32_t*>(w);           w += al(a.Mpad * 4);
-    int32_t* lists[2];
-    lists[0] = reinterpret_cast<int32_t*>(w);          w += al((size_t)a.n_jobs * 4);
-    lists[1] = reinterpret_cast<int32_t*>(w);          w += al((size_t)a.n_jobs * 4);
+    r.lists[0] = reinterpret_cast<int32_t*>(w);        w += al((size_t)a.n_jobs * 4);
+    r.lists[1] = reinterpret_cast<int32_t*>(w);        w += al((size_t)a.n_jobs * 4);
     a.job_flag = reinterpret_cast<int32_t*>(w);        w += al((size_t)a.n_jobs * 4);
     a.count = reinterpret_cast<int32_t*>(w);
+    r.n_it = a.p.fixed_iters > 0 ? a.p.fixed_iters : a.p.max_iter;
+    r.group = a.p.conv == PC_CONV_GROUP_MAX && a.p.fixed_iters == 0;
 
-    const int bs = 256;
-    const unsigned gm = (unsigned)((a.Mpad + bs - 1) / bs);
-    hipLaunchKernelGGL(pc_plain_load, dim3(gm), dim3(bs), 0, st, a);
+    const unsigned gm = (unsigned)((a.Mpad + kPlainBs - 1) / kPlainBs);
+    hipLaunchKernelGGL(pc_plain_load, dim3(gm), dim3(kPlainBs), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(pc_plain_bounds0, dim3(gm), dim3(bs), 0, st, a);
-    const int bpj = a.NP * a.T / kPlainForceBlock;
-    const int n_it = a.p.fixed_iters > 0 ? a.p.fixed_iters : a.p.max_iter;
-    const bool group = a.p.conv == PC_CONV_GROUP_MAX && a.p.fixed_iters == 0;
-    const double h = a.g_host.h;
-    for (int s = 0; s < a.S; ++s) {
-        const double Ts = a.g_host.t0 + h * s, Te = a.g_host.t0 + h * (s + 1);
-        const double w2 = 0.5 * (Te - Ts);
-        int cur = 0;
-        a.job_list = lists[cur];
-        const int64_t total = (int64_t)a.NP * a.Mpad;
-        hipLaunchKernelGGL(pc_plain_init, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, st, a, s, w2);
-        int count = a.n_jobs;
-        int status = -1;   // group-max rule: the segment's sweep count once the group converged
-        for (int it = 1; it <= n_it && count > 0; ++it) {
-            a.job_list = lists[cur];
-            a.job_list_out = lists[1 - cur];
-            hipLaunchKernelGGL(pc_plain_force, dim3((unsigned)(count * bpj)), dim3(kPlainForceBlock), 0, st, a, s);
-            e = (hipError_t)launch_step_np(a, count, s, it, w2, st);
-            if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(pc_plain_compact, dim3(1), dim3(1024), 0, st, a);
-            // host loop control: read back the number of jobs still iterating and, for the
-            // group-max rule, of jobs with a change above tol (Sec. 5.4.2)
-            e = hipMemcpyAsync(host_count, a.count + 1, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, st);
-            if (e != hipSuccess) return e;
-            e = hipMemcpyAsync(a.count, a.count + 1, sizeof(int32_t), hipMemcpyDeviceToDevice, st);
-            if (e != hipSuccess) return e;
-            e = hipStreamSynchronize(st);
-            if (e != hipSuccess) return e;
-            count = host_count[0];
-            cur = 1 - cur;
-            if (group && host_count[2] == 0) {
-                status = it;
-                break;
-            }
-        }
-        if (group) {
-            hipLaunchKernelGGL(pc_plain_group_end, dim3(gm), dim3(bs), 0, st, a, s, status);
-            e = hipGetLastError();
-            if (e != hipSuccess) return e;
-        }
-        hipLaunchKernelGGL(pc_plain_chain, dim3(gm), dim3(bs), 0, st, a, s, s == a.S - 1 ? 1 : 0);
+    hipLaunchKernelGGL(pc_plain_bounds0, dim3(gm), dim3(kPlainBs), 0, st, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return plain_begin_segment(r);
+}
+
+int pc_plain_advance(PcPlainRun& r)
+{
+    PcPlainArgs& a = r.a;
+    hipStream_t st = (hipStream_t)r.stream;
+    r.count = r.host[0];
+    r.cur = 1 - r.cur;
+    bool end = false;
+    if (r.group && r.host[2] == 0) {   // group-max rule: no job holds a change above tol
+        r.status = r.it;
+        end = true;
+    } else if (r.it >= r.n_it || r.count == 0) {
+        end = true;
     }
-    return hipGetLastError();
+    if (!end) {
+        ++r.it;
+        return plain_enqueue_iteration(r);
+    }
+    const unsigned gm = (unsigned)((a.Mpad + kPlainBs - 1) / kPlainBs);
+    if (r.group) {
+        hipLaunchKernelGGL(pc_plain_group_end, dim3(gm), dim3(kPlainBs), 0, st, a, r.s, r.status);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(pc_plain_chain, dim3(gm), dim3(kPlainBs), 0, st, a, r.s, r.s == a.S - 1 ? 1 : 0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (++r.s == a.S) {
+        r.done = true;
+        return hipSuccess;
+    }
+    return plain_begin_segment(r);
+}
+
+int pc_run_plain(PcPlainArgs a, void* workspace, int32_t* host_count, void* stream)
+{
+    PcPlainRun r;
+    hipError_t e = (hipError_t)pc_plain_begin(r, a, workspace, host_count, stream);
+    while (e == hipSuccess && !r.done) {
+        e = hipStreamSynchronize((hipStream_t)stream);
+        if (e == hipSuccess) e = (hipError_t)pc_plain_advance(r);
+    }
+    return e;
 }

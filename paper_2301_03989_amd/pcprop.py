@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libpcprop.so")
 
 PC_OK, PC_EINVAL, PC_ENOTCONV, PC_ENONFINITE, PC_EHIP, PC_ENOMEM = 0, 1, 2, 3, 4, 5
 PC_ITER_NOTCONV, PC_ITER_NONFINITE = -1, -2
-INIT = {"kepler": 0, "cold": 1}
+INIT = {"kepler": 0, "cold": 1, "guess": 2}
 TOL_MODE = {"rel": 0, "abs": 1}
 PATH = {"fused": 0, "plain": 1}
 PRECISION = {"fp64": 0, "fp32-fp64": 1}
@@ -48,7 +48,8 @@ class _Opts(ctypes.Structure):
                 ("path", ctypes.c_int32), ("fixed_iters", ctypes.c_int32),
                 ("tile_pairs", ctypes.c_int32), ("graph", ctypes.c_int32),
                 ("switch_tol", ctypes.c_double), ("max_fp32", ctypes.c_int32), ("job_list", ctypes.c_int32),
-                ("conv", ctypes.c_int32), ("streams", ctypes.c_int32)]
+                ("conv", ctypes.c_int32), ("streams", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("feedback", ctypes.c_int32), ("guess", ctypes.c_void_p)]
 
 
 class _Group(ctypes.Structure):
@@ -64,7 +65,8 @@ EXPORTS = ("pc_default_opts", "pc_ctx_create", "pc_ctx_destroy", "pc_workspace_b
            "pc_propagate", "pc_propagate_batched", "pc_get_operator", "pc_apply_operator",
            "pc_eval_force", "pc_eval_kepler", "pc_set_timing", "pc_last_kernel_ms", "pc_autotune",
            "pc_set_tile_pairs", "pc_get_tile_pairs", "pc_adjoint", "pc_strerror", "pc_last_error",
-           "pc_version")
+           "pc_version", "pc_graph_captures", "pc_measure_ceilings",
+           "pc_set_job_list", "pc_get_job_list")
 
 
 def load_library(path: str = LIB_PATH):
@@ -101,6 +103,10 @@ def load_library(path: str = LIB_PATH):
                                ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
                                _vp, _vp, _vp, ctypes.c_size_t, _vp]
     lib.pc_get_tile_pairs.argtypes = [_vp, ctypes.c_int32, P(ctypes.c_int32)]
+    lib.pc_set_job_list.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32]
+    lib.pc_get_job_list.argtypes = [_vp, ctypes.c_int32, P(ctypes.c_int32)]
+    lib.pc_graph_captures.argtypes = [_vp, P(ctypes.c_int64)]
+    lib.pc_measure_ceilings.argtypes = [_vp, _vp, ctypes.c_size_t, _vp, _dp]
     lib.pc_set_timing.argtypes = [_vp, ctypes.c_int]
     lib.pc_last_kernel_ms.argtypes = [_vp, ctypes.POINTER(ctypes.c_double)]
     lib.pc_strerror.argtypes = [ctypes.c_int]
@@ -192,7 +198,7 @@ class Context:
     @staticmethod
     def opts(init="kepler", max_iter=64, tol_mode="rel", path="fused", fixed_iters=0,
              tile_pairs=0, precision="fp64", graph=False, switch_tol=0.0, max_fp32=0, job_list=0, conv="ic",
-             streams=1):
+             streams=1, order=1, feedback=0, guess=None):
         o = _Opts()
         o.init, o.max_iter, o.tol_mode = INIT[init], int(max_iter), TOL_MODE[tol_mode]
         o.precision, o.path, o.fixed_iters = PRECISION[precision], PATH[path], int(fixed_iters)
@@ -200,6 +206,10 @@ class Context:
         o.switch_tol, o.max_fp32, o.job_list = float(switch_tol), int(max_fp32), int(job_list)
         o.conv = CONV[conv]
         o.streams = int(streams)
+        o.order, o.feedback = int(order), int(feedback)
+        if guess is not None:   # init "guess": device node states [n, S_max, N_max, 6]
+            _check_tensor(guess, "guess")
+            o.guess = guess.data_ptr()
         return o
 
     def workspace_bytes(self, groups, model, **opts):
@@ -213,12 +223,11 @@ class Context:
             self._raise(rc)
         return nb.value
 
-    def propagate_batched(self, ics, groups, model=None, *, want_bounds=False, want_nodes=False,
-                          raise_on_status=False, out=None, **opts):
-        """Two-level augmented propagation (Sec. 3.2).  Returns a dict with
-        ``states`` [n,6], ``iters`` [n,S_max] (int32), ``status`` and, when asked,
-        ``bounds`` [n,S_max+1,6] and ``nodes`` [n,S_max,N_max,6]."""
-        model = model or Model()
+    def _outputs(self, ics, groups, want_bounds, want_nodes, out, iters_out=None, bounds_out=None,
+                 nodes_out=None):
+        """Output tensors of a call: the caller's (out, iters_out, bounds_out, nodes_out; kept
+        across calls, e.g. for graph replay, whose signature includes the output pointers) or
+        new ones."""
         _check_tensor(ics, "ics")
         if ics.dim() != 2 or ics.shape[1] != 6:
             raise ValueError("ics must be [n, 6]")
@@ -226,12 +235,44 @@ class Context:
         S_max = max(g.segments for g in groups)
         N_max = max(g.nodes for g in groups)
         dev = ics.device
+        if out is not None:
+            _check_tensor(out, "out", (n, 6))
+        if iters_out is not None:
+            _check_tensor(iters_out, "iters_out", (n, S_max), torch.int32)
+        if bounds_out is not None:
+            _check_tensor(bounds_out, "bounds_out", (n, S_max + 1, 6))
+        if nodes_out is not None:
+            _check_tensor(nodes_out, "nodes_out", (n, S_max, N_max, 6))
         states = out if out is not None else torch.empty((n, 6), dtype=torch.float64, device=dev)
-        iters = torch.zeros((n, S_max), dtype=torch.int32, device=dev)
-        bounds = torch.empty((n, S_max + 1, 6), dtype=torch.float64, device=dev) if want_bounds else None
-        nodes = torch.empty((n, S_max, N_max, 6), dtype=torch.float64, device=dev) if want_nodes else None
+        # a caller's iters_out keeps its contents in the columns past a group's segments
+        iters = iters_out if iters_out is not None else torch.zeros((n, S_max), dtype=torch.int32, device=dev)
+        bounds = bounds_out if bounds_out is not None else (
+            torch.empty((n, S_max + 1, 6), dtype=torch.float64, device=dev) if want_bounds else None)
+        nodes = nodes_out if nodes_out is not None else (
+            torch.empty((n, S_max, N_max, 6), dtype=torch.float64, device=dev) if want_nodes else None)
         garr = (_Group * len(groups))(*[_Group(g.ic_offset, g.n_ic, g.t0, g.tf, g.nodes, g.segments, g.tol)
                                        for g in groups])
+        return n, S_max, N_max, states, iters, bounds, nodes, garr
+
+    @staticmethod
+    def _result(rc, states, iters, bounds, nodes):
+        res = {"states": states, "iters": iters, "status": rc}
+        if bounds is not None:
+            res["bounds"] = bounds
+        if nodes is not None:
+            res["nodes"] = nodes
+        return res
+
+    def propagate_batched(self, ics, groups, model=None, *, want_bounds=False, want_nodes=False,
+                          raise_on_status=False, out=None, iters_out=None, bounds_out=None, nodes_out=None,
+                          **opts):
+        """Two-level augmented propagation (Sec. 3.2).  Returns a dict with
+        ``states`` [n,6], ``iters`` [n,S_max] (int32), ``status`` and, when asked,
+        ``bounds`` [n,S_max+1,6] and ``nodes`` [n,S_max,N_max,6].  ``out``,
+        ``iters_out``, ``bounds_out`` and ``nodes_out`` give the output tensors."""
+        model = model or Model()
+        n, S_max, N_max, states, iters, bounds, nodes, garr = self._outputs(
+            ics, groups, want_bounds, want_nodes, out, iters_out, bounds_out, nodes_out)
         mc, oc = model._c(), self.opts(**opts)
         nb = ctypes.c_size_t()
         rc = self.lib.pc_workspace_bytes(self.handle, garr, len(groups), ctypes.byref(mc), ctypes.byref(oc),
@@ -244,15 +285,10 @@ class Context:
             ctypes.byref(oc), ctypes.c_void_p(states.data_ptr()), ctypes.c_void_p(iters.data_ptr()), S_max,
             ctypes.c_void_p(bounds.data_ptr() if bounds is not None else 0),
             ctypes.c_void_p(nodes.data_ptr() if nodes is not None else 0), N_max,
-            ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(dev))
+            ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(ics.device))
         if rc not in (PC_OK, PC_ENOTCONV, PC_ENONFINITE) or (raise_on_status and rc != PC_OK):
             self._raise(rc)
-        res = {"states": states, "iters": iters, "status": rc}
-        if want_bounds:
-            res["bounds"] = bounds
-        if want_nodes:
-            res["nodes"] = nodes
-        return res
+        return self._result(rc, states, iters, bounds, nodes)
 
     def propagate(self, ics, t0, tf, nodes, segments, tol, model=None, **kw):
         g = Group(0, int(ics.shape[0]), float(t0), float(tf), int(nodes), int(segments), float(tol))
@@ -264,6 +300,25 @@ class Context:
         if rc != PC_OK:
             self._raise(rc)
 
+    def measure_ceilings(self, mib=1024):
+        """On-chip ceilings: (FP64 matrix-core TFLOP/s, FP64 vector FMA TFLOP/s, device copy
+        GB/s read + written) from pc_measure_ceilings, with a scratch of ``mib`` MiB."""
+        buf = torch.empty(int(mib) << 20, dtype=torch.uint8, device=self.device)
+        out = np.zeros(3)
+        rc = self.lib.pc_measure_ceilings(self.handle, ctypes.c_void_p(buf.data_ptr()), buf.numel(),
+                                          _stream_ptr(self.device), out.ctypes.data_as(_dp))
+        if rc != PC_OK:
+            self._raise(rc)
+        return float(out[0]), float(out[1]), float(out[2])
+
+    def graph_captures(self):
+        """HIP graphs captured so far by graph=True calls of this context."""
+        v = ctypes.c_int64()
+        rc = self.lib.pc_graph_captures(self.handle, ctypes.byref(v))
+        if rc != PC_OK:
+            self._raise(rc)
+        return v.value
+
     def last_kernel_ms(self):
         ms = ctypes.c_double()
         rc = self.lib.pc_last_kernel_ms(self.handle, ctypes.byref(ms))
@@ -272,7 +327,8 @@ class Context:
         return ms.value
 
     def autotune(self, ics, groups, model=None):
-        """Pick the job shape for this batch (pc_autotune); returns the chosen tile_pairs."""
+        """Tune the job shape and the per-node-count job lengths for this batch (pc_autotune);
+        returns the chosen tile_pairs (the job lengths: ``job_list(padded_nodes)``)."""
         model = model or Model()
         _check_tensor(ics, "ics")
         garr = (_Group * len(groups))(*[_Group(g.ic_offset, g.n_ic, g.t0, g.tf, g.nodes, g.segments, g.tol)
@@ -342,6 +398,18 @@ class Context:
         if rc != PC_OK:
             self._raise(rc)
         return v.value
+
+    def job_list(self, padded_nodes):
+        v = ctypes.c_int32()
+        rc = self.lib.pc_get_job_list(self.handle, int(padded_nodes), ctypes.byref(v))
+        if rc != PC_OK:
+            self._raise(rc)
+        return v.value
+
+    def set_job_list(self, padded_nodes, blocks):
+        rc = self.lib.pc_set_job_list(self.handle, int(padded_nodes), int(blocks))
+        if rc != PC_OK:
+            self._raise(rc)
 
     def set_tile_pairs(self, padded_nodes, pairs):
         rc = self.lib.pc_set_tile_pairs(self.handle, int(padded_nodes), int(pairs))

@@ -333,23 +333,85 @@ def test_graph_replays_match_eager(pc):
     assert rel_err(r["states"].cpu().numpy()[::50], o["states"]).max() < TOL
 
 
+def test_graph_recaptured_when_the_staging_buffer_grows(pc):
+    """A captured graph copies its tables from the context's pinned staging buffer; a call
+    that needs a larger buffer reallocates it, and the next graph call with the same
+    signature must be captured again rather than replay copies from the freed buffer."""
+    from paper_2301_03989_amd import pcprop
+    ctx = pcprop.Context(0)
+    w = W.nbody_venus(64, days=112.5, segments=2)
+    g = w.groups[0]
+    ics = torch.tensor(w.ics, device="cuda")
+    groups = [pcprop.Group(0, w.n_ic, g.t0, g.tf, g.nodes, g.segments, g.tol)]
+    model = pcprop.Model(1.0, w.pert, 0.0)
+    ref = ctx.propagate_batched(ics, groups, model)["states"].clone()
+    out = torch.empty_like(ref)
+    c0 = ctx.graph_captures()
+    for _ in range(2):
+        r = ctx.propagate_batched(ics, groups, model, graph=True, out=out)
+        assert r["status"] == 0 and torch.equal(r["states"], ref)
+    assert ctx.graph_captures() == c0 + 1
+    # 40000 one-IC groups of 3 nodes: descriptor tables beyond the 4 MiB staging buffer
+    n_big = 40000
+    big = torch.tensor(np.tile(w.ics[:1], (n_big, 1)), device="cuda")
+    bgroups = [pcprop.Group(i, 1, 0.0, 0.05, 3, 1, 1e-12) for i in range(n_big)]
+    rb = ctx.propagate_batched(big, bgroups, pcprop.Model(1.0, None, 0.0))
+    assert rb["status"] == 0
+    r = ctx.propagate_batched(ics, groups, model, graph=True, out=out)
+    assert ctx.graph_captures() == c0 + 2
+    assert r["status"] == 0 and torch.equal(r["states"], ref)
+
+
 def test_autotune_records_a_shape(pc):
     from paper_2301_03989_amd import pcprop
+    ctx = pcprop.Context(0)
     w = W.nbody_venus(512)
     g = w.groups[0]
     ics = torch.tensor(w.ics, device="cuda")
     groups = [pcprop.Group(0, w.n_ic, g.t0, g.tf, g.nodes, g.segments, g.tol)]
     model = pcprop.Model(1.0, w.pert, 0.0)
-    chosen = pc.autotune(ics, groups, model)
+    ref = ctx.propagate_batched(ics, groups, model)
+    chosen = ctx.autotune(ics, groups, model)
     assert chosen in (1024, 2048)
-    assert pc.tile_pairs(128) == chosen
-    a = pc.propagate_batched(ics, groups, model)
-    b = pc.propagate_batched(ics, groups, model, tile_pairs=2048)
+    assert ctx.tile_pairs(128) == chosen
+    assert ctx.job_list(128) in (0, 1, 2, 4, 8)
+    a = ctx.propagate_batched(ics, groups, model)
+    b = ctx.propagate_batched(ics, groups, model, tile_pairs=2048)
     assert rel_err(a["states"].cpu().numpy(), b["states"].cpu().numpy()).max() < 1e-13
-    pc.set_tile_pairs(128, 0)
-    assert pc.tile_pairs(128) == 0
+    assert rel_err(a["states"].cpu().numpy(), ref["states"].cpu().numpy()).max() < 1e-13
+    ctx.set_tile_pairs(128, 0)
+    assert ctx.tile_pairs(128) == 0
     with pytest.raises(pcprop.PcError):
-        pc.set_tile_pairs(256, 1024)
+        ctx.set_tile_pairs(256, 1024)
+    with pytest.raises(pcprop.PcError):
+        ctx.set_job_list(128, 3)
+
+
+def test_autotune_per_node_count_job_lengths(pc):
+    """On a batch of three node counts the tuner records a job length per padded node
+    count; results do not depend on the job length (columns are refilled with further ICs
+    of the same segment, each IC's iteration is unchanged)."""
+    from paper_2301_03989_amd import pcprop
+    ctx = pcprop.Context(0)
+    w = W.uneven_batch(3000, seed=41)
+    for gr in w.groups:
+        gr.segments = 1 + gr.segments // 16
+        gr.tf = gr.segments * np.pi / 4.0
+    ics = torch.tensor(w.ics, device="cuda")
+    groups = [pcprop.Group(gr.ic_offset, gr.n_ic, gr.t0, gr.tf, gr.nodes, gr.segments, gr.tol) for gr in w.groups]
+    model = pcprop.Model(1.0, w.pert, 0.0)
+    ref = ctx.propagate_batched(ics, groups, model)
+    ctx.autotune(ics, groups, model)
+    assert ctx.tile_pairs(256) == 2048
+    for np_ in (64, 128, 256):
+        assert ctx.job_list(np_) in (0, 1, 2, 4, 8)
+    ctx.set_job_list(64, 8)
+    ctx.set_job_list(128, 1)
+    ctx.set_job_list(256, 4)
+    for r in (ctx.propagate_batched(ics, groups, model), ):
+        assert r["status"] == 0
+        assert np.array_equal(r["iters"].cpu().numpy(), ref["iters"].cpu().numpy())
+        assert rel_err(r["states"].cpu().numpy(), ref["states"].cpu().numpy()).max() < 1e-13
 
 
 # ---------------------------------------------------------------------------
@@ -407,7 +469,7 @@ def test_fp32_then_fp64_mixed_groups(pc):
 @pytest.mark.parametrize("conv", ["ic", "group"])
 def test_plain_path_on_several_streams(pc, conv):
     """The outer level on several streams (Sec. 5.4): 15 groups spread over 2, 4 and 16
-    streams, each driven by its own host thread, give the one-stream results bit for bit,
+    streams, all driven from the calling thread, give the one-stream results bit for bit,
     with the per-IC and the group-max rule."""
     from paper_2301_03989_amd import pcprop
     w = W.uneven_batch(450, seed=23)
