@@ -345,10 +345,12 @@ def test_graph_recaptured_when_the_staging_buffer_grows(pc):
     groups = [pcprop.Group(0, w.n_ic, g.t0, g.tf, g.nodes, g.segments, g.tol)]
     model = pcprop.Model(1.0, w.pert, 0.0)
     ref = ctx.propagate_batched(ics, groups, model)["states"].clone()
+    # every output pointer is part of the replay signature: keep all of them across calls
     out = torch.empty_like(ref)
+    iters = torch.zeros((w.n_ic, g.segments), dtype=torch.int32, device="cuda")
     c0 = ctx.graph_captures()
     for _ in range(2):
-        r = ctx.propagate_batched(ics, groups, model, graph=True, out=out)
+        r = ctx.propagate_batched(ics, groups, model, graph=True, out=out, iters_out=iters)
         assert r["status"] == 0 and torch.equal(r["states"], ref)
     assert ctx.graph_captures() == c0 + 1
     # 40000 one-IC groups of 3 nodes: descriptor tables beyond the 4 MiB staging buffer
@@ -357,7 +359,7 @@ def test_graph_recaptured_when_the_staging_buffer_grows(pc):
     bgroups = [pcprop.Group(i, 1, 0.0, 0.05, 3, 1, 1e-12) for i in range(n_big)]
     rb = ctx.propagate_batched(big, bgroups, pcprop.Model(1.0, None, 0.0))
     assert rb["status"] == 0
-    r = ctx.propagate_batched(ics, groups, model, graph=True, out=out)
+    r = ctx.propagate_batched(ics, groups, model, graph=True, out=out, iters_out=iters)
     assert ctx.graph_captures() == c0 + 2
     assert r["status"] == 0 and torch.equal(r["states"], ref)
 
