@@ -224,6 +224,35 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic,
                          double* bounds_out, double* nodes_out, int32_t nodes_stride,
                          void* workspace, size_t ws_bytes, pc_stream_t stream);
 
+/* Bytes of device memory that pc_propagate_batched_noalloc uses as its workspace. */
+#define PC_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+
+/* pc_propagate_batched for callers that cannot allocate (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same fused-path kernels and
+ * results, with no device or host allocation in the call.  Its workspace is a static
+ * device array of PC_NOALLOC_SCRATCH_BYTES (32 MiB) that the library holds on every
+ * device it runs on until the process ends, its address taken once per device when a
+ * context is created there.  The caller still owns ics and every output.
+ *   Arguments as pc_propagate_batched without workspace and ws_bytes.
+ *   Limits (PC_ENOMEM with a message naming the sizes when exceeded): the call's workspace
+ *   (pc_workspace_bytes: descriptor tables, ephemeris records) must fit the scratch, e.g.
+ *   up to about 110000 segment-node pairs over all groups at 8 point-mass perturbers;
+ *   its job tables must fit the context's pinned staging buffer (4 MiB, or more once an
+ *   earlier call has grown it).
+ *   PC_EINVAL: opts->path must be PC_PATH_FUSED and opts->graph 0; every node count of the
+ *   call must have been used before on this context (an earlier pc_propagate_batched
+ *   builds and caches its operators), since building them allocates.
+ *   Every call on one device shares that device's scratch and each call starts by copying
+ *   its tables over it (work-queue head and status counters included); calls that overlap
+ *   on one device, from any context or thread, race and must be serialised by the caller.
+ *   The call synchronises its stream before returning, as pc_propagate_batched does. */
+int pc_propagate_batched_noalloc(pc_ctx* ctx, const double* ics, int64_t n_ic,
+                                 const pc_group* groups /* host */, int32_t n_groups,
+                                 const pc_model* model, const pc_opts* opts,
+                                 double* states_out, int32_t* iters_out, int32_t iters_stride,
+                                 double* bounds_out, double* nodes_out, int32_t nodes_stride,
+                                 pc_stream_t stream);
+
 /* Gradient of a loss through the converged propagation (reverse mode, segment
  * checkpointing).  Per segment the converged node states satisfy Y = 1 y0^T + K_N G(Y)
  * (the fixed point of Sec. 2.2); with J_j = w2 df/dy at node j the loss gradient seeds

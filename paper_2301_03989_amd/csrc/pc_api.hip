@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <thread>
 #include <vector>
@@ -20,6 +21,8 @@
 #include "pc_plain.h"
 
 namespace {
+
+constexpr int kMaxDevices = 64;
 
 struct OperatorCache {
     int N = 0, NP = 0;
@@ -42,6 +45,15 @@ struct HostOperator {
     std::vector<double> frag2;    // fragments of K2_N (second-order sweeps)
     std::vector<double> tau;      // [NP]
 };
+
+// Device memory of pc_propagate_batched_noalloc: the workspace of its calls (descriptor
+// tables, kernel parameters, work-queue head and status counters, ephemeris records).
+// Each device holds its own copy for the life of the process; host code reaches it only
+// through the address hipGetSymbolAddress returns for that device (scratch_address).
+static __device__ __align__(256) char scratch[PC_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mutex;
+char* g_scratch_ptr[kMaxDevices] = {};   // device address of `scratch`, per device
 
 }  // namespace
 
@@ -69,6 +81,7 @@ struct pc_ctx {
     hipGraphExec_t graph_exec = nullptr;
     std::vector<char> graph_key;       // call signature of the captured graph
     int64_t graph_captures = 0;        // graphs captured so far (test hook)
+    char* scratch = nullptr;           // this device's `scratch` (pc_propagate_batched_noalloc)
     bool timing = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double last_ms = -1.0;
@@ -326,6 +339,25 @@ int ensure_plain_streams(pc_ctx* ctx, int ns)
     return PC_OK;
 }
 
+// Device address of `scratch` on the context's device (current when this runs), looked
+// up once per device and kept for every later context on it.
+int scratch_address(pc_ctx* ctx, char** out)
+{
+    *out = nullptr;
+    if (ctx->device >= kMaxDevices)
+        return set_error(ctx, PC_EINVAL, "device %d: the static scratch is kept for devices 0..%d",
+                         ctx->device, kMaxDevices - 1);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[ctx->device]) {
+        void* p = nullptr;
+        PC_HIP(ctx, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return set_error(ctx, PC_EHIP, "hipGetSymbolAddress returned no address for the scratch");
+        g_scratch_ptr[ctx->device] = static_cast<char*>(p);
+    }
+    *out = g_scratch_ptr[ctx->device];
+    return PC_OK;
+}
+
 int validate_model(pc_ctx* ctx, const pc_model* model)
 {
     if (!model) return set_error(ctx, PC_EINVAL, "model is NULL");
@@ -419,8 +451,10 @@ int choose_pairs(const pc_ctx* ctx, const pc_group* groups, int n_groups, const 
 
 // lists_ok: jobs may hold more ICs than columns (refilled columns; fused FP64 forward calls).
 // A plan without lists has the most jobs, so its workspace size bounds every other plan's.
+// cached_only: take the operators from the context's cache and fail where one is missing
+// (the allocation-free entry point builds none).
 int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, const pc_model* model,
-              const pc_opts& o, bool build_tables, Plan& plan, bool lists_ok = false)
+              const pc_opts& o, bool build_tables, Plan& plan, bool lists_ok = false, bool cached_only = false)
 {
     if (!groups || n_groups < 1) return set_error(ctx, PC_EINVAL, "need at least one group");
     if (o.tile_pairs != 0 && o.tile_pairs != 1024 && o.tile_pairs != 2048)
@@ -527,6 +561,10 @@ int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, c
         d.S = G.segments;
         if (build_tables) {
             const OperatorCache* oc = nullptr;
+            if (cached_only && ctx->ops.find(G.nodes) == ctx->ops.end())
+                return set_error(ctx, PC_EINVAL,
+                                 "the operators of %d nodes are not built in this context yet (a call of "
+                                 "pc_propagate_batched with that node count builds them)", G.nodes);
             int rc = get_operator(ctx, G.nodes, &oc);
             if (rc != PC_OK) return rc;
             d.kfrag = oc->kfrag;
@@ -754,6 +792,10 @@ int pc_ctx_create(int device, pc_ctx** out)
         pc_ctx_destroy(ctx);
         return PC_EHIP;
     }
+    // the allocation-free entry point's device memory on this device (a failure here only
+    // disables that entry point, which then reports it)
+    if (scratch_address(ctx, &ctx->scratch) != PC_OK) ctx->scratch = nullptr;
+    ctx->last_error[0] = 0;
     *out = ctx;
     return PC_OK;
 }
@@ -806,11 +848,15 @@ int pc_workspace_bytes(pc_ctx* ctx, const pc_group* groups, int32_t n_groups, co
     return PC_OK;
 }
 
-int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_group* groups,
-                         int32_t n_groups, const pc_model* model, const pc_opts* opts,
-                         double* states_out, int32_t* iters_out, int32_t iters_stride,
-                         double* bounds_out, double* nodes_out, int32_t nodes_stride,
-                         void* workspace, size_t ws_bytes, pc_stream_t stream)
+// The forward call.  no_alloc: the workspace is this device's static `scratch` (workspace
+// and ws_bytes are ignored), the operators must already be cached, the tables must fit the
+// staging buffer the context holds, and only the fused path without graph capture runs, so
+// that nothing is allocated.
+static int propagate_impl(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_group* groups,
+                          int32_t n_groups, const pc_model* model, const pc_opts* opts,
+                          double* states_out, int32_t* iters_out, int32_t iters_stride,
+                          double* bounds_out, double* nodes_out, int32_t nodes_stride,
+                          void* workspace, size_t ws_bytes, pc_stream_t stream, bool no_alloc)
 {
     if (!ctx) return PC_EINVAL;
     ctx->last_error[0] = 0;
@@ -820,12 +866,19 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_
     const pc_opts o = opts ? *opts : defaults();
     rc = validate_forward(ctx, o, model);
     if (rc != PC_OK) return rc;
+    if (no_alloc) {
+        if (o.path != PC_PATH_FUSED) return set_error(ctx, PC_EINVAL, "the allocation-free call runs the fused path");
+        if (o.graph) return set_error(ctx, PC_EINVAL, "the allocation-free call does not capture graphs");
+        if (!ctx->scratch) return set_error(ctx, PC_EHIP, "no scratch address on device %d", ctx->device);
+        workspace = ctx->scratch;
+        ws_bytes = PC_NOALLOC_SCRATCH_BYTES;
+    }
     const bool eih = model->inv_c2 > 0.0;
     PC_HIP(ctx, hipSetDevice(ctx->device));
     Plan plan;
     rc = make_plan(ctx, n_ic, groups, n_groups, model, o, true, plan,
                    o.path == PC_PATH_FUSED && o.precision == PC_FP64 && !eih && o.order == 1 &&
-                   o.init != PC_INIT_GUESS);
+                   o.init != PC_INIT_GUESS, no_alloc);
     if (rc != PC_OK) return rc;
     if ((iters_out || bounds_out || nodes_out) && iters_stride < plan.max_S)
         return set_error(ctx, PC_EINVAL, "iters_stride %d < %d segments", iters_stride, plan.max_S);
@@ -833,10 +886,16 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_
         return set_error(ctx, PC_EINVAL, "nodes_stride %d < %d nodes", nodes_stride, plan.max_N);
     if (o.guess && iters_stride < plan.max_S)
         return set_error(ctx, PC_EINVAL, "iters_stride %d < %d segments", iters_stride, plan.max_S);
+    if (no_alloc && plan.total > ws_bytes)
+        return set_error(ctx, PC_ENOMEM, "the call needs %zu bytes of workspace; the static scratch of the "
+                         "allocation-free call holds %zu", plan.total, ws_bytes);
     if (!workspace || ws_bytes < plan.total)
         return set_error(ctx, PC_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, plan.total);
 
     // stage [counters | params | groups | jobs | bodies] and copy them in one transfer
+    if (no_alloc && plan.staged + kAlign > ctx->staging_bytes)
+        return set_error(ctx, PC_ENOMEM, "the call's tables take %zu bytes; the context's staging buffer "
+                         "holds %zu", plan.staged + kAlign, ctx->staging_bytes);
     rc = ensure_staging(ctx, plan.staged + kAlign);
     if (rc != PC_OK) return rc;
     char* st = static_cast<char*>(ctx->staging);
@@ -1012,6 +1071,26 @@ int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_
     if (hc[1] > 0) return set_error(ctx, PC_ENONFINITE, "%d initial conditions became non-finite", hc[1]);
     if (hc[0] > 0) return set_error(ctx, PC_ENOTCONV, "%d initial conditions did not converge", hc[0]);
     return PC_OK;
+}
+
+int pc_propagate_batched(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_group* groups,
+                         int32_t n_groups, const pc_model* model, const pc_opts* opts,
+                         double* states_out, int32_t* iters_out, int32_t iters_stride,
+                         double* bounds_out, double* nodes_out, int32_t nodes_stride,
+                         void* workspace, size_t ws_bytes, pc_stream_t stream)
+{
+    return propagate_impl(ctx, ics, n_ic, groups, n_groups, model, opts, states_out, iters_out, iters_stride,
+                          bounds_out, nodes_out, nodes_stride, workspace, ws_bytes, stream, false);
+}
+
+int pc_propagate_batched_noalloc(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_group* groups,
+                                 int32_t n_groups, const pc_model* model, const pc_opts* opts,
+                                 double* states_out, int32_t* iters_out, int32_t iters_stride,
+                                 double* bounds_out, double* nodes_out, int32_t nodes_stride,
+                                 pc_stream_t stream)
+{
+    return propagate_impl(ctx, ics, n_ic, groups, n_groups, model, opts, states_out, iters_out, iters_stride,
+                          bounds_out, nodes_out, nodes_stride, nullptr, 0, stream, true);
 }
 
 int pc_propagate(pc_ctx* ctx, const double* ics, int64_t n_ic, double t0, double tf, int32_t nodes,

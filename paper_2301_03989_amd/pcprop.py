@@ -66,7 +66,7 @@ EXPORTS = ("pc_default_opts", "pc_ctx_create", "pc_ctx_destroy", "pc_workspace_b
            "pc_eval_force", "pc_eval_kepler", "pc_set_timing", "pc_last_kernel_ms", "pc_autotune",
            "pc_set_tile_pairs", "pc_get_tile_pairs", "pc_adjoint", "pc_strerror", "pc_last_error",
            "pc_version", "pc_graph_captures", "pc_measure_ceilings",
-           "pc_set_job_list", "pc_get_job_list")
+           "pc_set_job_list", "pc_get_job_list", "pc_propagate_batched_noalloc")
 
 
 def load_library(path: str = LIB_PATH):
@@ -91,6 +91,9 @@ def load_library(path: str = LIB_PATH):
     lib.pc_propagate_batched.argtypes = [_vp, _vp, ctypes.c_int64, P(_Group), ctypes.c_int32,
                                          P(_Model), P(_Opts), _vp, _vp, ctypes.c_int32, _vp, _vp,
                                          ctypes.c_int32, _vp, ctypes.c_size_t, _vp]
+    lib.pc_propagate_batched_noalloc.argtypes = [_vp, _vp, ctypes.c_int64, P(_Group), ctypes.c_int32,
+                                                 P(_Model), P(_Opts), _vp, _vp, ctypes.c_int32, _vp, _vp,
+                                                 ctypes.c_int32, _vp]
     lib.pc_get_operator.argtypes = [_vp, ctypes.c_int32, _dp]
     lib.pc_apply_operator.argtypes = [_vp, ctypes.c_int32, ctypes.c_int64, _vp, _vp, ctypes.c_double,
                                       _vp, _vp]
@@ -286,6 +289,25 @@ class Context:
             ctypes.c_void_p(bounds.data_ptr() if bounds is not None else 0),
             ctypes.c_void_p(nodes.data_ptr() if nodes is not None else 0), N_max,
             ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(ics.device))
+        if rc not in (PC_OK, PC_ENOTCONV, PC_ENONFINITE) or (raise_on_status and rc != PC_OK):
+            self._raise(rc)
+        return self._result(rc, states, iters, bounds, nodes)
+
+    def propagate_batched_noalloc(self, ics, groups, model=None, *, out, iters_out, bounds_out=None,
+                                  nodes_out=None, raise_on_status=False, **opts):
+        """pc_propagate_batched_noalloc: the fused path with the library's static device
+        scratch as its workspace, for callers that cannot allocate.  Every output tensor is
+        the caller's (``out`` [n,6], ``iters_out`` [n,S_max] int32, optional ``bounds_out``,
+        ``nodes_out``); the call allocates nothing.  Same result dict as propagate_batched."""
+        model = model or Model()
+        n, S_max, N_max, states, iters, bounds, nodes, garr = self._outputs(
+            ics, groups, bounds_out is not None, nodes_out is not None, out, iters_out, bounds_out, nodes_out)
+        mc, oc = model._c(), self.opts(**opts)
+        rc = self.lib.pc_propagate_batched_noalloc(
+            self.handle, ctypes.c_void_p(ics.data_ptr()), n, garr, len(groups), ctypes.byref(mc),
+            ctypes.byref(oc), ctypes.c_void_p(states.data_ptr()), ctypes.c_void_p(iters.data_ptr()), S_max,
+            ctypes.c_void_p(bounds.data_ptr() if bounds is not None else 0),
+            ctypes.c_void_p(nodes.data_ptr() if nodes is not None else 0), N_max, _stream_ptr(ics.device))
         if rc not in (PC_OK, PC_ENOTCONV, PC_ENONFINITE) or (raise_on_status and rc != PC_OK):
             self._raise(rc)
         return self._result(rc, states, iters, bounds, nodes)
