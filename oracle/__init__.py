@@ -47,7 +47,7 @@ def _load():
             ctypes.c_int, _dp, _dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
             ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
             ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double, _dp, _ip, _dp, _dp, ctypes.c_int,
-            ctypes.c_int, ctypes.c_int, _dp]
+            ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int]
         lib.orc_second_order_step.restype = None
         lib.orc_second_order_step.argtypes = [ctypes.c_int, _dp, _dp, _dp, ctypes.c_double, _dp, _dp]
         lib.orc_propagate_group.restype = ctypes.c_int
@@ -126,7 +126,7 @@ class Model:
 
 def propagate(ics, t0, tf, nodes, segments, tol, model=None, *, tol_mode=0, max_iter=64,
               fixed_iters=0, init=0, want_bounds=False, want_nodes=False, threads=0, conv=0,
-              order=1, feedback=0, guess=None):
+              order=1, feedback=0, guess=None, refine=0):
     """Propagate ICs [n,6] over [t0, tf] (scalars or per-IC arrays).
 
     Returns (states[n,6], iters[n,segments]) and, when asked, the segment-boundary
@@ -136,7 +136,9 @@ def propagate(ics, t0, tf, nodes, segments, tol, model=None, *, tol_mode=0, max_
     ``order``: 1 = the first-order iteration, 2 = the second-order form (velocity and
     position both from the accelerations); ``feedback``: 1 = the second-order form with
     integral error feedback (orc_propagate).  ``init`` 2 starts every segment from
-    ``guess`` [n, S, N, 6] (node states of an earlier propagation).
+    ``guess`` [n, S, N, 6] (node states of an earlier propagation).  ``refine`` > 0: a
+    segment that does not converge is solved again as 2, 4, ... 2^refine equal sub-segments
+    (orc_propagate; not with node outputs or a guess).
     """
     lib = _load()
     model = model or Model()
@@ -154,6 +156,8 @@ def propagate(ics, t0, tf, nodes, segments, tol, model=None, *, tol_mode=0, max_
     if (init == 2) != (guess is not None):
         raise ValueError("init 2 takes a guess [n, S, N, 6], and only it does")
     garr = _f64(guess, (n, S, N, 6)) if guess is not None else None
+    if refine and (want_nodes or guess is not None or conv == 1):
+        raise ValueError("refinement takes no node outputs, no guess and the per-IC rule")
     if conv == 1:
         if order != 1 or init == 2:
             raise ValueError("group-max convergence is written for the first-order iteration")
@@ -170,7 +174,7 @@ def propagate(ics, t0, tf, nodes, segments, tol, model=None, *, tol_mode=0, max_
                                  int(max_iter), int(fixed_iters), int(init), model.mu_sun,
                                  model.n_pert, model._pert_ptr(), model.epoch, model.inv_c2, _ptr(states),
                                  iters.ctypes.data_as(_ip), _ptr(bounds), _ptr(nodes_out), int(threads),
-                                 int(order), int(feedback), _ptr(garr))
+                                 int(order), int(feedback), _ptr(garr), int(refine))
     out = [states, iters]
     if want_bounds:
         out.append(bounds)

@@ -534,16 +534,175 @@ static double orc_iter_error(int N, const double* ynew, const double* yold, int 
  *                      vanishes, so the converged result is that of order 2 without it.
  * Returns the number of threads used.
  */
+/* What every segment solve of one orc_propagate call shares: the settings, the node
+ * grid and T_k(tau_j), and the force model. */
+typedef struct {
+    int N, tol_mode, max_iter, fixed_iters, init, order, feedback, np;
+    double tol, mu_sun, epoch, inv_c2;
+    const double* pert;
+    const double* Tkj;
+    const double* tau;
+    const double* mup;
+} OrcRun;
+
+/* Per-thread buffers of the segment solve. */
+typedef struct {
+    double *Y, *Yn, *G, *rp, *vp, *cbuf, *bbuf, *dbuf, *A2, *X2, *V2, *dX2, *dV2;
+} OrcWork;
+
+/*
+ * One segment [Ts, Te] of one trajectory from the initial state y0 (Sec. 2.2): perturber
+ * states at the nodes, the initial guess (Sec. 2.1; seg_guess [N][6] for a hot start, else
+ * NULL), then Picard iterations (steps i-vi) until the error (vi) is below tol.  The
+ * newest iterate is left in W->Y.  Returns the status of the segment: k >= 1 converged
+ * after k iterations, -1 not converged within max_iter, -2 non-finite.
+ */
+static int orc_segment(const OrcRun* R, OrcWork* W, const double y0[6], double Ts, double Te,
+                       const double* seg_guess)
+{
+    const int N = R->N, np = R->np;
+    const double* tau = R->tau;
+    const double w1 = 0.5 * (Te + Ts), w2 = 0.5 * (Te - Ts);
+    /* perturber positions (and velocities, for EIH) at the nodes, before iterating
+       (Sec. 5.4.1) */
+    for (int j = 0; j < N; ++j) {
+        double tj = w2 * tau[j] + w1;
+        for (int p = 0; p < np; ++p) {
+            if (R->inv_c2 != 0.0)
+                orc_ephem_state(R->pert + 7 * p, R->epoch, tj, W->rp + 3 * (j * np + p), W->vp + 3 * (j * np + p));
+            else
+                orc_ephem(R->pert + 7 * p, R->epoch, tj, W->rp + 3 * (j * np + p));
+        }
+    }
+    /* initial guess */
+    int cold = (R->init == 1);
+    if (seg_guess) {
+        for (int j = 0; j < N; ++j) {
+            const double* gq = seg_guess + 6 * j;
+            int fin = 1;
+            for (int k = 0; k < 6; ++k) fin = fin && isfinite(gq[k]);
+            memcpy(W->Y + 6 * j, fin ? gq : y0, sizeof(double) * 6);
+        }
+    } else if (!cold) {
+        for (int j = 0; j < N; ++j) {
+            double dt = w2 * (tau[j] + 1.0);
+            if (orc_kepler(y0, dt, W->Y + 6 * j) != 0) { cold = 1; break; }
+        }
+    }
+    if (cold)
+        for (int j = 0; j < N; ++j) memcpy(W->Y + 6 * j, y0, sizeof(double) * 6);
+    /* Picard iterations */
+    int status = -1;
+    int n_it = R->fixed_iters > 0 ? R->fixed_iters : R->max_iter;
+    for (int it = 1; it <= n_it; ++it) {
+        double *Y = W->Y, *Yn = W->Yn;
+        /* (i) force matrix */
+        for (int j = 0; j < N; ++j) {
+            double acc[3];
+            if (R->inv_c2 != 0.0)
+                orc_accel_eih(Y + 6 * j, np, W->rp + 3 * j * np, W->vp + 3 * j * np, R->mup, R->mu_sun, R->inv_c2, acc);
+            else
+                orc_accel(Y + 6 * j, np, W->rp + 3 * j * np, R->mup, R->mu_sun, acc);
+            for (int k = 0; k < 3; ++k) {
+                W->G[6 * j + k] = w2 * Y[6 * j + 3 + k];
+                W->G[6 * j + 3 + k] = w2 * acc[k];
+                W->A2[3 * j + k] = acc[k];
+            }
+        }
+        if (R->order == 2) {
+            /* second-order form: velocity and position from the accelerations */
+            orc_second_order_update(N, R->Tkj, W->A2, y0, y0 + 3, w2, tau, W->X2, W->V2, W->cbuf, W->bbuf, W->dbuf);
+            if (R->feedback) {
+                const double zero[3] = {0.0, 0.0, 0.0};
+                for (int j = 0; j < N; ++j) {
+                    double J[9], dx[3];
+                    orc_accel_jac(Y + 6 * j, np, W->rp + 3 * j * np, R->mup, R->mu_sun, J);
+                    for (int k = 0; k < 3; ++k) dx[k] = W->X2[3 * j + k] - Y[6 * j + k];
+                    for (int k = 0; k < 3; ++k)
+                        W->A2[3 * j + k] = J[3 * k] * dx[0] + J[3 * k + 1] * dx[1] + J[3 * k + 2] * dx[2];
+                }
+                orc_second_order_update(N, R->Tkj, W->A2, zero, zero, w2, tau, W->dX2, W->dV2, W->cbuf, W->bbuf,
+                                        W->dbuf);
+                for (int i = 0; i < 3 * N; ++i) {
+                    W->X2[i] += W->dX2[i];
+                    W->V2[i] += W->dV2[i];
+                }
+            }
+            for (int j = 0; j < N; ++j)
+                for (int k = 0; k < 3; ++k) {
+                    Yn[6 * j + k] = W->X2[3 * j + k];
+                    Yn[6 * j + 3 + k] = W->V2[3 * j + k];
+                }
+        } else {
+            /* (ii)-(v) */
+            orc_picard_update(N, 6, R->Tkj, W->G, y0, Yn, W->cbuf, W->bbuf);
+        }
+        /* (vi) */
+        double e = orc_iter_error(N, Yn, Y, R->tol_mode);
+        W->Y = Yn;   /* the newest iterate */
+        W->Yn = Y;
+        if (isnan(e)) { status = -2; break; }
+        if (R->fixed_iters > 0) { if (it == n_it) status = it; continue; }
+        if (e < R->tol) { status = it; break; }
+    }
+    return status;
+}
+
+/*
+ * Propagate n_ic trajectories.
+ *   ics[n][6]          initial states at t0[n]
+ *   t0[n], tf[n]       per-IC interval (tf < t0: backward)
+ *   N, S               nodes per segment, number of segments
+ *   tol, tol_mode      stopping tolerance; 0 = relative, 1 = absolute
+ *   max_iter           iteration cap per segment
+ *   fixed_iters        if > 0, every segment runs exactly this many
+ *                      iterations and reports that count (no stopping rule)
+ *   init               0 = Kepler warm start, 1 = cold start, 2 = the node states in
+ *                      guess[n][S][N][6] (a hot start from an earlier propagation, Sec. 2.1;
+ *                      a non-finite row starts from the segment's initial state)
+ *   mu_sun, n_pert, pert[n_pert][7], epoch : force model
+ *   states_out[n][6]   final states
+ *   iters_out[n][S]    per-segment iteration counts / status
+ *   bounds_out         [n][S+1][6] segment-boundary states, or NULL
+ *   nodes_out          [n][S][N][6] converged node states, or NULL
+ *   nthreads           OpenMP threads (<= 0: library default)
+ *   order              1: the iteration of Sec. 2.2 on the first-order system (steps
+ *                      i-vi above); 2: the second-order form (orc_second_order_update),
+ *                      the same stopping rule (vi) on the position and velocity iterates
+ *   feedback           order 2 only, 1 = integral error feedback, read here as: the
+ *                      sweep's accelerations were taken at the previous position iterate,
+ *                      so the change dx_j that the sweep makes to the position is fed back
+ *                      through the linear part of the dynamics, da_j = (da/dr)_j dx_j (the
+ *                      point-mass gravity gradient at the previous iterate), and the
+ *                      integrals of da (orc_second_order_update with zero initial state)
+ *                      are added to the new velocity and position.  At the fixed point dx
+ *                      vanishes, so the converged result is that of order 2 without it.
+ *   refine             adaptive segment refinement (0 = off): a segment whose iterations do
+ *                      not converge within max_iter is solved again from its initial state
+ *                      as 2, then 4, ... up to 2^refine equal sub-segments of the same N,
+ *                      each a complete segment solve (own warm start, own iterations),
+ *                      chained in order, until every sub-segment converges.  This is the
+ *                      piecewise remedy of Sec. 2.2 (shorter pieces where the span is too
+ *                      long for the iteration to converge), applied per segment as the
+ *                      adaptive variant cited in Sec. 1 sets segment lengths.  The segment
+ *                      then records the sum of its sub-segments' iteration counts; if the
+ *                      finest split still has a sub-segment at -1, it records -1 and keeps
+ *                      that split's end state.  Not with nodes_out or a guess (a split
+ *                      segment has no states at the original nodes).
+ * Returns the number of threads used.
+ */
 int orc_propagate(int n_ic, const double* ics, const double* t0, const double* tf,
                   int N, int S, double tol, int tol_mode, int max_iter, int fixed_iters,
                   int init, double mu_sun, int n_pert, const double* pert, double epoch,
                   double inv_c2, double* states_out, int* iters_out, double* bounds_out,
-                  double* nodes_out, int nthreads, int order, int feedback, const double* guess)
+                  double* nodes_out, int nthreads, int order, int feedback, const double* guess,
+                  int refine)
 {
     int used = 1;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #endif
+    if (refine > 0 && (nodes_out || guess)) return -1;
     double* Tkj = (double*)malloc(sizeof(double) * (size_t)(N + 1) * N);   /* k = 0..N */
     double* tau = (double*)malloc(sizeof(double) * (size_t)N);
     for (int k = 0; k <= N; ++k)
@@ -552,6 +711,11 @@ int orc_propagate(int n_ic, const double* ics, const double* t0, const double* t
     double mup[64];
     int np = n_pert > 64 ? 64 : n_pert;
     for (int p = 0; p < np; ++p) mup[p] = pert[7 * p];
+    OrcRun R;
+    R.N = N; R.tol_mode = tol_mode; R.max_iter = max_iter; R.fixed_iters = fixed_iters;
+    R.init = init == 2 ? 0 : init; R.order = order; R.feedback = feedback; R.np = np;
+    R.tol = tol; R.mu_sun = mu_sun; R.epoch = epoch; R.inv_c2 = inv_c2;
+    R.pert = pert; R.Tkj = Tkj; R.tau = tau; R.mup = mup;
 
 #pragma omp parallel
     {
@@ -559,19 +723,20 @@ int orc_propagate(int n_ic, const double* ics, const double* t0, const double* t
 #pragma omp single
         used = omp_get_num_threads();
 #endif
-        double* Y = (double*)malloc(sizeof(double) * (size_t)N * 6);
-        double* Yn = (double*)malloc(sizeof(double) * (size_t)N * 6);
-        double* G = (double*)malloc(sizeof(double) * (size_t)N * 6);
-        double* rp = (double*)malloc(sizeof(double) * (size_t)N * 3 * (np > 0 ? np : 1));
-        double* vp = (double*)malloc(sizeof(double) * (size_t)N * 3 * (np > 0 ? np : 1));
-        double* cbuf = (double*)malloc(sizeof(double) * (size_t)(N + 2));
-        double* bbuf = (double*)malloc(sizeof(double) * (size_t)(N + 2));
-        double* dbuf = (double*)malloc(sizeof(double) * (size_t)(N + 2));
-        double* A2 = (double*)malloc(sizeof(double) * (size_t)N * 3);    /* order 2: a at the nodes */
-        double* X2 = (double*)malloc(sizeof(double) * (size_t)N * 3);
-        double* V2 = (double*)malloc(sizeof(double) * (size_t)N * 3);
-        double* dX2 = (double*)malloc(sizeof(double) * (size_t)N * 3);
-        double* dV2 = (double*)malloc(sizeof(double) * (size_t)N * 3);
+        OrcWork W;
+        W.Y = (double*)malloc(sizeof(double) * (size_t)N * 6);
+        W.Yn = (double*)malloc(sizeof(double) * (size_t)N * 6);
+        W.G = (double*)malloc(sizeof(double) * (size_t)N * 6);
+        W.rp = (double*)malloc(sizeof(double) * (size_t)N * 3 * (np > 0 ? np : 1));
+        W.vp = (double*)malloc(sizeof(double) * (size_t)N * 3 * (np > 0 ? np : 1));
+        W.cbuf = (double*)malloc(sizeof(double) * (size_t)(N + 2));
+        W.bbuf = (double*)malloc(sizeof(double) * (size_t)(N + 2));
+        W.dbuf = (double*)malloc(sizeof(double) * (size_t)(N + 2));
+        W.A2 = (double*)malloc(sizeof(double) * (size_t)N * 3);    /* order 2: a at the nodes */
+        W.X2 = (double*)malloc(sizeof(double) * (size_t)N * 3);
+        W.V2 = (double*)malloc(sizeof(double) * (size_t)N * 3);
+        W.dX2 = (double*)malloc(sizeof(double) * (size_t)N * 3);
+        W.dV2 = (double*)malloc(sizeof(double) * (size_t)N * 3);
 #pragma omp for schedule(dynamic, 1)
         for (int m = 0; m < n_ic; ++m) {
             double y0[6];
@@ -593,98 +758,39 @@ int orc_propagate(int n_ic, const double* ics, const double* t0, const double* t
                 double h = (tf[m] - t0[m]) / (double)S;
                 double Ts = t0[m] + h * s;
                 double Te = t0[m] + h * (s + 1);
-                double w1 = 0.5 * (Te + Ts), w2 = 0.5 * (Te - Ts);
-                /* perturber positions (and velocities, for EIH) at the nodes, before
-                   iterating (Sec. 5.4.1) */
-                for (int j = 0; j < N; ++j) {
-                    double tj = w2 * tau[j] + w1;
-                    for (int p = 0; p < np; ++p) {
-                        if (inv_c2 != 0.0)
-                            orc_ephem_state(pert + 7 * p, epoch, tj, rp + 3 * (j * np + p), vp + 3 * (j * np + p));
-                        else
-                            orc_ephem(pert + 7 * p, epoch, tj, rp + 3 * (j * np + p));
+                const double* sg = init == 2 ? guess + ((size_t)m * S + s) * N * 6 : NULL;
+                int status = orc_segment(&R, &W, y0, Ts, Te, sg);
+                double yend[6];
+                memcpy(yend, W.Y + 6 * (N - 1), sizeof(yend));
+                /* adaptive refinement: 2, 4, ... equal sub-segments from the same y0 */
+                for (int d = 1; status == -1 && d <= refine; ++d) {
+                    const int parts = 1 << d;
+                    const double hq = (Te - Ts) / (double)parts;
+                    double yq[6];
+                    memcpy(yq, y0, sizeof(yq));
+                    int total = 0, st = 0;
+                    for (int q = 0; q < parts; ++q) {
+                        int sq = orc_segment(&R, &W, yq, Ts + hq * q, Ts + hq * (q + 1), NULL);
+                        memcpy(yq, W.Y + 6 * (N - 1), sizeof(yq));
+                        if (sq == -2) { st = -2; break; }
+                        if (sq == -1) st = -1;
+                        else total += sq;
                     }
-                }
-                /* initial guess */
-                int cold = (init == 1);
-                if (init == 2) {
-                    for (int j = 0; j < N; ++j) {
-                        const double* gq = guess + (((size_t)m * S + s) * N + j) * 6;
-                        int fin = 1;
-                        for (int k = 0; k < 6; ++k) fin = fin && isfinite(gq[k]);
-                        memcpy(Y + 6 * j, fin ? gq : y0, sizeof(y0));
-                    }
-                } else if (!cold) {
-                    for (int j = 0; j < N; ++j) {
-                        double dt = w2 * (tau[j] + 1.0);
-                        if (orc_kepler(y0, dt, Y + 6 * j) != 0) { cold = 1; break; }
-                    }
-                }
-                if (cold)
-                    for (int j = 0; j < N; ++j) memcpy(Y + 6 * j, y0, sizeof(y0));
-                /* Picard iterations */
-                int status = -1;
-                int n_it = fixed_iters > 0 ? fixed_iters : max_iter;
-                for (int it = 1; it <= n_it; ++it) {
-                    /* (i) force matrix */
-                    for (int j = 0; j < N; ++j) {
-                        double acc[3];
-                        if (inv_c2 != 0.0)
-                            orc_accel_eih(Y + 6 * j, np, rp + 3 * j * np, vp + 3 * j * np, mup, mu_sun, inv_c2, acc);
-                        else
-                            orc_accel(Y + 6 * j, np, rp + 3 * j * np, mup, mu_sun, acc);
-                        for (int k = 0; k < 3; ++k) {
-                            G[6 * j + k] = w2 * Y[6 * j + 3 + k];
-                            G[6 * j + 3 + k] = w2 * acc[k];
-                            A2[3 * j + k] = acc[k];
-                        }
-                    }
-                    if (order == 2) {
-                        /* second-order form: velocity and position from the accelerations */
-                        orc_second_order_update(N, Tkj, A2, y0, y0 + 3, w2, tau, X2, V2, cbuf, bbuf, dbuf);
-                        if (feedback) {
-                            const double zero[3] = {0.0, 0.0, 0.0};
-                            for (int j = 0; j < N; ++j) {
-                                double J[9], dx[3];
-                                orc_accel_jac(Y + 6 * j, np, rp + 3 * j * np, mup, mu_sun, J);
-                                for (int k = 0; k < 3; ++k) dx[k] = X2[3 * j + k] - Y[6 * j + k];
-                                for (int k = 0; k < 3; ++k)
-                                    A2[3 * j + k] = J[3 * k] * dx[0] + J[3 * k + 1] * dx[1] + J[3 * k + 2] * dx[2];
-                            }
-                            orc_second_order_update(N, Tkj, A2, zero, zero, w2, tau, dX2, dV2, cbuf, bbuf, dbuf);
-                            for (int i = 0; i < 3 * N; ++i) {
-                                X2[i] += dX2[i];
-                                V2[i] += dV2[i];
-                            }
-                        }
-                        for (int j = 0; j < N; ++j)
-                            for (int k = 0; k < 3; ++k) {
-                                Yn[6 * j + k] = X2[3 * j + k];
-                                Yn[6 * j + 3 + k] = V2[3 * j + k];
-                            }
-                    } else {
-                        /* (ii)-(v) */
-                        orc_picard_update(N, 6, Tkj, G, y0, Yn, cbuf, bbuf);
-                    }
-                    /* (vi) */
-                    double e = orc_iter_error(N, Yn, Y, tol_mode);
-                    double* tmp = Y; Y = Yn; Yn = tmp;   /* Y is now the newest iterate */
-                    if (isnan(e)) { status = -2; break; }
-                    if (fixed_iters > 0) { if (it == n_it) status = it; continue; }
-                    if (e < tol) { status = it; break; }
+                    status = st < 0 ? st : total;
+                    memcpy(yend, yq, sizeof(yend));
                 }
                 *it_out = status;
                 if (status == -2) dead = 1;
                 if (nodes_out)
-                    memcpy(nodes_out + (((size_t)m * S + s) * N) * 6, Y, sizeof(double) * 6 * N);
-                memcpy(y0, Y + 6 * (N - 1), sizeof(y0));
+                    memcpy(nodes_out + (((size_t)m * S + s) * N) * 6, W.Y, sizeof(double) * 6 * N);
+                memcpy(y0, yend, sizeof(y0));
                 if (dead) for (int k = 0; k < 6; ++k) y0[k] = NAN;
                 if (bounds_out) memcpy(bounds_out + ((size_t)m * (S + 1) + s + 1) * 6, y0, sizeof(y0));
             }
             memcpy(states_out + 6 * m, y0, sizeof(y0));
         }
-        free(Y); free(Yn); free(G); free(rp); free(vp); free(cbuf); free(bbuf);
-        free(dbuf); free(A2); free(X2); free(V2); free(dX2); free(dV2);
+        free(W.Y); free(W.Yn); free(W.G); free(W.rp); free(W.vp); free(W.cbuf); free(W.bbuf);
+        free(W.dbuf); free(W.A2); free(W.X2); free(W.V2); free(W.dX2); free(W.dV2);
     }
     free(Tkj); free(tau);
     return used;

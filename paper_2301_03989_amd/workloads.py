@@ -190,6 +190,23 @@ def uneven_batch(n_ic: int = 65536, seed: int = 103) -> Workload:
     return Workload("uneven-batch-65536", ics, groups, planet_elements(), init=0)
 
 
+def long_segments(n_ic: int = 4096, seed: int = 107, nodes: int = 256, segments: int = 2,
+                  seg_len: float = 3.0 * np.pi, e_max: float = 0.4) -> Workload:
+    """Long segments: a ~ U[0.7, 1.0], e ~ U[0, e_max], inc ~ U[0, 10 deg], Sun + 8
+    planets, ``segments`` segments of ``seg_len`` TU (default 1.5 orbits of a = 1) at
+    ``nodes`` nodes, tol 1e-12, Kepler warm start.  The nodes resolve such a segment, but
+    the Picard iteration over it contracts too slowly for most ICs to converge within 64
+    sweeps: the input of adaptive segment refinement."""
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(0.7, 1.0, n_ic)
+    e = rng.uniform(0.0, e_max, n_ic)
+    inc = rng.uniform(0.0, 10.0, n_ic) * DEG
+    raan, argp, M = (rng.uniform(0.0, 360.0, n_ic) * DEG for _ in range(3))
+    ics = elements_to_states(a, e, inc, raan, argp, M)
+    return Workload(f"long-segments-{n_ic}", ics, [Group(0, n_ic, 0.0, segments * seg_len, nodes, segments, 1e-12)],
+                    planet_elements(), init=0)
+
+
 def mixed_precision(n_ic: int = 262144, seed: int = 104) -> Workload:
     """The N-body Venus ensemble at 262144 ICs, FP32 sweeps then FP64 refinement."""
     return nbody_venus(n_ic, seed, precision=1, name="nbody-venus-262144-fp32-fp64")

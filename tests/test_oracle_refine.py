@@ -1,0 +1,107 @@
+"""Pins of the oracle's adaptive segment refinement (orc_propagate, refine > 0): a segment
+whose Picard iterations do not converge within max_iter is solved again as 2, 4, ...
+equal sub-segments (the piecewise remedy of Sec. 2.2, per segment, as the adaptive
+variant cited in Sec. 1 chooses segment lengths).
+
+Pinned against something other than the refinement code itself: an independent
+integrator (scipy's DOP853 driving the oracle's force) on the refined trajectories, the
+unrefined oracle where nothing fails, and plain multi-segment oracle runs of the split
+spans for the chaining, time grid and count bookkeeping."""
+import numpy as np
+import pytest
+from scipy.integrate import solve_ivp
+
+import oracle
+from paper_2301_03989_amd import workloads as W
+
+
+def _run(w, **kw):
+    g = w.groups[0]
+    return oracle.propagate(w.ics, g.t0, g.tf, g.nodes, g.segments, g.tol, oracle.Model(1.0, w.pert, 0.0),
+                            want_bounds=True, **kw)
+
+
+def _rel(a, b):
+    er = np.linalg.norm(a[..., :3] - b[..., :3], axis=-1) / np.linalg.norm(b[..., :3], axis=-1)
+    ev = np.linalg.norm(a[..., 3:] - b[..., 3:], axis=-1) / np.linalg.norm(b[..., 3:], axis=-1)
+    return np.maximum(er, ev)
+
+
+@pytest.fixture(scope="module")
+def ecc():
+    return W.long_segments(24, seed=5)
+
+
+def test_refinement_changes_nothing_where_every_segment_converges():
+    w = W.nbody_venus(16, seed=4, days=112.5, segments=2)
+    a = _run(w)
+    b = _run(w, refine=3)
+    assert (a[1] > 0).all()
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_refined_trajectories_match_an_independent_integrator(ecc):
+    s0, i0, b0 = _run(ecc)
+    s2, i2, b2 = _run(ecc, refine=2)
+    failed = np.nonzero((i0 < 0).any(axis=1))[0]
+    assert failed.size >= 3            # the workload does exercise refinement
+    assert (i2 > 0).all()              # and two halvings resolve every segment
+    model = oracle.Model(1.0, ecc.pert, 0.0)
+    g = ecc.groups[0]
+
+    def f(t, y):
+        return np.concatenate([y[3:], oracle.accel_t(y[:3], t, model)])
+    e_ref, e_unref = [], []
+    for m in failed[:6]:
+        ref = solve_ivp(f, (g.t0, g.tf), ecc.ics[m], method="DOP853", rtol=1e-13, atol=1e-16).y[:, -1]
+        e_ref.append(_rel(s2[m], ref))
+        e_unref.append(_rel(s0[m], ref))
+    assert max(e_ref) < 1e-10, e_ref
+    # the unrefined run kept non-converged iterates, some of them visibly off
+    assert max(e_unref) > 1e-9, e_unref
+
+
+def test_refined_segment_equals_the_split_span_run(ecc):
+    g = ecc.groups[0]
+    model = oracle.Model(1.0, ecc.pert, 0.0)
+    s0, i0, b0 = _run(ecc)
+    s1, i1, b1 = _run(ecc, refine=1)
+    h = (g.tf - g.t0) / g.segments
+    checked = 0
+    for m in range(ecc.n_ic):
+        bad = np.nonzero(i0[m] < 0)[0]
+        if bad.size == 0:
+            # nothing refined: identical to the unrefined run
+            assert np.array_equal(s0[m], s1[m]) and np.array_equal(i0[m], i1[m])
+            continue
+        s = bad[0]
+        # segments before the first failure are untouched
+        assert np.array_equal(b0[m, :s + 1], b1[m, :s + 1]) and np.array_equal(i0[m, :s], i1[m, :s])
+        Ts, Te = g.t0 + h * s, g.t0 + h * (s + 1)
+        st, it = oracle.propagate(b1[m, s][None], Ts, Te, g.nodes, 2, g.tol, model)
+        assert np.array_equal(st[0], b1[m, s + 1])
+        assert i1[m, s] == (it.sum() if (it > 0).all() else -1)
+        checked += 1
+    assert checked >= 3
+
+
+def test_finest_split_that_still_fails_records_minus_one(ecc):
+    g = ecc.groups[0]
+    model = oracle.Model(1.0, ecc.pert, 0.0)
+    s, it, b = _run(ecc, refine=1, max_iter=4)
+    assert (it == -1).any()
+    h = (g.tf - g.t0) / g.segments
+    m, k = np.argwhere(it == -1)[0]
+    first = np.nonzero(it[m] == -1)[0][0]
+    assert first == k
+    st, itq = oracle.propagate(b[m, k][None], g.t0 + h * k, g.t0 + h * (k + 1), g.nodes, 2, g.tol, model,
+                               max_iter=4)
+    assert (itq == -1).any()
+    assert np.array_equal(st[0], b[m, k + 1])
+
+
+def test_refinement_refuses_node_outputs_and_guesses(ecc):
+    g = ecc.groups[0]
+    with pytest.raises(ValueError):
+        oracle.propagate(ecc.ics, g.t0, g.tf, g.nodes, g.segments, g.tol, refine=1, want_nodes=True)
