@@ -190,13 +190,30 @@ def uneven_batch(n_ic: int = 65536, seed: int = 103) -> Workload:
     return Workload("uneven-batch-65536", ics, groups, planet_elements(), init=0)
 
 
-def long_segments(n_ic: int = 4096, seed: int = 107, nodes: int = 256, segments: int = 2,
-                  seg_len: float = 3.0 * np.pi, e_max: float = 0.4) -> Workload:
+def eccentric(nodes: int, n_ic: int = 16384, seed: int = 108, segments: int = 16) -> Workload:
+    """One node count of the uneven batch's recipe: a ~ U[0.7, 1.0], e ~ U[0, 0.6],
+    inc ~ U[0, 10 deg], ``segments`` segments of pi/4 TU at ``nodes`` nodes, tol 1e-12,
+    Sun + 8 planets.  Used to profile the job body of each node count on its own."""
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(0.7, 1.0, n_ic)
+    e = rng.uniform(0.0, 0.6, n_ic)
+    inc = rng.uniform(0.0, 10.0, n_ic) * DEG
+    raan, argp, M = (rng.uniform(0.0, 360.0, n_ic) * DEG for _ in range(3))
+    ics = elements_to_states(a, e, inc, raan, argp, M)
+    return Workload(f"eccentric-{n_ic}-n{nodes}", ics,
+                    [Group(0, n_ic, 0.0, segments * np.pi / 4.0, nodes, segments, 1e-12)], planet_elements(), init=0)
+
+
+def long_segments(n_ic: int = 4096, seed: int = 107, nodes: int = 128, segments: int = 2,
+                  seg_len: float = np.pi, e_max: float = 0.4) -> Workload:
     """Long segments: a ~ U[0.7, 1.0], e ~ U[0, e_max], inc ~ U[0, 10 deg], Sun + 8
-    planets, ``segments`` segments of ``seg_len`` TU (default 1.5 orbits of a = 1) at
-    ``nodes`` nodes, tol 1e-12, Kepler warm start.  The nodes resolve such a segment, but
-    the Picard iteration over it contracts too slowly for most ICs to converge within 64
-    sweeps: the input of adaptive segment refinement."""
+    planets, ``segments`` segments of ``seg_len`` TU (default half an orbit of a = 1) at
+    ``nodes`` nodes, tol 1e-12, Kepler warm start.  At the defaults the ICs need 20 to 32
+    sweeps per segment (median 26), and the change between sweeps settles near 1e-14, far
+    below tol, so a sweep budget of 24 (max_iter) leaves most segments unconverged for a
+    reason other than rounding: the input of adaptive segment refinement.  (Much longer
+    segments at 256 nodes settle at 1e-12..1e-11, where a 1e-12 stopping rule no longer
+    separates converged from unconverged.)"""
     rng = np.random.default_rng(seed)
     a = rng.uniform(0.7, 1.0, n_ic)
     e = rng.uniform(0.0, e_max, n_ic)
@@ -237,4 +254,8 @@ WORKLOADS = {
     "nbody-venus-262144-fp32-fp64": mixed_precision,
     "nbody-venus-16384-256d": adjoint_ensemble,
     "nbody-venus-4096-eih": relativistic,
+    "eccentric-16384-n64": lambda: eccentric(64),
+    "eccentric-16384-n128": lambda: eccentric(128),
+    "eccentric-16384-n256": lambda: eccentric(256),
+    "long-segments-4096": long_segments,
 }
