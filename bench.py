@@ -381,7 +381,8 @@ def main():
         mf, fm, cp = ctx.measure_ceilings(1024)
         ceilings = {"fp64_mfma_tflops": round(mf, 2), "fp64_fma_tflops": round(fm, 2), "copy_gbs": round(cp, 1),
                     "how": "pc_measure_ceilings: independent v_mfma_f64_16x16x4 chains (2 waves per SIMD), "
-                           "independent FP64 FMA chains (8 waves per SIMD), a 512 MiB device copy; best of 3"}
+                           "independent FP64 FMA chains (8 waves per SIMD), a 512 MiB device copy; best of 5 "
+                           "after about 50 ms of untimed runs"}
         print(f"bench: on-chip ceilings: FP64 MFMA {mf:.1f} TFLOP/s, FP64 FMA {fm:.1f} TFLOP/s, copy {cp:.0f} GB/s",
               flush=True)
 

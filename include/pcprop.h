@@ -168,6 +168,22 @@ typedef struct {
                              layout of the same call's nodes_out (e.g. the nodes_out of an
                              earlier call); a non-finite row falls back to the segment's
                              initial state at that node.  NULL otherwise (default) */
+    int32_t refine;       /* adaptive segment refinement, 0 (default, off) .. 8, fused path:
+                             long spans are integrated piecewise because the iteration does not
+                             hold over too long a piece (Sec. 2.2), and the adaptive variant of
+                             the method cited in Sec. 1 sets the piece length per segment.  A
+                             segment whose sweeps do not converge within max_iter is solved
+                             again from its initial state as 2, then 4, ... up to 2^refine equal
+                             sub-segments of the same node count (each with its own warm start
+                             and sweeps) until all of them converge; its iters_out entry is then
+                             the sum of their sweep counts (PC_ITER_NOTCONV, with the finest
+                             split's end state, if that still fails), bounds_out and states_out
+                             take the new states, and the rest of the span is run again from
+                             there on the original segment grid.  Runs after the main launch,
+                             in passes of up to 8192 refined ICs (one launch each).  Needs
+                             iters_out and bounds_out, takes no nodes_out and no guess;
+                             pc_workspace_bytes includes its region.  iters_out, bounds_out and
+                             states_out of ICs that need no refinement are those of refine = 0. */
 } pc_opts;
 
 /* One outer-level group of the two-level augmentation (Sec. 3.2): ICs

@@ -425,7 +425,16 @@ struct Plan {
     size_t plain_stride = 0;   // bytes of one plain-path state (one per stream)
     int plain_streams = 1;
     size_t staged = 0;   // bytes of [counters .. bodies] copied from the staging buffer
+    // adaptive refinement (opts.refine > 0): a region after the call's own, holding the
+    // sub-calls' inputs and outputs, copy descriptors and workspace
+    size_t off_refine = 0, ref_ics = 0, ref_states = 0, ref_iters = 0, ref_bounds = 0, ref_copies = 0,
+           ref_sub = 0, ref_sub_cap = 0;
+    int refine_smax = 0;          // segment stride of the sub-calls' records
+    int64_t refine_budget = 0;    // ephemeris records one refinement pass may plan
 };
+
+// Tasks of one refinement pass at most (the pass's buffers are sized for this many).
+constexpr int64_t kRefineChunk = 8192;
 
 int log2_index(int np)
 {
@@ -453,8 +462,11 @@ int choose_pairs(const pc_ctx* ctx, const pc_group* groups, int n_groups, const 
 // A plan without lists has the most jobs, so its workspace size bounds every other plan's.
 // cached_only: take the operators from the context's cache and fail where one is missing
 // (the allocation-free entry point builds none).
+// seg0 (or null): per group, the first segment to run on its t0 + k h grid (refinement
+// passes resume a span at a segment boundary); the group then runs segments - seg0[g].
 int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, const pc_model* model,
-              const pc_opts& o, bool build_tables, Plan& plan, bool lists_ok = false, bool cached_only = false)
+              const pc_opts& o, bool build_tables, Plan& plan, bool lists_ok = false, bool cached_only = false,
+              const int* seg0 = nullptr)
 {
     if (!groups || n_groups < 1) return set_error(ctx, PC_EINVAL, "need at least one group");
     if (o.tile_pairs != 0 && o.tile_pairs != 1024 && o.tile_pairs != 2048)
@@ -486,6 +498,8 @@ int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, c
         if (G.nodes < 3 || G.nodes > PC_MAX_NODES)
             return set_error(ctx, PC_EINVAL, "group %d: nodes must be in [3, %d]", gi, PC_MAX_NODES);
         if (G.segments < 1) return set_error(ctx, PC_EINVAL, "group %d: segments < 1", gi);
+        if (seg0 && (seg0[gi] < 0 || seg0[gi] >= G.segments))
+            return set_error(ctx, PC_EINVAL, "group %d: first segment out of range", gi);
         if (!std::isfinite(G.t0) || !std::isfinite(G.tf) || G.t0 == G.tf)
             return set_error(ctx, PC_EINVAL, "group %d: need finite t0 != tf", gi);
         if (!(G.tol > 0.0) || !std::isfinite(G.tol))
@@ -494,7 +508,7 @@ int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, c
         if (NP * 8 > plan.pairs)
             return set_error(ctx, PC_EINVAL, "group %d: %d nodes need tile_pairs >= %d", gi, G.nodes, NP * 8);
         spans.push_back({G.ic_offset, G.ic_offset + G.n_ic});
-        plan.max_S = std::max(plan.max_S, G.segments);
+        plan.max_S = std::max(plan.max_S, G.segments - (seg0 ? seg0[gi] : 0));
         plan.max_N = std::max(plan.max_N, G.nodes);
     }
     std::sort(spans.begin(), spans.end());
@@ -558,7 +572,8 @@ int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, c
         d.N = G.nodes;
         d.NP = padded_nodes(G.nodes);
         d.T = plan.pairs / d.NP;
-        d.S = G.segments;
+        d.s0 = seg0 ? seg0[gi] : 0;
+        d.S = G.segments - d.s0;
         if (build_tables) {
             const OperatorCache* oc = nullptr;
             if (cached_only && ctx->ops.find(G.nodes) == ctx->ops.end())
@@ -574,7 +589,7 @@ int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, c
             d.kfrag2 = oc->kfrag2;
             d.tau = oc->tau;
         }
-        plan.n_recs += (int64_t)G.segments * G.nodes;
+        plan.n_recs += (int64_t)d.S * G.nodes;
         plan.groups.push_back(d);
         // cost model of one job: segments x NP x column blocks (matrix work per iteration
         // ~ NP^2 T = NP * PAIRS per block)
@@ -584,7 +599,7 @@ int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, c
             j.ic0 = G.ic_offset + i0;
             j.group = gi;
             j.n = (int)std::min<int64_t>(per_job, G.n_ic - i0);
-            const double c = (double)G.segments * (double)d.NP * (double)((j.n + d.T - 1) / d.T);
+            const double c = (double)d.S * (double)d.NP * (double)((j.n + d.T - 1) / d.T);
             costs.push_back({d.NP, c, j});
         }
     }
@@ -627,6 +642,33 @@ int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, c
         off = align_up(off + plan.plain_stride * plan.plain_streams);
     }
     plan.total = off;
+    if (o.refine > 0 && !plan.plain) {
+        // region of the refinement passes: up to kRefineChunk tasks per pass, each pass
+        // planning at most refine_budget ephemeris records (enough for the longest single
+        // task: a whole group's span, or one segment split 2^refine ways)
+        const int parts = 1 << o.refine;
+        plan.refine_smax = std::max(plan.max_S, parts);
+        plan.refine_budget = plan.n_recs;
+        for (int gi = 0; gi < n_groups; ++gi)
+            plan.refine_budget = std::max<int64_t>(plan.refine_budget,
+                                                   (int64_t)std::max((int)groups[gi].segments, parts) * groups[gi].nodes);
+        const int64_t C = kRefineChunk;
+        size_t r = 0;
+        plan.ref_ics = r;    r = align_up(r + (size_t)C * 6 * sizeof(double));
+        plan.ref_states = r; r = align_up(r + (size_t)C * 6 * sizeof(double));
+        plan.ref_iters = r;  r = align_up(r + (size_t)C * plan.refine_smax * sizeof(int32_t));
+        plan.ref_bounds = r; r = align_up(r + (size_t)C * (plan.refine_smax + 1) * 6 * sizeof(double));
+        plan.ref_copies = r; r = align_up(r + (size_t)2 * C * sizeof(PcCopyDev));
+        plan.ref_sub = r;
+        size_t rec_bytes = (size_t)(P + 1) * 4 * sizeof(double);
+        if (model->inv_c2 > 0.0) rec_bytes += (size_t)(3 * (P + 1) + 1) * 4 * sizeof(double);
+        plan.ref_sub_cap = 8 * kAlign + 4 * sizeof(int32_t) + std::max(sizeof(PcParams), sizeof(PcAdjParams)) +
+                           (size_t)C * (sizeof(PcGroupDev) + sizeof(PcJobDev)) + std::max(1, P) * sizeof(PcBodyDev) +
+                           (size_t)plan.refine_budget * rec_bytes;
+        r = align_up(r + plan.ref_sub_cap);
+        plan.off_refine = plan.total;
+        plan.total += r;
+    }
     return PC_OK;
 }
 
@@ -664,6 +706,9 @@ int validate_forward(pc_ctx* ctx, const pc_opts& o, const pc_model* model)
     if (o.order == 2 && (o.path != PC_PATH_FUSED || o.precision != PC_FP64 || model->inv_c2 > 0.0 ||
                          o.conv != PC_CONV_PER_IC))
         return set_error(ctx, PC_EINVAL, "order 2 runs on the fused FP64 path, point masses, per-IC rule");
+    if (o.refine < 0 || o.refine > 8) return set_error(ctx, PC_EINVAL, "refine must be 0..8");
+    if (o.refine > 0 && (o.path != PC_PATH_FUSED || o.init == PC_INIT_GUESS))
+        return set_error(ctx, PC_EINVAL, "refinement runs on the fused path and without a guess");
     return PC_OK;
 }
 
@@ -724,6 +769,195 @@ void stage_call(pc_ctx* ctx, const Plan& plan, const pc_model* model, const pc_o
     std::memcpy(st + plan.off_params, &pp, sizeof(pp));   // the device copy the kernel reads
 }
 
+// Adaptive segment refinement after a fused call (opts.refine > 0), on the call's stream.
+// A segment that ended PC_ITER_NOTCONV is solved again from its initial state (its
+// boundary record) as 2, then 4, ... up to 2^refine equal sub-segments, until all of them
+// converge (each a complete segment solve: own warm start, own sweeps); it then records
+// the sum of their sweep counts (or PC_ITER_NOTCONV with the finest split's end state).
+// The rest of the span is run again from the new boundary, on the original segment grid,
+// and its first failing segment, if any, is refined in turn.  Tasks of one kind, group and
+// segment run as one group of a sub-call; one pass is one fused launch over up to
+// kRefineChunk tasks.  iters_out and bounds_out hold the call's records and are rewritten.
+// Returns the call's status from the final records.
+int refine_passes(pc_ctx* ctx, const Plan& plan, const pc_group* groups, int n_groups, const pc_model* model,
+                  const pc_opts& o, bool lists_ok, char* ws, int64_t n_ic, double* states_out, int32_t* iters_out,
+                  int32_t stride, double* bounds_out, hipStream_t hs)
+{
+    struct Task {
+        int64_t m;   // IC
+        int g;       // group
+        int s;       // segment
+        int depth;   // > 0: split segment s into 2^depth parts; 0: run segments s.. to the end
+    };
+    const int smax = plan.refine_smax;
+    char* R = ws + plan.off_refine;
+    double* ics_sub = reinterpret_cast<double*>(R + plan.ref_ics);
+    double* states_sub = reinterpret_cast<double*>(R + plan.ref_states);
+    int32_t* iters_sub = reinterpret_cast<int32_t*>(R + plan.ref_iters);
+    double* bounds_sub = reinterpret_cast<double*>(R + plan.ref_bounds);
+    PcCopyDev* copies_dev = reinterpret_cast<PcCopyDev*>(R + plan.ref_copies);
+    char* sub_ws = R + plan.ref_sub;
+
+    std::vector<int32_t> it((size_t)n_ic * stride);
+    PC_HIP_DRAIN(ctx, hs, hipMemcpyAsync(it.data(), iters_out, it.size() * sizeof(int32_t), hipMemcpyDeviceToHost, hs));
+    PC_HIP(ctx, hipStreamSynchronize(hs));
+    std::vector<Task> pending;
+    // the first failing segment of every IC (none after a non-finite one)
+    auto first_failure = [&](int64_t m, int gi, int from) {
+        for (int s = from; s < groups[gi].segments; ++s) {
+            const int32_t v = it[(size_t)m * stride + s];
+            if (v == PC_ITER_NONFINITE) return;
+            if (v == PC_ITER_NOTCONV) {
+                pending.push_back({m, gi, s, 1});
+                return;
+            }
+        }
+    };
+    for (int gi = 0; gi < n_groups; ++gi)
+        for (int64_t m = groups[gi].ic_offset; m < groups[gi].ic_offset + groups[gi].n_ic; ++m) first_failure(m, gi, 0);
+
+    pc_opts so = o;
+    so.refine = 0;
+    so.graph = 0;
+    int occ = 0;
+    std::vector<int32_t> its;
+    std::vector<PcCopyDev> cp;
+    while (!pending.empty()) {
+        std::stable_sort(pending.begin(), pending.end(), [](const Task& a, const Task& b) {
+            if (a.g != b.g) return a.g < b.g;
+            if (a.s != b.s) return a.s < b.s;
+            return a.depth < b.depth;
+        });
+        std::vector<pc_group> sg;
+        std::vector<int> s0;
+        std::vector<Task> pass;
+        int64_t recs = 0;
+        size_t take = 0;
+        for (size_t i = 0; i < pending.size() && (int64_t)pass.size() < kRefineChunk; ++i) {
+            const Task& t = pending[i];
+            const pc_group& G = groups[t.g];
+            const bool fresh = pass.empty() || t.g != pass.back().g || t.s != pass.back().s ||
+                               t.depth != pass.back().depth;
+            if (fresh) {
+                const int segs = t.depth > 0 ? (1 << t.depth) : G.segments - t.s;
+                const int64_t r = (int64_t)segs * G.nodes;
+                if (!pass.empty() && recs + r > plan.refine_budget) break;
+                recs += r;
+                pc_group q = G;
+                q.ic_offset = (int64_t)pass.size();
+                q.n_ic = 0;
+                if (t.depth > 0) {   // segment s alone, split; its ends as the oracle forms them
+                    const double h = (G.tf - G.t0) / (double)G.segments;
+                    q.t0 = G.t0 + h * t.s;
+                    q.tf = G.t0 + h * (t.s + 1);
+                    q.segments = segs;
+                    s0.push_back(0);
+                } else {             // segments s.. of the group's own grid
+                    s0.push_back(t.s);
+                }
+                sg.push_back(q);
+            }
+            pass.push_back(t);
+            ++sg.back().n_ic;
+            take = i + 1;
+        }
+        pending.erase(pending.begin(), pending.begin() + take);
+        const int64_t np = (int64_t)pass.size();
+
+        Plan sub;
+        int rc = make_plan(ctx, np, sg.data(), (int)sg.size(), model, so, true, sub, lists_ok, false, s0.data());
+        if (rc != PC_OK) return rc;
+        if (sub.total > plan.ref_sub_cap)
+            return set_error(ctx, PC_EHIP, "refinement pass needs %zu bytes of %zu", sub.total, plan.ref_sub_cap);
+        // gathers: each task starts from the boundary record of its segment
+        cp.resize(np);
+        for (int64_t k = 0; k < np; ++k)
+            cp[k] = {bounds_out + ((size_t)pass[k].m * (stride + 1) + pass[k].s) * 6, ics_sub + k * 6, 6};
+        const size_t dcopy = align_up(sub.staged);
+        rc = ensure_staging(ctx, dcopy + 2 * kRefineChunk * sizeof(PcCopyDev) + kAlign);
+        if (rc != PC_OK) return rc;
+        char* st = static_cast<char*>(ctx->staging);
+        std::memcpy(st + dcopy, cp.data(), np * sizeof(PcCopyDev));
+        PcEphemParams ep;
+        PcParams pp;
+        stage_call(ctx, sub, model, so, sub_ws, ics_sub, states_sub, iters_sub, smax, bounds_sub, nullptr, 0, ep, pp);
+        const PcParams* pp_dev = reinterpret_cast<const PcParams*>(sub_ws + sub.off_params);
+        PC_HIP_DRAIN(ctx, hs, (hipError_t)pc_fused_occupancy(sub.pairs, &occ));
+        const int grid = std::max(1, ctx->n_cu * std::max(1, occ));
+        PC_HIP_DRAIN(ctx, hs, hipMemcpyAsync(copies_dev, st + dcopy, np * sizeof(PcCopyDev), hipMemcpyHostToDevice, hs));
+        PC_HIP_DRAIN(ctx, hs, (hipError_t)pc_launch_copy_runs(copies_dev, np, hs));
+        PC_HIP_DRAIN(ctx, hs, hipMemcpyAsync(sub_ws, st, sub.staged, hipMemcpyHostToDevice, hs));
+        PC_HIP_DRAIN(ctx, hs, (hipError_t)pc_launch_ephem(ep, hs));
+        if (ctx->timing) PC_HIP_DRAIN(ctx, hs, hipEventRecord(ctx->ev0, hs));
+        PC_HIP_DRAIN(ctx, hs, (hipError_t)pc_launch_fused(pp, pp_dev, sub.pairs, grid, hs));
+        if (ctx->timing) PC_HIP_DRAIN(ctx, hs, hipEventRecord(ctx->ev1, hs));
+        its.resize((size_t)np * smax);
+        PC_HIP_DRAIN(ctx, hs, hipMemcpyAsync(its.data(), iters_sub, its.size() * sizeof(int32_t), hipMemcpyDeviceToHost, hs));
+        PC_HIP(ctx, hipStreamSynchronize(hs));
+        if (ctx->timing) {
+            float ms = 0.0f;
+            PC_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+            ctx->last_ms += ms;
+        }
+        // results: accept or split further; scatter accepted records into the outputs
+        cp.clear();
+        for (int64_t k = 0; k < np; ++k) {
+            const Task& t = pass[k];
+            const int S = groups[t.g].segments;
+            const int32_t* r = its.data() + (size_t)k * smax;
+            double* brow = bounds_out + (size_t)t.m * (stride + 1) * 6;
+            int32_t* irow = it.data() + (size_t)t.m * stride;
+            if (t.depth > 0) {
+                int32_t st_ = 0, total = 0;
+                for (int q = 0; q < (1 << t.depth); ++q) {
+                    if (r[q] == PC_ITER_NONFINITE) { st_ = PC_ITER_NONFINITE; break; }
+                    if (r[q] == PC_ITER_NOTCONV) st_ = PC_ITER_NOTCONV;
+                    else total += r[q];
+                }
+                const int32_t status = st_ < 0 ? st_ : total;
+                if (status == PC_ITER_NOTCONV && t.depth < o.refine) {
+                    pending.push_back({t.m, t.g, t.s, t.depth + 1});
+                    continue;
+                }
+                irow[t.s] = status;
+                cp.push_back({states_sub + k * 6, brow + (size_t)(t.s + 1) * 6, 6});
+                if (t.s + 1 < S) pending.push_back({t.m, t.g, t.s + 1, 0});
+                else cp.push_back({states_sub + k * 6, states_out + (size_t)t.m * 6, 6});
+            } else {
+                for (int j = 0; j < S - t.s; ++j) irow[t.s + j] = r[j];
+                cp.push_back({bounds_sub + ((size_t)k * (smax + 1) + 1) * 6, brow + (size_t)(t.s + 1) * 6,
+                              (int64_t)(S - t.s) * 6});
+                cp.push_back({states_sub + k * 6, states_out + (size_t)t.m * 6, 6});
+                first_failure(t.m, t.g, t.s);
+            }
+        }
+        if (!cp.empty()) {
+            std::memcpy(st + dcopy, cp.data(), cp.size() * sizeof(PcCopyDev));
+            PC_HIP_DRAIN(ctx, hs, hipMemcpyAsync(copies_dev, st + dcopy, cp.size() * sizeof(PcCopyDev),
+                                                 hipMemcpyHostToDevice, hs));
+            PC_HIP_DRAIN(ctx, hs, (hipError_t)pc_launch_copy_runs(copies_dev, (int64_t)cp.size(), hs));
+            PC_HIP(ctx, hipStreamSynchronize(hs));   // the staging buffer is written again next pass
+        }
+    }
+    PC_HIP_DRAIN(ctx, hs, hipMemcpyAsync(iters_out, it.data(), it.size() * sizeof(int32_t), hipMemcpyHostToDevice, hs));
+    PC_HIP(ctx, hipStreamSynchronize(hs));
+    int notconv = 0, nonfinite = 0;
+    for (int gi = 0; gi < n_groups; ++gi)
+        for (int64_t m = groups[gi].ic_offset; m < groups[gi].ic_offset + groups[gi].n_ic; ++m) {
+            bool nc = false, nf = false;
+            for (int s = 0; s < groups[gi].segments; ++s) {
+                nc = nc || it[(size_t)m * stride + s] == PC_ITER_NOTCONV;
+                nf = nf || it[(size_t)m * stride + s] == PC_ITER_NONFINITE;
+            }
+            notconv += nc;
+            nonfinite += nf;
+        }
+    if (nonfinite > 0) return set_error(ctx, PC_ENONFINITE, "%d initial conditions became non-finite", nonfinite);
+    if (notconv > 0)
+        return set_error(ctx, PC_ENOTCONV, "%d initial conditions did not converge after refinement", notconv);
+    return PC_OK;
+}
+
 pc_opts defaults()
 {
     pc_opts o;
@@ -754,6 +988,7 @@ void pc_default_opts(pc_opts* o)
     o->order = 1;
     o->feedback = 0;
     o->guess = nullptr;
+    o->refine = 0;
 }
 
 int pc_version(void) { return PC_VERSION; }
@@ -866,6 +1101,9 @@ static int propagate_impl(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc
     const pc_opts o = opts ? *opts : defaults();
     rc = validate_forward(ctx, o, model);
     if (rc != PC_OK) return rc;
+    if (o.refine > 0 && (!iters_out || !bounds_out || nodes_out || no_alloc))
+        return set_error(ctx, PC_EINVAL, "refinement needs iters_out and bounds_out, takes no nodes_out and "
+                         "does not run in the allocation-free call");
     if (no_alloc) {
         if (o.path != PC_PATH_FUSED) return set_error(ctx, PC_EINVAL, "the allocation-free call runs the fused path");
         if (o.graph) return set_error(ctx, PC_EINVAL, "the allocation-free call does not capture graphs");
@@ -876,9 +1114,9 @@ static int propagate_impl(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc
     const bool eih = model->inv_c2 > 0.0;
     PC_HIP(ctx, hipSetDevice(ctx->device));
     Plan plan;
-    rc = make_plan(ctx, n_ic, groups, n_groups, model, o, true, plan,
-                   o.path == PC_PATH_FUSED && o.precision == PC_FP64 && !eih && o.order == 1 &&
-                   o.init != PC_INIT_GUESS, no_alloc);
+    const bool lists_ok = o.path == PC_PATH_FUSED && o.precision == PC_FP64 && !eih && o.order == 1 &&
+                          o.init != PC_INIT_GUESS;
+    rc = make_plan(ctx, n_ic, groups, n_groups, model, o, true, plan, lists_ok, no_alloc);
     if (rc != PC_OK) return rc;
     if ((iters_out || bounds_out || nodes_out) && iters_stride < plan.max_S)
         return set_error(ctx, PC_EINVAL, "iters_stride %d < %d segments", iters_stride, plan.max_S);
@@ -1068,6 +1306,9 @@ static int propagate_impl(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc
         PC_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
         ctx->last_ms = ms;
     }
+    if (o.refine > 0 && hc[0] > 0)
+        return refine_passes(ctx, plan, groups, n_groups, model, o, lists_ok, ws, n_ic, states_out, iters_out,
+                             iters_stride, bounds_out, hs);
     if (hc[1] > 0) return set_error(ctx, PC_ENONFINITE, "%d initial conditions became non-finite", hc[1]);
     if (hc[0] > 0) return set_error(ctx, PC_ENOTCONV, "%d initial conditions did not converge", hc[0]);
     return PC_OK;

@@ -22,7 +22,7 @@
 #define PC_MAX_PERT_DEV 16       // perturbers per force evaluation
 
 struct PcGroupDev {
-    double t0, h, tol;         // segment s spans [t0 + s h, t0 + (s+1) h]
+    double t0, h, tol;         // segment s spans [t0 + (s0 + s) h, t0 + (s0 + s + 1) h]
     int64_t ic_offset, n_ic;
     int64_t rec_offset;        // first ephemeris record of the group (S * N records)
     const double* kfrag;       // [NP/16][NP/4][64]
@@ -32,6 +32,8 @@ struct PcGroupDev {
     const double* kfrag2;      // fragments of the double-integration operator K2_N (second order)
     const double* tau;         // [NP] CGL nodes, zero past N
     int32_t N, NP, T, S;
+    int32_t s0;                // first segment of the group on the t0 + k h grid (a call that
+                               // resumes a span at one of its segment boundaries), else 0
 };
 
 struct PcJobDev {
@@ -104,6 +106,14 @@ struct PcEphemParams {
     double mu_sun;
 };
 
+// One contiguous run of doubles to copy (the gathers and scatters between a call's
+// outputs and the sub-calls of its refinement passes).
+struct PcCopyDev {
+    const double* src;
+    double* dst;
+    int64_t n;
+};
+
 // Launchers (pc_kernels.hip).  All return a hipError_t as int.
 int pc_launch_ephem(const PcEphemParams& p, void* stream);
 // The launchers take the parameter block twice: by value for its host-side fields (job
@@ -111,6 +121,8 @@ int pc_launch_ephem(const PcEphemParams& p, void* stream);
 // that the kernels read, so that no lane keeps a private copy of it.
 int pc_launch_fused(const PcParams& p, const PcParams* p_dev, int pairs, int grid, void* stream);
 int pc_fused_occupancy(int pairs, int* blocks_per_cu);
+// list: device [n] copy descriptors, one workgroup each.
+int pc_launch_copy_runs(const PcCopyDev* list, int64_t n, void* stream);
 int pc_launch_adjoint(const PcAdjParams& a, const PcAdjParams* a_dev, int grid, void* stream);
 int pc_launch_apply_operator(int NP, const double* kfrag, int N, int64_t n_cols, const double* F,
                              const double* y0, double scale, double* Y, void* stream);

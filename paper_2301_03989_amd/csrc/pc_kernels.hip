@@ -29,7 +29,7 @@ __global__ void pc_ephem_kernel(const PcEphemParams p)
     const int64_t local = i - G.rec_offset;
     const int s = (int)(local / G.N);
     const int j = (int)(local - (int64_t)s * G.N);
-    const double Ts = G.t0 + G.h * s, Te = G.t0 + G.h * (s + 1);
+    const double Ts = G.t0 + G.h * (s + G.s0), Te = G.t0 + G.h * (s + G.s0 + 1);
     const double t = 0.5 * (Te - Ts) * G.tau[j] + 0.5 * (Te + Ts);   // eq. chnodes1
     const int P = p.n_pert;
     double4* rec = reinterpret_cast<double4*>(p.recs) + i * (P + 1);
@@ -84,6 +84,20 @@ int pc_launch_ephem(const PcEphemParams& p, void* stream)
     const int bs = 256;
     const int64_t grid = (p.n_recs + bs - 1) / bs;
     hipLaunchKernelGGL(pc_ephem_kernel, dim3((unsigned)grid), dim3(bs), 0, (hipStream_t)stream, p);
+    return hipGetLastError();
+}
+
+// Copies of contiguous runs of doubles, one workgroup per descriptor.
+__global__ __launch_bounds__(64) void pc_copy_runs_kernel(const PcCopyDev* __restrict__ list)
+{
+    const PcCopyDev c = list[blockIdx.x];
+    for (int64_t i = threadIdx.x; i < c.n; i += blockDim.x) c.dst[i] = c.src[i];
+}
+
+int pc_launch_copy_runs(const PcCopyDev* list, int64_t n, void* stream)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(pc_copy_runs_kernel, dim3((unsigned)n), dim3(64), 0, (hipStream_t)stream, list);
     return hipGetLastError();
 }
 
@@ -146,7 +160,7 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
     const int64_t ic = ic0 + tid;
     const bool rec_lds = N * 3 * (P + 1) <= rec_cap;
     const double t2 = g.tol * g.tol;
-    const double Ts = g.t0 + g.h * s, Te = g.t0 + g.h * (s + 1);
+    const double Ts = g.t0 + g.h * (s + g.s0), Te = g.t0 + g.h * (s + g.s0 + 1);
     const double w2 = 0.5 * (Te - Ts);
 
     // this segment's ephemeris records into LDS (perturber data per node, Sec. 5.4.1)
@@ -506,7 +520,7 @@ __device__ __attribute__((noinline)) void pc_job_list(const PcParams& p, const P
 
     double yc[6][4];
     for (int s = 0; s < S; ++s) {
-        const double Ts = g.t0 + g.h * s, Te = g.t0 + g.h * (s + 1);
+        const double Ts = g.t0 + g.h * (s + g.s0), Te = g.t0 + g.h * (s + g.s0 + 1);
         const double w2 = 0.5 * (Te - Ts);
         const double* src = s == 0 ? p.ics : p.states_out;
         const double4* grec = reinterpret_cast<const double4*>(p.recs) +

@@ -49,7 +49,7 @@ class _Opts(ctypes.Structure):
                 ("tile_pairs", ctypes.c_int32), ("graph", ctypes.c_int32),
                 ("switch_tol", ctypes.c_double), ("max_fp32", ctypes.c_int32), ("job_list", ctypes.c_int32),
                 ("conv", ctypes.c_int32), ("streams", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("feedback", ctypes.c_int32), ("guess", ctypes.c_void_p)]
+                ("feedback", ctypes.c_int32), ("guess", ctypes.c_void_p), ("refine", ctypes.c_int32)]
 
 
 class _Group(ctypes.Structure):
@@ -201,7 +201,7 @@ class Context:
     @staticmethod
     def opts(init="kepler", max_iter=64, tol_mode="rel", path="fused", fixed_iters=0,
              tile_pairs=0, precision="fp64", graph=False, switch_tol=0.0, max_fp32=0, job_list=0, conv="ic",
-             streams=1, order=1, feedback=0, guess=None):
+             streams=1, order=1, feedback=0, guess=None, refine=0):
         o = _Opts()
         o.init, o.max_iter, o.tol_mode = INIT[init], int(max_iter), TOL_MODE[tol_mode]
         o.precision, o.path, o.fixed_iters = PRECISION[precision], PATH[path], int(fixed_iters)
@@ -210,6 +210,7 @@ class Context:
         o.conv = CONV[conv]
         o.streams = int(streams)
         o.order, o.feedback = int(order), int(feedback)
+        o.refine = int(refine)
         if guess is not None:   # init "guess": device node states [n, S_max, N_max, 6]
             _check_tensor(guess, "guess")
             o.guess = guess.data_ptr()
@@ -274,6 +275,7 @@ class Context:
         ``bounds`` [n,S_max+1,6] and ``nodes`` [n,S_max,N_max,6].  ``out``,
         ``iters_out``, ``bounds_out`` and ``nodes_out`` give the output tensors."""
         model = model or Model()
+        want_bounds = want_bounds or bool(opts.get("refine", 0))   # refinement rewrites the boundary records
         n, S_max, N_max, states, iters, bounds, nodes, garr = self._outputs(
             ics, groups, want_bounds, want_nodes, out, iters_out, bounds_out, nodes_out)
         mc, oc = model._c(), self.opts(**opts)
