@@ -3,7 +3,10 @@
 //
 // Each kernel does a fixed, known amount of work with enough independent chains per wave to
 // keep its pipe busy, and writes a value derived from every chain so that none of the work
-// can be dropped.  The host function times them with HIP events on the caller's stream.
+// can be dropped.  The host function times them with HIP events on the caller's stream,
+// after a warm-up.  (A sweep of the matrix loop on this chip: 4 or 8 chains per wave at one
+// to four waves per SIMD all reach 75-78 TFLOP/s once warm; 16 chains per wave fall to
+// 31-38.)
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -16,11 +19,14 @@ namespace {
 typedef double f64x4c __attribute__((ext_vector_type(4)));
 
 constexpr int kChains = 8;          // independent accumulators per wave / lane
-constexpr int kMfmaBlock = 256;     // one wave per SIMD
+constexpr int kMfmaBlock = 256;     // four waves, one per SIMD (two workgroups per CU)
 constexpr int kFmaBlock = 256;
 
 // kChains independent v_mfma_f64_16x16x4_f64 chains per wave: 2 * 16 * 16 * 4 flop each.
-__global__ __launch_bounds__(kMfmaBlock) void pc_ceiling_mfma(int iters, double* sink)
+// No launch bound: with __launch_bounds__(256) the compiler kept the accumulators in VGPRs
+// and copied all 64 of them into AGPRs and back around every loop iteration (128 moves per
+// 8 MFMAs), which halved the measured rate (47 TFLOP/s); without it the loop is MFMAs only.
+__global__ void pc_ceiling_mfma(int iters, double* sink)
 {
     const double a = 1.0 + 1e-9 * (double)threadIdx.x;
     const double b = 1.0 - 1e-9 * (double)blockIdx.x;
@@ -75,12 +81,19 @@ int pc_ceilings_run(int n_cu, void* buf, size_t buf_bytes, void* stream, double*
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
-    // best of three timed launches after one untimed one
+    // best of five timed launches after the pipe has run for about 50 ms untimed
     auto best_ms = [&](auto launch, double* ms) -> hipError_t {
-        launch();
-        hipError_t r = hipGetLastError();
+        hipError_t r = hipEventRecord(e0, st);
+        float warm = 0.0f;
+        for (int rep = 0; rep < 200 && r == hipSuccess && warm < 50.0f; ++rep) {
+            launch();
+            r = hipGetLastError();
+            if (r == hipSuccess) r = hipEventRecord(e1, st);
+            if (r == hipSuccess) r = hipEventSynchronize(e1);
+            if (r == hipSuccess) r = hipEventElapsedTime(&warm, e0, e1);
+        }
         float best = 1e30f;
-        for (int rep = 0; rep < 3 && r == hipSuccess; ++rep) {
+        for (int rep = 0; rep < 5 && r == hipSuccess; ++rep) {
             r = hipEventRecord(e0, st);
             if (r == hipSuccess) launch();
             if (r == hipSuccess) r = hipGetLastError();
