@@ -79,6 +79,9 @@ def _load():
                                         ctypes.c_double, ctypes.c_double, _dp]
         lib.orc_accel_eih_bodies.restype = None
         lib.orc_accel_eih_bodies.argtypes = [_dp, ctypes.c_int, _dp, _dp, _dp, _dp, _dp, ctypes.c_double, _dp]
+        lib.orc_flyby_ratio.restype = None
+        lib.orc_flyby_ratio.argtypes = [ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                        ctypes.c_int, ctypes.c_int, _dp, ctypes.c_double, _dp]
         lib.orc_ephem_state.restype = None
         lib.orc_ephem_state.argtypes = [_dp, ctypes.c_double, ctypes.c_double, _dp, _dp]
         _lib = lib
@@ -185,6 +188,18 @@ def propagate(ics, t0, tf, nodes, segments, tol, model=None, *, tol_mode=0, max_
 
 
 propagate.last_threads = 1
+
+
+def flyby_ratio(ics, t0, tf, segments, model, samples=16):
+    """Smallest distance of each IC's two-body prediction to any perturber, in Hill radii,
+    over ``samples`` CGL points per segment of [t0, tf] (orc_flyby_ratio); 0 for an IC whose
+    orbit is not elliptic."""
+    lib = _load()
+    ics = _f64(ics).reshape(-1, 6)
+    out = np.zeros(ics.shape[0])
+    lib.orc_flyby_ratio(ics.shape[0], _ptr(ics), float(t0), float(tf), int(segments), int(samples),
+                        model.n_pert, model._pert_ptr(), model.epoch, _ptr(out))
+    return out
 
 
 def picard_step(g, y0):

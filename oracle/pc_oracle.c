@@ -927,6 +927,52 @@ int orc_propagate_group(int n_ic, const double* ics, double t0, double tf, int N
     return used;
 }
 
+/*
+ * Flyby detection for the outer level.  Sec. 3.2 proposes isolating a sub-group of
+ * trajectories that experience a planetary flyby into its own outer group, since their
+ * dynamics differ from the rest; Sec. 7 lists flyby detection as future work.  Reading
+ * (a screen before the propagation, on what is known then): the two-body (mu = 1)
+ * prediction of each IC from its initial state at t0, the same motion the warm start of
+ * Sec. 2.1 uses, is sampled at the `samples` CGL points of each of the S equal segments of
+ * [t0, tf] (t = w2 tau_k + w1 per segment, eq. chnodes) and compared with every perturber's
+ * ephemeris position at those times; ratio_out[m] is the smallest distance found, in
+ * units of that perturber's Hill radius a_p (mu_p / 3)^(1/3).  A massless perturber
+ * (mu_p = 0) has no sphere of influence and is skipped (INFINITY when nothing remains);
+ * an IC whose orbit is not elliptic gets 0.  An IC is isolated when its ratio is below
+ * the caller's threshold.
+ */
+void orc_flyby_ratio(int n_ic, const double* ics, double t0, double tf, int S, int samples, int n_pert,
+                     const double* pert, double epoch, double* ratio_out)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int m = 0; m < n_ic; ++m) {
+        const double* y0 = ics + 6 * m;
+        const double h = (tf - t0) / (double)S;
+        double best = INFINITY;
+        for (int s = 0; s < S && best > 0.0; ++s) {
+            const double Ts = t0 + h * s, Te = t0 + h * (s + 1);
+            const double w1 = 0.5 * (Te + Ts), w2 = 0.5 * (Te - Ts);
+            for (int k = 0; k < samples; ++k) {
+                const double t = w2 * orc_tau(k, samples) + w1;
+                double y[6];
+                if (orc_kepler(y0, t - t0, y) != 0) { best = 0.0; break; }
+                for (int p = 0; p < n_pert; ++p) {
+                    const double* el = pert + 7 * p;
+                    if (!(el[0] > 0.0)) continue;
+                    double rp[3];
+                    orc_ephem(el, epoch, t, rp);
+                    const double dx = y[0] - rp[0], dy = y[1] - rp[1], dz = y[2] - rp[2];
+                    const double d = sqrt(dx * dx + dy * dy + dz * dz);
+                    const double rh = el[1] * cbrt(el[0] / 3.0);
+                    const double q = d / rh;
+                    if (q < best) best = q;
+                }
+            }
+        }
+        ratio_out[m] = best;
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Independent integrator for pinning: classical fixed-step RK4              */
 /* ------------------------------------------------------------------------ */
