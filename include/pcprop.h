@@ -159,10 +159,15 @@ typedef struct {
                              has degree N).  Order 2 runs on the fused FP64 path with the
                              per-IC rule and the point-mass model, for node counts up to 128;
                              other calls with order 2 return PC_EINVAL. */
-    int32_t feedback;     /* order 2 with integral error feedback (the linear change of the
-                             acceleration over the position change of the sweep, integrated
-                             and added to the iterate): reserved, must be 0 (the HIP path
-                             returns PC_EINVAL for 1) */
+    int32_t feedback;     /* order 2: 1 = integral error feedback, the development Sec. 1 cites
+                             with the adaptive variant of the method.  The sweep's accelerations
+                             were taken at the previous position iterate; the change dx the
+                             sweep makes to the position is fed back through the linear part of
+                             the point-mass dynamics, da = (da/dr) dx at the previous iterate,
+                             whose single and double integrals (the same operators) are added
+                             to the new velocity and position.  A second product per sweep and
+                             one barrier; the fixed point is the second-order one.  0 (default)
+                             or 1, order 2 only */
     const double* guess;  /* init = PC_INIT_GUESS: device [n_ic][iters_stride][nodes_stride][6],
                              the node states of the initial guess of every segment, in the
                              layout of the same call's nodes_out (e.g. the nodes_out of an
@@ -184,6 +189,18 @@ typedef struct {
                              iters_out and bounds_out, takes no nodes_out and no guess;
                              pc_workspace_bytes includes its region.  iters_out, bounds_out and
                              states_out of ICs that need no refinement are those of refine = 0. */
+    double flyby_hill;    /* flyby isolation, 0 (default, off) or a threshold in Hill radii: the
+                             outer level isolates sub-groups of trajectories that experience a
+                             planetary flyby (Sec. 3.2; flyby detection, Sec. 7).  Before the
+                             propagation every IC is screened (pc_flyby_ratio, 16 sample points
+                             per segment); in every group, the ICs whose ratio is below
+                             flyby_hill form a group of their own with the same interval, nodes,
+                             segments and tolerance, and the call runs on the ICs reordered so
+                             (a copy in the workspace; outputs are returned in the caller's
+                             order).  Under the per-IC rule the results are those without
+                             isolation; under PC_CONV_GROUP_MAX the flyby ICs no longer set the
+                             sweep count of the rest of their group.  Not with nodes_out, a
+                             guess, refinement, graph capture or the allocation-free call. */
 } pc_opts;
 
 /* One outer-level group of the two-level augmentation (Sec. 3.2): ICs
@@ -294,6 +311,20 @@ int pc_adjoint(pc_ctx* ctx, int64_t n_ic, const pc_group* groups /* host */, int
                int32_t nodes_stride,
                double adj_tol, int32_t adj_max_iter, double* grad_ics, int32_t* adj_iters,
                void* workspace, size_t ws_bytes, pc_stream_t stream);
+
+/* Flyby screen of the outer level (Sec. 3.2, Sec. 7), the test of opts.flyby_hill: for
+ * every IC of the groups, the smallest distance of its two-body (mu = 1) prediction from
+ * t0 to any perturber of `model` (mu_p > 0), in units of that perturber's Hill radius
+ * a_p (mu_p/3)^(1/3), over `samples` Chebyshev-Gauss-Lobatto points of each segment of
+ * its group (t = w2 tau_k + w1).  An IC whose orbit is not elliptic gets 0; with no
+ * massive perturber the result is +inf.
+ *   ics    device [n_ic][6]
+ *   ratio  device [n_ic] out; entries of ICs outside the groups are left untouched
+ *   samples 2 .. 64 (opts.flyby_hill uses 16)
+ *   workspace: pc_workspace_bytes of the same groups */
+int pc_flyby_ratio(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_group* groups /* host */,
+                   int32_t n_groups, const pc_model* model, int32_t samples, double* ratio,
+                   void* workspace, size_t ws_bytes, pc_stream_t stream);
 
 /* ---- operator and kernel-level entry points (used by the tests) ---- */
 

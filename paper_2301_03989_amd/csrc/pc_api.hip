@@ -13,6 +13,7 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -431,7 +432,15 @@ struct Plan {
            ref_sub = 0, ref_sub_cap = 0;
     int refine_smax = 0;          // segment stride of the sub-calls' records
     int64_t refine_budget = 0;    // ephemeris records one refinement pass may plan
+    // flyby isolation (opts.flyby_hill > 0): a region after the call's own, holding the
+    // screen's ratios, the reordered copy of the ICs and outputs, copy descriptors and the
+    // reordered call's workspace
+    size_t off_flyby = 0, fly_ratio = 0, fly_ics = 0, fly_states = 0, fly_iters = 0, fly_bounds = 0, fly_copies = 0,
+           fly_sub = 0, fly_sub_cap = 0;
+    int64_t fly_span = 0, fly_cov = 0;   // ICs indexed by the groups (0 .. span-1), ICs in them
 };
+
+constexpr int kFlybySamples = 16;   // screen points per segment of opts.flyby_hill
 
 // Tasks of one refinement pass at most (the pass's buffers are sized for this many).
 constexpr int64_t kRefineChunk = 8192;
@@ -669,6 +678,48 @@ int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, c
         plan.off_refine = plan.total;
         plan.total += r;
     }
+    if (o.flyby_hill > 0.0) {
+        // sizes of the reordered call: every group split at worst into two (one more group
+        // and job per group, each part with its own ephemeris records)
+        std::vector<pc_group> split;
+        int64_t cov = 0, span = 0;
+        for (int gi = 0; gi < n_groups; ++gi) {
+            pc_group a = groups[gi];
+            span = std::max<int64_t>(span, a.ic_offset + a.n_ic);
+            a.ic_offset = cov;
+            if (a.n_ic >= 2) {
+                pc_group b = a;
+                a.n_ic -= 1;
+                b.ic_offset = cov + a.n_ic;
+                b.n_ic = 1;
+                split.push_back(a);
+                split.push_back(b);
+            } else {
+                split.push_back(a);
+            }
+            cov += groups[gi].n_ic;
+        }
+        pc_opts oi = o;
+        oi.flyby_hill = 0.0;
+        Plan inner;
+        int rc = make_plan(ctx, cov, split.data(), (int)split.size(), model, oi, false, inner, lists_ok);
+        if (rc != PC_OK) return rc;
+        const int S = plan.max_S;
+        size_t r = 0;
+        plan.fly_ratio = r;  r = align_up(r + (size_t)span * sizeof(double));
+        plan.fly_ics = r;    r = align_up(r + (size_t)cov * 6 * sizeof(double));
+        plan.fly_states = r; r = align_up(r + (size_t)cov * 6 * sizeof(double));
+        plan.fly_iters = r;  r = align_up(r + (size_t)cov * S * sizeof(int32_t));
+        plan.fly_bounds = r; r = align_up(r + (size_t)cov * (S + 1) * 6 * sizeof(double));
+        plan.fly_copies = r; r = align_up(r + (size_t)3 * cov * sizeof(PcCopyDev));
+        plan.fly_sub = r;
+        plan.fly_sub_cap = inner.total;
+        r = align_up(r + inner.total);
+        plan.fly_span = span;
+        plan.fly_cov = cov;
+        plan.off_flyby = plan.total;
+        plan.total += r;
+    }
     return PC_OK;
 }
 
@@ -702,11 +753,14 @@ int validate_forward(pc_ctx* ctx, const pc_opts& o, const pc_model* model)
     if (o.order != 1 && o.order != 2) return set_error(ctx, PC_EINVAL, "order must be 1 or 2");
     if (o.feedback != 0 && o.feedback != 1) return set_error(ctx, PC_EINVAL, "feedback must be 0 or 1");
     if (o.feedback && o.order != 2) return set_error(ctx, PC_EINVAL, "feedback needs order 2");
-    if (o.feedback) return set_error(ctx, PC_EINVAL, "the integral error feedback is not on the HIP path");
     if (o.order == 2 && (o.path != PC_PATH_FUSED || o.precision != PC_FP64 || model->inv_c2 > 0.0 ||
                          o.conv != PC_CONV_PER_IC))
         return set_error(ctx, PC_EINVAL, "order 2 runs on the fused FP64 path, point masses, per-IC rule");
     if (o.refine < 0 || o.refine > 8) return set_error(ctx, PC_EINVAL, "refine must be 0..8");
+    if (!(o.flyby_hill >= 0.0) || !std::isfinite(o.flyby_hill))
+        return set_error(ctx, PC_EINVAL, "flyby_hill must be >= 0 and finite");
+    if (o.flyby_hill > 0.0 && (o.refine > 0 || o.init == PC_INIT_GUESS || o.graph))
+        return set_error(ctx, PC_EINVAL, "flyby isolation runs without refinement, a guess or graph capture");
     if (o.refine > 0 && (o.path != PC_PATH_FUSED || o.init == PC_INIT_GUESS))
         return set_error(ctx, PC_EINVAL, "refinement runs on the fused path and without a guess");
     return PC_OK;
@@ -762,6 +816,7 @@ void stage_call(pc_ctx* ctx, const Plan& plan, const pc_model* model, const pc_o
     pp.guess = o.guess;
     pp.precision = o.precision;
     pp.order = o.order;
+    pp.feedback = o.feedback;
     pp.max_fp32 = o.max_fp32 > 0 ? o.max_fp32 : 24;
     pp.switch2 = o.switch_tol * o.switch_tol;   // 0: the kernel's default for the job's sweep kind
     pp.counters = reinterpret_cast<int32_t*>(base + plan.off_counters);
@@ -872,7 +927,7 @@ int refine_passes(pc_ctx* ctx, const Plan& plan, const pc_group* groups, int n_g
         // gathers: each task starts from the boundary record of its segment
         cp.resize(np);
         for (int64_t k = 0; k < np; ++k)
-            cp[k] = {bounds_out + ((size_t)pass[k].m * (stride + 1) + pass[k].s) * 6, ics_sub + k * 6, 6};
+            cp[k] = {bounds_out + ((size_t)pass[k].m * (stride + 1) + pass[k].s) * 6, ics_sub + k * 6, 12};
         const size_t dcopy = align_up(sub.staged);
         rc = ensure_staging(ctx, dcopy + 2 * kRefineChunk * sizeof(PcCopyDev) + kAlign);
         if (rc != PC_OK) return rc;
@@ -920,14 +975,14 @@ int refine_passes(pc_ctx* ctx, const Plan& plan, const pc_group* groups, int n_g
                     continue;
                 }
                 irow[t.s] = status;
-                cp.push_back({states_sub + k * 6, brow + (size_t)(t.s + 1) * 6, 6});
+                cp.push_back({states_sub + k * 6, brow + (size_t)(t.s + 1) * 6, 12});
                 if (t.s + 1 < S) pending.push_back({t.m, t.g, t.s + 1, 0});
-                else cp.push_back({states_sub + k * 6, states_out + (size_t)t.m * 6, 6});
+                else cp.push_back({states_sub + k * 6, states_out + (size_t)t.m * 6, 12});
             } else {
                 for (int j = 0; j < S - t.s; ++j) irow[t.s + j] = r[j];
                 cp.push_back({bounds_sub + ((size_t)k * (smax + 1) + 1) * 6, brow + (size_t)(t.s + 1) * 6,
-                              (int64_t)(S - t.s) * 6});
-                cp.push_back({states_sub + k * 6, states_out + (size_t)t.m * 6, 6});
+                              (int64_t)(S - t.s) * 12});
+                cp.push_back({states_sub + k * 6, states_out + (size_t)t.m * 6, 12});
                 first_failure(t.m, t.g, t.s);
             }
         }
@@ -955,6 +1010,61 @@ int refine_passes(pc_ctx* ctx, const Plan& plan, const pc_group* groups, int n_g
     if (nonfinite > 0) return set_error(ctx, PC_ENONFINITE, "%d initial conditions became non-finite", nonfinite);
     if (notconv > 0)
         return set_error(ctx, PC_ENOTCONV, "%d initial conditions did not converge after refinement", notconv);
+    return PC_OK;
+}
+
+// Flyby screen of the groups of `plan` into ratio (device, indexed like the ICs), queued on
+// hs: the plan's group table (each group with its first thread) and the perturbers staged
+// and copied into the workspace's table region, the groups' entries of ratio set to +inf,
+// then pc_flyby_kernel.
+int flyby_screen(pc_ctx* ctx, const Plan& plan, const pc_model* model, char* ws, const double* ics, double* ratio,
+                 int samples, hipStream_t hs)
+{
+    std::vector<PcGroupDev> gd = plan.groups;
+    int64_t threads = 0, cov = 0;
+    for (PcGroupDev& d : gd) {
+        d.thread_offset = threads;
+        threads += d.n_ic * samples;
+        cov = std::max<int64_t>(cov, d.n_ic);
+    }
+    const size_t off_inf = align_up(plan.staged);
+    int rc = ensure_staging(ctx, off_inf + (size_t)cov * sizeof(double) + kAlign);
+    if (rc != PC_OK) return rc;
+    char* st = static_cast<char*>(ctx->staging);
+    std::memset(st, 0, plan.staged);
+    std::memcpy(st + plan.off_groups, gd.data(), gd.size() * sizeof(PcGroupDev));
+    prepare_bodies(model, reinterpret_cast<PcBodyDev*>(st + plan.off_bodies));
+    double* inf = reinterpret_cast<double*>(st + off_inf);
+    for (int64_t i = 0; i < cov; ++i) inf[i] = INFINITY;
+    PC_HIP_DRAIN(ctx, hs, hipMemcpyAsync(ws, st, plan.staged, hipMemcpyHostToDevice, hs));
+    for (const PcGroupDev& d : gd)
+        PC_HIP_DRAIN(ctx, hs, hipMemcpyAsync(ratio + d.ic_offset, inf, (size_t)d.n_ic * sizeof(double),
+                                             hipMemcpyHostToDevice, hs));
+    PcFlybyParams fp{};
+    fp.groups = reinterpret_cast<const PcGroupDev*>(ws + plan.off_groups);
+    fp.n_groups = (int)gd.size();
+    fp.bodies = reinterpret_cast<const PcBodyDev*>(ws + plan.off_bodies);
+    fp.n_pert = model->n_pert;
+    fp.epoch = model->epoch;
+    fp.ics = ics;
+    fp.ratio = ratio;
+    fp.samples = samples;
+    fp.n_threads = threads;
+    PC_HIP_DRAIN(ctx, hs, (hipError_t)pc_launch_flyby(fp, hs));
+    return PC_OK;
+}
+
+// Copies described by `cp`, staged and run on hs through the device descriptor array `dev`;
+// returns once they are done (the staging buffer is free again).
+int run_copies(pc_ctx* ctx, const std::vector<PcCopyDev>& cp, PcCopyDev* dev, hipStream_t hs)
+{
+    if (cp.empty()) return PC_OK;
+    int rc = ensure_staging(ctx, cp.size() * sizeof(PcCopyDev) + kAlign);
+    if (rc != PC_OK) return rc;
+    std::memcpy(ctx->staging, cp.data(), cp.size() * sizeof(PcCopyDev));
+    PC_HIP_DRAIN(ctx, hs, hipMemcpyAsync(dev, ctx->staging, cp.size() * sizeof(PcCopyDev), hipMemcpyHostToDevice, hs));
+    PC_HIP_DRAIN(ctx, hs, (hipError_t)pc_launch_copy_runs(dev, (int64_t)cp.size(), hs));
+    PC_HIP(ctx, hipStreamSynchronize(hs));
     return PC_OK;
 }
 
@@ -989,6 +1099,7 @@ void pc_default_opts(pc_opts* o)
     o->feedback = 0;
     o->guess = nullptr;
     o->refine = 0;
+    o->flyby_hill = 0.0;
 }
 
 int pc_version(void) { return PC_VERSION; }
@@ -1083,6 +1194,10 @@ int pc_workspace_bytes(pc_ctx* ctx, const pc_group* groups, int32_t n_groups, co
     return PC_OK;
 }
 
+static int isolate_flybys(pc_ctx* ctx, const Plan& plan, const double* ics, const pc_group* groups, int32_t n_groups,
+                          const pc_model* model, const pc_opts& o, double* states_out, int32_t* iters_out,
+                          int32_t iters_stride, double* bounds_out, char* ws, hipStream_t hs);
+
 // The forward call.  no_alloc: the workspace is this device's static `scratch` (workspace
 // and ws_bytes are ignored), the operators must already be cached, the tables must fit the
 // staging buffer the context holds, and only the fused path without graph capture runs, so
@@ -1129,6 +1244,13 @@ static int propagate_impl(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc
                          "allocation-free call holds %zu", plan.total, ws_bytes);
     if (!workspace || ws_bytes < plan.total)
         return set_error(ctx, PC_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, plan.total);
+    if (o.flyby_hill > 0.0) {
+        if (nodes_out || no_alloc)
+            return set_error(ctx, PC_EINVAL, "flyby isolation takes no nodes_out and does not run in the "
+                             "allocation-free call");
+        return isolate_flybys(ctx, plan, ics, groups, n_groups, model, o, states_out, iters_out, iters_stride,
+                              bounds_out, static_cast<char*>(workspace), (hipStream_t)stream);
+    }
 
     // stage [counters | params | groups | jobs | bodies] and copy them in one transfer
     if (no_alloc && plan.staged + kAlign > ctx->staging_bytes)
@@ -1311,6 +1433,102 @@ static int propagate_impl(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc
                              iters_stride, bounds_out, hs);
     if (hc[1] > 0) return set_error(ctx, PC_ENONFINITE, "%d initial conditions became non-finite", hc[1]);
     if (hc[0] > 0) return set_error(ctx, PC_ENOTCONV, "%d initial conditions did not converge", hc[0]);
+    return PC_OK;
+}
+
+// Flyby isolation (opts.flyby_hill > 0): screen every IC, split every group into its quiet
+// ICs and its flyby ICs (ratio below the threshold), each part a group of its own, and
+// run the call on the ICs in that order: a copy of the ICs in the workspace, the reordered
+// call's outputs there too, scattered back to the caller's rows.  When no group is split
+// the call runs in place.
+static int isolate_flybys(pc_ctx* ctx, const Plan& plan, const double* ics, const pc_group* groups, int32_t n_groups,
+                          const pc_model* model, const pc_opts& o, double* states_out, int32_t* iters_out,
+                          int32_t iters_stride, double* bounds_out, char* ws, hipStream_t hs)
+{
+    char* F = ws + plan.off_flyby;
+    double* ratio = reinterpret_cast<double*>(F + plan.fly_ratio);
+    int rc = flyby_screen(ctx, plan, model, ws, ics, ratio, kFlybySamples, hs);
+    if (rc != PC_OK) return rc;
+    std::vector<double> hr((size_t)plan.fly_span);
+    PC_HIP_DRAIN(ctx, hs, hipMemcpyAsync(hr.data(), ratio, hr.size() * sizeof(double), hipMemcpyDeviceToHost, hs));
+    PC_HIP(ctx, hipStreamSynchronize(hs));
+    std::vector<pc_group> ng;
+    std::vector<int64_t> perm;
+    std::vector<int> seg_of;   // segments of the group of each reordered IC
+    bool split = false;
+    for (int gi = 0; gi < n_groups; ++gi) {
+        const pc_group& G = groups[gi];
+        std::vector<int64_t> quiet, fly;
+        for (int64_t m = G.ic_offset; m < G.ic_offset + G.n_ic; ++m)
+            (hr[(size_t)m] < o.flyby_hill ? fly : quiet).push_back(m);
+        for (const auto* part : {&quiet, &fly}) {
+            if (part->empty()) continue;
+            pc_group q = G;
+            q.ic_offset = (int64_t)perm.size();
+            q.n_ic = (int64_t)part->size();
+            ng.push_back(q);
+            perm.insert(perm.end(), part->begin(), part->end());
+            seg_of.insert(seg_of.end(), part->size(), G.segments);
+        }
+        split = split || (!quiet.empty() && !fly.empty());
+    }
+    pc_opts oi = o;
+    oi.flyby_hill = 0.0;
+    if (!split)   // every group is all quiet or all flyby: nothing moves
+        return propagate_impl(ctx, ics, plan.fly_span, groups, n_groups, model, &oi, states_out, iters_out,
+                              iters_stride, bounds_out, nullptr, 0, ws, plan.off_flyby, hs, false);
+    const int S = plan.max_S;
+    const int64_t cov = (int64_t)perm.size();
+    double* ics_p = reinterpret_cast<double*>(F + plan.fly_ics);
+    double* states_p = reinterpret_cast<double*>(F + plan.fly_states);
+    int32_t* iters_p = reinterpret_cast<int32_t*>(F + plan.fly_iters);
+    double* bounds_p = reinterpret_cast<double*>(F + plan.fly_bounds);
+    PcCopyDev* copies = reinterpret_cast<PcCopyDev*>(F + plan.fly_copies);
+    std::vector<PcCopyDev> cp((size_t)cov);
+    for (int64_t k = 0; k < cov; ++k) cp[k] = {ics + perm[k] * 6, ics_p + k * 6, 12};
+    rc = run_copies(ctx, cp, copies, hs);
+    if (rc != PC_OK) return rc;
+    const int status = propagate_impl(ctx, ics_p, cov, ng.data(), (int32_t)ng.size(), model, &oi, states_p,
+                                      iters_out ? iters_p : nullptr, S, bounds_out ? bounds_p : nullptr, nullptr, 0,
+                                      F + plan.fly_sub, plan.fly_sub_cap, hs, false);
+    if (status != PC_OK && status != PC_ENOTCONV && status != PC_ENONFINITE) return status;
+    const std::string msg = ctx->last_error;
+    cp.clear();
+    for (int64_t k = 0; k < cov; ++k) {
+        const int64_t m = perm[k];
+        cp.push_back({states_p + k * 6, states_out + m * 6, 12});
+        if (iters_out) cp.push_back({iters_p + k * S, iters_out + m * iters_stride, seg_of[k]});
+        if (bounds_out)
+            cp.push_back({bounds_p + k * (S + 1) * 6, bounds_out + m * (iters_stride + 1) * 6,
+                          (int64_t)(seg_of[k] + 1) * 12});
+    }
+    rc = run_copies(ctx, cp, copies, hs);
+    if (rc != PC_OK) return rc;
+    if (status != PC_OK) set_error(ctx, status, "%s", msg.c_str());
+    return status;
+}
+
+int pc_flyby_ratio(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc_group* groups, int32_t n_groups,
+                   const pc_model* model, int32_t samples, double* ratio, void* workspace, size_t ws_bytes,
+                   pc_stream_t stream)
+{
+    if (!ctx) return PC_EINVAL;
+    ctx->last_error[0] = 0;
+    if (!ics || !ratio || n_ic < 1) return set_error(ctx, PC_EINVAL, "null ics/ratio or n_ic < 1");
+    if (samples < 2 || samples > 64) return set_error(ctx, PC_EINVAL, "samples must be 2..64");
+    int rc = validate_model(ctx, model);
+    if (rc != PC_OK) return rc;
+    PC_HIP(ctx, hipSetDevice(ctx->device));
+    const pc_opts o = defaults();
+    Plan plan;
+    rc = make_plan(ctx, n_ic, groups, n_groups, model, o, false, plan);
+    if (rc != PC_OK) return rc;
+    if (!workspace || ws_bytes < plan.staged)
+        return set_error(ctx, PC_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, plan.staged);
+    hipStream_t hs = (hipStream_t)stream;
+    rc = flyby_screen(ctx, plan, model, static_cast<char*>(workspace), ics, ratio, samples, hs);
+    if (rc != PC_OK) return rc;
+    PC_HIP(ctx, hipStreamSynchronize(hs));
     return PC_OK;
 }
 

@@ -936,6 +936,137 @@ static __device__ __forceinline__ int pc_product2(const double* sF, const double
     return pc_wide_epilogue<PAIRS, NP, false, false>(sY0, yc, acc, w2, tl, N, L);
 }
 
+// Linear change of the point-mass acceleration over a position change, at R points of
+// node j: g = (da/dr)(r) dr = sum over the Sun (at the origin) and the perturbers of
+// mu (3 d (d . dr) / |d|^5 - dr / |d|^3), d the point's offset from the mass (the indirect
+// term does not depend on the position).  mu/|d|^3 as pc_mu_r3, and 1/|d|^2 from the same
+// estimate t of 1/|d|^2 as t (1 + e + e^2), e = 1 - |d|^2 t.  Records in LDS (compact
+// [node][body][3], masses in smu) or, when they do not fit there, double4 (x, y, z, mu)
+// in global memory.
+template <int R>
+static __device__ __forceinline__ void pc_grad_dot_node(const double (&x)[R], const double (&y)[R],
+                                                        const double (&z)[R], const double (&dx)[R],
+                                                        const double (&dy)[R], const double (&dz)[R], int j, int P,
+                                                        double mu_sun, bool rec_lds, const double* srec,
+                                                        const double* smu, const double4* grec, double (&gx)[R],
+                                                        double (&gy)[R], double (&gz)[R])
+{
+    auto add = [&](int r, double ox, double oy, double oz, double mu) {
+        const double qx = x[r] - ox, qy = y[r] - oy, qz = z[r] - oz;
+        const double q2 = qx * qx + qy * qy + qz * qz;
+        const double yv = __builtin_amdgcn_rsq(q2);
+        const double t = yv * yv;
+        const double e = fma(-q2, t, 1.0);
+        const double inv2 = fma(t, fma(e, e, e), t);
+        const double sd = mu * (yv * t) * fma(e, fma(1.875, e, 1.5), 1.0);
+        const double k = 3.0 * sd * inv2 * (qx * dx[r] + qy * dy[r] + qz * dz[r]);
+        gx[r] += fma(k, qx, -sd * dx[r]);
+        gy[r] += fma(k, qy, -sd * dy[r]);
+        gz[r] += fma(k, qz, -sd * dz[r]);
+    };
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        gx[r] = gy[r] = gz[r] = 0.0;
+        add(r, 0.0, 0.0, 0.0, mu_sun);
+    }
+    for (int b = 0; b < P; ++b) {
+        double ox, oy, oz, mu;
+        if (rec_lds) {
+            const double* q = srec + j * 3 * (P + 1) + 3 * b;
+            ox = q[0];
+            oy = q[1];
+            oz = q[2];
+            mu = smu[b];
+        } else {
+            const double4 q = grec[(size_t)j * (P + 1) + b];
+            ox = q.x;
+            oy = q.y;
+            oz = q.z;
+            mu = q.w;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) add(r, ox, oy, oz, mu);
+    }
+}
+
+// Second-order sweep with integral error feedback (WIDE shapes).  The sweep's accelerations
+// were taken at the previous position iterate; the position it predicts,
+// x = x0 + w2 v0 (tau_j + 1) + w2^2 K2_N a, changes that iterate by dx, and the linear change
+// of the acceleration over dx, da = (da/dr) dx at the previous iterate, is integrated like
+// the accelerations and added: v_new = v0 + w2 K_N (a + da), x_new = x0 + w2 v0 (tau_j + 1) +
+// w2^2 K2_N (a + da).  da is published in the velocity columns of F, which second-order
+// products do not read, and its product accumulates onto the first one (one barrier in
+// between).  At the fixed point dx vanishes, so the converged iterate is the second-order
+// one.  Flags as pc_product.
+template <int PAIRS, int NP>
+static __device__ __forceinline__ int pc_product2_fb(double* sF, const double* sY0, gconst_dp kp1, gconst_dp kp2,
+                                                      const double (&kpre)[8], const double (&yc)[6][4],
+                                                      f64x4 (&acc)[6], double w2, double tp1, const PcTol& tl, int N,
+                                                      const PcLane& L, int P, double mu_sun, bool rec_lds,
+                                                      const double* sRec, const double* sMu, const double4* grec)
+{
+    using Sh = PcShape<PAIRS, NP>;
+    static_assert(Sh::WIDE, "second-order sweeps run on WIDE job shapes");
+    constexpr int T = Sh::T, ROW = Sh::ROW, NQ = Sh::NQ;
+    const int lane = L.lane;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) acc[b] = f64x4{0.0, 0.0, 0.0, 0.0};
+    const double* bp[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        bp[u] = sF + (lane >> 4) * ROW + L.grp * 16 + ((lane & 15) ^ ((4 * u + (lane >> 4)) & 15));
+    auto product = [&](int c0) {
+        pc_kloop<NQ, 3, PcPairD, double, 3, 6, 2>(
+            [&](int u) { return PcPairD{kpre[u], kpre[4 + u]}; },
+            [&](int q) { return PcPairD{kp1[q * 64], kp2[q * 64]}; },
+            [&](int q, int u, double (&bq)[3]) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) bq[c] = bp[u][q * 4 * ROW + (c0 + c) * T];
+            },
+            [&](const PcPairD& ka, const double (&bq)[3]) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) acc[c] = mfma16(bq[c], ka.a1, acc[c]);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) acc[3 + c] = mfma16(bq[c], ka.a0, acc[3 + c]);
+            });
+    };
+    product(3);
+    // the predicted position, its change from the previous iterate, and da there
+    const int j = pc_node(L, 0, 0);
+    double ddx[4], ddy[4], ddz[4], gx[4], gy[4], gz[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int m = pc_ic(L, r);
+        double d[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            d[c] = (sY0[c * T + m] + w2 * fma(w2, acc[c][r], tp1 * sY0[(3 + c) * T + m])) - yc[c][r];
+        ddx[r] = d[0];
+        ddy[r] = d[1];
+        ddz[r] = d[2];
+    }
+    pc_grad_dot_node<4>(yc[0], yc[1], yc[2], ddx, ddy, ddz, j < N ? j : N - 1, P, mu_sun, rec_lds, sRec, sMu, grec,
+                        gx, gy, gz);
+    if (j < N) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            double* f = sF + j * ROW + pc_fcol<PAIRS, NP>(j, pc_ic(L, r));
+            f[0 * T] = gx[r];
+            f[1 * T] = gy[r];
+            f[2 * T] = gz[r];
+        }
+    }
+    __syncthreads();   // every node's da published
+    product(0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int m = pc_ic(L, r);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[c][r] = fma(w2, acc[c][r], tp1 * sY0[(3 + c) * T + m]);
+    }
+    return pc_wide_epilogue<PAIRS, NP, false, false>(sY0, yc, acc, w2, tl, N, L);
+}
+
 // acc = K_N^T mu for the lane's six blocks (WIDE shapes, transposed like pc_product): the
 // adjoint product, mu published in sF as [node][comp 6][IC] and kpT the lane's strip of
 // K_N^T fragments.

@@ -34,6 +34,7 @@ struct PcGroupDev {
     int32_t N, NP, T, S;
     int32_t s0;                // first segment of the group on the t0 + k h grid (a call that
                                // resumes a span at one of its segment boundaries), else 0
+    int64_t thread_offset;     // flyby screen: first thread of the group (n_ic * samples each)
 };
 
 struct PcJobDev {
@@ -72,6 +73,7 @@ struct PcParams {
     int32_t max_fp32;           // cap on FP32 sweeps per segment
     int32_t conv;               // PC_CONV_PER_IC or PC_CONV_GROUP_MAX (plain path only)
     int32_t order;              // 1: first-order sweeps; 2: second-order sweeps (WIDE shapes)
+    int32_t feedback;           // order 2: integral error feedback
     double switch2;             // squared relative change below which a job leaves FP32
     int32_t* counters;          // [0] ICs with a not-converged segment, [1] non-finite ICs
     int32_t* queue;             // next job of the persistent kernel (starts at 0)
@@ -106,12 +108,12 @@ struct PcEphemParams {
     double mu_sun;
 };
 
-// One contiguous run of doubles to copy (the gathers and scatters between a call's
-// outputs and the sub-calls of its refinement passes).
+// One contiguous run of 32-bit words to copy (the gathers and scatters between a call's
+// arrays and the sub-calls of its refinement passes or of flyby isolation).
 struct PcCopyDev {
-    const double* src;
-    double* dst;
-    int64_t n;
+    const void* src;
+    void* dst;
+    int64_t words;
 };
 
 // Launchers (pc_kernels.hip).  All return a hipError_t as int.
@@ -123,6 +125,21 @@ int pc_launch_fused(const PcParams& p, const PcParams* p_dev, int pairs, int gri
 int pc_fused_occupancy(int pairs, int* blocks_per_cu);
 // list: device [n] copy descriptors, one workgroup each.
 int pc_launch_copy_runs(const PcCopyDev* list, int64_t n, void* stream);
+// Flyby screen: ratio[m] = smallest distance of IC m's two-body (mu = 1) prediction to a
+// perturber, in Hill radii, over `samples` CGL points of every segment of its group; ICs
+// outside the groups are left alone.  ratio: device [n_ic].
+struct PcFlybyParams {
+    const PcGroupDev* groups;
+    int32_t n_groups;
+    const PcBodyDev* bodies;
+    int32_t n_pert;
+    double epoch;
+    const double* ics;
+    double* ratio;
+    int32_t samples;
+    int64_t n_threads;        // sum over groups of n_ic * samples
+};
+int pc_launch_flyby(const PcFlybyParams& p, void* stream);
 int pc_launch_adjoint(const PcAdjParams& a, const PcAdjParams* a_dev, int grid, void* stream);
 int pc_launch_apply_operator(int NP, const double* kfrag, int N, int64_t n_cols, const double* F,
                              const double* y0, double scale, double* Y, void* stream);

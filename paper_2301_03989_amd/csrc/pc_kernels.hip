@@ -87,11 +87,68 @@ int pc_launch_ephem(const PcEphemParams& p, void* stream)
     return hipGetLastError();
 }
 
-// Copies of contiguous runs of doubles, one workgroup per descriptor.
+// Copies of contiguous runs of 32-bit words, one workgroup per descriptor.
 __global__ __launch_bounds__(64) void pc_copy_runs_kernel(const PcCopyDev* __restrict__ list)
 {
     const PcCopyDev c = list[blockIdx.x];
-    for (int64_t i = threadIdx.x; i < c.n; i += blockDim.x) c.dst[i] = c.src[i];
+    const uint32_t* src = static_cast<const uint32_t*>(c.src);
+    uint32_t* dst = static_cast<uint32_t*>(c.dst);
+    for (int64_t i = threadIdx.x; i < c.words; i += blockDim.x) dst[i] = src[i];
+}
+
+// Flyby screen (the outer-level isolation of flyby sub-groups, Sec. 3.2): one thread per
+// (IC, sample point); the thread propagates its IC by two-body motion (mu = 1, the warm
+// start's) to its sample point of every segment, t = w2 tau_k + w1 (eq. chnodes1 with
+// `samples` CGL points), and keeps the smallest distance to any perturber in units of
+// its Hill radius a_p (mu_p/3)^(1/3); the IC's minimum over its threads is taken with an
+// atomic minimum on the bit patterns (positive doubles order as unsigned integers).  An
+// orbit that is not elliptic gives 0.  ratio must hold +inf for the screened ICs.
+__global__ __launch_bounds__(256) void pc_flyby_kernel(PcFlybyParams p)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= p.n_threads) return;
+    int lo = 0, hi = p.n_groups - 1;             // last group with thread_offset <= i
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (p.groups[mid].thread_offset <= i) lo = mid; else hi = mid - 1;
+    }
+    const PcGroupDev& G = p.groups[lo];
+    const int64_t local = i - G.thread_offset;
+    const int64_t m = G.ic_offset + local / p.samples;
+    const int k = (int)(local % p.samples);
+    const double tau = -cos(M_PI * (double)k / (double)(p.samples - 1));
+    double y0[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) y0[c] = p.ics[m * 6 + c];
+    double best = INFINITY;
+    for (int s = 0; s < G.S && best > 0.0; ++s) {
+        const double Ts = G.t0 + G.h * s, Te = G.t0 + G.h * (s + 1);
+        const double t = 0.5 * (Te - Ts) * tau + 0.5 * (Te + Ts);
+        double y[6];
+        if (!pc_kepler(y0, t - G.t0, y)) {
+            best = 0.0;
+            break;
+        }
+        for (int b = 0; b < p.n_pert; ++b) {
+            const PcBodyDev& B = p.bodies[b];
+            if (!(B.mu > 0.0)) continue;
+            double r[3];
+            pc_body_position(B, t - p.epoch, r);
+            const double dx = y[0] - r[0], dy = y[1] - r[1], dz = y[2] - r[2];
+            const double q = sqrt(dx * dx + dy * dy + dz * dz) / (B.a * cbrt(B.mu / 3.0));
+            best = fmin(best, q);
+        }
+    }
+    atomicMin(reinterpret_cast<unsigned long long*>(p.ratio + m), (unsigned long long)__double_as_longlong(best));
+}
+
+int pc_launch_flyby(const PcFlybyParams& p, void* stream)
+{
+    if (p.n_threads <= 0) return hipSuccess;
+    const int bs = 256;
+    const int64_t grid = (p.n_threads + bs - 1) / bs;
+    hipLaunchKernelGGL(pc_flyby_kernel, dim3((unsigned)grid), dim3(bs), 0, (hipStream_t)stream, p);
+    return hipGetLastError();
 }
 
 int pc_launch_copy_runs(const PcCopyDev* list, int64_t n, void* stream)
@@ -144,7 +201,7 @@ static __device__ __forceinline__ void pc_stage_records(const double4* grec, int
 // receives the iteration records.
 // MIXED: the job runs the FP32 -> FP64 precision schedule (compiled apart, so that FP64-only
 // jobs carry none of its registers).
-template <int PAIRS, int NP, bool MIXED = false, bool EIH = false, bool SO = false>
+template <int PAIRS, int NP, bool MIXED = false, bool EIH = false, int SO = 0>
 static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const PcGroupDev& g, int n, int64_t ic0,
                                                         int s, PcSmem<PAIRS>& sm, const PcLane& L, gconst_dp kp0,
                                                         double (&yc)[6][4], int32_t* iters_out, int& had_notconv,
@@ -281,6 +338,9 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
         } else if constexpr (MIXED) {
             flag = mode == 1 ? pc_product<PAIRS, NP, true>(sF, sY0, kp0, kpre, kp0f, yc, acc, w2, tl, N, L)
                              : pc_product<PAIRS, NP, false>(sF, sY0, kp0, kpre, kp0f, yc, acc, w2, tl, N, L);
+        } else if constexpr (SO == 2) {
+            flag = pc_product2_fb<PAIRS, NP>(sF, sY0, kp0, kp2, kpre, yc, acc, w2, tp1, tl, N, L, P, p.mu_sun,
+                                             rec_lds, sm.Rec, sm.Mu, grec);
         } else if constexpr (SO) {
             flag = pc_product2<PAIRS, NP>(sF, sY0, kp0, kp2, kpre, yc, acc, w2, tp1, tl, N, L);
         } else {
@@ -392,7 +452,7 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
 
 // Not inlined: one register allocation per node count, so the work-queue kernel that
 // dispatches to all of them does not pay for the largest one everywhere.
-template <int PAIRS, int NP, bool MIXED, bool EIH = false, bool SO = false>
+template <int PAIRS, int NP, bool MIXED, bool EIH = false, int SO = 0>
 __device__ __attribute__((noinline)) void pc_job(const PcParams& p, const PcJobDev& job, const PcGroupDev& g)
 {
     PcSmem<PAIRS>& sm = pc_smem<PAIRS>();
@@ -758,12 +818,14 @@ __global__ __launch_bounds__(PAIRS / 4, 2) void pc_fused_kernel(const PcParams* 
         const bool list = job.n > g.T;   // more ICs than columns: refilled columns (FP64 only)
         const bool mixed = p.precision == 1;
         const bool eih = p.inv_c2 != 0.0;   // relativistic model: one-block jobs
-        const bool order2 = p.order == 2;   // second-order sweeps: FP64, point masses, WIDE shapes
+        const bool order2 = p.order == 2;   // second-order sweeps (with the integral error feedback when
+                                            // asked): FP64, point masses, WIDE shapes
         switch (g.NP) {
         case 16:
             if constexpr (PcShape<PAIRS, 16>::WIDE) {
                 if (order2) {
-                    pc_job<PAIRS, 16, false, false, true>(p, job, g);
+                    if (p.feedback) pc_job<PAIRS, 16, false, false, 2>(p, job, g);
+                    else pc_job<PAIRS, 16, false, false, 1>(p, job, g);
                     break;
                 }
             }
@@ -776,7 +838,8 @@ __global__ __launch_bounds__(PAIRS / 4, 2) void pc_fused_kernel(const PcParams* 
         case 32:
             if constexpr (PcShape<PAIRS, 32>::WIDE) {
                 if (order2) {
-                    pc_job<PAIRS, 32, false, false, true>(p, job, g);
+                    if (p.feedback) pc_job<PAIRS, 32, false, false, 2>(p, job, g);
+                    else pc_job<PAIRS, 32, false, false, 1>(p, job, g);
                     break;
                 }
             }
@@ -789,7 +852,8 @@ __global__ __launch_bounds__(PAIRS / 4, 2) void pc_fused_kernel(const PcParams* 
         case 64:
             if constexpr (PcShape<PAIRS, 64>::WIDE) {
                 if (order2) {
-                    pc_job<PAIRS, 64, false, false, true>(p, job, g);
+                    if (p.feedback) pc_job<PAIRS, 64, false, false, 2>(p, job, g);
+                    else pc_job<PAIRS, 64, false, false, 1>(p, job, g);
                     break;
                 }
             }
@@ -802,7 +866,8 @@ __global__ __launch_bounds__(PAIRS / 4, 2) void pc_fused_kernel(const PcParams* 
         case 128:
             if constexpr (PcShape<PAIRS, 128>::WIDE) {
                 if (order2) {
-                    pc_job<PAIRS, 128, false, false, true>(p, job, g);
+                    if (p.feedback) pc_job<PAIRS, 128, false, false, 2>(p, job, g);
+                    else pc_job<PAIRS, 128, false, false, 1>(p, job, g);
                     break;
                 }
             }

@@ -49,7 +49,8 @@ class _Opts(ctypes.Structure):
                 ("tile_pairs", ctypes.c_int32), ("graph", ctypes.c_int32),
                 ("switch_tol", ctypes.c_double), ("max_fp32", ctypes.c_int32), ("job_list", ctypes.c_int32),
                 ("conv", ctypes.c_int32), ("streams", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("feedback", ctypes.c_int32), ("guess", ctypes.c_void_p), ("refine", ctypes.c_int32)]
+                ("feedback", ctypes.c_int32), ("guess", ctypes.c_void_p), ("refine", ctypes.c_int32),
+                ("flyby_hill", ctypes.c_double)]
 
 
 class _Group(ctypes.Structure):
@@ -66,7 +67,7 @@ EXPORTS = ("pc_default_opts", "pc_ctx_create", "pc_ctx_destroy", "pc_workspace_b
            "pc_eval_force", "pc_eval_kepler", "pc_set_timing", "pc_last_kernel_ms", "pc_autotune",
            "pc_set_tile_pairs", "pc_get_tile_pairs", "pc_adjoint", "pc_strerror", "pc_last_error",
            "pc_version", "pc_graph_captures", "pc_measure_ceilings",
-           "pc_set_job_list", "pc_get_job_list", "pc_propagate_batched_noalloc")
+           "pc_set_job_list", "pc_get_job_list", "pc_propagate_batched_noalloc", "pc_flyby_ratio")
 
 
 def load_library(path: str = LIB_PATH):
@@ -94,6 +95,8 @@ def load_library(path: str = LIB_PATH):
     lib.pc_propagate_batched_noalloc.argtypes = [_vp, _vp, ctypes.c_int64, P(_Group), ctypes.c_int32,
                                                  P(_Model), P(_Opts), _vp, _vp, ctypes.c_int32, _vp, _vp,
                                                  ctypes.c_int32, _vp]
+    lib.pc_flyby_ratio.argtypes = [_vp, _vp, ctypes.c_int64, P(_Group), ctypes.c_int32, P(_Model), ctypes.c_int32,
+                                   _vp, _vp, ctypes.c_size_t, _vp]
     lib.pc_get_operator.argtypes = [_vp, ctypes.c_int32, _dp]
     lib.pc_apply_operator.argtypes = [_vp, ctypes.c_int32, ctypes.c_int64, _vp, _vp, ctypes.c_double,
                                       _vp, _vp]
@@ -201,7 +204,7 @@ class Context:
     @staticmethod
     def opts(init="kepler", max_iter=64, tol_mode="rel", path="fused", fixed_iters=0,
              tile_pairs=0, precision="fp64", graph=False, switch_tol=0.0, max_fp32=0, job_list=0, conv="ic",
-             streams=1, order=1, feedback=0, guess=None, refine=0):
+             streams=1, order=1, feedback=0, guess=None, refine=0, flyby_hill=0.0):
         o = _Opts()
         o.init, o.max_iter, o.tol_mode = INIT[init], int(max_iter), TOL_MODE[tol_mode]
         o.precision, o.path, o.fixed_iters = PRECISION[precision], PATH[path], int(fixed_iters)
@@ -211,6 +214,7 @@ class Context:
         o.streams = int(streams)
         o.order, o.feedback = int(order), int(feedback)
         o.refine = int(refine)
+        o.flyby_hill = float(flyby_hill)
         if guess is not None:   # init "guess": device node states [n, S_max, N_max, 6]
             _check_tensor(guess, "guess")
             o.guess = guess.data_ptr()
@@ -313,6 +317,28 @@ class Context:
         if rc not in (PC_OK, PC_ENOTCONV, PC_ENONFINITE) or (raise_on_status and rc != PC_OK):
             self._raise(rc)
         return self._result(rc, states, iters, bounds, nodes)
+
+    def flyby_ratio(self, ics, groups, model, samples=16):
+        """pc_flyby_ratio: per IC, the smallest distance of its two-body prediction to any
+        perturber in Hill radii ([n] float64 tensor; +inf outside the groups)."""
+        _check_tensor(ics, "ics")
+        garr = (_Group * len(groups))(*[_Group(g.ic_offset, g.n_ic, g.t0, g.tf, g.nodes, g.segments, g.tol)
+                                       for g in groups])
+        mc = model._c()
+        ratio = torch.full((ics.shape[0],), float("inf"), dtype=torch.float64, device=ics.device)
+        nb = ctypes.c_size_t()
+        oc = self.opts()
+        rc = self.lib.pc_workspace_bytes(self.handle, garr, len(groups), ctypes.byref(mc), ctypes.byref(oc),
+                                         ctypes.byref(nb))
+        if rc != PC_OK:
+            self._raise(rc)
+        ws = self.workspace(nb.value)
+        rc = self.lib.pc_flyby_ratio(self.handle, ctypes.c_void_p(ics.data_ptr()), ics.shape[0], garr, len(groups),
+                                     ctypes.byref(mc), int(samples), ctypes.c_void_p(ratio.data_ptr()),
+                                     ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(ics.device))
+        if rc != PC_OK:
+            self._raise(rc)
+        return ratio
 
     def propagate(self, ics, t0, tf, nodes, segments, tol, model=None, **kw):
         g = Group(0, int(ics.shape[0]), float(t0), float(tf), int(nodes), int(segments), float(tol))

@@ -111,6 +111,45 @@ def test_fewer_sweeps_than_first_order(pc):
     assert rel_err(two["states"].cpu().numpy(), one["states"].cpu().numpy()).max() < 1e-10
 
 
+@pytest.mark.parametrize("nodes,tile", [(16, 2048), (64, 2048), (100, 2048), (128, 2048), (48, 1024)])
+def test_feedback_matches_oracle(pc, nodes, tile):
+    """Second-order sweeps with the integral error feedback against the oracle's feedback
+    form: states at every boundary to the bar, sweep counts within one."""
+    w = W.nbody_venus(37, seed=nodes + 7 * tile, days=112.5, segments=2, nodes=nodes)
+    r = _gpu(pc, w, tile_pairs=tile, feedback=1)
+    st, it, bd = _oracle(w, feedback=1)
+    assert r["status"] == 0
+    assert boundary_err(r["bounds"], bd).max() <= TOL
+    assert np.abs(r["iters"] - it).max() <= 1
+
+
+def test_feedback_fixed_sweeps_and_global_records(pc):
+    # fixed sweeps: the same arithmetic to rounding; 16 perturbers at 64 nodes in the
+    # 1024-pair shape read their records from global memory (3264 doubles, past the 3072 the
+    # shape keeps in LDS)
+    w = W.nbody_venus(40, seed=5, days=112.5, segments=2)
+    r = _gpu(pc, w, fixed_iters=6, feedback=1)
+    st, it, bd = _oracle(w, fixed_iters=6, feedback=1)
+    assert rel_err(r["states"], st).max() < 1e-12
+    w = W.nbody_venus(40, seed=6, days=112.5, segments=2, nodes=64)
+    pert16 = np.concatenate([w.pert, w.pert * np.array([0.5, 1.02, 1, 1, 1, 1, 1]) + np.array([0, 0, 0, 0, 0, 0, 1.0])])
+    w16 = W.Workload("p16", w.ics, w.groups, pert16, w.init)
+    r = _gpu(pc, w16, feedback=1, tile_pairs=1024)
+    st, it, bd = _oracle(w16, feedback=1)
+    assert r["status"] == 0 and boundary_err(r["bounds"], bd).max() <= TOL
+
+
+def test_feedback_takes_fewer_sweeps_than_second_order(pc):
+    w = W.nbody_venus(512, seed=8)
+    two = _gpu(pc, w)
+    fb = _gpu(pc, w, feedback=1)
+    i2, ifb = two["iters"], fb["iters"]
+    assert two["status"] == 0 and fb["status"] == 0
+    assert ifb.mean() < 0.8 * i2.mean()
+    # the same fixed point (to the stopping tolerance's truncation)
+    assert rel_err(fb["states"], two["states"]).max() < 1e-10
+
+
 def test_second_order_refusals(pc):
     from paper_2301_03989_amd import pcprop
     w = W.nbody_venus(16, days=56.25, segments=1)
@@ -120,7 +159,6 @@ def test_second_order_refusals(pc):
     bad = [dict(groups=[pcprop.Group(0, 16, g.t0, g.tf, 200, 1, g.tol)], kw={}),          # 256 padded nodes
            dict(groups=None, kw=dict(precision="fp32-fp64")),
            dict(groups=None, kw=dict(path="plain")),
-           dict(groups=None, kw=dict(feedback=1)),
            dict(groups=None, kw=dict(tile_pairs=1024, **{}), nodes=128)]
     for case in bad:
         nodes = case.get("nodes", g.nodes)
@@ -131,3 +169,6 @@ def test_second_order_refusals(pc):
     with pytest.raises(pcprop.PcError):
         pc.propagate_batched(ics, [pcprop.Group(0, 16, g.t0, g.tf, g.nodes, 1, g.tol)],
                              pcprop.Model(1.0, w.pert, 0.0, 1e-8), order=2)
+    with pytest.raises(pcprop.PcError) as e:   # feedback belongs to the second-order form
+        pc.propagate_batched(ics, [pcprop.Group(0, 16, g.t0, g.tf, g.nodes, 1, g.tol)], model, feedback=1)
+    assert e.value.code == pcprop.PC_EINVAL
