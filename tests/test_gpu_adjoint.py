@@ -187,7 +187,8 @@ def test_min_venus_distance_gradient(pc):
 
 def test_adjoint_full_size_sampled(pc):
     """The 16384-IC, 256-day, 5-segment, 128-node ensemble: every IC's gradient is computed on
-    the GPU; 4 of them are checked against the oracle."""
+    the GPU; a seeded sample of 64 of them (with the first and last IC) is checked against
+    the oracle."""
     w = W.adjoint_ensemble()
     ics, groups, model, om, g = _setup(w)
     fwd = pc.propagate_batched(ics, groups, model, want_bounds=True)
@@ -198,7 +199,7 @@ def test_adjoint_full_size_sampled(pc):
     assert st == 0
     gr = grad.cpu().numpy()
     assert np.isfinite(gr).all()
-    idx = np.array([0, 5000, 11111, w.n_ic - 1])
+    idx = np.unique(np.concatenate([[0, w.n_ic - 1], np.random.default_rng(12).choice(w.n_ic, 62, replace=False)]))
     ref = oracle.adjoint(w.ics[idx], g.t0, g.tf, g.nodes, g.segments, g.tol, om, gbar[idx])
     assert _gerr(gr[idx], ref).max() < GTOL
 
