@@ -247,6 +247,17 @@ static __device__ __forceinline__ void pc_accel(double x, double y, double z, co
 // ---------------------------------------------------------------------------
 typedef const __attribute__((address_space(1))) double* gconst_dp;
 typedef const __attribute__((address_space(1))) float* gconst_fp;
+typedef __attribute__((address_space(1))) double* gdp;
+typedef __attribute__((address_space(1))) int32_t* gi32p;
+
+// Global-memory views of the buffers the kernel parameters point to.  Pointers read from
+// the parameter block are generic, so the compiler emits flat loads and stores for them;
+// a flat access counts against the LDS counter too, so the next wait for an LDS read also
+// waits for it to reach memory, and it may alias LDS, so loads around LDS stores are
+// issued one at a time.  Through these views the accesses are global instructions.
+static __device__ __forceinline__ gdp pc_gd(double* q) { return (gdp)q; }
+static __device__ __forceinline__ gconst_dp pc_gcd(const double* q) { return (gconst_dp)q; }
+static __device__ __forceinline__ gi32p pc_gi(int32_t* q) { return (gi32p)q; }
 
 // Shared-memory arena of one workgroup (sized for the largest job shape).
 template <int PAIRS>

@@ -204,7 +204,7 @@ static __device__ __forceinline__ void pc_stage_records(const double4* grec, int
 template <int PAIRS, int NP, bool MIXED = false, bool EIH = false, int SO = 0>
 static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const PcGroupDev& g, int n, int64_t ic0,
                                                         int s, PcSmem<PAIRS>& sm, const PcLane& L, gconst_dp kp0,
-                                                        double (&yc)[6][4], int32_t* iters_out, int& had_notconv,
+                                                        double (&yc)[6][4], gi32p iters_out, int& had_notconv,
                                                         int rec_cap = PcSmem<PAIRS>::REC)
 {
     using Sh = PcShape<PAIRS, NP>;
@@ -216,6 +216,9 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
     const int P = p.n_pert;
     const int64_t ic = ic0 + tid;
     const bool rec_lds = N * 3 * (P + 1) <= rec_cap;
+    const int istride = p.iters_stride;
+    const int fixed_iters = p.fixed_iters, max_iter = p.max_iter;
+    const double mu_sun = p.mu_sun;
     const double t2 = g.tol * g.tol;
     const double Ts = g.t0 + g.h * (s + g.s0), Te = g.t0 + g.h * (s + g.s0 + 1);
     const double w2 = 0.5 * (Te - Ts);
@@ -248,7 +251,7 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
                 }
                 have = fin;
             } else if (j < N && warm) {
-                have = pc_kepler(y0, w2 * (g.tau[j] + 1.0), y);
+                have = pc_kepler(y0, w2 * (pc_gcd(g.tau)[j] + 1.0), y);
             }
             if (!have) {
 #pragma unroll
@@ -306,14 +309,14 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
         erec = reinterpret_cast<const double4*>(p.recs_eih) + (size_t)(g.rec_offset + (int64_t)s * N) * pc_eih_rec(P);
     if (act[0] | act[1] | act[2] | act[3]) {
         if constexpr (EIH) pc_publish_eih<PAIRS, NP>(sF, yc, L, N, P, erec, p.inv_c2);
-        else if (MIXED && mode == 1) pc_publish<PAIRS, NP, MIXED>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
-        else pc_publish<PAIRS, NP>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
+        else if (MIXED && mode == 1) pc_publish<PAIRS, NP, MIXED>(sF, yc, L, N, P, mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
+        else pc_publish<PAIRS, NP>(sF, yc, L, N, P, mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
     }
     __syncthreads();
 
     // FP32 fragments: natural order for the transposed WIDE product, row-permuted otherwise
     gconst_fp kp0f = (gconst_fp)(Sh::WIDE ? g.kfrag32 : g.kfrag32p) + (size_t)L.strip0 * NQ * 64 + L.lane;
-    const int n_it = p.fixed_iters > 0 ? p.fixed_iters : p.max_iter;
+    const int n_it = fixed_iters > 0 ? fixed_iters : max_iter;
     double kpre[8];
     pc_kpre_load<PAIRS, NP>(kp0, kpre);
     // second-order sweeps: the K2_N strip and its first fragments next to K_N's, and the
@@ -324,7 +327,7 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
         kp2 = (gconst_dp)g.kfrag2 + (size_t)L.strip0 * NQ * 64 + L.lane;
 #pragma unroll
         for (int u = 0; u < 4; ++u) kpre[4 + u] = kp2[u * 64];
-        tp1 = g.tau[pc_node(L, 0, 0)] + 1.0;
+        tp1 = pc_gcd(g.tau)[pc_node(L, 0, 0)] + 1.0;
     }
     for (int it = 1; it <= n_it; ++it) {
         // (1)-(2) product and stopping-rule flags
@@ -339,7 +342,7 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
             flag = mode == 1 ? pc_product<PAIRS, NP, true>(sF, sY0, kp0, kpre, kp0f, yc, acc, w2, tl, N, L)
                              : pc_product<PAIRS, NP, false>(sF, sY0, kp0, kpre, kp0f, yc, acc, w2, tl, N, L);
         } else if constexpr (SO == 2) {
-            flag = pc_product2_fb<PAIRS, NP>(sF, sY0, kp0, kp2, kpre, yc, acc, w2, tp1, tl, N, L, P, p.mu_sun,
+            flag = pc_product2_fb<PAIRS, NP>(sF, sY0, kp0, kp2, kpre, yc, acc, w2, tp1, tl, N, L, P, mu_sun,
                                              rec_lds, sm.Rec, sm.Mu, grec);
         } else if constexpr (SO) {
             flag = pc_product2<PAIRS, NP>(sF, sY0, kp0, kp2, kpre, yc, acc, w2, tp1, tl, N, L);
@@ -389,14 +392,14 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
             const int f = pc_gather_flags<PAIRS, NP>(sm.Flag, tid);
             int rec = 0;
             if (f & 2) rec = -2;
-            else if (p.fixed_iters > 0) rec = (it == p.fixed_iters) ? it : 0;
+            else if (fixed_iters > 0) rec = (it == fixed_iters) ? it : 0;
             else if (stops && !(f & 1)) rec = it;
-            else if (it == p.max_iter) rec = -1;
+            else if (it == max_iter) rec = -1;
             if (rec != 0) {
                 sm.Active[tid] = 0;
                 if (rec == -2) sm.Dead[tid] = 1;
                 if (rec == -1) had_notconv = 1;
-                if (tid < n && iters_out) iters_out[(size_t)ic * p.iters_stride + s] = rec;
+                if (tid < n && iters_out) iters_out[(size_t)ic * istride + s] = rec;
             }
         }
         pc_note_active<PAIRS, NP>(sm, L);
@@ -415,7 +418,7 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
                     }
                 }
                 // after an FP64 sweep the new iterate is the anchor: G evaluated there
-                pc_publish_chord<PAIRS, NP>(sD, sG, yc, dy, act, mode != 2, L, N, P, p.mu_sun, sm.Rec, sm.Mu);
+                pc_publish_chord<PAIRS, NP>(sD, sG, yc, dy, act, mode != 2, L, N, P, mu_sun, sm.Rec, sm.Mu);
                 fp32 = next32;
                 mode = next_mode;
                 __syncthreads();   // F complete; the active notes visible
@@ -439,8 +442,8 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
             if (it < n_it) {
                 if constexpr (EIH) pc_publish_eih<PAIRS, NP>(sF, yc, L, N, P, erec, p.inv_c2);
                 else if (MIXED && next_mode == 1)
-                    pc_publish<PAIRS, NP, MIXED>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
-                else pc_publish<PAIRS, NP>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
+                    pc_publish<PAIRS, NP, MIXED>(sF, yc, L, N, P, mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
+                else pc_publish<PAIRS, NP>(sF, yc, L, N, P, mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
             }
         }
         fp32 = next32;
@@ -465,9 +468,14 @@ __device__ __attribute__((noinline)) void pc_job(const PcParams& p, const PcJobD
     const int N = g.N, S = g.S;
     const int n = job.n;
     const int64_t ic = job.ic0 + tid;      // this thread's IC when tid < n
+    // the buffers of the call, read once from the parameter block as global pointers
+    const gdp g_bounds = pc_gd(p.bounds_out);
+    const gdp g_nodes = pc_gd(p.nodes_out);
+    const gi32p g_iters = pc_gi(p.iters_out);
+    const int istride = p.iters_stride, nstride = p.nodes_stride;
 
     if (tid < T) {
-        const double* y = p.ics + (job.ic0 + (tid < n ? tid : 0)) * 6;
+        const gconst_dp y = pc_gcd(p.ics) + (job.ic0 + (tid < n ? tid : 0)) * 6;
         bool fin = true;
         for (int c = 0; c < 6; ++c) {
             const double v = y[c];
@@ -483,13 +491,13 @@ __device__ __attribute__((noinline)) void pc_job(const PcParams& p, const PcJobD
     int had_notconv = 0;
     for (int s = 0; s < S; ++s) {
         if (tid < n) {
-            if (p.bounds_out) {
-                double* bo = p.bounds_out + ((size_t)ic * (p.iters_stride + 1) + s) * 6;
+            if (g_bounds) {
+                const gdp bo = g_bounds + ((size_t)ic * (istride + 1) + s) * 6;
                 for (int c = 0; c < 6; ++c) bo[c] = sY0[c * T + tid];
             }
-            if (sm.Dead[tid] && p.iters_out) p.iters_out[(size_t)ic * p.iters_stride + s] = -2;
+            if (sm.Dead[tid] && g_iters) g_iters[(size_t)ic * istride + s] = -2;
         }
-        pc_segment_solve<PAIRS, NP, MIXED, EIH, SO>(p, g, n, job.ic0, s, sm, L, kp0, yc, p.iters_out, had_notconv);
+        pc_segment_solve<PAIRS, NP, MIXED, EIH, SO>(p, g, n, job.ic0, s, sm, L, kp0, yc, g_iters, had_notconv);
 
         // converged node states of the segment (optional output), chaining (Sec. 2.2)
 #pragma unroll
@@ -500,9 +508,8 @@ __device__ __attribute__((noinline)) void pc_job(const PcParams& p, const PcJobD
                 const int m = pc_ic(L, r);
                 const bool dead = sm.Dead[m];
                 if (j >= N) continue;
-                if (p.nodes_out && m < n) {
-                    double* o = p.nodes_out +
-                                (((size_t)(job.ic0 + m) * p.iters_stride + s) * p.nodes_stride + j) * 6;
+                if (g_nodes && m < n) {
+                    const gdp o = g_nodes + (((size_t)(job.ic0 + m) * istride + s) * nstride + j) * 6;
                     if constexpr (Sh::WIDE) {
 #pragma unroll
                         for (int c = 0; c < 6; ++c) o[c] = yc[c][r];
@@ -527,10 +534,10 @@ __device__ __attribute__((noinline)) void pc_job(const PcParams& p, const PcJobD
     }
 
     if (tid < n) {
-        double* so = p.states_out + (size_t)ic * 6;
+        const gdp so = pc_gd(p.states_out) + (size_t)ic * 6;
         for (int c = 0; c < 6; ++c) so[c] = sY0[c * T + tid];
-        if (p.bounds_out) {
-            double* bo = p.bounds_out + ((size_t)ic * (p.iters_stride + 1) + S) * 6;
+        if (g_bounds) {
+            const gdp bo = g_bounds + ((size_t)ic * (istride + 1) + S) * 6;
             for (int c = 0; c < 6; ++c) bo[c] = sY0[c * T + tid];
         }
         if (had_notconv) atomicAdd(&p.counters[0], 1);
@@ -577,12 +584,21 @@ __device__ __attribute__((noinline)) void pc_job_list(const PcParams& p, const P
     auto ic_of = [&](int e) -> int64_t { return job.ic0 + grp + (int64_t)GN * e; };
     auto col_of = [&](int e) -> int { return Sh::WIDE ? pc_ic(L, e) - grp * 16 : (L.lane & 7); };
     int notconv = 0;
+    // the buffers of the call, read once from the parameter block as global pointers
+    const gconst_dp g_ics = pc_gcd(p.ics);
+    const gdp g_states = pc_gd(p.states_out);
+    const gdp g_bounds = pc_gd(p.bounds_out);
+    const gdp g_nodes = pc_gd(p.nodes_out);
+    const gi32p g_iters = pc_gi(p.iters_out);
+    const int istride = p.iters_stride, nstride = p.nodes_stride;
+    const int fixed_iters = p.fixed_iters, max_iter = p.max_iter;
+    const double mu_sun = p.mu_sun;
 
     double yc[6][4];
     for (int s = 0; s < S; ++s) {
         const double Ts = g.t0 + g.h * (s + g.s0), Te = g.t0 + g.h * (s + g.s0 + 1);
         const double w2 = 0.5 * (Te - Ts);
-        const double* src = s == 0 ? p.ics : p.states_out;
+        const gconst_dp src = s == 0 ? g_ics : g_states;
         const double4* grec = reinterpret_cast<const double4*>(p.recs) +
                               (size_t)(g.rec_offset + (int64_t)s * N) * (P + 1);
         // Warm (or cold) start, Sec. 2.1, of the group's columns in `rm`, column c taking entry
@@ -600,7 +616,7 @@ __device__ __attribute__((noinline)) void pc_job_list(const PcParams& p, const P
                 const int c = __ffs(m) - 1;
                 const int j = L.strip0 * 16 + jn;
                 if (j >= N) continue;
-                const double* y0p = src + ic_of(base + ci) * 6;
+                const gconst_dp y0p = src + ic_of(base + ci) * 6;
                 double y0[6];
                 bool fin = true;
 #pragma unroll
@@ -609,7 +625,7 @@ __device__ __attribute__((noinline)) void pc_job_list(const PcParams& p, const P
                     fin = fin && isfinite(y0[cc]);
                 }
                 double y[6];
-                if (!(p.init == 0 && fin && pc_kepler(y0, w2 * (g.tau[j] + 1.0), y))) {
+                if (!(p.init == 0 && fin && pc_kepler(y0, w2 * (pc_gcd(g.tau)[j] + 1.0), y))) {
 #pragma unroll
                     for (int cc = 0; cc < 6; ++cc) y[cc] = y0[cc];
                 }
@@ -643,12 +659,16 @@ __device__ __attribute__((noinline)) void pc_job_list(const PcParams& p, const P
         // the owner lane of a column writes its IC's y0 (product epilogue) and checkpoint
         auto own_column = [&](int en) {
             const int64_t icg = ic_of(en);
-            const double* y0p = src + icg * 6;
+            const gconst_dp y0p = src + icg * 6;
+            double v[6];
 #pragma unroll
-            for (int c = 0; c < 6; ++c) {
-                const double v = y0p[c];
-                sY0[c * T + grp * 16 + fcol] = v;
-                if (p.bounds_out) p.bounds_out[((size_t)icg * (p.iters_stride + 1) + s) * 6 + c] = v;
+            for (int c = 0; c < 6; ++c) v[c] = y0p[c];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) sY0[c * T + grp * 16 + fcol] = v[c];
+            if (g_bounds) {
+                const gdp bo = g_bounds + ((size_t)icg * (istride + 1) + s) * 6;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) bo[c] = v[c];
             }
         };
 
@@ -666,7 +686,7 @@ __device__ __attribute__((noinline)) void pc_job_list(const PcParams& p, const P
         int it0 = 0;                          // flag lane: sweep before its IC's first one
         if (owner && fent >= 0) own_column(fent);
         __syncthreads();   // y0 written
-        if (amask) pc_publish<PAIRS, NP>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
+        if (amask) pc_publish<PAIRS, NP>(sF, yc, L, N, P, mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
         __syncthreads();
 
         for (int it = 1;; ++it) {
@@ -681,14 +701,14 @@ __device__ __attribute__((noinline)) void pc_job_list(const PcParams& p, const P
                 const int f = pc_gather_flags<PAIRS, NP>(sm.Flag, grp * 16 + fcol);
                 const int k = it - it0;
                 if (f & 2) rec = -2;
-                else if (p.fixed_iters > 0) rec = (k == p.fixed_iters) ? k : 0;
+                else if (fixed_iters > 0) rec = (k == fixed_iters) ? k : 0;
                 else if (!(f & 1)) rec = k;
-                else if (k >= p.max_iter) rec = -1;
+                else if (k >= max_iter) rec = -1;
             }
             const unsigned smask = (unsigned)__ballot(rec != 0) & CMASK;
             const unsigned dmask = (unsigned)__ballot(rec == -2) & CMASK;
             if (owner && rec != 0) {
-                if (p.iters_out) p.iters_out[(size_t)ic_of(fent) * p.iters_stride + s] = rec;
+                if (g_iters) g_iters[(size_t)ic_of(fent) * istride + s] = rec;
                 if (rec == -1) ++notconv;
             }
             // the columns that were iterating take the new iterate
@@ -719,27 +739,34 @@ __device__ __attribute__((noinline)) void pc_job_list(const PcParams& p, const P
                             if (Sh::WIDE && r != e) continue;
                             const int j = Sh::WIDE ? pc_node(L, 0, 0) : pc_node(L, h, r);
                             if (j >= N) continue;
-                            double* nd = p.nodes_out
-                                             ? p.nodes_out + (((size_t)icg * p.iters_stride + s) * p.nodes_stride + j) * 6
-                                             : nullptr;
-                            double* so = j == N - 1 ? p.states_out + icg * 6 : nullptr;
-                            double* bo = (j == N - 1 && p.bounds_out)
-                                             ? p.bounds_out + ((size_t)icg * (p.iters_stride + 1) + s + 1) * 6
-                                             : nullptr;
-                            if constexpr (Sh::WIDE) {
+                            if (g_nodes) {
+                                const gdp nd = g_nodes + (((size_t)icg * istride + s) * nstride + j) * 6;
+                                if constexpr (Sh::WIDE) {
 #pragma unroll
-                                for (int cc = 0; cc < 6; ++cc) {
-                                    if (nd) nd[cc] = yc[cc][e];
-                                    if (so) so[cc] = dead ? (double)NAN : yc[cc][e];
-                                    if (bo) bo[cc] = dead ? (double)NAN : yc[cc][e];
+                                    for (int cc = 0; cc < 6; ++cc) nd[cc] = yc[cc][e];
+                                } else {
+#pragma unroll
+                                    for (int cb = 0; cb < 3; ++cb) nd[2 * cb + L.hi] = yc[3 * h + cb][r];
                                 }
-                            } else {
+                            }
+                            if (j == N - 1) {
+                                const gdp so = g_states + icg * 6;
+                                const gdp bo = g_bounds ? g_bounds + ((size_t)icg * (istride + 1) + s + 1) * 6 : g_bounds;
+                                if constexpr (Sh::WIDE) {
 #pragma unroll
-                                for (int cb = 0; cb < 3; ++cb) {
-                                    const int cc = 2 * cb + L.hi;
-                                    if (nd) nd[cc] = yc[3 * h + cb][r];
-                                    if (so) so[cc] = dead ? (double)NAN : yc[3 * h + cb][r];
-                                    if (bo) bo[cc] = dead ? (double)NAN : yc[3 * h + cb][r];
+                                    for (int cc = 0; cc < 6; ++cc) {
+                                        const double v = dead ? (double)NAN : yc[cc][e];
+                                        so[cc] = v;
+                                        if (bo) bo[cc] = v;
+                                    }
+                                } else {
+#pragma unroll
+                                    for (int cb = 0; cb < 3; ++cb) {
+                                        const int cc = 2 * cb + L.hi;
+                                        const double v = dead ? (double)NAN : yc[3 * h + cb][r];
+                                        so[cc] = v;
+                                        if (bo) bo[cc] = v;
+                                    }
                                 }
                             }
                         }
@@ -774,7 +801,7 @@ __device__ __attribute__((noinline)) void pc_job_list(const PcParams& p, const P
                 next += take;
                 amask = (amask & ~smask) | rmask;
             }
-            if (amask) pc_publish<PAIRS, NP>(sF, yc, L, N, P, p.mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
+            if (amask) pc_publish<PAIRS, NP>(sF, yc, L, N, P, mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
             // every wave of an IC group holds the group's column mask: the first strip's waves
             // note it (rewritten only after the next sweep's first barrier)
             if (L.strip0 == 0 && L.lane == 0) sm.Go[L.grp] = amask != 0u;
@@ -788,7 +815,7 @@ __device__ __attribute__((noinline)) void pc_job_list(const PcParams& p, const P
     if (notconv) atomicAdd(&p.counters[0], notconv);
     __syncthreads();   // every end state written
     for (int e = tid; e < n; e += NT) {
-        const double* y = p.states_out + (job.ic0 + e) * 6;
+        const gconst_dp y = g_states + (job.ic0 + e) * 6;
         bool fin = true;
         for (int c = 0; c < 6; ++c) fin = fin && isfinite(y[c]);
         if (!fin) atomicAdd(&p.counters[1], 1);
