@@ -247,9 +247,9 @@ def boundary_errors(gpu_bounds, ref_bounds):
     return np.where(used, e, 0.0).max(axis=1)
 
 
-def oracle_run(w, idx, threads=0):
+def oracle_run(w, idx, threads=0, order=1):
     """Oracle states, iterations and segment-boundary states of the ICs ``idx`` of ``w``,
-    and the wall time and thread count it took."""
+    and the wall time and thread count it took (``order`` 2: the second-order form)."""
     import oracle
     model = oracle.Model(w.mu_sun, w.pert, w.epoch, inv_c2=w.inv_c2)
     S_max = max(g.segments for g in w.groups)
@@ -262,7 +262,7 @@ def oracle_run(w, idx, threads=0):
         sel = np.nonzero((idx >= g.ic_offset) & (idx < g.ic_offset + g.n_ic))[0]
         if sel.size:
             s, it, b = oracle.propagate(w.ics[idx[sel]], g.t0, g.tf, g.nodes, g.segments, g.tol, model,
-                                        init=w.init, want_bounds=True, threads=threads)
+                                        init=w.init, want_bounds=True, threads=threads, order=order)
             states[sel], iters[sel, :g.segments], bounds[sel, :g.segments + 1] = s, it, b
             used = max(used, oracle.propagate.last_threads)
     return states, iters, bounds, time.perf_counter() - t0, used
@@ -332,6 +332,12 @@ def main():
     ap.add_argument("--mixed-steps", type=int, default=3)
     ap.add_argument("--mixed-check-ics", type=int, default=1024)
     ap.add_argument("--no-ceilings", action="store_true", help="skip the on-chip ceiling loops")
+    ap.add_argument("--second-order-workload", default="nbody-venus-4096",
+                    help="workload of the second-order sub-record ('' skips it)")
+    ap.add_argument("--second-order-steps", type=int, default=5)
+    ap.add_argument("--flyby-hill", type=float, default=5.0,
+                    help="threshold (Hill radii) of the flyby-isolation sub-record on the group-max plain "
+                         "path (0 skips it)")
     ap.add_argument("--adjoint-nodes", action="store_true",
                     help="with --adjoint: keep the forward's node states and read them in the adjoint "
                          "instead of re-solving each segment from its checkpoint")
@@ -503,6 +509,14 @@ def main():
     if args.mixed_workload and precision == "fp64":
         mixed = run_mixed(args, ctx, workloads.WORKLOADS[args.mixed_workload](), pcprop)
 
+    second = None
+    if args.second_order_workload and precision == "fp64":
+        second = run_second_order(args, ctx, workloads.WORKLOADS[args.second_order_workload](), pcprop)
+
+    flyby = None
+    if args.flyby_hill > 0 and precision == "fp64" and w.inv_c2 == 0.0:
+        flyby = run_flyby(args, ctx, w, pcprop)
+
     cpu = None
     if not args.no_cpu_baseline:
         name, affinity = cpu_model()
@@ -552,11 +566,102 @@ def main():
         "segment_iterations_per_s": round(float(np.where(iters > 0, iters, 0).sum()) / (ms_per_step * 1e-3), 1),
         "vs_plain": plain or None,
         "mixed_precision": mixed,
+        "second_order": second,
+        "flyby_isolation": flyby,
         "autotune": tuned,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def run_second_order(args, ctx, w, pcprop):
+    """The second-order sub-record: the workload with first-order sweeps (the iteration of
+    Sec. 2.2) and with second-order sweeps (velocity and position both from the acceleration
+    fit), the same fused FP64 kernel; time, sweeps per segment, and each form's error against
+    the oracle run in the same form on a seeded sample, at every segment boundary."""
+    import torch
+    n_ic = w.n_ic
+    S = max(g.segments for g in w.groups)
+    ics = torch.tensor(w.ics, dtype=torch.float64, device="cuda")
+    groups = [pcprop.Group(g.ic_offset, g.n_ic, g.t0, g.tf, g.nodes, g.segments, g.tol) for g in w.groups]
+    model = pcprop.Model(w.mu_sun, w.pert, w.epoch, w.inv_c2)
+    idx = np.sort(np.random.default_rng(11).choice(n_ic, size=min(64, n_ic), replace=False))
+    res = {}
+    for order in (1, 2):
+        st = torch.empty((n_ic, 6), dtype=torch.float64, device="cuda")
+        it = torch.zeros((n_ic, S), dtype=torch.int32, device="cuda")
+        bd = torch.empty((n_ic, S + 1, 6), dtype=torch.float64, device="cuda")
+        kw = dict(order=order, out=st, iters_out=it, bounds_out=bd)
+        ctx.propagate_batched(ics, groups, model, **kw)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.second_order_steps):
+            r = ctx.propagate_batched(ics, groups, model, **kw)
+        e1.record()
+        torch.cuda.synchronize()
+        _, ref_it, ref_b, _, _ = oracle_run(w, idx, order=order)
+        iters = it.cpu().numpy()
+        err = boundary_errors(bd.cpu().numpy()[idx], ref_b)
+        res[order] = {"ms_per_step": round(e0.elapsed_time(e1) / args.second_order_steps, 4),
+                      "status": int(r["status"]),
+                      "mean_sweeps_per_segment": round(float(iters[iters > 0].mean()), 3),
+                      "max_rel_err_vs_oracle_same_form": float(err.max()),
+                      "max_sweep_diff_vs_oracle": int(np.abs(iters[idx] - ref_it).max())}
+        res[order]["states"] = st.cpu().numpy()
+    diff = float(rel_err(res[2].pop("states"), res[1].pop("states")).max())
+    n_icseg = sum(g.n_ic * g.segments for g in w.groups)
+    out = {"workload": w.name, "n_ic": n_ic, "steps": args.second_order_steps,
+           "first_order": res[1], "second_order": res[2],
+           "ic_segments_per_s_second_order": round(n_icseg / (res[2]["ms_per_step"] * 1e-3), 1),
+           "speedup_second_vs_first": round(res[1]["ms_per_step"] / res[2]["ms_per_step"], 3),
+           "max_rel_diff_between_forms": diff,
+           "checked_ics": int(idx.size),
+           "valid": bool(res[2]["max_rel_err_vs_oracle_same_form"] <= 1e-10 and res[2]["status"] == 0)}
+    print(f"bench: {w.name}: second-order {res[2]['ms_per_step']:.3f} ms/step "
+          f"({res[2]['mean_sweeps_per_segment']} sweeps/segment), first-order {res[1]['ms_per_step']:.3f} ms/step "
+          f"({res[1]['mean_sweeps_per_segment']}), speedup {out['speedup_second_vs_first']}x, max err vs its "
+          f"oracle {res[2]['max_rel_err_vs_oracle_same_form']:.2e}, forms differ by {diff:.1e}", flush=True)
+    return out
+
+
+def run_flyby(args, ctx, w, pcprop):
+    """The flyby-isolation sub-record: the workload on the plain path under the group-max
+    stopping rule (the paper's per-system convergence), each group as one outer group and
+    with its flyby ICs (two-body prediction within --flyby-hill Hill radii of a planet) in a
+    group of their own; time and mean sweeps per segment of the quiet ICs."""
+    import torch
+    S = max(g.segments for g in w.groups)
+    ics = torch.tensor(w.ics, dtype=torch.float64, device="cuda")
+    groups = [pcprop.Group(g.ic_offset, g.n_ic, g.t0, g.tf, g.nodes, g.segments, g.tol) for g in w.groups]
+    model = pcprop.Model(w.mu_sun, w.pert, w.epoch, w.inv_c2)
+    ratio = ctx.flyby_ratio(ics, groups, model).cpu().numpy()
+    quiet = ratio >= args.flyby_hill
+    res = {}
+    for hill in (0.0, args.flyby_hill):
+        it = torch.zeros((w.n_ic, S), dtype=torch.int32, device="cuda")
+        kw = dict(path="plain", conv="group", flyby_hill=hill, iters_out=it)
+        ctx.propagate_batched(ics, groups, model, **kw)   # untimed: first launches of its kernels
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = ctx.propagate_batched(ics, groups, model, **kw)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        iters = it.cpu().numpy()
+        res[hill] = {"ms": round(ms, 2), "status": int(r["status"]),
+                     "mean_sweeps_per_segment_quiet": round(float(iters[quiet][iters[quiet] > 0].mean()), 3),
+                     "mean_sweeps_per_segment_all": round(float(iters[iters > 0].mean()), 3)}
+    out = {"workload": w.name, "path": "plain", "conv": "group", "hill_radii": args.flyby_hill,
+           "isolated_ics": int((~quiet).sum()), "n_ic": w.n_ic,
+           "without_isolation": res[0.0], "with_isolation": res[args.flyby_hill],
+           "speedup": round(res[0.0]["ms"] / res[args.flyby_hill]["ms"], 3)}
+    print(f"bench: flyby isolation ({(~quiet).sum()} of {w.n_ic} ICs within {args.flyby_hill} Hill radii), group-max "
+          f"plain path: {res[0.0]['ms']:.1f} -> {res[args.flyby_hill]['ms']:.1f} ms, quiet ICs' sweeps "
+          f"{res[0.0]['mean_sweeps_per_segment_quiet']} -> {res[args.flyby_hill]['mean_sweeps_per_segment_quiet']}",
+          flush=True)
+    return out
 
 
 def run_mixed(args, ctx, w, pcprop):
