@@ -507,11 +507,11 @@ def main():
 
     mixed = None
     if args.mixed_workload and precision == "fp64":
-        mixed = run_mixed(args, ctx, workloads.WORKLOADS[args.mixed_workload](), pcprop)
+        mixed = run_mixed(args, workloads.WORKLOADS[args.mixed_workload](), pcprop)
 
     second = None
     if args.second_order_workload and precision == "fp64":
-        second = run_second_order(args, ctx, workloads.WORKLOADS[args.second_order_workload](), pcprop)
+        second = run_second_order(args, workloads.WORKLOADS[args.second_order_workload](), pcprop)
 
     flyby = None
     if args.flyby_hill > 0 and precision == "fp64" and w.inv_c2 == 0.0:
@@ -575,17 +575,22 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def run_second_order(args, ctx, w, pcprop):
+def run_second_order(args, w, pcprop):
     """The second-order sub-record: the workload with first-order sweeps (the iteration of
     Sec. 2.2) and with second-order sweeps (velocity and position both from the acceleration
     fit), the same fused FP64 kernel; time, sweeps per segment, and each form's error against
-    the oracle run in the same form on a seeded sample, at every segment boundary."""
+    the oracle run in the same form on a seeded sample, at every segment boundary.  A context
+    of its own, tuned for this workload (the first-order sweeps may run refilled column
+    lists, the second-order ones run one-block jobs), so the main batch's tuning plays no
+    part."""
     import torch
     n_ic = w.n_ic
     S = max(g.segments for g in w.groups)
     ics = torch.tensor(w.ics, dtype=torch.float64, device="cuda")
     groups = [pcprop.Group(g.ic_offset, g.n_ic, g.t0, g.tf, g.nodes, g.segments, g.tol) for g in w.groups]
     model = pcprop.Model(w.mu_sun, w.pert, w.epoch, w.inv_c2)
+    ctx = pcprop.Context(0)
+    ctx.autotune(ics, groups, model)
     idx = np.sort(np.random.default_rng(11).choice(n_ic, size=min(64, n_ic), replace=False))
     res = {}
     for order in (1, 2):
@@ -664,16 +669,19 @@ def run_flyby(args, ctx, w, pcprop):
     return out
 
 
-def run_mixed(args, ctx, w, pcprop):
+def run_mixed(args, w, pcprop):
     """The mixed-precision sub-record: the workload under the FP32 -> FP64 schedule and all
     in FP64, the same kernel and call, with per-IC errors of both against the FP64 oracle on
-    a seeded sample (at every segment boundary)."""
+    a seeded sample (at every segment boundary).  A context of its own, its FP64 run tuned
+    for this workload."""
     import torch
     n_ic = w.n_ic
     S = max(g.segments for g in w.groups)
     ics = torch.tensor(w.ics, dtype=torch.float64, device="cuda")
     groups = [pcprop.Group(g.ic_offset, g.n_ic, g.t0, g.tf, g.nodes, g.segments, g.tol) for g in w.groups]
     model = pcprop.Model(w.mu_sun, w.pert, w.epoch, w.inv_c2)
+    ctx = pcprop.Context(0)
+    ctx.autotune(ics, groups, model)
     res = {}
     for prec in ("fp32-fp64", "fp64"):
         st = torch.empty((n_ic, 6), dtype=torch.float64, device="cuda")
