@@ -636,7 +636,8 @@ def run_flyby(args, ctx, w, pcprop):
     """The flyby-isolation sub-record: the workload on the plain path under the group-max
     stopping rule (the paper's per-system convergence), each group as one outer group and
     with its flyby ICs (two-body prediction within --flyby-hill Hill radii of a planet) in a
-    group of their own; time and mean sweeps per segment of the quiet ICs."""
+    group of their own; time and mean sweeps per segment of the quiet ICs, and, under the
+    per-IC rule on the fused path, the mean sweeps of the flyby and of the quiet ICs."""
     import torch
     S = max(g.segments for g in w.groups)
     ics = torch.tensor(w.ics, dtype=torch.float64, device="cuda")
@@ -658,14 +659,22 @@ def run_flyby(args, ctx, w, pcprop):
         res[hill] = {"ms": round(ms, 2), "status": int(r["status"]),
                      "mean_sweeps_per_segment_quiet": round(float(iters[quiet][iters[quiet] > 0].mean()), 3),
                      "mean_sweeps_per_segment_all": round(float(iters[iters > 0].mean()), 3)}
+    # the same ICs under the per-IC rule (fused path): do the flyby ICs need more sweeps?
+    it = torch.zeros((w.n_ic, S), dtype=torch.int32, device="cuda")
+    ctx.propagate_batched(ics, groups, model, iters_out=it)
+    iters = it.cpu().numpy()
+    per_ic = {"mean_sweeps_per_segment_quiet": round(float(iters[quiet][iters[quiet] > 0].mean()), 3),
+              "mean_sweeps_per_segment_flyby": round(float(iters[~quiet][iters[~quiet] > 0].mean()), 3)
+              if (~quiet).any() else None}
     out = {"workload": w.name, "path": "plain", "conv": "group", "hill_radii": args.flyby_hill,
-           "isolated_ics": int((~quiet).sum()), "n_ic": w.n_ic,
+           "isolated_ics": int((~quiet).sum()), "n_ic": w.n_ic, "per_ic_rule_fused": per_ic,
            "without_isolation": res[0.0], "with_isolation": res[args.flyby_hill],
            "speedup": round(res[0.0]["ms"] / res[args.flyby_hill]["ms"], 3)}
     print(f"bench: flyby isolation ({(~quiet).sum()} of {w.n_ic} ICs within {args.flyby_hill} Hill radii), group-max "
           f"plain path: {res[0.0]['ms']:.1f} -> {res[args.flyby_hill]['ms']:.1f} ms, quiet ICs' sweeps "
-          f"{res[0.0]['mean_sweeps_per_segment_quiet']} -> {res[args.flyby_hill]['mean_sweeps_per_segment_quiet']}",
-          flush=True)
+          f"{res[0.0]['mean_sweeps_per_segment_quiet']} -> {res[args.flyby_hill]['mean_sweeps_per_segment_quiet']}; "
+          f"per-IC rule: flyby ICs {per_ic['mean_sweeps_per_segment_flyby']} sweeps/segment, quiet "
+          f"{per_ic['mean_sweeps_per_segment_quiet']}", flush=True)
     return out
 
 

@@ -173,6 +173,46 @@ def test_node_counts_and_padding(pc, nodes):
     assert np.abs(r["iters"] - o["iters"]).max() <= 1
 
 
+def test_degenerate_and_ragged_batches(pc):
+    """Smallest and most ragged shapes in one call: a single IC at the minimum of three
+    nodes and one segment, a single IC at 256 nodes (seven idle columns of its 8-IC job),
+    one IC more than a 16-IC block at 16 nodes, and a two-IC group going backward."""
+    base = W.nbody_venus(21)
+    day = 1.0 / W.TU_DAYS
+    groups = [W.Group(0, 1, 0.0, 2.0 * day, 3, 1, 1e-12),
+              W.Group(1, 1, 0.0, 40.0 * day, 256, 1, 1e-12),
+              W.Group(2, 17, 0.0, 30.0 * day, 16, 3, 1e-12),
+              W.Group(19, 2, 10.0 * day, -20.0 * day, 64, 2, 1e-12)]
+    w = W.Workload("degenerate", base.ics, groups, base.pert)
+    r, _ = _run(pc, w)
+    o = oracle_run(w)
+    assert (r["iters"][:, 0] > 0).all() and r["status"] == 0
+    assert rel_err(r["states"], o["states"]).max() < TOL
+    assert np.abs(r["iters"] - o["iters"]).max() <= 1
+
+
+def test_empty_and_malformed_batches_are_refused(pc):
+    from paper_2301_03989_amd import pcprop
+    w = W.nbody_venus(8)
+    ics = torch.tensor(w.ics, dtype=torch.float64, device="cuda")
+    model = pcprop.Model(w.mu_sun, w.pert, w.epoch)
+    g = w.groups[0]
+    bad = [
+        [],                                                                        # no groups
+        [pcprop.Group(0, 0, g.t0, g.tf, g.nodes, g.segments, g.tol)],              # empty group
+        [pcprop.Group(0, 8, g.t0, g.tf, 257, g.segments, g.tol)],                  # too many nodes
+        [pcprop.Group(0, 8, g.t0, g.tf, 2, g.segments, g.tol)],                    # too few nodes
+        [pcprop.Group(4, 8, g.t0, g.tf, g.nodes, g.segments, g.tol)],              # past the ICs
+        [pcprop.Group(0, 8, g.t0, g.t0, g.nodes, g.segments, g.tol)],              # empty span
+        [pcprop.Group(0, 8, g.t0, g.tf, g.nodes, g.segments, 0.0)],                # no tolerance
+    ]
+    for groups in bad:
+        with pytest.raises((pcprop.PcError, ValueError)):
+            pc.propagate_batched(ics, groups, model)
+    with pytest.raises((pcprop.PcError, ValueError)):
+        pc.propagate_batched(ics[:0], [pcprop.Group(0, 1, g.t0, g.tf, g.nodes, g.segments, g.tol)], model)
+
+
 def test_tile_shapes_agree(pc):
     w = W.nbody_venus(40, nodes=128)
     a, _ = _run(pc, w, tile_pairs=2048)
