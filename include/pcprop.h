@@ -293,7 +293,8 @@ int pc_propagate_batched_noalloc(pc_ctx* ctx, const double* ics, int64_t n_ic,
  * the propagated gradient changes by less than adj_tol (relative).  Segments are taken
  * from the last: each is re-solved from its checkpoint with the forward code (or, when
  * fwd_nodes is given, its converged node states are read from there), then its gradient
- * seeds the end node of the previous one.  Fused FP64 path, nodes <= 128.
+ * seeds the end node of the previous one.  Fused FP64 path, point masses, any node count
+ * (3 .. 256).
  *   groups, model, opts  as in the forward pc_propagate_batched call
  *   ckpt        device [n_ic][ckpt_stride + 1][6] segment-boundary states of the forward call
  *               (its bounds_out); ckpt_stride >= every group's segment count

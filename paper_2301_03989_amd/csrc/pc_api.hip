@@ -1635,8 +1635,6 @@ int pc_adjoint(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int32_t n_grou
     Plan plan;
     rc = make_plan(ctx, n_ic, groups, n_groups, model, o, true, plan);
     if (rc != PC_OK) return rc;
-    for (const PcGroupDev& d : plan.groups)
-        if (d.NP > 128) return set_error(ctx, PC_EINVAL, "the adjoint supports up to 128 nodes per segment");
     if (ckpt_stride < plan.max_S) return set_error(ctx, PC_EINVAL, "ckpt_stride < segments");
     if ((gbar_nodes || fwd_nodes) && nodes_stride < plan.max_N)
         return set_error(ctx, PC_EINVAL, "nodes_stride < nodes");

@@ -1086,25 +1086,44 @@ static __device__ __forceinline__ void pc_product_adj(const double* sF, gconst_d
                                                       const PcLane& L)
 {
     using Sh = PcShape<PAIRS, NP>;
-    static_assert(Sh::WIDE, "the adjoint runs on WIDE job shapes");
     constexpr int T = Sh::T, ROW = Sh::ROW, NQ = Sh::NQ;
     const int lane = L.lane;
 #pragma unroll
     for (int b = 0; b < 6; ++b) acc[b] = f64x4{0.0, 0.0, 0.0, 0.0};
-    const double* bp[4];
+    if constexpr (Sh::WIDE) {
+        const double* bp[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-        bp[u] = sF + (lane >> 4) * ROW + L.grp * 16 + ((lane & 15) ^ ((4 * u + (lane >> 4)) & 15));
-    pc_kloop<NQ, 6, double, double, 3, 6, 1>(
-        [&](int q) { return kpT[q * 64]; }, [&](int q) { return kpT[q * 64]; },
-        [&](int q, int u, double (&bq)[6]) {
+        for (int u = 0; u < 4; ++u)
+            bp[u] = sF + (lane >> 4) * ROW + L.grp * 16 + ((lane & 15) ^ ((4 * u + (lane >> 4)) & 15));
+        pc_kloop<NQ, 6, double, double, 3, 6, 1>(
+            [&](int q) { return kpT[q * 64]; }, [&](int q) { return kpT[q * 64]; },
+            [&](int q, int u, double (&bq)[6]) {
 #pragma unroll
-            for (int b = 0; b < 6; ++b) bq[b] = bp[u][q * 4 * ROW + b * T];
-        },
-        [&](double ka, const double (&bq)[6]) {
+                for (int b = 0; b < 6; ++b) bq[b] = bp[u][q * 4 * ROW + b * T];
+            },
+            [&](double ka, const double (&bq)[6]) {
 #pragma unroll
-            for (int b = 0; b < 6; ++b) acc[b] = mfma16(bq[b], ka, acc[b]);
-        });
+                for (int b = 0; b < 6; ++b) acc[b] = mfma16(bq[b], ka, acc[b]);
+            });
+    } else {
+        // 8-IC jobs: the forward product's node-row form with the K_N^T strips of the
+        // wave's two row blocks; acc[3h + c] is column block c of strip h
+        gconst_dp kpT1 = kpT + (size_t)NQ * 64;
+        const double* bp = sF + (lane >> 4) * ROW + (lane & 15);
+        pc_kloop<NQ, 3, PcPairD, double>(
+            [&](int q) { return PcPairD{kpT[q * 64], kpT1[q * 64]}; },
+            [&](int q) { return PcPairD{kpT[q * 64], kpT1[q * 64]}; },
+            [&](int q, int, double (&bq)[3]) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) bq[c] = bp[q * 4 * ROW + 16 * c];
+            },
+            [&](const PcPairD& ka, const double (&bq)[3]) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) acc[c] = mfma16(ka.a0, bq[c], acc[c]);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) acc[3 + c] = mfma16(ka.a1, bq[c], acc[3 + c]);
+            });
+    }
 }
 
 // OR of the per-wave flags of IC m (written as Flag[wave][lane] by lanes < 16).

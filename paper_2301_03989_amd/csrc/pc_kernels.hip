@@ -952,7 +952,10 @@ int pc_launch_fused(const PcParams& p, const PcParams* p_dev, int pairs, int gri
 //   (J^T w)_r = w2 H w_v,   (J^T w)_v = w2 w_r.
 // Segments are processed from the last: each is first re-solved from its checkpoint (the
 // same forward code, so the same converged states), and its gradient seeds the end node of
-// the previous one.  Only WIDE job shapes (NP <= 128) run the adjoint.
+// the previous one.  WIDE job shapes hold one node of four ICs per lane; 8-IC jobs (256
+// nodes) hold the node-row layout of the forward product (a lane pair (l, l ^ 8) shares the
+// components of one IC), and their lanes exchange what the Hessian product and the
+// velocity rows need with their partner.
 template <int PAIRS, int NP>
 __device__ __attribute__((noinline)) void pc_adjoint_job(const PcAdjParams& a, const PcJobDev& job,
                                                          const PcGroupDev& g)
@@ -1002,17 +1005,29 @@ __device__ __attribute__((noinline)) void pc_adjoint_job(const PcAdjParams& a, c
                               (size_t)(g.rec_offset + (int64_t)s * N) * (P + 1);
         if (a.fwd_nodes) {
             if (rec_lds) pc_stage_records<PAIRS>(grec, N, P, sm);
-            const int j = pc_node(L, 0, 0);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int m = pc_ic(L, r);
-                if (j < N && m < n) {
-                    const double* y = a.fwd_nodes + (((size_t)(job.ic0 + m) * a.ckpt_stride + s) * a.nodes_stride + j) * 6;
+            for (int h = 0; h < Sh::H; ++h) {
 #pragma unroll
-                    for (int c = 0; c < 6; ++c) yc[c][r] = y[c];
-                } else {   // padding node or column: any finite state (its results are unused)
+                for (int r = 0; r < 4; ++r) {
+                    const int j = pc_node(L, h, r);
+                    const int m = pc_ic(L, r);
+                    double v[6];
+                    if (j < N && m < n) {
+                        const gconst_dp y = pc_gcd(a.fwd_nodes) +
+                                            (((size_t)(job.ic0 + m) * a.ckpt_stride + s) * a.nodes_stride + j) * 6;
 #pragma unroll
-                    for (int c = 0; c < 6; ++c) yc[c][r] = sY0[c * T + m];
+                        for (int c = 0; c < 6; ++c) v[c] = y[c];
+                    } else {   // padding node or column: any finite state (its results are unused)
+#pragma unroll
+                        for (int c = 0; c < 6; ++c) v[c] = sY0[c * T + m];
+                    }
+                    if constexpr (Sh::WIDE) {
+#pragma unroll
+                        for (int c = 0; c < 6; ++c) yc[c][r] = v[c];
+                    } else {
+#pragma unroll
+                        for (int cb = 0; cb < 3; ++cb) yc[3 * h + cb][r] = v[2 * cb + L.hi];
+                    }
                 }
             }
         } else {
@@ -1024,20 +1039,21 @@ __device__ __attribute__((noinline)) void pc_adjoint_job(const PcAdjParams& a, c
 
         // seed of this segment at the lane's nodes: the next segment's gradient at the end
         // node, plus the node seeds when given (recomputed where needed, not held)
+        // the Hessian's points: WIDE, the lane's node of its four ICs; 8-IC jobs, the four
+        // rows of strip hi (each lane of a pair takes one strip)
         int jr[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int j = pc_node(L, 0, r);
+            const int j = pc_node(L, Sh::WIDE ? 0 : L.hi, r);
             jr[r] = j < N ? j : N - 1;
         }
-        auto seed = [&](int c, int r) -> double {
-            const int j = pc_node(L, 0, r);
-            const int m = pc_ic(L, r);
+        auto seed_at = [&](int c, int j, int m) -> double {
             double v = (j == N - 1) ? sLam[c * T + m] : 0.0;
             if (a.gbar_nodes && m < n && j < N)
                 v += a.gbar_nodes[(((size_t)(job.ic0 + m) * a.ckpt_stride + s) * a.nodes_stride + j) * 6 + c];
             return v;
         };
+        auto seed = [&](int c, int r) -> double { return seed_at(c, pc_node(L, 0, r), pc_ic(L, r)); };
         for (int i = tid; i < 6 * PAIRS; i += NT) sF[i] = 0.0;
         if (tid < T) {
             sm.Active[tid] = (tid < n) && !sm.Dead[tid];
@@ -1046,11 +1062,23 @@ __device__ __attribute__((noinline)) void pc_adjoint_job(const PcAdjParams& a, c
         __syncthreads();
         // mu^(0) = gbar
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int j = pc_node(L, 0, r);
-            if (j < N) {
+        for (int h = 0; h < Sh::H; ++h) {
 #pragma unroll
-                for (int c = 0; c < 6; ++c) sF[j * ROW + c * T + pc_fcol<PAIRS, NP>(j, pc_ic(L, r))] = seed(c, r);
+            for (int r = 0; r < 4; ++r) {
+                const int j = pc_node(L, h, r);
+                const int m = pc_ic(L, r);
+                if (j < N) {
+                    if constexpr (Sh::WIDE) {
+#pragma unroll
+                        for (int c = 0; c < 6; ++c) sF[j * ROW + c * T + pc_fcol<PAIRS, NP>(j, m)] = seed_at(c, j, m);
+                    } else {
+#pragma unroll
+                        for (int cb = 0; cb < 3; ++cb) {
+                            const int c = 2 * cb + L.hi;
+                            sF[j * ROW + c * T + pc_fcol<PAIRS, NP>(j, m)] = seed_at(c, j, m);
+                        }
+                    }
+                }
             }
         }
         __syncthreads();
@@ -1059,38 +1087,104 @@ __device__ __attribute__((noinline)) void pc_adjoint_job(const PcAdjParams& a, c
         for (; it <= a.adj_max_iter; ++it) {
             f64x4 acc[6];
             pc_product_adj<PAIRS, NP>(sF, kpT, acc, L);          // w = K^T mu
-            double wx[4], wy[4], wz[4], hx[4], hy[4], hz[4];
+            double hx[4], hy[4], hz[4];
+            if constexpr (Sh::WIDE) {
+                double wx[4], wy[4], wz[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                wx[r] = acc[3][r];
-                wy[r] = acc[4][r];
-                wz[r] = acc[5][r];
-            }
-            if (rec_lds)
-                pc_hess_apply<4, true>(yc[0], yc[1], yc[2], wx, wy, wz, jr, P, p.mu_sun, sm.Rec, sm.Mu, grec,
-                                       hx, hy, hz);
-            else
-                pc_hess_apply<4, false>(yc[0], yc[1], yc[2], wx, wy, wz, jr, P, p.mu_sun, sm.Rec, sm.Mu, grec,
-                                        hx, hy, hz);
-            // mu_new = gbar + J^T w, and its sum over the strip's nodes (the 16 lanes of a
-            // row group hold one node each of the same four ICs)
-            const bool node_ok = pc_node(L, 0, 0) < N;
+                for (int r = 0; r < 4; ++r) {
+                    wx[r] = acc[3][r];
+                    wy[r] = acc[4][r];
+                    wz[r] = acc[5][r];
+                }
+                if (rec_lds)
+                    pc_hess_apply<4, true>(yc[0], yc[1], yc[2], wx, wy, wz, jr, P, p.mu_sun, sm.Rec, sm.Mu, grec,
+                                           hx, hy, hz);
+                else
+                    pc_hess_apply<4, false>(yc[0], yc[1], yc[2], wx, wy, wz, jr, P, p.mu_sun, sm.Rec, sm.Mu, grec,
+                                            hx, hy, hz);
+                // mu_new = gbar + J^T w, and its sum over the strip's nodes (the 16 lanes of a
+                // row group hold one node each of the same four ICs)
+                const bool node_ok = pc_node(L, 0, 0) < N;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const double nv0 = seed(3, r) + w2 * acc[0][r];
-                const double nv1 = seed(4, r) + w2 * acc[1][r];
-                const double nv2 = seed(5, r) + w2 * acc[2][r];
-                acc[0][r] = seed(0, r) + w2 * hx[r];
-                acc[1][r] = seed(1, r) + w2 * hy[r];
-                acc[2][r] = seed(2, r) + w2 * hz[r];
-                acc[3][r] = nv0;
-                acc[4][r] = nv1;
-                acc[5][r] = nv2;
+                for (int r = 0; r < 4; ++r) {
+                    const double nv0 = seed(3, r) + w2 * acc[0][r];
+                    const double nv1 = seed(4, r) + w2 * acc[1][r];
+                    const double nv2 = seed(5, r) + w2 * acc[2][r];
+                    acc[0][r] = seed(0, r) + w2 * hx[r];
+                    acc[1][r] = seed(1, r) + w2 * hy[r];
+                    acc[2][r] = seed(2, r) + w2 * hz[r];
+                    acc[3][r] = nv0;
+                    acc[4][r] = nv1;
+                    acc[5][r] = nv2;
 #pragma unroll
-                for (int c = 0; c < 6; ++c) {
-                    double part = node_ok ? acc[c][r] : 0.0;
-                    part = pc_row_sum16(part);
-                    if ((L.lane & 15) == 0) sLamPart[(L.wave * 6 + c) * 16 + (L.lane >> 4) + 4 * r] = part;
+                    for (int c = 0; c < 6; ++c) {
+                        double part = node_ok ? acc[c][r] : 0.0;
+                        part = pc_row_sum16(part);
+                        if ((L.lane & 15) == 0) sLamPart[(L.wave * 6 + c) * 16 + (L.lane >> 4) + 4 * r] = part;
+                    }
+                }
+            } else {
+                // node-row layout: element (3h + cb, r) is comp 2cb + hi of node j(h, r); the
+                // low lane of a pair holds comps 0, 2, 4, the high lane 1, 3, 5.  Each lane
+                // forms H w_v at the four points of strip hi (position and w_v = (w3, w4, w5),
+                // taking the three components it lacks from its partner)
+                const int hi = L.hi;
+                const int m = pc_ic(L, 0);
+                double xs[4], ys[4], zs[4], wxs[4], wys[4], wzs[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const double e1 = pc_dpp<0x128>(hi ? yc[0][r] : yc[3][r]);     // lo: y(0); hi: x(1)
+                    const double e2 = pc_dpp<0x128>(hi ? acc[1][r] : yc[4][r]);    // lo: w3(0); hi: z(1)
+                    const double e3 = pc_dpp<0x128>(hi ? acc[2][r] : acc[5][r]);   // lo: w5(0); hi: w4(1)
+                    xs[r] = hi ? e1 : yc[0][r];
+                    ys[r] = hi ? yc[3][r] : e1;
+                    zs[r] = hi ? e2 : yc[1][r];
+                    wxs[r] = hi ? acc[4][r] : e2;
+                    wys[r] = hi ? e3 : acc[2][r];
+                    wzs[r] = hi ? acc[5][r] : e3;
+                }
+                if (rec_lds)
+                    pc_hess_apply<4, true>(xs, ys, zs, wxs, wys, wzs, jr, P, p.mu_sun, sm.Rec, sm.Mu, grec, hx, hy,
+                                           hz);
+                else
+                    pc_hess_apply<4, false>(xs, ys, zs, wxs, wys, wzs, jr, P, p.mu_sun, sm.Rec, sm.Mu, grec, hx, hy,
+                                            hz);
+                // mu_new = gbar + J^T w: position rows (comp c < 3) take w2 (H w_v)_c of their
+                // point, from the lane that formed it; velocity rows (comp c >= 3) take
+                // w2 w_(c-3), which the partner lane holds
+                double part[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const double f1 = pc_dpp<0x128>(hi ? hx[r] : hy[r]);   // lo: hx(1); hi: hy(0)
+                    const double f2 = pc_dpp<0x128>(hz[r]);                // lo: hz(1)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const double g = pc_dpp<0x128>(acc[3 * h][r]);      // lo: w1(h); hi: w0(h)
+                        const double k = pc_dpp<0x128>(acc[3 * h + 1][r]);  // hi: w2(h)
+                        const int j = pc_node(L, h, r);
+                        const double hc0 = h == 0 ? (hi ? f1 : hx[r]) : (hi ? hy[r] : f1);   // comp hi
+                        const double hc2 = h == 0 ? hz[r] : f2;                              // comp 2 (lo)
+                        const double n0 = seed_at(hi, j, m) + w2 * hc0;
+                        const double n1 = seed_at(2 + hi, j, m) + w2 * (hi ? g : hc2);
+                        const double n2 = seed_at(4 + hi, j, m) + w2 * (hi ? k : g);
+                        acc[3 * h][r] = n0;
+                        acc[3 * h + 1][r] = n1;
+                        acc[3 * h + 2][r] = n2;
+                        if (j < N) {
+                            part[0] += n0;
+                            part[1] += n1;
+                            part[2] += n2;
+                        }
+                    }
+                }
+                // sum over the wave's 32 nodes: the four row groups of 16 lanes hold nodes
+                // l / 16 + 4 r of both strips
+#pragma unroll
+                for (int cb = 0; cb < 3; ++cb) {
+                    double v = part[cb];
+                    v += __shfl_xor(v, 16);
+                    v += __shfl_xor(v, 32);
+                    if (L.lane < 16) sLamPart[(L.wave * 6 + 2 * cb + hi) * 16 + m] = v;
                 }
             }
             int act[4];
@@ -1103,7 +1197,11 @@ __device__ __attribute__((noinline)) void pc_adjoint_job(const PcAdjParams& a, c
                 double ln[6], d2 = 0.0, n2 = 0.0;
                 for (int c = 0; c < 6; ++c) {
                     double v = 0.0;
-                    for (int w = tid >> 4; w < W; w += Sh::G16) v += sLamPart[(w * 6 + c) * 16 + (tid & 15)];
+                    if constexpr (Sh::WIDE) {
+                        for (int w = tid >> 4; w < W; w += Sh::G16) v += sLamPart[(w * 6 + c) * 16 + (tid & 15)];
+                    } else {
+                        for (int w = 0; w < W; ++w) v += sLamPart[(w * 6 + c) * 16 + tid];
+                    }
                     ln[c] = v;
                     const double d = v - sLamIt[c * T + tid];
                     d2 += d * d;
@@ -1121,13 +1219,30 @@ __device__ __attribute__((noinline)) void pc_adjoint_job(const PcAdjParams& a, c
                     if (tid < n && a.adj_iters) a.adj_iters[(size_t)ic * a.ckpt_stride + s] = rec;
                 }
             }
-            if (node_ok) {
-                const int j = pc_node(L, 0, 0);
+            if constexpr (Sh::WIDE) {
+                if (pc_node(L, 0, 0) < N) {
+                    const int j = pc_node(L, 0, 0);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    if (act[r]) {
+                    for (int r = 0; r < 4; ++r) {
+                        if (act[r]) {
 #pragma unroll
-                        for (int c = 0; c < 6; ++c) sF[j * ROW + c * T + pc_fcol<PAIRS, NP>(j, pc_ic(L, r))] = acc[c][r];
+                            for (int c = 0; c < 6; ++c)
+                                sF[j * ROW + c * T + pc_fcol<PAIRS, NP>(j, pc_ic(L, r))] = acc[c][r];
+                        }
+                    }
+                }
+            } else if (act[0]) {
+                const int m = pc_ic(L, 0);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int j = pc_node(L, h, r);
+                        if (j < N) {
+#pragma unroll
+                            for (int cb = 0; cb < 3; ++cb)
+                                sF[j * ROW + (2 * cb + L.hi) * T + pc_fcol<PAIRS, NP>(j, m)] = acc[3 * h + cb][r];
+                        }
                     }
                 }
             }
@@ -1169,6 +1284,7 @@ __global__ __launch_bounds__(PAIRS / 4) void pc_adjoint_kernel(const PcAdjParams
         case 32: pc_adjoint_job<PAIRS, 32>(a, job, g); break;
         case 64: pc_adjoint_job<PAIRS, 64>(a, job, g); break;
         case 128: pc_adjoint_job<PAIRS, 128>(a, job, g); break;
+        case 256: pc_adjoint_job<PAIRS, 256>(a, job, g); break;
         default: break;
         }
     }

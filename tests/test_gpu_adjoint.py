@@ -206,11 +206,13 @@ def test_adjoint_full_size_sampled(pc):
 
 def test_adjoint_argument_errors(pc):
     from paper_2301_03989_amd import pcprop
-    w = W.nbody_venus(4, nodes=256, days=30.0, segments=1)
+    w = W.nbody_venus(4, nodes=64, days=30.0, segments=1)
     ics, groups, model, om, g = _setup(w)
     fwd = pc.propagate_batched(ics, groups, model, want_bounds=True)
+    # the adjoint is written for the point-mass model
+    eih = pcprop.Model(w.mu_sun, w.pert, w.epoch, 1e-8)
     with pytest.raises(pcprop.PcError):
-        pc.adjoint(fwd["bounds"], torch.zeros((4, 6), dtype=torch.float64, device="cuda"), groups, model)
+        pc.adjoint(fwd["bounds"], torch.zeros((4, 6), dtype=torch.float64, device="cuda"), groups, eih)
     # the adjoint linearises the map converged per IC: the group-max rule is refused
     w = W.nbody_venus(4, days=30.0, segments=1)
     ics, groups, model, om, g = _setup(w)
@@ -221,9 +223,10 @@ def test_adjoint_argument_errors(pc):
     assert e.value.code == pcprop.PC_EINVAL
 
 
-@pytest.mark.parametrize("nodes", [12, 24, 100])
+@pytest.mark.parametrize("nodes", [12, 24, 100, 200, 256])
 def test_adjoint_every_job_shape(pc, nodes):
-    """16 to 128 ICs per job (NP = 16, 32, 128) with a ragged IC count."""
+    """16 to 128 ICs per job (NP = 16, 32, 128) and the 8-IC node-row jobs (NP = 256), with a
+    ragged IC count."""
     w = W.nbody_venus(41, seed=109, days=40.0, segments=2, nodes=nodes, tol=1e-13)
     ics, groups, model, om, g = _setup(w)
     fwd = pc.propagate_batched(ics, groups, model, want_bounds=True)
@@ -258,10 +261,10 @@ def test_adjoint_mixed_groups_and_backward(pc):
 
 @pytest.mark.parametrize("seed", range(12))
 def test_adjoint_random_configuration(pc, seed):
-    """Seeded random adjoint cases against the oracle: node counts 3..128, 1-3 segments,
+    """Seeded random adjoint cases against the oracle: node counts 3..256, 1-3 segments,
     forward or backward spans, final-state and node seeds, checkpoints or stored nodes."""
     rng = np.random.default_rng(700 + seed)
-    N = int(rng.integers(3, 129))
+    N = int(rng.integers(3, 257))
     S = int(rng.integers(1, 4))
     n = int(rng.integers(2, 7))
     w = W.nbody_venus(n, seed=800 + seed, days=float(rng.uniform(15.0, 40.0)) * S, segments=S, nodes=N,
@@ -286,3 +289,27 @@ def test_adjoint_random_configuration(pc, seed):
     assert st == 0
     ref = oracle.adjoint(w.ics, g.t0, g.tf, g.nodes, g.segments, g.tol, om, gbar, gn)
     assert _gerr(grad.cpu().numpy(), ref).max() < GTOL
+
+
+def test_adjoint_node_row_jobs_stored_nodes_and_node_seeds(pc):
+    """256-node jobs (node-row layout, lane pairs exchanging components) from the forward's
+    stored node states, with seeds on interior nodes of both strips of a wave and on the
+    last node, three segments, against the oracle; the re-solve gives the same gradient."""
+    w = W.nbody_venus(13, seed=111, days=90.0, segments=3, nodes=256, tol=1e-13)
+    ics, groups, model, om, g = _setup(w)
+    fwd = pc.propagate_batched(ics, groups, model, want_bounds=True, want_nodes=True)
+    assert fwd["status"] == 0
+    rng = np.random.default_rng(17)
+    gbar = rng.standard_normal((w.n_ic, 6))
+    gn = np.zeros((w.n_ic, 3, 256, 6))
+    for j in (5, 21, 130, 255):
+        gn[:, rng.integers(0, 3), j] = rng.standard_normal((w.n_ic, 6))
+    gnt = torch.tensor(gn, device="cuda")
+    a, it_a, st_a = pc.adjoint(fwd["bounds"], torch.tensor(gbar, device="cuda"), groups, model,
+                               gbar_nodes=gnt, fwd_nodes=fwd["nodes"])
+    b, it_b, st_b = pc.adjoint(fwd["bounds"], torch.tensor(gbar, device="cuda"), groups, model, gbar_nodes=gnt)
+    assert st_a == 0 and st_b == 0
+    ref = oracle.adjoint(w.ics, g.t0, g.tf, g.nodes, g.segments, g.tol, om, gbar, gn)
+    assert _gerr(a.cpu().numpy(), ref).max() < GTOL
+    assert _gerr(b.cpu().numpy(), ref).max() < GTOL
+    assert _gerr(a.cpu().numpy(), b.cpu().numpy()).max() < 1e-12
