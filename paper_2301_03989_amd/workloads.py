@@ -229,10 +229,11 @@ def mixed_precision(n_ic: int = 262144, seed: int = 104) -> Workload:
     return nbody_venus(n_ic, seed, precision=1, name="nbody-venus-262144-fp32-fp64")
 
 
-def adjoint_ensemble(n_ic: int = 16384, seed: int = 105) -> Workload:
-    """The N-body Venus ensemble at 16384 ICs over 256 days in 5 segments, tol 1e-13."""
-    return nbody_venus(n_ic, seed, days=256.0, segments=5, tol=1e-13,
-                       name="nbody-venus-16384-256d")
+def adjoint_ensemble(n_ic: int = 16384, seed: int = 105, nodes: int = 128) -> Workload:
+    """The N-body Venus ensemble at 16384 ICs over 256 days in 5 segments, tol 1e-13
+    (128 nodes; the 256-node variant runs the adjoint's node-row jobs)."""
+    return nbody_venus(n_ic, seed, days=256.0, segments=5, tol=1e-13, nodes=nodes,
+                       name="nbody-venus-16384-256d" + ("" if nodes == 128 else f"-n{nodes}"))
 
 
 # speed of light in AU per time unit (299792.458 km/s, 1 AU = 149597870.7 km)
@@ -253,6 +254,7 @@ WORKLOADS = {
     "uneven-batch-65536": uneven_batch,
     "nbody-venus-262144-fp32-fp64": mixed_precision,
     "nbody-venus-16384-256d": adjoint_ensemble,
+    "nbody-venus-16384-256d-n256": lambda: adjoint_ensemble(nodes=256),
     "nbody-venus-4096-eih": relativistic,
     "eccentric-16384-n64": lambda: eccentric(64),
     "eccentric-16384-n128": lambda: eccentric(128),
