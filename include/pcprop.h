@@ -157,8 +157,9 @@ typedef struct {
                              sweeps at the same product cost per sweep).  Its fixed point is a
                              different discretisation of the same ODE (the position series
                              has degree N).  Order 2 runs on the fused FP64 path with the
-                             per-IC rule and the point-mass model, for node counts up to 128;
-                             other calls with order 2 return PC_EINVAL. */
+                             per-IC rule and the point-mass model, for every node count (3 to
+                             256; the feedback up to 128); other calls with order 2 return
+                             PC_EINVAL. */
     int32_t feedback;     /* order 2: 1 = integral error feedback, the development Sec. 1 cites
                              with the adaptive variant of the method.  The sweep's accelerations
                              were taken at the previous position iterate; the change dx the

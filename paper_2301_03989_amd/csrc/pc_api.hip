@@ -484,10 +484,15 @@ int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, c
     plan.plain = (o.path == PC_PATH_PLAIN);
     if (plan.plain) plan.pairs = 2048;
     if (o.order == 2) {
-        // second-order sweeps need blocks of 16 or more ICs (the transposed product)
+        // second-order sweeps need blocks of 16 or more ICs (the transposed product) up to
+        // 128 nodes; 256-node groups run 8-IC node-row jobs (without the feedback)
         for (int gi = 0; gi < n_groups; ++gi) {
             const int np = padded_nodes(std::max(3, std::min((int)groups[gi].nodes, PC_MAX_NODES)));
-            if (np > 128) return set_error(ctx, PC_EINVAL, "order 2 runs with up to 128 nodes per segment");
+            if (np > 128) {
+                if (o.feedback)
+                    return set_error(ctx, PC_EINVAL, "the integral error feedback runs with up to 128 nodes");
+                continue;
+            }
             if (plan.pairs / np < 16) {
                 if (o.tile_pairs == 1024) return set_error(ctx, PC_EINVAL, "order 2 with %d nodes needs tile_pairs 2048", groups[gi].nodes);
                 plan.pairs = 2048;

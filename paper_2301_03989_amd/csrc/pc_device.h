@@ -764,6 +764,54 @@ static __device__ __forceinline__ int pc_product_incr(const float* sD, gconst_fp
 // bit 0 = some node not converged, bit 1 = non-finite, bit 2 = some node changed by more
 // than sqrt(sw2) (relative).  WIDE blocks are computed as (K_N F)^T = F^T K_N^T: the F
 // slice is the A operand and the K_N fragment the B operand.  SW: evaluate bit 2.
+// Epilogue of an 8-IC job's product (node-row layout: element (3h + cb, r) is comp 2cb + hi
+// of node pc_node(L, h, r) of IC l % 8): y_new = y0 + w2 acc, the position and velocity
+// change norms summed over the lane pair (l, l ^ 8) that shares the IC's components, and
+// the stopping-rule flags OR-ed over the lane's nodes and its partner's.  The caller ORs
+// the four row groups.
+template <int PAIRS, int NP, bool SW>
+static __device__ __forceinline__ int pc_row_epilogue(const double* sY0, const double (&yc)[6][4],
+                                                      f64x4 (&acc)[6], double w2, const PcTol& tl, int N,
+                                                      const PcLane& L)
+{
+    constexpr int T = PcShape<PAIRS, NP>::T;
+    const int hi = L.hi;
+    const int my_m = pc_ic(L, 0);
+    int flag = 0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = pc_node(L, h, r);
+            double dd[3], yy[3];
+#pragma unroll
+            for (int cb = 0; cb < 3; ++cb) {
+                const double yn = sY0[(2 * cb + hi) * T + my_m] + w2 * acc[3 * h + cb][r];
+                acc[3 * h + cb][r] = yn;
+                const double d = yn - yc[3 * h + cb][r];
+                dd[cb] = d * d;
+                yy[cb] = yn * yn;
+            }
+            double pd = dd[0] + (hi ? 0.0 : dd[1]);
+            double py = yy[0] + (hi ? 0.0 : yy[1]);
+            double vd = (hi ? dd[1] : 0.0) + dd[2];
+            double vy = (hi ? yy[1] : 0.0) + yy[2];
+            pd += pc_dpp<0x128>(pd);   // lane ^ 8
+            py += pc_dpp<0x128>(py);
+            vd += pc_dpp<0x128>(vd);
+            vy += pc_dpp<0x128>(vy);
+            if (j < N) {
+                const bool ok = pd < fma(tl.ta, py, tl.tb) && vd < fma(tl.ta, vy, tl.tb);
+                const bool lo = !SW || (pd < fma(tl.sa, py, tl.sb) && vd < fma(tl.sa, vy, tl.sb));
+                const bool nf = !isfinite(py + vy);
+                flag |= (ok ? 0 : 1) | (nf ? 2 : 0) | (lo ? 0 : 4);
+            }
+        }
+    }
+    flag |= pc_dpp<0x128>(flag);
+    return flag;
+}
+
 template <int PAIRS, int NP, bool FP32 = false, bool SW = true>
 static __device__ __forceinline__ int pc_product(const double* sF, const double* sY0, gconst_dp kp0,
                                                   const double (&kpre)[8], gconst_fp kp0f,
@@ -773,7 +821,7 @@ static __device__ __forceinline__ int pc_product(const double* sF, const double*
 {
     using Sh = PcShape<PAIRS, NP>;
     constexpr int T = Sh::T, ROW = Sh::ROW, NQ = Sh::NQ;
-    const int lane = L.lane, hi = L.hi;
+    const int lane = L.lane;
 #pragma unroll
     for (int b = 0; b < 6; ++b) acc[b] = f64x4{0.0, 0.0, 0.0, 0.0};
     int flag = 0;
@@ -862,89 +910,116 @@ static __device__ __forceinline__ int pc_product(const double* sF, const double*
                     for (int c = 0; c < 3; ++c) acc[3 + c] = mfma16(ka.a1, bq[c], acc[3 + c]);
                 });
         }
-        const int my_m = pc_ic(L, 0);
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int j = pc_node(L, h, r);
-                double dd[3], yy[3];
-#pragma unroll
-                for (int cb = 0; cb < 3; ++cb) {
-                    const double yn = sY0[(2 * cb + hi) * T + my_m] + w2 * acc[3 * h + cb][r];
-                    acc[3 * h + cb][r] = yn;
-                    const double d = yn - yc[3 * h + cb][r];
-                    dd[cb] = d * d;
-                    yy[cb] = yn * yn;
-                }
-                double pd = dd[0] + (hi ? 0.0 : dd[1]);
-                double py = yy[0] + (hi ? 0.0 : yy[1]);
-                double vd = (hi ? dd[1] : 0.0) + dd[2];
-                double vy = (hi ? yy[1] : 0.0) + yy[2];
-                pd += pc_dpp<0x128>(pd);   // lane ^ 8
-                py += pc_dpp<0x128>(py);
-                vd += pc_dpp<0x128>(vd);
-                vy += pc_dpp<0x128>(vy);
-                if (j < N) {
-                    const bool ok = pd < fma(tl.ta, py, tl.tb) && vd < fma(tl.ta, vy, tl.tb);
-                    const bool lo = !SW || (pd < fma(tl.sa, py, tl.sb) && vd < fma(tl.sa, vy, tl.sb));
-                    const bool nf = !isfinite(py + vy);
-                    flag |= (ok ? 0 : 1) | (nf ? 2 : 0) | (lo ? 0 : 4);
-                }
-            }
-        }
-        flag |= pc_dpp<0x128>(flag);
+        flag = pc_row_epilogue<PAIRS, NP, SW>(sY0, yc, acc, w2, tl, N, L);
     }
     flag |= __shfl_xor(flag, 16);
     flag |= __shfl_xor(flag, 32);
     return flag;
 }
 
-// Second-order sweep (WIDE shapes): the velocity and the position both come from the
-// acceleration columns of F (comps 3..5), v_new = v0 + w2 K_N a and
+struct PcQuadD {
+    double k0, k1, q0, q1;   // K_N and K2_N fragments of the wave's two strips
+};
+
+// Second-order sweep: the velocity and the position both come from the acceleration
+// columns of F (comps 3..5), v_new = v0 + w2 K_N a and
 // x_new = x0 + w2 v0 (tau_j + 1) + w2^2 K2_N a, with K2_N the double-integration operator
-// (the degree N-2 fit integrated twice, zero value and slope at tau = -1).  Per k step a
-// lane loads the two operators' fragments (kp1: K_N, kp2: K2_N) and three F values, and
-// issues six MFMAs, as the first-order product does.  tp1 = tau_j + 1 of the lane's node.
-// Flags as pc_product.
+// (the degree N-2 fit integrated twice, zero value and slope at tau = -1).
+// WIDE shapes: per k step a lane loads the two operators' fragments (kp1: K_N, kp2: K2_N)
+// and three F values, and issues six MFMAs, as the first-order product does.
+// 8-IC jobs (node-row layout, a column block holding comps 2cb and 2cb + 1 of the 8 ICs):
+// block 0 (x, y) is K2_N times (a_x, a_y) and block 2 (v_y, v_z) K_N times (a_y, a_z), but
+// block 1 (z, v_x) needs K2_N for its low half and K_N for its high half, so it takes two
+// MFMAs whose B operands are zero in the other half (read from F's velocity columns, which
+// second-order sweeps leave at zero): four MFMAs per strip and k step against three.
+// tp = tau_j + 1 of the lane's nodes (WIDE: tp[0]; 8-IC jobs: tp[4h + r]).  Flags as
+// pc_product.
 template <int PAIRS, int NP>
 static __device__ __forceinline__ int pc_product2(const double* sF, const double* sY0, gconst_dp kp1,
                                                    gconst_dp kp2, const double (&kpre)[8],
                                                    const double (&yc)[6][4], f64x4 (&acc)[6], double w2,
-                                                   double tp1, const PcTol& tl, int N, const PcLane& L)
+                                                   const double (&tp)[8], const PcTol& tl, int N, const PcLane& L)
 {
     using Sh = PcShape<PAIRS, NP>;
-    static_assert(Sh::WIDE, "second-order sweeps run on WIDE job shapes");
     constexpr int T = Sh::T, ROW = Sh::ROW, NQ = Sh::NQ;
     const int lane = L.lane;
 #pragma unroll
     for (int b = 0; b < 6; ++b) acc[b] = f64x4{0.0, 0.0, 0.0, 0.0};
-    const double* bp[4];
+    if constexpr (!Sh::WIDE) {
+        const int hi = L.hi, m = lane & 7;
+        // per-lane F columns of the four B operands (comp * T + IC; comp 0 is zero)
+        const double* row = sF + (lane >> 4) * ROW;
+        const double* b0 = row + (hi ? 4 : 3) * T + m;   // a_x | a_y
+        const double* b1 = row + (hi ? 0 : 5) * T + m;   // a_z | 0
+        const double* b2 = row + (hi ? 3 : 0) * T + m;   // 0   | a_x
+        const double* b3 = row + (hi ? 5 : 4) * T + m;   // a_y | a_z
+        gconst_dp kp1b = kp1 + (size_t)NQ * 64, kp2b = kp2 + (size_t)NQ * 64;
+        pc_kloop<NQ, 4, PcQuadD, double>(
+            [&](int q) { return PcQuadD{kp1[q * 64], kp1b[q * 64], kp2[q * 64], kp2b[q * 64]}; },
+            [&](int q) { return PcQuadD{kp1[q * 64], kp1b[q * 64], kp2[q * 64], kp2b[q * 64]}; },
+            [&](int q, int, double (&bq)[4]) {
+                const int o = q * 4 * ROW;
+                bq[0] = b0[o];
+                bq[1] = b1[o];
+                bq[2] = b2[o];
+                bq[3] = b3[o];
+            },
+            [&](const PcQuadD& ka, const double (&bq)[4]) {
+                // the two MFMAs into block 1 of a strip are five MFMAs apart
+                acc[0] = mfma16(ka.q0, bq[0], acc[0]);
+                acc[1] = mfma16(ka.q0, bq[1], acc[1]);
+                acc[2] = mfma16(ka.k0, bq[3], acc[2]);
+                acc[3] = mfma16(ka.q1, bq[0], acc[3]);
+                acc[4] = mfma16(ka.q1, bq[1], acc[4]);
+                acc[5] = mfma16(ka.k1, bq[3], acc[5]);
+                acc[1] = mfma16(ka.k0, bq[2], acc[1]);
+                acc[4] = mfma16(ka.k1, bq[2], acc[4]);
+            });
+        // position elements (block 0, and block 1 in the low lane): w2 acc + v0 (tau + 1),
+        // so the common epilogue's y0 + w2 acc gives x0 + w2 v0 (tau + 1) + w2^2 K2_N a
+        const double v0a = sY0[(3 + hi) * T + m], v0z = sY0[5 * T + m];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-        bp[u] = sF + (lane >> 4) * ROW + L.grp * 16 + ((lane & 15) ^ ((4 * u + (lane >> 4)) & 15));
-    pc_kloop<NQ, 3, PcPairD, double, 3, 6, 2>(
-        [&](int u) { return PcPairD{kpre[u], kpre[4 + u]}; },
-        [&](int q) { return PcPairD{kp1[q * 64], kp2[q * 64]}; },
-        [&](int q, int u, double (&bq)[3]) {
+        for (int h = 0; h < 2; ++h) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) bq[c] = bp[u][q * 4 * ROW + (3 + c) * T];
-        },
-        [&](const PcPairD& ka, const double (&bq)[3]) {
+            for (int r = 0; r < 4; ++r) {
+                const double t = tp[4 * h + r];
+                acc[3 * h][r] = fma(w2, acc[3 * h][r], t * v0a);
+                acc[3 * h + 1][r] = hi ? acc[3 * h + 1][r] : fma(w2, acc[3 * h + 1][r], t * v0z);
+            }
+        }
+        int flag = pc_row_epilogue<PAIRS, NP, false>(sY0, yc, acc, w2, tl, N, L);
+        flag |= __shfl_xor(flag, 16);
+        flag |= __shfl_xor(flag, 32);
+        return flag;
+    } else {
+        const double tp1 = tp[0];
+        const double* bp[4];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) acc[c] = mfma16(bq[c], ka.a1, acc[c]);
+        for (int u = 0; u < 4; ++u)
+            bp[u] = sF + (lane >> 4) * ROW + L.grp * 16 + ((lane & 15) ^ ((4 * u + (lane >> 4)) & 15));
+        pc_kloop<NQ, 3, PcPairD, double, 3, 6, 2>(
+            [&](int u) { return PcPairD{kpre[u], kpre[4 + u]}; },
+            [&](int q) { return PcPairD{kp1[q * 64], kp2[q * 64]}; },
+            [&](int q, int u, double (&bq)[3]) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) acc[3 + c] = mfma16(bq[c], ka.a0, acc[3 + c]);
-        });
-    // position: x0 + w2 v0 (tau + 1) + w2^2 acc; the common epilogue adds w2 * acc to
-    // its base, so the position blocks become w2 acc + v0 (tau + 1) first
+                for (int c = 0; c < 3; ++c) bq[c] = bp[u][q * 4 * ROW + (3 + c) * T];
+            },
+            [&](const PcPairD& ka, const double (&bq)[3]) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int m = pc_ic(L, r);
+                for (int c = 0; c < 3; ++c) acc[c] = mfma16(bq[c], ka.a1, acc[c]);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) acc[c][r] = fma(w2, acc[c][r], tp1 * sY0[(3 + c) * T + m]);
+                for (int c = 0; c < 3; ++c) acc[3 + c] = mfma16(bq[c], ka.a0, acc[3 + c]);
+            });
+        // position: x0 + w2 v0 (tau + 1) + w2^2 acc; the common epilogue adds w2 * acc to
+        // its base, so the position blocks become w2 acc + v0 (tau + 1) first
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int m = pc_ic(L, r);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[c][r] = fma(w2, acc[c][r], tp1 * sY0[(3 + c) * T + m]);
+        }
+        return pc_wide_epilogue<PAIRS, NP, false, false>(sY0, yc, acc, w2, tl, N, L);
     }
-    return pc_wide_epilogue<PAIRS, NP, false, false>(sY0, yc, acc, w2, tl, N, L);
 }
 
 // Linear change of the point-mass acceleration over a position change, at R points of
@@ -1143,7 +1218,9 @@ static __device__ __forceinline__ int pc_gather_flags(const int* sFlag, int m)
 // Dynamics of the lane's (node, IC) pairs from its registers, published with the
 // velocities as the force matrix F = (v, a) of Sec. 2.2 into sF[node][comp'][IC].
 // sRec/sMu: the segment's records in LDS (when rec_lds), grec: the same in global memory.
-template <int PAIRS, int NP, bool FP32 = false>
+// VEL = false (second-order sweeps, which read the accelerations only): the velocity
+// columns are left as they are.
+template <int PAIRS, int NP, bool FP32 = false, bool VEL = true>
 static __device__ __forceinline__ void pc_publish(double* sF, const double (&yc)[6][4], const PcLane& L,
                                                   int N, int P, double mu_sun, bool rec_lds,
                                                   const double* sRec, const double* sMu, const double4* grec)
@@ -1164,9 +1241,11 @@ static __device__ __forceinline__ void pc_publish(double* sF, const double (&yc)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 double* f = sF + j * ROW + pc_fcol<PAIRS, NP>(j, pc_ic(L, r));
-                f[0 * T] = yc[3][r];
-                f[1 * T] = yc[4][r];
-                f[2 * T] = yc[5][r];
+                if constexpr (VEL) {
+                    f[0 * T] = yc[3][r];
+                    f[1 * T] = yc[4][r];
+                    f[2 * T] = yc[5][r];
+                }
                 f[3 * T] = ax[r];
                 f[4 * T] = ay[r];
                 f[5 * T] = az[r];
@@ -1203,18 +1282,20 @@ static __device__ __forceinline__ void pc_publish(double* sF, const double (&yc)
                 f[5 * T] = az[r];
             }
         }
+        if constexpr (VEL) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+            for (int h = 0; h < 2; ++h) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int j = pc_node(L, h, r);
-                if (j < N) {
-                    double* f = sF + j * ROW + my_m;
-                    if (hi) {
-                        f[0 * T] = yc[3 * h + 1][r];   // vx (comp 3)
-                        f[2 * T] = yc[3 * h + 2][r];   // vz (comp 5)
-                    } else {
-                        f[1 * T] = yc[3 * h + 2][r];   // vy (comp 4)
+                for (int r = 0; r < 4; ++r) {
+                    const int j = pc_node(L, h, r);
+                    if (j < N) {
+                        double* f = sF + j * ROW + my_m;
+                        if (hi) {
+                            f[0 * T] = yc[3 * h + 1][r];   // vx (comp 3)
+                            f[2 * T] = yc[3 * h + 2][r];   // vz (comp 5)
+                        } else {
+                            f[1 * T] = yc[3 * h + 2][r];   // vy (comp 4)
+                        }
                     }
                 }
             }

@@ -310,7 +310,7 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
     if (act[0] | act[1] | act[2] | act[3]) {
         if constexpr (EIH) pc_publish_eih<PAIRS, NP>(sF, yc, L, N, P, erec, p.inv_c2);
         else if (MIXED && mode == 1) pc_publish<PAIRS, NP, MIXED>(sF, yc, L, N, P, mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
-        else pc_publish<PAIRS, NP>(sF, yc, L, N, P, mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
+        else pc_publish<PAIRS, NP, false, SO == 0>(sF, yc, L, N, P, mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
     }
     __syncthreads();
 
@@ -322,12 +322,20 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
     // second-order sweeps: the K2_N strip and its first fragments next to K_N's, and the
     // lane's node offset tau_j + 1 for the x0 + w2 v0 (tau_j + 1) term
     gconst_dp kp2 = nullptr;
-    double tp1 = 0.0;
+    double tp[8] = {};
     if constexpr (SO) {
         kp2 = (gconst_dp)g.kfrag2 + (size_t)L.strip0 * NQ * 64 + L.lane;
+        if constexpr (Sh::WIDE) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) kpre[4 + u] = kp2[u * 64];
-        tp1 = pc_gcd(g.tau)[pc_node(L, 0, 0)] + 1.0;
+            for (int u = 0; u < 4; ++u) kpre[4 + u] = kp2[u * 64];
+            tp[0] = pc_gcd(g.tau)[pc_node(L, 0, 0)] + 1.0;
+        } else {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) tp[4 * h + r] = pc_gcd(g.tau)[pc_node(L, h, r)] + 1.0;
+            }
+        }
     }
     for (int it = 1; it <= n_it; ++it) {
         // (1)-(2) product and stopping-rule flags
@@ -342,10 +350,10 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
             flag = mode == 1 ? pc_product<PAIRS, NP, true>(sF, sY0, kp0, kpre, kp0f, yc, acc, w2, tl, N, L)
                              : pc_product<PAIRS, NP, false>(sF, sY0, kp0, kpre, kp0f, yc, acc, w2, tl, N, L);
         } else if constexpr (SO == 2) {
-            flag = pc_product2_fb<PAIRS, NP>(sF, sY0, kp0, kp2, kpre, yc, acc, w2, tp1, tl, N, L, P, mu_sun,
+            flag = pc_product2_fb<PAIRS, NP>(sF, sY0, kp0, kp2, kpre, yc, acc, w2, tp[0], tl, N, L, P, mu_sun,
                                              rec_lds, sm.Rec, sm.Mu, grec);
         } else if constexpr (SO) {
-            flag = pc_product2<PAIRS, NP>(sF, sY0, kp0, kp2, kpre, yc, acc, w2, tp1, tl, N, L);
+            flag = pc_product2<PAIRS, NP>(sF, sY0, kp0, kp2, kpre, yc, acc, w2, tp, tl, N, L);
         } else {
             flag = pc_product<PAIRS, NP, false, false>(sF, sY0, kp0, kpre, kp0f, yc, acc, w2, tl, N, L);
         }
@@ -443,7 +451,7 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
                 if constexpr (EIH) pc_publish_eih<PAIRS, NP>(sF, yc, L, N, P, erec, p.inv_c2);
                 else if (MIXED && next_mode == 1)
                     pc_publish<PAIRS, NP, MIXED>(sF, yc, L, N, P, mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
-                else pc_publish<PAIRS, NP>(sF, yc, L, N, P, mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
+                else pc_publish<PAIRS, NP, false, SO == 0>(sF, yc, L, N, P, mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
             }
         }
         fp32 = next32;
@@ -906,6 +914,10 @@ __global__ __launch_bounds__(PAIRS / 4, 2) void pc_fused_kernel(const PcParams* 
             break;
         case 256:
             if constexpr (PAIRS >= 2048) {
+                if (order2) {   // node-row second-order sweeps (no feedback at 256 nodes)
+                    pc_job<PAIRS, 256, false, false, 1>(p, job, g);
+                    break;
+                }
                 if (eih && mixed) pc_job<PAIRS, 256, true, true>(p, job, g);
                 else if (eih) pc_job<PAIRS, 256, false, true>(p, job, g);
                 else if (list) pc_job_list<PAIRS, 256>(p, job, g);

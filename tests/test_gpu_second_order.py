@@ -54,7 +54,7 @@ def _oracle(w, **kw):
 
 
 @pytest.mark.parametrize("nodes,tile", [(16, 2048), (33, 2048), (64, 2048), (100, 2048), (128, 2048),
-                                        (16, 1024), (48, 1024), (64, 1024)])
+                                        (16, 1024), (48, 1024), (64, 1024), (200, 2048), (256, 2048)])
 def test_second_order_matches_oracle(pc, nodes, tile):
     w = W.nbody_venus(37, seed=nodes + tile, days=112.5, segments=2, nodes=nodes)
     r = _gpu(pc, w, tile_pairs=tile)
@@ -81,11 +81,8 @@ def test_backward_cold_start_and_groups(pc):
     st, it, bd = _oracle(w)
     assert r["status"] == 0 and boundary_err(r["bounds"], bd).max() <= TOL
     assert np.abs(r["iters"] - it).max() <= 1
-    # groups of 64 and 128 nodes of the eccentric batch in one call
+    # groups of 64, 128 and 256 nodes of the eccentric batch in one call
     wu = W.uneven_batch(600, seed=11)
-    wu.groups = [g for g in wu.groups if g.nodes <= 128]
-    keep = np.concatenate([np.arange(g.ic_offset, g.ic_offset + g.n_ic) for g in wu.groups])
-    wu = wu.subset(keep)
     for g in wu.groups:
         g.segments = 1 + g.segments // 16
         g.tf = g.segments * np.pi / 4.0
@@ -156,7 +153,7 @@ def test_second_order_refusals(pc):
     g = w.groups[0]
     ics = torch.tensor(w.ics, device="cuda")
     model = pcprop.Model(1.0, w.pert, 0.0)
-    bad = [dict(groups=[pcprop.Group(0, 16, g.t0, g.tf, 200, 1, g.tol)], kw={}),          # 256 padded nodes
+    bad = [dict(groups=[pcprop.Group(0, 16, g.t0, g.tf, 200, 1, g.tol)], kw=dict(feedback=1)),   # feedback at 256
            dict(groups=None, kw=dict(precision="fp32-fp64")),
            dict(groups=None, kw=dict(path="plain")),
            dict(groups=None, kw=dict(tile_pairs=1024, **{}), nodes=128)]
@@ -172,3 +169,26 @@ def test_second_order_refusals(pc):
     with pytest.raises(pcprop.PcError) as e:   # feedback belongs to the second-order form
         pc.propagate_batched(ics, [pcprop.Group(0, 16, g.t0, g.tf, g.nodes, 1, g.tol)], model, feedback=1)
     assert e.value.code == pcprop.PC_EINVAL
+
+
+def test_node_row_second_order_fixed_sweeps_backward_and_nodes(pc):
+    """256-node jobs (8 ICs, node-row layout, two MFMAs into the mixed column block) with a
+    ragged IC count: fixed sweeps to rounding, backward and cold start, and the node states
+    against the oracle's."""
+    w = W.nbody_venus(19, seed=12, days=112.5, segments=2, nodes=256)
+    r = _gpu(pc, w, fixed_iters=9)
+    st, it, bd = _oracle(w, fixed_iters=9)
+    assert np.all(r["iters"] == 9)
+    assert rel_err(r["states"], st).max() < 1e-13
+    g = w.groups[0]
+    g.t0, g.tf = g.tf, g.t0
+    w.init = 1
+    r = _gpu(pc, w, want_nodes=True)
+    st, it, bd = _oracle(w)
+    assert r["status"] == 0 and boundary_err(r["bounds"], bd).max() <= TOL
+    assert np.abs(r["iters"] - it).max() <= 1
+    m = oracle.Model(w.mu_sun, w.pert, w.epoch)
+    o = oracle.propagate(w.ics[:5], g.t0, g.tf, g.nodes, g.segments, g.tol, m, init=1, want_nodes=True, order=2)
+    nodes = r["nodes"][:5, :, :256]
+    err = np.abs(nodes - o[2]).max() / np.abs(o[2]).max()
+    assert err < 1e-10, err
