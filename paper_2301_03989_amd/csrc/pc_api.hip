@@ -1234,7 +1234,7 @@ static int propagate_impl(pc_ctx* ctx, const double* ics, int64_t n_ic, const pc
     const bool eih = model->inv_c2 > 0.0;
     PC_HIP(ctx, hipSetDevice(ctx->device));
     Plan plan;
-    const bool lists_ok = o.path == PC_PATH_FUSED && o.precision == PC_FP64 && !eih && o.order == 1 &&
+    const bool lists_ok = o.path == PC_PATH_FUSED && o.precision == PC_FP64 && !eih && !o.feedback &&
                           o.init != PC_INIT_GUESS;
     rc = make_plan(ctx, n_ic, groups, n_groups, model, o, true, plan, lists_ok, no_alloc);
     if (rc != PC_OK) return rc;

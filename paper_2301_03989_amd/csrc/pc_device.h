@@ -931,7 +931,7 @@ struct PcQuadD {
 // block 0 (x, y) is K2_N times (a_x, a_y) and block 2 (v_y, v_z) K_N times (a_y, a_z), but
 // block 1 (z, v_x) needs K2_N for its low half and K_N for its high half, so it takes two
 // MFMAs whose B operands are zero in the other half (read from F's velocity columns, which
-// second-order sweeps leave at zero): four MFMAs per strip and k step against three.
+// second-order sweeps keep at zero): four MFMAs per strip and k step against three.
 // tp = tau_j + 1 of the lane's nodes (WIDE: tp[0]; 8-IC jobs: tp[4h + r]).  Flags as
 // pc_product.
 template <int PAIRS, int NP>
@@ -1219,7 +1219,8 @@ static __device__ __forceinline__ int pc_gather_flags(const int* sFlag, int m)
 // velocities as the force matrix F = (v, a) of Sec. 2.2 into sF[node][comp'][IC].
 // sRec/sMu: the segment's records in LDS (when rec_lds), grec: the same in global memory.
 // VEL = false (second-order sweeps, which read the accelerations only): the velocity
-// columns are left as they are.
+// columns are not written (they stay zero from the segment's start, and the 8-IC
+// second-order product reads them as zero B operands).
 template <int PAIRS, int NP, bool FP32 = false, bool VEL = true>
 static __device__ __forceinline__ void pc_publish(double* sF, const double (&yc)[6][4], const PcLane& L,
                                                   int N, int P, double mu_sun, bool rec_lds,

@@ -563,7 +563,8 @@ __device__ __attribute__((noinline)) void pc_job(const PcParams& p, const PcJobD
 // so the two barriers per sweep stay the only ones.  Each IC's sequence of iterates is the
 // one the one-block job body computes.  Between segments an IC's state lives in
 // states_out (the end state of its last completed segment).
-template <int PAIRS, int NP>
+// SO = 1: second-order sweeps (pc_product2) instead of the first-order product.
+template <int PAIRS, int NP, int SO = 0>
 __device__ __attribute__((noinline)) void pc_job_list(const PcParams& p, const PcJobDev& job, const PcGroupDev& g)
 {
     using Sh = PcShape<PAIRS, NP>;
@@ -586,6 +587,23 @@ __device__ __attribute__((noinline)) void pc_job_list(const PcParams& p, const P
     gconst_dp kp0 = (gconst_dp)g.kfrag + (size_t)L.strip0 * NQ * 64 + L.lane;
     double kpre[8];
     pc_kpre_load<PAIRS, NP>(kp0, kpre);
+    // second-order sweeps: the K2_N strip next to K_N's and the nodes' tau + 1
+    gconst_dp kp2 = nullptr;
+    double tp[8] = {};
+    if constexpr (SO) {
+        kp2 = (gconst_dp)g.kfrag2 + (size_t)L.strip0 * NQ * 64 + L.lane;
+        if constexpr (Sh::WIDE) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) kpre[4 + u] = kp2[u * 64];
+            tp[0] = pc_gcd(g.tau)[pc_node(L, 0, 0)] + 1.0;
+        } else {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) tp[4 * h + r] = pc_gcd(g.tau)[pc_node(L, h, r)] + 1.0;
+            }
+        }
+    }
     const bool flane = L.lane < COLS;             // lanes < COLS carry the per-column decisions
     const int fcol = L.lane & (COLS - 1);
     const bool owner = flane && L.strip0 == 0;    // one wave per group writes per-IC records
@@ -651,13 +669,21 @@ __device__ __attribute__((noinline)) void pc_job_list(const PcParams& p, const P
                     for (int r = 0; r < (Sh::WIDE ? 1 : 4); ++r) {
                         const int j = pc_node(L, h, r);
                         if (j >= N) continue;
-                        const double* f = sF + j * ROW + pc_fcol<PAIRS, NP>(j, Sh::WIDE ? pc_ic(L, e) : (L.lane & 7));
+                        double* f = sF + j * ROW + pc_fcol<PAIRS, NP>(j, Sh::WIDE ? pc_ic(L, e) : (L.lane & 7));
+                        // second-order sweeps keep F's velocity columns at zero: the lane
+                        // that reads a staged velocity clears it
                         if constexpr (Sh::WIDE) {
 #pragma unroll
-                            for (int cc = 0; cc < 6; ++cc) yc[cc][e] = f[cc * T];
+                            for (int cc = 0; cc < 6; ++cc) {
+                                yc[cc][e] = f[cc * T];
+                                if (SO && cc < 3) f[cc * T] = 0.0;
+                            }
                         } else {
 #pragma unroll
-                            for (int cb = 0; cb < 3; ++cb) yc[3 * h + cb][r] = f[(2 * cb + L.hi) * T];
+                            for (int cb = 0; cb < 3; ++cb) {
+                                yc[3 * h + cb][r] = f[(2 * cb + L.hi) * T];
+                                if (SO && 2 * cb + L.hi < 3) f[(2 * cb + L.hi) * T] = 0.0;
+                            }
                         }
                     }
                 }
@@ -694,12 +720,14 @@ __device__ __attribute__((noinline)) void pc_job_list(const PcParams& p, const P
         int it0 = 0;                          // flag lane: sweep before its IC's first one
         if (owner && fent >= 0) own_column(fent);
         __syncthreads();   // y0 written
-        if (amask) pc_publish<PAIRS, NP>(sF, yc, L, N, P, mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
+        if (amask) pc_publish<PAIRS, NP, false, SO == 0>(sF, yc, L, N, P, mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
         __syncthreads();
 
         for (int it = 1;; ++it) {
             f64x4 acc[6];
-            const int flag = pc_product<PAIRS, NP, false, false>(sF, sY0, kp0, kpre, nullptr, yc, acc, w2, tl, N, L);
+            int flag;
+            if constexpr (SO) flag = pc_product2<PAIRS, NP>(sF, sY0, kp0, kp2, kpre, yc, acc, w2, tp, tl, N, L);
+            else flag = pc_product<PAIRS, NP, false, false>(sF, sY0, kp0, kpre, nullptr, yc, acc, w2, tl, N, L);
             if (L.lane < 16) sm.Flag[L.wave * 16 + L.lane] = flag;
             __syncthreads();   // every wave is done reading F; flags complete
 
@@ -809,7 +837,7 @@ __device__ __attribute__((noinline)) void pc_job_list(const PcParams& p, const P
                 next += take;
                 amask = (amask & ~smask) | rmask;
             }
-            if (amask) pc_publish<PAIRS, NP>(sF, yc, L, N, P, mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
+            if (amask) pc_publish<PAIRS, NP, false, SO == 0>(sF, yc, L, N, P, mu_sun, rec_lds, sm.Rec, sm.Mu, grec);
             // every wave of an IC group holds the group's column mask: the first strip's waves
             // note it (rewritten only after the next sweep's first barrier)
             if (L.strip0 == 0 && L.lane == 0) sm.Go[L.grp] = amask != 0u;
@@ -829,6 +857,35 @@ __device__ __attribute__((noinline)) void pc_job_list(const PcParams& p, const P
         if (!fin) atomicAdd(&p.counters[1], 1);
     }
     __syncthreads();
+}
+
+// The job body for node count NP and the call's options: second-order sweeps (with the
+// feedback on WIDE shapes), relativistic, refilled column lists, precision schedule or
+// plain FP64 one-block jobs.
+template <int PAIRS, int NP>
+static __device__ __forceinline__ void pc_run_job(const PcParams& p, const PcJobDev& job, const PcGroupDev& g,
+                                                  bool list, bool mixed, bool eih, bool order2)
+{
+    if (order2) {
+        if constexpr (PcShape<PAIRS, NP>::WIDE) {
+            if (p.feedback) {
+                pc_job<PAIRS, NP, false, false, 2>(p, job, g);
+                return;
+            }
+        }
+        if (list) pc_job_list<PAIRS, NP, 1>(p, job, g);
+        else pc_job<PAIRS, NP, false, false, 1>(p, job, g);
+    } else if (eih && mixed) {
+        pc_job<PAIRS, NP, true, true>(p, job, g);
+    } else if (eih) {
+        pc_job<PAIRS, NP, false, true>(p, job, g);
+    } else if (list) {
+        pc_job_list<PAIRS, NP>(p, job, g);
+    } else if (mixed) {
+        pc_job<PAIRS, NP, true>(p, job, g);
+    } else {
+        pc_job<PAIRS, NP, false>(p, job, g);
+    }
 }
 
 // Persistent work-queue kernel: every workgroup takes the next job of the plan (jobs of
@@ -854,76 +911,14 @@ __global__ __launch_bounds__(PAIRS / 4, 2) void pc_fused_kernel(const PcParams* 
         const bool mixed = p.precision == 1;
         const bool eih = p.inv_c2 != 0.0;   // relativistic model: one-block jobs
         const bool order2 = p.order == 2;   // second-order sweeps (with the integral error feedback when
-                                            // asked): FP64, point masses, WIDE shapes
+                                            // asked, WIDE shapes): FP64, point masses
         switch (g.NP) {
-        case 16:
-            if constexpr (PcShape<PAIRS, 16>::WIDE) {
-                if (order2) {
-                    if (p.feedback) pc_job<PAIRS, 16, false, false, 2>(p, job, g);
-                    else pc_job<PAIRS, 16, false, false, 1>(p, job, g);
-                    break;
-                }
-            }
-            if (eih && mixed) pc_job<PAIRS, 16, true, true>(p, job, g);
-            else if (eih) pc_job<PAIRS, 16, false, true>(p, job, g);
-            else if (list) pc_job_list<PAIRS, 16>(p, job, g);
-            else if (mixed) pc_job<PAIRS, 16, true>(p, job, g);
-            else pc_job<PAIRS, 16, false>(p, job, g);
-            break;
-        case 32:
-            if constexpr (PcShape<PAIRS, 32>::WIDE) {
-                if (order2) {
-                    if (p.feedback) pc_job<PAIRS, 32, false, false, 2>(p, job, g);
-                    else pc_job<PAIRS, 32, false, false, 1>(p, job, g);
-                    break;
-                }
-            }
-            if (eih && mixed) pc_job<PAIRS, 32, true, true>(p, job, g);
-            else if (eih) pc_job<PAIRS, 32, false, true>(p, job, g);
-            else if (list) pc_job_list<PAIRS, 32>(p, job, g);
-            else if (mixed) pc_job<PAIRS, 32, true>(p, job, g);
-            else pc_job<PAIRS, 32, false>(p, job, g);
-            break;
-        case 64:
-            if constexpr (PcShape<PAIRS, 64>::WIDE) {
-                if (order2) {
-                    if (p.feedback) pc_job<PAIRS, 64, false, false, 2>(p, job, g);
-                    else pc_job<PAIRS, 64, false, false, 1>(p, job, g);
-                    break;
-                }
-            }
-            if (eih && mixed) pc_job<PAIRS, 64, true, true>(p, job, g);
-            else if (eih) pc_job<PAIRS, 64, false, true>(p, job, g);
-            else if (list) pc_job_list<PAIRS, 64>(p, job, g);
-            else if (mixed) pc_job<PAIRS, 64, true>(p, job, g);
-            else pc_job<PAIRS, 64, false>(p, job, g);
-            break;
-        case 128:
-            if constexpr (PcShape<PAIRS, 128>::WIDE) {
-                if (order2) {
-                    if (p.feedback) pc_job<PAIRS, 128, false, false, 2>(p, job, g);
-                    else pc_job<PAIRS, 128, false, false, 1>(p, job, g);
-                    break;
-                }
-            }
-            if (eih && mixed) pc_job<PAIRS, 128, true, true>(p, job, g);
-            else if (eih) pc_job<PAIRS, 128, false, true>(p, job, g);
-            else if (list) pc_job_list<PAIRS, 128>(p, job, g);
-            else if (mixed) pc_job<PAIRS, 128, true>(p, job, g);
-            else pc_job<PAIRS, 128, false>(p, job, g);
-            break;
+        case 16: pc_run_job<PAIRS, 16>(p, job, g, list, mixed, eih, order2); break;
+        case 32: pc_run_job<PAIRS, 32>(p, job, g, list, mixed, eih, order2); break;
+        case 64: pc_run_job<PAIRS, 64>(p, job, g, list, mixed, eih, order2); break;
+        case 128: pc_run_job<PAIRS, 128>(p, job, g, list, mixed, eih, order2); break;
         case 256:
-            if constexpr (PAIRS >= 2048) {
-                if (order2) {   // node-row second-order sweeps (no feedback at 256 nodes)
-                    pc_job<PAIRS, 256, false, false, 1>(p, job, g);
-                    break;
-                }
-                if (eih && mixed) pc_job<PAIRS, 256, true, true>(p, job, g);
-                else if (eih) pc_job<PAIRS, 256, false, true>(p, job, g);
-                else if (list) pc_job_list<PAIRS, 256>(p, job, g);
-                else if (mixed) pc_job<PAIRS, 256, true>(p, job, g);
-                else pc_job<PAIRS, 256, false>(p, job, g);
-            }
+            if constexpr (PAIRS >= 2048) pc_run_job<PAIRS, 256>(p, job, g, list, mixed, eih, order2);
             break;
         default: break;
         }

@@ -192,3 +192,19 @@ def test_node_row_second_order_fixed_sweeps_backward_and_nodes(pc):
     nodes = r["nodes"][:5, :, :256]
     err = np.abs(nodes - o[2]).max() / np.abs(o[2]).max()
     assert err < 1e-10, err
+
+
+@pytest.mark.parametrize("nodes", [64, 128, 256])
+def test_second_order_refilled_columns(pc, nodes):
+    """Jobs longer than one column block (a stopped IC's column takes the next IC of the
+    segment) under second-order sweeps: against the oracle, and the same sweep counts and
+    states as one-block jobs."""
+    w = W.nbody_venus(150, seed=20 + nodes, days=112.5, segments=2, nodes=nodes)
+    a = _gpu(pc, w, job_list=4)
+    b = _gpu(pc, w, job_list=1)
+    st, it, bd = _oracle(w)
+    assert a["status"] == 0 and b["status"] == 0
+    assert boundary_err(a["bounds"], bd).max() <= TOL
+    assert np.abs(a["iters"] - it).max() <= 1
+    assert np.array_equal(a["iters"], b["iters"])
+    assert rel_err(a["states"], b["states"]).max() < 1e-13
