@@ -129,13 +129,14 @@ def test_random_batch(pc, seed):
 
 def _option_case(seed):
     """A seeded case of one of the later options: second-order sweeps (with or without the
-    integral error feedback), adaptive refinement under a sweep budget, flyby isolation
-    (per-IC or group-max rule), or a hot start from the oracle's node states of nearby ICs."""
+    integral error feedback), adaptive refinement under a sweep budget (first- or
+    second-order sweeps), flyby isolation (per-IC or group-max rule), or a hot start from
+    the oracle's node states of nearby ICs."""
     rng = np.random.default_rng(9000 + seed)
-    mode = ["order2", "feedback", "refine", "flyby", "guess"][seed % 5]
+    mode = ["order2", "feedback", "refine", "flyby", "guess", "order2_refine"][seed % 6]
     kw, okw = {}, {}
     if mode in ("order2", "feedback"):
-        N = int(rng.integers(3, 129))
+        N = int(rng.integers(3, 129 if mode == "feedback" else 257))
         S = int(rng.integers(1, 4))
         w = W.nbody_venus(int(rng.integers(5, 40)), seed=400 + seed, days=float(rng.uniform(20, 90)) * S,
                           segments=S, nodes=N, tol=float(rng.choice([1e-11, 1e-12])))
@@ -150,6 +151,13 @@ def _option_case(seed):
         budget, depth = int(rng.integers(16, 29)), int(rng.integers(1, 4))
         kw = dict(refine=depth, max_iter=budget)
         okw = dict(refine=depth, max_iter=budget)
+    elif mode == "order2_refine":
+        # second-order sweeps take about half the first-order count: a smaller budget
+        w = W.long_segments(int(rng.integers(8, 40)), seed=550 + seed, nodes=int(rng.integers(48, 257)),
+                            segments=int(rng.integers(1, 4)))
+        budget, depth = int(rng.integers(8, 15)), int(rng.integers(1, 4))
+        kw = dict(refine=depth, max_iter=budget, order=2)
+        okw = dict(refine=depth, max_iter=budget, order=2)
     elif mode == "flyby":
         u = W.uneven_batch(int(rng.integers(200, 600)), seed=600 + seed)
         keep = sorted(rng.choice(len(u.groups), size=int(rng.integers(2, 5)), replace=False))
@@ -214,7 +222,7 @@ def test_random_options(pc, seed):
     o = oracle_run(w, **okw)
     assert rel_err(states, o["states"]).max() < 1e-10
     d = np.abs(iters - o["iters"])
-    if mode == "refine":   # a budget hit one sweep apart splits a segment differently on each side
+    if mode in ("refine", "order2_refine"):   # a budget hit one sweep apart splits a segment differently
         assert (np.all(d <= 2, axis=1)).mean() >= 0.9
     else:
         assert d.max() <= 1, d.max()
