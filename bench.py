@@ -637,10 +637,11 @@ def run_second_order(args, w, pcprop):
 
 def run_flyby(args, ctx, w, pcprop):
     """The flyby-isolation sub-record: the workload on the plain path under the group-max
-    stopping rule (the paper's per-system convergence), each group as one outer group and
-    with its flyby ICs (two-body prediction within --flyby-hill Hill radii of a planet) in a
-    group of their own; time and mean sweeps per segment of the quiet ICs, and, under the
-    per-IC rule on the fused path, the mean sweeps of the flyby and of the quiet ICs."""
+    stopping rule (the paper's per-system convergence) with the outer level on 10 streams,
+    each group as one outer group and with its flyby ICs (two-body prediction within
+    --flyby-hill Hill radii of a planet) in a group of their own; time and mean sweeps per
+    segment of the quiet ICs, and, under the per-IC rule on the fused path, the mean sweeps
+    of the flyby and of the quiet ICs."""
     import torch
     S = max(g.segments for g in w.groups)
     ics = torch.tensor(w.ics, dtype=torch.float64, device="cuda")
@@ -651,7 +652,7 @@ def run_flyby(args, ctx, w, pcprop):
     res = {}
     for hill in (0.0, args.flyby_hill):
         it = torch.zeros((w.n_ic, S), dtype=torch.int32, device="cuda")
-        kw = dict(path="plain", conv="group", flyby_hill=hill, iters_out=it)
+        kw = dict(path="plain", conv="group", flyby_hill=hill, iters_out=it, streams=10)
         ctx.propagate_batched(ics, groups, model, **kw)   # untimed: first launches of its kernels
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -669,7 +670,7 @@ def run_flyby(args, ctx, w, pcprop):
     per_ic = {"mean_sweeps_per_segment_quiet": round(float(iters[quiet][iters[quiet] > 0].mean()), 3),
               "mean_sweeps_per_segment_flyby": round(float(iters[~quiet][iters[~quiet] > 0].mean()), 3)
               if (~quiet).any() else None}
-    out = {"workload": w.name, "path": "plain", "conv": "group", "hill_radii": args.flyby_hill,
+    out = {"workload": w.name, "path": "plain", "conv": "group", "streams": 10, "hill_radii": args.flyby_hill,
            "isolated_ics": int((~quiet).sum()), "n_ic": w.n_ic, "per_ic_rule_fused": per_ic,
            "without_isolation": res[0.0], "with_isolation": res[args.flyby_hill],
            "speedup": round(res[0.0]["ms"] / res[args.flyby_hill]["ms"], 3)}
