@@ -194,7 +194,7 @@ def test_node_row_second_order_fixed_sweeps_backward_and_nodes(pc):
     assert err < 1e-10, err
 
 
-@pytest.mark.parametrize("nodes", [64, 128, 256])
+@pytest.mark.parametrize("nodes", [64, 100, 128, 200, 256])
 def test_second_order_refilled_columns(pc, nodes):
     """Jobs longer than one column block (a stopped IC's column takes the next IC of the
     segment) under second-order sweeps: against the oracle, and the same sweep counts and
