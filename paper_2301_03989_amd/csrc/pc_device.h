@@ -19,6 +19,11 @@ static __device__ __forceinline__ int pc_dpp(int v)
     return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
 }
 template <int CTRL>
+static __device__ __forceinline__ float pc_dpp(float v)
+{
+    return __builtin_bit_cast(float, pc_dpp<CTRL>(__builtin_bit_cast(int, v)));
+}
+template <int CTRL>
 static __device__ __forceinline__ double pc_dpp(double v)
 {
     const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
@@ -713,7 +718,57 @@ static __device__ __forceinline__ int pc_wide_epilogue(const double* sY0, const 
     return (__shfl(fr, 16 * (L.lane & 3)) >> (4 * ((L.lane >> 2) & 3))) & 7;
 }
 
-// Increment sweep of the precision schedule (WIDE shapes): Y_new = Y + w2 K_N dF with
+// Epilogue of an 8-IC job's product (node-row layout: element (3h + cb, r) is comp 2cb + hi
+// of node pc_node(L, h, r) of IC l % 8): y_new = y0 + w2 acc (INCR: yc + w2 acc), the
+// position and velocity
+// change norms summed over the lane pair (l, l ^ 8) that shares the IC's components, and
+// the stopping-rule flags OR-ed over the lane's nodes and its partner's.  The caller ORs
+// the four row groups.
+template <int PAIRS, int NP, bool SW, bool INCR = false>
+static __device__ __forceinline__ int pc_row_epilogue(const double* sY0, const double (&yc)[6][4],
+                                                      f64x4 (&acc)[6], double w2, const PcTol& tl, int N,
+                                                      const PcLane& L)
+{
+    constexpr int T = PcShape<PAIRS, NP>::T;
+    const int hi = L.hi;
+    const int my_m = pc_ic(L, 0);
+    int flag = 0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = pc_node(L, h, r);
+            double dd[3], yy[3];
+#pragma unroll
+            for (int cb = 0; cb < 3; ++cb) {
+                const double base = INCR ? yc[3 * h + cb][r] : sY0[(2 * cb + hi) * T + my_m];
+                const double yn = base + w2 * acc[3 * h + cb][r];
+                acc[3 * h + cb][r] = yn;
+                const double d = yn - yc[3 * h + cb][r];
+                dd[cb] = d * d;
+                yy[cb] = yn * yn;
+            }
+            double pd = dd[0] + (hi ? 0.0 : dd[1]);
+            double py = yy[0] + (hi ? 0.0 : yy[1]);
+            double vd = (hi ? dd[1] : 0.0) + dd[2];
+            double vy = (hi ? yy[1] : 0.0) + yy[2];
+            pd += pc_dpp<0x128>(pd);   // lane ^ 8
+            py += pc_dpp<0x128>(py);
+            vd += pc_dpp<0x128>(vd);
+            vy += pc_dpp<0x128>(vy);
+            if (j < N) {
+                const bool ok = pd < fma(tl.ta, py, tl.tb) && vd < fma(tl.ta, vy, tl.tb);
+                const bool lo = !SW || (pd < fma(tl.sa, py, tl.sb) && vd < fma(tl.sa, vy, tl.sb));
+                const bool nf = !isfinite(py + vy);
+                flag |= (ok ? 0 : 1) | (nf ? 2 : 0) | (lo ? 0 : 4);
+            }
+        }
+    }
+    flag |= pc_dpp<0x128>(flag);
+    return flag;
+}
+
+// Increment sweep of the precision schedule: Y_new = Y + w2 K_N dF with
 // dF, the change of F (pc_publish_chord), held in LDS as FP32 (sD, [node][comp 6][IC]
 // with the column swizzle of pc_fcol) and multiplied on the FP32 matrix cores; the sum
 // into Y stays FP64.  The FP32 rounding is relative to the increment, so it shrinks as the
@@ -725,12 +780,39 @@ static __device__ __forceinline__ int pc_product_incr(const float* sD, gconst_fp
                                                       const PcLane& L)
 {
     using Sh = PcShape<PAIRS, NP>;
-    static_assert(Sh::WIDE, "increment sweeps run on WIDE job shapes");
     constexpr int T = Sh::T, ROW = Sh::ROW, NQ = Sh::NQ;
     const int lane = L.lane;
     f32x4 accf[6];
 #pragma unroll
     for (int b = 0; b < 6; ++b) accf[b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    if constexpr (!Sh::WIDE) {
+        // 8-IC jobs: the node-row FP32 product of pc_product (K_N rows permuted in kp0f so
+        // that the f32 result layout matches the f64 one) on dF, added to the iterate
+        gconst_fp kp1f = kp0f + (size_t)NQ * 64;
+        const float* bp = sD + (lane >> 4) * ROW + (lane & 15);
+        pc_kloop<NQ, 3, PcPairF, float>(
+            [&](int q) { return PcPairF{kp0f[q * 64], kp1f[q * 64]}; },
+            [&](int q) { return PcPairF{kp0f[q * 64], kp1f[q * 64]}; },
+            [&](int q, int, float (&bq)[3]) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) bq[c] = bp[q * 4 * ROW + 16 * c];
+            },
+            [&](const PcPairF& ka, const float (&bq)[3]) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) accf[c] = mfma16f(ka.a0, bq[c], accf[c]);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) accf[3 + c] = mfma16f(ka.a1, bq[c], accf[3 + c]);
+            });
+#pragma unroll
+        for (int b = 0; b < 6; ++b) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[b][r] = (double)accf[b][r];
+        }
+        int flag = pc_row_epilogue<PAIRS, NP, true, true>(nullptr, yc, acc, w2, tl, N, L);
+        flag |= __shfl_xor(flag, 16);
+        flag |= __shfl_xor(flag, 32);
+        return flag;
+    }
     // IC rows read in the order perm(i) = i/4 + 4 (i%4), so the f32 result layout puts IC
     // l/16 + 4r in element r as the f64 one does
     const int i = lane & 15, pi = (i >> 2) + 4 * (i & 3);
@@ -764,54 +846,6 @@ static __device__ __forceinline__ int pc_product_incr(const float* sD, gconst_fp
 // bit 0 = some node not converged, bit 1 = non-finite, bit 2 = some node changed by more
 // than sqrt(sw2) (relative).  WIDE blocks are computed as (K_N F)^T = F^T K_N^T: the F
 // slice is the A operand and the K_N fragment the B operand.  SW: evaluate bit 2.
-// Epilogue of an 8-IC job's product (node-row layout: element (3h + cb, r) is comp 2cb + hi
-// of node pc_node(L, h, r) of IC l % 8): y_new = y0 + w2 acc, the position and velocity
-// change norms summed over the lane pair (l, l ^ 8) that shares the IC's components, and
-// the stopping-rule flags OR-ed over the lane's nodes and its partner's.  The caller ORs
-// the four row groups.
-template <int PAIRS, int NP, bool SW>
-static __device__ __forceinline__ int pc_row_epilogue(const double* sY0, const double (&yc)[6][4],
-                                                      f64x4 (&acc)[6], double w2, const PcTol& tl, int N,
-                                                      const PcLane& L)
-{
-    constexpr int T = PcShape<PAIRS, NP>::T;
-    const int hi = L.hi;
-    const int my_m = pc_ic(L, 0);
-    int flag = 0;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int j = pc_node(L, h, r);
-            double dd[3], yy[3];
-#pragma unroll
-            for (int cb = 0; cb < 3; ++cb) {
-                const double yn = sY0[(2 * cb + hi) * T + my_m] + w2 * acc[3 * h + cb][r];
-                acc[3 * h + cb][r] = yn;
-                const double d = yn - yc[3 * h + cb][r];
-                dd[cb] = d * d;
-                yy[cb] = yn * yn;
-            }
-            double pd = dd[0] + (hi ? 0.0 : dd[1]);
-            double py = yy[0] + (hi ? 0.0 : yy[1]);
-            double vd = (hi ? dd[1] : 0.0) + dd[2];
-            double vy = (hi ? yy[1] : 0.0) + yy[2];
-            pd += pc_dpp<0x128>(pd);   // lane ^ 8
-            py += pc_dpp<0x128>(py);
-            vd += pc_dpp<0x128>(vd);
-            vy += pc_dpp<0x128>(vy);
-            if (j < N) {
-                const bool ok = pd < fma(tl.ta, py, tl.tb) && vd < fma(tl.ta, vy, tl.tb);
-                const bool lo = !SW || (pd < fma(tl.sa, py, tl.sb) && vd < fma(tl.sa, vy, tl.sb));
-                const bool nf = !isfinite(py + vy);
-                flag |= (ok ? 0 : 1) | (nf ? 2 : 0) | (lo ? 0 : 4);
-            }
-        }
-    }
-    flag |= pc_dpp<0x128>(flag);
-    return flag;
-}
-
 template <int PAIRS, int NP, bool FP32 = false, bool SW = true>
 static __device__ __forceinline__ int pc_product(const double* sF, const double* sY0, gconst_dp kp0,
                                                   const double (&kpre)[8], gconst_fp kp0f,
@@ -1312,13 +1346,14 @@ static __device__ __forceinline__ void pc_publish(double* sF, const double (&yc)
 // the error of G times the distance of the anchor from the solution: d is formed in FP64
 // and then rounded (near a close approach, rounding the positions first would leave an
 // error of 1e-5 in G and of about 1e-12 in the result), the rest is FP32.
-template <int R>
+template <int R, bool ONE_NODE = true>
 static __device__ __forceinline__ void pc_grad_lds_node32(const double (&x)[R], const double (&y)[R],
-                                                          const double (&z)[R], int j, int P, double mu_sun,
-                                                          const double* srec, const double* smu,
+                                                          const double (&z)[R], const int (&jr)[R], int P,
+                                                          double mu_sun, const double* srec, const double* smu,
                                                           float (&G)[6][R])
 {
-    const double* rec = srec + j * 3 * (P + 1);
+    // ONE_NODE: the R points share node jr[0] (WIDE); else point r is at node jr[r]
+    auto rec = [&](int r) { return srec + (ONE_NODE ? jr[0] : jr[r]) * 3 * (P + 1); };
 #pragma unroll
     for (int r = 0; r < R; ++r) {
 #pragma unroll
@@ -1341,10 +1376,12 @@ static __device__ __forceinline__ void pc_grad_lds_node32(const double (&x)[R], 
 #pragma unroll
     for (int r = 0; r < R; ++r) add(r, (float)x[r], (float)y[r], (float)z[r], ms);
     for (int b = 0; b < P; ++b) {
-        const double qx = rec[3 * b], qy = rec[3 * b + 1], qz = rec[3 * b + 2];
         const float mu = (float)smu[b];
 #pragma unroll
-        for (int r = 0; r < R; ++r) add(r, (float)(x[r] - qx), (float)(y[r] - qy), (float)(z[r] - qz), mu);
+        for (int r = 0; r < R; ++r) {
+            const double* q = rec(r) + 3 * b;
+            add(r, (float)(x[r] - q[0]), (float)(y[r] - q[1]), (float)(z[r] - q[2]), mu);
+        }
     }
 }
 
@@ -1517,7 +1554,7 @@ static __device__ __forceinline__ void pc_publish_eih(double* sF, const double (
     }
 }
 
-// Publish for an increment sweep (WIDE shapes).  The increment of F = (v, a) from the last
+// Publish for an increment sweep.  The increment of F = (v, a) from the last
 // change dy of the iterate, to first order: dF = (dv, G dr), with G the gravity gradient
 // at the anchor, the iterate after the last FP64 sweep (ANCHOR: evaluated here at yc and
 // kept in sG, [node][6][IC] FP32, read back only by the same lane; else read from sG).
@@ -1530,8 +1567,77 @@ static __device__ __forceinline__ void pc_publish_chord(float* sD, float* sG, co
                                                         double mu_sun, const double* sRec, const double* sMu)
 {
     using Sh = PcShape<PAIRS, NP>;
-    static_assert(Sh::WIDE, "increment sweeps run on WIDE job shapes");
     constexpr int T = Sh::T, ROW = Sh::ROW;
+    if constexpr (!Sh::WIDE) {
+        // 8-IC jobs (node-row layout, lane pairs sharing an IC's components): each lane
+        // stores dv for its own velocity components at its eight nodes, and forms G dr at
+        // the four points of strip hi (G from the anchor's position, kept in sG by the same
+        // lane), taking the components it lacks from its partner as pc_publish does
+        const int hi = L.hi, m = pc_ic(L, 0);
+        const bool on = act[0];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = pc_node(L, h, r);
+                float* d = sD + j * ROW + m;
+                const bool ok = j < N;   // rows past N stay zero (they meet zero operator columns)
+#pragma unroll
+                for (int cb = 0; cb < 3; ++cb) {
+                    const int c = 2 * cb + hi;
+                    if (c >= 3) d[(c - 3) * T] = ok ? dy[3 * h + cb][r] : 0.0f;
+                }
+            }
+        }
+        double xs[4], ys[4], zs[4];
+        float rx[4], ry[4], rz[4];
+        int jr[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const double e1 = pc_dpp<0x128>(hi ? yc[0][r] : yc[3][r]);   // lo: y(0); hi: x(1)
+            const double e2 = pc_dpp<0x128>(yc[4][r]);                   // hi: z(1)
+            const float f1 = pc_dpp<0x128>(hi ? dy[0][r] : dy[3][r]);    // lo: dy(0); hi: dx(1)
+            const float f2 = pc_dpp<0x128>(dy[4][r]);                    // hi: dz(1)
+            xs[r] = hi ? e1 : yc[0][r];
+            ys[r] = hi ? yc[3][r] : e1;
+            zs[r] = hi ? e2 : yc[1][r];
+            rx[r] = hi ? f1 : dy[0][r];
+            ry[r] = hi ? dy[3][r] : f1;
+            rz[r] = hi ? f2 : dy[1][r];
+            const int j = pc_node(L, hi, r);
+            jr[r] = j < N ? j : N - 1;
+        }
+        float G[6][4];
+        if (anchor) {
+            pc_grad_lds_node32<4, false>(xs, ys, zs, jr, P, mu_sun, sRec, sMu, G);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float* g = sG + pc_node(L, hi, r) * 6 * T + m;
+#pragma unroll
+                for (int e = 0; e < 6; ++e) {
+                    G[e][r] = on ? G[e][r] : 0.0f;
+                    g[e * T] = G[e][r];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float* g = sG + pc_node(L, hi, r) * 6 * T + m;
+#pragma unroll
+                for (int e = 0; e < 6; ++e) G[e][r] = g[e * T];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = pc_node(L, hi, r);
+            const bool ok = j < N;
+            float* d = sD + j * ROW + m;
+            d[3 * T] = ok ? fmaf(G[0][r], rx[r], fmaf(G[3][r], ry[r], G[4][r] * rz[r])) : 0.0f;
+            d[4 * T] = ok ? fmaf(G[3][r], rx[r], fmaf(G[1][r], ry[r], G[5][r] * rz[r])) : 0.0f;
+            d[5 * T] = ok ? fmaf(G[4][r], rx[r], fmaf(G[5][r], ry[r], G[2][r] * rz[r])) : 0.0f;
+        }
+        return;
+    }
     const int j = pc_node(L, 0, 0);
     if (j >= N) {   // rows past N meet zero operator columns: keep them zero (no stale NaN bits)
 #pragma unroll
@@ -1544,7 +1650,7 @@ static __device__ __forceinline__ void pc_publish_chord(float* sD, float* sG, co
     }
     float G[6][4];
     if (anchor) {
-        pc_grad_lds_node32<4>(yc[0], yc[1], yc[2], j, P, mu_sun, sRec, sMu, G);
+        pc_grad_lds_node32<4>(yc[0], yc[1], yc[2], {j, j, j, j}, P, mu_sun, sRec, sMu, G);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             float* g = sG + j * 6 * T + pc_fcol<PAIRS, NP>(j, pc_ic(L, r));

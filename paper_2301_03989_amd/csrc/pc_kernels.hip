@@ -269,8 +269,8 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
     for (int i = tid; i < 6 * PAIRS; i += NT) sF[i] = 0.0;
     __syncthreads();
     // precision schedule (uniform per job): an FP32 phase first when asked, then FP64
-    // sweeps.  Sweep kinds: 0 FP64 Picard sweep, 1 FP32 Picard sweep (8-IC jobs),
-    // 2 FP32 increment sweep (WIDE jobs, after one FP64 sweep; records in LDS).
+    // sweeps.  Sweep kinds: 0 FP64 Picard sweep, 1 FP32 Picard sweep (jobs whose records do
+    // not fit in LDS), 2 FP32 increment sweep (after one FP64 sweep; records in LDS).
     // An increment sweep adds w2 K_N dF to the FP64 iterate, dF the change of F to first
     // order in the last change of the iterate, (dv, G dr), with G the gravity gradient at
     // the iterate of the last FP64 sweep (the anchor); dF and the product are FP32, and no
@@ -284,7 +284,7 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
     // the only ones the stopping rule is applied to, so that every IC stops on an FP64
     // sweep that changed it by less than tol (one sweep for most ICs; more where the
     // linearisation left more, as near close approaches, or where stage 2 hit its cap).
-    const bool incr = Sh::WIDE && rec_lds;
+    const bool incr = rec_lds;
     // increment jobs open with FP64 sweeps until no IC changes by more than 1e-3 (stage
     // -1): the linearisation needs an anchor near the solution, which a warm start gives
     // after one sweep and a cold start after several
@@ -347,8 +347,11 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
             else
                 flag = pc_product<PAIRS, NP, false>(sF, sY0, kp0, kpre, kp0f, yc, acc, w2, tl, N, L);
         } else if constexpr (MIXED) {
-            flag = mode == 1 ? pc_product<PAIRS, NP, true>(sF, sY0, kp0, kpre, kp0f, yc, acc, w2, tl, N, L)
-                             : pc_product<PAIRS, NP, false>(sF, sY0, kp0, kpre, kp0f, yc, acc, w2, tl, N, L);
+            if (mode == 2)
+                flag = pc_product_incr<PAIRS, NP>(sD, kp0f, yc, acc, w2, tl, N, L);
+            else
+                flag = mode == 1 ? pc_product<PAIRS, NP, true>(sF, sY0, kp0, kpre, kp0f, yc, acc, w2, tl, N, L)
+                                 : pc_product<PAIRS, NP, false>(sF, sY0, kp0, kpre, kp0f, yc, acc, w2, tl, N, L);
         } else if constexpr (SO == 2) {
             flag = pc_product2_fb<PAIRS, NP>(sF, sY0, kp0, kp2, kpre, yc, acc, w2, tp[0], tl, N, L, P, mu_sun,
                                              rec_lds, sm.Rec, sm.Mu, grec);
@@ -414,7 +417,7 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
         const int next_mode = next32 ? (incr ? 2 : 1) : 0;
         // (4) ICs that were iterating take the new iterate and publish its F (or, before an
         //     increment sweep, the change of F)
-        if constexpr (MIXED && Sh::WIDE) {
+        if constexpr (MIXED) {
             if (next_mode == 2 && it < n_it) {
                 float dy[6][4];
 #pragma unroll
@@ -434,7 +437,7 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
                 continue;
             }
         }
-        if constexpr (MIXED && Sh::WIDE) {
+        if constexpr (MIXED) {
             // back to FP64 after increment sweeps: the FP32 arrays left arbitrary bits in the
             // rows past N of the FP64 view, which meet zero operator columns; clear them
             if (mode == 2 && N < NP) {

@@ -479,11 +479,11 @@ def test_fp32_then_fp64_matches_fp64_oracle(pc, n_ic):
     assert d.mean() <= 1.5, d.mean()
 
 
-@pytest.mark.parametrize("nodes", [48, 100])
+@pytest.mark.parametrize("nodes", [48, 100, 200])
 def test_fp32_then_fp64_padded_nodes_and_nonfinite_ic(pc, nodes):
-    """Increment sweeps on job shapes padded past N (48 of 64 and 100 of 128 nodes: rows
-    past N of the force array, written by the FP32 sweeps, meet zero operator columns once
-    FP64 sweeps resume), with a non-finite IC in the job."""
+    """Increment sweeps on job shapes padded past N (48 of 64, 100 of 128 and 200 of 256
+    nodes: rows past N of the force array, written by the FP32 sweeps, meet zero operator
+    columns once FP64 sweeps resume), with a non-finite IC in the job."""
     w = W.nbody_venus(40, seed=105, nodes=nodes, segments=2, days=112.5)
     w.ics = w.ics.copy()
     w.ics[3, 1] = np.nan
@@ -494,6 +494,21 @@ def test_fp32_then_fp64_padded_nodes_and_nonfinite_ic(pc, nodes):
     assert (r["iters"][ok] > 0).all()
     err = rel_err(r["states"][ok], o["states"][ok])
     assert err.max() < 1e-11, err.max()
+
+
+def test_fp32_then_fp64_node_row_jobs(pc):
+    """Increment sweeps on 8-IC jobs (256 nodes, node-row layout: lane pairs exchange the
+    position and its change for the gravity gradient) against the FP64 oracle, with the
+    same bars as the 128-node jobs."""
+    w = W.nbody_venus(60, seed=106, nodes=256, segments=4, days=225.0)
+    r, _ = _run(pc, w, precision="fp32-fp64", want_bounds=True)
+    o = oracle_run(w, want_bounds=True)
+    assert r["status"] == 0
+    err = rel_err(r["bounds"].reshape(-1, 6), o["bounds"].reshape(-1, 6))
+    assert err.max() < 1e-11, err.max()
+    d = r["iters"] - o["iters"]
+    assert d.min() >= -1 and d.max() <= 3, (d.min(), d.max())
+    assert d.mean() <= 1.5, d.mean()
 
 
 def test_fp32_then_fp64_mixed_groups(pc):
