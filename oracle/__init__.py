@@ -344,6 +344,63 @@ def accel_jac_t(r, t, model):
     return J.reshape(3, 3)
 
 
+def _eih_major_bodies(t, model):
+    """Major-body states of the relativistic model at time t, as orc_accel_eih builds them:
+    the Sun at rest at the origin, the perturbers on their Keplerian orbits (mu = 1) with
+    the accelerations of those orbits, and each body's potential of the other major bodies."""
+    nb = model.n_pert + 1
+    rb, vb, ab = np.zeros((nb, 3)), np.zeros((nb, 3)), np.zeros((nb, 3))
+    mub = np.empty(nb)
+    mub[0] = model.mu_sun
+    for p in range(model.n_pert):
+        r, v = ephem_state(model.pert[p], model.epoch, t)
+        rb[p + 1], vb[p + 1] = r, v
+        ab[p + 1] = -r / np.linalg.norm(r) ** 3
+        mub[p + 1] = model.pert[p, 0]
+    Ub = np.array([sum(mub[k] / np.linalg.norm(rb[b] - rb[k]) for k in range(nb) if k != b)
+                   for b in range(nb)])
+    return rb, vb, ab, mub, Ub
+
+
+def _eih_accel_np(y, rb, vb, ab, mub, Ub, inv_c2):
+    """The relativistic sums of Sec. 5.4.1 (PPN beta = gamma = 1, massless body), restated
+    in numpy so that they also take a complex state (no indirect term):
+      a = sum_b -mu_b d_b / rho_b^3 [1 - (4 Phi + U_b - v^2 - 2 v_b^2 + 4 v.v_b
+                                          + 3/2 (d_b.v_b / rho_b)^2 + 1/2 d_b.a_b) / c^2]
+        + sum_b mu_b / (c^2 rho_b^3) [d_b.(4 v - 3 v_b)] (v - v_b) + 7/2 sum_b mu_b a_b / (c^2 rho_b)
+    with d_b = r - r_b, rho_b = |d_b| (the plain sum of squares, analytic for a complex
+    step) and Phi = sum_b mu_b / rho_b."""
+    r, v = y[:3], y[3:]
+    d = r[None, :] - rb
+    rho = np.sqrt((d * d).sum(axis=1))
+    phi = (mub / rho).sum()
+    v2 = (v * v).sum()
+    a = np.zeros(3, dtype=np.result_type(y, 1.0))
+    for b in range(rb.shape[0]):
+        db, wb, gb = d[b], vb[b], ab[b]
+        i3 = 1.0 / rho[b] ** 3
+        brk = 1.0 - inv_c2 * (4.0 * phi + Ub[b] - v2 - 2.0 * (wb * wb).sum() + 4.0 * (v * wb).sum()
+                              + 1.5 * ((db * wb).sum() / rho[b]) ** 2 + 0.5 * (db * gb).sum())
+        a = a - mub[b] * i3 * db * brk
+        a = a + inv_c2 * mub[b] * i3 * (db * (4.0 * v - 3.0 * wb)).sum() * (v - wb)
+        a = a + 3.5 * inv_c2 * mub[b] * gb / rho[b]
+    return a
+
+
+def accel_eih_jac_t(y, t, model, h=1e-30):
+    """da/d(r, v) (3 x 6) of the relativistic acceleration at state y and time t, by the
+    complex step: column k is Im a(y + i h e_k) / h, exact to rounding (the indirect term
+    does not depend on the state)."""
+    bodies = _eih_major_bodies(t, model)
+    y = _f64(y).reshape(6)
+    J = np.zeros((3, 6))
+    for k in range(6):
+        yc = y.astype(np.complex128)
+        yc[k] += 1j * h
+        J[:, k] = _eih_accel_np(yc, *bodies, model.inv_c2).imag / h
+    return J
+
+
 def adjoint(ics, t0, tf, nodes, segments, tol, model=None, gbar_final=None, gbar_nodes=None, *,
             init=0, tol_mode=0, max_iter=64):
     """Gradient dL/dy0 [n, 6] of a loss L(y_final, node states) through the converged
@@ -353,14 +410,13 @@ def adjoint(ics, t0, tf, nodes, segments, tol, model=None, gbar_final=None, gbar
     (Sec. 2.2 with the fit/integrate/evaluate steps as the linear map K, obtained here by
     applying the oracle's update to unit vectors).  With J_j = w2 df/dy at node j, the
     adjoint mu solves (I - K J)^T mu = gbar (a dense 6N x 6N solve, numpy), and
-    dL/dy0 = sum_j mu_j.  Segments are chained backwards: the end node of segment s-1 is
-    the initial state of segment s, so its seed is the gradient of segment s.
+    dL/dy0 = sum_j mu_j.  With the relativistic model J_j also has the velocity block
+    w2 da/dv (accel_eih_jac_t).  Segments are chained backwards: the end node of segment
+    s-1 is the initial state of segment s, so its seed is the gradient of segment s.
 
     gbar_final [n, 6] = dL/dy_final; gbar_nodes [n, S, N, 6] = dL/dY (optional).
     """
     model = model or Model()
-    if model.inv_c2:
-        raise ValueError("the adjoint is written for the point-mass model")
     ics = _f64(ics).reshape(-1, 6)
     n = ics.shape[0]
     S, N = int(segments), int(nodes)
@@ -381,9 +437,11 @@ def adjoint(ics, t0, tf, nodes, segments, tol, model=None, gbar_final=None, gbar
             w1, w2 = 0.5 * (Te + Ts), 0.5 * (Te - Ts)
             Jb = np.zeros((N, 6, 6))
             for j in range(N):
-                A = accel_jac_t(Ys[m, s, j, :3], w2 * tau[j] + w1, model)
                 Jb[j, :3, 3:] = w2 * np.eye(3)
-                Jb[j, 3:, :3] = w2 * A
+                if model.inv_c2:   # the relativistic force depends on the velocity too
+                    Jb[j, 3:, :] = w2 * accel_eih_jac_t(Ys[m, s, j], w2 * tau[j] + w1, model)
+                else:
+                    Jb[j, 3:, :3] = w2 * accel_jac_t(Ys[m, s, j, :3], w2 * tau[j] + w1, model)
             # M[(j,a),(l,b)] = delta - K[j,l] J_l[a,b]
             M = np.eye(6 * N) - np.einsum("jl,lab->jalb", K, Jb).reshape(6 * N, 6 * N)
             gb = np.zeros((N, 6))

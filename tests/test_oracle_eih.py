@@ -8,7 +8,9 @@ integration of the same equations (the Picard-Chebyshev iteration with a velocit
 dependent force), and the Lorentz boost of a resting mass (a mass in uniform motion, which
 checks the terms in the perturbers' velocities), and the Euler-Lagrange equations of the
 first post-Newtonian Lagrangian solved numerically (which pins every term, the perturbers'
-accelerations and potentials included, up to O(1/c^4))."""
+accelerations and potentials included, up to O(1/c^4)).  The adjoint's derivatives of the
+same sums (the complex step on a numpy restatement) are pinned to the C function, to its
+central differences and, through the adjoint, to finite differences of propagations."""
 import numpy as np
 import pytest
 
@@ -133,14 +135,67 @@ def test_picard_chebyshev_with_eih_matches_small_step_rk4():
     assert np.linalg.norm(st0[0, :3] - st[0, :3]) / np.linalg.norm(st[0, :3]) > 1e-6
 
 
-def test_eih_refused_by_group_mode_and_adjoint():
+def test_eih_refused_by_group_mode():
     w = W.nbody_venus(2, days=20.0, segments=1, nodes=16)
     m = oracle.Model(1.0, w.pert, 0.0, inv_c2=1e-8)
     g = w.groups[0]
     with pytest.raises(ValueError):
         oracle.propagate(w.ics, g.t0, g.tf, g.nodes, g.segments, 1e-12, m, conv=1)
-    with pytest.raises(ValueError):
-        oracle.adjoint(w.ics, g.t0, g.tf, g.nodes, g.segments, 1e-12, m, gbar_final=np.ones((2, 6)))
+
+
+# -- the relativistic adjoint ------------------------------------------------------------
+# The adjoint needs da/dr and da/dv of the relativistic force.  The oracle takes them by
+# the complex step on a numpy restatement of the sums; the restatement is pinned to the C
+# function, the derivatives to central differences of the C function, and the adjoint
+# built on them to finite differences of whole propagations.
+
+@pytest.mark.parametrize("inv_c2", [1e-3, 1.0 / W.C_AU_TU ** 2])
+def test_numpy_restatement_matches_the_c_sums(inv_c2):
+    pert = W.planet_elements()
+    m = oracle.Model(1.0, pert, 0.0, inv_c2=inv_c2)
+    for i, y in enumerate(_states(12, 4)):
+        t = 0.53 * i
+        bodies = oracle._eih_major_bodies(t, m)
+        a_np = oracle._eih_accel_np(y, *bodies, inv_c2)
+        ind = sum(p[0] * oracle.ephem(p, 0.0, t) / np.linalg.norm(oracle.ephem(p, 0.0, t)) ** 3 for p in pert)
+        a_c = oracle.accel_eih_t(y, t, m)
+        assert np.abs(a_np - ind - a_c).max() <= 1e-14 * np.abs(a_c).max()
+
+
+def test_relativistic_jacobian_matches_central_differences():
+    pert = W.planet_elements()
+    m = oracle.Model(1.0, pert, 0.0, inv_c2=1e-3)   # exaggerated: the velocity block is O(1/c^2)
+    for i, y in enumerate(_states(6, 5)):
+        t = 0.71 * i
+        J = oracle.accel_eih_jac_t(y, t, m)
+        h = 1e-6
+        fd = np.stack([(oracle.accel_eih_t(y + h * e, t, m) - oracle.accel_eih_t(y - h * e, t, m)) / (2 * h)
+                       for e in np.eye(6)], axis=1)
+        np.testing.assert_allclose(J, fd, rtol=0, atol=2e-8 * np.abs(J).max())
+        assert np.abs(J[:, 3:]).max() > 1e-4 * np.abs(J[:, :3]).max()      # da/dv is there
+        assert np.abs(J[:, :3] - J[:, :3].T).max() > 1e-9 * np.abs(J).max()  # and da/dr is not symmetric
+
+
+@pytest.mark.parametrize("inv_c2", [1e-3, 1e-4])
+def test_relativistic_adjoint_matches_finite_differences(inv_c2):
+    # finite differences of the map iterated to a fixed number of sweeps, against the
+    # implicit derivative at the converged point; the point-mass adjoint misses them
+    w = W.nbody_venus(2, days=112.5, segments=2, nodes=48, tol=1e-13)
+    g = w.groups[0]
+    m = oracle.Model(1.0, w.pert, 0.0, inv_c2=inv_c2)
+    gbar = np.random.default_rng(11).standard_normal((2, 6))
+    gr = oracle.adjoint(w.ics, g.t0, g.tf, g.nodes, g.segments, g.tol, m, gbar)
+    h = 1e-6
+    fd = np.zeros((2, 6))
+    for k in range(6):
+        e = np.zeros(6)
+        e[k] = h
+        sp, _ = oracle.propagate(w.ics + e, g.t0, g.tf, g.nodes, g.segments, g.tol, m, fixed_iters=40)
+        sm, _ = oracle.propagate(w.ics - e, g.t0, g.tf, g.nodes, g.segments, g.tol, m, fixed_iters=40)
+        fd[:, k] = ((sp - sm) * gbar).sum(axis=1) / (2 * h)
+    np.testing.assert_allclose(gr, fd, rtol=0, atol=1e-8 * np.abs(fd).max())
+    pm = oracle.adjoint(w.ics, g.t0, g.tf, g.nodes, g.segments, g.tol, oracle.Model(1.0, w.pert, 0.0), gbar)
+    assert np.abs(pm - fd).max() > 100 * 1e-8 * np.abs(fd).max()
 
 
 # -- the first post-Newtonian Lagrangian ---------------------------------------------------
