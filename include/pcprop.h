@@ -68,8 +68,8 @@ typedef void* pc_stream_t;        /* a hipStream_t */
  * accelerations and potentials of the major bodies (the central body at rest at the
  * origin, the perturbers on their orbits, differentiated in time), all evaluated once per
  * node before the iterations; the Newtonian indirect term is kept, so inv_c2 = 0 is the
- * point-mass model.  It runs with the per-IC stopping rule, forward only (fused and plain
- * paths); other calls with inv_c2 > 0 return PC_EINVAL.  Under PC_FP32_THEN_FP64 the
+ * point-mass model.  It runs with the per-IC stopping rule, forward (fused and plain
+ * paths) and in pc_adjoint; other calls with inv_c2 > 0 return PC_EINVAL.  Under PC_FP32_THEN_FP64 the
  * FP64 sweeps evaluate this acceleration and the increment sweeps linearise with the
  * point-mass gravity gradient (the relativistic terms change it by O(1/c^2), which only
  * perturbs the linearisation the FP64 sweeps correct). */
@@ -294,8 +294,10 @@ int pc_propagate_batched_noalloc(pc_ctx* ctx, const double* ics, int64_t n_ic,
  * the propagated gradient changes by less than adj_tol (relative).  Segments are taken
  * from the last: each is re-solved from its checkpoint with the forward code (or, when
  * fwd_nodes is given, its converged node states are read from there), then its gradient
- * seeds the end node of the previous one.  Fused FP64 path, point masses, any node count
- * (3 .. 256).
+ * seeds the end node of the previous one.  Fused FP64 path, any node count (3 .. 256).
+ * With the relativistic model (inv_c2 > 0) the acceleration also depends on the velocity,
+ * so J^T w = ((da/dr)^T w_v, w_r + (da/dv)^T w_v), both products evaluated exactly at
+ * each node (the major bodies' states are the call's own, re-evaluated as forward).
  *   groups, model, opts  as in the forward pc_propagate_batched call
  *   ckpt        device [n_ic][ckpt_stride + 1][6] segment-boundary states of the forward call
  *               (its bounds_out); ckpt_stride >= every group's segment count

@@ -1623,8 +1623,6 @@ int pc_adjoint(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int32_t n_grou
     int rc = validate_model(ctx, model);
     if (rc != PC_OK) return rc;
     pc_opts o = opts ? *opts : defaults();
-    if (model->inv_c2 > 0.0)
-        return set_error(ctx, PC_EINVAL, "the adjoint is written for the point-mass model");
     if (o.path != PC_PATH_FUSED || o.precision != PC_FP64)
         return set_error(ctx, PC_EINVAL, "the adjoint re-solves segments on the fused FP64 path");
     if (o.conv != PC_CONV_PER_IC)
@@ -1662,6 +1660,9 @@ int pc_adjoint(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int32_t n_grou
     ep.n_pert = model->n_pert;
     ep.epoch = model->epoch;
     ep.recs = reinterpret_cast<double*>(ws + plan.off_recs);
+    const bool eih = model->inv_c2 > 0.0;
+    ep.recs_eih = eih ? reinterpret_cast<double*>(ws + plan.off_recs_eih) : nullptr;
+    ep.mu_sun = model->mu_sun;
 
     PcAdjParams a{};
     a.fwd.groups = ep.groups;
@@ -1670,6 +1671,8 @@ int pc_adjoint(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int32_t n_grou
     a.fwd.n_pert = model->n_pert;
     a.fwd.recs = ep.recs;
     a.fwd.mu_sun = model->mu_sun;
+    a.fwd.recs_eih = ep.recs_eih;
+    a.fwd.inv_c2 = eih ? model->inv_c2 : 0.0;
     a.fwd.max_iter = o.max_iter;
     a.fwd.fixed_iters = o.fixed_iters;
     a.fwd.tol_mode = o.tol_mode;

@@ -1478,6 +1478,88 @@ static __device__ __forceinline__ void pc_force_eih(const double (&x)[R], const 
     }
 }
 
+// Vector-Jacobian product of the relativistic acceleration of pc_force_eih at R points:
+// with s = u . a, gr = ds/dr = (da/dr)^T u and gv = ds/dv = (da/dv)^T u (the adjoint's
+// J^T w with u = w_v).  Per body, with d, rho, m3 = mu/rho^3, m5 = 3 mu/rho^5,
+// S = U_b - v^2 - 2 v_b^2 + 4 v.v_b + 3/2 (d.v_b/rho)^2 + 1/2 d.a_b, q = 4 v - 3 v_b and
+// e = 1/c^2:
+//   gv += e m3 [-(u.d)(2 v - 4 v_b) + (d.q) u + 4 (u.(v - v_b)) d]
+//   gr += (1 - e S) (m5 (u.d) d - m3 u) + e m3 (u.d) dS/dr
+//         + e (u.(v - v_b)) (m3 q - m5 (d.q) d) - 7/2 e (u.a_b) m3 d,
+//   dS/dr = 3 (d.v_b/rho) (v_b - (d.v_b/rho) d/rho)/rho + a_b/2,
+// and the terms through Phi = sum_b mu_b/rho_b, whose gradient is -N with
+// N = sum_b m3 d: gr += -4 e Phi H - 4 e (u.N) N, H = sum_b (m5 (u.d) d - m3 u).  At
+// e = 0 this is the point-mass Hessian product (symmetric in r).  The indirect term does
+// not depend on the state.  Records and node indices as pc_force_eih.
+template <int R, bool ONE_NODE>
+static __device__ __forceinline__ void pc_eih_vjp(const double (&x)[R], const double (&y)[R],
+                                                  const double (&z)[R], const double (&vx)[R],
+                                                  const double (&vy)[R], const double (&vz)[R],
+                                                  const double (&ux)[R], const double (&uy)[R],
+                                                  const double (&uz)[R], const double4* __restrict__ e,
+                                                  const int (&jr)[R], int ns, int P, double inv_c2,
+                                                  double (&grx)[R], double (&gry)[R], double (&grz)[R],
+                                                  double (&gvx)[R], double (&gvy)[R], double (&gvz)[R])
+{
+    auto rec = [&](int k, int r) -> double4 { return e[(size_t)k * ns + jr[ONE_NODE ? 0 : r]]; };
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        double phi = 0.0, v2 = vx[r] * vx[r] + vy[r] * vy[r] + vz[r] * vz[r];
+        double nx = 0.0, ny = 0.0, nz = 0.0, hx = 0.0, hy = 0.0, hz = 0.0;
+        double ax = 0.0, ay = 0.0, az = 0.0, bx = 0.0, by = 0.0, bz = 0.0;
+        for (int b = 0; b <= P; ++b) {
+            const double4 q = rec(3 * b, r), w = rec(3 * b + 1, r), g = rec(3 * b + 2, r);
+            const double mu = w.w;
+            const double dx = x[r] - q.x, dy = y[r] - q.y, dz = z[r] - q.z;
+            const double i1 = pc_rsqrt_full(dx * dx + dy * dy + dz * dz);
+            const double m1 = mu * i1, m3 = m1 * i1 * i1, m5 = 3.0 * m3 * i1 * i1;
+            phi += m1;
+            nx = fma(m3, dx, nx);
+            ny = fma(m3, dy, ny);
+            nz = fma(m3, dz, nz);
+            const double ud = ux[r] * dx + uy[r] * dy + uz[r] * dz;
+            // Newtonian part of the bracket, kept apart for the term in Phi
+            const double tx = m5 * ud * dx - m3 * ux[r], ty = m5 * ud * dy - m3 * uy[r], tz = m5 * ud * dz - m3 * uz[r];
+            hx += tx;
+            hy += ty;
+            hz += tz;
+            const double wb2 = w.x * w.x + w.y * w.y + w.z * w.z;
+            const double vbv = vx[r] * w.x + vy[r] * w.y + vz[r] * w.z;
+            const double dvb = (dx * w.x + dy * w.y + dz * w.z) * i1;
+            const double dab = dx * g.x + dy * g.y + dz * g.z;
+            const double S = q.w - v2 - 2.0 * wb2 + 4.0 * vbv + 1.5 * dvb * dvb + 0.5 * dab;
+            const double dq = dx * (4.0 * vx[r] - 3.0 * w.x) + dy * (4.0 * vy[r] - 3.0 * w.y) +
+                              dz * (4.0 * vz[r] - 3.0 * w.z);
+            const double uvw = ux[r] * (vx[r] - w.x) + uy[r] * (vy[r] - w.y) + uz[r] * (vz[r] - w.z);
+            const double ug = ux[r] * g.x + uy[r] * g.y + uz[r] * g.z;
+            // dS/dr
+            const double c1 = 3.0 * dvb * i1, c2 = c1 * dvb * i1;
+            const double sx = c1 * w.x - c2 * dx + 0.5 * g.x;
+            const double sy = c1 * w.y - c2 * dy + 0.5 * g.y;
+            const double sz = c1 * w.z - c2 * dz + 0.5 * g.z;
+            const double k0 = -S;                       // times e, on the Newtonian bracket
+            const double k1 = m3 * ud;                  // times e, on dS/dr
+            const double k2 = uvw;                      // times e, on m3 q - m5 (d.q) d
+            const double k3 = -3.5 * ug * m3;           // times e, on d
+            ax += k0 * tx + k1 * sx + k2 * (m3 * (4.0 * vx[r] - 3.0 * w.x) - m5 * dq * dx) + k3 * dx;
+            ay += k0 * ty + k1 * sy + k2 * (m3 * (4.0 * vy[r] - 3.0 * w.y) - m5 * dq * dy) + k3 * dy;
+            az += k0 * tz + k1 * sz + k2 * (m3 * (4.0 * vz[r] - 3.0 * w.z) - m5 * dq * dz) + k3 * dz;
+            // velocity gradient
+            bx += m3 * (-ud * (2.0 * vx[r] - 4.0 * w.x) + dq * ux[r] + 4.0 * uvw * dx);
+            by += m3 * (-ud * (2.0 * vy[r] - 4.0 * w.y) + dq * uy[r] + 4.0 * uvw * dy);
+            bz += m3 * (-ud * (2.0 * vz[r] - 4.0 * w.z) + dq * uz[r] + 4.0 * uvw * dz);
+        }
+        const double un = ux[r] * nx + uy[r] * ny + uz[r] * nz;
+        const double fp = -4.0 * inv_c2 * phi, fn = -4.0 * inv_c2 * un;
+        grx[r] = hx + inv_c2 * ax + fp * hx + fn * nx;
+        gry[r] = hy + inv_c2 * ay + fp * hy + fn * ny;
+        grz[r] = hz + inv_c2 * az + fp * hz + fn * nz;
+        gvx[r] = inv_c2 * bx;
+        gvy[r] = inv_c2 * by;
+        gvz[r] = inv_c2 * bz;
+    }
+}
+
 // Publish F = (v, a) with the relativistic acceleration.  erec: the segment's records,
 // pc_eih_rec(P) slots of N double4.  WIDE shapes: a lane's four points share node j.
 // 8-column shapes: as in pc_publish, lane pairs (l, l ^ 8) hold the points of one IC (the

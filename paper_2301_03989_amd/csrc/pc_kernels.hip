@@ -966,7 +966,9 @@ int pc_launch_fused(const PcParams& p, const PcParams* p_dev, int pairs, int gri
 // nodes) hold the node-row layout of the forward product (a lane pair (l, l ^ 8) shares the
 // components of one IC), and their lanes exchange what the Hessian product and the
 // velocity rows need with their partner.
-template <int PAIRS, int NP>
+// EIH: the relativistic dynamics, whose force also depends on the velocity: J^T w is
+// ((da/dr)^T w_v, w_r + (da/dv)^T w_v) (pc_eih_vjp) instead of (H w_v, w_r).
+template <int PAIRS, int NP, bool EIH = false>
 __device__ __attribute__((noinline)) void pc_adjoint_job(const PcAdjParams& a, const PcJobDev& job,
                                                          const PcGroupDev& g)
 {
@@ -1013,8 +1015,11 @@ __device__ __attribute__((noinline)) void pc_adjoint_job(const PcAdjParams& a, c
         __syncthreads();
         const double4* grec = reinterpret_cast<const double4*>(p.recs) +
                               (size_t)(g.rec_offset + (int64_t)s * N) * (P + 1);
+        const double4* erec = nullptr;
+        if constexpr (EIH)
+            erec = reinterpret_cast<const double4*>(p.recs_eih) + (size_t)(g.rec_offset + (int64_t)s * N) * pc_eih_rec(P);
         if (a.fwd_nodes) {
-            if (rec_lds) pc_stage_records<PAIRS>(grec, N, P, sm);
+            if (!EIH && rec_lds) pc_stage_records<PAIRS>(grec, N, P, sm);
 #pragma unroll
             for (int h = 0; h < Sh::H; ++h) {
 #pragma unroll
@@ -1041,7 +1046,8 @@ __device__ __attribute__((noinline)) void pc_adjoint_job(const PcAdjParams& a, c
                 }
             }
         } else {
-            pc_segment_solve<PAIRS, NP>(p, g, n, job.ic0, s, sm, L, kp0, yc, nullptr, had_notconv, REC_CAP);
+            pc_segment_solve<PAIRS, NP, false, EIH>(p, g, n, job.ic0, s, sm, L, kp0, yc, nullptr, had_notconv,
+                                                    REC_CAP);
         }
         __syncthreads();
         const double Ts = g.t0 + g.h * s, Te = g.t0 + g.h * (s + 1);
@@ -1106,7 +1112,11 @@ __device__ __attribute__((noinline)) void pc_adjoint_job(const PcAdjParams& a, c
                     wy[r] = acc[4][r];
                     wz[r] = acc[5][r];
                 }
-                if (rec_lds)
+                double gx[4] = {}, gy[4] = {}, gz[4] = {};   // (da/dv)^T w_v (relativistic)
+                if constexpr (EIH)
+                    pc_eih_vjp<4, true>(yc[0], yc[1], yc[2], yc[3], yc[4], yc[5], wx, wy, wz, erec, jr, N, P, p.inv_c2,
+                                        hx, hy, hz, gx, gy, gz);
+                else if (rec_lds)
                     pc_hess_apply<4, true>(yc[0], yc[1], yc[2], wx, wy, wz, jr, P, p.mu_sun, sm.Rec, sm.Mu, grec,
                                            hx, hy, hz);
                 else
@@ -1117,9 +1127,9 @@ __device__ __attribute__((noinline)) void pc_adjoint_job(const PcAdjParams& a, c
                 const bool node_ok = pc_node(L, 0, 0) < N;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const double nv0 = seed(3, r) + w2 * acc[0][r];
-                    const double nv1 = seed(4, r) + w2 * acc[1][r];
-                    const double nv2 = seed(5, r) + w2 * acc[2][r];
+                    const double nv0 = seed(3, r) + w2 * (acc[0][r] + gx[r]);
+                    const double nv1 = seed(4, r) + w2 * (acc[1][r] + gy[r]);
+                    const double nv2 = seed(5, r) + w2 * (acc[2][r] + gz[r]);
                     acc[0][r] = seed(0, r) + w2 * hx[r];
                     acc[1][r] = seed(1, r) + w2 * hy[r];
                     acc[2][r] = seed(2, r) + w2 * hz[r];
@@ -1153,12 +1163,28 @@ __device__ __attribute__((noinline)) void pc_adjoint_job(const PcAdjParams& a, c
                     wys[r] = hi ? e3 : acc[2][r];
                     wzs[r] = hi ? acc[5][r] : e3;
                 }
-                if (rec_lds)
+                // relativistic: (da/dv)^T w_v at the same points, which also need the velocity
+                // (lo: vy(0) held, vx(0) and vz(0) from hi; hi: vx(1), vz(1) held, vy(1) from lo)
+                double gvx[4] = {}, gvy[4] = {}, gvz[4] = {};
+                if constexpr (EIH) {
+                    double vxs[4], vys[4], vzs[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const double e4 = pc_dpp<0x128>(hi ? yc[1][r] : yc[5][r]);   // lo: vx(0); hi: vy(1)
+                        const double e5 = pc_dpp<0x128>(yc[2][r]);                   // lo: vz(0)
+                        vxs[r] = hi ? yc[4][r] : e4;
+                        vys[r] = hi ? e4 : yc[2][r];
+                        vzs[r] = hi ? yc[5][r] : e5;
+                    }
+                    pc_eih_vjp<4, false>(xs, ys, zs, vxs, vys, vzs, wxs, wys, wzs, erec, jr, N, P, p.inv_c2, hx, hy,
+                                         hz, gvx, gvy, gvz);
+                } else if (rec_lds) {
                     pc_hess_apply<4, true>(xs, ys, zs, wxs, wys, wzs, jr, P, p.mu_sun, sm.Rec, sm.Mu, grec, hx, hy,
                                            hz);
-                else
+                } else {
                     pc_hess_apply<4, false>(xs, ys, zs, wxs, wys, wzs, jr, P, p.mu_sun, sm.Rec, sm.Mu, grec, hx, hy,
                                             hz);
+                }
                 // mu_new = gbar + J^T w: position rows (comp c < 3) take w2 (H w_v)_c of their
                 // point, from the lane that formed it; velocity rows (comp c >= 3) take
                 // w2 w_(c-3), which the partner lane holds
@@ -1167,6 +1193,13 @@ __device__ __attribute__((noinline)) void pc_adjoint_job(const PcAdjParams& a, c
                 for (int r = 0; r < 4; ++r) {
                     const double f1 = pc_dpp<0x128>(hi ? hx[r] : hy[r]);   // lo: hx(1); hi: hy(0)
                     const double f2 = pc_dpp<0x128>(hz[r]);                // lo: hz(1)
+                    // relativistic velocity terms, on the lane that holds the row: comp 3
+                    // (hi) gvx, comp 4 (lo) gvy, comp 5 (hi) gvz of each strip
+                    double f3 = 0.0, f4 = 0.0;
+                    if constexpr (EIH) {
+                        f3 = pc_dpp<0x128>(hi ? gvy[r] : gvx[r]);   // lo: gvy(1); hi: gvx(0)
+                        f4 = pc_dpp<0x128>(gvz[r]);                 // hi: gvz(0)
+                    }
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
                         const double g = pc_dpp<0x128>(acc[3 * h][r]);      // lo: w1(h); hi: w0(h)
@@ -1174,9 +1207,11 @@ __device__ __attribute__((noinline)) void pc_adjoint_job(const PcAdjParams& a, c
                         const int j = pc_node(L, h, r);
                         const double hc0 = h == 0 ? (hi ? f1 : hx[r]) : (hi ? hy[r] : f1);   // comp hi
                         const double hc2 = h == 0 ? hz[r] : f2;                              // comp 2 (lo)
+                        const double gv1 = h == 0 ? f3 : gvx[r];                             // comp 3 (hi)
+                        const double gv2 = hi ? (h == 0 ? f4 : gvz[r]) : (h == 0 ? gvy[r] : f3);   // comp 4 + hi
                         const double n0 = seed_at(hi, j, m) + w2 * hc0;
-                        const double n1 = seed_at(2 + hi, j, m) + w2 * (hi ? g : hc2);
-                        const double n2 = seed_at(4 + hi, j, m) + w2 * (hi ? k : g);
+                        const double n1 = seed_at(2 + hi, j, m) + w2 * (hi ? g + gv1 : hc2);
+                        const double n2 = seed_at(4 + hi, j, m) + w2 * ((hi ? k : g) + gv2);
                         acc[3 * h][r] = n0;
                         acc[3 * h + 1][r] = n1;
                         acc[3 * h + 2][r] = n2;
@@ -1289,12 +1324,13 @@ __global__ __launch_bounds__(PAIRS / 4) void pc_adjoint_kernel(const PcAdjParams
         if (jb >= a.fwd.n_jobs) break;
         const PcJobDev job = a.fwd.jobs[jb];
         const PcGroupDev g = a.fwd.groups[job.group];
+        const bool eih = a.fwd.inv_c2 != 0.0;
         switch (g.NP) {
-        case 16: pc_adjoint_job<PAIRS, 16>(a, job, g); break;
-        case 32: pc_adjoint_job<PAIRS, 32>(a, job, g); break;
-        case 64: pc_adjoint_job<PAIRS, 64>(a, job, g); break;
-        case 128: pc_adjoint_job<PAIRS, 128>(a, job, g); break;
-        case 256: pc_adjoint_job<PAIRS, 256>(a, job, g); break;
+        case 16: eih ? pc_adjoint_job<PAIRS, 16, true>(a, job, g) : pc_adjoint_job<PAIRS, 16>(a, job, g); break;
+        case 32: eih ? pc_adjoint_job<PAIRS, 32, true>(a, job, g) : pc_adjoint_job<PAIRS, 32>(a, job, g); break;
+        case 64: eih ? pc_adjoint_job<PAIRS, 64, true>(a, job, g) : pc_adjoint_job<PAIRS, 64>(a, job, g); break;
+        case 128: eih ? pc_adjoint_job<PAIRS, 128, true>(a, job, g) : pc_adjoint_job<PAIRS, 128>(a, job, g); break;
+        case 256: eih ? pc_adjoint_job<PAIRS, 256, true>(a, job, g) : pc_adjoint_job<PAIRS, 256>(a, job, g); break;
         default: break;
         }
     }

@@ -209,10 +209,9 @@ def test_adjoint_argument_errors(pc):
     w = W.nbody_venus(4, nodes=64, days=30.0, segments=1)
     ics, groups, model, om, g = _setup(w)
     fwd = pc.propagate_batched(ics, groups, model, want_bounds=True)
-    # the adjoint is written for the point-mass model
-    eih = pcprop.Model(w.mu_sun, w.pert, w.epoch, 1e-8)
+    # the adjoint linearises the first-order map: order 2 is refused
     with pytest.raises(pcprop.PcError):
-        pc.adjoint(fwd["bounds"], torch.zeros((4, 6), dtype=torch.float64, device="cuda"), groups, eih)
+        pc.adjoint(fwd["bounds"], torch.zeros((4, 6), dtype=torch.float64, device="cuda"), groups, model, order=2)
     # the adjoint linearises the map converged per IC: the group-max rule is refused
     w = W.nbody_venus(4, days=30.0, segments=1)
     ics, groups, model, om, g = _setup(w)
@@ -308,6 +307,68 @@ def test_adjoint_node_row_jobs_stored_nodes_and_node_seeds(pc):
     a, it_a, st_a = pc.adjoint(fwd["bounds"], torch.tensor(gbar, device="cuda"), groups, model,
                                gbar_nodes=gnt, fwd_nodes=fwd["nodes"])
     b, it_b, st_b = pc.adjoint(fwd["bounds"], torch.tensor(gbar, device="cuda"), groups, model, gbar_nodes=gnt)
+    assert st_a == 0 and st_b == 0
+    ref = oracle.adjoint(w.ics, g.t0, g.tf, g.nodes, g.segments, g.tol, om, gbar, gn)
+    assert _gerr(a.cpu().numpy(), ref).max() < GTOL
+    assert _gerr(b.cpu().numpy(), ref).max() < GTOL
+    assert _gerr(a.cpu().numpy(), b.cpu().numpy()).max() < 1e-12
+
+
+# -- the relativistic dynamics ------------------------------------------------------------
+# The Einstein-Infeld-Hoffmann acceleration depends on the velocity: J^T w gains the
+# velocity rows' (da/dv)^T w_v and the position rows take (da/dr)^T w_v of the full
+# acceleration.  The oracle forms both by the complex step on its own restatement of the
+# sums (pinned to finite differences of propagations in the CPU suite).  With the
+# exaggerated 1/c^2 the point-mass derivative misses the gradient by far more than the
+# bar, so a dropped or wrong relativistic term fails; the physical 1/c^2 checks the
+# workload's own scale.
+
+def _eih_setup(n, nodes, inv_c2, seed, days=40.0, segments=2):
+    from paper_2301_03989_amd import pcprop
+    w = W.nbody_venus(n, seed=seed, days=days, segments=segments, nodes=nodes, tol=1e-13)
+    g = w.groups[0]
+    ics = torch.tensor(w.ics, dtype=torch.float64, device="cuda")
+    groups = [pcprop.Group(0, w.n_ic, g.t0, g.tf, g.nodes, g.segments, g.tol)]
+    return (w, ics, groups, pcprop.Model(1.0, w.pert, 0.0, inv_c2), oracle.Model(1.0, w.pert, 0.0, inv_c2=inv_c2),
+            g)
+
+
+@pytest.mark.parametrize("inv_c2", [1e-4, 1.0 / W.C_AU_TU ** 2])
+@pytest.mark.parametrize("nodes", [24, 100, 256])
+def test_relativistic_adjoint_matches_oracle(pc, nodes, inv_c2):
+    """Transposed jobs (24, 100 nodes) and 8-IC node-row jobs (256 nodes, lane pairs
+    exchanging positions, velocities and the products), with a ragged IC count."""
+    w, ics, groups, model, om, g = _eih_setup(9, nodes, inv_c2, seed=130 + nodes)
+    print(f"relativistic adjoint: N {nodes} inv_c2 {inv_c2:.3e}", flush=True)
+    fwd = pc.propagate_batched(ics, groups, model, want_bounds=True)
+    assert fwd["status"] == 0
+    gbar = np.random.default_rng(nodes).standard_normal((w.n_ic, 6))
+    grad, adj_it, st = pc.adjoint(fwd["bounds"], torch.tensor(gbar, device="cuda"), groups, model)
+    assert st == 0 and (adj_it.cpu().numpy()[:, :g.segments] > 1).all()
+    ref = oracle.adjoint(w.ics, g.t0, g.tf, g.nodes, g.segments, g.tol, om, gbar)
+    gr = grad.cpu().numpy()
+    assert _gerr(gr, ref).max() < GTOL
+    if inv_c2 > 1e-6:
+        pm = oracle.adjoint(w.ics, g.t0, g.tf, g.nodes, g.segments, g.tol, oracle.Model(1.0, w.pert, 0.0), gbar)
+        assert _gerr(gr, pm).min() > 100 * GTOL
+
+
+@pytest.mark.parametrize("nodes", [64, 256])
+def test_relativistic_adjoint_stored_nodes_and_node_seeds(pc, nodes):
+    """From the forward's stored node states and from re-solves, with seeds on interior
+    nodes and the last one, three segments, against the oracle."""
+    w, ics, groups, model, om, g = _eih_setup(10, nodes, 1e-4, seed=140 + nodes, days=60.0, segments=3)
+    fwd = pc.propagate_batched(ics, groups, model, want_bounds=True, want_nodes=True)
+    assert fwd["status"] == 0
+    rng = np.random.default_rng(nodes + 1)
+    gbar = rng.standard_normal((w.n_ic, 6))
+    gn = np.zeros((w.n_ic, 3, nodes, 6))
+    for j in (3, nodes // 2 + 1, nodes - 1):
+        gn[:, rng.integers(0, 3), j] = rng.standard_normal((w.n_ic, 6))
+    gnt = torch.tensor(gn, device="cuda")
+    a, _, st_a = pc.adjoint(fwd["bounds"], torch.tensor(gbar, device="cuda"), groups, model, gbar_nodes=gnt,
+                            fwd_nodes=fwd["nodes"])
+    b, _, st_b = pc.adjoint(fwd["bounds"], torch.tensor(gbar, device="cuda"), groups, model, gbar_nodes=gnt)
     assert st_a == 0 and st_b == 0
     ref = oracle.adjoint(w.ics, g.t0, g.tf, g.nodes, g.segments, g.tol, om, gbar, gn)
     assert _gerr(a.cpu().numpy(), ref).max() < GTOL

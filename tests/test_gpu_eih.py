@@ -128,10 +128,8 @@ def test_eih_refused_where_not_supported(pc):
     ics = torch.tensor(w.ics, dtype=torch.float64, device="cuda")
     g = w.groups[0]
     groups = [pcprop.Group(g.ic_offset, g.n_ic, g.t0, g.tf, g.nodes, g.segments, g.tol)]
-    with pytest.raises(pcprop.PcError):
-        pc.adjoint(torch.zeros((8, g.segments + 1, 6), dtype=torch.float64, device="cuda") + ics[:, None, :],
-                   torch.ones((8, 6), dtype=torch.float64, device="cuda"), groups,
-                   pcprop.Model(1.0, w.pert, 0.0, 1e-8))
+    with pytest.raises(pcprop.PcError):   # order 2 is refused with the relativistic model
+        pc.propagate_batched(ics, groups, pcprop.Model(1.0, w.pert, 0.0, 1e-8), order=2)
 
 
 def test_eih_graph_replay_and_model_switch(pc):
