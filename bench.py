@@ -102,14 +102,20 @@ def adjoint_flops(w, iters, adj_iters, resolve=True):
     (as algorithmic_flops; not when the forward's node states are read instead) plus, per
     adjoint sweep, the transposed product (6 columns x 2 N^2) and the Hessian-vector
     products H w_v at N nodes (30 flops per body: offset, distance powers, the projection
-    d (d.w) and the accumulation) and the 12 flops that form mu_new."""
+    d (d.w) and the accumulation) and the 12 flops that form mu_new.  With the
+    Einstein-Infeld-Hoffmann model the products are (da/dr)^T w_v and (da/dv)^T w_v: 190
+    flops per body (offset and distance powers, the potential and Newtonian sums, the
+    scalar products and factors of the relativistic bracket, its derivative in r, and the
+    two accumulations) and 34 per point (v^2, u.N and the combination of the sums)."""
     P = w.pert.shape[0]
+    eih = getattr(w, "inv_c2", 0.0) > 0.0
     total = algorithmic_flops(w, iters) if resolve else 0.0
     for g in w.groups:
         it = adj_iters[g.ic_offset:g.ic_offset + g.n_ic, :g.segments]
         it = np.where(it > 0, it, 0).astype(np.float64)
         N = g.nodes
-        total += (12.0 * N * N + (30.0 * (P + 1) + 12.0) * N) * it.sum()
+        vjp = (190.0 * (P + 1) + 34.0) if eih else 30.0 * (P + 1)
+        total += (12.0 * N * N + (vjp + 12.0) * N) * it.sum()
     return total
 
 
@@ -323,6 +329,8 @@ def main():
     ap.add_argument("--cpu-1t-per-group", type=int, default=6,
                     help="ICs per group of the oracle's one-thread timing sample (0 skips it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="--adjoint: about this much wall time of the oracle's adjoint for the CPU baseline")
     ap.add_argument("--plain-streams", default="1,10",
                     help="stream counts of the plain path's outer level to time ('' skips the plain path)")
     ap.add_argument("--plain-steps", type=int, default=2,

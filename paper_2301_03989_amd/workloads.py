@@ -229,11 +229,15 @@ def mixed_precision(n_ic: int = 262144, seed: int = 104) -> Workload:
     return nbody_venus(n_ic, seed, precision=1, name="nbody-venus-262144-fp32-fp64")
 
 
-def adjoint_ensemble(n_ic: int = 16384, seed: int = 105, nodes: int = 128) -> Workload:
+def adjoint_ensemble(n_ic: int = 16384, seed: int = 105, nodes: int = 128, eih: bool = False) -> Workload:
     """The N-body Venus ensemble at 16384 ICs over 256 days in 5 segments, tol 1e-13
-    (128 nodes; the 256-node variant runs the adjoint's node-row jobs)."""
-    return nbody_venus(n_ic, seed, days=256.0, segments=5, tol=1e-13, nodes=nodes,
-                       name="nbody-venus-16384-256d" + ("" if nodes == 128 else f"-n{nodes}"))
+    (128 nodes; the 256-node variant runs the adjoint's node-row jobs; eih: with the
+    relativistic dynamics at the physical 1/c^2)."""
+    w = nbody_venus(n_ic, seed, days=256.0, segments=5, tol=1e-13, nodes=nodes,
+                    name="nbody-venus-16384-256d" + ("" if nodes == 128 else f"-n{nodes}") + ("-eih" if eih else ""))
+    if eih:
+        w.inv_c2 = 1.0 / (C_AU_TU * C_AU_TU)
+    return w
 
 
 # speed of light in AU per time unit (299792.458 km/s, 1 AU = 149597870.7 km)
@@ -270,6 +274,7 @@ WORKLOADS = {
     "nbody-venus-262144-fp32-fp64": mixed_precision,
     "nbody-venus-16384-256d": adjoint_ensemble,
     "nbody-venus-16384-256d-n256": lambda: adjoint_ensemble(nodes=256),
+    "nbody-venus-16384-256d-eih": lambda: adjoint_ensemble(eih=True),
     "nbody-venus-4096-eih": relativistic,
     "eccentric-16384-n64": lambda: eccentric(64),
     "eccentric-16384-n128": lambda: eccentric(128),

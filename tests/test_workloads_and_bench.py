@@ -91,6 +91,19 @@ def test_algorithmic_flops_per_iteration():
     assert bench.algorithmic_flops(w, iters) == n_it * (12 * 128 ** 2 + (96 * 9 + 15) * 128)
 
 
+def test_adjoint_flops_per_sweep():
+    w = W.nbody_venus(2, nodes=64, segments=2)
+    iters = np.array([[10, 12], [9, 0]], dtype=np.int32)
+    adj = np.array([[4, 5], [6, -1]], dtype=np.int32)
+    fwd = bench.algorithmic_flops(w, iters)
+    per = 12 * 64 ** 2 + (30 * 9 + 12) * 64
+    assert bench.adjoint_flops(w, iters, adj, resolve=False) == 15 * per
+    assert bench.adjoint_flops(w, iters, adj) == fwd + 15 * per
+    w.inv_c2 = 1e-8
+    assert bench.adjoint_flops(w, iters, adj, resolve=False) == 15 * (12 * 64 ** 2 + (190 * 9 + 34 + 12) * 64)
+    assert W.WORKLOADS["nbody-venus-16384-256d-eih"]().inv_c2 == 1.0 / W.C_AU_TU ** 2
+
+
 def test_stratified_sample_and_boundary_errors():
     w = W.uneven_batch(600, seed=4)
     idx = bench.stratified_sample(w, 5, seed=2)
