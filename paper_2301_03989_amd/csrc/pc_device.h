@@ -550,13 +550,18 @@ struct PcLane {
     int lane, wave, strip0, grp, hi;
     int wide;
     int ic_base, ic_step;   // the lane's element r belongs to IC ic_base + ic_step r of the job
+    int nq;                 // k steps the products run: the 16-node blocks that hold a node < N
 };
 
+// nq: K_N's fragments are zero in every column at or past N, so the products stop after
+// the last 16-node block holding a node (4 k steps each; at least two blocks when the
+// padded count has them, which the k loop's prologue needs)
 template <int PAIRS, int NP>
-static __device__ __forceinline__ PcLane pc_lane_geometry(int tid)
+static __device__ __forceinline__ PcLane pc_lane_geometry(int tid, int N)
 {
     using Sh = PcShape<PAIRS, NP>;
     PcLane L;
+    L.nq = Sh::NQ > 4 ? min(Sh::NQ, max(8, ((N + 15) >> 4) << 2)) : Sh::NQ;
     L.lane = tid & 63;
     L.wave = tid >> 6;
     L.strip0 = Sh::WIDE ? L.wave / Sh::G16 : 2 * L.wave;
@@ -599,7 +604,8 @@ static __device__ __forceinline__ int pc_fcol(int j, int m)
     return PcShape<PAIRS, NP>::WIDE ? (m ^ (j & 15)) : m;
 }
 
-// Software-pipelined k loop of a 16x16x4 product over NQ steps.  The A operand of step q
+// Software-pipelined k loop of a 16x16x4 product over nq steps (a multiple of 4, at most
+// NQ, at least 8 when NQ is; NQ fixes the layout of the operands).  The A operand of step q
 // (a K_N fragment, read from L2) is loaded DK steps ahead into a ring of DK registers, the
 // B operands (LDS) one step ahead into two buffers, and the loop body is unrolled DK
 // times, so both rings rotate by register renaming.  A register move out of a ring would
@@ -612,7 +618,7 @@ static __device__ __forceinline__ int pc_fcol(int j, int m)
 // their registers, and the wave then waits on each read right after issuing it).
 template <int NQ, int NB, class AT, class BT, int SG_DS = 0, int SG_MFMA = 0, int SG_VMEM = 0, class LA0,
           class LA, class LB, class MM>
-static __device__ __forceinline__ void pc_kloop(LA0 loadA0, LA loadA, LB loadB, MM mma)
+static __device__ __forceinline__ void pc_kloop(int nq, LA0 loadA0, LA loadA, LB loadB, MM mma)
 {
     constexpr int DK = 4;
     static_assert(NQ % DK == 0, "k steps must be a multiple of the A ring depth");
@@ -638,13 +644,25 @@ static __device__ __forceinline__ void pc_kloop(LA0 loadA0, LA loadA, LB loadB, 
     // accumulators directly (a zero start becomes the MFMA's inline constant instead of
     // register moves on every sweep)
     if constexpr (NQ > DK) steps(0);
+    auto rest = [&](int n) __attribute__((always_inline)) {
 #pragma unroll 1
-    for (int q0 = DK; q0 < NQ - DK; q0 += DK) steps(q0);
+        for (int q0 = DK; q0 < n - DK; q0 += DK) steps(q0);
 #pragma unroll
-    for (int u = 0; u < DK; ++u) {   // the last DK steps load nothing past the end
-        if (u + 1 < DK) loadB(NQ - DK + u + 1, (u + 1) & 3, bb[(u + 1) & 1]);
-        mma(ka[u], bb[u & 1]);
+        for (int u = 0; u < DK; ++u) {   // the last DK steps load nothing past the end
+            if (u + 1 < DK) loadB(n - DK + u + 1, (u + 1) & 3, bb[(u + 1) & 1]);
+            mma(ka[u], bb[u & 1]);
+        }
+    };
+    // a job whose nodes fill every k step keeps the compile-time bound (constant B
+    // offsets in the last steps); a shorter one runs to its own bound, one value per wave
+    // (a scalar, which keeps the loop and the B addresses off the vector registers)
+    if constexpr (NQ > 2 * DK) {
+        if (nq < NQ) {
+            rest(__builtin_amdgcn_readfirstlane(nq));
+            return;
+        }
     }
+    rest(NQ);
 }
 
 struct PcPairD {
@@ -790,7 +808,7 @@ static __device__ __forceinline__ int pc_product_incr(const float* sD, gconst_fp
         // that the f32 result layout matches the f64 one) on dF, added to the iterate
         gconst_fp kp1f = kp0f + (size_t)NQ * 64;
         const float* bp = sD + (lane >> 4) * ROW + (lane & 15);
-        pc_kloop<NQ, 3, PcPairF, float>(
+        pc_kloop<NQ, 3, PcPairF, float>(L.nq, 
             [&](int q) { return PcPairF{kp0f[q * 64], kp1f[q * 64]}; },
             [&](int q) { return PcPairF{kp0f[q * 64], kp1f[q * 64]}; },
             [&](int q, int, float (&bq)[3]) {
@@ -820,7 +838,7 @@ static __device__ __forceinline__ int pc_product_incr(const float* sD, gconst_fp
 #pragma unroll
     for (int u = 0; u < 4; ++u)
         bp[u] = sD + (lane >> 4) * ROW + L.grp * 16 + (pi ^ ((4 * u + (lane >> 4)) & 15));
-    pc_kloop<NQ, 6, float, float, 3, 6, 1>(
+    pc_kloop<NQ, 6, float, float, 3, 6, 1>(L.nq, 
         [&](int q) { return kp0f[q * 64]; }, [&](int q) { return kp0f[q * 64]; },
         [&](int q, int u, float (&bq)[6]) {
 #pragma unroll
@@ -873,7 +891,7 @@ static __device__ __forceinline__ int pc_product(const double* sF, const double*
 #pragma unroll
             for (int u = 0; u < 4; ++u)
                 bp[u] = sF + (lane >> 4) * ROW + L.grp * 16 + (pi ^ ((4 * u + (lane >> 4)) & 15));
-            pc_kloop<NQ, 6, float, float>(
+            pc_kloop<NQ, 6, float, float>(L.nq, 
                 [&](int q) { return kp0f[q * 64]; }, [&](int q) { return kp0f[q * 64]; },
                 [&](int q, int u, float (&bq)[6]) {
 #pragma unroll
@@ -886,7 +904,7 @@ static __device__ __forceinline__ int pc_product(const double* sF, const double*
         } else {
             gconst_fp kp1f = kp0f + (size_t)NQ * 64;
             const double* bp = sF + (lane >> 4) * ROW + (lane & 15);
-            pc_kloop<NQ, 3, PcPairF, float>(
+            pc_kloop<NQ, 3, PcPairF, float>(L.nq, 
                 [&](int q) { return PcPairF{kp0f[q * 64], kp1f[q * 64]}; },
                 [&](int q) { return PcPairF{kp0f[q * 64], kp1f[q * 64]}; },
                 [&](int q, int, float (&bq)[3]) {
@@ -914,7 +932,7 @@ static __device__ __forceinline__ int pc_product(const double* sF, const double*
 #pragma unroll
             for (int u = 0; u < 4; ++u)
                 bp[u] = sF + (lane >> 4) * ROW + L.grp * 16 + ((lane & 15) ^ ((4 * u + (lane >> 4)) & 15));
-            pc_kloop<NQ, 6, double, double, 3, 6, 1>(
+            pc_kloop<NQ, 6, double, double, 3, 6, 1>(L.nq, 
                 [&](int u) { return kpre[u]; }, [&](int q) { return kp0[q * 64]; },
                 [&](int q, int u, double (&bq)[6]) {
 #pragma unroll
@@ -930,7 +948,7 @@ static __device__ __forceinline__ int pc_product(const double* sF, const double*
         if constexpr (!FP32) {
             gconst_dp kp1 = kp0 + (size_t)NQ * 64;
             const double* bp = sF + (lane >> 4) * ROW + (lane & 15);
-            pc_kloop<NQ, 3, PcPairD, double>(
+            pc_kloop<NQ, 3, PcPairD, double>(L.nq, 
                 [&](int u) { return PcPairD{kpre[u], kpre[4 + u]}; },
                 [&](int q) { return PcPairD{kp0[q * 64], kp1[q * 64]}; },
                 [&](int q, int, double (&bq)[3]) {
@@ -988,7 +1006,7 @@ static __device__ __forceinline__ int pc_product2(const double* sF, const double
         const double* b2 = row + (hi ? 3 : 0) * T + m;   // 0   | a_x
         const double* b3 = row + (hi ? 5 : 4) * T + m;   // a_y | a_z
         gconst_dp kp1b = kp1 + (size_t)NQ * 64, kp2b = kp2 + (size_t)NQ * 64;
-        pc_kloop<NQ, 4, PcQuadD, double>(
+        pc_kloop<NQ, 4, PcQuadD, double>(L.nq, 
             [&](int q) { return PcQuadD{kp1[q * 64], kp1b[q * 64], kp2[q * 64], kp2b[q * 64]}; },
             [&](int q) { return PcQuadD{kp1[q * 64], kp1b[q * 64], kp2[q * 64], kp2b[q * 64]}; },
             [&](int q, int, double (&bq)[4]) {
@@ -1031,7 +1049,7 @@ static __device__ __forceinline__ int pc_product2(const double* sF, const double
 #pragma unroll
         for (int u = 0; u < 4; ++u)
             bp[u] = sF + (lane >> 4) * ROW + L.grp * 16 + ((lane & 15) ^ ((4 * u + (lane >> 4)) & 15));
-        pc_kloop<NQ, 3, PcPairD, double, 3, 6, 2>(
+        pc_kloop<NQ, 3, PcPairD, double, 3, 6, 2>(L.nq, 
             [&](int u) { return PcPairD{kpre[u], kpre[4 + u]}; },
             [&](int q) { return PcPairD{kp1[q * 64], kp2[q * 64]}; },
             [&](int q, int u, double (&bq)[3]) {
@@ -1136,7 +1154,7 @@ static __device__ __forceinline__ int pc_product2_fb(double* sF, const double* s
     for (int u = 0; u < 4; ++u)
         bp[u] = sF + (lane >> 4) * ROW + L.grp * 16 + ((lane & 15) ^ ((4 * u + (lane >> 4)) & 15));
     auto product = [&](int c0) {
-        pc_kloop<NQ, 3, PcPairD, double, 3, 6, 2>(
+        pc_kloop<NQ, 3, PcPairD, double, 3, 6, 2>(L.nq, 
             [&](int u) { return PcPairD{kpre[u], kpre[4 + u]}; },
             [&](int q) { return PcPairD{kp1[q * 64], kp2[q * 64]}; },
             [&](int q, int u, double (&bq)[3]) {
@@ -1204,7 +1222,7 @@ static __device__ __forceinline__ void pc_product_adj(const double* sF, gconst_d
 #pragma unroll
         for (int u = 0; u < 4; ++u)
             bp[u] = sF + (lane >> 4) * ROW + L.grp * 16 + ((lane & 15) ^ ((4 * u + (lane >> 4)) & 15));
-        pc_kloop<NQ, 6, double, double, 3, 6, 1>(
+        pc_kloop<NQ, 6, double, double, 3, 6, 1>(L.nq, 
             [&](int q) { return kpT[q * 64]; }, [&](int q) { return kpT[q * 64]; },
             [&](int q, int u, double (&bq)[6]) {
 #pragma unroll
@@ -1219,7 +1237,7 @@ static __device__ __forceinline__ void pc_product_adj(const double* sF, gconst_d
         // wave's two row blocks; acc[3h + c] is column block c of strip h
         gconst_dp kpT1 = kpT + (size_t)NQ * 64;
         const double* bp = sF + (lane >> 4) * ROW + (lane & 15);
-        pc_kloop<NQ, 3, PcPairD, double>(
+        pc_kloop<NQ, 3, PcPairD, double>(L.nq, 
             [&](int q) { return PcPairD{kpT[q * 64], kpT1[q * 64]}; },
             [&](int q) { return PcPairD{kpT[q * 64], kpT1[q * 64]}; },
             [&](int q, int, double (&bq)[3]) {

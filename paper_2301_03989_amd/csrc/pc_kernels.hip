@@ -475,7 +475,7 @@ __device__ __attribute__((noinline)) void pc_job(const PcParams& p, const PcJobD
 
     double* sY0 = sm.Y0;
     const int tid = threadIdx.x;
-    const PcLane L = pc_lane_geometry<PAIRS, NP>(tid);
+    const PcLane L = pc_lane_geometry<PAIRS, NP>(tid, g.N);
     const int N = g.N, S = g.S;
     const int n = job.n;
     const int64_t ic = job.ic0 + tid;      // this thread's IC when tid < n
@@ -580,7 +580,7 @@ __device__ __attribute__((noinline)) void pc_job_list(const PcParams& p, const P
     double* sF = sm.F;
     double* sY0 = sm.Y0;
     const int tid = threadIdx.x;
-    const PcLane L = pc_lane_geometry<PAIRS, NP>(tid);
+    const PcLane L = pc_lane_geometry<PAIRS, NP>(tid, g.N);
     const int N = g.N, S = g.S, P = p.n_pert;
     const int n = job.n;
     const int grp = Sh::WIDE ? L.grp : 0;
@@ -979,7 +979,7 @@ __device__ __attribute__((noinline)) void pc_adjoint_job(const PcAdjParams& a, c
     double* sF = sm.F;
     double* sY0 = sm.Y0;
     const int tid = threadIdx.x;
-    const PcLane L = pc_lane_geometry<PAIRS, NP>(tid);
+    const PcLane L = pc_lane_geometry<PAIRS, NP>(tid, g.N);
     const int N = g.N, S = g.S, P = p.n_pert;
     const int n = job.n;
     const int64_t ic = job.ic0 + tid;

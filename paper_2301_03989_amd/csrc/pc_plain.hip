@@ -143,7 +143,7 @@ __global__ __launch_bounds__(PAIRS / 4) void pc_plain_step(PcPlainArgs a, int s,
     const int job = a.job_list[blockIdx.x];
     const int64_t m0 = (int64_t)job * T;
     const int N = a.N;
-    const PcLane L = pc_lane_geometry<PAIRS, NP>(tid);
+    const PcLane L = pc_lane_geometry<PAIRS, NP>(tid, N);
     const size_t row = (size_t)9 * a.Mpad;
 
     // stage F = (v, a) (Y comps 3..8) and r (Y comps 0..2) of the job, and its initial states
