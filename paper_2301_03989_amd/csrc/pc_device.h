@@ -1413,11 +1413,41 @@ static __device__ __forceinline__ double pc_rsqrt_full(double x)
 }
 
 // Records of the relativistic model per node: for every major body b = 0..P (0 = the
-// central body) three double4, (r_b, U_b), (v_b, mu_b), (a_b, 0), with U_b the potential
-// of the other major bodies at b, then the indirect term (ax, ay, az, 0).  A segment's
-// records are stored slot-major, [slot][node], so that the lanes of a wave, which hold
-// consecutive nodes, read consecutive double4.
+// central body) three double4, (r_b, U_b - 2 v_b^2), (v_b, mu_b), (a_b, 0), with U_b the
+// potential of the other major bodies at b (the two terms of the bracket below that depend
+// on body b alone, summed once per node), then the indirect term (ax, ay, az, 0).  A
+// segment's records are stored slot-major, [slot][node], so that the lanes of a wave,
+// which hold consecutive nodes, read consecutive double4.
 constexpr int pc_eih_rec(int P) { return 3 * (P + 1) + 1; }
+
+typedef const __attribute__((address_space(1))) char* gconst_cp;
+typedef double pc_d2v __attribute__((ext_vector_type(2)));
+typedef const __attribute__((address_space(1))) pc_d2v* gconst_d2p;
+
+// A segment's records read from a base address and a slot stride that are one value per
+// wave (scalar registers): each load adds only the 32-bit byte offset of the lane's node,
+// a global load with a scalar base and no per-lane address arithmetic.  Every caller's
+// records are those of one segment of one group, the same for all lanes of the wave.
+struct PcEihRecs {
+    gconst_cp base;   // slot 0, node 0
+    uint32_t slot;    // bytes per slot (ns double4)
+};
+static __device__ __forceinline__ PcEihRecs pc_eih_recs(const double4* e, int ns)
+{
+    const uint64_t v = reinterpret_cast<uint64_t>(e);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    PcEihRecs E;
+    E.base = (gconst_cp)((((uint64_t)hi) << 32) | lo);
+    E.slot = (uint32_t)__builtin_amdgcn_readfirstlane(ns) * 32u;
+    return E;
+}
+static __device__ __forceinline__ double4 pc_eih_load(const PcEihRecs& E, int k, uint32_t vo)
+{
+    const gconst_d2p q = (gconst_d2p)(E.base + (size_t)k * E.slot + vo);
+    const pc_d2v a = q[0], b = q[1];
+    return make_double4(a.x, a.y, b.x, b.y);
+}
 
 // Einstein-Infeld-Hoffmann acceleration of R massless points (x, y, z, vx, vy, vz) at one
 // node (PPN beta = gamma = 1, Sec. 5.4.1): with d = r - r_b, rho = |d| and the potential
@@ -1438,7 +1468,12 @@ static __device__ __forceinline__ void pc_force_eih(const double (&x)[R], const 
                                                     int P, double inv_c2, double (&ax)[R], double (&ay)[R],
                                                     double (&az)[R])
 {
-    auto rec = [&](int k, int r) -> double4 { return e[(size_t)k * ns + jr[ONE_NODE ? 0 : r]]; };
+    const PcEihRecs E = pc_eih_recs(e, ns);
+    uint32_t vo[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) vo[r] = (uint32_t)jr[ONE_NODE ? 0 : r] * 32u;
+    auto rec = [&](int k, int r) -> double4 { return pc_eih_load(E, k, vo[r]); };
+    const double c35 = 3.5 * inv_c2;
     double phi[R], v2[R], nx[R], ny[R], nz[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -1463,7 +1498,7 @@ static __device__ __forceinline__ void pc_force_eih(const double (&x)[R], const 
                 w = rec(3 * b + 1, r);
                 g = rec(3 * b + 2, r);
             }
-            const double mu = w.w, wb2 = w.x * w.x + w.y * w.y + w.z * w.z;
+            const double mu = w.w;
             const double dx = x[r] - q.x, dy = y[r] - q.y, dz = z[r] - q.z;
             const double i1 = pc_rsqrt_full(dx * dx + dy * dy + dz * dz);
             const double m1 = mu * i1;
@@ -1473,14 +1508,14 @@ static __device__ __forceinline__ void pc_force_eih(const double (&x)[R], const 
             ny[r] = fma(m3, dy, ny[r]);
             nz[r] = fma(m3, dz, nz[r]);
             const double vbv = vx[r] * w.x + vy[r] * w.y + vz[r] * w.z;
-            const double dvb = (dx * w.x + dy * w.y + dz * w.z) * i1;
+            const double dwb = dx * w.x + dy * w.y + dz * w.z;   // d.v_b
+            const double dvb = dwb * i1;
             const double dab = dx * g.x + dy * g.y + dz * g.z;
-            const double s = q.w - v2[r] - 2.0 * wb2 + 4.0 * vbv + 1.5 * dvb * dvb + 0.5 * dab;
+            const double s = q.w - v2[r] + 4.0 * vbv + 1.5 * dvb * dvb + 0.5 * dab;   // q.w = U_b - 2 v_b^2
             const double k1 = -m3 * fma(-inv_c2, s, 1.0);
-            const double dw = dx * (4.0 * vx[r] - 3.0 * w.x) + dy * (4.0 * vy[r] - 3.0 * w.y) +
-                              dz * (4.0 * vz[r] - 3.0 * w.z);
-            const double k2 = inv_c2 * m3 * dw;
-            const double k3 = 3.5 * inv_c2 * m1;
+            const double dv = dx * vx[r] + dy * vy[r] + dz * vz[r];
+            const double k2 = inv_c2 * m3 * fma(4.0, dv, -3.0 * dwb);   // d.(4 v - 3 v_b)
+            const double k3 = c35 * m1;
             ax[r] += k1 * dx + k2 * (vx[r] - w.x) + k3 * g.x;
             ay[r] += k1 * dy + k2 * (vy[r] - w.y) + k3 * g.y;
             az[r] += k1 * dz + k2 * (vz[r] - w.z) + k3 * g.z;
@@ -1519,9 +1554,11 @@ static __device__ __forceinline__ void pc_eih_vjp(const double (&x)[R], const do
                                                   double (&grx)[R], double (&gry)[R], double (&grz)[R],
                                                   double (&gvx)[R], double (&gvy)[R], double (&gvz)[R])
 {
-    auto rec = [&](int k, int r) -> double4 { return e[(size_t)k * ns + jr[ONE_NODE ? 0 : r]]; };
+    const PcEihRecs E = pc_eih_recs(e, ns);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
+        const uint32_t vo = (uint32_t)jr[ONE_NODE ? 0 : r] * 32u;
+        auto rec = [&](int k, int) -> double4 { return pc_eih_load(E, k, vo); };
         double phi = 0.0, v2 = vx[r] * vx[r] + vy[r] * vy[r] + vz[r] * vz[r];
         double nx = 0.0, ny = 0.0, nz = 0.0, hx = 0.0, hy = 0.0, hz = 0.0;
         double ax = 0.0, ay = 0.0, az = 0.0, bx = 0.0, by = 0.0, bz = 0.0;
@@ -1541,13 +1578,12 @@ static __device__ __forceinline__ void pc_eih_vjp(const double (&x)[R], const do
             hx += tx;
             hy += ty;
             hz += tz;
-            const double wb2 = w.x * w.x + w.y * w.y + w.z * w.z;
             const double vbv = vx[r] * w.x + vy[r] * w.y + vz[r] * w.z;
-            const double dvb = (dx * w.x + dy * w.y + dz * w.z) * i1;
+            const double dwb = dx * w.x + dy * w.y + dz * w.z;
+            const double dvb = dwb * i1;
             const double dab = dx * g.x + dy * g.y + dz * g.z;
-            const double S = q.w - v2 - 2.0 * wb2 + 4.0 * vbv + 1.5 * dvb * dvb + 0.5 * dab;
-            const double dq = dx * (4.0 * vx[r] - 3.0 * w.x) + dy * (4.0 * vy[r] - 3.0 * w.y) +
-                              dz * (4.0 * vz[r] - 3.0 * w.z);
+            const double S = q.w - v2 + 4.0 * vbv + 1.5 * dvb * dvb + 0.5 * dab;   // q.w = U_b - 2 v_b^2
+            const double dq = fma(4.0, dx * vx[r] + dy * vy[r] + dz * vz[r], -3.0 * dwb);
             const double uvw = ux[r] * (vx[r] - w.x) + uy[r] * (vy[r] - w.y) + uz[r] * (vz[r] - w.z);
             const double ug = ux[r] * g.x + uy[r] * g.y + uz[r] * g.z;
             // dS/dr

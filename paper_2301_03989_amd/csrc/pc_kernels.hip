@@ -67,7 +67,8 @@ __global__ void pc_ephem_kernel(const PcEphemParams p)
                 u += p.bodies[k].mu / sqrt(dx * dx + dy * dy + dz * dz);
             }
             const double iq3 = 1.0 / (q * q * q);   // Keplerian orbit about the central body
-            er(3 * (b + 1)) = make_double4(rb[b][0], rb[b][1], rb[b][2], u);
+            const double vb2 = vb[b][0] * vb[b][0] + vb[b][1] * vb[b][1] + vb[b][2] * vb[b][2];
+            er(3 * (b + 1)) = make_double4(rb[b][0], rb[b][1], rb[b][2], u - 2.0 * vb2);
             er(3 * (b + 1) + 1) = make_double4(vb[b][0], vb[b][1], vb[b][2], p.bodies[b].mu);
             er(3 * (b + 1) + 2) = make_double4(-rb[b][0] * iq3, -rb[b][1] * iq3, -rb[b][2] * iq3, 0.0);
         }
