@@ -980,7 +980,9 @@ __device__ __attribute__((noinline)) void pc_adjoint_job(const PcAdjParams& a, c
     double* sF = sm.F;
     double* sY0 = sm.Y0;
     const int tid = threadIdx.x;
-    const PcLane L = pc_lane_geometry<PAIRS, NP>(tid, g.N);
+    // the products run every k step here (the bound NP folds to the compile-time count): a
+    // second, shorter k loop per product costs this body registers at every node count
+    const PcLane L = pc_lane_geometry<PAIRS, NP>(tid, NP);
     const int N = g.N, S = g.S, P = p.n_pert;
     const int n = job.n;
     const int64_t ic = job.ic0 + tid;
