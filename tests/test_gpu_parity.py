@@ -173,6 +173,28 @@ def test_node_counts_and_padding(pc, nodes):
     assert np.abs(r["iters"] - o["iters"]).max() <= 1
 
 
+@pytest.mark.parametrize("nodes", [17, 33, 65, 129])
+def test_node_counts_just_past_a_power_of_two(pc, nodes):
+    """One node past a power of two pads to twice the count; the products stop after the
+    last 16-node block holding a node (K_N is zero past N), the shortest k range against
+    the padded one.  First-order FP64 sweeps, the precision schedule and second-order
+    sweeps against the oracle."""
+    w = W.nbody_venus(21, seed=300 + nodes, days=40.0, segments=2, nodes=nodes, tol=1e-12)
+    kw = dict(fixed_iters=8) if nodes < 40 else {}
+    print(f"past a power of two: N {nodes} {kw}", flush=True)
+    r, _ = _run(pc, w, **kw)
+    o = oracle_run(w, **kw)
+    assert rel_err(r["states"], o["states"]).max() < (1e-12 if kw else TOL)
+    assert np.abs(r["iters"] - o["iters"]).max() <= 1
+    if not kw:
+        m, _ = _run(pc, w, precision="fp32-fp64")
+        assert rel_err(m["states"], o["states"]).max() < 1e-11
+        r2, _ = _run(pc, w, order=2)
+        o2 = oracle_run(w, order=2)
+        assert rel_err(r2["states"], o2["states"]).max() < TOL
+        assert np.abs(r2["iters"] - o2["iters"]).max() <= 1
+
+
 def test_degenerate_and_ragged_batches(pc):
     """Smallest and most ragged shapes in one call: a single IC at the minimum of three
     nodes and one segment, a single IC at 256 nodes (seven idle columns of its 8-IC job),
