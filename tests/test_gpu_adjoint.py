@@ -374,3 +374,17 @@ def test_relativistic_adjoint_stored_nodes_and_node_seeds(pc, nodes):
     assert _gerr(a.cpu().numpy(), ref).max() < GTOL
     assert _gerr(b.cpu().numpy(), ref).max() < GTOL
     assert _gerr(a.cpu().numpy(), b.cpu().numpy()).max() < 1e-12
+
+
+def test_relativistic_autograd_function(pc):
+    """The torch.autograd wrapper with the relativistic model: the backward pass is the
+    relativistic adjoint, from checkpoints and from stored node states."""
+    from paper_2301_03989_amd import autograd
+    w, ics, groups, model, om, g = _eih_setup(12, 48, 1e-4, seed=150)
+    c = torch.tensor(np.random.default_rng(6).standard_normal((w.n_ic, 6)), device="cuda")
+    ref = oracle.adjoint(w.ics, g.t0, g.tf, g.nodes, g.segments, g.tol, om, c.cpu().numpy())
+    for store in (False, True):
+        x = ics.clone().requires_grad_(True)
+        loss = (autograd.propagate(x, groups, model, pc=pc, store_nodes=store) * c).sum()
+        (gx,) = torch.autograd.grad(loss, x)
+        assert _gerr(gx.cpu().numpy(), ref).max() < GTOL, store
