@@ -158,8 +158,8 @@ typedef struct {
                              different discretisation of the same ODE (the position series
                              has degree N).  Order 2 runs on the fused FP64 path with the
                              per-IC rule and the point-mass model, for every node count (3 to
-                             256; the feedback up to 128); other calls with order 2 return
-                             PC_EINVAL. */
+                             256, with or without the feedback); other calls with order 2
+                             return PC_EINVAL. */
     int32_t feedback;     /* order 2: 1 = integral error feedback, the development Sec. 1 cites
                              with the adaptive variant of the method.  The sweep's accelerations
                              were taken at the previous position iterate; the change dx the

@@ -485,14 +485,10 @@ int make_plan(pc_ctx* ctx, int64_t n_ic, const pc_group* groups, int n_groups, c
     if (plan.plain) plan.pairs = 2048;
     if (o.order == 2) {
         // second-order sweeps need blocks of 16 or more ICs (the transposed product) up to
-        // 128 nodes; 256-node groups run 8-IC node-row jobs (without the feedback)
+        // 128 nodes; 256-node groups run 8-IC node-row jobs
         for (int gi = 0; gi < n_groups; ++gi) {
             const int np = padded_nodes(std::max(3, std::min((int)groups[gi].nodes, PC_MAX_NODES)));
-            if (np > 128) {
-                if (o.feedback)
-                    return set_error(ctx, PC_EINVAL, "the integral error feedback runs with up to 128 nodes");
-                continue;
-            }
+            if (np > 128) continue;
             if (plan.pairs / np < 16) {
                 if (o.tile_pairs == 1024) return set_error(ctx, PC_EINVAL, "order 2 with %d nodes needs tile_pairs 2048", groups[gi].nodes);
                 plan.pairs = 2048;

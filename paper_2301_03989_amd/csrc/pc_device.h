@@ -1109,13 +1109,13 @@ static __device__ __forceinline__ int pc_product2(const double* sF, const double
 // estimate t of 1/|d|^2 as t (1 + e + e^2), e = 1 - |d|^2 t.  Records in LDS (compact
 // [node][body][3], masses in smu) or, when they do not fit there, double4 (x, y, z, mu)
 // in global memory.
-template <int R>
+template <int R, bool ONE_NODE = true>
 static __device__ __forceinline__ void pc_grad_dot_node(const double (&x)[R], const double (&y)[R],
                                                         const double (&z)[R], const double (&dx)[R],
-                                                        const double (&dy)[R], const double (&dz)[R], int j, int P,
-                                                        double mu_sun, bool rec_lds, const double* srec,
-                                                        const double* smu, const double4* grec, double (&gx)[R],
-                                                        double (&gy)[R], double (&gz)[R])
+                                                        const double (&dy)[R], const double (&dz)[R],
+                                                        const int (&jr)[R], int P, double mu_sun, bool rec_lds,
+                                                        const double* srec, const double* smu, const double4* grec,
+                                                        double (&gx)[R], double (&gy)[R], double (&gz)[R])
 {
     auto add = [&](int r, double ox, double oy, double oz, double mu) {
         const double qx = x[r] - ox, qy = y[r] - oy, qz = z[r] - oz;
@@ -1135,8 +1135,8 @@ static __device__ __forceinline__ void pc_grad_dot_node(const double (&x)[R], co
         gx[r] = gy[r] = gz[r] = 0.0;
         add(r, 0.0, 0.0, 0.0, mu_sun);
     }
-    for (int b = 0; b < P; ++b) {
-        double ox, oy, oz, mu;
+    // body b's record at node j (ONE_NODE: every point at node jr[0], one read for all)
+    auto rec = [&](int j, int b, double& ox, double& oy, double& oz, double& mu) {
         if (rec_lds) {
             const double* q = srec + j * 3 * (P + 1) + 3 * b;
             ox = q[0];
@@ -1150,12 +1150,25 @@ static __device__ __forceinline__ void pc_grad_dot_node(const double (&x)[R], co
             oz = q.z;
             mu = q.w;
         }
+    };
+    for (int b = 0; b < P; ++b) {
+        if constexpr (ONE_NODE) {
+            double ox, oy, oz, mu;
+            rec(jr[0], b, ox, oy, oz, mu);
 #pragma unroll
-        for (int r = 0; r < R; ++r) add(r, ox, oy, oz, mu);
+            for (int r = 0; r < R; ++r) add(r, ox, oy, oz, mu);
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                double ox, oy, oz, mu;
+                rec(jr[r], b, ox, oy, oz, mu);
+                add(r, ox, oy, oz, mu);
+            }
+        }
     }
 }
 
-// Second-order sweep with integral error feedback (WIDE shapes).  The sweep's accelerations
+// Second-order sweep with integral error feedback.  The sweep's accelerations
 // were taken at the previous position iterate; the position it predicts,
 // x = x0 + w2 v0 (tau_j + 1) + w2^2 K2_N a, changes that iterate by dx, and the linear change
 // of the acceleration over dx, da = (da/dr) dx at the previous iterate, is integrated like
@@ -1164,19 +1177,115 @@ static __device__ __forceinline__ void pc_grad_dot_node(const double (&x)[R], co
 // products do not read, and its product accumulates onto the first one (one barrier in
 // between).  At the fixed point dx vanishes, so the converged iterate is the second-order
 // one.  Flags as pc_product.
+// 8-IC jobs (node-row layout, as pc_product2): the velocity columns hold da, so both
+// products take the zero halves of their mixed operands by select instead of from those
+// columns; each lane forms da at the four points of strip hi, taking the position and
+// change components it lacks from its partner (l ^ 8).
 template <int PAIRS, int NP>
 static __device__ __forceinline__ int pc_product2_fb(double* sF, const double* sY0, gconst_dp kp1, gconst_dp kp2,
                                                       const double (&kpre)[8], const double (&yc)[6][4],
-                                                      f64x4 (&acc)[6], double w2, double tp1, const PcTol& tl, int N,
-                                                      const PcLane& L, int P, double mu_sun, bool rec_lds,
-                                                      const double* sRec, const double* sMu, const double4* grec)
+                                                      f64x4 (&acc)[6], double w2, const double (&tp)[8],
+                                                      const PcTol& tl, int N, const PcLane& L, int P, double mu_sun,
+                                                      bool rec_lds, const double* sRec, const double* sMu,
+                                                      const double4* grec)
 {
     using Sh = PcShape<PAIRS, NP>;
-    static_assert(Sh::WIDE, "second-order sweeps run on WIDE job shapes");
     constexpr int T = Sh::T, ROW = Sh::ROW, NQ = Sh::NQ;
     const int lane = L.lane;
 #pragma unroll
     for (int b = 0; b < 6; ++b) acc[b] = f64x4{0.0, 0.0, 0.0, 0.0};
+    if constexpr (!Sh::WIDE) {
+        const int hi = L.hi, m = lane & 7;
+        const double* row = sF + (lane >> 4) * ROW;
+        gconst_dp kp1b = kp1 + (size_t)NQ * 64, kp2b = kp2 + (size_t)NQ * 64;
+        // K2_N and K_N products of the columns c0 = base, c1, c2 (accelerations: base 3;
+        // da: base 0) into the position and velocity blocks, as pc_product2
+        auto product = [&](int base) {
+            const double* b0 = row + (base + hi) * T + m;       // c0 | c1
+            const double* b1 = row + (base + 2) * T + m;        // c2 | 0
+            const double* b2 = row + base * T + m;              // 0  | c0
+            const double* b3 = row + (base + 1 + hi) * T + m;   // c1 | c2
+            pc_kloop<NQ, 4, PcQuadD, double>(L.nq,
+                [&](int q) { return PcQuadD{kp1[q * 64], kp1b[q * 64], kp2[q * 64], kp2b[q * 64]}; },
+                [&](int q) { return PcQuadD{kp1[q * 64], kp1b[q * 64], kp2[q * 64], kp2b[q * 64]}; },
+                [&](int q, int, double (&bq)[4]) {
+                    const int o = q * 4 * ROW;
+                    const double v1 = b1[o], v2 = b2[o];
+                    bq[0] = b0[o];
+                    bq[1] = hi ? 0.0 : v1;
+                    bq[2] = hi ? v2 : 0.0;
+                    bq[3] = b3[o];
+                },
+                [&](const PcQuadD& ka, const double (&bq)[4]) {
+                    acc[0] = mfma16(ka.q0, bq[0], acc[0]);
+                    acc[1] = mfma16(ka.q0, bq[1], acc[1]);
+                    acc[2] = mfma16(ka.k0, bq[3], acc[2]);
+                    acc[3] = mfma16(ka.q1, bq[0], acc[3]);
+                    acc[4] = mfma16(ka.q1, bq[1], acc[4]);
+                    acc[5] = mfma16(ka.k1, bq[3], acc[5]);
+                    acc[1] = mfma16(ka.k0, bq[2], acc[1]);
+                    acc[4] = mfma16(ka.k1, bq[2], acc[4]);
+                });
+        };
+        product(3);
+        // predicted position and its change from the previous iterate: block 3h holds
+        // comp hi of strip h, block 3h + 1 comp 2 in the low lane
+        const double x0a = sY0[hi * T + m], x0z = sY0[2 * T + m];
+        const double v0a = sY0[(3 + hi) * T + m], v0z = sY0[5 * T + m];
+        double xs[4], ys[4], zs[4], ddx[4], ddy[4], ddz[4], gx[4], gy[4], gz[4];
+        int jr[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            double d0[2], d1[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const double t = tp[4 * h + r];
+                d0[h] = (x0a + w2 * fma(w2, acc[3 * h][r], t * v0a)) - yc[3 * h][r];
+                d1[h] = (x0z + w2 * fma(w2, acc[3 * h + 1][r], t * v0z)) - yc[3 * h + 1][r];
+            }
+            // the lane's points are those of strip hi
+            const double s1 = pc_dpp<0x128>(hi ? yc[0][r] : yc[3][r]);   // lo: y(0); hi: x(1)
+            const double s2 = pc_dpp<0x128>(yc[4][r]);                   // hi: z(1)
+            const double g1 = pc_dpp<0x128>(hi ? d0[0] : d0[1]);         // lo: dy(0); hi: dx(1)
+            const double g2 = pc_dpp<0x128>(d1[1]);                      // hi: dz(1)
+            xs[r] = hi ? s1 : yc[0][r];
+            ys[r] = hi ? yc[3][r] : s1;
+            zs[r] = hi ? s2 : yc[1][r];
+            ddx[r] = hi ? g1 : d0[0];
+            ddy[r] = hi ? d0[1] : g1;
+            ddz[r] = hi ? g2 : d1[0];
+            const int j = pc_node(L, hi, r);
+            jr[r] = j < N ? j : N - 1;
+        }
+        pc_grad_dot_node<4, false>(xs, ys, zs, ddx, ddy, ddz, jr, P, mu_sun, rec_lds, sRec, sMu, grec, gx, gy,
+                                   gz);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = pc_node(L, hi, r);
+            if (j < N) {
+                double* f = sF + j * ROW + m;
+                f[0 * T] = gx[r];
+                f[1 * T] = gy[r];
+                f[2 * T] = gz[r];
+            }
+        }
+        __syncthreads();   // every node's da published
+        product(0);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const double t = tp[4 * h + r];
+                acc[3 * h][r] = fma(w2, acc[3 * h][r], t * v0a);
+                acc[3 * h + 1][r] = hi ? acc[3 * h + 1][r] : fma(w2, acc[3 * h + 1][r], t * v0z);
+            }
+        }
+        int flag = pc_row_epilogue<PAIRS, NP, false>(sY0, yc, acc, w2, tl, N, L);
+        flag |= __shfl_xor(flag, 16);
+        flag |= __shfl_xor(flag, 32);
+        return flag;
+    }
+    const double tp1 = tp[0];
     const double* bp[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -1211,8 +1320,9 @@ static __device__ __forceinline__ int pc_product2_fb(double* sF, const double* s
         ddy[r] = d[1];
         ddz[r] = d[2];
     }
-    pc_grad_dot_node<4>(yc[0], yc[1], yc[2], ddx, ddy, ddz, j < N ? j : N - 1, P, mu_sun, rec_lds, sRec, sMu, grec,
-                        gx, gy, gz);
+    const int jj = j < N ? j : N - 1;
+    const int jr[4] = {jj, jj, jj, jj};
+    pc_grad_dot_node<4>(yc[0], yc[1], yc[2], ddx, ddy, ddz, jr, P, mu_sun, rec_lds, sRec, sMu, grec, gx, gy, gz);
     if (j < N) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {

@@ -354,7 +354,7 @@ static __device__ __forceinline__ void pc_segment_solve(const PcParams& p, const
                 flag = mode == 1 ? pc_product<PAIRS, NP, true>(sF, sY0, kp0, kpre, kp0f, yc, acc, w2, tl, N, L)
                                  : pc_product<PAIRS, NP, false>(sF, sY0, kp0, kpre, kp0f, yc, acc, w2, tl, N, L);
         } else if constexpr (SO == 2) {
-            flag = pc_product2_fb<PAIRS, NP>(sF, sY0, kp0, kp2, kpre, yc, acc, w2, tp[0], tl, N, L, P, mu_sun,
+            flag = pc_product2_fb<PAIRS, NP>(sF, sY0, kp0, kp2, kpre, yc, acc, w2, tp, tl, N, L, P, mu_sun,
                                              rec_lds, sm.Rec, sm.Mu, grec);
         } else if constexpr (SO) {
             flag = pc_product2<PAIRS, NP>(sF, sY0, kp0, kp2, kpre, yc, acc, w2, tp, tl, N, L);
@@ -871,11 +871,9 @@ static __device__ __forceinline__ void pc_run_job(const PcParams& p, const PcJob
                                                   bool list, bool mixed, bool eih, bool order2)
 {
     if (order2) {
-        if constexpr (PcShape<PAIRS, NP>::WIDE) {
-            if (p.feedback) {
-                pc_job<PAIRS, NP, false, false, 2>(p, job, g);
-                return;
-            }
+        if (p.feedback) {
+            pc_job<PAIRS, NP, false, false, 2>(p, job, g);
+            return;
         }
         if (list) pc_job_list<PAIRS, NP, 1>(p, job, g);
         else pc_job<PAIRS, NP, false, false, 1>(p, job, g);

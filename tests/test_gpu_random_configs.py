@@ -136,7 +136,7 @@ def _option_case(seed):
     mode = ["order2", "feedback", "refine", "flyby", "guess", "order2_refine"][seed % 6]
     kw, okw = {}, {}
     if mode in ("order2", "feedback"):
-        N = int(rng.integers(3, 129 if mode == "feedback" else 257))
+        N = int(rng.integers(3, 257))
         S = int(rng.integers(1, 4))
         w = W.nbody_venus(int(rng.integers(5, 40)), seed=400 + seed, days=float(rng.uniform(20, 90)) * S,
                           segments=S, nodes=N, tol=float(rng.choice([1e-11, 1e-12])))

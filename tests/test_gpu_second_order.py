@@ -108,7 +108,8 @@ def test_fewer_sweeps_than_first_order(pc):
     assert rel_err(two["states"].cpu().numpy(), one["states"].cpu().numpy()).max() < 1e-10
 
 
-@pytest.mark.parametrize("nodes,tile", [(16, 2048), (64, 2048), (100, 2048), (128, 2048), (48, 1024)])
+@pytest.mark.parametrize("nodes,tile", [(16, 2048), (64, 2048), (100, 2048), (128, 2048), (48, 1024),
+                                        (200, 2048), (256, 2048)])
 def test_feedback_matches_oracle(pc, nodes, tile):
     """Second-order sweeps with the integral error feedback against the oracle's feedback
     form: states at every boundary to the bar, sweep counts within one."""
@@ -136,6 +137,39 @@ def test_feedback_fixed_sweeps_and_global_records(pc):
     assert r["status"] == 0 and boundary_err(r["bounds"], bd).max() <= TOL
 
 
+def test_node_row_feedback_fixed_sweeps_global_records_and_backward(pc):
+    """The feedback on 8-IC jobs (256 nodes, node-row layout: lane pairs exchange the
+    position and its change for da, the mixed column blocks take their zero halves by
+    select): fixed sweeps to rounding, 16 perturbers (records in global memory) and a
+    backward span against the oracle; ragged IC counts."""
+    w = W.nbody_venus(21, seed=12, days=112.5, segments=2, nodes=256)
+    r = _gpu(pc, w, fixed_iters=6, feedback=1)
+    st, it, bd = _oracle(w, fixed_iters=6, feedback=1)
+    assert rel_err(r["states"], st).max() < 1e-12
+    w = W.nbody_venus(13, seed=13, days=112.5, segments=2, nodes=220)
+    pert16 = np.concatenate([w.pert, w.pert * np.array([0.5, 1.02, 1, 1, 1, 1, 1]) + np.array([0, 0, 0, 0, 0, 0, 1.0])])
+    w16 = W.Workload("p16", w.ics, w.groups, pert16, w.init)
+    r = _gpu(pc, w16, feedback=1)
+    st, it, bd = _oracle(w16, feedback=1)
+    assert r["status"] == 0 and boundary_err(r["bounds"], bd).max() <= TOL
+    assert np.abs(r["iters"] - it).max() <= 1
+    wb = W.nbody_venus(11, seed=14, days=80.0, segments=2, nodes=256)
+    wb.groups[0].t0, wb.groups[0].tf = wb.groups[0].tf, wb.groups[0].t0
+    r = _gpu(pc, wb, feedback=1)
+    st, it, bd = _oracle(wb, feedback=1)
+    assert r["status"] == 0 and boundary_err(r["bounds"], bd).max() <= TOL
+
+
+@pytest.mark.parametrize("nodes", [128, 256])
+def test_feedback_takes_fewer_sweeps_at_high_node_counts(pc, nodes):
+    w = W.nbody_venus(64, seed=9, nodes=nodes)
+    two = _gpu(pc, w)
+    fb = _gpu(pc, w, feedback=1)
+    assert two["status"] == 0 and fb["status"] == 0
+    assert fb["iters"].mean() < two["iters"].mean()
+    assert rel_err(fb["states"], two["states"]).max() < 1e-10
+
+
 def test_feedback_takes_fewer_sweeps_than_second_order(pc):
     w = W.nbody_venus(512, seed=8)
     two = _gpu(pc, w)
@@ -153,8 +187,7 @@ def test_second_order_refusals(pc):
     g = w.groups[0]
     ics = torch.tensor(w.ics, device="cuda")
     model = pcprop.Model(1.0, w.pert, 0.0)
-    bad = [dict(groups=[pcprop.Group(0, 16, g.t0, g.tf, 200, 1, g.tol)], kw=dict(feedback=1)),   # feedback at 256
-           dict(groups=None, kw=dict(precision="fp32-fp64")),
+    bad = [dict(groups=None, kw=dict(precision="fp32-fp64")),
            dict(groups=None, kw=dict(path="plain")),
            dict(groups=None, kw=dict(tile_pairs=1024, **{}), nodes=128)]
     for case in bad:
