@@ -177,9 +177,10 @@ def run_adjoint(args):
     flops = adjoint_flops(w, iters, ait, resolve=not args.adjoint_nodes)
     kms = float(np.mean(adj_ms))
     achieved = flops / (kms * 1e-3) / 1e12
+    traffic, traffic_src = measured_traffic("pc_adjoint_kernel", w.name + ("-nodes" if args.adjoint_nodes else ""))
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
-                "traffic_source": "not collected for the adjoint kernel",
+                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": traffic,
+                "traffic_source": traffic_src,
                 "kernel": "pc_adjoint_kernel", "kernel_ms": round(kms, 4), "flops_per_launch": flops}
     cpu = None
     if not args.no_cpu_baseline:
